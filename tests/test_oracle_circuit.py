@@ -1,0 +1,288 @@
+"""Pins of the oracle's trajectories against facts fixed by the paper and by
+the mathematics of stabilizer measurement (Sec. II-III of arXiv:2204.11404)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import frame
+from oracle import statevec as sv
+
+CR, TB = oracle.GATESET_CR, oracle.GATESET_TEXTBOOK
+
+
+def trivial_bits(d, gateset):
+    """Raw ancilla bit of a +1 eigenvalue: w/2 mod 2 for the cross-resonance
+    circuit (product of w rotations by pi/4 about Z_q X_a), 0 for textbook."""
+    return np.array([(sum(1 for q in s if q) // 2) % 2 if gateset == CR else 0
+                     for _, s in oracle.layout(d)], dtype=np.uint8)
+
+
+def closed_form_logical_zero(d):
+    """2^(-n_X/2) on every data basis state in the GF(2) span of the X
+    stabilizer supports (the orbit of |0...0> under the X stabilizer group)."""
+    gens = []
+    for t, s in oracle.layout(d):
+        if t == "X":
+            v = 0
+            for q in s:
+                if q:
+                    v |= 1 << (q - 1)
+            gens.append(v)
+    span = {0}
+    for g in gens:
+        span |= {x ^ g for x in span}
+    psi = np.zeros(1 << (d * d), dtype=np.complex128)
+    psi[list(span)] = 2.0 ** (-len(gens) / 2)
+    assert len(span) == 2 ** len(gens)
+    return psi
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_logical_zero_closed_form(d, gateset):
+    # Sec. III.B: |0...0> projected by noise-free syndrome measurements with
+    # trivial outcomes; phase fixed so <0...0|psi> > 0.
+    assert np.allclose(oracle.logical_zero(d, gateset), closed_form_logical_zero(d), atol=1e-12)
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_noiseless_rounds_are_trivial_and_leave_code_state(d, gateset):
+    r = oracle.run_trajectory(d, gateset, 3, seed=5, t=1, p=0.0, want_state=True)
+    assert np.array_equal(r["records"], np.tile(trivial_bits(d, gateset), (3, 1)))
+    assert set(np.unique(r["p1"])) <= {0.0, 1.0}
+    lz = closed_form_logical_zero(d)
+    # invariant up to a global phase
+    assert abs(abs(np.vdot(lz, r["state"])) - 1.0) < 1e-12
+    # final Z measurement gives a codeword of the X orbit: Z stabilizers and
+    # the top-row logical Z have even parity
+    fb = r["final_bits"]
+    for t, s in oracle.layout(d):
+        if t == "Z":
+            assert sum(int(fb[q - 1]) for q in s if q) % 2 == 0
+    assert sum(int(fb[q]) for q in range(d)) % 2 == 0
+
+
+def test_textbook_first_block_over_rotation():
+    """Textbook circuit with exp(-i eps X) after each H and no other noise: the
+    first check (X1X2 on logical 0) reads 1 with probability sin^2(eps)
+    (the over-rotation relation of Sec. III.A with theta = 2 eps)."""
+    eps = 0.02
+    r = oracle.run_trajectory(3, TB, 1, seed=0, t=0, p=0.0, eps=eps)
+    assert abs(r["p1"][0, 0] - np.sin(eps) ** 2) < 1e-14
+    assert abs(np.sin(eps) ** 2 - 3.9995e-4) < 1e-8
+
+
+def _cr_sites(d):
+    """Kind of each gate site of the cross-resonance round template."""
+    kinds = []
+    for t, s in oracle.layout(d):
+        w = sum(1 for q in s if q)
+        if t == "X":
+            kinds += ["anc"] + ["cr"] * w + ["anc"] + ["restore"] * w
+        else:
+            kinds += ["cr"] * w + ["restore"] * w
+    return kinds
+
+
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_cr_first_block_over_rotation_on_cr_gates(d):
+    """Over-rotation eps only on the two CR gates of X1X2: the ancilla turns by
+    2(pi/4 + eps) instead of pi/2, so the check misses its trivial bit with
+    probability sin^2(2 eps)."""
+    eps = 0.013
+    kinds = _cr_sites(d)
+    es = np.array([eps if k == "cr" else 0.0 for k in kinds])
+    r = oracle.run_trajectory(d, CR, 1, seed=0, t=0, p=0.0, eps_site=es)
+    # raw trivial bit of a weight-2 check is 1
+    assert abs((1.0 - r["p1"][0, 0]) - np.sin(2 * eps) ** 2) < 1e-13
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+def test_norm_preserved(gateset):
+    r = oracle.run_trajectory(3, gateset, 4, seed=9, t=3, p=0.02, eps=0.03, zeta=0.02,
+                              want_state=True)
+    assert abs(np.linalg.norm(r["state"]) - 1.0) < 1e-12
+
+
+def test_zz_only_never_fires_z_checks_or_flips_logical_z():
+    """ZZ crosstalk is diagonal: it commutes with Z checks and Z_L, so with no
+    other noise Z records stay trivial and the top-row parity stays even."""
+    d = 3
+    tb = trivial_bits(d, CR)
+    isz = np.array([t == "Z" for t, _ in oracle.layout(d)])
+    fired_x = 0
+    for t in range(40):
+        r = oracle.run_trajectory(d, CR, 3, seed=4, t=t, p=0.0, zeta=0.15)
+        assert np.array_equal(r["records"][:, isz], np.tile(tb[isz], (3, 1)))
+        assert sum(int(r["final_bits"][q]) for q in range(d)) % 2 == 0
+        fired_x += int(np.any(r["records"][:, ~isz] != tb[~isz]))
+    assert fired_x > 0  # but X checks do see it
+
+
+def _detectors(flips):
+    prev = np.concatenate([np.zeros_like(flips[:, :1]), flips[:, :-1]], axis=1)
+    return (flips ^ prev).reshape(flips.shape[0], -1)
+
+
+@pytest.mark.parametrize("gateset,d,p", [(CR, 3, 0.01), (TB, 3, 0.01), (CR, 2, 0.03)])
+def test_pauli_only_matches_frame_sampler(gateset, d, p):
+    """Pauli-only noise makes the circuit Clifford; detector and logical-Z flip
+    rates of the oracle agree with the Pauli-frame sampler."""
+    R, N = 3, 2500
+    tb = trivial_bits(d, gateset)
+    recs, zl = [], []
+    for t in range(N):
+        r = oracle.run_trajectory(d, gateset, R, seed=11, t=t, p=p)
+        recs.append(r["records"] ^ tb)
+        zl.append(sum(int(r["final_bits"][q]) for q in range(d)) % 2)
+    recs = np.array(recs)
+    frec, ffin = frame.sample(d, gateset, R, p, 200000, seed=2)
+    a = _detectors(recs).mean(0)
+    b = _detectors(frec).mean(0)
+    sig = np.sqrt(np.maximum(b * (1 - b), 1.0 / N) / N)
+    z = (a - b) / sig
+    assert np.max(np.abs(z)) < 4.0
+    assert np.sum(z ** 2) < len(z) + 4.0 * np.sqrt(2 * len(z)) + 10
+    zl_f = np.bitwise_xor.reduce(ffin[:, :d], axis=1).mean()
+    zl_o = np.mean(zl)
+    assert abs(zl_o - zl_f) < 4.0 * np.sqrt(max(zl_f * (1 - zl_f), 1.0 / N) / N)
+
+
+def test_final_measurement_is_born_sampling():
+    """The sequential MSB-first Z measurement of the data register samples the
+    Born distribution: for noiseless d=2 the four X-orbit codewords appear
+    uniformly and nothing else appears."""
+    d = 2
+    lz = closed_form_logical_zero(d)
+    allowed = set(np.nonzero(np.abs(lz) > 0)[0].tolist())
+    counts = {}
+    N = 2000
+    for t in range(N):
+        fb = oracle.run_trajectory(d, CR, 1, seed=21, t=t, p=0.0)["final_bits"]
+        x = sum(int(b) << q for q, b in enumerate(fb))
+        counts[x] = counts.get(x, 0) + 1
+    assert set(counts) == allowed
+    exp = N / len(allowed)
+    chi2 = sum((c - exp) ** 2 / exp for c in counts.values())
+    assert chi2 < 16.3  # 3 dof, p = 1e-3
+
+
+# ---- dense brute force of a whole d=2 trajectory with the same draws ------
+
+def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta):
+    nd = d * d
+    n = nd + 1
+    anc = nd
+    X, Y, Z = sv.pauli("X"), sv.pauli("Y"), sv.pauli("Z")
+    P = [sv.pauli("I"), X, Y, Z]
+    H = np.array([[1, 1], [1, -1]]) / np.sqrt(2)
+
+    def rot(M, beta):
+        return np.cos(beta) * np.eye(M.shape[0]) - 1j * np.sin(beta) * M
+
+    def g(qs, m):
+        return sv.kron_gate(n, qs, m)
+
+    psi = np.kron(np.array([1, 0]), closed_form_logical_zero(d)).astype(np.complex128)
+    k = 0
+    rec = np.zeros((rounds, nd - 1), dtype=np.uint8)
+
+    def draw():
+        nonlocal k
+        u = oracle.uniform(seed, t, k)
+        k += 1
+        return u
+
+    def n1(q):
+        nonlocal psi
+        u = draw()
+        for j in (1, 2, 3):
+            if u < j * p / 3.0:
+                psi = g([q], P[j]) @ psi
+                return
+
+    def n2(q1, q2):
+        nonlocal psi
+        u = draw()
+        for j in range(1, 16):
+            if u < j * p / 15.0:
+                psi = g([q1, q2], np.kron(P[j & 3], P[j >> 2])) @ psi
+                return
+
+    # ZX with bit0 = control (Z), bit1 = target (X): kron(X, Z)
+    ZX = np.kron(X, Z)
+    edges = []
+    for row in range(d):
+        for col in range(d):
+            b = d * row + col
+            if col + 1 < d:
+                edges.append((b, b + 1))
+            if row + 1 < d:
+                edges.append((b, b + d))
+    idx = np.arange(1 << n)
+    zzsum = np.zeros(1 << n)
+    for a, b in edges:
+        zzsum += np.where(((idx >> a) & 1) == ((idx >> b) & 1), 1.0, -1.0)
+    zzphase = np.exp(-1j * zeta * zzsum)
+    q4 = np.pi / 4
+    for r in range(rounds):
+        for i, (typ, slots) in enumerate(oracle.layout(d)):
+            if gateset == CR:
+                if typ == "X":
+                    psi = g([anc], rot(X, -(q4 + eps))) @ psi; n1(anc)
+                    for q in slots:
+                        if q:
+                            psi = g([anc, q - 1], rot(ZX, q4 + eps)) @ psi; n2(anc, q - 1)
+                        else:
+                            n1(anc)
+                    psi = g([anc], rot(X, q4 + eps)) @ psi; n1(anc)
+                    for q in slots:
+                        if q:
+                            psi = g([q - 1], rot(X, q4 + eps)) @ psi; n1(q - 1)
+                else:
+                    for q in slots:
+                        if q:
+                            psi = g([q - 1, anc], rot(ZX, q4 + eps)) @ psi; n2(q - 1, anc)
+                        else:
+                            n1(anc)
+                    for q in slots:
+                        if q:
+                            psi = g([q - 1], rot(Z, q4 + eps)) @ psi; n1(q - 1)
+            else:
+                psi = g([anc], rot(X, eps) @ H) @ psi; n1(anc)
+                for q in slots:
+                    if q:
+                        if typ == "X":
+                            m = np.zeros((4, 4)); m[0, 0] = m[2, 2] = m[3, 1] = m[1, 3] = 1
+                        else:
+                            m = np.diag([1, 1, 1, -1]).astype(float)
+                        psi = g([anc, q - 1], m) @ psi; n2(anc, q - 1)
+                psi = g([anc], rot(X, eps) @ H) @ psi; n1(anc)
+            psi = zzphase * psi
+            m, _, psi = sv.measure_reset(psi, anc, u=draw())
+            rec[r, i] = m
+    state = psi[: 1 << nd].copy()
+    fb = np.zeros(nd, dtype=np.uint8)
+    for q in range(nd, 0, -1):
+        S0, S1 = sv.half_norms(psi, q - 1)
+        p1 = S1 / (S0 + S1)
+        p1 = 0.0 if p1 < 1e-10 else (1.0 if p1 > 1 - 1e-10 else p1)
+        b = int(draw() < p1)
+        keep = ((idx >> (q - 1)) & 1) == b
+        psi = np.where(keep, psi, 0) / np.sqrt(S1 if b else S0)
+        fb[q - 1] = b
+    return rec, fb, state
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+def test_dense_brute_force_d2_trajectories(gateset):
+    d, R = 2, 3
+    for t, (p, eps, zeta) in enumerate([(0.05, 0.0, 0.0), (0.08, 0.04, 0.0), (0.1, 0.03, 0.05),
+                                        (0.2, 0.1, 0.1)]):
+        rec, fb, st = _dense_trajectory(d, gateset, R, 17, t, p, eps, zeta)
+        o = oracle.run_trajectory(d, gateset, R, seed=17, t=t, p=p, eps=eps, zeta=zeta,
+                                  want_state=True)
+        assert np.array_equal(o["records"], rec)
+        assert np.array_equal(o["final_bits"], fb)
+        assert np.allclose(o["state"], st, atol=1e-12)
