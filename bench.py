@@ -1,0 +1,116 @@
+"""Benchmark of the trajectory engine on one MI355X.
+
+Workload (N=1): the 26-qubit d=5 rotated surface code with the cross-resonance
+gate set, complex128 state (the live data register of 2^25 amplitudes,
+512 MiB), p = 1e-3 depolarizing noise, per-site over-rotation theta ~
+U[0, 0.05) rad (eps = theta/2) drawn once per job, ZZ crosstalk zeta = 0.01,
+5 noisy rounds of 24 stabilizer circuits, seed 1; synthetic by construction.
+
+A step is one whole trajectory: logical |0>, 5 rounds (120 fused passes, one
+per stabilizer circuit, each deciding its measurement on the device), the
+final Z measurement of the 25 data qubits.  K steps are timed as one
+sv_run_rounds call of K trajectories after W warm-up trajectories.
+
+Printed: one JSON line with the round time (ms, lower is better), the
+algorithmic HBM rate, the roofline of the dominant kernel (the fused pass:
+one read and one write of the 2^25-amplitude register = 1 GiB per launch)
+timed with HIP events on its stream inside the library, and the oracle timed
+on the host cores on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def cpu_baseline(c, eps, n_blocks):
+    """Oracle (complex128, gate by gate on 26 qubits) on the first n_blocks
+    noisy circuits of a round; scaled to ms per 24-circuit round."""
+    import oracle
+    sec, threads = oracle.time_blocks(c["d"], oracle.GATESET_CR, c["seed"], 0, c["p"], n_blocks,
+                                      zeta=c["zeta"], eps_site=eps)
+    n_stab = c["d"] ** 2 - 1
+    ms_round = sec * 1e3 * n_stab / n_blocks
+    return {"value": ms_round, "unit": "ms/round", "cores": threads, "kind": "oracle",
+            "sample": f"{n_blocks} of the {n_stab} noisy stabilizer circuits of round 1 "
+                      f"(26 qubits, complex128, gate by gate), {sec:.1f} s, scaled to one round"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--cpu-blocks", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2204_11404_amd as qs
+    import workloads
+
+    torch.cuda.set_device(0)
+    c = dict(workloads.CONFIGS["d5_cr_c128"])
+    d, R = c["d"], c["rounds"]
+    n_stab, n_sites, _ = qs.template_info(d, "cr")
+    eps = workloads.eps_sites(n_sites, c["theta"], c["seed"])
+    kw = dict(d=d, gateset="cr", rounds=R, seed=c["seed"], p=c["p"], eps_site=eps,
+              zeta=c["zeta"], dtype=args.dtype)
+
+    if args.warmup > 0:
+        qs.run_rounds(n_traj=args.warmup, traj0=1_000_000, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = qs.run_rounds(n_traj=args.steps, traj0=0, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    amp_bytes = 16 if args.dtype == "c128" else 8
+    blk_bytes = 2 * (1 << (d * d)) * amp_bytes          # read + write of the live register
+    rounds_total = args.steps * R
+    ms_round = wall * 1e3 / rounds_total
+    alg_gbs = n_stab * blk_bytes / (ms_round * 1e-3) / 1e9
+    pass_ms = r["pass_ms"]
+    achieved = blk_bytes / (pass_ms * 1e-3) / 1e9
+    out = {
+        "metric": "d=5 26q QEC round time (ms) + HBM GB/s; d=3 trajectories/s; p99 latency",
+        "value": ms_round,
+        "unit": "ms/round",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.dtype == "c128" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "d5_cr_c128: rotated surface code d=5, 26 qubits, cross-resonance "
+                               "gates, p=1e-3, theta~U[0,0.05) per site, zeta=0.01, 5 rounds",
+                   "state": args.dtype, "trajectories_per_step": 1, "rounds": R,
+                   "stabilizers_per_round": n_stab},
+        "hbm_gbs_algorithmic": alg_gbs,
+        "gpu_ms_device": r["gpu_ms"],
+        "trajectories_per_s": args.steps / wall,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_pass", "bytes_per_launch": blk_bytes,
+                     "avg_launch_ms": pass_ms},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c, eps, args.cpu_blocks)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

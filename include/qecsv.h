@@ -1,0 +1,208 @@
+/* qecsv: state-vector Monte Carlo trajectories of rotated-surface-code syndrome
+ * extraction on an AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Katsuda, Mitarai and Fujii, "Simulation and
+ * performance analysis of quantum error correction with a rotated surface code
+ * under a realistic noise model" (arXiv:2204.11404):
+ *   - Sec. II.A, Table I: the d x d rotated surface code, its d^2-1
+ *     stabilizers and the CNOT order inside each plaquette, with "wait" slots on
+ *     the boundary;
+ *   - Sec. II.B: the stabilizer circuits are delayed so that one runs at a
+ *     time, and a single ancilla is measured, reset and reused, so that d=5
+ *     needs 26 simulated qubits instead of 49;
+ *   - Sec. III.A: the cross-resonance gate set, depolarizing noise after every
+ *     gate and on waiting qubits, coherent over-rotation exp(-i eps A) of every
+ *     rotation gate (theta = 2 eps = 2 c sqrt(p));
+ *   - Sec. III.B: logical |0> prepared by noise-free syndrome measurements with
+ *     trivial outcomes, noisy rounds, a final Z measurement of the data.
+ * ZZ crosstalk, named by the paper as a further coherent source (Introduction,
+ * Conclusion), is supported as exp(-i zeta Z_i Z_j) on nearest-neighbour data
+ * pairs once per stabilizer circuit.
+ *
+ * Conventions used throughout:
+ *   - qubit q is bit q of the amplitude index (little-endian); data qubit label
+ *     i (1-based, Table I) is qubit i-1; in a full register of d^2+1 qubits the
+ *     ancilla is qubit d^2;
+ *   - amplitudes are interleaved (re, im): SV_C128 = two doubles (16 B),
+ *     SV_C64 = two floats (8 B);
+ *   - matrices are passed from the host as row-major interleaved complex128;
+ *     for a k-qubit matrix, bit j of the row/column index is qubits[j].
+ *
+ * Errors: every call returns an sv_status; arguments are checked on the host
+ * before anything is launched and nothing is written on error.  HIP errors map
+ * to SV_EDEVICE.  sv_last_error() returns a thread-local message describing the
+ * last failure on the calling thread.  No call throws across this boundary.
+ *
+ * Streams: every sv_state is bound to one HIP stream (may be NULL = the legacy
+ * default stream); the ops are enqueued on it and are asynchronous unless
+ * noted.  One sv_state must not be used from two threads at once.
+ */
+#ifndef QECSV_H
+#define QECSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SV_OK = 0,
+  SV_EINVAL = -1,   /* bad argument (range, duplicate qubit, size) */
+  SV_ENOMEM = -2,   /* device allocation failed or budget exceeded */
+  SV_EDEVICE = -3,  /* a HIP call failed */
+  SV_ENUMERIC = -4, /* a forced outcome has probability below the clamp */
+  SV_EBUSY = -5     /* resource in use */
+} sv_status;
+
+typedef enum { SV_C64 = 0, SV_C128 = 1 } sv_dtype;
+
+typedef enum {
+  SV_GATESET_CR = 0,       /* Sec. III.A cross-resonance circuit */
+  SV_GATESET_TEXTBOOK = 1  /* H / CNOT / CZ circuit of Fig. 1 */
+} sv_gateset;
+
+/* Probabilities below this are clamped to 0 (above 1 - SV_TAU to 1) before an
+ * outcome is decided. */
+#define SV_TAU 1e-10
+
+typedef struct sv_state_s* sv_state;
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* sv_last_error(void);
+
+/* Library ABI version (major * 100 + minor). */
+int sv_version(void);
+
+/* ------------------------------------------------------------------ memory */
+
+/* Allocate a register of n_qubits (1..34) in dtype on the current HIP device,
+ * bound to hip_stream (a hipStream_t, may be NULL).  The library owns the
+ * memory; sv_free releases it.  The register starts in |0...0>. */
+sv_status sv_alloc(int n_qubits, sv_dtype dtype, void* hip_stream, sv_state* out);
+
+/* Wrap caller-owned device memory (e.g. a torch tensor) of at least
+ * 2^n_qubits amplitudes as a register.  The library never frees dev_ptr.
+ * dev_ptr must be 16-byte aligned. */
+sv_status sv_wrap(void* dev_ptr, size_t bytes, int n_qubits, sv_dtype dtype,
+                  void* hip_stream, sv_state* out);
+
+/* Release the handle (and the memory if sv_alloc made it).  Waits for the
+ * stream.  NULL is accepted. */
+sv_status sv_free(sv_state s);
+
+/* Copy 2^n amplitudes from / to host memory (bytes must equal the register
+ * size).  Synchronous. */
+sv_status sv_set_state(sv_state s, const void* host, size_t bytes);
+sv_status sv_get_state(sv_state s, void* host, size_t bytes);
+
+/* |index>. */
+sv_status sv_set_basis(sv_state s, uint64_t index);
+
+/* Logical |0> of the distance-d code on data qubits 0..d^2-1 (Sec. III.B):
+ * amplitude 2^(-n_X/2) on every basis state of the orbit of |0...0> under the
+ * X-stabilizer group, zero elsewhere (ancilla and higher qubits 0).  This is
+ * the state the noise-free projection with trivial outcomes produces, with
+ * its global phase fixed real and positive.  Needs n_qubits >= d^2. */
+sv_status sv_load_logical0(sv_state s, int d);
+
+/* Wait for the register's stream. */
+sv_status sv_synchronize(sv_state s);
+
+/* --------------------------------------------------------------------- ops */
+
+/* Dense k-qubit gate, k in {1, 2}: m is 2^k x 2^k row-major interleaved
+ * complex128 (host pointer, copied before return); distinct qubits < n. */
+sv_status sv_apply_gate(sv_state s, int k, const int* qubits, const double* m);
+
+/* Diagonal on k <= 5 qubits: amplitude *= phases[local index] (2^k
+ * interleaved complex128, host pointer). */
+sv_status sv_apply_diag(sv_state s, int k, const int* qubits, const double* phases);
+
+/* Dense fused k-qubit matrix, 1 <= k <= 5 (up to 32 x 32 complex) applied to
+ * all 2^(n-k) vectors; same layout as sv_apply_gate.  Used for runs of gates
+ * multiplied on the host into one matrix. */
+sv_status sv_apply_fused(sv_state s, int k, const int* qubits, const double* m);
+
+/* ------------------------------------------------------------- measurement */
+
+/* Measure qubit anc in Z and reset it (Sec. II.B): S0, S1 = squared norms of
+ * the halves with anc = 0 / 1 (FP64), p1 = S1/(S0+S1) clamped by SV_TAU,
+ * outcome = [u < p1]; the kept half is scaled by 1/sqrt(S_outcome) and moved
+ * to anc = 0, the other half is zeroed.  Synchronous: waits for the stream.
+ * outcome and p1 may be NULL. */
+sv_status sv_measure_reset_ancilla(sv_state s, int anc, double u, int* outcome, double* p1);
+
+/* Same with the outcome given; returns SV_ENUMERIC (state unchanged) if the
+ * outcome's probability is below SV_TAU. */
+sv_status sv_measure_reset_ancilla_forced(sv_state s, int anc, int outcome, double* p1);
+
+/* ------------------------------------------------------------- whole runs */
+
+/* One round of the template: number of stabilizers (d^2-1), gate sites (each
+ * rotation gate instance, the unit of the per-site over-rotation) and random
+ * draws (noise locations plus one per measurement). */
+sv_status sv_template_info(int d, int gateset, int* n_stab, int* n_sites, int* n_draws_per_round);
+
+typedef struct sv_job {
+  int d;               /* code distance, 2..5 */
+  int gateset;         /* sv_gateset */
+  int rounds;          /* noisy rounds, >= 1 */
+  int dtype;           /* sv_dtype of the state */
+  int n_traj;          /* trajectories */
+  int flags;           /* reserved, must be 0 */
+  uint64_t traj0;      /* first trajectory index (draw stream id) */
+  uint64_t seed;       /* Philox key */
+  double p;            /* depolarizing probability, [0, 1] */
+  double eps;          /* over-rotation exponent for every site (if eps_site NULL) */
+  const double* eps_site; /* host array of n_sites exponents, or NULL */
+  double zeta;         /* ZZ crosstalk strength */
+  void* hip_stream;    /* stream to run on (NULL = default) */
+} sv_job;
+
+typedef struct sv_result {
+  uint8_t* records;     /* host [n_traj][rounds][d^2-1] raw ancilla bits (required) */
+  uint8_t* final_bits;  /* host [n_traj][d^2], index q-1 for data qubit q (required) */
+  double* p1_trace;     /* host [n_traj][rounds][d^2-1] clamped p1, or NULL */
+  void* final_states;   /* host [n_traj][2^(d^2)] amplitudes of dtype before the
+                           final measurement, or NULL */
+  double gpu_ms;        /* out: device time of the whole run (hipEvents) */
+  double pass_ms;       /* out: mean device time per stabilizer pass */
+} sv_result;
+
+/* Run job->n_traj trajectories (indices traj0 ..): logical |0>, `rounds`
+ * noisy rounds of the d^2-1 stabilizer circuits in Table I order (all X
+ * checks, then all Z checks), each followed by an ancilla measurement and
+ * reset, then a Z measurement of every data qubit from label d^2 down to 1.
+ * Draw k of trajectory t is uniform(seed, t, k) from Philox4x32-10; the draws
+ * are enumerated in circuit order: per round, per stabilizer, one per noise
+ * location and then one for the measurement; after the last round one per
+ * final data measurement.  Synchronous.  Records are the raw ancilla bits. */
+sv_status sv_run_rounds(const sv_job* job, sv_result* res);
+
+/* Philox4x32-10 uniform used by the device code, evaluated on the host (for
+ * tests of the draw stream). */
+double sv_uniform(uint64_t seed, uint64_t t, uint64_t k);
+
+/* Host-side evaluation (no GPU) of the operator the trajectory engine applies
+ * for stabilizer `stab` (0-based, Table I order) in round `round` of
+ * trajectory t.  With the ancilla starting in |0>, the circuit's unitary U and
+ * the outcome m, K_m = <m|_anc U |0>_anc acts on the block's w data qubits;
+ * for this noise model it is monomial in the block basis B (Hadamard on the
+ * data qubits for X checks, identity for Z checks):
+ *   K_m = B . P_F . diag(D_m) . B,   P_F |x> = |x XOR F>.
+ * Outputs: D = [2][2^w] interleaved complex128 (host buffer of 64 doubles,
+ * entries beyond 2^w are 0; for X checks the two unnormalised Walsh-Hadamard
+ * factors 2^-w are folded in), *F, *u (the measurement draw), *type (0 = X,
+ * 1 = Z), *w, qubits[0..w-1] (data qubit indices in CNOT-slot order).
+ * Returns SV_EINVAL if the circuit is not monomial in that basis. */
+sv_status sv_block_kraus(int d, int gateset, int stab, int round, uint64_t seed, uint64_t t,
+                         double p, double eps, const double* eps_site, double* D, uint32_t* F,
+                         double* u, int* type, int* w, int* qubits);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QECSV_H */

@@ -70,6 +70,8 @@ def lib():
         L.orc_logical_zero.restype = ctypes.c_int
         L.orc_apply_gate.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip, dp]
         L.orc_apply_gate.restype = ctypes.c_int
+        L.orc_time_blocks.argtypes = [ctypes.POINTER(_Job), ctypes.c_ulonglong, ctypes.c_int, ip]
+        L.orc_time_blocks.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -163,3 +165,21 @@ def apply_gate_cpp(state, qubits, m):
     if rc != 0:
         raise ValueError("bad gate")
     return s
+
+
+def time_blocks(d, gateset, seed, t, p, n_blocks, zeta=0.0, eps=0.0, eps_site=None):
+    """Wall time (s) of the first n_blocks noisy circuits of a round, and the
+    OpenMP thread count used."""
+    job = _Job()
+    job.d, job.gateset, job.rounds = d, gateset, 1
+    job.seed, job.p, job.zeta, job.eps = int(seed), float(p), float(zeta), float(eps)
+    keep = None
+    if eps_site is not None:
+        keep = np.ascontiguousarray(eps_site, dtype=np.float64)
+        job.eps_site = _ptr(keep, ctypes.c_double)
+    th = ctypes.c_int()
+    sec = lib().orc_time_blocks(ctypes.byref(job), int(t), int(n_blocks), ctypes.byref(th))
+    del keep
+    if sec < 0:
+        raise ValueError("bad arguments")
+    return sec, th.value

@@ -38,10 +38,14 @@
 // trajectory index).  One uniform per draw.
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdint>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -633,6 +637,43 @@ int orc_apply_gate(double* state, int n, int k, const int* qubits, const double*
     state[2 * x + 1] = s.a[x].imag();
   }
   return 0;
+}
+
+// Benchmark sample: run the first n_blocks noisy stabilizer circuits of round
+// 1 (gates, noise, ZZ layer, measurement and reset) from |0...0> and return the
+// wall time in seconds; *threads receives the OpenMP thread count.  The cost
+// of a circuit does not depend on the state, so this times the same work as
+// the corresponding part of a trajectory.
+double orc_time_blocks(const orc_job* j, unsigned long long t, int n_blocks, int* threads) {
+  if (!j || j->d < 2 || j->d > 5 || n_blocks < 1) return -1.0;
+  Job job{j->d, j->gateset, 1, j->seed, j->p, j->zeta, j->eps_site, j->eps};
+  const int d = job.d, anc = d * d;
+  const std::vector<Stab> stabs = build_layout(d);
+  State s(d * d + 1);
+  Ctx cx{&job, t, 0, true, 0};
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < n_blocks; ++i) {
+    const Stab& st = stabs[i % stabs.size()];
+    if (i % stabs.size() == 0) cx.site = 0;
+    run_stabilizer_gates(s, cx, st, anc);
+    if (job.zeta != 0.0) zz_layer(s, d, job.zeta);
+    double S0, S1;
+    half_norms(s, anc, &S0, &S1);
+    double p1 = S1 / (S0 + S1);
+    apply_measure_clamp(&p1);
+    const double u = uniform01(job.seed, t, cx.k++);
+    const int m = (u < p1) ? 1 : 0;
+    project(s, anc, m, m ? S1 : S0, true);
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  if (threads) {
+#ifdef _OPENMP
+    *threads = omp_get_max_threads();
+#else
+    *threads = 1;
+#endif
+  }
+  return std::chrono::duration<double>(t1 - t0).count();
 }
 
 }  // extern "C"

@@ -1,0 +1,262 @@
+"""Python binding of libqecsv (include/qecsv.h): argument marshalling only.
+
+Every step of the simulation runs in the HIP kernels of the shared library;
+this module converts numpy / torch arguments to the C ABI and back.  It never
+falls back to a CPU path: if the library is missing, every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libqecsv.so")
+
+SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ENUMERIC, SV_EBUSY = 0, -1, -2, -3, -4, -5
+SV_C64, SV_C128 = 0, 1
+SV_GATESET_CR, SV_GATESET_TEXTBOOK = 0, 1
+TAU = 1e-10
+
+_DTYPES = {"c64": SV_C64, "c128": SV_C128, SV_C64: SV_C64, SV_C128: SV_C128}
+_NP = {SV_C64: np.complex64, SV_C128: np.complex128}
+_GATESETS = {"cr": SV_GATESET_CR, "textbook": SV_GATESET_TEXTBOOK,
+             SV_GATESET_CR: SV_GATESET_CR, SV_GATESET_TEXTBOOK: SV_GATESET_TEXTBOOK}
+
+
+class SvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"qecsv error {status}: {msg}")
+        self.status = status
+
+
+class Job(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int), ("gateset", ctypes.c_int), ("rounds", ctypes.c_int),
+        ("dtype", ctypes.c_int), ("n_traj", ctypes.c_int), ("flags", ctypes.c_int),
+        ("traj0", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("p", ctypes.c_double),
+        ("eps", ctypes.c_double), ("eps_site", ctypes.POINTER(ctypes.c_double)),
+        ("zeta", ctypes.c_double), ("hip_stream", ctypes.c_void_p),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("records", ctypes.POINTER(ctypes.c_uint8)), ("final_bits", ctypes.POINTER(ctypes.c_uint8)),
+        ("p1_trace", ctypes.POINTER(ctypes.c_double)), ("final_states", ctypes.c_void_p),
+        ("gpu_ms", ctypes.c_double), ("pass_ms", ctypes.c_double),
+    ]
+
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "sv_last_error": (ctypes.c_char_p, []),
+    "sv_version": (ctypes.c_int, []),
+    "sv_alloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "sv_wrap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                               ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "sv_free": (ctypes.c_int, [ctypes.c_void_p]),
+    "sv_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "sv_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "sv_set_basis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "sv_load_logical0": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "sv_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
+    "sv_apply_gate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_double)]),
+    "sv_apply_diag": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_double)]),
+    "sv_apply_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_double)]),
+    "sv_measure_reset_ancilla": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
+    "sv_measure_reset_ancilla_forced": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                                       ctypes.POINTER(ctypes.c_double)]),
+    "sv_template_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "sv_run_rounds": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(Result)]),
+    "sv_uniform": (ctypes.c_double, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]),
+    "sv_block_kraus": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libqecsv.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP extension missing: {LIB_PATH} (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(status):
+    if status != SV_OK:
+        raise SvError(status, lib().sv_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+def template_info(d, gateset):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().sv_template_info(d, _GATESETS[gateset], ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def uniform(seed, t, k):
+    return lib().sv_uniform(int(seed), int(t), int(k))
+
+
+def block_kraus(d, gateset, stab, rnd, seed, t, p, eps=0.0, eps_site=None):
+    """sv_block_kraus: returns dict(D=complex[2, 2^w], F, u, type ('X'/'Z'), qubits)."""
+    D = np.zeros(64, dtype=np.float64)
+    F, u, typ, w = ctypes.c_uint32(), ctypes.c_double(), ctypes.c_int(), ctypes.c_int()
+    q = np.zeros(4, dtype=np.int32)
+    es = None
+    if eps_site is not None:
+        es = np.ascontiguousarray(eps_site, dtype=np.float64)
+    _check(lib().sv_block_kraus(d, _GATESETS[gateset], stab, rnd, int(seed), int(t), float(p),
+                                float(eps), _dptr(es) if es is not None else None, _dptr(D),
+                                ctypes.byref(F), ctypes.byref(u), ctypes.byref(typ), ctypes.byref(w),
+                                _iptr(q)))
+    n = 1 << w.value
+    Dc = D.view(np.complex128).reshape(2, 16)[:, :n].copy()
+    return dict(D=Dc, F=F.value, u=u.value, type="X" if typ.value == 0 else "Z",
+                qubits=[int(x) for x in q[: w.value]])
+
+
+class State:
+    """A register on the GPU (sv_alloc / sv_wrap)."""
+
+    def __init__(self, n_qubits, dtype="c128", stream=None, tensor=None):
+        self.n = n_qubits
+        self.dtype = _DTYPES[dtype]
+        self._tensor = tensor
+        h = ctypes.c_void_p()
+        if tensor is None:
+            _check(lib().sv_alloc(n_qubits, self.dtype, _stream_ptr(stream), ctypes.byref(h)))
+        else:
+            nbytes = tensor.numel() * tensor.element_size()
+            _check(lib().sv_wrap(ctypes.c_void_p(tensor.data_ptr()), nbytes, n_qubits, self.dtype,
+                                 _stream_ptr(stream), ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def nbytes(self):
+        return (16 if self.dtype == SV_C128 else 8) << self.n
+
+    def free(self):
+        if self.h:
+            _check(lib().sv_free(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def set(self, host):
+        a = np.ascontiguousarray(host, dtype=_NP[self.dtype])
+        _check(lib().sv_set_state(self.h, a.ctypes.data, a.nbytes))
+
+    def get(self):
+        a = np.empty(1 << self.n, dtype=_NP[self.dtype])
+        _check(lib().sv_get_state(self.h, a.ctypes.data, a.nbytes))
+        return a
+
+    def set_basis(self, index):
+        _check(lib().sv_set_basis(self.h, int(index)))
+
+    def load_logical0(self, d):
+        _check(lib().sv_load_logical0(self.h, d))
+
+    def synchronize(self):
+        _check(lib().sv_synchronize(self.h))
+
+    def _mat(self, qubits, m):
+        q = np.ascontiguousarray(qubits, dtype=np.int32)
+        mm = np.ascontiguousarray(m, dtype=np.complex128).view(np.float64)
+        return q, mm
+
+    def apply_gate(self, qubits, m):
+        q, mm = self._mat(qubits, m)
+        _check(lib().sv_apply_gate(self.h, len(q), _iptr(q), _dptr(mm)))
+
+    def apply_diag(self, qubits, phases):
+        q, mm = self._mat(qubits, phases)
+        _check(lib().sv_apply_diag(self.h, len(q), _iptr(q), _dptr(mm)))
+
+    def apply_fused(self, qubits, m):
+        q, mm = self._mat(qubits, m)
+        _check(lib().sv_apply_fused(self.h, len(q), _iptr(q), _dptr(mm)))
+
+    def measure_reset(self, anc, u):
+        m, p1 = ctypes.c_int(), ctypes.c_double()
+        _check(lib().sv_measure_reset_ancilla(self.h, anc, float(u), ctypes.byref(m), ctypes.byref(p1)))
+        return m.value, p1.value
+
+    def measure_reset_forced(self, anc, outcome):
+        p1 = ctypes.c_double()
+        _check(lib().sv_measure_reset_ancilla_forced(self.h, anc, int(outcome), ctypes.byref(p1)))
+        return p1.value
+
+
+def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0,
+               dtype="c128", traj0=0, want_p1=False, want_states=False, stream=None):
+    """sv_run_rounds: returns dict(records[n_traj, rounds, n_stab], final_bits[n_traj, d*d],
+    p1 or None, states or None, gpu_ms, pass_ms)."""
+    n_stab, n_sites, _ = template_info(d, gateset)
+    job = Job()
+    job.d, job.gateset, job.rounds = d, _GATESETS[gateset], rounds
+    job.dtype, job.n_traj, job.flags = _DTYPES[dtype], n_traj, 0
+    job.traj0, job.seed, job.p, job.eps, job.zeta = int(traj0), int(seed), float(p), float(eps), float(zeta)
+    job.hip_stream = _stream_ptr(stream)
+    keep = None
+    if eps_site is not None:
+        keep = np.ascontiguousarray(eps_site, dtype=np.float64)
+        if keep.shape != (n_sites,):
+            raise ValueError(f"eps_site must have {n_sites} entries")
+        job.eps_site = _dptr(keep)
+    rec = np.zeros((n_traj, rounds, n_stab), dtype=np.uint8)
+    fb = np.zeros((n_traj, d * d), dtype=np.uint8)
+    p1 = np.zeros((n_traj, rounds, n_stab), dtype=np.float64) if want_p1 else None
+    states = np.zeros((n_traj, 1 << (d * d)), dtype=_NP[job.dtype]) if want_states else None
+    res = Result()
+    res.records = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    res.final_bits = fb.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    if p1 is not None:
+        res.p1_trace = _dptr(p1)
+    if states is not None:
+        res.final_states = states.ctypes.data
+    _check(lib().sv_run_rounds(ctypes.byref(job), ctypes.byref(res)))
+    del keep
+    return dict(records=rec, final_bits=fb, p1=p1, states=states, gpu_ms=res.gpu_ms, pass_ms=res.pass_ms)

@@ -1,0 +1,339 @@
+// Host/device definitions shared by the qecsv runtime and its HIP kernels:
+// the counter-based generator, the encoded stabilizer-circuit template, and
+// the per-block Kraus builder used by the trajectory engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define QEC_HD __host__ __device__ __forceinline__
+
+namespace qec {
+
+// ------------------------------------------------------------------ Philox --
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): two 32x32->64 multiplies
+// per round with constants M0, M1, key bumped by the Weyl constants W0, W1.
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+QEC_HD U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t a = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t b = (uint64_t)0xCD9E8D57u * c.z;
+    U4 n;
+    n.x = (uint32_t)(b >> 32) ^ c.y ^ k0;
+    n.y = (uint32_t)b;
+    n.z = (uint32_t)(a >> 32) ^ c.w ^ k1;
+    n.w = (uint32_t)a;
+    c = n;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Draw k of trajectory t: counter (k, t), key = seed, 53 random bits from the
+// first two output words, scaled to [0, 1).
+QEC_HD double uniform(uint64_t seed, uint64_t t, uint64_t k) {
+  U4 c{(uint32_t)k, (uint32_t)(k >> 32), (uint32_t)t, (uint32_t)(t >> 32)};
+  const U4 o = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t bits = ((((uint64_t)o.y) << 32) | o.x) >> 11;
+  return (double)bits * (1.0 / 9007199254740992.0);
+}
+
+// ------------------------------------------------------- complex helpers --
+struct cd {
+  double re, im;
+};
+QEC_HD cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+QEC_HD cd cadd(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+QEC_HD cd cscale(cd a, double s) { return {a.re * s, a.im * s}; }
+QEC_HD cd cexpi(double th) { return {cos(th), sin(th)}; }  // e^{i th}
+
+// ---------------------------------------------------- circuit template --
+// One stabilizer circuit is a list of ops on the ancilla and the block's data
+// qubits (local index j = position among the block's data qubits in CNOT
+// slot order).  Rotation ops carry a gate site (index into the per-round
+// over-rotation table) and an angle base (pi/4 for the cross-resonance gate
+// set, 0 for the textbook over-rotation gate).  Noise ops carry a local draw
+// index.
+enum OpKind : uint8_t {
+  OP_ROT_ANC = 1,   // exp(-i beta sgn P) on the ancilla, P = axis
+  OP_ROT_DATA = 2,  // exp(-i beta P) on data j
+  OP_CR_AD = 3,     // exp(-i beta Z_anc X_j)
+  OP_CR_DA = 4,     // exp(-i beta Z_j X_anc)
+  OP_H_ANC = 5,     // Hadamard on the ancilla
+  OP_CNOT_AD = 6,   // CNOT control ancilla, target data j
+  OP_CZ_AD = 7,     // CZ ancilla, data j
+  OP_N1_ANC = 8,    // one-qubit depolarizing location on the ancilla
+  OP_N1_DATA = 9,   // ... on data j
+  OP_N2_AD = 10,    // two-qubit location, first qubit ancilla, second data j
+  OP_N2_DA = 11,    // two-qubit location, first qubit data j, second ancilla
+};
+
+struct TOp {
+  uint8_t kind;
+  uint8_t j;        // local data index
+  uint8_t axis;     // 1 = X, 2 = Y, 3 = Z
+  int8_t sgn;       // +1 / -1 generator sign
+  uint8_t quarter;  // 1: angle base pi/4; 0: base 0
+  uint8_t pad;
+  int16_t site;     // gate site within the round, -1 if none
+  int16_t draw;     // local draw index, -1 if none
+  int16_t pad2;
+};
+
+constexpr int kMaxOps = 24;
+
+struct TBlock {
+  int type;          // 0 = X check (data in the X basis), 1 = Z check
+  int w;             // data qubits (2 or 4)
+  int qubit[4];      // data qubit (bit index) per local index
+  int n_ops;
+  int n_draws;       // noise draws + 1 measurement draw
+  int draw_off;      // first draw of this block within the round
+  int site_off;      // first site of this block within the round
+  TOp ops[kMaxOps];
+};
+
+// Per (trajectory, block instance) result of the Kraus builder.  With B the
+// block basis (Hadamard on the block's data for X checks, identity for Z
+// checks), the post-measurement operator of outcome m on the data register is
+// K_m = B Pi_F diag(D_m) B, a monomial matrix: the kernels apply it as
+// WHT -> diag -> WHT -> sign pattern (X checks) or diag -> XOR permutation (Z
+// checks).  D holds D_m with 2^-w folded in for X checks; W holds the weights
+// |D_m|^2 (again with 2^-w for X checks) that give S_m from the transformed
+// amplitudes.
+struct BlockRT {
+  double D[2][16][2];
+  double W[2][16];
+  double u;       // measurement draw
+  uint32_t F;     // XOR pattern (local data bits)
+  uint32_t pad;
+};
+
+// Thresholds of the depolarizing channels: Pauli j is chosen for the first
+// j with u < j p / 3 (one-qubit, j = 1..3 -> X, Y, Z) or u < j p / 15
+// (two-qubit, j = 1..15 -> P[j >> 2] (x) P[j & 3] on (first, second)).
+QEC_HD int pick_pauli1(double u, double p) {
+  for (int j = 1; j <= 3; ++j)
+    if (u < (double)j * p / 3.0) return j;
+  return 0;
+}
+QEC_HD int pick_pauli2(double u, double p) {
+  for (int j = 1; j <= 15; ++j)
+    if (u < (double)j * p / 15.0) return j;
+  return 0;
+}
+
+// Pauli P (1 X, 2 Y, 3 Z) on the ancilla 2-vector.
+QEC_HD void anc_pauli(int P, cd& v0, cd& v1) {
+  if (P == 1) {
+    cd t = v0; v0 = v1; v1 = t;
+  } else if (P == 2) {  // Y = [[0,-i],[i,0]]
+    cd t = v0;
+    v0 = {v1.im, -v1.re};   // -i * v1
+    v1 = {-t.im, t.re};     //  i * v0
+  } else if (P == 3) {
+    v1 = {-v1.re, -v1.im};
+  }
+}
+
+// Pauli P on data bit j of the block-basis label `cur`: returns the phase
+// and flips cur if needed.  In the X basis X is diagonal (eigenvalue +-1),
+// Z flips |+> <-> |->, Y|+> = -i|->, Y|-> = i|+>.  In the Z basis Z is
+// diagonal, X flips, Y|0> = i|1>, Y|1> = -i|0>.
+QEC_HD cd data_pauli(int P, bool xbasis, int j, uint32_t& cur) {
+  const int bit = (cur >> j) & 1;
+  const double e = bit ? -1.0 : 1.0;
+  cd ph{1.0, 0.0};
+  if (P == 0) return ph;
+  const int diag_axis = xbasis ? 1 : 3;
+  if (P == diag_axis) return {e, 0.0};
+  if (P == 2) {
+    // X basis: bit 0 -> -i, bit 1 -> +i;  Z basis: bit 0 -> +i, bit 1 -> -i
+    const double s = xbasis ? -e : e;
+    ph = {0.0, s};
+  }
+  cur ^= (1u << j);
+  return ph;
+}
+
+// exp(-i theta P) on the ancilla 2-vector.
+QEC_HD void anc_rot(int axis, double theta, cd& v0, cd& v1) {
+  const double c = cos(theta), s = sin(theta);
+  if (axis == 1) {  // [[c, -is], [-is, c]]
+    cd a{c * v0.re + s * v1.im, c * v0.im - s * v1.re};
+    cd b{c * v1.re + s * v0.im, c * v1.im - s * v0.re};
+    v0 = a; v1 = b;
+  } else if (axis == 2) {  // [[c, -s], [s, c]]
+    cd a{c * v0.re - s * v1.re, c * v0.im - s * v1.im};
+    cd b{s * v0.re + c * v1.re, s * v0.im + c * v1.im};
+    v0 = a; v1 = b;
+  } else {  // diag(e^{-i th}, e^{i th})
+    v0 = cmul(v0, cexpi(-theta));
+    v1 = cmul(v1, cexpi(theta));
+  }
+}
+
+// Builds BlockRT for one block instance.  pauli[i] is the Pauli code drawn for
+// op i (0 = none; for two-qubit locations the pair index 1..15).  Returns
+// false if an op is not monomial in the block basis.
+QEC_HD bool build_block(const TBlock& b, const double* eps_site, const uint8_t* pauli,
+                        BlockRT& out) {
+  const bool xb = (b.type == 0);
+  const int n = 1 << b.w;
+  const double norm = xb ? 1.0 / (double)n : 1.0;
+  const double q4 = 0.78539816339744830962;  // pi/4
+  uint32_t F = 0;
+  for (int x = 0; x < n; ++x) {
+    cd v0{1.0, 0.0}, v1{0.0, 0.0};
+    uint32_t cur = (uint32_t)x;
+    for (int i = 0; i < b.n_ops; ++i) {
+      const TOp& op = b.ops[i];
+      const double beta = (op.quarter ? q4 : 0.0) + (op.site >= 0 ? eps_site[op.site] : 0.0);
+      switch (op.kind) {
+        case OP_ROT_ANC:
+          anc_rot(op.axis, beta * (double)op.sgn, v0, v1);
+          break;
+        case OP_ROT_DATA: {
+          if ((xb && op.axis != 1) || (!xb && op.axis != 3)) return false;
+          const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
+          const cd ph = cexpi(-beta * e * (double)op.sgn);
+          v0 = cmul(v0, ph);
+          v1 = cmul(v1, ph);
+          break;
+        }
+        case OP_CR_AD: {
+          if (!xb) return false;
+          const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
+          v0 = cmul(v0, cexpi(-beta * e));
+          v1 = cmul(v1, cexpi(beta * e));
+          break;
+        }
+        case OP_CR_DA: {
+          if (xb) return false;
+          const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
+          anc_rot(1, beta * e, v0, v1);
+          break;
+        }
+        case OP_H_ANC: {
+          const double h = 0.70710678118654752440;
+          cd a{(v0.re + v1.re) * h, (v0.im + v1.im) * h};
+          cd c{(v0.re - v1.re) * h, (v0.im - v1.im) * h};
+          v0 = a; v1 = c;
+          break;
+        }
+        case OP_CNOT_AD: {
+          if (!xb) return false;
+          if ((cur >> op.j) & 1) v1 = {-v1.re, -v1.im};
+          break;
+        }
+        case OP_CZ_AD: {
+          if (xb) return false;
+          if ((cur >> op.j) & 1) v1 = {-v1.re, -v1.im};
+          break;
+        }
+        case OP_N1_ANC:
+          anc_pauli(pauli[i], v0, v1);
+          break;
+        case OP_N1_DATA: {
+          const cd ph = data_pauli(pauli[i], xb, op.j, cur);
+          v0 = cmul(v0, ph);
+          v1 = cmul(v1, ph);
+          break;
+        }
+        case OP_N2_AD: {
+          const int pj = pauli[i];
+          anc_pauli(pj >> 2, v0, v1);
+          const cd ph = data_pauli(pj & 3, xb, op.j, cur);
+          v0 = cmul(v0, ph);
+          v1 = cmul(v1, ph);
+          break;
+        }
+        case OP_N2_DA: {
+          const int pj = pauli[i];
+          const cd ph = data_pauli(pj >> 2, xb, op.j, cur);
+          v0 = cmul(v0, ph);
+          v1 = cmul(v1, ph);
+          anc_pauli(pj & 3, v0, v1);
+          break;
+        }
+        default:
+          return false;
+      }
+    }
+    F = cur ^ (uint32_t)x;
+    out.D[0][x][0] = v0.re * norm;
+    out.D[0][x][1] = v0.im * norm;
+    out.D[1][x][0] = v1.re * norm;
+    out.D[1][x][1] = v1.im * norm;
+    out.W[0][x] = (v0.re * v0.re + v0.im * v0.im) * norm;
+    out.W[1][x] = (v1.re * v1.re + v1.im * v1.im) * norm;
+  }
+  for (int x = n; x < 16; ++x) {
+    out.D[0][x][0] = out.D[0][x][1] = out.D[1][x][0] = out.D[1][x][1] = 0.0;
+    out.W[0][x] = out.W[1][x] = 0.0;
+  }
+  out.F = F;
+  return true;
+}
+
+// Draws of one block instance: Pauli choices per op, measurement uniform.
+QEC_HD void draw_block(const TBlock& b, uint64_t seed, uint64_t t, uint64_t k0, double p,
+                       uint8_t* pauli, double* u_meas) {
+  for (int i = 0; i < b.n_ops; ++i) {
+    const TOp& op = b.ops[i];
+    pauli[i] = 0;
+    if (op.draw < 0) continue;
+    const double u = uniform(seed, t, k0 + (uint64_t)op.draw);
+    if (op.kind == OP_N1_ANC || op.kind == OP_N1_DATA)
+      pauli[i] = (uint8_t)pick_pauli1(u, p);
+    else
+      pauli[i] = (uint8_t)pick_pauli2(u, p);
+  }
+  *u_meas = uniform(seed, t, k0 + (uint64_t)(b.n_draws - 1));
+}
+
+// ------------------------------------------------------------ pass layout --
+// A pass applies block a (K_m of its decided outcome, then the ZZ layer and
+// the 1/sqrt(S_m) renormalisation) and accumulates S_0, S_1 of block b, over
+// tiles of 2^TB amplitudes that contain every data qubit of a and b.  In
+// phase 1 a thread owns 16 amplitudes: the 2^wa combinations of block a's
+// qubits times 2^(4-wa) further tile bits; in phase 2 (through LDS) it owns
+// the 2^wb combinations of block b's qubits times 2^(4-wb) tile bits.
+struct PassDesc {
+  int wa, wb;          // 0 = none (init / last pass)
+  int typea, typeb;    // 0 = X, 1 = Z
+  int blk_a, blk_b;    // template block indices
+  int tb;              // tile bits
+  int n_outer;         // bits outside the tile
+  uint32_t outer_bit[32];  // value (1 << position) of each outer bit
+  uint32_t a_tid_g[8], a_tid_l[8];
+  uint32_t a_j_g[16], a_j_l[16];
+  uint32_t a_q_g[4], a_q_l[4];  // global / LDS bit of block a's local bit
+  uint32_t b_tid_l[8];
+  uint32_t b_j_l[16];
+};
+
+struct JobConst {
+  int d;
+  int n;               // data qubits
+  int n_x;             // X stabilizers (rank of the X-support span)
+  int n_edges;         // ZZ pairs
+  uint32_t hmask, vmask;
+  double amp0;         // 2^(-n_x/2)
+  uint32_t span_vec[16];   // echelon basis of the X supports
+  uint32_t span_piv[16];   // pivot bit of each basis vector
+  double zz[2 * 64];       // exp(-i zeta (|E| - 2k)), k = 0..|E|
+  int use_zz;
+};
+
+struct Decision {
+  double Sm;      // norm^2 of the kept half
+  int m;          // outcome
+  int pad;
+};
+
+}  // namespace qec

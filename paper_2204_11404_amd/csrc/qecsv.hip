@@ -1,0 +1,819 @@
+// qecsv host runtime and C ABI (see include/qecsv.h).
+//
+// Host side of the trajectory engine: the code layout of Sec. II.A (Table I
+// order, CNOT slot order, boundary waits), the encoded stabilizer-circuit
+// template of Sec. III.A (cross-resonance or textbook gate set, noise
+// locations, over-rotation sites), tile descriptors for the fused passes, and
+// the launch sequence of one trajectory (Sec. III.B).  All simulation
+// arithmetic runs in the kernels of kernels.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qecsv.h"
+#include "qec_common.h"
+#include "kernels.hip"
+
+using namespace qec;
+
+namespace {
+
+thread_local std::string g_err;
+
+sv_status fail(sv_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_OK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(SV_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Device buffers released on scope exit.
+struct DevBufs {
+  std::vector<void*> ptrs;
+  ~DevBufs() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename P>
+  hipError_t alloc(P** out, size_t bytes) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+    if (e == hipSuccess) {
+      ptrs.push_back(p);
+      *out = reinterpret_cast<P*>(p);
+    }
+    return e;
+  }
+};
+
+// --------------------------------------------------------------- layout --
+struct Stab {
+  int type;     // 0 X, 1 Z
+  int slot[4];  // data labels 1..d^2 in CNOT order, 0 = wait
+};
+
+// Rotated surface code of distance d.  Faces sit between data rows r, r+1
+// and columns c, c+1 for r, c in -1..d-1; a face is X-type when r + c is odd.
+// Interior faces have four data qubits; the weight-2 faces kept on the border
+// are X-type on the top/bottom edges and Z-type on the left/right edges.  X
+// faces are measured in row-major order, Z faces column by column from the
+// bottom row up (Table I).  CNOT slots: X faces bottom-right, bottom-left,
+// top-left, top-right; Z faces top-right, bottom-right, bottom-left,
+// top-left (Sec. II.A).
+std::vector<Stab> code_layout(int d) {
+  auto q = [d](int row, int col) -> int {
+    if (row < 0 || col < 0 || row >= d || col >= d) return 0;
+    return row * d + col + 1;
+  };
+  std::vector<Stab> out;
+  // X faces, row-major
+  for (int r = -1; r < d; ++r)
+    for (int c = -1; c < d; ++c) {
+      if (((r + c) & 1) == 0) continue;
+      const bool interior = r >= 0 && c >= 0 && r < d - 1 && c < d - 1;
+      const bool edge = (r == -1 || r == d - 1) && c >= 0 && c < d - 1;
+      if (!interior && !edge) continue;
+      out.push_back({0, {q(r + 1, c + 1), q(r + 1, c), q(r, c), q(r, c + 1)}});
+    }
+  // Z faces, by column, bottom row first
+  for (int c = -1; c < d; ++c)
+    for (int r = d - 1; r >= -1; --r) {
+      if ((r + c) & 1) continue;
+      const bool interior = r >= 0 && c >= 0 && r < d - 1 && c < d - 1;
+      const bool edge = (c == -1 || c == d - 1) && r >= 0 && r < d - 1;
+      if (!interior && !edge) continue;
+      out.push_back({1, {q(r, c + 1), q(r + 1, c + 1), q(r + 1, c), q(r, c)}});
+    }
+  return out;
+}
+
+// ------------------------------------------------------------- template --
+struct Template {
+  std::vector<TBlock> blocks;
+  int n_sites = 0;
+  int n_draws = 0;
+};
+
+struct OpSink {
+  TBlock& b;
+  int site_base;
+  int sites = 0;
+  int draws = 0;
+  void gate(uint8_t kind, int j, int axis, int sgn, int quarter) {
+    TOp& o = b.ops[b.n_ops++];
+    o = TOp{};
+    o.kind = kind; o.j = (uint8_t)j; o.axis = (uint8_t)axis; o.sgn = (int8_t)sgn;
+    o.quarter = (uint8_t)quarter;
+    o.site = (int16_t)(site_base + sites++);
+    o.draw = -1;
+  }
+  void plain(uint8_t kind, int j) {
+    TOp& o = b.ops[b.n_ops++];
+    o = TOp{};
+    o.kind = kind; o.j = (uint8_t)j; o.site = -1; o.draw = -1;
+  }
+  void noise(uint8_t kind, int j) {
+    TOp& o = b.ops[b.n_ops++];
+    o = TOp{};
+    o.kind = kind; o.j = (uint8_t)j; o.site = -1; o.draw = (int16_t)draws++;
+  }
+};
+
+Template build_template(int d, int gateset) {
+  Template T;
+  for (const Stab& st : code_layout(d)) {
+    TBlock b{};
+    b.type = st.type;
+    b.w = 0;
+    int local[4];
+    for (int s = 0; s < 4; ++s) {
+      local[s] = -1;
+      if (st.slot[s]) {
+        local[s] = b.w;
+        b.qubit[b.w++] = st.slot[s] - 1;
+      }
+    }
+    b.draw_off = T.n_draws;
+    b.site_off = T.n_sites;
+    OpSink o{b, T.n_sites};
+    if (gateset == SV_GATESET_CR) {
+      if (st.type == 0) {
+        o.gate(OP_ROT_ANC, 0, 1, -1, 1);  // Rx^dag(pi/2)
+        o.noise(OP_N1_ANC, 0);
+        for (int s = 0; s < 4; ++s) {
+          if (local[s] >= 0) {
+            o.gate(OP_CR_AD, local[s], 0, 1, 1);
+            o.noise(OP_N2_AD, local[s]);
+          } else {
+            o.noise(OP_N1_ANC, 0);  // wait
+          }
+        }
+        o.gate(OP_ROT_ANC, 0, 1, 1, 1);  // Rx(pi/2)
+        o.noise(OP_N1_ANC, 0);
+        for (int l = 0; l < b.w; ++l) {
+          o.gate(OP_ROT_DATA, l, 1, 1, 1);  // restoring Rx(pi/2) on data
+          o.noise(OP_N1_DATA, l);
+        }
+      } else {
+        for (int s = 0; s < 4; ++s) {
+          if (local[s] >= 0) {
+            o.gate(OP_CR_DA, local[s], 0, 1, 1);
+            o.noise(OP_N2_DA, local[s]);
+          } else {
+            o.noise(OP_N1_ANC, 0);
+          }
+        }
+        for (int l = 0; l < b.w; ++l) {
+          o.gate(OP_ROT_DATA, l, 3, 1, 1);  // restoring Rz(pi/2) on data
+          o.noise(OP_N1_DATA, l);
+        }
+      }
+    } else {
+      o.plain(OP_H_ANC, 0);
+      o.gate(OP_ROT_ANC, 0, 1, 1, 0);  // coherent error exp(-i eps X) after H
+      o.noise(OP_N1_ANC, 0);
+      for (int s = 0; s < 4; ++s) {
+        if (local[s] < 0) continue;
+        o.plain(st.type == 0 ? OP_CNOT_AD : OP_CZ_AD, local[s]);
+        o.noise(OP_N2_AD, local[s]);
+      }
+      o.plain(OP_H_ANC, 0);
+      o.gate(OP_ROT_ANC, 0, 1, 1, 0);
+      o.noise(OP_N1_ANC, 0);
+    }
+    b.n_draws = o.draws + 1;  // + measurement
+    T.n_sites += o.sites;
+    T.n_draws += b.n_draws;
+    T.blocks.push_back(b);
+  }
+  return T;
+}
+
+// ------------------------------------------------------- job constants --
+JobConst make_job_const(int d, double zeta) {
+  JobConst jc{};
+  jc.d = d;
+  jc.n = d * d;
+  // reduced echelon basis of the X-stabilizer supports over GF(2)
+  std::vector<uint32_t> basis;
+  for (const Stab& st : code_layout(d)) {
+    if (st.type != 0) continue;
+    uint32_t v = 0;
+    for (int s = 0; s < 4; ++s)
+      if (st.slot[s]) v |= 1u << (st.slot[s] - 1);
+    for (uint32_t bv : basis) {
+      const uint32_t piv = 1u << (31 - __builtin_clz(bv));
+      if (v & piv) v ^= bv;
+    }
+    if (!v) continue;
+    const uint32_t piv = 1u << (31 - __builtin_clz(v));
+    for (uint32_t& bv : basis)
+      if (bv & piv) bv ^= v;
+    basis.push_back(v);
+  }
+  jc.n_x = (int)basis.size();
+  for (int i = 0; i < jc.n_x; ++i) {
+    jc.span_vec[i] = basis[i];
+    jc.span_piv[i] = 1u << (31 - __builtin_clz(basis[i]));
+  }
+  jc.amp0 = std::pow(2.0, -0.5 * jc.n_x);
+  uint32_t hm = 0, vm = 0;
+  int ne = 0;
+  for (int i = 0; i < d * d; ++i) {
+    if (i % d != d - 1) { hm |= 1u << i; ++ne; }
+    if (i + d < d * d) { vm |= 1u << i; ++ne; }
+  }
+  jc.hmask = hm;
+  jc.vmask = vm;
+  jc.n_edges = ne;
+  for (int k = 0; k <= ne; ++k) {
+    const double th = -zeta * (double)(ne - 2 * k);
+    jc.zz[2 * k] = std::cos(th);
+    jc.zz[2 * k + 1] = std::sin(th);
+  }
+  jc.use_zz = zeta != 0.0;
+  return jc;
+}
+
+// ------------------------------------------------------ pass descriptors --
+PassDesc make_pass(int n, int tb_max, const TBlock* A, const TBlock* B, int ia, int ib) {
+  PassDesc pd{};
+  const int tb = std::min(tb_max, n);
+  pd.tb = tb;
+  pd.wa = A ? A->w : 0;
+  pd.wb = B ? B->w : 0;
+  pd.typea = A ? A->type : 0;
+  pd.typeb = B ? B->type : 0;
+  pd.blk_a = ia;
+  pd.blk_b = ib;
+  std::vector<int> qa, qb;
+  for (int l = 0; l < pd.wa; ++l) qa.push_back(A->qubit[l]);
+  for (int l = 0; l < pd.wb; ++l) qb.push_back(B->qubit[l]);
+  std::vector<bool> in_t(n, false);
+  int cnt = 0;
+  for (int x : qa) if (!in_t[x]) { in_t[x] = true; ++cnt; }
+  for (int x : qb) if (!in_t[x]) { in_t[x] = true; ++cnt; }
+  for (int bit = 0; bit < n && cnt < tb; ++bit)
+    if (!in_t[bit]) { in_t[bit] = true; ++cnt; }
+  std::vector<int> rank(n, -1);
+  int r = 0;
+  pd.n_outer = 0;
+  for (int bit = 0; bit < n; ++bit) {
+    if (in_t[bit]) rank[bit] = r++;
+    else pd.outer_bit[pd.n_outer++] = 1u << bit;
+  }
+  auto fill = [&](const std::vector<int>& qs, uint32_t* tid_g, uint32_t* tid_l, uint32_t* j_g,
+                  uint32_t* j_l, uint32_t* q_g, uint32_t* q_l) {
+    std::vector<int> rest;
+    for (int bit = 0; bit < n; ++bit)
+      if (in_t[bit] && std::find(qs.begin(), qs.end(), bit) == qs.end()) rest.push_back(bit);
+    const int w = (int)qs.size();
+    const int ntid = tb - 4;
+    for (int i = 0; i < ntid; ++i) {
+      if (tid_g) tid_g[i] = 1u << rest[i];
+      tid_l[i] = 1u << rank[rest[i]];
+    }
+    for (int j = 0; j < 16; ++j) {
+      uint32_t g = 0, l = 0;
+      for (int b = 0; b < w; ++b)
+        if ((j >> b) & 1) { g |= 1u << qs[b]; l |= 1u << rank[qs[b]]; }
+      for (int h = 0; h < 4 - w; ++h)
+        if ((j >> (w + h)) & 1) {
+          const int bit = rest[ntid + h];
+          g |= 1u << bit;
+          l |= 1u << rank[bit];
+        }
+      if (j_g) j_g[j] = g;
+      j_l[j] = l;
+    }
+    if (q_g)
+      for (int b = 0; b < w; ++b) {
+        q_g[b] = 1u << qs[b];
+        q_l[b] = 1u << rank[qs[b]];
+      }
+  };
+  fill(qa, pd.a_tid_g, pd.a_tid_l, pd.a_j_g, pd.a_j_l, pd.a_q_g, pd.a_q_l);
+  if (B) fill(qb, nullptr, pd.b_tid_l, nullptr, pd.b_j_l, nullptr, nullptr);
+  return pd;
+}
+
+template <typename T>
+void launch_pass(int wa, int wb, dim3 g, dim3 b, hipStream_t s, T* st, const PassDesc* pd,
+                 const JobConst* jc, const BlockRT* rta, const BlockRT* rtb,
+                 const Decision* da, Decision* db, double2* part, unsigned* cnt, uint8_t* rec,
+                 double* p1) {
+#define QEC_PASS(A, B)                                                                      \
+  if (wa == A && wb == B) {                                                                 \
+    hipLaunchKernelGGL((k_pass<T, A, B>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, part, cnt, \
+                       rec, p1);                                                            \
+    return;                                                                                 \
+  }
+  QEC_PASS(0, 2) QEC_PASS(0, 4) QEC_PASS(2, 0) QEC_PASS(2, 2) QEC_PASS(2, 4)
+  QEC_PASS(4, 0) QEC_PASS(4, 2) QEC_PASS(4, 4)
+#undef QEC_PASS
+}
+
+}  // namespace
+
+namespace {
+
+template <typename T>
+sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp) {
+  const int d = job->d, n = d * d, ns = (int)tp.blocks.size(), R = job->rounds;
+  const int tb = std::min(kTileMax, n);
+  const int per_traj = R * ns;
+  hipStream_t s = (hipStream_t)job->hip_stream;
+  DevBufs M;
+  T* st = nullptr;
+  double2* partials = nullptr;
+  unsigned* counter = nullptr;
+  TBlock* dblocks = nullptr;
+  PassDesc* dpass = nullptr;
+  JobConst* djc = nullptr;
+  double* deps = nullptr;
+  Decision* ddec = nullptr;
+  uint8_t* drec = nullptr;
+  uint8_t* dbits = nullptr;
+  double* dp1 = nullptr;
+  double* dsums = nullptr;
+  int* derr = nullptr;
+  BlockRT* drt = nullptr;
+  const uint64_t na = 1ull << n;
+  const int cb = std::min(12, n);
+  const size_t n_tiles = (size_t)1 << (n - tb);
+  // trajectories per prepare chunk: keep the block table under 64 MiB
+  const size_t rt_per_traj = sizeof(BlockRT) * (size_t)per_traj;
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)job->n_traj, ((size_t)64 << 20) / rt_per_traj));
+  const size_t nrec = (size_t)job->n_traj * per_traj;
+  HIP_OK(M.alloc(&st, sizeof(T) * 2 * na));
+  HIP_OK(M.alloc(&partials, sizeof(double2) * n_tiles));
+  HIP_OK(M.alloc(&counter, 256));
+  HIP_OK(M.alloc(&dblocks, sizeof(TBlock) * ns));
+  HIP_OK(M.alloc(&dpass, sizeof(PassDesc) * (ns + 2)));
+  HIP_OK(M.alloc(&djc, sizeof(JobConst)));
+  HIP_OK(M.alloc(&deps, sizeof(double) * std::max(1, tp.n_sites)));
+  HIP_OK(M.alloc(&ddec, sizeof(Decision) * (per_traj + 1)));
+  HIP_OK(M.alloc(&drec, nrec));
+  HIP_OK(M.alloc(&dbits, (size_t)job->n_traj * n));
+  if (res->p1_trace) HIP_OK(M.alloc(&dp1, sizeof(double) * nrec));
+  HIP_OK(M.alloc(&dsums, sizeof(double) << (n - cb)));
+  HIP_OK(M.alloc(&derr, sizeof(int)));
+  HIP_OK(M.alloc(&drt, rt_per_traj * chunk));
+
+  std::vector<PassDesc> pds(ns + 2);
+  pds[0] = make_pass(n, tb, nullptr, &tp.blocks[0], -1, 0);
+  for (int i = 0; i < ns; ++i)
+    pds[1 + i] = make_pass(n, tb, &tp.blocks[i], &tp.blocks[(i + 1) % ns], i, (i + 1) % ns);
+  pds[ns + 1] = make_pass(n, tb, &tp.blocks[ns - 1], nullptr, ns - 1, -1);
+  const JobConst jc = make_job_const(d, job->zeta);
+  std::vector<double> eps(std::max(1, tp.n_sites), job->eps);
+  if (job->eps_site)
+    for (int i = 0; i < tp.n_sites; ++i) eps[i] = job->eps_site[i];
+
+  HIP_OK(hipMemcpyAsync(dblocks, tp.blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(PassDesc) * (ns + 2), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(djc, &jc, sizeof jc, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(deps, eps.data(), sizeof(double) * eps.size(), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemsetAsync(counter, 0, 256, s));
+  HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
+  HIP_OK(hipMemsetAsync(ddec, 0, sizeof(Decision) * (per_traj + 1), s));
+
+  hipEvent_t ev0, ev1, evp0, evp1;
+  HIP_OK(hipEventCreate(&ev0));
+  HIP_OK(hipEventCreate(&ev1));
+  HIP_OK(hipEventCreate(&evp0));
+  HIP_OK(hipEventCreate(&evp1));
+  struct EvGuard {
+    hipEvent_t a, b, c, d;
+    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); (void)hipEventDestroy(d); }
+  } evg{ev0, ev1, evp0, evp1};
+  HIP_OK(hipEventRecord(ev0, s));
+
+  const dim3 grid((unsigned)n_tiles), block((unsigned)std::max(64, 1 << (tb - 4)));
+  const int draws_round = tp.n_draws;
+  const int last_t = job->n_traj - 1;
+  for (int c0 = 0; c0 < job->n_traj; c0 += chunk) {
+    const int cn = std::min(chunk, job->n_traj - c0);
+    const int64_t nthreads = (int64_t)cn * per_traj;
+    hipLaunchKernelGGL(k_prepare, dim3((unsigned)((nthreads + 127) / 128)), dim3(128), 0, s, dblocks,
+                       ns, R, draws_round, job->seed, job->traj0 + (uint64_t)c0, cn, job->p, deps,
+                       drt, derr);
+    HIP_OK(hipGetLastError());
+    for (int ti = 0; ti < cn; ++ti) {
+      const int tg = c0 + ti;
+      const BlockRT* rt = drt + (size_t)ti * per_traj;
+      uint8_t* rec = drec + (size_t)tg * per_traj;
+      double* p1 = dp1 ? dp1 + (size_t)tg * per_traj : nullptr;
+      launch_pass<T>(0, tp.blocks[0].w, grid, block, s, st, &dpass[0], djc, nullptr, rt, nullptr,
+                     &ddec[0], partials, counter, rec, p1);
+      if (tg == last_t) HIP_OK(hipEventRecord(evp0, s));
+      for (int bi = 0; bi < per_traj; ++bi) {
+        const int sidx = bi % ns;
+        const bool last = (bi == per_traj - 1);
+        const int pidx = last ? ns + 1 : 1 + sidx;
+        const int wb = last ? 0 : tp.blocks[(sidx + 1) % ns].w;
+        launch_pass<T>(tp.blocks[sidx].w, wb, grid, block, s, st, &dpass[pidx], djc, rt + bi,
+                       last ? nullptr : rt + bi + 1, &ddec[bi], &ddec[bi + 1], partials, counter,
+                       last ? nullptr : rec + bi + 1, (p1 && !last) ? p1 + bi + 1 : nullptr);
+      }
+      if (tg == last_t) HIP_OK(hipEventRecord(evp1, s));
+      HIP_OK(hipGetLastError());
+      if (res->final_states) {
+        HIP_OK(hipStreamSynchronize(s));
+        HIP_OK(hipMemcpy((char*)res->final_states + (size_t)tg * sizeof(T) * 2 * na, st,
+                         sizeof(T) * 2 * na, hipMemcpyDeviceToHost));
+      }
+      hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb)), dim3(256), 0, s, st, cb, dsums);
+      hipLaunchKernelGGL(k_final_measure<T>, dim3(1), dim3(1024), 0, s, st, n, cb, dsums,
+                         job->seed, job->traj0 + (uint64_t)tg,
+                         (uint64_t)R * (uint64_t)draws_round, dbits + (size_t)tg * n);
+      HIP_OK(hipGetLastError());
+    }
+  }
+  HIP_OK(hipEventRecord(ev1, s));
+  int herr = 0;
+  HIP_OK(hipMemcpyAsync(&herr, derr, sizeof herr, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (herr) return fail(SV_EINVAL, "circuit template is not monomial in its block basis");
+  // Records: the decision for block b is written by the pass before it; the
+  // record of the very first block lands at index 0 via the init pass.
+  HIP_OK(hipMemcpy(res->records, drec, nrec, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(res->final_bits, dbits, (size_t)job->n_traj * n, hipMemcpyDeviceToHost));
+  if (res->p1_trace) HIP_OK(hipMemcpy(res->p1_trace, dp1, sizeof(double) * nrec, hipMemcpyDeviceToHost));
+  float ms = 0.f, pms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, ev0, ev1));
+  HIP_OK(hipEventElapsedTime(&pms, evp0, evp1));
+  res->gpu_ms = ms;
+  res->pass_ms = pms / per_traj;
+  return SV_OK;
+}
+
+}  // namespace
+
+// ==================================================================== ABI ==
+struct sv_state_s {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int n = 0;
+  sv_dtype dt = SV_C128;
+  hipStream_t stream = nullptr;
+  bool owned = false;
+  double2* partials = nullptr;
+  unsigned* counter = nullptr;
+  MeasOut* mo = nullptr;
+};
+
+static constexpr int kMeasGrid = 1024;
+
+extern "C" {
+
+const char* sv_last_error(void) { return g_err.c_str(); }
+
+int sv_version(void) { return 100; }
+
+static size_t elem_size(sv_dtype dt) { return dt == SV_C128 ? 16 : 8; }
+
+static sv_status make_state(void* ptr, size_t bytes, int n, sv_dtype dt, void* stream, bool owned,
+                            sv_state* out) {
+  sv_state s = new (std::nothrow) sv_state_s;
+  if (!s) return fail(SV_ENOMEM, "host allocation failed");
+  s->ptr = ptr;
+  s->bytes = bytes;
+  s->n = n;
+  s->dt = dt;
+  s->stream = (hipStream_t)stream;
+  s->owned = owned;
+  void* scratch = nullptr;
+  const size_t sb = sizeof(double2) * kMeasGrid + 256 + sizeof(MeasOut);
+  if (hipMalloc(&scratch, sb) != hipSuccess) {
+    delete s;
+    return fail(SV_ENOMEM, "scratch allocation failed");
+  }
+  s->partials = (double2*)scratch;
+  s->counter = (unsigned*)((char*)scratch + sizeof(double2) * kMeasGrid);
+  s->mo = (MeasOut*)((char*)scratch + sizeof(double2) * kMeasGrid + 256);
+  if (hipMemset(s->counter, 0, 256) != hipSuccess) {
+    (void)hipFree(scratch);
+    delete s;
+    return fail(SV_EDEVICE, "memset failed");
+  }
+  *out = s;
+  return SV_OK;
+}
+
+sv_status sv_alloc(int n_qubits, sv_dtype dtype, void* hip_stream, sv_state* out) {
+  if (!out) return fail(SV_EINVAL, "out is NULL");
+  if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d out of 1..34", n_qubits);
+  if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
+  const size_t bytes = elem_size(dtype) << n_qubits;
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(SV_ENOMEM, "hipMalloc(%zu) failed", bytes);
+  sv_status st = make_state(p, bytes, n_qubits, dtype, hip_stream, true, out);
+  if (st != SV_OK) {
+    (void)hipFree(p);
+    return st;
+  }
+  return sv_set_basis(*out, 0);
+}
+
+sv_status sv_wrap(void* dev_ptr, size_t bytes, int n_qubits, sv_dtype dtype, void* hip_stream,
+                  sv_state* out) {
+  if (!out || !dev_ptr) return fail(SV_EINVAL, "NULL pointer");
+  if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d out of 1..34", n_qubits);
+  if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
+  if (((uintptr_t)dev_ptr) % 16) return fail(SV_EINVAL, "dev_ptr not 16-byte aligned");
+  const size_t need = elem_size(dtype) << n_qubits;
+  if (bytes < need) return fail(SV_EINVAL, "buffer of %zu bytes < %zu needed", bytes, need);
+  return make_state(dev_ptr, need, n_qubits, dtype, hip_stream, false, out);
+}
+
+sv_status sv_free(sv_state s) {
+  if (!s) return SV_OK;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->owned) (void)hipFree(s->ptr);
+  (void)hipFree(s->partials);
+  delete s;
+  return SV_OK;
+}
+
+sv_status sv_synchronize(sv_state s) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  HIP_OK(hipStreamSynchronize(s->stream));
+  return SV_OK;
+}
+
+sv_status sv_set_state(sv_state s, const void* host, size_t bytes) {
+  if (!s || !host) return fail(SV_EINVAL, "NULL pointer");
+  if (bytes != s->bytes) return fail(SV_EINVAL, "expected %zu bytes, got %zu", s->bytes, bytes);
+  HIP_OK(hipStreamSynchronize(s->stream));
+  HIP_OK(hipMemcpy(s->ptr, host, bytes, hipMemcpyHostToDevice));
+  return SV_OK;
+}
+
+sv_status sv_get_state(sv_state s, void* host, size_t bytes) {
+  if (!s || !host) return fail(SV_EINVAL, "NULL pointer");
+  if (bytes != s->bytes) return fail(SV_EINVAL, "expected %zu bytes, got %zu", s->bytes, bytes);
+  HIP_OK(hipStreamSynchronize(s->stream));
+  HIP_OK(hipMemcpy(host, s->ptr, bytes, hipMemcpyDeviceToHost));
+  return SV_OK;
+}
+
+static unsigned grid_for(uint64_t n, unsigned block) {
+  return (unsigned)((n + block - 1) / block);
+}
+
+sv_status sv_set_basis(sv_state s, uint64_t index) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  const uint64_t na = 1ull << s->n;
+  if (index >= na) return fail(SV_EINVAL, "basis index out of range");
+  if (s->dt == SV_C128)
+    hipLaunchKernelGGL(k_fill_basis<double>, dim3(grid_for(na, 256)), dim3(256), 0, s->stream,
+                       (double*)s->ptr, na, index);
+  else
+    hipLaunchKernelGGL(k_fill_basis<float>, dim3(grid_for(na, 256)), dim3(256), 0, s->stream,
+                       (float*)s->ptr, na, index);
+  HIP_OK(hipGetLastError());
+  return SV_OK;
+}
+
+sv_status sv_load_logical0(sv_state s, int d) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  if (d < 2 || d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", d);
+  if (s->n < d * d) return fail(SV_EINVAL, "register of %d qubits < d^2 = %d", s->n, d * d);
+  JobConst jc = make_job_const(d, 0.0);
+  JobConst* djc = nullptr;
+  HIP_OK(hipMalloc(&djc, sizeof(JobConst)));
+  hipError_t e = hipMemcpyAsync(djc, &jc, sizeof jc, hipMemcpyHostToDevice, s->stream);
+  const uint64_t na = 1ull << s->n;
+  if (e == hipSuccess) {
+    if (s->dt == SV_C128)
+      hipLaunchKernelGGL(k_logical0<double>, dim3(grid_for(na, 256)), dim3(256), 0, s->stream,
+                         (double*)s->ptr, na, djc);
+    else
+      hipLaunchKernelGGL(k_logical0<float>, dim3(grid_for(na, 256)), dim3(256), 0, s->stream,
+                         (float*)s->ptr, na, djc);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFree(djc);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "logical0: %s", hipGetErrorString(e));
+  return SV_OK;
+}
+
+static sv_status check_qubits(const sv_state s, int k, const int* qubits, int kmax) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  if (!qubits) return fail(SV_EINVAL, "NULL qubits");
+  if (k < 1 || k > kmax) return fail(SV_EINVAL, "k=%d out of 1..%d", k, kmax);
+  if (k > s->n) return fail(SV_EINVAL, "k=%d > n=%d", k, s->n);
+  for (int i = 0; i < k; ++i) {
+    if (qubits[i] < 0 || qubits[i] >= s->n) return fail(SV_EINVAL, "qubit %d out of range", qubits[i]);
+    for (int j = 0; j < i; ++j)
+      if (qubits[i] == qubits[j]) return fail(SV_EINVAL, "duplicate qubit %d", qubits[i]);
+  }
+  return SV_OK;
+}
+
+sv_status sv_apply_gate(sv_state s, int k, const int* qubits, const double* m) {
+  sv_status st = check_qubits(s, k, qubits, 2);
+  if (st != SV_OK) return st;
+  if (!m) return fail(SV_EINVAL, "NULL matrix");
+  const uint64_t na = 1ull << s->n;
+  if (k == 1) {
+    Mat2 M;
+    std::memcpy(M.m, m, sizeof M.m);
+    const uint64_t np = na >> 1;
+    if (s->dt == SV_C128)
+      hipLaunchKernelGGL(k_gate1<double>, dim3(grid_for(np, 256)), dim3(256), 0, s->stream,
+                         (double*)s->ptr, np, qubits[0], M);
+    else
+      hipLaunchKernelGGL(k_gate1<float>, dim3(grid_for(np, 256)), dim3(256), 0, s->stream,
+                         (float*)s->ptr, np, qubits[0], M);
+  } else {
+    Mat4 M;
+    std::memcpy(M.m, m, sizeof M.m);
+    const uint64_t nq = na >> 2;
+    if (s->dt == SV_C128)
+      hipLaunchKernelGGL(k_gate2<double>, dim3(grid_for(nq, 256)), dim3(256), 0, s->stream,
+                         (double*)s->ptr, nq, qubits[0], qubits[1], M);
+    else
+      hipLaunchKernelGGL(k_gate2<float>, dim3(grid_for(nq, 256)), dim3(256), 0, s->stream,
+                         (float*)s->ptr, nq, qubits[0], qubits[1], M);
+  }
+  HIP_OK(hipGetLastError());
+  return SV_OK;
+}
+
+sv_status sv_apply_diag(sv_state s, int k, const int* qubits, const double* phases) {
+  sv_status st = check_qubits(s, k, qubits, 5);
+  if (st != SV_OK) return st;
+  if (!phases) return fail(SV_EINVAL, "NULL phases");
+  Diag32 D{};
+  std::memcpy(D.ph, phases, sizeof(double) * 2 * (1 << k));
+  int q[5] = {0, 0, 0, 0, 0};
+  for (int i = 0; i < k; ++i) q[i] = qubits[i];
+  const uint64_t na = 1ull << s->n;
+  if (s->dt == SV_C128)
+    hipLaunchKernelGGL(k_diag<double>, dim3(grid_for(na, 256)), dim3(256), 0, s->stream,
+                       (double*)s->ptr, na, k, q[0], q[1], q[2], q[3], q[4], D);
+  else
+    hipLaunchKernelGGL(k_diag<float>, dim3(grid_for(na, 256)), dim3(256), 0, s->stream,
+                       (float*)s->ptr, na, k, q[0], q[1], q[2], q[3], q[4], D);
+  HIP_OK(hipGetLastError());
+  return SV_OK;
+}
+
+sv_status sv_apply_fused(sv_state s, int k, const int* qubits, const double* m) {
+  sv_status st = check_qubits(s, k, qubits, 5);
+  if (st != SV_OK) return st;
+  if (!m) return fail(SV_EINVAL, "NULL matrix");
+  const size_t mb = sizeof(double) * 2 * (1u << (2 * k));
+  double* dm = nullptr;
+  HIP_OK(hipMalloc(&dm, mb));
+  hipError_t e = hipMemcpyAsync(dm, m, mb, hipMemcpyHostToDevice, s->stream);
+  int q[5] = {0, 0, 0, 0, 0};
+  for (int i = 0; i < k; ++i) q[i] = qubits[i];
+  const uint64_t ng = 1ull << (s->n - k);
+  const dim3 g(grid_for(ng, 256)), b(256);
+#define QEC_FUSED(K)                                                                             \
+  case K:                                                                                       \
+    if (s->dt == SV_C128)                                                                       \
+      hipLaunchKernelGGL((k_fused<double, K>), g, b, 0, s->stream, (double*)s->ptr, ng, dm, q[0], \
+                         q[1], q[2], q[3], q[4]);                                               \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_fused<float, K>), g, b, 0, s->stream, (float*)s->ptr, ng, dm, q[0],   \
+                         q[1], q[2], q[3], q[4]);                                               \
+    break;
+  if (e == hipSuccess) {
+    switch (k) {
+      QEC_FUSED(1) QEC_FUSED(2) QEC_FUSED(3) QEC_FUSED(4) QEC_FUSED(5)
+    }
+    e = hipGetLastError();
+  }
+#undef QEC_FUSED
+  // the matrix buffer must outlive the kernel
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFree(dm);
+  if (e != hipSuccess) return fail(SV_EDEVICE, "apply_fused: %s", hipGetErrorString(e));
+  return SV_OK;
+}
+
+static sv_status measure_common(sv_state s, int anc, double u, int forced, int* outcome, double* p1) {
+  if (!s) return fail(SV_EINVAL, "NULL state");
+  if (anc < 0 || anc >= s->n) return fail(SV_EINVAL, "qubit %d out of range", anc);
+  const uint64_t na = 1ull << s->n;
+  const unsigned grid = (unsigned)std::min<uint64_t>(kMeasGrid, std::max<uint64_t>(1, na / 1024));
+  if (s->dt == SV_C128)
+    hipLaunchKernelGGL(k_measure_sums<double>, dim3(grid), dim3(256), 0, s->stream,
+                       (const double*)s->ptr, na, anc, u, forced, s->partials, s->counter, s->mo);
+  else
+    hipLaunchKernelGGL(k_measure_sums<float>, dim3(grid), dim3(256), 0, s->stream,
+                       (const float*)s->ptr, na, anc, u, forced, s->partials, s->counter, s->mo);
+  HIP_OK(hipGetLastError());
+  if (forced >= 0) {
+    MeasOut mo;
+    HIP_OK(hipMemcpyAsync(&mo, s->mo, sizeof mo, hipMemcpyDeviceToHost, s->stream));
+    HIP_OK(hipStreamSynchronize(s->stream));
+    const double pf = (forced ? mo.S1 : mo.S0) / (mo.S0 + mo.S1);
+    if (!(pf >= SV_TAU))
+      return fail(SV_ENUMERIC, "forced outcome %d has probability %.3e < %.1e", forced, pf, SV_TAU);
+  }
+  const uint64_t np = na >> 1;
+  if (s->dt == SV_C128)
+    hipLaunchKernelGGL(k_project<double>, dim3(grid_for(np, 256)), dim3(256), 0, s->stream,
+                       (double*)s->ptr, np, anc, s->mo);
+  else
+    hipLaunchKernelGGL(k_project<float>, dim3(grid_for(np, 256)), dim3(256), 0, s->stream,
+                       (float*)s->ptr, np, anc, s->mo);
+  HIP_OK(hipGetLastError());
+  MeasOut mo;
+  HIP_OK(hipMemcpyAsync(&mo, s->mo, sizeof mo, hipMemcpyDeviceToHost, s->stream));
+  HIP_OK(hipStreamSynchronize(s->stream));
+  if (outcome) *outcome = mo.m;
+  if (p1) *p1 = mo.p1;
+  return SV_OK;
+}
+
+sv_status sv_measure_reset_ancilla(sv_state s, int anc, double u, int* outcome, double* p1) {
+  if (!(u >= 0.0 && u < 1.0)) return fail(SV_EINVAL, "u must be in [0, 1)");
+  return measure_common(s, anc, u, -1, outcome, p1);
+}
+
+sv_status sv_measure_reset_ancilla_forced(sv_state s, int anc, int outcome, double* p1) {
+  if (outcome != 0 && outcome != 1) return fail(SV_EINVAL, "outcome must be 0 or 1");
+  return measure_common(s, anc, 0.0, outcome, nullptr, p1);
+}
+
+sv_status sv_template_info(int d, int gateset, int* n_stab, int* n_sites, int* n_draws_per_round) {
+  if (d < 2 || d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", d);
+  if (gateset != SV_GATESET_CR && gateset != SV_GATESET_TEXTBOOK) return fail(SV_EINVAL, "bad gateset");
+  const Template T = build_template(d, gateset);
+  if (n_stab) *n_stab = (int)T.blocks.size();
+  if (n_sites) *n_sites = T.n_sites;
+  if (n_draws_per_round) *n_draws_per_round = T.n_draws;
+  return SV_OK;
+}
+
+double sv_uniform(uint64_t seed, uint64_t t, uint64_t k) { return qec::uniform(seed, t, k); }
+
+sv_status sv_block_kraus(int d, int gateset, int stab, int round, uint64_t seed, uint64_t t,
+                         double p, double eps, const double* eps_site, double* D, uint32_t* F,
+                         double* u, int* type, int* w, int* qubits) {
+  if (d < 2 || d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", d);
+  if (gateset != SV_GATESET_CR && gateset != SV_GATESET_TEXTBOOK) return fail(SV_EINVAL, "bad gateset");
+  if (!D || !F || !u || !type || !w || !qubits) return fail(SV_EINVAL, "NULL output");
+  const Template tp = build_template(d, gateset);
+  if (stab < 0 || stab >= (int)tp.blocks.size() || round < 0) return fail(SV_EINVAL, "bad block");
+  std::vector<double> es(std::max(1, tp.n_sites), eps);
+  if (eps_site)
+    for (int i = 0; i < tp.n_sites; ++i) es[i] = eps_site[i];
+  const TBlock& b = tp.blocks[stab];
+  uint8_t pauli[kMaxOps];
+  BlockRT rt;
+  const uint64_t k0 = (uint64_t)round * (uint64_t)tp.n_draws + (uint64_t)b.draw_off;
+  draw_block(b, seed, t, k0, p, pauli, &rt.u);
+  if (!build_block(b, es.data(), pauli, rt)) return fail(SV_EINVAL, "block is not monomial");
+  std::memcpy(D, rt.D, sizeof rt.D);
+  *F = rt.F;
+  *u = rt.u;
+  *type = b.type;
+  *w = b.w;
+  for (int l = 0; l < b.w; ++l) qubits[l] = b.qubit[l];
+  return SV_OK;
+}
+
+sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
+  if (!job || !res) return fail(SV_EINVAL, "NULL job or result");
+  if (job->d < 2 || job->d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", job->d);
+  if (job->gateset != SV_GATESET_CR && job->gateset != SV_GATESET_TEXTBOOK)
+    return fail(SV_EINVAL, "bad gateset %d", job->gateset);
+  if (job->rounds < 1 || job->rounds > 100000) return fail(SV_EINVAL, "rounds=%d", job->rounds);
+  if (job->dtype != SV_C64 && job->dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
+  if (job->n_traj < 0) return fail(SV_EINVAL, "n_traj < 0");
+  if (job->flags != 0) return fail(SV_EINVAL, "flags must be 0");
+  if (!(job->p >= 0.0 && job->p <= 1.0)) return fail(SV_EINVAL, "p out of [0, 1]");
+  if (!std::isfinite(job->eps) || !std::isfinite(job->zeta)) return fail(SV_EINVAL, "non-finite eps/zeta");
+  if (!res->records || !res->final_bits) return fail(SV_EINVAL, "records and final_bits are required");
+  const Template tp = build_template(job->d, job->gateset);
+  if (job->eps_site)
+    for (int i = 0; i < tp.n_sites; ++i)
+      if (!std::isfinite(job->eps_site[i])) return fail(SV_EINVAL, "non-finite eps_site[%d]", i);
+  res->gpu_ms = 0.0;
+  res->pass_ms = 0.0;
+  if (job->n_traj == 0) return SV_OK;
+  if (job->dtype == SV_C128) return run_rounds_t<double>(job, res, tp);
+  return run_rounds_t<float>(job, res, tp);
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+"""GPU parity of sv_run_rounds (the trajectory engine) against the CPU oracle.
+
+Same seeded draws on both sides (Philox4x32-10 keyed by the seed, counter =
+(draw index, trajectory)): syndrome records and final data bits must agree
+bit for bit; p1 and the data register before the final measurement to 1e-10
+in complex128.  In complex64 (amplitudes in float32, probabilities and
+renormalisation in float64) the register must agree to 1e-5 and records bit
+for bit for these seeds.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2204_11404_amd as qs
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GS = {"cr": oracle.GATESET_CR, "textbook": oracle.GATESET_TEXTBOOK}
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "d5_cr_oracle.npz")
+
+
+def _compare(d, gateset, R, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0, dtype="c128",
+             traj0=0, atol=1e-10):
+    print(f"case rounds d={d} {gateset} R={R} n={n_traj} p={p} eps={eps} zeta={zeta} {dtype}",
+          flush=True)
+    g = qs.run_rounds(d, gateset, R, n_traj, seed, p, eps=eps, eps_site=eps_site, zeta=zeta,
+                      dtype=dtype, traj0=traj0, want_p1=True, want_states=True)
+    for i in range(n_traj):
+        o = oracle.run_trajectory(d, GS[gateset], R, seed, traj0 + i, p, eps=eps, eps_site=eps_site,
+                                  zeta=zeta, want_state=True)
+        assert np.array_equal(g["records"][i], o["records"]), f"trajectory {i}"
+        assert np.array_equal(g["final_bits"][i], o["final_bits"]), f"trajectory {i}"
+        assert np.max(np.abs(g["p1"][i] - o["p1"])) < atol
+        assert np.max(np.abs(g["states"][i] - o["state"])) < atol
+    return g
+
+
+@pytest.mark.parametrize("gateset", ["cr", "textbook"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_small_distance_parity(gateset, d):
+    _compare(d, gateset, 3, 40, seed=7, p=0.02, eps=0.03, zeta=0.02)
+
+
+def test_d3_textbook_workload_parity():
+    c = workloads.CONFIGS["d3_textbook_c128"]
+    _compare(3, "textbook", c["rounds"], 200, c["seed"], c["p"], eps=c["eps"])
+
+
+def test_d4_parity_spans_several_tiles():
+    # 16 data qubits: 2^16 amplitudes = 16 tiles of 2^12
+    n_sites = oracle.template_counts(4, oracle.GATESET_CR)[1]
+    eps = workloads.eps_sites(n_sites, (0.0, 0.05), 3)
+    _compare(4, "cr", 2, 4, seed=3, p=0.01, eps_site=eps, zeta=0.01)
+
+
+def test_noiseless_records_are_trivial():
+    g = qs.run_rounds(3, "cr", 4, 8, 0, 0.0)
+    r0 = np.array([(sum(1 for q in s if q) // 2) % 2 for _, s in oracle.layout(3)], dtype=np.uint8)
+    assert np.array_equal(g["records"], np.broadcast_to(r0, g["records"].shape))
+
+
+@pytest.mark.parametrize("d", [3, 4])
+def test_complex64_parity(d):
+    n_sites = oracle.template_counts(d, oracle.GATESET_CR)[1]
+    eps = workloads.eps_sites(n_sites, (0.0, 0.05), 11)
+    _compare(d, "cr", 2, 6 if d == 4 else 30, seed=11, p=0.01, eps_site=eps, zeta=0.01,
+             dtype="c64", atol=1e-5)
+
+
+def test_deterministic_and_resumable():
+    kw = dict(d=4, gateset="cr", rounds=2, seed=5, p=0.02, eps=0.02, zeta=0.01, want_p1=True)
+    a = qs.run_rounds(n_traj=4, traj0=0, **kw)
+    b = qs.run_rounds(n_traj=4, traj0=0, **kw)
+    c = qs.run_rounds(n_traj=2, traj0=2, **kw)
+    assert np.array_equal(a["records"], b["records"])
+    assert np.array_equal(a["p1"], b["p1"])  # bitwise: fixed reduction order
+    assert np.array_equal(a["final_bits"], b["final_bits"])
+    assert np.array_equal(a["records"][2:], c["records"])
+    assert np.array_equal(a["final_bits"][2:], c["final_bits"])
+
+
+def test_d5_full_size_against_stored_oracle():
+    """26-qubit cross-resonance workload (p=1e-3, theta ~ U[0,0.05) per site,
+    zeta=0.01) in the benchmark's launch configuration: records, p1, final
+    bits and 4096 sampled amplitudes against the oracle's stored run."""
+    z = np.load(GOLDEN)
+    traj = [int(t) for t in z["traj"]]
+    R, seed = int(z["rounds"]), int(z["seed"])
+    print(f"case d5 golden traj={traj} R={R}", flush=True)
+    g = qs.run_rounds(5, "cr", R, len(traj), seed, float(z["p"]), eps_site=z["eps"],
+                      zeta=float(z["zeta"]), traj0=traj[0], want_p1=True, want_states=True)
+    for i, t in enumerate(traj):
+        assert np.array_equal(g["records"][i], z[f"records_{t}"])
+        assert np.array_equal(g["final_bits"][i], z[f"final_bits_{t}"])
+        assert np.max(np.abs(g["p1"][i] - z[f"p1_{t}"])) < 1e-10
+        st = g["states"][i]
+        assert np.max(np.abs(st[z["idx"]] - z[f"amps_{t}"])) < 1e-10
+        assert np.max(np.abs(st[z[f"top_idx_{t}"]] - z[f"top_amps_{t}"])) < 1e-10
+        assert abs(np.linalg.norm(st) - 1.0) < 1e-10
+
+
+def test_d5_bench_config_properties():
+    """The full d=5, 5-round benchmark workload for a few trajectories: the
+    register stays normalised, runs are bit-reproducible, and detection
+    events are rare at p = 1e-3."""
+    c = workloads.CONFIGS["d5_cr_c128"]
+    n_sites = qs.template_info(5, "cr")[1]
+    eps = workloads.eps_sites(n_sites, c["theta"], c["seed"])
+    kw = dict(d=5, gateset="cr", rounds=c["rounds"], n_traj=2, seed=c["seed"], p=c["p"],
+              eps_site=eps, zeta=c["zeta"])
+    a = qs.run_rounds(want_states=True, want_p1=True, **kw)
+    b = qs.run_rounds(want_p1=True, **kw)
+    assert np.array_equal(a["records"], b["records"])
+    assert np.array_equal(a["p1"], b["p1"])
+    for st in a["states"]:
+        assert abs(np.linalg.norm(st) - 1.0) < 1e-10
+    r0 = np.array([(sum(1 for q in s if q) // 2) % 2 for _, s in oracle.layout(5)], dtype=np.uint8)
+    flips = a["records"] ^ r0
+    det = flips ^ np.concatenate([np.zeros_like(flips[:, :1]), flips[:, :-1]], axis=1)
+    assert det.mean() < 0.1
