@@ -42,6 +42,23 @@ def cpu_baseline(c, eps, n_blocks):
                       f"(26 qubits, complex128, gate by gate), {sec:.1f} s, scaled to one round"}
 
 
+def copy_calibration(qs, torch, steps):
+    """Plain copy of a 2^26-amplitude complex128 register (1 GiB read + 1 GiB
+    written per launch) with the library's streaming copy kernel."""
+    a, b = qs.State(26, "c128"), qs.State(26, "c128")
+    b.copy_from(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        b.copy_from(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
+                      "copy_ms": ms, "copy_gbs": 2 * (1 << 30) / (ms * 1e-3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +67,8 @@ def main():
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--cpu-blocks", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="time only the library's plain register copy (HBM calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -60,6 +79,9 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
+    if args.copy_only:
+        copy_calibration(qs, torch, args.steps)
+        return
     c = dict(workloads.CONFIGS["d5_cr_c128"])
     d, R = c["d"], c["rounds"]
     n_stab, n_sites, _ = qs.template_info(d, "cr")

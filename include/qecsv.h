@@ -97,6 +97,11 @@ sv_status sv_free(sv_state s);
 sv_status sv_set_state(sv_state s, const void* host, size_t bytes);
 sv_status sv_get_state(sv_state s, void* host, size_t bytes);
 
+/* Copy the amplitudes of src into dst (same n_qubits and dtype) with a
+ * streaming device kernel on dst's stream (waits for src's stream first if it
+ * differs).  Asynchronous on dst's stream. */
+sv_status sv_copy_state(sv_state dst, sv_state src);
+
 /* |index>. */
 sv_status sv_set_basis(sv_state s, uint64_t index);
 

@@ -58,6 +58,7 @@ _SIGS = {
     "sv_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "sv_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "sv_set_basis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "sv_copy_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sv_load_logical0": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sv_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
     "sv_apply_gate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -91,6 +92,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP extension missing: {LIB_PATH} (run __graft_entry__.build())")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one; load it first so the library binds to the runtime that owns
+        # torch's device memory and streams (one runtime per process).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
@@ -192,6 +200,9 @@ class State:
         a = np.empty(1 << self.n, dtype=_NP[self.dtype])
         _check(lib().sv_get_state(self.h, a.ctypes.data, a.nbytes))
         return a
+
+    def copy_from(self, other):
+        _check(lib().sv_copy_state(self.h, other.h))
 
     def set_basis(self, index):
         _check(lib().sv_set_basis(self.h, int(index)))

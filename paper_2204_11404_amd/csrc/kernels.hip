@@ -122,162 +122,213 @@ __global__ void k_prepare(const TBlock* __restrict__ blocks, int n_stab, int rou
 // -------------------------------------------------------------------- pass --
 constexpr int kTileMax = 12;  // 4096 amplitudes per tile
 
+// What follows the applied block in a pass: nothing (last circuit of the
+// trajectory), a Z check (S_m is a pointwise sum over the tile: no data
+// exchange), or an X check (S_m needs a Walsh-Hadamard transform over the
+// check's qubits: the tile is regrouped through LDS).
+enum : int { B_NONE = 0, B_ZCHECK = 1, B_XCHECK = 2 };
+
 template <typename T>
 struct PassLds {
   T v[2 << kTileMax];
 };
 
-template <typename T, int WA, int WB>
-__global__ __launch_bounds__(256) void k_pass(
-    T* __restrict__ st, const PassDesc* __restrict__ pd, const JobConst* __restrict__ jc,
-    const BlockRT* __restrict__ rta, const BlockRT* __restrict__ rtb,
-    const Decision* __restrict__ dec_a, Decision* __restrict__ dec_b,
-    double2* __restrict__ partials, unsigned* __restrict__ counter,
-    uint8_t* __restrict__ rec_b, double* __restrict__ p1_b) {
+// Phase 2 for an X check: regroup the tile through LDS by the check's qubits.
+template <typename T, int WB>
+__device__ __forceinline__ void xcheck_sums(const C2<T>* o, uint32_t lt_a, const PassDesc* pd,
+                                            uint32_t fl, const double* wt, bool active,
+                                            double& s0, double& s1) {
   __shared__ PassLds<T> sh;
-  __shared__ double red[16];
-  __shared__ int is_last;
-  const int tid = threadIdx.x;
-  const int tb = pd->tb;
-  const int nt = 1 << (tb - 4);
-  const bool active = tid < nt;
-
-  uint32_t base = 0;
-  for (int i = 0; i < pd->n_outer; ++i)
-    if ((blockIdx.x >> i) & 1u) base |= pd->outer_bit[i];
-
-  // ---------------- phase 1: apply block a (or write logical |0>) ----------
   if (active) {
-    uint32_t gt = 0, lt = 0;
-    for (int i = 0; i < tb - 4; ++i)
-      if ((tid >> i) & 1) {
-        gt |= pd->a_tid_g[i];
-        lt |= pd->a_tid_l[i];
-      }
-    C2<T> v[16];
-    if constexpr (WA == 0) {
-      const T amp = (T)jc->amp0;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        uint32_t x = base | gt | pd->a_j_g[j];
-        for (int i = 0; i < jc->n_x; ++i)
-          if (x & jc->span_piv[i]) x ^= jc->span_vec[i];
-        v[j] = {x == 0 ? amp : (T)0, (T)0};
-        const uint32_t g = base | gt | pd->a_j_g[j];
-        st2(st, g, v[j]);
-        st2(sh.v, lslot(lt | pd->a_j_l[j]), v[j]);
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) v[j] = ld2(st, base | gt | pd->a_j_g[j]);
-      const int m = dec_a->m;
-      const double scale = 1.0 / sqrt(dec_a->Sm);
-      const uint32_t F = rta->F;
-      const double* D = &rta->D[m][0][0];
-      constexpr int NA = 1 << WA;
-      if (pd->typea == 0) {
-#pragma unroll
-        for (int hi = 0; hi < 16; hi += NA) {
-          wht<T, WA>(v + hi);
-#pragma unroll
-          for (int x = 0; x < NA; ++x) v[hi + x] = mulc(v[hi + x], (T)D[2 * x], (T)D[2 * x + 1]);
-          wht<T, WA>(v + hi);
-#pragma unroll
-          for (int x = 0; x < NA; ++x)
-            if (__popc((uint32_t)x & F) & 1) v[hi + x] = {-v[hi + x].re, -v[hi + x].im};
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const int x = j & (NA - 1);
-          v[j] = mulc(v[j], (T)D[2 * x], (T)D[2 * x + 1]);
-        }
-      }
-      // destination: XOR permutation of block a's bits for Z checks
-      uint32_t fg = 0, fl = 0;
-      if (pd->typea != 0) {
-#pragma unroll
-        for (int l = 0; l < WA; ++l)
-          if ((F >> l) & 1) {
-            fg |= pd->a_q_g[l];
-            fl |= pd->a_q_l[l];
-          }
-      }
-      const int use_zz = jc->use_zz;
-      const int d = jc->d;
-      const uint32_t hm = jc->hmask, vm = jc->vmask;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const uint32_t g = (base | gt | pd->a_j_g[j]) ^ fg;
-        C2<T> o = v[j];
-        if (use_zz) {
-          const int k = __popc((g ^ (g >> 1)) & hm) + __popc((g ^ (g >> d)) & vm);
-          o = mulc(o, (T)jc->zz[2 * k], (T)jc->zz[2 * k + 1]);
-        }
-        if constexpr (sizeof(T) == 8) {
-          o.re *= scale;
-          o.im *= scale;
-        } else {
-          o.re = (T)((double)o.re * scale);
-          o.im = (T)((double)o.im * scale);
-        }
-        st2(st, g, o);
-        if constexpr (WB != 0) st2(sh.v, lslot((lt | pd->a_j_l[j]) ^ fl), o);
-      }
-    }
+    for (int j = 0; j < 16; ++j) st2(sh.v, lslot((lt_a | pd->a_j_l[j]) ^ fl), o[j]);
   }
-  if constexpr (WB == 0) return;
-
   __syncthreads();
-  // ---------------- phase 2: S_0, S_1 of block b ----------------------------
-  double s0 = 0.0, s1 = 0.0;
   if (active) {
     uint32_t lt = 0;
-    for (int i = 0; i < tb - 4; ++i)
-      if ((tid >> i) & 1) lt |= pd->b_tid_l[i];
+    for (int i = 0; i < pd->tb - 4; ++i)
+      if ((threadIdx.x >> i) & 1) lt |= pd->b_tid_l[i];
     C2<T> v[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = ld2(sh.v, lslot(lt | pd->b_j_l[j]));
-    constexpr int NB = (WB == 0) ? 1 : (1 << WB);
-    const double* W0 = rtb->W[0];
-    const double* W1 = rtb->W[1];
+    constexpr int NB = 1 << WB;
 #pragma unroll
     for (int hi = 0; hi < 16; hi += NB) {
-      if (pd->typeb == 0) wht<T, WB>(v + hi);
+      wht<T, WB>(v + hi);
 #pragma unroll
       for (int x = 0; x < NB; ++x) {
         const double re = (double)v[hi + x].re, im = (double)v[hi + x].im;
         const double a2 = re * re + im * im;
-        s0 += W0[x] * a2;
-        s1 += W1[x] * a2;
+        s0 += wt[x] * a2;
+        s1 += wt[16 + x] * a2;
       }
     }
   }
-  block_sum2(s0, s1, red);
-  if (tid == 0) {
-    __hip_atomic_store(&partials[blockIdx.x].x, s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&partials[blockIdx.x].y, s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    is_last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
+  __syncthreads();  // the tile buffer is reused by the next tile
+}
+
+// One pass: apply block a's Kraus operator for its decided outcome (or write
+// logical |0> when WA == 0), the ZZ layer and 1/sqrt(S_m); accumulate S_0,
+// S_1 of block b.  Each workgroup handles `tpw` consecutive tiles and writes
+// one partial pair.
+template <typename T, int WA, int WB, int BMODE>
+__global__ __launch_bounds__(256) void k_pass(
+    T* __restrict__ st, const PassDesc* __restrict__ pd, const JobConst* __restrict__ jc,
+    const BlockRT* __restrict__ rta, const BlockRT* __restrict__ rtb,
+    const Decision* __restrict__ dec_a, double2* __restrict__ partials, int tpw, int reverse) {
+  __shared__ double red[16];
+  __shared__ double wtab[32];
+  __shared__ C2<T> zzt[64];
+  const int tid = threadIdx.x;
+  const int tb = pd->tb;
+  const int nt = 1 << (tb - 4);
+  const bool active = tid < nt;
+  const int use_zz = (WA != 0) && jc->use_zz;
+
+  if (BMODE != B_NONE && tid < 32) wtab[tid] = rtb->W[tid >> 4][tid & 15];
+  if (use_zz && tid <= jc->n_edges) zzt[tid] = C2<T>{(T)jc->zz[2 * tid], (T)jc->zz[2 * tid + 1]};
   __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+
+  uint32_t gt = 0, lt = 0, lbt = 0;
+  for (int i = 0; i < tb - 4; ++i)
+    if ((tid >> i) & 1) {
+      gt |= pd->a_tid_g[i];
+      lt |= pd->a_tid_l[i];
+      lbt |= pd->a_tid_lb[i];
+    }
+  // decided outcome of block a and the operator's XOR pattern
+  int m = 0;
+  double scale = 1.0;
+  uint32_t F = 0, fg = 0, fl = 0, lbf = 0;
+  if constexpr (WA != 0) {
+    m = dec_a->m;
+    scale = 1.0 / sqrt(dec_a->Sm);
+    F = rta->F;
+    if (pd->typea != 0) {  // Z checks move amplitude x to x XOR F on the check's qubits
+      for (int l = 0; l < WA; ++l)
+        if ((F >> l) & 1) {
+          fg |= pd->a_q_g[l];
+          fl |= pd->a_q_l[l];
+          lbf ^= pd->a_q_lb[l];
+        }
+    }
+  }
+  const int d = jc->d;
+  const uint32_t hm = jc->hmask, vm = jc->vmask;
+  double s0 = 0.0, s1 = 0.0;
+
+  const int wg = reverse ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+  for (int tile = wg * tpw; tile < (wg + 1) * tpw; ++tile) {
+    uint32_t base = 0;
+    for (int i = 0; i < pd->n_outer; ++i)
+      if ((tile >> i) & 1) base |= pd->outer_bit[i];
+    C2<T> o[16];
+    if (active) {
+      if constexpr (WA == 0) {
+        const T amp = (T)jc->amp0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const uint32_t g = base | gt | pd->a_j_g[j];
+          uint32_t x = g;
+          for (int i = 0; i < jc->n_x; ++i)
+            if (x & jc->span_piv[i]) x ^= jc->span_vec[i];
+          o[j] = {x == 0 ? amp : (T)0, (T)0};
+          st2(st, g, o[j]);
+        }
+      } else {
+        C2<T> v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = ld2(st, base | gt | pd->a_j_g[j]);
+        const double* D = &rta->D[m][0][0];
+        constexpr int NA = 1 << WA;
+        if (pd->typea == 0) {
+#pragma unroll
+          for (int hi = 0; hi < 16; hi += NA) {
+            wht<T, WA>(v + hi);
+#pragma unroll
+            for (int x = 0; x < NA; ++x) v[hi + x] = mulc(v[hi + x], (T)D[2 * x], (T)D[2 * x + 1]);
+            wht<T, WA>(v + hi);
+#pragma unroll
+            for (int x = 0; x < NA; ++x)
+              if (__popc((uint32_t)x & F) & 1) v[hi + x] = {-v[hi + x].re, -v[hi + x].im};
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            const int x = j & (NA - 1);
+            v[j] = mulc(v[j], (T)D[2 * x], (T)D[2 * x + 1]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const uint32_t g = (base | gt | pd->a_j_g[j]) ^ fg;
+          C2<T> r = v[j];
+          if (use_zz) {
+            const int k = __popc((g ^ (g >> 1)) & hm) + __popc((g ^ (g >> d)) & vm);
+            const C2<T> z = zzt[k];
+            r = mulc(r, z.re, z.im);
+          }
+          if constexpr (sizeof(T) == 8) {
+            r.re *= scale;
+            r.im *= scale;
+          } else {
+            r.re = (T)((double)r.re * scale);
+            r.im = (T)((double)r.im * scale);
+          }
+          st2(st, g, r);
+          o[j] = r;
+        }
+      }
+      if constexpr (BMODE == B_ZCHECK) {
+        // local index of each output amplitude on block b's qubits
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const uint32_t x = (lbt | pd->a_j_lb[j]) ^ lbf;
+          const double re = (double)o[j].re, im = (double)o[j].im;
+          const double a2 = re * re + im * im;
+          s0 += wtab[x] * a2;
+          s1 += wtab[16 + x] * a2;
+        }
+      }
+    }
+    if constexpr (BMODE == B_XCHECK) xcheck_sums<T, WB>(o, lt, pd, fl, wtab, active, s0, s1);
+  }
+  if constexpr (BMODE == B_NONE) return;
+  block_sum2(s0, s1, red);
+  if (tid == 0) partials[wg] = make_double2(s0, s1);
+}
+
+// Outcome of block b: reduce the per-tile partials in a fixed order, clamp
+// p1, compare with the block's measurement draw.
+__global__ __launch_bounds__(1024) void k_decide(const double2* __restrict__ partials, int n,
+                                                 const BlockRT* __restrict__ rtb,
+                                                 Decision* __restrict__ dec_b,
+                                                 uint8_t* __restrict__ rec_b,
+                                                 double* __restrict__ p1_b) {
+  __shared__ double red[32];
   double a0 = 0.0, a1 = 0.0;
-  for (unsigned i = tid; i < gridDim.x; i += blockDim.x) {
-    a0 += __hip_atomic_load(&partials[i].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a1 += __hip_atomic_load(&partials[i].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // up to 8 independent loads in flight per thread, summed in a fixed order
+  for (int i0 = 0; i0 < n; i0 += 8 * (int)blockDim.x) {
+    double2 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = i0 + k * (int)blockDim.x + (int)threadIdx.x;
+      v[k] = i < n ? partials[i] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      a0 += v[k].x;
+      a1 += v[k].y;
+    }
   }
   block_sum2(a0, a1, red);
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     const double p1 = clamp_p1(a1 / (a0 + a1));
     const int m = (rtb->u < p1) ? 1 : 0;
     dec_b->m = m;
     dec_b->Sm = m ? a1 : a0;
     *rec_b = (uint8_t)m;
     if (p1_b) *p1_b = p1;
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -362,6 +413,21 @@ __global__ __launch_bounds__(1024) void k_final_measure(const T* __restrict__ st
 }
 
 // --------------------------------------------------------- register ops --
+// Plain streaming copy, 16-byte elements, four per thread per iteration.
+__global__ __launch_bounds__(256) void k_copy16(double2* __restrict__ dst,
+                                                const double2* __restrict__ src, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 4;
+  for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x) * 4 + threadIdx.x; i < n; i += stride) {
+    double2 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i + (uint64_t)k * blockDim.x < n) v[k] = src[i + (uint64_t)k * blockDim.x];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i + (uint64_t)k * blockDim.x < n) dst[i + (uint64_t)k * blockDim.x] = v[k];
+  }
+}
+
 struct Mat2 { double m[8]; };
 struct Mat4 { double m[32]; };
 struct Diag32 { double ph[64]; };
@@ -486,7 +552,7 @@ __global__ __launch_bounds__(256) void k_fused(T* __restrict__ st, uint64_t n_gr
   }
 }
 
-// S0 / S1 over bit q; last workgroup decides (forced >= 0 overrides u).
+// S0 / S1 over bit q: per-workgroup partial sums (fixed order).
 struct MeasOut {
   double S0, S1, p1;
   int m;
@@ -495,12 +561,8 @@ struct MeasOut {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_measure_sums(const T* __restrict__ st, uint64_t n_amp, int q,
-                                                      double u, int forced,
-                                                      double2* __restrict__ partials,
-                                                      unsigned* __restrict__ counter,
-                                                      MeasOut* __restrict__ out) {
+                                                      double2* __restrict__ partials) {
   __shared__ double red[16];
-  __shared__ int is_last;
   double s0 = 0.0, s1 = 0.0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_amp; i += stride) {
@@ -509,20 +571,19 @@ __global__ __launch_bounds__(256) void k_measure_sums(const T* __restrict__ st, 
     if ((i >> q) & 1) s1 += w; else s0 += w;
   }
   block_sum2(s0, s1, red);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&partials[blockIdx.x].x, s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&partials[blockIdx.x].y, s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    is_last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+  if (threadIdx.x == 0) partials[blockIdx.x] = make_double2(s0, s1);
+}
+
+// Reduce the partials in a fixed order and decide (forced >= 0 overrides u).
+__global__ __launch_bounds__(256) void k_measure_decide(const double2* __restrict__ partials, int n,
+                                                        double u, int forced,
+                                                        MeasOut* __restrict__ out) {
+  __shared__ double red[16];
   double a0 = 0.0, a1 = 0.0;
-  for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
-    a0 += __hip_atomic_load(&partials[i].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a1 += __hip_atomic_load(&partials[i].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double2 v = partials[i];
+    a0 += v.x;
+    a1 += v.y;
   }
   block_sum2(a0, a1, red);
   if (threadIdx.x == 0) {
@@ -531,7 +592,6 @@ __global__ __launch_bounds__(256) void k_measure_sums(const T* __restrict__ st, 
     out->S1 = a1;
     out->p1 = p1;
     out->m = forced >= 0 ? forced : ((u < p1) ? 1 : 0);
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

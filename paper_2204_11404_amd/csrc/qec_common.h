@@ -315,6 +315,11 @@ struct PassDesc {
   uint32_t a_q_g[4], a_q_l[4];  // global / LDS bit of block a's local bit
   uint32_t b_tid_l[8];
   uint32_t b_j_l[16];
+  // local index on block b's qubits carried by each phase-1 bit (pointwise
+  // S_m of a following Z check)
+  uint32_t a_tid_lb[8];
+  uint32_t a_j_lb[16];
+  uint32_t a_q_lb[4];
 };
 
 struct JobConst {

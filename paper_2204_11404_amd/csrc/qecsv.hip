@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -306,22 +307,50 @@ PassDesc make_pass(int n, int tb_max, const TBlock* A, const TBlock* B, int ia, 
   };
   fill(qa, pd.a_tid_g, pd.a_tid_l, pd.a_j_g, pd.a_j_l, pd.a_q_g, pd.a_q_l);
   if (B) fill(qb, nullptr, pd.b_tid_l, nullptr, pd.b_j_l, nullptr, nullptr);
+  // block-b local index carried by each phase-1 bit
+  auto lb = [&](uint32_t gbits) {
+    uint32_t x = 0;
+    for (int l = 0; l < pd.wb; ++l)
+      if (gbits & (1u << qb[l])) x |= 1u << l;
+    return x;
+  };
+  for (int i = 0; i < tb - 4; ++i) pd.a_tid_lb[i] = lb(pd.a_tid_g[i]);
+  for (int j = 0; j < 16; ++j) pd.a_j_lb[j] = lb(pd.a_j_g[j]);
+  for (int l = 0; l < pd.wa; ++l) pd.a_q_lb[l] = lb(pd.a_q_g[l]);
   return pd;
 }
 
+// Tiles per workgroup of the fused pass: QECSV_TILES_PER_WG if set (power of
+// two), else 1 (measured fastest on gfx950 for 2^25-amplitude registers).
+int pass_tiles_per_wg(size_t n_tiles) {
+  int tpw = 1;
+  if (const char* e = std::getenv("QECSV_TILES_PER_WG")) tpw = std::max(1, std::atoi(e));
+  while (tpw > 1 && (n_tiles % (size_t)tpw) != 0) tpw >>= 1;
+  if ((size_t)tpw > n_tiles) tpw = (int)n_tiles;
+  return tpw;
+}
+
+// Alternate the tile traversal direction between consecutive passes so that a
+// pass starts on the lines its predecessor wrote last (QECSV_SNAKE=0 turns it
+// off).
+int pass_snake_order() {
+  if (const char* e = std::getenv("QECSV_SNAKE")) return std::atoi(e) != 0;
+  return 1;
+}
+
 template <typename T>
-void launch_pass(int wa, int wb, dim3 g, dim3 b, hipStream_t s, T* st, const PassDesc* pd,
-                 const JobConst* jc, const BlockRT* rta, const BlockRT* rtb,
-                 const Decision* da, Decision* db, double2* part, unsigned* cnt, uint8_t* rec,
-                 double* p1) {
-#define QEC_PASS(A, B)                                                                      \
-  if (wa == A && wb == B) {                                                                 \
-    hipLaunchKernelGGL((k_pass<T, A, B>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, part, cnt, \
-                       rec, p1);                                                            \
-    return;                                                                                 \
+void launch_pass(int wa, int wb, int bmode, dim3 g, dim3 b, hipStream_t s, T* st,
+                 const PassDesc* pd, const JobConst* jc, const BlockRT* rta, const BlockRT* rtb,
+                 const Decision* da, double2* part, int tpw, int rev) {
+#define QEC_PASS(A, B, M)                                                                       \
+  if (wa == A && wb == B && bmode == M) {                                                       \
+    hipLaunchKernelGGL((k_pass<T, A, B, M>), g, b, 0, s, st, pd, jc, rta, rtb, da, part, tpw, rev); \
+    return;                                                                                     \
   }
-  QEC_PASS(0, 2) QEC_PASS(0, 4) QEC_PASS(2, 0) QEC_PASS(2, 2) QEC_PASS(2, 4)
-  QEC_PASS(4, 0) QEC_PASS(4, 2) QEC_PASS(4, 4)
+  QEC_PASS(0, 2, B_XCHECK) QEC_PASS(0, 4, B_XCHECK) QEC_PASS(0, 2, B_ZCHECK) QEC_PASS(0, 4, B_ZCHECK)
+  QEC_PASS(2, 0, B_NONE) QEC_PASS(4, 0, B_NONE)
+  QEC_PASS(2, 2, B_XCHECK) QEC_PASS(2, 4, B_XCHECK) QEC_PASS(4, 2, B_XCHECK) QEC_PASS(4, 4, B_XCHECK)
+  QEC_PASS(2, 2, B_ZCHECK) QEC_PASS(2, 4, B_ZCHECK) QEC_PASS(4, 2, B_ZCHECK) QEC_PASS(4, 4, B_ZCHECK)
 #undef QEC_PASS
 }
 
@@ -338,7 +367,6 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp) {
   DevBufs M;
   T* st = nullptr;
   double2* partials = nullptr;
-  unsigned* counter = nullptr;
   TBlock* dblocks = nullptr;
   PassDesc* dpass = nullptr;
   JobConst* djc = nullptr;
@@ -359,7 +387,6 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp) {
   const size_t nrec = (size_t)job->n_traj * per_traj;
   HIP_OK(M.alloc(&st, sizeof(T) * 2 * na));
   HIP_OK(M.alloc(&partials, sizeof(double2) * n_tiles));
-  HIP_OK(M.alloc(&counter, 256));
   HIP_OK(M.alloc(&dblocks, sizeof(TBlock) * ns));
   HIP_OK(M.alloc(&dpass, sizeof(PassDesc) * (ns + 2)));
   HIP_OK(M.alloc(&djc, sizeof(JobConst)));
@@ -386,22 +413,26 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp) {
   HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(PassDesc) * (ns + 2), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(djc, &jc, sizeof jc, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(deps, eps.data(), sizeof(double) * eps.size(), hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemsetAsync(counter, 0, 256, s));
   HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
   HIP_OK(hipMemsetAsync(ddec, 0, sizeof(Decision) * (per_traj + 1), s));
 
-  hipEvent_t ev0, ev1, evp0, evp1;
-  HIP_OK(hipEventCreate(&ev0));
-  HIP_OK(hipEventCreate(&ev1));
-  HIP_OK(hipEventCreate(&evp0));
-  HIP_OK(hipEventCreate(&evp1));
-  struct EvGuard {
-    hipEvent_t a, b, c, d;
-    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); (void)hipEventDestroy(d); }
-  } evg{ev0, ev1, evp0, evp1};
+  // whole-run events plus one pair around every pass of the last trajectory
+  struct Events {
+    std::vector<hipEvent_t> ev;
+    ~Events() {
+      for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+  } E;
+  E.ev.resize(2 + 2 * per_traj, nullptr);
+  for (auto& e : E.ev) HIP_OK(hipEventCreate(&e));
+  hipEvent_t ev0 = E.ev[0], ev1 = E.ev[1];
+  hipEvent_t* evs = E.ev.data() + 2;
   HIP_OK(hipEventRecord(ev0, s));
 
-  const dim3 grid((unsigned)n_tiles), block((unsigned)std::max(64, 1 << (tb - 4)));
+  const int tpw = pass_tiles_per_wg(n_tiles);
+  const int snake = pass_snake_order();
+  const size_t n_wg = n_tiles / tpw;
+  const dim3 grid((unsigned)n_wg), block((unsigned)std::max(64, 1 << (tb - 4)));
   const int draws_round = tp.n_draws;
   const int last_t = job->n_traj - 1;
   for (int c0 = 0; c0 < job->n_traj; c0 += chunk) {
@@ -416,19 +447,26 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp) {
       const BlockRT* rt = drt + (size_t)ti * per_traj;
       uint8_t* rec = drec + (size_t)tg * per_traj;
       double* p1 = dp1 ? dp1 + (size_t)tg * per_traj : nullptr;
-      launch_pass<T>(0, tp.blocks[0].w, grid, block, s, st, &dpass[0], djc, nullptr, rt, nullptr,
-                     &ddec[0], partials, counter, rec, p1);
-      if (tg == last_t) HIP_OK(hipEventRecord(evp0, s));
+      auto bmode_of = [&](int blk) { return tp.blocks[blk].type == 0 ? B_XCHECK : B_ZCHECK; };
+      launch_pass<T>(0, tp.blocks[0].w, bmode_of(0), grid, block, s, st, &dpass[0], djc, nullptr,
+                     rt, nullptr, partials, tpw, 0);
+      hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, partials, (int)n_wg, rt, &ddec[0],
+                         rec, p1);
+      const bool timed = (tg == last_t);
       for (int bi = 0; bi < per_traj; ++bi) {
         const int sidx = bi % ns;
         const bool last = (bi == per_traj - 1);
         const int pidx = last ? ns + 1 : 1 + sidx;
-        const int wb = last ? 0 : tp.blocks[(sidx + 1) % ns].w;
-        launch_pass<T>(tp.blocks[sidx].w, wb, grid, block, s, st, &dpass[pidx], djc, rt + bi,
-                       last ? nullptr : rt + bi + 1, &ddec[bi], &ddec[bi + 1], partials, counter,
-                       last ? nullptr : rec + bi + 1, (p1 && !last) ? p1 + bi + 1 : nullptr);
+        const int nb = (sidx + 1) % ns;
+        if (timed) HIP_OK(hipEventRecord(evs[2 * bi], s));
+        launch_pass<T>(tp.blocks[sidx].w, last ? 0 : tp.blocks[nb].w, last ? B_NONE : bmode_of(nb),
+                       grid, block, s, st, &dpass[pidx], djc, rt + bi, last ? nullptr : rt + bi + 1,
+                       &ddec[bi], partials, tpw, snake ? ((bi + 1) & 1) : 0);
+        if (timed) HIP_OK(hipEventRecord(evs[2 * bi + 1], s));
+        if (!last)
+          hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, partials, (int)n_wg,
+                             rt + bi + 1, &ddec[bi + 1], rec + bi + 1, p1 ? p1 + bi + 1 : nullptr);
       }
-      if (tg == last_t) HIP_OK(hipEventRecord(evp1, s));
       HIP_OK(hipGetLastError());
       if (res->final_states) {
         HIP_OK(hipStreamSynchronize(s));
@@ -452,11 +490,16 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp) {
   HIP_OK(hipMemcpy(res->records, drec, nrec, hipMemcpyDeviceToHost));
   HIP_OK(hipMemcpy(res->final_bits, dbits, (size_t)job->n_traj * n, hipMemcpyDeviceToHost));
   if (res->p1_trace) HIP_OK(hipMemcpy(res->p1_trace, dp1, sizeof(double) * nrec, hipMemcpyDeviceToHost));
-  float ms = 0.f, pms = 0.f;
+  float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, ev0, ev1));
-  HIP_OK(hipEventElapsedTime(&pms, evp0, evp1));
+  double pass_sum = 0.0;
+  for (int bi = 0; bi < per_traj; ++bi) {
+    float pm = 0.f;
+    HIP_OK(hipEventElapsedTime(&pm, evs[2 * bi], evs[2 * bi + 1]));
+    pass_sum += pm;
+  }
   res->gpu_ms = ms;
-  res->pass_ms = pms / per_traj;
+  res->pass_ms = pass_sum / per_traj;
   return SV_OK;
 }
 
@@ -471,7 +514,6 @@ struct sv_state_s {
   hipStream_t stream = nullptr;
   bool owned = false;
   double2* partials = nullptr;
-  unsigned* counter = nullptr;
   MeasOut* mo = nullptr;
 };
 
@@ -502,13 +544,7 @@ static sv_status make_state(void* ptr, size_t bytes, int n, sv_dtype dt, void* s
     return fail(SV_ENOMEM, "scratch allocation failed");
   }
   s->partials = (double2*)scratch;
-  s->counter = (unsigned*)((char*)scratch + sizeof(double2) * kMeasGrid);
   s->mo = (MeasOut*)((char*)scratch + sizeof(double2) * kMeasGrid + 256);
-  if (hipMemset(s->counter, 0, 256) != hipSuccess) {
-    (void)hipFree(scratch);
-    delete s;
-    return fail(SV_EDEVICE, "memset failed");
-  }
   *out = s;
   return SV_OK;
 }
@@ -572,6 +608,20 @@ sv_status sv_get_state(sv_state s, void* host, size_t bytes) {
 
 static unsigned grid_for(uint64_t n, unsigned block) {
   return (unsigned)((n + block - 1) / block);
+}
+
+sv_status sv_copy_state(sv_state dst, sv_state src) {
+  if (!dst || !src) return fail(SV_EINVAL, "NULL state");
+  if (dst->n != src->n || dst->dt != src->dt) return fail(SV_EINVAL, "registers differ in size or dtype");
+  if (dst->ptr == src->ptr) return SV_OK;
+  // order the copy after both registers' pending work, on dst's stream
+  if (src->stream != dst->stream) HIP_OK(hipStreamSynchronize(src->stream));
+  const uint64_t n16 = dst->bytes / 16;
+  const unsigned grid = (unsigned)std::min<uint64_t>((n16 + 4 * 256 - 1) / (4 * 256), 1u << 20);
+  hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, dst->stream, (double2*)dst->ptr,
+                     (const double2*)src->ptr, n16);
+  HIP_OK(hipGetLastError());
+  return SV_OK;
 }
 
 sv_status sv_set_basis(sv_state s, uint64_t index) {
@@ -716,10 +766,12 @@ static sv_status measure_common(sv_state s, int anc, double u, int forced, int* 
   const unsigned grid = (unsigned)std::min<uint64_t>(kMeasGrid, std::max<uint64_t>(1, na / 1024));
   if (s->dt == SV_C128)
     hipLaunchKernelGGL(k_measure_sums<double>, dim3(grid), dim3(256), 0, s->stream,
-                       (const double*)s->ptr, na, anc, u, forced, s->partials, s->counter, s->mo);
+                       (const double*)s->ptr, na, anc, s->partials);
   else
     hipLaunchKernelGGL(k_measure_sums<float>, dim3(grid), dim3(256), 0, s->stream,
-                       (const float*)s->ptr, na, anc, u, forced, s->partials, s->counter, s->mo);
+                       (const float*)s->ptr, na, anc, s->partials);
+  hipLaunchKernelGGL(k_measure_decide, dim3(1), dim3(256), 0, s->stream, s->partials, (int)grid, u,
+                     forced, s->mo);
   HIP_OK(hipGetLastError());
   if (forced >= 0) {
     MeasOut mo;

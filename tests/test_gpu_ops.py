@@ -141,3 +141,14 @@ def test_invalid_arguments_rejected_before_launch():
     with pytest.raises(qs.SvError):
         s.load_logical0(3)  # 6 qubits < 9
     assert np.array_equal(s.get(), np.eye(1, 64, 0, dtype=np.complex128)[0])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_copy_state(dtype):
+    n = 15
+    a, ref = _state(n, dtype, 77)
+    b = qs.State(n, dtype)
+    b.copy_from(a)
+    assert np.array_equal(b.get(), a.get())
+    with pytest.raises(qs.SvError):
+        b.copy_from(qs.State(n - 1, dtype))
