@@ -186,6 +186,38 @@ typedef struct sv_result {
  * final data measurement.  Synchronous.  Records are the raw ancilla bits. */
 sv_status sv_run_rounds(const sv_job* job, sv_result* res);
 
+/* Batched small-distance trajectories: one persistent launch runs n_traj
+ * trajectories, each with its own round count, depolarizing probability and
+ * per-site over-rotation exponents.  Trajectory i uses draw stream traj0 + i
+ * and is the same trajectory sv_run_rounds computes for those parameters
+ * (same draw enumeration, same records and final bits).  d = 2 or 3 keep the
+ * whole data register in LDS; d = 4 streams it from HBM, one workgroup per
+ * trajectory.  Synchronous. */
+typedef struct sv_batch_job {
+  int d;                    /* 2..4 */
+  int gateset;              /* sv_gateset */
+  int dtype;                /* sv_dtype */
+  int n_traj;
+  int max_rounds;           /* >= every rounds[i] */
+  int flags;                /* reserved, must be 0 */
+  uint64_t traj0;
+  uint64_t seed;
+  const int* rounds;        /* host [n_traj], each in 1..max_rounds */
+  const double* p;          /* host [n_traj], each in [0, 1] */
+  const double* eps_site;   /* host [n_traj][n_sites] exponents, or NULL */
+  double eps;               /* every site of every trajectory if eps_site is NULL */
+  double zeta;
+  void* hip_stream;
+} sv_batch_job;
+
+typedef struct sv_batch_result {
+  uint8_t* records;     /* host [n_traj][max_rounds][d^2-1]; rows past rounds[i] are 0 */
+  uint8_t* final_bits;  /* host [n_traj][d^2] */
+  double gpu_ms;        /* out: device time of the launch (hipEvents) */
+} sv_batch_result;
+
+sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res);
+
 /* Philox4x32-10 uniform used by the device code, evaluated on the host (for
  * tests of the draw stream). */
 double sv_uniform(uint64_t seed, uint64_t t, uint64_t k);

@@ -47,6 +47,24 @@ class Result(ctypes.Structure):
     ]
 
 
+class BatchJob(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int), ("gateset", ctypes.c_int), ("dtype", ctypes.c_int),
+        ("n_traj", ctypes.c_int), ("max_rounds", ctypes.c_int), ("flags", ctypes.c_int),
+        ("traj0", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+        ("rounds", ctypes.POINTER(ctypes.c_int)), ("p", ctypes.POINTER(ctypes.c_double)),
+        ("eps_site", ctypes.POINTER(ctypes.c_double)), ("eps", ctypes.c_double),
+        ("zeta", ctypes.c_double), ("hip_stream", ctypes.c_void_p),
+    ]
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [
+        ("records", ctypes.POINTER(ctypes.c_uint8)), ("final_bits", ctypes.POINTER(ctypes.c_uint8)),
+        ("gpu_ms", ctypes.c_double),
+    ]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "sv_last_error": (ctypes.c_char_p, []),
@@ -74,6 +92,7 @@ _SIGS = {
     "sv_template_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "sv_run_rounds": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(Result)]),
+    "sv_run_batch": (ctypes.c_int, [ctypes.POINTER(BatchJob), ctypes.POINTER(BatchResult)]),
     "sv_uniform": (ctypes.c_double, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]),
     "sv_block_kraus": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
@@ -271,3 +290,39 @@ def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta
     _check(lib().sv_run_rounds(ctypes.byref(job), ctypes.byref(res)))
     del keep
     return dict(records=rec, final_bits=fb, p1=p1, states=states, gpu_ms=res.gpu_ms, pass_ms=res.pass_ms)
+
+
+def run_batch(d, gateset, rounds, p, seed, eps=0.0, eps_site=None, zeta=0.0, dtype="c64", traj0=0,
+              max_rounds=None, stream=None):
+    """sv_run_batch: rounds and p are per-trajectory arrays; eps_site is None
+    or [n_traj, n_sites].  Returns dict(records[n_traj, max_rounds, n_stab],
+    final_bits[n_traj, d*d], gpu_ms)."""
+    rounds = np.ascontiguousarray(rounds, dtype=np.int32)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    n_traj = int(rounds.size)
+    if p.shape != (n_traj,):
+        raise ValueError("p must have one entry per trajectory")
+    n_stab, n_sites, _ = template_info(d, gateset)
+    mr = int(max_rounds if max_rounds is not None else (rounds.max() if n_traj else 1))
+    job = BatchJob()
+    job.d, job.gateset, job.dtype = d, _GATESETS[gateset], _DTYPES[dtype]
+    job.n_traj, job.max_rounds, job.flags = n_traj, mr, 0
+    job.traj0, job.seed = int(traj0), int(seed)
+    job.rounds = rounds.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    job.p = _dptr(p)
+    keep = None
+    if eps_site is not None:
+        keep = np.ascontiguousarray(eps_site, dtype=np.float64)
+        if keep.shape != (n_traj, n_sites):
+            raise ValueError(f"eps_site must be [{n_traj}, {n_sites}]")
+        job.eps_site = _dptr(keep)
+    job.eps, job.zeta = float(eps), float(zeta)
+    job.hip_stream = _stream_ptr(stream)
+    rec = np.zeros((n_traj, mr, n_stab), dtype=np.uint8)
+    fb = np.zeros((n_traj, d * d), dtype=np.uint8)
+    res = BatchResult()
+    res.records = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    res.final_bits = fb.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    _check(lib().sv_run_batch(ctypes.byref(job), ctypes.byref(res)))
+    del keep
+    return dict(records=rec, final_bits=fb, gpu_ms=res.gpu_ms)

@@ -177,93 +177,108 @@ QEC_HD void anc_rot(int axis, double theta, cd& v0, cd& v1) {
   }
 }
 
-// Builds BlockRT for one block instance.  pauli[i] is the Pauli code drawn for
-// op i (0 = none; for two-qubit locations the pair index 1..15).  Returns
-// false if an op is not monomial in the block basis.
+// Runs the ops of block b on the ancilla 2-vector for the block-basis input
+// label x (ancilla starting in |0>), with pauli[i] the Pauli code drawn for op
+// i (0 = none; for two-qubit locations the pair index 1..15).  Returns the
+// ancilla amplitudes (v0, v1) = (D_0(x), D_1(x)) before normalisation and the
+// output label in *cur; false if an op is not monomial in the block basis.
+QEC_HD bool track_column(const TBlock& b, const double* eps_site, const uint8_t* pauli, int x,
+                         cd& v0, cd& v1, uint32_t* cur_out) {
+  const bool xb = (b.type == 0);
+  const double q4 = 0.78539816339744830962;  // pi/4
+  v0 = {1.0, 0.0};
+  v1 = {0.0, 0.0};
+  uint32_t cur = (uint32_t)x;
+  for (int i = 0; i < b.n_ops; ++i) {
+    const TOp& op = b.ops[i];
+    const double beta = (op.quarter ? q4 : 0.0) + (op.site >= 0 ? eps_site[op.site] : 0.0);
+    switch (op.kind) {
+      case OP_ROT_ANC:
+        anc_rot(op.axis, beta * (double)op.sgn, v0, v1);
+        break;
+      case OP_ROT_DATA: {
+        if ((xb && op.axis != 1) || (!xb && op.axis != 3)) return false;
+        const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
+        const cd ph = cexpi(-beta * e * (double)op.sgn);
+        v0 = cmul(v0, ph);
+        v1 = cmul(v1, ph);
+        break;
+      }
+      case OP_CR_AD: {
+        if (!xb) return false;
+        const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
+        v0 = cmul(v0, cexpi(-beta * e));
+        v1 = cmul(v1, cexpi(beta * e));
+        break;
+      }
+      case OP_CR_DA: {
+        if (xb) return false;
+        const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
+        anc_rot(1, beta * e, v0, v1);
+        break;
+      }
+      case OP_H_ANC: {
+        const double h = 0.70710678118654752440;
+        cd a{(v0.re + v1.re) * h, (v0.im + v1.im) * h};
+        cd c{(v0.re - v1.re) * h, (v0.im - v1.im) * h};
+        v0 = a; v1 = c;
+        break;
+      }
+      case OP_CNOT_AD: {
+        if (!xb) return false;
+        if ((cur >> op.j) & 1) v1 = {-v1.re, -v1.im};
+        break;
+      }
+      case OP_CZ_AD: {
+        if (xb) return false;
+        if ((cur >> op.j) & 1) v1 = {-v1.re, -v1.im};
+        break;
+      }
+      case OP_N1_ANC:
+        anc_pauli(pauli[i], v0, v1);
+        break;
+      case OP_N1_DATA: {
+        const cd ph = data_pauli(pauli[i], xb, op.j, cur);
+        v0 = cmul(v0, ph);
+        v1 = cmul(v1, ph);
+        break;
+      }
+      case OP_N2_AD: {
+        const int pj = pauli[i];
+        anc_pauli(pj >> 2, v0, v1);
+        const cd ph = data_pauli(pj & 3, xb, op.j, cur);
+        v0 = cmul(v0, ph);
+        v1 = cmul(v1, ph);
+        break;
+      }
+      case OP_N2_DA: {
+        const int pj = pauli[i];
+        const cd ph = data_pauli(pj >> 2, xb, op.j, cur);
+        v0 = cmul(v0, ph);
+        v1 = cmul(v1, ph);
+        anc_pauli(pj & 3, v0, v1);
+        break;
+      }
+      default:
+        return false;
+    }
+  }
+  *cur_out = cur;
+  return true;
+}
+
+// Builds BlockRT for one block instance from the Pauli codes of its noise
+// locations.  Returns false if an op is not monomial in the block basis.
 QEC_HD bool build_block(const TBlock& b, const double* eps_site, const uint8_t* pauli,
                         BlockRT& out) {
   const bool xb = (b.type == 0);
   const int n = 1 << b.w;
   const double norm = xb ? 1.0 / (double)n : 1.0;
-  const double q4 = 0.78539816339744830962;  // pi/4
   uint32_t F = 0;
   for (int x = 0; x < n; ++x) {
-    cd v0{1.0, 0.0}, v1{0.0, 0.0};
-    uint32_t cur = (uint32_t)x;
-    for (int i = 0; i < b.n_ops; ++i) {
-      const TOp& op = b.ops[i];
-      const double beta = (op.quarter ? q4 : 0.0) + (op.site >= 0 ? eps_site[op.site] : 0.0);
-      switch (op.kind) {
-        case OP_ROT_ANC:
-          anc_rot(op.axis, beta * (double)op.sgn, v0, v1);
-          break;
-        case OP_ROT_DATA: {
-          if ((xb && op.axis != 1) || (!xb && op.axis != 3)) return false;
-          const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
-          const cd ph = cexpi(-beta * e * (double)op.sgn);
-          v0 = cmul(v0, ph);
-          v1 = cmul(v1, ph);
-          break;
-        }
-        case OP_CR_AD: {
-          if (!xb) return false;
-          const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
-          v0 = cmul(v0, cexpi(-beta * e));
-          v1 = cmul(v1, cexpi(beta * e));
-          break;
-        }
-        case OP_CR_DA: {
-          if (xb) return false;
-          const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
-          anc_rot(1, beta * e, v0, v1);
-          break;
-        }
-        case OP_H_ANC: {
-          const double h = 0.70710678118654752440;
-          cd a{(v0.re + v1.re) * h, (v0.im + v1.im) * h};
-          cd c{(v0.re - v1.re) * h, (v0.im - v1.im) * h};
-          v0 = a; v1 = c;
-          break;
-        }
-        case OP_CNOT_AD: {
-          if (!xb) return false;
-          if ((cur >> op.j) & 1) v1 = {-v1.re, -v1.im};
-          break;
-        }
-        case OP_CZ_AD: {
-          if (xb) return false;
-          if ((cur >> op.j) & 1) v1 = {-v1.re, -v1.im};
-          break;
-        }
-        case OP_N1_ANC:
-          anc_pauli(pauli[i], v0, v1);
-          break;
-        case OP_N1_DATA: {
-          const cd ph = data_pauli(pauli[i], xb, op.j, cur);
-          v0 = cmul(v0, ph);
-          v1 = cmul(v1, ph);
-          break;
-        }
-        case OP_N2_AD: {
-          const int pj = pauli[i];
-          anc_pauli(pj >> 2, v0, v1);
-          const cd ph = data_pauli(pj & 3, xb, op.j, cur);
-          v0 = cmul(v0, ph);
-          v1 = cmul(v1, ph);
-          break;
-        }
-        case OP_N2_DA: {
-          const int pj = pauli[i];
-          const cd ph = data_pauli(pj >> 2, xb, op.j, cur);
-          v0 = cmul(v0, ph);
-          v1 = cmul(v1, ph);
-          anc_pauli(pj & 3, v0, v1);
-          break;
-        }
-        default:
-          return false;
-      }
-    }
+    cd v0, v1;
+    uint32_t cur = 0;
+    if (!track_column(b, eps_site, pauli, x, v0, v1, &cur)) return false;
     F = cur ^ (uint32_t)x;
     out.D[0][x][0] = v0.re * norm;
     out.D[0][x][1] = v0.im * norm;

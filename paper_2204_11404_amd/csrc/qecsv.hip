@@ -18,6 +18,7 @@
 #include "qecsv.h"
 #include "qec_common.h"
 #include "kernels.hip"
+#include "kernels_batch.hip"
 
 using namespace qec;
 
@@ -503,6 +504,125 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp) {
   return SV_OK;
 }
 
+// Lane / register maps of the small-register batch kernel for each block
+// template: a lane's 16 amplitudes span the check's qubits (low bits of the
+// local index) plus the lowest other bits; the remaining bits index lanes.
+std::vector<SmallDesc> make_small_descs(int n, const Template& tp) {
+  std::vector<SmallDesc> out(tp.blocks.size());
+  for (size_t i = 0; i < tp.blocks.size(); ++i) {
+    const TBlock& b = tp.blocks[i];
+    SmallDesc sd{};
+    std::vector<int> rest;
+    for (int bit = 0; bit < n; ++bit) {
+      bool in = false;
+      for (int l = 0; l < b.w; ++l) in = in || (b.qubit[l] == bit);
+      if (!in) rest.push_back(bit);
+    }
+    const int nh = 4 - b.w;
+    for (int j = 0; j < 16; ++j) {
+      uint32_t g = 0;
+      for (int l = 0; l < b.w; ++l)
+        if ((j >> l) & 1) g |= 1u << b.qubit[l];
+      for (int hbit = 0; hbit < nh; ++hbit)
+        if ((j >> (b.w + hbit)) & 1) g |= 1u << rest[hbit];
+      sd.j_off[j] = g;
+    }
+    sd.n_lane_bits = n - 4;
+    for (int k = 0; k < n - 4; ++k) sd.lane_bit[k] = 1u << rest[nh + k];
+    for (int l = 0; l < b.w; ++l) sd.q_bit[l] = 1u << b.qubit[l];
+    out[i] = sd;
+  }
+  return out;
+}
+
+int device_cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 256;
+  return cus;
+}
+
+int env_int(const char* name, int dflt) {
+  if (const char* e = std::getenv(name)) return std::atoi(e);
+  return dflt;
+}
+
+template <typename T>
+sv_status run_batch_t(const sv_batch_job* job, sv_batch_result* res, const Template& tp) {
+  const int d = job->d, n = d * d, ns = (int)tp.blocks.size();
+  const int nt = job->n_traj;
+  if (n > kSmallBits) return fail(SV_EINVAL, "d=%d batch path not available", d);
+  hipStream_t s = (hipStream_t)job->hip_stream;
+  DevBufs M;
+  TBlock* dblocks = nullptr;
+  SmallDesc* dsd = nullptr;
+  JobConst* djc = nullptr;
+  int *dorder = nullptr, *drounds = nullptr, *derr = nullptr;
+  double *dp = nullptr, *deps = nullptr;
+  uint8_t *drec = nullptr, *dbits = nullptr;
+  const size_t nrec = (size_t)nt * job->max_rounds * ns;
+  const int eps_stride = job->eps_site ? tp.n_sites : 0;
+  const size_t neps = job->eps_site ? (size_t)nt * tp.n_sites : (size_t)std::max(1, tp.n_sites);
+  HIP_OK(M.alloc(&dblocks, sizeof(TBlock) * ns));
+  HIP_OK(M.alloc(&dsd, sizeof(SmallDesc) * ns));
+  HIP_OK(M.alloc(&djc, sizeof(JobConst)));
+  HIP_OK(M.alloc(&dorder, sizeof(int) * nt));
+  HIP_OK(M.alloc(&drounds, sizeof(int) * nt));
+  HIP_OK(M.alloc(&derr, sizeof(int)));
+  HIP_OK(M.alloc(&dp, sizeof(double) * nt));
+  HIP_OK(M.alloc(&deps, sizeof(double) * neps));
+  HIP_OK(M.alloc(&drec, nrec));
+  HIP_OK(M.alloc(&dbits, (size_t)nt * n));
+  // longest trajectories first, so the static assignment balances
+  std::vector<int> order(nt);
+  for (int i = 0; i < nt; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return job->rounds[a] > job->rounds[b]; });
+  const std::vector<SmallDesc> sd = make_small_descs(n, tp);
+  const JobConst jc = make_job_const(d, job->zeta);
+  std::vector<double> epsv;
+  if (!job->eps_site) epsv.assign(neps, job->eps);
+  HIP_OK(hipMemcpyAsync(dblocks, tp.blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dsd, sd.data(), sizeof(SmallDesc) * ns, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(djc, &jc, sizeof jc, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dorder, order.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(drounds, job->rounds, sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dp, job->p, sizeof(double) * nt, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(deps, job->eps_site ? job->eps_site : epsv.data(), sizeof(double) * neps,
+                        hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemsetAsync(drec, 0, nrec, s));
+  HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
+  struct Ev {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Ev() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  HIP_OK(hipEventCreate(&ev.a));
+  HIP_OK(hipEventCreate(&ev.b));
+  const int per_cu = std::max(1, env_int("QECSV_BATCH_WAVES_PER_CU", 12));
+  const int max_wg = device_cu_count() * per_cu;
+  const int grid = std::max(1, std::min((nt + 1) / 2, max_wg));
+  HIP_OK(hipEventRecord(ev.a, s));
+  hipLaunchKernelGGL(k_batch_small<T>, dim3(grid), dim3(64), 0, s, dblocks, dsd, ns, n, tp.n_draws,
+                     tp.n_sites, djc, job->seed, job->traj0, dorder, nt, drounds, dp, deps,
+                     eps_stride, drec, job->max_rounds, dbits, derr);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipEventRecord(ev.b, s));
+  int herr = 0;
+  HIP_OK(hipMemcpyAsync(&herr, derr, sizeof herr, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (herr) return fail(SV_EINVAL, "circuit template is not monomial in its block basis");
+  HIP_OK(hipMemcpy(res->records, drec, nrec, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(res->final_bits, dbits, (size_t)nt * n, hipMemcpyDeviceToHost));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, ev.a, ev.b));
+  res->gpu_ms = ms;
+  return SV_OK;
+}
+
 }  // namespace
 
 // ==================================================================== ABI ==
@@ -866,6 +986,31 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
   if (job->n_traj == 0) return SV_OK;
   if (job->dtype == SV_C128) return run_rounds_t<double>(job, res, tp);
   return run_rounds_t<float>(job, res, tp);
+}
+
+sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res) {
+  if (!job || !res) return fail(SV_EINVAL, "NULL job or result");
+  if (job->d < 2 || job->d > 4) return fail(SV_EINVAL, "d=%d out of 2..4", job->d);
+  if (job->gateset != SV_GATESET_CR && job->gateset != SV_GATESET_TEXTBOOK)
+    return fail(SV_EINVAL, "bad gateset %d", job->gateset);
+  if (job->dtype != SV_C64 && job->dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
+  if (job->n_traj < 0 || job->max_rounds < 1) return fail(SV_EINVAL, "bad n_traj / max_rounds");
+  if (job->flags != 0) return fail(SV_EINVAL, "flags must be 0");
+  if (!job->rounds || !job->p) return fail(SV_EINVAL, "rounds and p are required");
+  if (!res->records || !res->final_bits) return fail(SV_EINVAL, "records and final_bits are required");
+  if (!std::isfinite(job->eps) || !std::isfinite(job->zeta)) return fail(SV_EINVAL, "non-finite eps/zeta");
+  for (int i = 0; i < job->n_traj; ++i) {
+    if (job->rounds[i] < 1 || job->rounds[i] > job->max_rounds)
+      return fail(SV_EINVAL, "rounds[%d]=%d out of 1..%d", i, job->rounds[i], job->max_rounds);
+    if (!(job->p[i] >= 0.0 && job->p[i] <= 1.0)) return fail(SV_EINVAL, "p[%d] out of [0, 1]", i);
+  }
+  const Template tp = build_template(job->d, job->gateset);
+  if (job->eps_site)
+    for (size_t i = 0; i < (size_t)job->n_traj * tp.n_sites; ++i)
+      if (!std::isfinite(job->eps_site[i])) return fail(SV_EINVAL, "non-finite eps_site");
+  res->gpu_ms = 0.0;
+  if (job->n_traj == 0) return SV_OK;
+  return job->dtype == SV_C128 ? run_batch_t<double>(job, res, tp) : run_batch_t<float>(job, res, tp);
 }
 
 }  // extern "C"
