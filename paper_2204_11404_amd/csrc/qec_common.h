@@ -94,6 +94,7 @@ struct TBlock {
   int n_draws;       // noise draws + 1 measurement draw
   int draw_off;      // first draw of this block within the round
   int site_off;      // first site of this block within the round
+  uint32_t n2mask;   // bit k set if noise draw k is a two-qubit location
   TOp ops[kMaxOps];
 };
 
@@ -160,9 +161,8 @@ QEC_HD cd data_pauli(int P, bool xbasis, int j, uint32_t& cur) {
   return ph;
 }
 
-// exp(-i theta P) on the ancilla 2-vector.
-QEC_HD void anc_rot(int axis, double theta, cd& v0, cd& v1) {
-  const double c = cos(theta), s = sin(theta);
+// exp(-i theta P) on the ancilla 2-vector given c = cos(theta), s = sin(theta).
+QEC_HD void anc_rot_cs(int axis, double c, double s, cd& v0, cd& v1) {
   if (axis == 1) {  // [[c, -is], [-is, c]]
     cd a{c * v0.re + s * v1.im, c * v0.im - s * v1.re};
     cd b{c * v1.re + s * v0.im, c * v1.im - s * v0.re};
@@ -172,34 +172,59 @@ QEC_HD void anc_rot(int axis, double theta, cd& v0, cd& v1) {
     cd b{s * v0.re + c * v1.re, s * v0.im + c * v1.im};
     v0 = a; v1 = b;
   } else {  // diag(e^{-i th}, e^{i th})
-    v0 = cmul(v0, cexpi(-theta));
-    v1 = cmul(v1, cexpi(theta));
+    v0 = cmul(v0, cd{c, -s});
+    v1 = cmul(v1, cd{c, s});
   }
 }
+
+// Angle of a rotation op: pi/4 (cross-resonance gate set) or 0 (textbook
+// over-rotation gate) plus the over-rotation exponent of its site.
+QEC_HD double op_angle(const TOp& op, const double* eps_site) {
+  return (op.quarter ? 0.78539816339744830962 : 0.0) + (op.site >= 0 ? eps_site[op.site] : 0.0);
+}
+
+// Accessor evaluating cos/sin of each op's angle on the fly.
+struct CsFromEps {
+  const double* eps;
+  QEC_HD cd operator()(const TOp& op) const {
+    const double beta = op_angle(op, eps);
+    return {cos(beta), sin(beta)};
+  }
+};
+
+// Accessor reading a per-site (cos, sin) table.
+struct CsFromTable {
+  const double* cs;  // [site][2]
+  QEC_HD cd operator()(const TOp& op) const { return {cs[2 * op.site], cs[2 * op.site + 1]}; }
+};
 
 // Runs the ops of block b on the ancilla 2-vector for the block-basis input
 // label x (ancilla starting in |0>), with pauli[i] the Pauli code drawn for op
 // i (0 = none; for two-qubit locations the pair index 1..15).  Returns the
 // ancilla amplitudes (v0, v1) = (D_0(x), D_1(x)) before normalisation and the
 // output label in *cur; false if an op is not monomial in the block basis.
-QEC_HD bool track_column(const TBlock& b, const double* eps_site, const uint8_t* pauli, int x,
-                         cd& v0, cd& v1, uint32_t* cur_out) {
+// `cs(op)` returns (cos beta, sin beta) of a rotation op's angle beta = base +
+// eps of its site; rotations by +-beta only flip the sine.
+template <class CS>
+QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd& v0, cd& v1,
+                         uint32_t* cur_out) {
   const bool xb = (b.type == 0);
-  const double q4 = 0.78539816339744830962;  // pi/4
   v0 = {1.0, 0.0};
   v1 = {0.0, 0.0};
   uint32_t cur = (uint32_t)x;
   for (int i = 0; i < b.n_ops; ++i) {
     const TOp& op = b.ops[i];
-    const double beta = (op.quarter ? q4 : 0.0) + (op.site >= 0 ? eps_site[op.site] : 0.0);
     switch (op.kind) {
-      case OP_ROT_ANC:
-        anc_rot(op.axis, beta * (double)op.sgn, v0, v1);
+      case OP_ROT_ANC: {
+        const cd c = cs(op);
+        anc_rot_cs(op.axis, c.re, c.im * (double)op.sgn, v0, v1);
         break;
+      }
       case OP_ROT_DATA: {
         if ((xb && op.axis != 1) || (!xb && op.axis != 3)) return false;
         const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
-        const cd ph = cexpi(-beta * e * (double)op.sgn);
+        const cd c = cs(op);
+        const cd ph{c.re, -c.im * e * (double)op.sgn};  // exp(-i beta e sgn)
         v0 = cmul(v0, ph);
         v1 = cmul(v1, ph);
         break;
@@ -207,14 +232,16 @@ QEC_HD bool track_column(const TBlock& b, const double* eps_site, const uint8_t*
       case OP_CR_AD: {
         if (!xb) return false;
         const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
-        v0 = cmul(v0, cexpi(-beta * e));
-        v1 = cmul(v1, cexpi(beta * e));
+        const cd c = cs(op);
+        v0 = cmul(v0, cd{c.re, -c.im * e});
+        v1 = cmul(v1, cd{c.re, c.im * e});
         break;
       }
       case OP_CR_DA: {
         if (xb) return false;
         const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
-        anc_rot(1, beta * e, v0, v1);
+        const cd c = cs(op);
+        anc_rot_cs(1, c.re, c.im * e, v0, v1);
         break;
       }
       case OP_H_ANC: {
@@ -278,7 +305,7 @@ QEC_HD bool build_block(const TBlock& b, const double* eps_site, const uint8_t* 
   for (int x = 0; x < n; ++x) {
     cd v0, v1;
     uint32_t cur = 0;
-    if (!track_column(b, eps_site, pauli, x, v0, v1, &cur)) return false;
+    if (!track_column(b, CsFromEps{eps_site}, pauli, x, v0, v1, &cur)) return false;
     F = cur ^ (uint32_t)x;
     out.D[0][x][0] = v0.re * norm;
     out.D[0][x][1] = v0.im * norm;

@@ -129,7 +129,9 @@ struct OpSink {
   void noise(uint8_t kind, int j) {
     TOp& o = b.ops[b.n_ops++];
     o = TOp{};
-    o.kind = kind; o.j = (uint8_t)j; o.site = -1; o.draw = (int16_t)draws++;
+    o.kind = kind; o.j = (uint8_t)j; o.site = -1;
+    if (kind == OP_N2_AD || kind == OP_N2_DA) b.n2mask |= 1u << draws;
+    o.draw = (int16_t)draws++;
   }
 };
 
@@ -552,7 +554,8 @@ template <typename T>
 sv_status run_batch_t(const sv_batch_job* job, sv_batch_result* res, const Template& tp) {
   const int d = job->d, n = d * d, ns = (int)tp.blocks.size();
   const int nt = job->n_traj;
-  if (n > kSmallBits) return fail(SV_EINVAL, "d=%d batch path not available", d);
+  if (n > kSmallBits || ns > kSmallStab || tp.n_sites > kSmallSites)
+    return fail(SV_EINVAL, "d=%d batch path not available", d);
   hipStream_t s = (hipStream_t)job->hip_stream;
   DevBufs M;
   TBlock* dblocks = nullptr;
@@ -602,12 +605,12 @@ sv_status run_batch_t(const sv_batch_job* job, sv_batch_result* res, const Templ
   } ev;
   HIP_OK(hipEventCreate(&ev.a));
   HIP_OK(hipEventCreate(&ev.b));
-  const int per_cu = std::max(1, env_int("QECSV_BATCH_WAVES_PER_CU", 12));
+  const int per_cu = std::max(1, env_int("QECSV_BATCH_WAVES_PER_CU", 8));
   const int max_wg = device_cu_count() * per_cu;
   const int grid = std::max(1, std::min((nt + 1) / 2, max_wg));
   HIP_OK(hipEventRecord(ev.a, s));
   hipLaunchKernelGGL(k_batch_small<T>, dim3(grid), dim3(64), 0, s, dblocks, dsd, ns, n, tp.n_draws,
-                     tp.n_sites, djc, job->seed, job->traj0, dorder, nt, drounds, dp, deps,
+                     djc, job->seed, job->traj0, dorder, nt, drounds, dp, deps,
                      eps_stride, drec, job->max_rounds, dbits, derr);
   HIP_OK(hipGetLastError());
   HIP_OK(hipEventRecord(ev.b, s));
