@@ -19,6 +19,7 @@
 #include "qec_common.h"
 #include "kernels.hip"
 #include "kernels_batch.hip"
+#include "kernels_tiled.hip"
 
 using namespace qec;
 
@@ -554,8 +555,9 @@ template <typename T>
 sv_status run_batch_t(const sv_batch_job* job, sv_batch_result* res, const Template& tp) {
   const int d = job->d, n = d * d, ns = (int)tp.blocks.size();
   const int nt = job->n_traj;
-  if (n > kSmallBits || ns > kSmallStab || tp.n_sites > kSmallSites)
-    return fail(SV_EINVAL, "d=%d batch path not available", d);
+  const bool small = n <= kSmallBits && ns <= kSmallStab && tp.n_sites <= kSmallSites;
+  const bool tiled = !small && n <= 16 && ns <= kTiledStab && tp.n_sites <= kTiledSites;
+  if (!small && !tiled) return fail(SV_EINVAL, "d=%d batch path not available", d);
   hipStream_t s = (hipStream_t)job->hip_stream;
   DevBufs M;
   TBlock* dblocks = nullptr;
@@ -582,7 +584,7 @@ sv_status run_batch_t(const sv_batch_job* job, sv_batch_result* res, const Templ
   for (int i = 0; i < nt; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return job->rounds[a] > job->rounds[b]; });
-  const std::vector<SmallDesc> sd = make_small_descs(n, tp);
+  const std::vector<SmallDesc> sd = small ? make_small_descs(n, tp) : std::vector<SmallDesc>(ns);
   const JobConst jc = make_job_const(d, job->zeta);
   std::vector<double> epsv;
   if (!job->eps_site) epsv.assign(neps, job->eps);
@@ -605,13 +607,34 @@ sv_status run_batch_t(const sv_batch_job* job, sv_batch_result* res, const Templ
   } ev;
   HIP_OK(hipEventCreate(&ev.a));
   HIP_OK(hipEventCreate(&ev.b));
-  const int per_cu = std::max(1, env_int("QECSV_BATCH_WAVES_PER_CU", 8));
-  const int max_wg = device_cu_count() * per_cu;
-  const int grid = std::max(1, std::min((nt + 1) / 2, max_wg));
-  HIP_OK(hipEventRecord(ev.a, s));
-  hipLaunchKernelGGL(k_batch_small<T>, dim3(grid), dim3(64), 0, s, dblocks, dsd, ns, n, tp.n_draws,
-                     djc, job->seed, job->traj0, dorder, nt, drounds, dp, deps,
-                     eps_stride, drec, job->max_rounds, dbits, derr);
+  if (small) {
+    const int per_cu = std::max(1, env_int("QECSV_BATCH_WAVES_PER_CU", 8));
+    const int max_wg = device_cu_count() * per_cu;
+    const int grid = std::max(1, std::min((nt + 1) / 2, max_wg));
+    HIP_OK(hipEventRecord(ev.a, s));
+    hipLaunchKernelGGL(k_batch_small<T>, dim3(grid), dim3(64), 0, s, dblocks, dsd, ns, n, tp.n_draws,
+                       djc, job->seed, job->traj0, dorder, nt, drounds, dp, deps,
+                       eps_stride, drec, job->max_rounds, dbits, derr);
+  } else {
+    // one workgroup per trajectory, each with its own 2^n-amplitude slice
+    const int per_cu = std::max(1, env_int("QECSV_TILED_WG_PER_CU", sizeof(T) == 8 ? 2 : 3));
+    const int grid = std::max(1, std::min(nt, device_cu_count() * per_cu));
+    T* work = nullptr;
+    PassDesc* dpass = nullptr;
+    HIP_OK(M.alloc(&work, ((size_t)grid << n) * 2 * sizeof(T)));
+    HIP_OK(M.alloc(&dpass, sizeof(PassDesc) * (ns + 2)));
+    const int tb = std::min(kTileMax, n);
+    std::vector<PassDesc> pds(ns + 2);
+    pds[0] = make_pass(n, tb, nullptr, &tp.blocks[0], -1, 0);
+    for (int i = 0; i < ns; ++i)
+      pds[1 + i] = make_pass(n, tb, &tp.blocks[i], &tp.blocks[(i + 1) % ns], i, (i + 1) % ns);
+    pds[ns + 1] = make_pass(n, tb, &tp.blocks[ns - 1], nullptr, ns - 1, -1);
+    HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(PassDesc) * (ns + 2), hipMemcpyHostToDevice, s));
+    HIP_OK(hipEventRecord(ev.a, s));
+    hipLaunchKernelGGL(k_batch_tiled<T>, dim3(grid), dim3(256), 0, s, dblocks, dpass, ns, n,
+                       tp.n_draws, djc, job->seed, job->traj0, dorder, nt, drounds, dp, deps,
+                       eps_stride, drec, job->max_rounds, dbits, work, derr);
+  }
   HIP_OK(hipGetLastError());
   HIP_OK(hipEventRecord(ev.b, s));
   int herr = 0;

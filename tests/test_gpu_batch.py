@@ -66,3 +66,12 @@ def test_batch_rejects_bad_arguments():
         qs.run_batch(3, "cr", [2], [1.5], 0)             # p > 1
     with pytest.raises(qs.SvError):
         qs.run_batch(3, "cr", [5], [0.01], 0, max_rounds=4)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("gateset", ["cr", "textbook"])
+def test_batch_d4_parity(gateset, dtype):
+    """d=4 (16 data qubits, 2^16 amplitudes per trajectory, streamed from HBM
+    by one workgroup per trajectory), several tiles per pass."""
+    _check(4, gateset, dtype, 24 if dtype == "c128" else 12, seed=17, p_range=(5e-3, 3e-2),
+           zeta=0.01)
