@@ -218,6 +218,74 @@ typedef struct sv_batch_result {
 
 sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res);
 
+/* ---------------------------------------------------------------- serving */
+
+/* A server runs submitted jobs (each an sv_job: distance, rounds, dtype, noise
+ * parameters, trajectory range) with continuous batching: jobs are admitted
+ * in arrival order while the device bytes they hold fit in hbm_budget;
+ * admitted jobs with d <= 4 join a lane per (d, gate set, dtype, zeta) whose
+ * worker merges the waiting trajectories of any number of jobs into one
+ * persistent batched launch (a job arriving during a launch joins the next);
+ * d = 5 jobs run on one of big_streams workers with their own HIP streams, so
+ * their passes overlap on the device.  A job's records and final bits are the
+ * same as those of sv_run_rounds for the same job.  All calls are thread-safe.
+ */
+typedef struct sv_server_s* sv_server;
+
+typedef struct sv_server_config {
+  size_t hbm_budget;   /* device bytes admitted jobs may hold at once (> 0) */
+  int big_streams;     /* d = 5 jobs running at once, 1..16 */
+  int max_batch_traj;  /* trajectories per merged launch, >= 1 */
+  int flags;           /* reserved, must be 0 */
+} sv_server_config;
+
+typedef struct sv_request {
+  sv_job job;          /* hip_stream ignored; eps_site copied at submission */
+  uint8_t* records;    /* host [n_traj][rounds][d^2-1], caller-owned until completion */
+  uint8_t* final_bits; /* host [n_traj][d^2] */
+  uint64_t tag;        /* returned with the completion */
+} sv_request;
+
+typedef struct sv_completion {
+  uint64_t tag;
+  int status;          /* sv_status of the job (SV_EBUSY: cancelled) */
+  int pad;
+  double t_submit;     /* server clock, seconds */
+  double t_admit;
+  double t_done;
+} sv_completion;
+
+typedef struct sv_server_stats {
+  size_t hbm_in_use;      /* bytes held by admitted, unfinished jobs */
+  size_t hbm_high_water;  /* maximum of hbm_in_use so far (<= hbm_budget) */
+  int pending;            /* submitted, not admitted */
+  int running;            /* launches in flight */
+  int completed;
+  int launches;           /* batched launches plus d = 5 jobs run */
+} sv_server_stats;
+
+sv_status sv_server_create(const sv_server_config* cfg, sv_server* out);
+
+/* Enqueue a job; returns at once.  SV_ENOMEM if the job alone exceeds the
+ * budget, SV_EINVAL for bad arguments (nothing is queued). */
+sv_status sv_server_submit(sv_server s, const sv_request* req);
+
+/* Move up to max completions (oldest first) into out; returns how many. */
+int sv_server_poll(sv_server s, sv_completion* out, int max);
+
+/* Wait until every submitted job has completed, or SV_EBUSY after timeout_s. */
+sv_status sv_server_wait_idle(sv_server s, double timeout_s);
+
+sv_status sv_server_stats_get(sv_server s, sv_server_stats* out);
+
+/* Seconds since the server was created (the clock of the completions). */
+double sv_server_clock(sv_server s);
+
+/* Finish and free the server.  cancel = 0 waits for every job; cancel = 1
+ * completes queued jobs with SV_EBUSY and stops admitted ones at their next
+ * trajectory or launch. */
+sv_status sv_server_destroy(sv_server s, int cancel);
+
 /* Philox4x32-10 uniform used by the device code, evaluated on the host (for
  * tests of the draw stream). */
 double sv_uniform(uint64_t seed, uint64_t t, uint64_t k);

@@ -65,6 +65,27 @@ class BatchResult(ctypes.Structure):
     ]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("big_streams", ctypes.c_int),
+                ("max_batch_traj", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("job", Job), ("records", ctypes.POINTER(ctypes.c_uint8)),
+                ("final_bits", ctypes.POINTER(ctypes.c_uint8)), ("tag", ctypes.c_uint64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("pad", ctypes.c_int),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("hbm_in_use", ctypes.c_size_t), ("hbm_high_water", ctypes.c_size_t),
+                ("pending", ctypes.c_int), ("running", ctypes.c_int), ("completed", ctypes.c_int),
+                ("launches", ctypes.c_int)]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "sv_last_error": (ctypes.c_char_p, []),
@@ -93,6 +114,13 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "sv_run_rounds": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(Result)]),
     "sv_run_batch": (ctypes.c_int, [ctypes.POINTER(BatchJob), ctypes.POINTER(BatchResult)]),
+    "sv_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
+    "sv_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request)]),
+    "sv_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Completion), ctypes.c_int]),
+    "sv_server_wait_idle": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "sv_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "sv_server_clock": (ctypes.c_double, [ctypes.c_void_p]),
+    "sv_server_destroy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "sv_uniform": (ctypes.c_double, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]),
     "sv_block_kraus": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
@@ -326,3 +354,74 @@ def run_batch(d, gateset, rounds, p, seed, eps=0.0, eps_site=None, zeta=0.0, dty
     _check(lib().sv_run_batch(ctypes.byref(job), ctypes.byref(res)))
     del keep
     return dict(records=rec, final_bits=fb, gpu_ms=res.gpu_ms)
+
+
+class Server:
+    """sv_server: continuous batching with HBM-budget admission.  Output
+    buffers of each job are kept here until its completion is polled."""
+
+    def __init__(self, hbm_budget, big_streams=2, max_batch_traj=65536):
+        cfg = ServerConfig(int(hbm_budget), int(big_streams), int(max_batch_traj), 0)
+        h = ctypes.c_void_p()
+        _check(lib().sv_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+        self._jobs = {}
+
+    def submit(self, tag, d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0,
+               dtype="c128", traj0=0):
+        n_stab, n_sites, _ = template_info(d, gateset)
+        req = Request()
+        j = req.job
+        j.d, j.gateset, j.rounds, j.dtype = d, _GATESETS[gateset], rounds, _DTYPES[dtype]
+        j.n_traj, j.flags, j.traj0, j.seed = n_traj, 0, int(traj0), int(seed)
+        j.p, j.eps, j.zeta = float(p), float(eps), float(zeta)
+        keep = None
+        if eps_site is not None:
+            keep = np.ascontiguousarray(eps_site, dtype=np.float64)
+            if keep.shape != (n_sites,):
+                raise ValueError(f"eps_site must have {n_sites} entries")
+            j.eps_site = _dptr(keep)
+        rec = np.zeros((n_traj, rounds, n_stab), dtype=np.uint8)
+        fb = np.zeros((n_traj, d * d), dtype=np.uint8)
+        req.records = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        req.final_bits = fb.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        req.tag = int(tag)
+        self._jobs[int(tag)] = (rec, fb)
+        try:
+            _check(lib().sv_server_submit(self.h, ctypes.byref(req)))
+        except SvError:
+            del self._jobs[int(tag)]
+            raise
+        del keep
+
+    def poll(self, max_n=1024):
+        buf = (Completion * max_n)()
+        k = lib().sv_server_poll(self.h, buf, max_n)
+        out = []
+        for c in buf[:k]:
+            rec, fb = self._jobs.pop(int(c.tag))
+            out.append(dict(tag=int(c.tag), status=int(c.status), t_submit=c.t_submit,
+                            t_admit=c.t_admit, t_done=c.t_done, records=rec, final_bits=fb))
+        return out
+
+    def wait_idle(self, timeout_s=600.0):
+        _check(lib().sv_server_wait_idle(self.h, float(timeout_s)))
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().sv_server_stats_get(self.h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def clock(self):
+        return lib().sv_server_clock(self.h)
+
+    def close(self, cancel=False):
+        if self.h:
+            _check(lib().sv_server_destroy(self.h, 1 if cancel else 0))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close(cancel=True)
+        except Exception:
+            pass

@@ -118,7 +118,8 @@ __device__ void small_setup_kraus(SmallSlot<T>& S, int lane, int ns, const TBloc
 template <typename T>
 __global__ __launch_bounds__(64) void k_batch_small(
     const TBlock* __restrict__ blocks, const SmallDesc* __restrict__ sdesc, int ns, int n,
-    int draws_round, const JobConst* __restrict__ jc, uint64_t seed, uint64_t traj0,
+    int draws_round, const JobConst* __restrict__ jc, const uint64_t* __restrict__ tseed,
+    const uint64_t* __restrict__ tstream,
     const int* __restrict__ order, int n_traj, const int* __restrict__ rounds,
     const double* __restrict__ pvec, const double* __restrict__ eps, int eps_stride,
     uint8_t* __restrict__ rec, int max_rounds, uint8_t* __restrict__ bits, int* __restrict__ err) {
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(64) void k_batch_small(
     for (int s = 0; s < ns; ++s) {
       const TBlock& b = blocks[s];
       const SmallDesc& sd = sdesc[s];
-      const uint64_t tg = traj0 + (uint64_t)t;
+      const uint64_t tg = tstream[t], seed = tseed[t];
       const uint64_t k0 = (uint64_t)r * (uint64_t)draws_round + (uint64_t)b.draw_off;
       // 1. draws; did any noise location pick a Pauli?
       bool hit = false;
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(64) void k_batch_small(
           L += (double)a.re * (double)a.re + (double)a.im * (double)a.im;
         }
       }
-      const uint64_t tg = traj0 + (uint64_t)t;
+      const uint64_t tg = tstream[t], seed = tseed[t];
       const uint64_t kf = (uint64_t)R * (uint64_t)draws_round;
       const double uf = lane < n ? uniform(seed, tg, kf + (uint64_t)lane) : 0.0;
       int lo = 0, size = groups, level = 0;

@@ -253,7 +253,8 @@ __device__ void tiled_decide(TiledLds<T>& L, int kbi, double s0, double s1, uint
 template <typename T>
 __global__ __launch_bounds__(256) void k_batch_tiled(
     const TBlock* __restrict__ blocks, const PassDesc* __restrict__ pds, int ns, int n,
-    int draws_round, const JobConst* __restrict__ jc, uint64_t seed, uint64_t traj0,
+    int draws_round, const JobConst* __restrict__ jc, const uint64_t* __restrict__ tseed,
+    const uint64_t* __restrict__ tstream,
     const int* __restrict__ order, int n_traj, const int* __restrict__ rounds,
     const double* __restrict__ pvec, const double* __restrict__ eps, int eps_stride,
     uint8_t* __restrict__ rec, int max_rounds, uint8_t* __restrict__ bits, T* __restrict__ work,
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(256) void k_batch_tiled(
     const int R = rounds[t];
     const double p = pvec[t];
     const double* ep = eps + (size_t)t * eps_stride;
-    const uint64_t tg = traj0 + (uint64_t)t;
+    const uint64_t tg = tstream[t], seed = tseed[t];
     // tables
     for (int s = 0; s < ns; ++s) {
       const TBlock& b = blocks[s];

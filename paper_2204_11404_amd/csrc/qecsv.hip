@@ -7,6 +7,13 @@
 // the launch sequence of one trajectory (Sec. III.B).  All simulation
 // arithmetic runs in the kernels of kernels.hip.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -363,7 +370,8 @@ void launch_pass(int wa, int wb, int bmode, dim3 g, dim3 b, hipStream_t s, T* st
 namespace {
 
 template <typename T>
-sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp) {
+sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
+                       const std::atomic<int>* cancel = nullptr) {
   const int d = job->d, n = d * d, ns = (int)tp.blocks.size(), R = job->rounds;
   const int tb = std::min(kTileMax, n);
   const int per_traj = R * ns;
@@ -447,6 +455,10 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp) {
                        drt, derr);
     HIP_OK(hipGetLastError());
     for (int ti = 0; ti < cn; ++ti) {
+      if (cancel && cancel->load(std::memory_order_relaxed)) {
+        (void)hipStreamSynchronize(s);
+        return fail(SV_EBUSY, "cancelled");
+      }
       const int tg = c0 + ti;
       const BlockRT* rt = drt + (size_t)ti * per_traj;
       uint8_t* rec = drec + (size_t)tg * per_traj;
@@ -551,24 +563,41 @@ int env_int(const char* name, int dflt) {
   return dflt;
 }
 
+// Inputs of one batched launch; every array has one entry per trajectory
+// (eps: eps_stride doubles per trajectory, stride 0 = shared by all).
+struct BatchInputs {
+  int d, gateset, n_traj, max_rounds;
+  double zeta;
+  const uint64_t* seed;
+  const uint64_t* stream;
+  const int* rounds;
+  const double* p;
+  const double* eps;
+  int eps_stride;
+  uint8_t* records;     // host [n_traj][max_rounds][n_stab]
+  uint8_t* final_bits;  // host [n_traj][d^2]
+  hipStream_t hs;
+  double gpu_ms;
+};
+
 template <typename T>
-sv_status run_batch_t(const sv_batch_job* job, sv_batch_result* res, const Template& tp) {
-  const int d = job->d, n = d * d, ns = (int)tp.blocks.size();
-  const int nt = job->n_traj;
+sv_status run_batch_core(BatchInputs& in, const Template& tp) {
+  const int d = in.d, n = d * d, ns = (int)tp.blocks.size();
+  const int nt = in.n_traj;
   const bool small = n <= kSmallBits && ns <= kSmallStab && tp.n_sites <= kSmallSites;
   const bool tiled = !small && n <= 16 && ns <= kTiledStab && tp.n_sites <= kTiledSites;
   if (!small && !tiled) return fail(SV_EINVAL, "d=%d batch path not available", d);
-  hipStream_t s = (hipStream_t)job->hip_stream;
+  hipStream_t s = in.hs;
   DevBufs M;
   TBlock* dblocks = nullptr;
   SmallDesc* dsd = nullptr;
   JobConst* djc = nullptr;
   int *dorder = nullptr, *drounds = nullptr, *derr = nullptr;
   double *dp = nullptr, *deps = nullptr;
+  uint64_t *dseed = nullptr, *dstream = nullptr;
   uint8_t *drec = nullptr, *dbits = nullptr;
-  const size_t nrec = (size_t)nt * job->max_rounds * ns;
-  const int eps_stride = job->eps_site ? tp.n_sites : 0;
-  const size_t neps = job->eps_site ? (size_t)nt * tp.n_sites : (size_t)std::max(1, tp.n_sites);
+  const size_t nrec = (size_t)nt * in.max_rounds * ns;
+  const size_t neps = in.eps_stride ? (size_t)nt * in.eps_stride : (size_t)std::max(1, tp.n_sites);
   HIP_OK(M.alloc(&dblocks, sizeof(TBlock) * ns));
   HIP_OK(M.alloc(&dsd, sizeof(SmallDesc) * ns));
   HIP_OK(M.alloc(&djc, sizeof(JobConst)));
@@ -576,6 +605,8 @@ sv_status run_batch_t(const sv_batch_job* job, sv_batch_result* res, const Templ
   HIP_OK(M.alloc(&drounds, sizeof(int) * nt));
   HIP_OK(M.alloc(&derr, sizeof(int)));
   HIP_OK(M.alloc(&dp, sizeof(double) * nt));
+  HIP_OK(M.alloc(&dseed, sizeof(uint64_t) * nt));
+  HIP_OK(M.alloc(&dstream, sizeof(uint64_t) * nt));
   HIP_OK(M.alloc(&deps, sizeof(double) * neps));
   HIP_OK(M.alloc(&drec, nrec));
   HIP_OK(M.alloc(&dbits, (size_t)nt * n));
@@ -583,19 +614,18 @@ sv_status run_batch_t(const sv_batch_job* job, sv_batch_result* res, const Templ
   std::vector<int> order(nt);
   for (int i = 0; i < nt; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return job->rounds[a] > job->rounds[b]; });
+                   [&](int a, int b) { return in.rounds[a] > in.rounds[b]; });
   const std::vector<SmallDesc> sd = small ? make_small_descs(n, tp) : std::vector<SmallDesc>(ns);
-  const JobConst jc = make_job_const(d, job->zeta);
-  std::vector<double> epsv;
-  if (!job->eps_site) epsv.assign(neps, job->eps);
+  const JobConst jc = make_job_const(d, in.zeta);
   HIP_OK(hipMemcpyAsync(dblocks, tp.blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(dsd, sd.data(), sizeof(SmallDesc) * ns, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(djc, &jc, sizeof jc, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(dorder, order.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(drounds, job->rounds, sizeof(int) * nt, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(dp, job->p, sizeof(double) * nt, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(deps, job->eps_site ? job->eps_site : epsv.data(), sizeof(double) * neps,
-                        hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(drounds, in.rounds, sizeof(int) * nt, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dp, in.p, sizeof(double) * nt, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dseed, in.seed, sizeof(uint64_t) * nt, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dstream, in.stream, sizeof(uint64_t) * nt, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(deps, in.eps, sizeof(double) * neps, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemsetAsync(drec, 0, nrec, s));
   HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
   struct Ev {
@@ -613,11 +643,11 @@ sv_status run_batch_t(const sv_batch_job* job, sv_batch_result* res, const Templ
     const int grid = std::max(1, std::min((nt + 1) / 2, max_wg));
     HIP_OK(hipEventRecord(ev.a, s));
     hipLaunchKernelGGL(k_batch_small<T>, dim3(grid), dim3(64), 0, s, dblocks, dsd, ns, n, tp.n_draws,
-                       djc, job->seed, job->traj0, dorder, nt, drounds, dp, deps,
-                       eps_stride, drec, job->max_rounds, dbits, derr);
+                       djc, dseed, dstream, dorder, nt, drounds, dp, deps, in.eps_stride, drec,
+                       in.max_rounds, dbits, derr);
   } else {
     // one workgroup per trajectory, each with its own 2^n-amplitude slice
-    const int per_cu = std::max(1, env_int("QECSV_TILED_WG_PER_CU", sizeof(T) == 8 ? 2 : 3));
+    const int per_cu = std::max(1, env_int("QECSV_TILED_WG_PER_CU", sizeof(T) == 8 ? 2 : 2));
     const int grid = std::max(1, std::min(nt, device_cu_count() * per_cu));
     T* work = nullptr;
     PassDesc* dpass = nullptr;
@@ -632,21 +662,34 @@ sv_status run_batch_t(const sv_batch_job* job, sv_batch_result* res, const Templ
     HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(PassDesc) * (ns + 2), hipMemcpyHostToDevice, s));
     HIP_OK(hipEventRecord(ev.a, s));
     hipLaunchKernelGGL(k_batch_tiled<T>, dim3(grid), dim3(256), 0, s, dblocks, dpass, ns, n,
-                       tp.n_draws, djc, job->seed, job->traj0, dorder, nt, drounds, dp, deps,
-                       eps_stride, drec, job->max_rounds, dbits, work, derr);
+                       tp.n_draws, djc, dseed, dstream, dorder, nt, drounds, dp, deps,
+                       in.eps_stride, drec, in.max_rounds, dbits, work, derr);
   }
   HIP_OK(hipGetLastError());
   HIP_OK(hipEventRecord(ev.b, s));
   int herr = 0;
   HIP_OK(hipMemcpyAsync(&herr, derr, sizeof herr, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(in.records, drec, nrec, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(in.final_bits, dbits, (size_t)nt * n, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   if (herr) return fail(SV_EINVAL, "circuit template is not monomial in its block basis");
-  HIP_OK(hipMemcpy(res->records, drec, nrec, hipMemcpyDeviceToHost));
-  HIP_OK(hipMemcpy(res->final_bits, dbits, (size_t)nt * n, hipMemcpyDeviceToHost));
   float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, ev.a, ev.b));
-  res->gpu_ms = ms;
+  in.gpu_ms = ms;
   return SV_OK;
+}
+
+// Device bytes one batched launch of n_traj trajectories holds (admission).
+size_t batch_footprint(int d, int dtype, int n_traj, int max_rounds, int n_sites) {
+  const int n = d * d;
+  const size_t elem = dtype == SV_C128 ? 16 : 8;
+  size_t b = (size_t)n_traj * ((size_t)max_rounds * (n + 1) + n + 40 + 8 * (size_t)n_sites);
+  if (n > kSmallBits) {
+    const int per_cu = std::max(1, env_int("QECSV_TILED_WG_PER_CU", 2));
+    const size_t grid = std::min<size_t>((size_t)n_traj, (size_t)device_cu_count() * per_cu);
+    b += (grid << n) * elem;
+  }
+  return b + (1 << 20);
 }
 
 }  // namespace
@@ -1036,7 +1079,20 @@ sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res) {
       if (!std::isfinite(job->eps_site[i])) return fail(SV_EINVAL, "non-finite eps_site");
   res->gpu_ms = 0.0;
   if (job->n_traj == 0) return SV_OK;
-  return job->dtype == SV_C128 ? run_batch_t<double>(job, res, tp) : run_batch_t<float>(job, res, tp);
+  const int nt = job->n_traj;
+  std::vector<uint64_t> seeds(nt, job->seed), streams(nt);
+  for (int i = 0; i < nt; ++i) streams[i] = job->traj0 + (uint64_t)i;
+  std::vector<double> epsv;
+  if (!job->eps_site) epsv.assign(std::max(1, tp.n_sites), job->eps);
+  BatchInputs in{job->d, job->gateset, nt, job->max_rounds, job->zeta, seeds.data(), streams.data(),
+                 job->rounds, job->p, job->eps_site ? job->eps_site : epsv.data(),
+                 job->eps_site ? tp.n_sites : 0, res->records, res->final_bits,
+                 (hipStream_t)job->hip_stream, 0.0};
+  const sv_status st = job->dtype == SV_C128 ? run_batch_core<double>(in, tp) : run_batch_core<float>(in, tp);
+  res->gpu_ms = in.gpu_ms;
+  return st;
 }
 
 }  // extern "C"
+
+#include "server.hip"
