@@ -59,6 +59,56 @@ def copy_calibration(qs, torch, steps):
                       "copy_ms": ms, "copy_gbs": 2 * (1 << 30) / (ms * 1e-3) / 1e9}), flush=True)
 
 
+def serving_run(qs, kind, window_s, horizon_s, budget_gib=256):
+    """Replay a Poisson job stream against the server in real time; at
+    `horizon_s` cancel what is left.  Latency = completion - submission on the
+    server clock (queueing included)."""
+    import numpy as np
+    import workloads
+    stream = workloads.serving_stream(window_s, seed=2, companion=(kind == "companion"),
+                                      n_sites=lambda d: qs.template_info(d, "cr")[1])
+    srv = qs.Server(hbm_budget=budget_gib << 30, big_streams=2, max_batch_traj=65536)
+    done, t0 = [], time.perf_counter()
+    meta = {}
+    for arr, job in stream:
+        while time.perf_counter() - t0 < arr:
+            done += srv.poll()
+            time.sleep(0.0005)
+        srv.submit(**job)
+        meta[job["tag"]] = job
+    while time.perf_counter() - t0 < horizon_s and len(done) < len(stream):
+        done += srv.poll()
+        time.sleep(0.002)
+    stats = srv.stats()
+    srv.close(cancel=True)
+    ok = [c for c in done if c["status"] == 0]
+    lat = np.array([c["t_done"] - c["t_submit"] for c in ok]) * 1e3
+    traj_rounds = sum(meta[c["tag"]]["n_traj"] * meta[c["tag"]]["rounds"] for c in ok)
+    by_d = {d: int(sum(1 for c in ok if meta[c["tag"]]["d"] == d)) for d in (3, 4, 5)}
+    return {"stream": kind, "arrival_window_s": window_s, "horizon_s": horizon_s,
+            "jobs_offered": len(stream), "jobs_completed": len(ok), "completed_by_d": by_d,
+            "backlog_at_horizon": len(stream) - len(ok),
+            "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+            "trajectory_rounds_per_s": traj_rounds / horizon_s,
+            "launches": stats["launches"], "hbm_high_water_gib": stats["hbm_high_water"] / (1 << 30)}
+
+
+def batch_run(qs, d, n_traj, dtype, seed=7):
+    """One batched launch of the small-distance workload shape: rounds uniform
+    on 1..9, p uniform on [5e-4, 5e-3), theta uniform on [0, 0.05) per site."""
+    import workloads
+    n_stab, n_sites, _ = qs.template_info(d, "cr")
+    R, p, eps = workloads.batch_params(n_traj, n_sites, seed)
+    qs.run_batch(d, "cr", R[:256], p[:256], seed, eps_site=eps[:256], dtype=dtype)
+    g = qs.run_batch(d, "cr", R, p, seed, eps_site=eps, dtype=dtype, max_rounds=9)
+    amp = 8 if dtype == "c64" else 16
+    alg = (int(R.sum()) * n_stab + n_traj) * 2 * (1 << (d * d)) * amp
+    return {"d": d, "trajectories": n_traj, "dtype": dtype, "launch_ms": g["gpu_ms"],
+            "trajectories_per_s": n_traj / (g["gpu_ms"] * 1e-3),
+            "alg_gbs": alg / (g["gpu_ms"] * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +119,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="time only the library's plain register copy (HBM calibration)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-launch and serving measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -129,6 +181,11 @@ def main():
                      "kernel": "k_pass", "bytes_per_launch": blk_bytes,
                      "avg_launch_ms": pass_ms},
     }
+    if not args.no_extras:
+        out["batched"] = [batch_run(qs, 3, 65536, "c64"), batch_run(qs, 4, 4096, "c64")]
+        out["d3_trajectories_per_s"] = out["batched"][0]["trajectories_per_s"]
+        out["serving"] = [serving_run(qs, "companion", 5.0, 8.0), serving_run(qs, "spec", 2.0, 4.0)]
+        out["p99_latency_ms"] = out["serving"][0]["p99_ms"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, eps, args.cpu_blocks)
     print(json.dumps(out), flush=True)

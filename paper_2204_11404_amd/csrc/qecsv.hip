@@ -50,16 +50,35 @@ sv_status fail(sv_status st, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(SV_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-// Device buffers released on scope exit.
+// Device buffers for one call, allocated and released in stream order from
+// the device's default pool (no device-wide synchronisation, memory is reused
+// across calls).
+void keep_pool_memory(int dev) {
+  static std::once_flag once[64];
+  if (dev < 0 || dev >= 64) return;
+  std::call_once(once[dev], [dev] {
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
+      uint64_t keep = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+  });
+}
+
 struct DevBufs {
+  hipStream_t s;
   std::vector<void*> ptrs;
+  explicit DevBufs(hipStream_t stream) : s(stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) keep_pool_memory(dev);
+  }
   ~DevBufs() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
   }
   template <typename P>
   hipError_t alloc(P** out, size_t bytes) {
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+    hipError_t e = hipMallocAsync(&p, bytes ? bytes : 16, s);
     if (e == hipSuccess) {
       ptrs.push_back(p);
       *out = reinterpret_cast<P*>(p);
@@ -376,7 +395,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   const int tb = std::min(kTileMax, n);
   const int per_traj = R * ns;
   hipStream_t s = (hipStream_t)job->hip_stream;
-  DevBufs M;
+  DevBufs M(s);
   T* st = nullptr;
   double2* partials = nullptr;
   TBlock* dblocks = nullptr;
@@ -485,9 +504,9 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       }
       HIP_OK(hipGetLastError());
       if (res->final_states) {
+        HIP_OK(hipMemcpyAsync((char*)res->final_states + (size_t)tg * sizeof(T) * 2 * na, st,
+                              sizeof(T) * 2 * na, hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
-        HIP_OK(hipMemcpy((char*)res->final_states + (size_t)tg * sizeof(T) * 2 * na, st,
-                         sizeof(T) * 2 * na, hipMemcpyDeviceToHost));
       }
       hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb)), dim3(256), 0, s, st, cb, dsums);
       hipLaunchKernelGGL(k_final_measure<T>, dim3(1), dim3(1024), 0, s, st, n, cb, dsums,
@@ -503,9 +522,11 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   if (herr) return fail(SV_EINVAL, "circuit template is not monomial in its block basis");
   // Records: the decision for block b is written by the pass before it; the
   // record of the very first block lands at index 0 via the init pass.
-  HIP_OK(hipMemcpy(res->records, drec, nrec, hipMemcpyDeviceToHost));
-  HIP_OK(hipMemcpy(res->final_bits, dbits, (size_t)job->n_traj * n, hipMemcpyDeviceToHost));
-  if (res->p1_trace) HIP_OK(hipMemcpy(res->p1_trace, dp1, sizeof(double) * nrec, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpyAsync(res->records, drec, nrec, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(res->final_bits, dbits, (size_t)job->n_traj * n, hipMemcpyDeviceToHost, s));
+  if (res->p1_trace)
+    HIP_OK(hipMemcpyAsync(res->p1_trace, dp1, sizeof(double) * nrec, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
   float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, ev0, ev1));
   double pass_sum = 0.0;
@@ -588,7 +609,7 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   const bool tiled = !small && n <= 16 && ns <= kTiledStab && tp.n_sites <= kTiledSites;
   if (!small && !tiled) return fail(SV_EINVAL, "d=%d batch path not available", d);
   hipStream_t s = in.hs;
-  DevBufs M;
+  DevBufs M(s);
   TBlock* dblocks = nullptr;
   SmallDesc* dsd = nullptr;
   JobConst* djc = nullptr;

@@ -69,3 +69,34 @@ def random_matrix(k, seed, unitary=True):
         return a
     q, r = np.linalg.qr(a)
     return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def serving_stream(window_s, seed=2, rate=200.0, companion=False, n_sites=None):
+    """Poisson job stream of the serving workload: arrivals at `rate` jobs/s
+    over `window_s` seconds; distance 3/4/5 with probabilities 0.6/0.3/0.1,
+    rounds uniform on 1..10, trajectories log-uniform on [10, 10^4], p uniform
+    on [5e-4, 5e-3), per-site theta uniform on [0, 0.05) (eps = theta/2),
+    complex64 or complex128 with probability 1/2 each.
+
+    companion=True scales the offered load down to fit one GPU: d=4 jobs get a
+    tenth of the trajectories and d=5 jobs one trajectory.  `n_sites(d)` gives
+    the gate-site count per round.  Returns a list of (arrival_s, job dict)."""
+    rng = np.random.default_rng([0x5E4E, int(seed), int(companion)])
+    t, out, tag = 0.0, [], 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= window_s:
+            break
+        d = int(rng.choice([3, 4, 5], p=[0.6, 0.3, 0.1]))
+        rounds = int(rng.integers(1, 11))
+        n_traj = int(round(np.exp(rng.uniform(np.log(10.0), np.log(1e4)))))
+        if companion:
+            n_traj = 1 if d == 5 else (max(1, n_traj // 10) if d == 4 else n_traj)
+        p = float(rng.uniform(5e-4, 5e-3))
+        eps = rng.uniform(0.0, 0.05, size=n_sites(d)) / 2.0
+        dtype = "c64" if rng.random() < 0.5 else "c128"
+        out.append((t, dict(tag=tag, d=d, gateset="cr", rounds=rounds, n_traj=n_traj,
+                            seed=int(rng.integers(0, 2 ** 62)), p=p, eps_site=eps, zeta=0.0,
+                            dtype=dtype, traj0=0)))
+        tag += 1
+    return out
