@@ -109,6 +109,39 @@ def batch_run(qs, d, n_traj, dtype, seed=7):
             "alg_gbs": alg / (g["gpu_ms"] * 1e-3) / 1e9}
 
 
+def precision_run(qs, n_traj, thetas=(0.01, 0.03, 0.05)):
+    """Complex64 amplitudes (FP64 probabilities and renormalisation) against
+    complex128 on the same draws: d=5 cross-resonance circuit, p=1e-3,
+    zeta=0.01, 5 rounds, every site over-rotated by theta (eps = theta/2).
+    Infidelity 1 - |<psi64|psi128>|^2 of the register before the final
+    measurement, per trajectory."""
+    import numpy as np
+    from oracle import decoder
+    out = []
+    for theta in thetas:
+        inf, div = [], 0
+        recs = {"c64": [], "c128": []}
+        fins = {"c64": [], "c128": []}
+        for t in range(n_traj):
+            st = {}
+            for dt in ("c128", "c64"):
+                r = qs.run_rounds(5, "cr", 5, 1, seed=1, p=1e-3, eps=theta / 2, zeta=0.01, dtype=dt,
+                                  traj0=t, want_states=True)
+                st[dt] = r["states"][0]
+                recs[dt].append(r["records"][0])
+                fins[dt].append(r["final_bits"][0])
+            a = st["c64"].astype(np.complex128)
+            b = st["c128"]
+            inf.append(1.0 - abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real))
+            div += int(not np.array_equal(recs["c64"][-1], recs["c128"][-1]))
+        pl = {dt: decoder.logical_error_rate(5, 0, np.array(recs[dt]), np.array(fins[dt]))[0]
+              for dt in recs}
+        out.append({"theta": theta, "trajectories": n_traj, "infidelity_max": float(max(inf)),
+                    "infidelity_mean": float(np.mean(inf)), "diverged_trajectories": div,
+                    "p_L_c64": pl["c64"], "p_L_c128": pl["c128"], "delta_p_L": pl["c64"] - pl["c128"]})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,7 +153,9 @@ def main():
     ap.add_argument("--copy-only", action="store_true",
                     help="time only the library's plain register copy (HBM calibration)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched-launch and serving measurements")
+                    help="skip the batched-launch, serving and precision measurements")
+    ap.add_argument("--precision-traj", type=int, default=4,
+                    help="trajectories per angle in the complex64 vs complex128 comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -186,6 +221,7 @@ def main():
         out["d3_trajectories_per_s"] = out["batched"][0]["trajectories_per_s"]
         out["serving"] = [serving_run(qs, "companion", 5.0, 8.0), serving_run(qs, "spec", 2.0, 4.0)]
         out["p99_latency_ms"] = out["serving"][0]["p99_ms"]
+        out["precision"] = precision_run(qs, args.precision_traj)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, eps, args.cpu_blocks)
     print(json.dumps(out), flush=True)
