@@ -119,6 +119,80 @@ __global__ void k_prepare(const TBlock* __restrict__ blocks, int n_stab, int rou
   out[gid] = rt;
 }
 
+// cos / sin of every gate site's angle for each trajectory slot (one thread
+// per slot and op of the round template).
+__global__ void k_site_cs(const TBlock* __restrict__ blocks, int n_stab,
+                          const double* __restrict__ eps, int eps_stride, int n_sites, int slots,
+                          double* __restrict__ cs) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)slots * n_stab * kMaxOps) return;
+  const int slot = (int)(gid / (n_stab * kMaxOps));
+  const int rem = (int)(gid % (n_stab * kMaxOps));
+  const TBlock& b = blocks[rem / kMaxOps];
+  const int i = rem % kMaxOps;
+  if (i >= b.n_ops || b.ops[i].site < 0) return;
+  const TOp& op = b.ops[i];
+  const double beta = op_angle(op, eps + (size_t)slot * eps_stride);
+  cs[((size_t)slot * n_sites + op.site) * 2] = cos(beta);
+  cs[((size_t)slot * n_sites + op.site) * 2 + 1] = sin(beta);
+}
+
+// Kraus pairs of round r for `slots` trajectories with their own seed, draw
+// stream and p: 16 lanes per block instance, lane x evaluates draw x (shared
+// with the group by shuffles) and then the circuit's column x.
+__global__ __launch_bounds__(256) void k_prepare_round(
+    const TBlock* __restrict__ blocks, int n_stab, int r, int draws_round,
+    const uint64_t* __restrict__ seeds, const uint64_t* __restrict__ streams,
+    const double* __restrict__ pvec, const double* __restrict__ cs, int n_sites, int slots,
+    BlockRT* __restrict__ out, int* __restrict__ err) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t inst = gid >> 4;  // (slot, stabilizer)
+  const int x = (int)(gid & 15);
+  const bool valid = inst < (int64_t)slots * n_stab;
+  const int slot = valid ? (int)(inst / n_stab) : 0;
+  const int s = valid ? (int)(inst % n_stab) : 0;
+  const TBlock& b = blocks[s];
+  const double p = pvec[slot];
+  const uint64_t k0 = (uint64_t)r * (uint64_t)draws_round + (uint64_t)b.draw_off;
+  const double u = (valid && x < b.n_draws) ? uniform(seeds[slot], streams[slot], k0 + (uint64_t)x) : 1.0;
+  // every lane runs every shuffle (the op count differs between groups)
+  uint8_t pauli[kMaxOps];
+  for (int i = 0; i < kMaxOps; ++i) {
+    const TOp& op = b.ops[i];
+    const bool drawn = i < b.n_ops && op.draw >= 0;
+    const double ui = __shfl(u, drawn ? op.draw : 0, 16);
+    pauli[i] = 0;
+    if (drawn)
+      pauli[i] = (uint8_t)((op.kind == OP_N1_ANC || op.kind == OP_N1_DATA) ? pick_pauli1(ui, p)
+                                                                            : pick_pauli2(ui, p));
+  }
+  const double um = __shfl(u, b.n_draws - 1, 16);
+  if (!valid) return;
+  BlockRT& o = out[inst];
+  const int nx = 1 << b.w;
+  const double norm = b.type == 0 ? 1.0 / (double)nx : 1.0;
+  if (x < nx) {
+    cd v0, v1;
+    uint32_t cur = 0;
+    if (!track_column(b, CsFromTable{cs + (size_t)slot * n_sites * 2}, pauli, x, v0, v1, &cur))
+      atomicOr(err, 1);
+    o.D[0][x][0] = v0.re * norm;
+    o.D[0][x][1] = v0.im * norm;
+    o.D[1][x][0] = v1.re * norm;
+    o.D[1][x][1] = v1.im * norm;
+    o.W[0][x] = (v0.re * v0.re + v0.im * v0.im) * norm;
+    o.W[1][x] = (v1.re * v1.re + v1.im * v1.im) * norm;
+    if (x == 0) {
+      o.F = cur;
+      o.u = um;
+      o.pad = 0;
+    }
+  } else {
+    o.D[0][x][0] = o.D[0][x][1] = o.D[1][x][0] = o.D[1][x][1] = 0.0;
+    o.W[0][x] = o.W[1][x] = 0.0;
+  }
+}
+
 // -------------------------------------------------------------------- pass --
 constexpr int kTileMax = 12;  // 4096 amplitudes per tile
 
@@ -171,11 +245,26 @@ __device__ __forceinline__ void xcheck_sums(const C2<T>* o, uint32_t lt_a, const
 // logical |0> when WA == 0), the ZZ layer and 1/sqrt(S_m); accumulate S_0,
 // S_1 of block b.  Each workgroup handles `tpw` consecutive tiles and writes
 // one partial pair.
+// Several trajectories in one launch: blockIdx.y selects a trajectory slot;
+// its register, Kraus tables, decision and partial sums sit at the given
+// strides (all zero for a single trajectory).
+struct SlotStrides {
+  size_t st;     // elements of T between registers
+  size_t rt;     // BlockRT entries between slots
+  size_t dec;    // Decision entries between slots
+};
+
 template <typename T, int WA, int WB, int BMODE>
 __global__ __launch_bounds__(256) void k_pass(
     T* __restrict__ st, const PassDesc* __restrict__ pd, const JobConst* __restrict__ jc,
     const BlockRT* __restrict__ rta, const BlockRT* __restrict__ rtb,
-    const Decision* __restrict__ dec_a, double2* __restrict__ partials, int tpw, int reverse) {
+    const Decision* __restrict__ dec_a, double2* __restrict__ partials, int tpw, int reverse,
+    SlotStrides ss) {
+  st += (size_t)blockIdx.y * ss.st;
+  if (rta) rta += (size_t)blockIdx.y * ss.rt;
+  if (rtb) rtb += (size_t)blockIdx.y * ss.rt;
+  if (dec_a) dec_a += (size_t)blockIdx.y * ss.dec;
+  partials += (size_t)blockIdx.y * gridDim.x;
   __shared__ double red[16];
   __shared__ double wtab[32];
   __shared__ C2<T> zzt[64];
@@ -304,7 +393,14 @@ __global__ __launch_bounds__(1024) void k_decide(const double2* __restrict__ par
                                                  const BlockRT* __restrict__ rtb,
                                                  Decision* __restrict__ dec_b,
                                                  uint8_t* __restrict__ rec_b,
-                                                 double* __restrict__ p1_b) {
+                                                 double* __restrict__ p1_b, SlotStrides ss,
+                                                 size_t rec_stride) {
+  // one workgroup per trajectory slot
+  partials += (size_t)blockIdx.x * n;
+  rtb += (size_t)blockIdx.x * ss.rt;
+  dec_b += (size_t)blockIdx.x * ss.dec;
+  rec_b += (size_t)blockIdx.x * rec_stride;
+  if (p1_b) p1_b += (size_t)blockIdx.x * rec_stride;
   __shared__ double red[32];
   double a0 = 0.0, a1 = 0.0;
   // up to 8 independent loads in flight per thread, summed in a fixed order
@@ -336,7 +432,9 @@ __global__ __launch_bounds__(1024) void k_decide(const double2* __restrict__ par
 // Sums of |psi|^2 over contiguous chunks of 2^cb amplitudes.
 template <typename T>
 __global__ __launch_bounds__(256) void k_final_sums(const T* __restrict__ st, int cb,
-                                                     double* __restrict__ sums) {
+                                                     double* __restrict__ sums, size_t st_stride) {
+  st += (size_t)blockIdx.y * st_stride;
+  sums += (size_t)blockIdx.y * gridDim.x;
   __shared__ double red[16];
   const uint64_t base = (uint64_t)blockIdx.x << cb;
   const int len = 1 << cb;
@@ -364,11 +462,24 @@ __device__ double range_sum(const double* buf, int lo, int len, double* red) {
 
 // Sequential measurement of data qubits n-1 .. 0 (labels n .. 1) using the
 // chunk sums for the high n - cb bits and the selected chunk for the rest.
+// Slot blockIdx.x: its register at st + slot * st_stride, its draw stream
+// (seed[slot], t[slot]) when the arrays are given, else (seed0, t0 + slot).
 template <typename T>
 __global__ __launch_bounds__(1024) void k_final_measure(const T* __restrict__ st, int n, int cb,
                                                          const double* __restrict__ sums,
-                                                         uint64_t seed, uint64_t t, uint64_t k0,
-                                                         uint8_t* __restrict__ bits) {
+                                                         uint64_t seed0, uint64_t t0, uint64_t k0,
+                                                         uint8_t* __restrict__ bits, size_t st_stride,
+                                                         const uint64_t* __restrict__ seeds,
+                                                         const uint64_t* __restrict__ streams,
+                                                         const int* __restrict__ rounds,
+                                                         uint64_t draws_round) {
+  const int slot = blockIdx.x;
+  st += (size_t)slot * st_stride;
+  sums += (size_t)slot << (n - cb);
+  bits += (size_t)slot * n;
+  const uint64_t seed = seeds ? seeds[slot] : seed0;
+  const uint64_t t = streams ? streams[slot] : t0 + (uint64_t)slot;
+  if (rounds) k0 = (uint64_t)rounds[slot] * draws_round;
   __shared__ double buf[8192];
   __shared__ double red[32];
   const int hb = n - cb;  // bits resolved by chunk sums

@@ -371,10 +371,12 @@ int pass_snake_order() {
 template <typename T>
 void launch_pass(int wa, int wb, int bmode, dim3 g, dim3 b, hipStream_t s, T* st,
                  const PassDesc* pd, const JobConst* jc, const BlockRT* rta, const BlockRT* rtb,
-                 const Decision* da, double2* part, int tpw, int rev) {
+                 const Decision* da, double2* part, int tpw, int rev,
+                 SlotStrides ss = SlotStrides{0, 0, 0}) {
 #define QEC_PASS(A, B, M)                                                                       \
   if (wa == A && wb == B && bmode == M) {                                                       \
-    hipLaunchKernelGGL((k_pass<T, A, B, M>), g, b, 0, s, st, pd, jc, rta, rtb, da, part, tpw, rev); \
+    hipLaunchKernelGGL((k_pass<T, A, B, M>), g, b, 0, s, st, pd, jc, rta, rtb, da, part, tpw, rev, \
+                       ss);                                                                     \
     return;                                                                                     \
   }
   QEC_PASS(0, 2, B_XCHECK) QEC_PASS(0, 4, B_XCHECK) QEC_PASS(0, 2, B_ZCHECK) QEC_PASS(0, 4, B_ZCHECK)
@@ -486,7 +488,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       launch_pass<T>(0, tp.blocks[0].w, bmode_of(0), grid, block, s, st, &dpass[0], djc, nullptr,
                      rt, nullptr, partials, tpw, 0);
       hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, partials, (int)n_wg, rt, &ddec[0],
-                         rec, p1);
+                         rec, p1, SlotStrides{0, 0, 0}, (size_t)0);
       const bool timed = (tg == last_t);
       for (int bi = 0; bi < per_traj; ++bi) {
         const int sidx = bi % ns;
@@ -500,7 +502,8 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
         if (timed) HIP_OK(hipEventRecord(evs[2 * bi + 1], s));
         if (!last)
           hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, partials, (int)n_wg,
-                             rt + bi + 1, &ddec[bi + 1], rec + bi + 1, p1 ? p1 + bi + 1 : nullptr);
+                             rt + bi + 1, &ddec[bi + 1], rec + bi + 1, p1 ? p1 + bi + 1 : nullptr,
+                             SlotStrides{0, 0, 0}, (size_t)0);
       }
       HIP_OK(hipGetLastError());
       if (res->final_states) {
@@ -508,10 +511,13 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
                               sizeof(T) * 2 * na, hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
       }
-      hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb)), dim3(256), 0, s, st, cb, dsums);
+      hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb)), dim3(256), 0, s, st, cb, dsums,
+                         (size_t)0);
       hipLaunchKernelGGL(k_final_measure<T>, dim3(1), dim3(1024), 0, s, st, n, cb, dsums,
                          job->seed, job->traj0 + (uint64_t)tg,
-                         (uint64_t)R * (uint64_t)draws_round, dbits + (size_t)tg * n);
+                         (uint64_t)R * (uint64_t)draws_round, dbits + (size_t)tg * n, (size_t)0,
+                         (const uint64_t*)nullptr, (const uint64_t*)nullptr, (const int*)nullptr,
+                         (uint64_t)0);
       HIP_OK(hipGetLastError());
     }
   }
@@ -602,12 +608,16 @@ struct BatchInputs {
 };
 
 template <typename T>
+sv_status run_batch_lockstep(BatchInputs& in, const Template& tp);
+
+template <typename T>
 sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   const int d = in.d, n = d * d, ns = (int)tp.blocks.size();
   const int nt = in.n_traj;
   const bool small = n <= kSmallBits && ns <= kSmallStab && tp.n_sites <= kSmallSites;
   const bool tiled = !small && n <= 16 && ns <= kTiledStab && tp.n_sites <= kTiledSites;
   if (!small && !tiled) return fail(SV_EINVAL, "d=%d batch path not available", d);
+  if (tiled && env_int("QECSV_D4_PERSISTENT", 0) == 0) return run_batch_lockstep<T>(in, tp);
   hipStream_t s = in.hs;
   DevBufs M(s);
   TBlock* dblocks = nullptr;
@@ -692,6 +702,187 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   HIP_OK(hipMemcpyAsync(&herr, derr, sizeof herr, hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(in.records, drec, nrec, hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(in.final_bits, dbits, (size_t)nt * n, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (herr) return fail(SV_EINVAL, "circuit template is not monomial in its block basis");
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, ev.a, ev.b));
+  in.gpu_ms = ms;
+  return SV_OK;
+}
+
+// Batched trajectories too large for LDS, run in lockstep: every launch of
+// the fused pass covers (tile, trajectory) pairs, so thousands of 2^16-amplitude
+// registers fill the GPU like one 2^25-amplitude register does.  Slots are the
+// trajectories sorted by round count (longest first), so the trajectories still
+// running in round r are always the first A(r) slots.
+template <typename T>
+sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
+  const int d = in.d, n = d * d, ns = (int)tp.blocks.size(), nt = in.n_traj;
+  const int tb = std::min(kTileMax, n);
+  const size_t n_tiles = (size_t)1 << (n - tb);
+  const int cb = std::min(12, n);
+  const size_t reg = (size_t)2 << n;  // T elements per register
+  const size_t per_reg_bytes = reg * sizeof(T);
+  const size_t cap = (size_t)std::max(1, env_int("QECSV_LOCKSTEP_MIB", 4096)) << 20;
+  const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)nt, cap / per_reg_bytes));
+  const int per_traj = in.max_rounds * ns;
+  const int n_sites = std::max(1, tp.n_sites);
+  hipStream_t s = in.hs;
+  DevBufs M(s);
+  TBlock* dblocks = nullptr;
+  PassDesc* dpass = nullptr;
+  JobConst* djc = nullptr;
+  T* st = nullptr;
+  double2* partials = nullptr;
+  Decision* ddec = nullptr;
+  BlockRT *rtA = nullptr, *rtB = nullptr;
+  uint64_t *dseed = nullptr, *dstream = nullptr;
+  double *dp = nullptr, *deps = nullptr, *dsums = nullptr;
+  int *drounds = nullptr, *derr = nullptr;
+  uint8_t *drec = nullptr, *dbits = nullptr;
+  HIP_OK(M.alloc(&dblocks, sizeof(TBlock) * ns));
+  HIP_OK(M.alloc(&dpass, sizeof(PassDesc) * (ns + 2)));
+  HIP_OK(M.alloc(&djc, sizeof(JobConst)));
+  HIP_OK(M.alloc(&st, per_reg_bytes * G));
+  HIP_OK(M.alloc(&partials, sizeof(double2) * n_tiles * G));
+  HIP_OK(M.alloc(&ddec, sizeof(Decision) * (size_t)(per_traj + 1) * G));
+  HIP_OK(M.alloc(&rtA, sizeof(BlockRT) * (size_t)ns * G));
+  HIP_OK(M.alloc(&rtB, sizeof(BlockRT) * (size_t)ns * G));
+  HIP_OK(M.alloc(&dseed, sizeof(uint64_t) * G));
+  HIP_OK(M.alloc(&dstream, sizeof(uint64_t) * G));
+  HIP_OK(M.alloc(&dp, sizeof(double) * G));
+  HIP_OK(M.alloc(&deps, sizeof(double) * (size_t)n_sites * G));
+  double* dcs = nullptr;
+  HIP_OK(M.alloc(&dcs, sizeof(double) * 2 * (size_t)n_sites * G));
+  HIP_OK(M.alloc(&dsums, (sizeof(double) << (n - cb)) * G));
+  HIP_OK(M.alloc(&drounds, sizeof(int) * G));
+  HIP_OK(M.alloc(&derr, sizeof(int)));
+  HIP_OK(M.alloc(&drec, (size_t)per_traj * G));
+  HIP_OK(M.alloc(&dbits, (size_t)n * G));
+
+  std::vector<PassDesc> pds(ns + 2);
+  pds[0] = make_pass(n, tb, nullptr, &tp.blocks[0], -1, 0);
+  for (int i = 0; i < ns; ++i)
+    pds[1 + i] = make_pass(n, tb, &tp.blocks[i], &tp.blocks[(i + 1) % ns], i, (i + 1) % ns);
+  pds[ns + 1] = make_pass(n, tb, &tp.blocks[ns - 1], nullptr, ns - 1, -1);
+  const JobConst jc = make_job_const(d, in.zeta);
+  HIP_OK(hipMemcpyAsync(dblocks, tp.blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(PassDesc) * (ns + 2), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(djc, &jc, sizeof jc, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
+
+  std::vector<int> order(nt);
+  for (int i = 0; i < nt; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return in.rounds[a] > in.rounds[b]; });
+  struct Ev {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Ev() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  HIP_OK(hipEventCreate(&ev.a));
+  HIP_OK(hipEventCreate(&ev.b));
+  const dim3 block((unsigned)std::max(64, 1 << (tb - 4)));
+  const SlotStrides ss{reg, (size_t)ns, (size_t)per_traj + 1};
+  auto bmode_of = [&](int blk) { return tp.blocks[blk].type == 0 ? B_XCHECK : B_ZCHECK; };
+  std::vector<uint64_t> hseed(G), hstream(G);
+  std::vector<double> hp(G), heps((size_t)n_sites * G);
+  std::vector<int> hrounds(G);
+  std::vector<uint8_t> hrec((size_t)per_traj * G), hbits((size_t)n * G);
+  std::memset(in.records, 0, (size_t)nt * per_traj);
+  int pass_no = 0;
+  HIP_OK(hipEventRecord(ev.a, s));
+  for (int g0 = 0; g0 < nt; g0 += G) {
+    const int gn = std::min(G, nt - g0);
+    for (int i = 0; i < gn; ++i) {
+      const int t = order[g0 + i];
+      hseed[i] = in.seed[t];
+      hstream[i] = in.stream[t];
+      hp[i] = in.p[t];
+      hrounds[i] = in.rounds[t];
+      for (int k = 0; k < tp.n_sites; ++k)
+        heps[(size_t)i * n_sites + k] = in.eps[(size_t)t * in.eps_stride + k];
+    }
+    HIP_OK(hipMemcpyAsync(dseed, hseed.data(), sizeof(uint64_t) * gn, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(dstream, hstream.data(), sizeof(uint64_t) * gn, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(dp, hp.data(), sizeof(double) * gn, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(deps, heps.data(), sizeof(double) * n_sites * gn, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(drounds, hrounds.data(), sizeof(int) * gn, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemsetAsync(drec, 0, (size_t)per_traj * gn, s));
+    auto active = [&](int r) {  // slots with more than r rounds (a prefix)
+      int a = 0;
+      while (a < gn && hrounds[a] > r) ++a;
+      return a;
+    };
+    {
+      const int64_t nth = (int64_t)gn * ns * kMaxOps;
+      hipLaunchKernelGGL(k_site_cs, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, dblocks, ns,
+                         deps, n_sites, n_sites, gn, dcs);
+    }
+    auto prepare = [&](int r, BlockRT* out, int slots) {
+      const int64_t nth = (int64_t)slots * ns * 16;
+      hipLaunchKernelGGL(k_prepare_round, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, dblocks,
+                         ns, r, tp.n_draws, dseed, dstream, dp, dcs, n_sites, slots, out, derr);
+    };
+    auto decide = [&](int slots, const BlockRT* rtb, int bi_b) {
+      hipLaunchKernelGGL(k_decide, dim3(slots), dim3(64), 0, s, partials, (int)n_tiles, rtb,
+                         ddec + bi_b, drec + bi_b, (double*)nullptr, ss, (size_t)per_traj);
+    };
+    prepare(0, rtA, gn);
+    launch_pass<T>(0, tp.blocks[0].w, bmode_of(0), dim3((unsigned)n_tiles, gn), block, s, st, &dpass[0],
+                   djc, nullptr, rtA, nullptr, partials, 1, 0, ss);
+    decide(gn, rtA, 0);
+    const int R0 = hrounds[0];
+    for (int r = 0; r < R0; ++r) {
+      const int Ar = active(r), An = active(r + 1);
+      BlockRT* rt_cur = (r & 1) ? rtB : rtA;
+      BlockRT* rt_nxt = (r & 1) ? rtA : rtB;
+      if (An > 0) prepare(r + 1, rt_nxt, An);
+      for (int sidx = 0; sidx < ns; ++sidx) {
+        const int bi = r * ns + sidx;
+        const int rev = (++pass_no) & 1;
+        if (sidx < ns - 1) {
+          launch_pass<T>(tp.blocks[sidx].w, tp.blocks[sidx + 1].w, bmode_of(sidx + 1),
+                         dim3((unsigned)n_tiles, Ar), block, s, st, &dpass[1 + sidx], djc,
+                         rt_cur + sidx, rt_cur + sidx + 1, ddec + bi, partials, 1, rev, ss);
+          decide(Ar, rt_cur + sidx + 1, bi + 1);
+          continue;
+        }
+        if (An > 0) {
+          launch_pass<T>(tp.blocks[sidx].w, tp.blocks[0].w, bmode_of(0), dim3((unsigned)n_tiles, An),
+                         block, s, st, &dpass[1 + sidx], djc, rt_cur + sidx, rt_nxt, ddec + bi,
+                         partials, 1, rev, ss);
+          decide(An, rt_nxt, bi + 1);
+        }
+        if (Ar > An) {  // trajectories ending with this round
+          const int cnt = Ar - An;
+          launch_pass<T>(tp.blocks[sidx].w, 0, B_NONE, dim3((unsigned)n_tiles, cnt), block, s,
+                         st + (size_t)An * reg, &dpass[ns + 1], djc, rt_cur + (size_t)An * ns + sidx,
+                         nullptr, ddec + (size_t)An * (per_traj + 1) + bi, partials, 1, rev, ss);
+          hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb), cnt), dim3(256), 0, s,
+                             st + (size_t)An * reg, cb, dsums, reg);
+          hipLaunchKernelGGL(k_final_measure<T>, dim3(cnt), dim3(1024), 0, s, st + (size_t)An * reg, n,
+                             cb, dsums, (uint64_t)0, (uint64_t)0, (uint64_t)0, dbits + (size_t)An * n,
+                             reg, dseed + An, dstream + An, drounds + An, (uint64_t)tp.n_draws);
+        }
+      }
+      HIP_OK(hipGetLastError());
+    }
+    HIP_OK(hipMemcpyAsync(hrec.data(), drec, (size_t)per_traj * gn, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(hbits.data(), dbits, (size_t)n * gn, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int i = 0; i < gn; ++i) {
+      const int t = order[g0 + i];
+      std::memcpy(in.records + (size_t)t * per_traj, hrec.data() + (size_t)i * per_traj,
+                  (size_t)hrounds[i] * ns);
+      std::memcpy(in.final_bits + (size_t)t * n, hbits.data() + (size_t)i * n, n);
+    }
+  }
+  HIP_OK(hipEventRecord(ev.b, s));
+  int herr = 0;
+  HIP_OK(hipMemcpyAsync(&herr, derr, sizeof herr, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   if (herr) return fail(SV_EINVAL, "circuit template is not monomial in its block basis");
   float ms = 0.f;
