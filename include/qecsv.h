@@ -173,7 +173,11 @@ typedef struct sv_result {
   void* final_states;   /* host [n_traj][2^(d^2)] amplitudes of dtype before the
                            final measurement, or NULL */
   double gpu_ms;        /* out: device time of the whole run (hipEvents) */
-  double pass_ms;       /* out: mean device time per stabilizer pass */
+  double pass_ms;       /* out: mean device time per register pass of the last
+                           trajectory (one pass applies an X check or a chain
+                           of up to four Z checks) */
+  int passes_per_round; /* out: register passes per round */
+  int pad;
 } sv_result;
 
 /* Run job->n_traj trajectories (indices traj0 ..): logical |0>, `rounds`

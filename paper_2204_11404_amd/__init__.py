@@ -44,6 +44,7 @@ class Result(ctypes.Structure):
         ("records", ctypes.POINTER(ctypes.c_uint8)), ("final_bits", ctypes.POINTER(ctypes.c_uint8)),
         ("p1_trace", ctypes.POINTER(ctypes.c_double)), ("final_states", ctypes.c_void_p),
         ("gpu_ms", ctypes.c_double), ("pass_ms", ctypes.c_double),
+        ("passes_per_round", ctypes.c_int), ("pad", ctypes.c_int),
     ]
 
 
@@ -291,7 +292,7 @@ class State:
 def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0,
                dtype="c128", traj0=0, want_p1=False, want_states=False, stream=None):
     """sv_run_rounds: returns dict(records[n_traj, rounds, n_stab], final_bits[n_traj, d*d],
-    p1 or None, states or None, gpu_ms, pass_ms)."""
+    p1 or None, states or None, gpu_ms, pass_ms, passes_per_round)."""
     n_stab, n_sites, _ = template_info(d, gateset)
     job = Job()
     job.d, job.gateset, job.rounds = d, _GATESETS[gateset], rounds
@@ -317,7 +318,8 @@ def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta
         res.final_states = states.ctypes.data
     _check(lib().sv_run_rounds(ctypes.byref(job), ctypes.byref(res)))
     del keep
-    return dict(records=rec, final_bits=fb, p1=p1, states=states, gpu_ms=res.gpu_ms, pass_ms=res.pass_ms)
+    return dict(records=rec, final_bits=fb, p1=p1, states=states, gpu_ms=res.gpu_ms, pass_ms=res.pass_ms,
+                passes_per_round=res.passes_per_round)
 
 
 def run_batch(d, gateset, rounds, p, seed, eps=0.0, eps_site=None, zeta=0.0, dtype="c64", traj0=0,

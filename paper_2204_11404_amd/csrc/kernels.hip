@@ -3,11 +3,12 @@
 // Trajectory engine (the delayed-measurement loop of Sec. II.B):
 //   k_prepare      per (trajectory, block instance): draw the block's noise
 //                  and measurement uniforms, build its two Kraus operators.
-//   k_pass         one HBM pass per stabilizer circuit: apply the decided
-//                  Kraus operator of block a, the ZZ layer and the
-//                  renormalisation, and accumulate S_0, S_1 of block b; the
-//                  last workgroup reduces the partial sums in a fixed order and
-//                  decides block b's outcome on the device.
+//   k_upass        one HBM pass per unit (an X check, or a chain of Z
+//                  checks): apply the decided Kraus operators of unit A, the
+//                  ZZ layers and the renormalisation, and accumulate the
+//                  outcome sums of unit B.
+//   k_udecide      fixed-order reduction of the per-workgroup sums and the
+//                  outcomes of unit B's checks, on the device.
 //   k_final_sums / k_final_measure   sequential Z measurement of the data
 //                  register (highest label first) from a two-level sum tree.
 // General register ops behind sv_apply_gate / sv_apply_diag / sv_apply_fused /
@@ -66,6 +67,28 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// Wave totals of 32 per-lane values in 32 shuffles (a reduce-scatter: each
+// step hands half of the remaining values to the partner lane): afterwards
+// lanes 2a and 2a + 1 hold the wave total of value a.  Fixed order.
+template <int K>
+__device__ __forceinline__ void reduce_half(double (&v)[32]) {
+  const bool up = (threadIdx.x & (2 * K)) != 0;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const double send = up ? v[i] : v[K + i];
+    const double keep = up ? v[K + i] : v[i];
+    v[i] = keep + __shfl_xor(send, 2 * K, 64);
+  }
+}
+__device__ __forceinline__ double wave_reduce32(double (&v)[32]) {
+  reduce_half<16>(v);
+  reduce_half<8>(v);
+  reduce_half<4>(v);
+  reduce_half<2>(v);
+  reduce_half<1>(v);
+  return v[0] + __shfl_xor(v[0], 1, 64);
 }
 
 // Deterministic block reduction of two doubles (fixed order).  `scratch`
@@ -196,26 +219,50 @@ __global__ __launch_bounds__(256) void k_prepare_round(
 // -------------------------------------------------------------------- pass --
 constexpr int kTileMax = 12;  // 4096 amplitudes per tile
 
-// What follows the applied block in a pass: nothing (last circuit of the
-// trajectory), a Z check (S_m is a pointwise sum over the tile: no data
-// exchange), or an X check (S_m needs a Walsh-Hadamard transform over the
-// check's qubits: the tile is regrouped through LDS).
+// What follows the applied block in a pass of the persistent d = 4 kernel:
+// nothing, a Z check (pointwise sums) or an X check (regrouped through LDS).
 enum : int { B_NONE = 0, B_ZCHECK = 1, B_XCHECK = 2 };
 
+// Several trajectories in one launch: blockIdx.y selects a trajectory slot;
+// its register, Kraus tables and decisions sit at these strides (all zero for
+// a single trajectory).
+struct SlotStrides {
+  size_t st;     // elements of T between registers
+  size_t rt;     // BlockRT entries between slots
+  size_t dec;    // Decision entries between slots
+};
+
+// Local index on a check's qubits (global bits q[0..w)) of global index g,
+// and the global bits of a local pattern F.
+__device__ __forceinline__ uint32_t gather_loc(uint32_t g, const uint32_t* q, int w) {
+  uint32_t x = 0;
+  for (int l = 0; l < w; ++l)
+    if (g & q[l]) x |= 1u << l;
+  return x;
+}
+__device__ __forceinline__ uint32_t scatter_loc(uint32_t F, const uint32_t* q, int w) {
+  uint32_t g = 0;
+  for (int l = 0; l < w; ++l)
+    if ((F >> l) & 1) g |= q[l];
+  return g;
+}
+
 template <typename T>
-struct PassLds {
+struct XposeLds {
   T v[2 << kTileMax];
 };
 
-// Phase 2 for an X check: regroup the tile through LDS by the check's qubits.
+// Sums of an X check from a tile held in layout 1: regroup it through LDS
+// into layout 2, where a lane holds the 16 amplitudes spanning the check's
+// qubits.
 template <typename T, int WB>
-__device__ __forceinline__ void xcheck_sums(const C2<T>* o, uint32_t lt_a, const PassDesc* pd,
-                                            uint32_t fl, const double* wt, bool active,
+__device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const UnitPass* pd,
+                                            const double* w0, const double* w1, bool active,
                                             double& s0, double& s1) {
-  __shared__ PassLds<T> sh;
+  __shared__ XposeLds<T> sh;
   if (active) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) st2(sh.v, lslot((lt_a | pd->a_j_l[j]) ^ fl), o[j]);
+    for (int j = 0; j < 16; ++j) st2(sh.v, lslot(lt_a | pd->j_l[j]), o[j]);
   }
   __syncthreads();
   if (active) {
@@ -233,128 +280,271 @@ __device__ __forceinline__ void xcheck_sums(const C2<T>* o, uint32_t lt_a, const
       for (int x = 0; x < NB; ++x) {
         const double re = (double)v[hi + x].re, im = (double)v[hi + x].im;
         const double a2 = re * re + im * im;
-        s0 += wt[x] * a2;
-        s1 += wt[16 + x] * a2;
+        s0 += w0[x] * a2;
+        s1 += w1[x] * a2;
       }
     }
   }
-  __syncthreads();  // the tile buffer is reused by the next tile
 }
 
-// One pass: apply block a's Kraus operator for its decided outcome (or write
-// logical |0> when WA == 0), the ZZ layer and 1/sqrt(S_m); accumulate S_0,
-// S_1 of block b.  Each workgroup handles `tpw` consecutive tiles and writes
-// one partial pair.
-// Several trajectories in one launch: blockIdx.y selects a trajectory slot;
-// its register, Kraus tables, decision and partial sums sit at the given
-// strides (all zero for a single trajectory).
-struct SlotStrides {
-  size_t st;     // elements of T between registers
-  size_t rt;     // BlockRT entries between slots
-  size_t dec;    // Decision entries between slots
-};
+// Sum of |amplitude|^2 over the 16 layout-2 slots of this thread, from a tile
+// held in layout 1 (regrouped through LDS).
+__device__ __forceinline__ double xpose_norms(const double* a2, uint32_t lt_a, const UnitPass* pd,
+                                              bool active) {
+  __shared__ double buf[1 << kTileMax];
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) buf[lslot(lt_a | pd->j_l[j])] = a2[j];
+  }
+  __syncthreads();
+  double s = 0.0;
+  if (active) {
+    uint32_t lt = 0;
+    for (int i = 0; i < pd->tb - 4; ++i)
+      if ((threadIdx.x >> i) & 1) lt |= pd->b_tid_l[i];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) s += buf[lslot(lt | pd->b_j_l[j])];
+  }
+  return s;
+}
 
-template <typename T, int WA, int WB, int BMODE>
-__global__ __launch_bounds__(256) void k_pass(
-    T* __restrict__ st, const PassDesc* __restrict__ pd, const JobConst* __restrict__ jc,
+// Hypothesis-tree sums of a Z chain for one weight a2 whose local indices on
+// the members are x[0..lb): S[l][h] += a2 * prod_{i <= l} W_i[h_i](x_i).
+template <int LB>
+__device__ __forceinline__ void chain_tree(double a2, const uint32_t* x,
+                                           const double (*wt)[2][16], double* acc) {
+  double pre[8];
+  pre[0] = a2;
+#pragma unroll
+  for (int l = 0; l < kChainMax; ++l) {
+    if (l < LB) {
+      const double w0 = wt[l][0][x[l]], w1 = wt[l][1][x[l]];
+      const int off = (2 << l) - 2;
+#pragma unroll
+      for (int h = 0; h < (1 << l); ++h) {
+        const double p0 = pre[h] * w0, p1 = pre[h] * w1;
+        acc[off + h] += p0;
+        acc[off + h + (1 << l)] += p1;
+        if (l + 1 < kChainMax) {
+          pre[h] = p0;
+          pre[h + (1 << l)] = p1;
+        }
+      }
+    }
+  }
+}
+
+// One pass over the register: apply unit A with its decided outcomes (or
+// write logical |0> when A is U_INIT), each member's ZZ layer and the
+// renormalisation 1/sqrt(S_m); accumulate the sums of unit B from the values
+// still on chip.  B an X check: S_0, S_1 over the check's Hadamard basis.
+// B a chain of L Z checks: S[l][h] for l < L and every outcome string h of
+// members 0..l (bit i = outcome of member i), at index 2^(l+1) - 2 + h.
+// One tile per workgroup; `reverse` walks the tiles backwards (consecutive
+// passes alternate, so a pass starts on the lines its predecessor wrote
+// last).  Workgroup 0 records the frame after A in dec_b.
+// AP: weight of an X check A, or the length of a Z chain A (BP likewise).
+template <typename T, int AK, int AP, int BK, int BP>
+__global__ __launch_bounds__(256) void k_upass(
+    T* __restrict__ st, const UnitPass* __restrict__ pd, const JobConst* __restrict__ jc,
     const BlockRT* __restrict__ rta, const BlockRT* __restrict__ rtb,
-    const Decision* __restrict__ dec_a, double2* __restrict__ partials, int tpw, int reverse,
-    SlotStrides ss) {
+    const Decision* __restrict__ dec_a, Decision* __restrict__ dec_b,
+    double* __restrict__ partials, int reverse, SlotStrides ss) {
   st += (size_t)blockIdx.y * ss.st;
   if (rta) rta += (size_t)blockIdx.y * ss.rt;
   if (rtb) rtb += (size_t)blockIdx.y * ss.rt;
   if (dec_a) dec_a += (size_t)blockIdx.y * ss.dec;
-  partials += (size_t)blockIdx.y * gridDim.x;
-  __shared__ double red[16];
-  __shared__ double wtab[32];
-  __shared__ C2<T> zzt[64];
+  dec_b += (size_t)blockIdx.y * ss.dec;
+  partials += (size_t)blockIdx.y * kChainAcc * gridDim.x;
+  __shared__ C2<T> da[kChainMax][16];
+  __shared__ double wt[kChainMax][2][16];
+  __shared__ C2<T> zzt[4 * 40 + 1];
+  __shared__ double red[kChainAcc][4];
   const int tid = threadIdx.x;
   const int tb = pd->tb;
   const int nt = 1 << (tb - 4);
   const bool active = tid < nt;
-  const int use_zz = (WA != 0) && jc->use_zz;
+  constexpr int WA = AK == U_X ? AP : 0;
+  constexpr int WB = BK == U_X ? BP : 0;
+  constexpr int la = AK == U_Z ? AP : (AK == U_X ? 1 : 0);
+  constexpr int lb = BK == U_Z ? BP : (BK == U_X ? 1 : 0);
+  constexpr int LB = lb;
 
-  if (BMODE != B_NONE && tid < 32) wtab[tid] = rtb->W[tid >> 4][tid & 15];
-  if (use_zz && tid <= jc->n_edges) zzt[tid] = C2<T>{(T)jc->zz[2 * tid], (T)jc->zz[2 * tid + 1]};
-  __syncthreads();
-
-  uint32_t gt = 0, lt = 0, lbt = 0;
-  for (int i = 0; i < tb - 4; ++i)
-    if ((tid >> i) & 1) {
-      gt |= pd->a_tid_g[i];
-      lt |= pd->a_tid_l[i];
-      lbt |= pd->a_tid_lb[i];
-    }
-  // decided outcome of block a and the operator's XOR pattern
-  int m = 0;
+  // frame and decided outcomes of A; frame-dependent offsets
+  uint32_t phi = 0;
+  int mbits = 0;
   double scale = 1.0;
-  uint32_t F = 0, fg = 0, fl = 0, lbf = 0;
-  if constexpr (WA != 0) {
-    m = dec_a->m;
+  if constexpr (AK != U_INIT) {
+    phi = dec_a->phi;
+    mbits = dec_a->m;
     scale = 1.0 / sqrt(dec_a->Sm);
-    F = rta->F;
-    if (pd->typea != 0) {  // Z checks move amplitude x to x XOR F on the check's qubits
-      for (int l = 0; l < WA; ++l)
-        if ((F >> l) & 1) {
-          fg |= pd->a_q_g[l];
-          fl |= pd->a_q_l[l];
-          lbf ^= pd->a_q_lb[l];
-        }
+  }
+  uint32_t M[kChainMax] = {phi, phi, phi, phi};  // logical-index masks of A's ZZ layers
+  uint32_t ca[kChainMax] = {0, 0, 0, 0};         // member-local input offsets
+  uint32_t phi_new = phi;
+  uint32_t Fa = 0;
+  if constexpr (AK == U_X) {
+    Fa = rta->F;
+    if (__popc(gather_loc(phi, pd->aq[0], WA) & Fa) & 1) scale = -scale;
+  }
+  if constexpr (AK == U_Z) {
+    uint32_t G = 0;
+#pragma unroll
+    for (int i = 0; i < kChainMax; ++i)
+      if (i < la) {
+        ca[i] = gather_loc(phi ^ G, pd->aq[i], pd->aw[i]);
+        G ^= scatter_loc(rta[i].F, pd->aq[i], pd->aw[i]);
+        M[i] = phi ^ G;
+      }
+    phi_new = phi ^ G;
+  }
+  uint32_t cb[kChainMax] = {0, 0, 0, 0};
+  if constexpr (BK == U_Z) {
+    uint32_t G = 0;
+#pragma unroll
+    for (int i = 0; i < kChainMax; ++i)
+      if (i < lb) {
+        cb[i] = gather_loc(phi_new ^ G, pd->bq[i], pd->bw[i]);
+        G ^= scatter_loc(rtb[i].F, pd->bq[i], pd->bw[i]);
+      }
+  }
+  if (blockIdx.x == 0 && tid == 0) dec_b->phi = phi_new;
+
+  // tables (the workgroup may have only 64 threads)
+  if constexpr (AK == U_Z) {
+    for (int k = tid; k < kChainMax * 16; k += blockDim.x) {
+      const int i = k >> 4, x = k & 15;
+      if (i < la) {
+        const int m = (mbits >> i) & 1;
+        da[i][x] = C2<T>{(T)rta[i].D[m][x][0], (T)rta[i].D[m][x][1]};
+      }
     }
   }
+  if constexpr (BK == U_Z) {
+    for (int k = tid; k < kChainMax * 32; k += blockDim.x) {
+      const int i = k >> 5, m = (k >> 4) & 1, x = k & 15;
+      if (i < lb) wt[i][m][x] = rtb[i].W[m][x];
+    }
+  }
+  if constexpr (BK == U_X) {
+    if (tid < 32) wt[0][tid >> 4][tid & 15] = rtb->W[tid >> 4][tid & 15];
+  }
+  constexpr int nl = AK == U_Z ? la : 1;
+  const int use_zz = (AK != U_INIT) && jc->use_zz;
+  if (use_zz)
+    for (int k = tid; k <= nl * jc->n_edges; k += blockDim.x)
+      zzt[k] = C2<T>{(T)jc->zzl[nl - 1][2 * k], (T)jc->zzl[nl - 1][2 * k + 1]};
+  __syncthreads();
+
   const int d = jc->d;
   const uint32_t hm = jc->hmask, vm = jc->vmask;
-  double s0 = 0.0, s1 = 0.0;
-
-  const int wg = reverse ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
-  for (int tile = wg * tpw; tile < (wg + 1) * tpw; ++tile) {
-    uint32_t base = 0;
-    for (int i = 0; i < pd->n_outer; ++i)
-      if ((tile >> i) & 1) base |= pd->outer_bit[i];
-    C2<T> o[16];
-    if (active) {
-      if constexpr (WA == 0) {
-        const T amp = (T)jc->amp0;
+  uint32_t eM[kChainMax], vM[kChainMax];
+  bool zz_same = true;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const uint32_t g = base | gt | pd->a_j_g[j];
-          uint32_t x = g;
-          for (int i = 0; i < jc->n_x; ++i)
-            if (x & jc->span_piv[i]) x ^= jc->span_vec[i];
-          o[j] = {x == 0 ? amp : (T)0, (T)0};
-          st2(st, g, o[j]);
+  for (int i = 0; i < kChainMax; ++i) {
+    eM[i] = M[i] ^ (M[i] >> 1);
+    vM[i] = M[i] ^ (M[i] >> d);
+    if (i > 0 && i < nl && M[i] != M[0]) zz_same = false;
+  }
+
+  uint32_t gt = 0, lt = 0;
+  for (int i = 0; i < tb - 4; ++i)
+    if ((tid >> i) & 1) {
+      gt |= pd->tid_g[i];
+      lt |= pd->tid_l[i];
+    }
+  const int wg = reverse ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+  uint32_t base = 0;
+  for (int i = 0; i < pd->n_outer; ++i)
+    if ((wg >> i) & 1) base |= pd->outer_bit[i];
+  const uint32_t gb = base | gt;
+
+  double acc[32];
+#pragma unroll
+  for (int a = 0; a < 32; ++a) acc[a] = 0.0;
+  C2<T> o[16];
+  if (active) {
+    if constexpr (AK == U_INIT) {
+      // g is in the X-stabilizer orbit of 0 iff its reduction against the
+      // echelon basis vanishes; the reduction is linear, so it splits into
+      // the thread's part and the slot's part
+      const T amp = (T)jc->amp0;
+      auto reduce = [&](uint32_t x) {
+        for (int i = 0; i < jc->n_x; ++i)
+          if (x & jc->span_piv[i]) x ^= jc->span_vec[i];
+        return x;
+      };
+      const uint32_t rb = reduce(gb);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t g = gb | pd->j_g[j];
+        o[j] = {(rb ^ reduce(pd->j_g[j])) == 0 ? amp : (T)0, (T)0};
+        st2(st, g, o[j]);
+      }
+    } else {
+      C2<T> v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = ld2(st, gb | pd->j_g[j]);
+      if constexpr (AK == U_X) {
+        const double* D = &rta->D[mbits][0][0];
+        constexpr int NA = 1 << WA;
+#pragma unroll
+        for (int hi = 0; hi < 16; hi += NA) {
+          wht<T, WA>(v + hi);
+#pragma unroll
+          for (int x = 0; x < NA; ++x) v[hi + x] = mulc(v[hi + x], (T)D[2 * x], (T)D[2 * x + 1]);
+          wht<T, WA>(v + hi);
+#pragma unroll
+          for (int x = 0; x < NA; ++x)
+            if (__popc((uint32_t)x & Fa) & 1) v[hi + x] = {-v[hi + x].re, -v[hi + x].im};
         }
       } else {
-        C2<T> v[16];
+        uint32_t oa[kChainMax];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = ld2(st, base | gt | pd->a_j_g[j]);
-        const double* D = &rta->D[m][0][0];
-        constexpr int NA = 1 << WA;
-        if (pd->typea == 0) {
+        for (int i = 0; i < kChainMax; ++i)
+          oa[i] = i < la ? gather_loc(gb, pd->aq[i], pd->aw[i]) ^ ca[i] : 0u;
+        if (pd->amode) {  // the chain's factor is shared by the thread's 16 amplitudes
+          C2<T> f = da[0][oa[0]];
 #pragma unroll
-          for (int hi = 0; hi < 16; hi += NA) {
-            wht<T, WA>(v + hi);
+          for (int i = 1; i < kChainMax; ++i)
+            if (i < la) {
+              const C2<T> e = da[i][oa[i]];
+              f = mulc(f, e.re, e.im);
+            }
 #pragma unroll
-            for (int x = 0; x < NA; ++x) v[hi + x] = mulc(v[hi + x], (T)D[2 * x], (T)D[2 * x + 1]);
-            wht<T, WA>(v + hi);
-#pragma unroll
-            for (int x = 0; x < NA; ++x)
-              if (__popc((uint32_t)x & F) & 1) v[hi + x] = {-v[hi + x].re, -v[hi + x].im};
-          }
+          for (int j = 0; j < 16; ++j) v[j] = mulc(v[j], f.re, f.im);
         } else {
 #pragma unroll
           for (int j = 0; j < 16; ++j) {
-            const int x = j & (NA - 1);
-            v[j] = mulc(v[j], (T)D[2 * x], (T)D[2 * x + 1]);
+            C2<T> f = da[0][oa[0] ^ pd->a_j_loc[0][j]];
+#pragma unroll
+            for (int i = 1; i < kChainMax; ++i)
+              if (i < la) {
+                const C2<T> e = da[i][oa[i] ^ pd->a_j_loc[i][j]];
+                f = mulc(f, e.re, e.im);
+              }
+            v[j] = mulc(v[j], f.re, f.im);
           }
         }
+      }
+      // ZZ phase index: anti-aligned neighbour pairs summed over A's layers
+      // (one popcount pair when every layer sees the same frame)
+      auto finish = [&](auto layers) {
+        constexpr int NZ = decltype(layers)::value;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          const uint32_t g = (base | gt | pd->a_j_g[j]) ^ fg;
+          const uint32_t g = gb | pd->j_g[j];
           C2<T> r = v[j];
           if (use_zz) {
-            const int k = __popc((g ^ (g >> 1)) & hm) + __popc((g ^ (g >> d)) & vm);
-            const C2<T> z = zzt[k];
+            const uint32_t e = g ^ (g >> 1), w = g ^ (g >> d);
+            int K = __popc((e ^ eM[0]) & hm) + __popc((w ^ vM[0]) & vm);
+            if constexpr (NZ == 0) {
+              K *= nl;
+            } else {
+#pragma unroll
+              for (int i = 1; i < NZ; ++i) K += __popc((e ^ eM[i]) & hm) + __popc((w ^ vM[i]) & vm);
+            }
+            const C2<T> z = zzt[K];
             r = mulc(r, z.re, z.im);
           }
           if constexpr (sizeof(T) == 8) {
@@ -367,65 +557,159 @@ __global__ __launch_bounds__(256) void k_pass(
           st2(st, g, r);
           o[j] = r;
         }
-      }
-      if constexpr (BMODE == B_ZCHECK) {
-        // local index of each output amplitude on block b's qubits
+      };
+      if (nl == 1 || zz_same)
+        finish(std::integral_constant<int, 0>{});
+      else
+        finish(std::integral_constant<int, nl>{});
+    }
+  }
+  if constexpr (BK == U_X) {
+    if (pd->bmode == 2) {
+      xpose_xsums<T, WB>(o, lt, pd, wt[0][0], wt[0][1], active, acc[0], acc[1]);
+    } else if (active) {
+      constexpr int NB = 1 << WB;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const uint32_t x = (lbt | pd->a_j_lb[j]) ^ lbf;
-          const double re = (double)o[j].re, im = (double)o[j].im;
+      for (int hi = 0; hi < 16; hi += NB) {
+        C2<T> v[NB];
+#pragma unroll
+        for (int x = 0; x < NB; ++x) v[x] = o[hi + x];
+        wht<T, WB>(v);
+#pragma unroll
+        for (int x = 0; x < NB; ++x) {
+          const double re = (double)v[x].re, im = (double)v[x].im;
           const double a2 = re * re + im * im;
-          s0 += wtab[x] * a2;
-          s1 += wtab[16 + x] * a2;
+          acc[0] += wt[0][0][x] * a2;
+          acc[1] += wt[0][1][x] * a2;
         }
       }
     }
-    if constexpr (BMODE == B_XCHECK) xcheck_sums<T, WB>(o, lt, pd, fl, wtab, active, s0, s1);
   }
-  if constexpr (BMODE == B_NONE) return;
-  block_sum2(s0, s1, red);
-  if (tid == 0) partials[wg] = make_double2(s0, s1);
+  if constexpr (BK == U_Z) {
+    double a2[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double re = (double)o[j].re, im = (double)o[j].im;
+      a2[j] = active ? re * re + im * im : 0.0;
+    }
+    if (pd->bmode == 0) {
+      if (active) {
+        uint32_t ob[kChainMax];
+#pragma unroll
+        for (int i = 0; i < kChainMax; ++i)
+          ob[i] = i < lb ? gather_loc(gb, pd->bq[i], pd->bw[i]) ^ cb[i] : 0u;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          uint32_t x[kChainMax];
+#pragma unroll
+          for (int i = 0; i < kChainMax; ++i) x[i] = ob[i] ^ pd->b_j_loc[i][j];
+          chain_tree<LB>(a2[j], x, wt, acc);
+        }
+      }
+    } else {
+      double s = 0.0;
+      uint32_t g2 = gb;
+      if (pd->bmode == 1) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) s += a2[j];
+      } else {
+        s = xpose_norms(a2, lt, pd, active);
+        g2 = base;
+        for (int i = 0; i < tb - 4; ++i)
+          if ((tid >> i) & 1) g2 |= pd->b_tid_g[i];
+      }
+      if (active) {
+        uint32_t x[kChainMax];
+#pragma unroll
+        for (int i = 0; i < kChainMax; ++i)
+          x[i] = i < lb ? gather_loc(g2, pd->bq[i], pd->bw[i]) ^ cb[i] : 0u;
+        chain_tree<LB>(s, x, wt, acc);
+      }
+    }
+  }
+  if constexpr (BK == U_NONE) return;
+  constexpr int nacc = (2 << lb) - 2;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int nw = (int)(blockDim.x + 63) >> 6;
+  if constexpr (nacc <= 6) {
+#pragma unroll
+    for (int a = 0; a < nacc; ++a) {
+      const double s = wave_sum(acc[a]);
+      if (lane == 0) red[a][wid] = s;
+    }
+  } else {
+    const double s = wave_reduce32(acc);
+    if ((lane & 1) == 0 && (lane >> 1) < nacc) red[lane >> 1][wid] = s;
+  }
+  __syncthreads();
+  if (tid < nacc) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[tid][w];
+    partials[(size_t)tid * gridDim.x + wg] = s;
+  }
 }
 
-// Outcome of block b: reduce the per-tile partials in a fixed order, clamp
-// p1, compare with the block's measurement draw.
-__global__ __launch_bounds__(1024) void k_decide(const double2* __restrict__ partials, int n,
-                                                 const BlockRT* __restrict__ rtb,
+// Outcomes of unit B (a chain of lb checks; lb = 1 for an X check).  Grid
+// (nacc, slots): workgroup a reduces sum a over the per-workgroup partials in
+// a fixed order; the last workgroup of a slot to finish (ticket counter,
+// reset for the next use) decides the members in order, each from the two
+// sums that follow the outcomes already drawn:
+// p1 = S[l][h | 1 << l] / (S[l][h] + S[l][h | 1 << l]), clamped, against
+// member l's measurement draw.
+__global__ __launch_bounds__(256) void k_udecide(const double* __restrict__ partials, int n,
+                                                 int lb, const BlockRT* __restrict__ rtb,
                                                  Decision* __restrict__ dec_b,
                                                  uint8_t* __restrict__ rec_b,
                                                  double* __restrict__ p1_b, SlotStrides ss,
-                                                 size_t rec_stride) {
-  // one workgroup per trajectory slot
-  partials += (size_t)blockIdx.x * n;
-  rtb += (size_t)blockIdx.x * ss.rt;
-  dec_b += (size_t)blockIdx.x * ss.dec;
-  rec_b += (size_t)blockIdx.x * rec_stride;
-  if (p1_b) p1_b += (size_t)blockIdx.x * rec_stride;
-  __shared__ double red[32];
-  double a0 = 0.0, a1 = 0.0;
+                                                 size_t rec_stride, double* __restrict__ sums,
+                                                 unsigned* __restrict__ tickets) {
+  const int a = blockIdx.x, slot = blockIdx.y;
+  const int nacc = (2 << lb) - 2;
+  partials += ((size_t)slot * kChainAcc + a) * n;
+  sums += (size_t)slot * kChainAcc;
+  __shared__ double red[8];
+  __shared__ int last;
+  double s = 0.0, dummy = 0.0;
   // up to 8 independent loads in flight per thread, summed in a fixed order
   for (int i0 = 0; i0 < n; i0 += 8 * (int)blockDim.x) {
-    double2 v[8];
+    double v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int i = i0 + k * (int)blockDim.x + (int)threadIdx.x;
-      v[k] = i < n ? partials[i] : make_double2(0.0, 0.0);
+      v[k] = i < n ? partials[i] : 0.0;
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      a0 += v[k].x;
-      a1 += v[k].y;
-    }
+    for (int k = 0; k < 8; ++k) s += v[k];
   }
-  block_sum2(a0, a1, red);
+  block_sum2(s, dummy, red);
   if (threadIdx.x == 0) {
-    const double p1 = clamp_p1(a1 / (a0 + a1));
-    const int m = (rtb->u < p1) ? 1 : 0;
-    dec_b->m = m;
-    dec_b->Sm = m ? a1 : a0;
-    *rec_b = (uint8_t)m;
-    if (p1_b) *p1_b = p1;
+    sums[a] = s;
+    __threadfence();
+    last = atomicAdd(&tickets[slot], 1u) == (unsigned)(nacc - 1);
   }
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  __threadfence();
+  const volatile double* S = sums;
+  rtb += (size_t)slot * ss.rt;
+  dec_b += (size_t)slot * ss.dec;
+  rec_b += (size_t)slot * rec_stride;
+  if (p1_b) p1_b += (size_t)slot * rec_stride;
+  int h = 0;
+  double Sm = 0.0;
+  for (int l = 0; l < lb; ++l) {
+    const int off = (2 << l) - 2;
+    const double s0 = S[off + h], s1 = S[off + (h | (1 << l))];
+    const double p1 = clamp_p1(s1 / (s0 + s1));
+    const int m = (rtb[l].u < p1) ? 1 : 0;
+    rec_b[l] = (uint8_t)m;
+    if (p1_b) p1_b[l] = p1;
+    h |= m << l;
+    Sm = m ? s1 : s0;
+  }
+  dec_b->m = h;
+  dec_b->Sm = Sm;
+  tickets[slot] = 0u;
 }
 
 // ------------------------------------------------------ final measurement --
@@ -461,7 +745,8 @@ __device__ double range_sum(const double* buf, int lo, int len, double* red) {
 }
 
 // Sequential measurement of data qubits n-1 .. 0 (labels n .. 1) using the
-// chunk sums for the high n - cb bits and the selected chunk for the rest.
+// chunk sums for the high n - cb bits and the selected chunk for the rest;
+// the register is read in the Pauli-X frame recorded in dfin (if given).
 // Slot blockIdx.x: its register at st + slot * st_stride, its draw stream
 // (seed[slot], t[slot]) when the arrays are given, else (seed0, t0 + slot).
 template <typename T>
@@ -472,8 +757,12 @@ __global__ __launch_bounds__(1024) void k_final_measure(const T* __restrict__ st
                                                          const uint64_t* __restrict__ seeds,
                                                          const uint64_t* __restrict__ streams,
                                                          const int* __restrict__ rounds,
-                                                         uint64_t draws_round) {
+                                                         uint64_t draws_round,
+                                                         const Decision* __restrict__ dfin,
+                                                         size_t dfin_stride) {
   const int slot = blockIdx.x;
+  // Pauli-X frame of the register: logical bit q = physical bit q ^ phi_q
+  const uint32_t phi = dfin ? dfin[(size_t)slot * dfin_stride].phi : 0u;
   st += (size_t)slot * st_stride;
   sums += (size_t)slot << (n - cb);
   bits += (size_t)slot * n;
@@ -490,13 +779,15 @@ __global__ __launch_bounds__(1024) void k_final_measure(const T* __restrict__ st
   int level = 0;
   for (; level < hb; ++level) {
     const int half = size >> 1;
-    const double S0 = range_sum(buf, lo, half, red);
-    const double S1 = range_sum(buf, lo + half, half, red);
+    const double P0 = range_sum(buf, lo, half, red);
+    const double P1 = range_sum(buf, lo + half, half, red);
+    const int fq = (phi >> (n - 1 - level)) & 1;
+    const double S0 = fq ? P1 : P0, S1 = fq ? P0 : P1;
     const double p1 = clamp_p1(S1 / (S0 + S1));
     const double u = uniform(seed, t, k0 + (uint64_t)level);
     const int b = (u < p1) ? 1 : 0;
     if (threadIdx.x == 0) bits[n - 1 - level] = (uint8_t)b;
-    if (b) lo += half;
+    if (b ^ fq) lo += half;
     size = half;
   }
   const uint64_t cbase = (uint64_t)lo << cb;
@@ -512,13 +803,15 @@ __global__ __launch_bounds__(1024) void k_final_measure(const T* __restrict__ st
   size = len;
   for (; level < n; ++level) {
     const int half = size >> 1;
-    const double S0 = range_sum(buf, lo, half, red);
-    const double S1 = range_sum(buf, lo + half, half, red);
+    const double P0 = range_sum(buf, lo, half, red);
+    const double P1 = range_sum(buf, lo + half, half, red);
+    const int fq = (phi >> (n - 1 - level)) & 1;
+    const double S0 = fq ? P1 : P0, S1 = fq ? P0 : P1;
     const double p1 = clamp_p1(S1 / (S0 + S1));
     const double u = uniform(seed, t, k0 + (uint64_t)level);
     const int b = (u < p1) ? 1 : 0;
     if (threadIdx.x == 0) bits[n - 1 - level] = (uint8_t)b;
-    if (b) lo += half;
+    if (b ^ fq) lo += half;
     size = half;
   }
 }

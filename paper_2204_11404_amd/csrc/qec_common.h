@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #define QEC_HD __host__ __device__ __forceinline__
 
@@ -375,12 +376,63 @@ struct JobConst {
   uint32_t span_piv[16];   // pivot bit of each basis vector
   double zz[2 * 64];       // exp(-i zeta (|E| - 2k)), k = 0..|E|
   int use_zz;
+  int pad;
+  // L consecutive ZZ layers: exp(-i zeta (L |E| - 2K)), K = 0..L|E|, L = 1..kChainMax
+  double zzl[4][2 * (4 * 40 + 1)];
 };
 
+// Outcome of one pass unit (a single check, or a chain of Z checks: bit i of
+// m is the outcome of chain member i), the norm^2 of the kept branch, and the
+// register's Pauli-X frame before the unit is applied (see UnitPass).
 struct Decision {
-  double Sm;      // norm^2 of the kept half
-  int m;          // outcome
-  int pad;
+  double Sm;
+  int m;
+  uint32_t phi;
+};
+
+// ------------------------------------------------------------ pass units --
+// The trajectory engine runs one HBM pass per "unit": a single X check, or a
+// chain of up to kChainMax consecutive Z checks.  Z checks are monomial in the
+// computational basis (diag(D_m), then an XOR permutation by F), so a chain is
+// pointwise on the amplitude index: its S_m for every prefix of outcomes
+// (a binary tree of 2^(L+1) - 2 sums) comes out of one read of the register,
+// and the next pass applies the whole decided chain.  The XOR permutations are
+// never carried out in memory: the register is kept in a Pauli-X frame phi,
+// physical index p holding logical amplitude p ^ phi.  A Z check then rewrites
+// every amplitude in place and updates phi; an X check commutes with the frame
+// up to the global sign (-1)^{popcount(phi_b & F)} (phi_b: phi on the check's
+// qubits); S_m of an X check does not depend on phi; the final measurement
+// reads logical bit q as physical bit q ^ phi_q.
+constexpr int kChainMax = 4;
+constexpr int kChainAcc = (2 << kChainMax) - 2;  // sums of a full chain
+enum : int { U_NONE = 0, U_X = 1, U_Z = 2, U_INIT = 3 };
+
+// Layout and unit description of one pass: apply unit A (decided), accumulate
+// the sums of unit B.  Tiles of 2^tb amplitudes; a thread owns 16 amplitudes
+// (register slot j) at a time.  Phase 1 (apply A) uses layout 1, whose slot
+// bits are A's qubits for an X check, or for a Z chain bits outside A's qubits
+// where possible (then the chain's factor is the same for the thread's 16
+// amplitudes: amode = 1).  Phase 2 (sums of B) either stays in layout 1
+// (bmode 1: an X check B whose qubits are the slot bits, or a Z chain B whose
+// qubits avoid the slot bits, summed once per thread), regroups the tile
+// through LDS into layout 2 (bmode 2: slot bits = B's qubits for an X check,
+// bits outside B's qubits for a Z chain), or evaluates a Z chain amplitude by
+// amplitude in layout 1 (bmode 0, when no 4 tile bits avoid B's qubits).
+struct UnitPass {
+  int tb, n_outer;
+  int akind, la, wa;       // A: U_INIT / U_X / U_Z, chain length, X weight
+  int bkind, lb, wb;       // B: U_NONE / U_X / U_Z
+  int amode, bmode;
+  uint32_t outer_bit[32];
+  uint32_t tid_g[8], tid_l[8];     // layout 1: global / LDS bit of each thread-index bit
+  uint32_t j_g[16], j_l[16];       // layout 1: global / LDS bits of slot j
+  uint32_t b_tid_g[8], b_tid_l[8];  // layout 2
+  uint32_t b_j_l[16];
+  uint32_t aq[kChainMax][4];     // global bit of local bit l of A's member i
+  uint32_t bq[kChainMax][4];
+  int aw[kChainMax], bw[kChainMax];
+  uint32_t a_j_loc[kChainMax][16];  // member-i local index carried by slot j's bits (layout 1)
+  uint32_t b_j_loc[kChainMax][16];
 };
 
 }  // namespace qec

@@ -50,6 +50,12 @@ sv_status fail(sv_status st, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(SV_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+#define SV_OK_OR_RETURN(expr)                \
+  do {                                       \
+    const sv_status s_ = (expr);             \
+    if (s_ != SV_OK) return s_;              \
+  } while (0)
+
 // Device buffers for one call, allocated and released in stream order from
 // the device's default pool (no device-wide synchronisation, memory is reused
 // across calls).
@@ -275,7 +281,196 @@ JobConst make_job_const(int d, double zeta) {
     jc.zz[2 * k + 1] = std::sin(th);
   }
   jc.use_zz = zeta != 0.0;
+  for (int L = 1; L <= kChainMax; ++L)
+    for (int k = 0; k <= L * ne; ++k) {
+      const double th = -zeta * (double)(L * ne - 2 * k);
+      jc.zzl[L - 1][2 * k] = std::cos(th);
+      jc.zzl[L - 1][2 * k + 1] = std::sin(th);
+    }
   return jc;
+}
+
+// ------------------------------------------------------------ pass units --
+struct Unit {
+  int kind;   // U_X or U_Z
+  int first;  // template index of the first member
+  int len;    // members (1 for an X check)
+};
+
+// Longest Z chain per pass: QECSV_ZCHAIN (1..kChainMax), default kChainMax.
+int zchain_max() {
+  int L = kChainMax;
+  if (const char* e = std::getenv("QECSV_ZCHAIN")) L = std::atoi(e);
+  return std::max(1, std::min(kChainMax, L));
+}
+
+// Units of one round: every X check alone, runs of consecutive Z checks cut
+// into chains of at most max_chain members.
+std::vector<Unit> make_units(const Template& tp, int max_chain) {
+  std::vector<Unit> u;
+  for (int s = 0; s < (int)tp.blocks.size(); ++s) {
+    if (tp.blocks[s].type == 0)
+      u.push_back({U_X, s, 1});
+    else if (!u.empty() && u.back().kind == U_Z && u.back().len < max_chain &&
+             u.back().first + u.back().len == s)
+      u.back().len++;
+    else
+      u.push_back({U_Z, s, 1});
+  }
+  return u;
+}
+
+// Pass descriptor: apply unit A (nullptr: write logical |0>), sum unit B
+// (nullptr: none).  Slot bits of a layout: an X check's qubits (then further
+// bits as needed), or four bits outside the qubits of the chain(s) to be
+// evaluated per thread, taken from bit tb - 4 upwards so that the
+// thread-index bits are the lowest tile bits (coalesced runs).  The tile
+// holds both layouts' slot bits and then the lowest remaining bits.
+UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, const Unit* B) {
+  UnitPass pd{};
+  const int tb = std::min(tb_max, n);
+  pd.tb = tb;
+  pd.akind = A ? A->kind : U_INIT;
+  pd.la = A ? A->len : 0;
+  pd.bkind = B ? B->kind : U_NONE;
+  pd.lb = B ? B->len : 0;
+  pd.wa = (A && A->kind == U_X) ? tp.blocks[A->first].w : 0;
+  pd.wb = (B && B->kind == U_X) ? tp.blocks[B->first].w : 0;
+  auto members = [&](const Unit* U, uint32_t (*q)[4], int* w) {
+    if (!U) return;
+    for (int i = 0; i < U->len; ++i) {
+      const TBlock& b = tp.blocks[U->first + i];
+      w[i] = b.w;
+      for (int l = 0; l < b.w; ++l) q[i][l] = 1u << b.qubit[l];
+    }
+  };
+  members(A, pd.aq, pd.aw);
+  members(B, pd.bq, pd.bw);
+  auto xqubits = [&](const Unit* U) {
+    std::vector<int> qs;
+    const TBlock& b = tp.blocks[U->first];
+    for (int l = 0; l < b.w; ++l) qs.push_back(b.qubit[l]);
+    return qs;
+  };
+  auto umask = [&](const Unit* U) {  // union of a unit's qubits
+    uint32_t m = 0;
+    if (U)
+      for (int i = 0; i < U->len; ++i)
+        for (int l = 0; l < tp.blocks[U->first + i].w; ++l) m |= 1u << tp.blocks[U->first + i].qubit[l];
+    return m;
+  };
+  const uint32_t UA = (A && A->kind == U_Z) ? umask(A) : 0u;
+  const uint32_t UB = (B && B->kind == U_Z) ? umask(B) : 0u;
+  // `fixed` first, then the highest bits outside `avoid` until 4 bits; false
+  // if there are not enough such bits
+  auto slots = [&](std::vector<int> fixed, uint32_t avoid, std::vector<int>& out) {
+    out = fixed;
+    uint32_t used = avoid;
+    for (int q : fixed) used |= 1u << q;
+    for (int k = 0; k < n && (int)out.size() < 4; ++k) {
+      const int bit = (k + tb - 4) % n;  // from just above the thread-index bits
+      if (!((used >> bit) & 1)) { out.push_back(bit); used |= 1u << bit; }
+    }
+    return (int)out.size() == 4;
+  };
+  auto disjoint = [](const std::vector<int>& qs, uint32_t m) {
+    for (int q : qs) if ((m >> q) & 1) return false;
+    return true;
+  };
+  std::vector<int> J1, J2;
+  bool have2 = false;
+  pd.amode = 0;
+  pd.bmode = 0;
+  const bool ax = A && A->kind == U_X, az = A && A->kind == U_Z;
+  const bool bx = B && B->kind == U_X, bz = B && B->kind == U_Z;
+  // an X check's qubits serve as layout-1 slot bits only if that keeps the
+  // four lowest bits for the thread index (runs of >= 256 bytes)
+  const bool bx_high = bx && disjoint(xqubits(B), 0xFu);
+  if (ax) {
+    if (!slots(xqubits(A), UB, J1)) slots(xqubits(A), 0u, J1);
+  } else if (az) {
+    if (bx_high && disjoint(xqubits(B), UA) && slots(xqubits(B), UA, J1)) {
+      pd.amode = 1;
+    } else if (slots({}, UA | UB, J1) || slots({}, UA, J1)) {
+      pd.amode = 1;
+    } else {
+      slots({}, 0u, J1);
+    }
+  } else {  // logical |0>
+    if (bx_high) slots(xqubits(B), 0u, J1);
+    else if (!(bz && slots({}, UB, J1))) slots({}, 0u, J1);
+  }
+  auto jmask = [](const std::vector<int>& J) {
+    uint32_t m = 0;
+    for (int q : J) m |= 1u << q;
+    return m;
+  };
+  if (bx) {
+    const std::vector<int> bq = xqubits(B);
+    bool in_regs = !ax && J1.size() >= bq.size();
+    for (size_t l = 0; l < bq.size() && in_regs; ++l) in_regs = J1[l] == bq[l];
+    if (in_regs) {
+      pd.bmode = 1;
+    } else {
+      slots(bq, 0u, J2);
+      have2 = true;
+      pd.bmode = 2;
+    }
+  } else if (bz) {
+    if ((jmask(J1) & UB) == 0) {
+      pd.bmode = 1;
+    } else if (slots({}, UB, J2)) {
+      have2 = true;
+      pd.bmode = 2;
+    } else {
+      pd.bmode = 0;
+    }
+  }
+  // tile: slot bits of both layouts, then the lowest remaining bits
+  std::vector<bool> in_t(n, false);
+  int cnt = 0;
+  for (int x : J1) if (!in_t[x]) { in_t[x] = true; ++cnt; }
+  if (have2)
+    for (int x : J2) if (!in_t[x]) { in_t[x] = true; ++cnt; }
+  for (int bit = 0; bit < n && cnt < tb; ++bit)
+    if (!in_t[bit]) { in_t[bit] = true; ++cnt; }
+  std::vector<int> rank(n, -1);
+  int r = 0;
+  pd.n_outer = 0;
+  for (int bit = 0; bit < n; ++bit) {
+    if (in_t[bit]) rank[bit] = r++;
+    else pd.outer_bit[pd.n_outer++] = 1u << bit;
+  }
+  auto fill = [&](const std::vector<int>& J, uint32_t* tid_g, uint32_t* tid_l, uint32_t* j_g,
+                  uint32_t* j_l) {
+    std::vector<int> rest;
+    for (int bit = 0; bit < n; ++bit)
+      if (in_t[bit] && std::find(J.begin(), J.end(), bit) == J.end()) rest.push_back(bit);
+    for (int i = 0; i < tb - 4; ++i) {
+      tid_g[i] = 1u << rest[i];
+      tid_l[i] = 1u << rank[rest[i]];
+    }
+    for (int j = 0; j < 16; ++j) {
+      uint32_t g = 0, l = 0;
+      for (int b = 0; b < 4; ++b)
+        if ((j >> b) & 1) { g |= 1u << J[b]; l |= 1u << rank[J[b]]; }
+      if (j_g) j_g[j] = g;
+      j_l[j] = l;
+    }
+  };
+  fill(J1, pd.tid_g, pd.tid_l, pd.j_g, pd.j_l);
+  if (have2) fill(J2, pd.b_tid_g, pd.b_tid_l, nullptr, pd.b_j_l);
+  auto loc = [](uint32_t g, const uint32_t* q, int w) {
+    uint32_t x = 0;
+    for (int l = 0; l < w; ++l)
+      if (g & q[l]) x |= 1u << l;
+    return x;
+  };
+  for (int i = 0; i < pd.la; ++i)
+    for (int j = 0; j < 16; ++j) pd.a_j_loc[i][j] = loc(pd.j_g[j], pd.aq[i], pd.aw[i]);
+  for (int i = 0; i < pd.lb; ++i)
+    for (int j = 0; j < 16; ++j) pd.b_j_loc[i][j] = loc(pd.j_g[j], pd.bq[i], pd.bw[i]);
+  return pd;
 }
 
 // ------------------------------------------------------ pass descriptors --
@@ -350,16 +545,6 @@ PassDesc make_pass(int n, int tb_max, const TBlock* A, const TBlock* B, int ia, 
   return pd;
 }
 
-// Tiles per workgroup of the fused pass: QECSV_TILES_PER_WG if set (power of
-// two), else 1 (measured fastest on gfx950 for 2^25-amplitude registers).
-int pass_tiles_per_wg(size_t n_tiles) {
-  int tpw = 1;
-  if (const char* e = std::getenv("QECSV_TILES_PER_WG")) tpw = std::max(1, std::atoi(e));
-  while (tpw > 1 && (n_tiles % (size_t)tpw) != 0) tpw >>= 1;
-  if ((size_t)tpw > n_tiles) tpw = (int)n_tiles;
-  return tpw;
-}
-
 // Alternate the tile traversal direction between consecutive passes so that a
 // pass starts on the lines its predecessor wrote last (QECSV_SNAKE=0 turns it
 // off).
@@ -368,22 +553,43 @@ int pass_snake_order() {
   return 1;
 }
 
+// Launches the pass kernel instantiated for the descriptor's unit kinds.
 template <typename T>
-void launch_pass(int wa, int wb, int bmode, dim3 g, dim3 b, hipStream_t s, T* st,
-                 const PassDesc* pd, const JobConst* jc, const BlockRT* rta, const BlockRT* rtb,
-                 const Decision* da, double2* part, int tpw, int rev,
-                 SlotStrides ss = SlotStrides{0, 0, 0}) {
-#define QEC_PASS(A, B, M)                                                                       \
-  if (wa == A && wb == B && bmode == M) {                                                       \
-    hipLaunchKernelGGL((k_pass<T, A, B, M>), g, b, 0, s, st, pd, jc, rta, rtb, da, part, tpw, rev, \
-                       ss);                                                                     \
-    return;                                                                                     \
+sv_status launch_upass(const UnitPass& h, dim3 g, dim3 b, hipStream_t s, T* st, const UnitPass* pd,
+                       const JobConst* jc, const BlockRT* rta, const BlockRT* rtb,
+                       const Decision* da, Decision* db, double* part, int rev,
+                       SlotStrides ss = SlotStrides{0, 0, 0}) {
+#define QEC_UP(AK, AP, BK, BP)                                                                  \
+  if (h.akind == AK && ap == AP && h.bkind == BK && bp == BP) {                                 \
+    hipLaunchKernelGGL((k_upass<T, AK, AP, BK, BP>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, \
+                       part, rev, ss);                                                          \
+    return SV_OK;                                                                               \
   }
-  QEC_PASS(0, 2, B_XCHECK) QEC_PASS(0, 4, B_XCHECK) QEC_PASS(0, 2, B_ZCHECK) QEC_PASS(0, 4, B_ZCHECK)
-  QEC_PASS(2, 0, B_NONE) QEC_PASS(4, 0, B_NONE)
-  QEC_PASS(2, 2, B_XCHECK) QEC_PASS(2, 4, B_XCHECK) QEC_PASS(4, 2, B_XCHECK) QEC_PASS(4, 4, B_XCHECK)
-  QEC_PASS(2, 2, B_ZCHECK) QEC_PASS(2, 4, B_ZCHECK) QEC_PASS(4, 2, B_ZCHECK) QEC_PASS(4, 4, B_ZCHECK)
-#undef QEC_PASS
+#define QEC_UP_B(AK, AP) \
+  QEC_UP(AK, AP, U_X, 2) QEC_UP(AK, AP, U_X, 4) QEC_UP(AK, AP, U_Z, 1) QEC_UP(AK, AP, U_Z, 2) \
+  QEC_UP(AK, AP, U_Z, 3) QEC_UP(AK, AP, U_Z, 4)
+  const int ap = h.akind == U_X ? h.wa : (h.akind == U_Z ? h.la : 0);
+  const int bp = h.bkind == U_X ? h.wb : (h.bkind == U_Z ? h.lb : 0);
+  QEC_UP_B(U_INIT, 0)
+  QEC_UP_B(U_X, 2) QEC_UP_B(U_X, 4) QEC_UP(U_X, 2, U_NONE, 0) QEC_UP(U_X, 4, U_NONE, 0)
+  QEC_UP_B(U_Z, 1) QEC_UP_B(U_Z, 2) QEC_UP_B(U_Z, 3) QEC_UP_B(U_Z, 4)
+  QEC_UP(U_Z, 1, U_NONE, 0) QEC_UP(U_Z, 2, U_NONE, 0) QEC_UP(U_Z, 3, U_NONE, 0) QEC_UP(U_Z, 4, U_NONE, 0)
+#undef QEC_UP_B
+#undef QEC_UP
+  return fail(SV_EINVAL, "no pass kernel for units (%d,%d)->(%d,%d)", h.akind, h.wa, h.bkind, h.wb);
+}
+
+// Passes of a round sequence: [0] writes logical |0> and sums unit 0;
+// [1 + u] applies unit u and sums unit u + 1 (unit 0 of the next round after
+// the last); [nu + 1] applies the last unit and sums nothing.
+std::vector<UnitPass> make_unit_passes(int n, int tb, const Template& tp,
+                                       const std::vector<Unit>& units) {
+  const int nu = (int)units.size();
+  std::vector<UnitPass> pds(nu + 2);
+  pds[0] = make_unit_pass(n, tb, tp, nullptr, &units[0]);
+  for (int u = 0; u < nu; ++u) pds[1 + u] = make_unit_pass(n, tb, tp, &units[u], &units[(u + 1) % nu]);
+  pds[nu + 1] = make_unit_pass(n, tb, tp, &units[nu - 1], nullptr);
+  return pds;
 }
 
 }  // namespace
@@ -395,13 +601,16 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
                        const std::atomic<int>* cancel = nullptr) {
   const int d = job->d, n = d * d, ns = (int)tp.blocks.size(), R = job->rounds;
   const int tb = std::min(kTileMax, n);
-  const int per_traj = R * ns;
+  const int per_traj = R * ns;  // block instances (records) per trajectory
+  const std::vector<Unit> units = make_units(tp, zchain_max());
+  const int nu = (int)units.size();
+  const int per_units = R * nu;  // passes per trajectory after the first
   hipStream_t s = (hipStream_t)job->hip_stream;
   DevBufs M(s);
   T* st = nullptr;
-  double2* partials = nullptr;
+  double* partials = nullptr;
   TBlock* dblocks = nullptr;
-  PassDesc* dpass = nullptr;
+  UnitPass* dpass = nullptr;
   JobConst* djc = nullptr;
   double* deps = nullptr;
   Decision* ddec = nullptr;
@@ -419,12 +628,17 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)job->n_traj, ((size_t)64 << 20) / rt_per_traj));
   const size_t nrec = (size_t)job->n_traj * per_traj;
   HIP_OK(M.alloc(&st, sizeof(T) * 2 * na));
-  HIP_OK(M.alloc(&partials, sizeof(double2) * n_tiles));
+  HIP_OK(M.alloc(&partials, sizeof(double) * kChainAcc * n_tiles));
+  double* dacc = nullptr;
+  unsigned* dticket = nullptr;
+  HIP_OK(M.alloc(&dacc, sizeof(double) * kChainAcc));
+  HIP_OK(M.alloc(&dticket, sizeof(unsigned)));
+  HIP_OK(hipMemsetAsync(dticket, 0, sizeof(unsigned), s));
   HIP_OK(M.alloc(&dblocks, sizeof(TBlock) * ns));
-  HIP_OK(M.alloc(&dpass, sizeof(PassDesc) * (ns + 2)));
+  HIP_OK(M.alloc(&dpass, sizeof(UnitPass) * (nu + 2)));
   HIP_OK(M.alloc(&djc, sizeof(JobConst)));
   HIP_OK(M.alloc(&deps, sizeof(double) * std::max(1, tp.n_sites)));
-  HIP_OK(M.alloc(&ddec, sizeof(Decision) * (per_traj + 1)));
+  HIP_OK(M.alloc(&ddec, sizeof(Decision) * (per_units + 1)));
   HIP_OK(M.alloc(&drec, nrec));
   HIP_OK(M.alloc(&dbits, (size_t)job->n_traj * n));
   if (res->p1_trace) HIP_OK(M.alloc(&dp1, sizeof(double) * nrec));
@@ -432,22 +646,18 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   HIP_OK(M.alloc(&derr, sizeof(int)));
   HIP_OK(M.alloc(&drt, rt_per_traj * chunk));
 
-  std::vector<PassDesc> pds(ns + 2);
-  pds[0] = make_pass(n, tb, nullptr, &tp.blocks[0], -1, 0);
-  for (int i = 0; i < ns; ++i)
-    pds[1 + i] = make_pass(n, tb, &tp.blocks[i], &tp.blocks[(i + 1) % ns], i, (i + 1) % ns);
-  pds[ns + 1] = make_pass(n, tb, &tp.blocks[ns - 1], nullptr, ns - 1, -1);
+  const std::vector<UnitPass> pds = make_unit_passes(n, tb, tp, units);
   const JobConst jc = make_job_const(d, job->zeta);
   std::vector<double> eps(std::max(1, tp.n_sites), job->eps);
   if (job->eps_site)
     for (int i = 0; i < tp.n_sites; ++i) eps[i] = job->eps_site[i];
 
   HIP_OK(hipMemcpyAsync(dblocks, tp.blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(PassDesc) * (ns + 2), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(UnitPass) * (nu + 2), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(djc, &jc, sizeof jc, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(deps, eps.data(), sizeof(double) * eps.size(), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
-  HIP_OK(hipMemsetAsync(ddec, 0, sizeof(Decision) * (per_traj + 1), s));
+  HIP_OK(hipMemsetAsync(ddec, 0, sizeof(Decision) * (per_units + 1), s));
 
   // whole-run events plus one pair around every pass of the last trajectory
   struct Events {
@@ -456,18 +666,18 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
   } E;
-  E.ev.resize(2 + 2 * per_traj, nullptr);
+  E.ev.resize(2 + 2 * per_units, nullptr);
   for (auto& e : E.ev) HIP_OK(hipEventCreate(&e));
   hipEvent_t ev0 = E.ev[0], ev1 = E.ev[1];
   hipEvent_t* evs = E.ev.data() + 2;
   HIP_OK(hipEventRecord(ev0, s));
 
-  const int tpw = pass_tiles_per_wg(n_tiles);
   const int snake = pass_snake_order();
-  const size_t n_wg = n_tiles / tpw;
-  const dim3 grid((unsigned)n_wg), block((unsigned)std::max(64, 1 << (tb - 4)));
+  const dim3 grid((unsigned)n_tiles), block((unsigned)std::max(64, 1 << (tb - 4)));
+  const SlotStrides ss0{0, 0, 0};
   const int draws_round = tp.n_draws;
   const int last_t = job->n_traj - 1;
+  std::vector<uint32_t> phi_host(res->final_states ? job->n_traj : 0);
   for (int c0 = 0; c0 < job->n_traj; c0 += chunk) {
     const int cn = std::min(chunk, job->n_traj - c0);
     const int64_t nthreads = (int64_t)cn * per_traj;
@@ -484,32 +694,39 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       const BlockRT* rt = drt + (size_t)ti * per_traj;
       uint8_t* rec = drec + (size_t)tg * per_traj;
       double* p1 = dp1 ? dp1 + (size_t)tg * per_traj : nullptr;
-      auto bmode_of = [&](int blk) { return tp.blocks[blk].type == 0 ? B_XCHECK : B_ZCHECK; };
-      launch_pass<T>(0, tp.blocks[0].w, bmode_of(0), grid, block, s, st, &dpass[0], djc, nullptr,
-                     rt, nullptr, partials, tpw, 0);
-      hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, partials, (int)n_wg, rt, &ddec[0],
-                         rec, p1, SlotStrides{0, 0, 0}, (size_t)0);
+      // block instance of the first member of unit instance ui
+      auto inst = [&](int ui) { return (ui / nu) * ns + units[ui % nu].first; };
+      auto decide = [&](int ui) {
+        const int bi = inst(ui);
+        const int lb = units[ui % nu].len;
+        hipLaunchKernelGGL(k_udecide, dim3((2 << lb) - 2), dim3(256), 0, s, partials, (int)n_tiles,
+                           lb, rt + bi, &ddec[ui], rec + bi, p1 ? p1 + bi : nullptr, ss0, (size_t)0,
+                           dacc, dticket);
+      };
+      SV_OK_OR_RETURN(launch_upass<T>(pds[0], grid, block, s, st, &dpass[0], djc, nullptr,
+                                      rt + inst(0), nullptr, &ddec[0], partials, 0));
+      decide(0);
       const bool timed = (tg == last_t);
-      for (int bi = 0; bi < per_traj; ++bi) {
-        const int sidx = bi % ns;
-        const bool last = (bi == per_traj - 1);
-        const int pidx = last ? ns + 1 : 1 + sidx;
-        const int nb = (sidx + 1) % ns;
-        if (timed) HIP_OK(hipEventRecord(evs[2 * bi], s));
-        launch_pass<T>(tp.blocks[sidx].w, last ? 0 : tp.blocks[nb].w, last ? B_NONE : bmode_of(nb),
-                       grid, block, s, st, &dpass[pidx], djc, rt + bi, last ? nullptr : rt + bi + 1,
-                       &ddec[bi], partials, tpw, snake ? ((bi + 1) & 1) : 0);
-        if (timed) HIP_OK(hipEventRecord(evs[2 * bi + 1], s));
-        if (!last)
-          hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, partials, (int)n_wg,
-                             rt + bi + 1, &ddec[bi + 1], rec + bi + 1, p1 ? p1 + bi + 1 : nullptr,
-                             SlotStrides{0, 0, 0}, (size_t)0);
+      for (int ui = 0; ui < per_units; ++ui) {
+        const int u = ui % nu;
+        const bool last = (ui == per_units - 1);
+        const int pidx = last ? nu + 1 : 1 + u;
+        if (timed) HIP_OK(hipEventRecord(evs[2 * ui], s));
+        SV_OK_OR_RETURN(launch_upass<T>(pds[pidx], grid, block, s, st, &dpass[pidx], djc,
+                                        rt + inst(ui), last ? nullptr : rt + inst(ui + 1),
+                                        &ddec[ui], &ddec[ui + 1], partials,
+                                        snake ? ((ui + 1) & 1) : 0));
+        if (timed) HIP_OK(hipEventRecord(evs[2 * ui + 1], s));
+        if (!last) decide(ui + 1);
       }
       HIP_OK(hipGetLastError());
       if (res->final_states) {
         HIP_OK(hipMemcpyAsync((char*)res->final_states + (size_t)tg * sizeof(T) * 2 * na, st,
                               sizeof(T) * 2 * na, hipMemcpyDeviceToHost, s));
+        Decision fin{};
+        HIP_OK(hipMemcpyAsync(&fin, &ddec[per_units], sizeof fin, hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
+        phi_host[tg] = fin.phi;
       }
       hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb)), dim3(256), 0, s, st, cb, dsums,
                          (size_t)0);
@@ -517,7 +734,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
                          job->seed, job->traj0 + (uint64_t)tg,
                          (uint64_t)R * (uint64_t)draws_round, dbits + (size_t)tg * n, (size_t)0,
                          (const uint64_t*)nullptr, (const uint64_t*)nullptr, (const int*)nullptr,
-                         (uint64_t)0);
+                         (uint64_t)0, (const Decision*)&ddec[per_units], (size_t)0);
       HIP_OK(hipGetLastError());
     }
   }
@@ -526,23 +743,33 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   HIP_OK(hipMemcpyAsync(&herr, derr, sizeof herr, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   if (herr) return fail(SV_EINVAL, "circuit template is not monomial in its block basis");
-  // Records: the decision for block b is written by the pass before it; the
-  // record of the very first block lands at index 0 via the init pass.
   HIP_OK(hipMemcpyAsync(res->records, drec, nrec, hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(res->final_bits, dbits, (size_t)job->n_traj * n, hipMemcpyDeviceToHost, s));
   if (res->p1_trace)
     HIP_OK(hipMemcpyAsync(res->p1_trace, dp1, sizeof(double) * nrec, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
+  // registers handed back in the logical frame: amplitude x sits at x ^ phi
+  if (res->final_states)
+    for (int t = 0; t < job->n_traj; ++t) {
+      const uint32_t phi = phi_host[t];
+      if (!phi) continue;
+      C2<T>* a = reinterpret_cast<C2<T>*>((char*)res->final_states + (size_t)t * sizeof(T) * 2 * na);
+      for (uint64_t x = 0; x < na; ++x) {
+        const uint64_t y = x ^ phi;
+        if (x < y) std::swap(a[x], a[y]);
+      }
+    }
   float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, ev0, ev1));
   double pass_sum = 0.0;
-  for (int bi = 0; bi < per_traj; ++bi) {
+  for (int ui = 0; ui < per_units; ++ui) {
     float pm = 0.f;
-    HIP_OK(hipEventElapsedTime(&pm, evs[2 * bi], evs[2 * bi + 1]));
+    HIP_OK(hipEventElapsedTime(&pm, evs[2 * ui], evs[2 * ui + 1]));
     pass_sum += pm;
   }
   res->gpu_ms = ms;
-  res->pass_ms = pass_sum / per_traj;
+  res->pass_ms = pass_sum / per_units;
+  res->passes_per_round = nu;
   return SV_OK;
 }
 
@@ -726,14 +953,17 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
   const size_t cap = (size_t)std::max(1, env_int("QECSV_LOCKSTEP_MIB", 4096)) << 20;
   const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)nt, cap / per_reg_bytes));
   const int per_traj = in.max_rounds * ns;
+  const std::vector<Unit> units = make_units(tp, zchain_max());
+  const int nu = (int)units.size();
+  const size_t dec_stride = (size_t)in.max_rounds * nu + 1;
   const int n_sites = std::max(1, tp.n_sites);
   hipStream_t s = in.hs;
   DevBufs M(s);
   TBlock* dblocks = nullptr;
-  PassDesc* dpass = nullptr;
+  UnitPass* dpass = nullptr;
   JobConst* djc = nullptr;
   T* st = nullptr;
-  double2* partials = nullptr;
+  double* partials = nullptr;
   Decision* ddec = nullptr;
   BlockRT *rtA = nullptr, *rtB = nullptr;
   uint64_t *dseed = nullptr, *dstream = nullptr;
@@ -741,11 +971,16 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
   int *drounds = nullptr, *derr = nullptr;
   uint8_t *drec = nullptr, *dbits = nullptr;
   HIP_OK(M.alloc(&dblocks, sizeof(TBlock) * ns));
-  HIP_OK(M.alloc(&dpass, sizeof(PassDesc) * (ns + 2)));
+  HIP_OK(M.alloc(&dpass, sizeof(UnitPass) * (nu + 2)));
   HIP_OK(M.alloc(&djc, sizeof(JobConst)));
   HIP_OK(M.alloc(&st, per_reg_bytes * G));
-  HIP_OK(M.alloc(&partials, sizeof(double2) * n_tiles * G));
-  HIP_OK(M.alloc(&ddec, sizeof(Decision) * (size_t)(per_traj + 1) * G));
+  HIP_OK(M.alloc(&partials, sizeof(double) * kChainAcc * n_tiles * G));
+  double* dacc = nullptr;
+  unsigned* dticket = nullptr;
+  HIP_OK(M.alloc(&dacc, sizeof(double) * kChainAcc * G));
+  HIP_OK(M.alloc(&dticket, sizeof(unsigned) * G));
+  HIP_OK(hipMemsetAsync(dticket, 0, sizeof(unsigned) * G, s));
+  HIP_OK(M.alloc(&ddec, sizeof(Decision) * dec_stride * G));
   HIP_OK(M.alloc(&rtA, sizeof(BlockRT) * (size_t)ns * G));
   HIP_OK(M.alloc(&rtB, sizeof(BlockRT) * (size_t)ns * G));
   HIP_OK(M.alloc(&dseed, sizeof(uint64_t) * G));
@@ -760,14 +995,10 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
   HIP_OK(M.alloc(&drec, (size_t)per_traj * G));
   HIP_OK(M.alloc(&dbits, (size_t)n * G));
 
-  std::vector<PassDesc> pds(ns + 2);
-  pds[0] = make_pass(n, tb, nullptr, &tp.blocks[0], -1, 0);
-  for (int i = 0; i < ns; ++i)
-    pds[1 + i] = make_pass(n, tb, &tp.blocks[i], &tp.blocks[(i + 1) % ns], i, (i + 1) % ns);
-  pds[ns + 1] = make_pass(n, tb, &tp.blocks[ns - 1], nullptr, ns - 1, -1);
+  const std::vector<UnitPass> pds = make_unit_passes(n, tb, tp, units);
   const JobConst jc = make_job_const(d, in.zeta);
   HIP_OK(hipMemcpyAsync(dblocks, tp.blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(PassDesc) * (ns + 2), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(UnitPass) * (nu + 2), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(djc, &jc, sizeof jc, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
 
@@ -785,8 +1016,7 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
   HIP_OK(hipEventCreate(&ev.a));
   HIP_OK(hipEventCreate(&ev.b));
   const dim3 block((unsigned)std::max(64, 1 << (tb - 4)));
-  const SlotStrides ss{reg, (size_t)ns, (size_t)per_traj + 1};
-  auto bmode_of = [&](int blk) { return tp.blocks[blk].type == 0 ? B_XCHECK : B_ZCHECK; };
+  const SlotStrides ss{reg, (size_t)ns, dec_stride};
   std::vector<uint64_t> hseed(G), hstream(G);
   std::vector<double> hp(G), heps((size_t)n_sites * G);
   std::vector<int> hrounds(G);
@@ -826,46 +1056,54 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
       hipLaunchKernelGGL(k_prepare_round, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, dblocks,
                          ns, r, tp.n_draws, dseed, dstream, dp, dcs, n_sites, slots, out, derr);
     };
-    auto decide = [&](int slots, const BlockRT* rtb, int bi_b) {
-      hipLaunchKernelGGL(k_decide, dim3(slots), dim3(64), 0, s, partials, (int)n_tiles, rtb,
-                         ddec + bi_b, drec + bi_b, (double*)nullptr, ss, (size_t)per_traj);
+    // outcomes of unit u of round r (tables of that round at rt)
+    auto decide = [&](int slots, const BlockRT* rt, int r, int u) {
+      const int bi = r * ns + units[u].first;
+      const int lb = units[u].len;
+      hipLaunchKernelGGL(k_udecide, dim3((2 << lb) - 2, slots), dim3(64), 0, s, partials, (int)n_tiles,
+                         lb, rt + units[u].first, ddec + (size_t)r * nu + u, drec + bi,
+                         (double*)nullptr, ss, (size_t)per_traj, dacc, dticket);
     };
     prepare(0, rtA, gn);
-    launch_pass<T>(0, tp.blocks[0].w, bmode_of(0), dim3((unsigned)n_tiles, gn), block, s, st, &dpass[0],
-                   djc, nullptr, rtA, nullptr, partials, 1, 0, ss);
-    decide(gn, rtA, 0);
+    SV_OK_OR_RETURN(launch_upass<T>(pds[0], dim3((unsigned)n_tiles, gn), block, s, st, &dpass[0], djc,
+                                    nullptr, rtA + units[0].first, nullptr, ddec, partials, 0, ss));
+    decide(gn, rtA, 0, 0);
     const int R0 = hrounds[0];
     for (int r = 0; r < R0; ++r) {
       const int Ar = active(r), An = active(r + 1);
       BlockRT* rt_cur = (r & 1) ? rtB : rtA;
       BlockRT* rt_nxt = (r & 1) ? rtA : rtB;
       if (An > 0) prepare(r + 1, rt_nxt, An);
-      for (int sidx = 0; sidx < ns; ++sidx) {
-        const int bi = r * ns + sidx;
+      for (int u = 0; u < nu; ++u) {
+        const int ui = r * nu + u;
         const int rev = (++pass_no) & 1;
-        if (sidx < ns - 1) {
-          launch_pass<T>(tp.blocks[sidx].w, tp.blocks[sidx + 1].w, bmode_of(sidx + 1),
-                         dim3((unsigned)n_tiles, Ar), block, s, st, &dpass[1 + sidx], djc,
-                         rt_cur + sidx, rt_cur + sidx + 1, ddec + bi, partials, 1, rev, ss);
-          decide(Ar, rt_cur + sidx + 1, bi + 1);
+        const BlockRT* rta = rt_cur + units[u].first;
+        if (u < nu - 1) {
+          SV_OK_OR_RETURN(launch_upass<T>(pds[1 + u], dim3((unsigned)n_tiles, Ar), block, s, st,
+                                          &dpass[1 + u], djc, rta, rt_cur + units[u + 1].first,
+                                          ddec + ui, ddec + ui + 1, partials, rev, ss));
+          decide(Ar, rt_cur, r, u + 1);
           continue;
         }
         if (An > 0) {
-          launch_pass<T>(tp.blocks[sidx].w, tp.blocks[0].w, bmode_of(0), dim3((unsigned)n_tiles, An),
-                         block, s, st, &dpass[1 + sidx], djc, rt_cur + sidx, rt_nxt, ddec + bi,
-                         partials, 1, rev, ss);
-          decide(An, rt_nxt, bi + 1);
+          SV_OK_OR_RETURN(launch_upass<T>(pds[1 + u], dim3((unsigned)n_tiles, An), block, s, st,
+                                          &dpass[1 + u], djc, rta, rt_nxt + units[0].first,
+                                          ddec + ui, ddec + ui + 1, partials, rev, ss));
+          decide(An, rt_nxt, r + 1, 0);
         }
         if (Ar > An) {  // trajectories ending with this round
           const int cnt = Ar - An;
-          launch_pass<T>(tp.blocks[sidx].w, 0, B_NONE, dim3((unsigned)n_tiles, cnt), block, s,
-                         st + (size_t)An * reg, &dpass[ns + 1], djc, rt_cur + (size_t)An * ns + sidx,
-                         nullptr, ddec + (size_t)An * (per_traj + 1) + bi, partials, 1, rev, ss);
+          Decision* dfin = ddec + (size_t)An * dec_stride + ui + 1;
+          SV_OK_OR_RETURN(launch_upass<T>(pds[nu + 1], dim3((unsigned)n_tiles, cnt), block, s,
+                                          st + (size_t)An * reg, &dpass[nu + 1], djc,
+                                          rta + (size_t)An * ns, nullptr,
+                                          ddec + (size_t)An * dec_stride + ui, dfin, partials, rev, ss));
           hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb), cnt), dim3(256), 0, s,
                              st + (size_t)An * reg, cb, dsums, reg);
           hipLaunchKernelGGL(k_final_measure<T>, dim3(cnt), dim3(1024), 0, s, st + (size_t)An * reg, n,
                              cb, dsums, (uint64_t)0, (uint64_t)0, (uint64_t)0, dbits + (size_t)An * n,
-                             reg, dseed + An, dstream + An, drounds + An, (uint64_t)tp.n_draws);
+                             reg, dseed + An, dstream + An, drounds + An, (uint64_t)tp.n_draws,
+                             (const Decision*)dfin, dec_stride);
         }
       }
       HIP_OK(hipGetLastError());
@@ -1264,6 +1502,7 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
       if (!std::isfinite(job->eps_site[i])) return fail(SV_EINVAL, "non-finite eps_site[%d]", i);
   res->gpu_ms = 0.0;
   res->pass_ms = 0.0;
+  res->passes_per_round = 0;
   if (job->n_traj == 0) return SV_OK;
   if (job->dtype == SV_C128) return run_rounds_t<double>(job, res, tp);
   return run_rounds_t<float>(job, res, tp);

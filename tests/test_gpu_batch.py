@@ -75,3 +75,9 @@ def test_batch_d4_parity(gateset, dtype):
     by one workgroup per trajectory), several tiles per pass."""
     _check(4, gateset, dtype, 24 if dtype == "c128" else 12, seed=17, p_range=(5e-3, 3e-2),
            zeta=0.01)
+
+
+def test_batch_d4_chain_of_two(monkeypatch):
+    """Lockstep d=4 batches with Z chains of at most two checks per pass."""
+    monkeypatch.setenv("QECSV_ZCHAIN", "2")
+    _check(4, "cr", "c128", 8, seed=19, p_range=(1e-2, 4e-2), zeta=0.01)

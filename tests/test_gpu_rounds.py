@@ -123,3 +123,22 @@ def test_d5_bench_config_properties():
     for t in (0, 1):
         assert np.array_equal(a["records"][t, :2], z[f"records_{t}"])
         assert np.max(np.abs(a["p1"][t, :2] - z[f"p1_{t}"])) < 1e-10
+
+
+@pytest.mark.parametrize("chain", [1, 2, 3])
+@pytest.mark.parametrize("d", [3, 4])
+def test_z_chain_lengths_parity(monkeypatch, d, chain):
+    """Passes that apply and decide chains of 1..3 Z checks (QECSV_ZCHAIN)
+    give the oracle's records, p1 and register, with enough noise that most
+    Z checks carry an X-type Pauli (a non-trivial Pauli-X frame)."""
+    monkeypatch.setenv("QECSV_ZCHAIN", str(chain))
+    n_sites = oracle.template_counts(d, oracle.GATESET_CR)[1]
+    eps = workloads.eps_sites(n_sites, (0.0, 0.05), 21)
+    _compare(d, "cr", 2, 3 if d == 4 else 12, seed=21, p=0.04, eps_site=eps, zeta=0.015)
+
+
+def test_high_noise_frames_d4():
+    """p = 0.08: nearly every Z check moves amplitudes (XOR permutations kept
+    as a frame); the register handed back and the final bits are in the
+    logical frame."""
+    _compare(4, "textbook", 2, 3, seed=33, p=0.08, eps=0.02, zeta=0.01)
