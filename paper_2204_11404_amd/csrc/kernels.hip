@@ -649,23 +649,61 @@ __global__ __launch_bounds__(256) void k_upass(
   }
 }
 
-// Outcomes of unit B (a chain of lb checks; lb = 1 for an X check).  Grid
-// (nacc, slots): workgroup a reduces sum a over the per-workgroup partials in
-// a fixed order; the last workgroup of a slot to finish (ticket counter,
-// reset for the next use) decides the members in order, each from the two
-// sums that follow the outcomes already drawn:
-// p1 = S[l][h | 1 << l] / (S[l][h] + S[l][h | 1 << l]), clamped, against
-// member l's measurement draw.
+// Member-by-member outcomes of unit B from its sums S (see k_upass): each
+// member l is decided from the two sums that follow the outcomes already
+// drawn, p1 = S[l][h | 1 << l] / (S[l][h] + S[l][h | 1 << l]), clamped, against
+// its measurement draw.
+__device__ void decide_chain(const volatile double* S, int lb, const BlockRT* rtb, Decision* dec_b,
+                             uint8_t* rec_b, double* p1_b) {
+  int h = 0;
+  double Sm = 0.0;
+  for (int l = 0; l < lb; ++l) {
+    const int off = (2 << l) - 2;
+    const double s0 = S[off + h], s1 = S[off + (h | (1 << l))];
+    const double p1 = clamp_p1(s1 / (s0 + s1));
+    const int m = (rtb[l].u < p1) ? 1 : 0;
+    rec_b[l] = (uint8_t)m;
+    if (p1_b) p1_b[l] = p1;
+    h |= m << l;
+    Sm = m ? s1 : s0;
+  }
+  dec_b->m = h;
+  dec_b->Sm = Sm;
+}
+
+// Outcomes of unit B (a chain of lb checks; lb = 1 for an X check), reducing
+// each sum over the n per-workgroup partials in a fixed order.
+// split = 1, grid (nacc, slots): workgroup a reduces sum a; the last
+// workgroup of a slot to finish (ticket counter, reset for the next use)
+// decides.  split = 0, grid (slots): one workgroup per slot, thread a sums
+// sum a serially (few partials: many small registers side by side).
 __global__ __launch_bounds__(256) void k_udecide(const double* __restrict__ partials, int n,
                                                  int lb, const BlockRT* __restrict__ rtb,
                                                  Decision* __restrict__ dec_b,
                                                  uint8_t* __restrict__ rec_b,
                                                  double* __restrict__ p1_b, SlotStrides ss,
                                                  size_t rec_stride, double* __restrict__ sums,
-                                                 unsigned* __restrict__ tickets) {
-  const int a = blockIdx.x, slot = blockIdx.y;
+                                                 unsigned* __restrict__ tickets, int split) {
   const int nacc = (2 << lb) - 2;
-  partials += ((size_t)slot * kChainAcc + a) * n;
+  const int slot = split ? (int)blockIdx.y : (int)blockIdx.x;
+  partials += (size_t)slot * kChainAcc * n;
+  rtb += (size_t)slot * ss.rt;
+  dec_b += (size_t)slot * ss.dec;
+  rec_b += (size_t)slot * rec_stride;
+  if (p1_b) p1_b += (size_t)slot * rec_stride;
+  if (!split) {
+    __shared__ double S[kChainAcc];
+    if ((int)threadIdx.x < nacc) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s += partials[(size_t)threadIdx.x * n + i];
+      S[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) decide_chain(S, lb, rtb, dec_b, rec_b, p1_b);
+    return;
+  }
+  const int a = blockIdx.x;
+  partials += (size_t)a * n;
   sums += (size_t)slot * kChainAcc;
   __shared__ double red[8];
   __shared__ int last;
@@ -690,25 +728,7 @@ __global__ __launch_bounds__(256) void k_udecide(const double* __restrict__ part
   __syncthreads();
   if (!last || threadIdx.x != 0) return;
   __threadfence();
-  const volatile double* S = sums;
-  rtb += (size_t)slot * ss.rt;
-  dec_b += (size_t)slot * ss.dec;
-  rec_b += (size_t)slot * rec_stride;
-  if (p1_b) p1_b += (size_t)slot * rec_stride;
-  int h = 0;
-  double Sm = 0.0;
-  for (int l = 0; l < lb; ++l) {
-    const int off = (2 << l) - 2;
-    const double s0 = S[off + h], s1 = S[off + (h | (1 << l))];
-    const double p1 = clamp_p1(s1 / (s0 + s1));
-    const int m = (rtb[l].u < p1) ? 1 : 0;
-    rec_b[l] = (uint8_t)m;
-    if (p1_b) p1_b[l] = p1;
-    h |= m << l;
-    Sm = m ? s1 : s0;
-  }
-  dec_b->m = h;
-  dec_b->Sm = Sm;
+  decide_chain(sums, lb, rtb, dec_b, rec_b, p1_b);
   tickets[slot] = 0u;
 }
 

@@ -701,7 +701,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
         const int lb = units[ui % nu].len;
         hipLaunchKernelGGL(k_udecide, dim3((2 << lb) - 2), dim3(256), 0, s, partials, (int)n_tiles,
                            lb, rt + bi, &ddec[ui], rec + bi, p1 ? p1 + bi : nullptr, ss0, (size_t)0,
-                           dacc, dticket);
+                           dacc, dticket, 1);
       };
       SV_OK_OR_RETURN(launch_upass<T>(pds[0], grid, block, s, st, &dpass[0], djc, nullptr,
                                       rt + inst(0), nullptr, &ddec[0], partials, 0));
@@ -1060,9 +1060,9 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
     auto decide = [&](int slots, const BlockRT* rt, int r, int u) {
       const int bi = r * ns + units[u].first;
       const int lb = units[u].len;
-      hipLaunchKernelGGL(k_udecide, dim3((2 << lb) - 2, slots), dim3(64), 0, s, partials, (int)n_tiles,
-                         lb, rt + units[u].first, ddec + (size_t)r * nu + u, drec + bi,
-                         (double*)nullptr, ss, (size_t)per_traj, dacc, dticket);
+      hipLaunchKernelGGL(k_udecide, dim3(slots), dim3(64), 0, s, partials, (int)n_tiles, lb,
+                         rt + units[u].first, ddec + (size_t)r * nu + u, drec + bi, (double*)nullptr,
+                         ss, (size_t)per_traj, dacc, dticket, 0);
     };
     prepare(0, rtA, gn);
     SV_OK_OR_RETURN(launch_upass<T>(pds[0], dim3((unsigned)n_tiles, gn), block, s, st, &dpass[0], djc,
