@@ -195,8 +195,9 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res);
  * per-site over-rotation exponents.  Trajectory i uses draw stream traj0 + i
  * and is the same trajectory sv_run_rounds computes for those parameters
  * (same draw enumeration, same records and final bits).  d = 2 or 3 keep the
- * whole data register in LDS; d = 4 streams it from HBM, one workgroup per
- * trajectory.  Synchronous. */
+ * whole data register in LDS (one persistent launch); d = 4 keeps the
+ * registers in HBM and runs the trajectories in lockstep through the register
+ * passes, the trajectory being a grid dimension.  Synchronous. */
 typedef struct sv_batch_job {
   int d;                    /* 2..4 */
   int gateset;              /* sv_gateset */
