@@ -67,6 +67,12 @@ typedef enum {
  * outcome is decided. */
 #define SV_TAU 1e-10
 
+/* sv_job.flags for sv_run_rounds */
+#define SV_RUN_GRAPH 1 /* capture one trajectory's launch sequence (draws,
+                          passes, decisions, final measurement, record copy)
+                          in a HIP graph once and replay it per trajectory;
+                          results are identical to the stream launches */
+
 typedef struct sv_state_s* sv_state;
 
 /* Thread-local description of the last error on this thread ("" if none). */
@@ -156,7 +162,8 @@ typedef struct sv_job {
   int rounds;          /* noisy rounds, >= 1 */
   int dtype;           /* sv_dtype of the state */
   int n_traj;          /* trajectories */
-  int flags;           /* reserved, must be 0 */
+  int flags;           /* 0 or SV_RUN_GRAPH (sv_run_rounds only; with it,
+                          final_states must be NULL) */
   uint64_t traj0;      /* first trajectory index (draw stream id) */
   uint64_t seed;       /* Philox key */
   double p;            /* depolarizing probability, [0, 1] */

@@ -122,10 +122,13 @@ __device__ __forceinline__ double clamp_p1(double p1) {
 }
 
 // ---------------------------------------------------------------- prepare --
+// Draws and Kraus pairs of every block instance of n_traj trajectories
+// (draw streams traj0 + i, or *stream for a single trajectory when given).
 __global__ void k_prepare(const TBlock* __restrict__ blocks, int n_stab, int rounds,
                           int draws_per_round, uint64_t seed, uint64_t traj0, int n_traj,
                           double p, const double* __restrict__ eps_site,
-                          BlockRT* __restrict__ out, int* __restrict__ err) {
+                          BlockRT* __restrict__ out, int* __restrict__ err,
+                          const uint64_t* __restrict__ stream) {
   const int per_traj = rounds * n_stab;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)per_traj * n_traj) return;
@@ -136,7 +139,8 @@ __global__ void k_prepare(const TBlock* __restrict__ blocks, int n_stab, int rou
   uint8_t pauli[kMaxOps];
   BlockRT rt;
   const uint64_t k0 = (uint64_t)r * (uint64_t)draws_per_round + (uint64_t)b.draw_off;
-  draw_block(b, seed, traj0 + (uint64_t)ti, k0, p, pauli, &rt.u);
+  const uint64_t t = stream ? *stream : traj0 + (uint64_t)ti;
+  draw_block(b, seed, t, k0, p, pauli, &rt.u);
   if (!build_block(b, eps_site, pauli, rt)) atomicOr(err, 1);
   rt.pad = 0;
   out[gid] = rt;
@@ -833,6 +837,25 @@ __global__ __launch_bounds__(1024) void k_final_measure(const T* __restrict__ st
     if (threadIdx.x == 0) bits[n - 1 - level] = (uint8_t)b;
     if (b ^ fq) lo += half;
     size = half;
+  }
+}
+
+// Replayed trajectories: copy the staged records, p1 trace and final bits of
+// trajectory *cur to their slots, then advance *cur and its draw stream.
+__global__ void k_commit(const uint8_t* __restrict__ rec_s, const double* __restrict__ p1_s,
+                         const uint8_t* __restrict__ bits_s, uint8_t* __restrict__ rec,
+                         double* __restrict__ p1, uint8_t* __restrict__ bits, int per_traj, int n,
+                         uint64_t* __restrict__ cur, uint64_t* __restrict__ stream, uint64_t traj0) {
+  const uint64_t c = *cur;
+  for (int i = threadIdx.x; i < per_traj; i += blockDim.x) {
+    rec[c * per_traj + i] = rec_s[i];
+    if (p1) p1[c * per_traj + i] = p1_s[i];
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) bits[c * n + i] = bits_s[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *cur = c + 1;
+    *stream = traj0 + c + 1;
   }
 }
 

@@ -677,68 +677,139 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   const SlotStrides ss0{0, 0, 0};
   const int draws_round = tp.n_draws;
   const int last_t = job->n_traj - 1;
-  std::vector<uint32_t> phi_host(res->final_states ? job->n_traj : 0);
-  for (int c0 = 0; c0 < job->n_traj; c0 += chunk) {
-    const int cn = std::min(chunk, job->n_traj - c0);
-    const int64_t nthreads = (int64_t)cn * per_traj;
-    hipLaunchKernelGGL(k_prepare, dim3((unsigned)((nthreads + 127) / 128)), dim3(128), 0, s, dblocks,
-                       ns, R, draws_round, job->seed, job->traj0 + (uint64_t)c0, cn, job->p, deps,
-                       drt, derr);
+  // block instance of the first member of unit instance ui
+  auto inst = [&](int ui) { return (ui / nu) * ns + units[ui % nu].first; };
+  // passes and decisions of one trajectory whose block tables are at rt
+  auto traj_passes = [&](hipStream_t q, const BlockRT* rt, uint8_t* rec, double* p1,
+                         bool timed) -> sv_status {
+    auto decide = [&](int ui) {
+      const int bi = inst(ui);
+      const int lb = units[ui % nu].len;
+      hipLaunchKernelGGL(k_udecide, dim3((2 << lb) - 2), dim3(256), 0, q, partials, (int)n_tiles, lb,
+                         rt + bi, &ddec[ui], rec + bi, p1 ? p1 + bi : nullptr, ss0, (size_t)0, dacc,
+                         dticket, 1);
+    };
+    SV_OK_OR_RETURN(launch_upass<T>(pds[0], grid, block, q, st, &dpass[0], djc, nullptr, rt + inst(0),
+                                    nullptr, &ddec[0], partials, 0));
+    decide(0);
+    for (int ui = 0; ui < per_units; ++ui) {
+      const int u = ui % nu;
+      const bool last = (ui == per_units - 1);
+      const int pidx = last ? nu + 1 : 1 + u;
+      if (timed) HIP_OK(hipEventRecord(evs[2 * ui], q));
+      SV_OK_OR_RETURN(launch_upass<T>(pds[pidx], grid, block, q, st, &dpass[pidx], djc, rt + inst(ui),
+                                      last ? nullptr : rt + inst(ui + 1), &ddec[ui], &ddec[ui + 1],
+                                      partials, snake ? ((ui + 1) & 1) : 0));
+      if (timed) HIP_OK(hipEventRecord(evs[2 * ui + 1], q));
+      if (!last) decide(ui + 1);
+    }
     HIP_OK(hipGetLastError());
-    for (int ti = 0; ti < cn; ++ti) {
+    return SV_OK;
+  };
+  // final Z measurement of the data register (draw stream t, or *tptr)
+  auto traj_final = [&](hipStream_t q, uint8_t* bits, uint64_t t, const uint64_t* tptr) {
+    hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb)), dim3(256), 0, q, st, cb, dsums,
+                       (size_t)0);
+    hipLaunchKernelGGL(k_final_measure<T>, dim3(1), dim3(1024), 0, q, st, n, cb, dsums, job->seed, t,
+                       (uint64_t)R * (uint64_t)draws_round, bits, (size_t)0, (const uint64_t*)nullptr,
+                       tptr, (const int*)nullptr, (uint64_t)0, (const Decision*)&ddec[per_units],
+                       (size_t)0);
+  };
+  double pass_ms_graph = -1.0;
+  std::vector<uint32_t> phi_host(res->final_states ? job->n_traj : 0);
+  if (job->flags & SV_RUN_GRAPH) {
+    // one trajectory's sequence, staged through fixed buffers and a device
+    // trajectory counter, captured once and replayed n_traj times
+    BlockRT* rt_s = nullptr;
+    uint8_t *rec_s = nullptr, *bits_s = nullptr;
+    double* p1_s = nullptr;
+    uint64_t* dcur = nullptr;  // [0] trajectory counter, [1] its draw stream
+    HIP_OK(M.alloc(&rt_s, rt_per_traj));
+    HIP_OK(M.alloc(&rec_s, (size_t)per_traj));
+    HIP_OK(M.alloc(&bits_s, (size_t)n));
+    if (dp1) HIP_OK(M.alloc(&p1_s, sizeof(double) * per_traj));
+    HIP_OK(M.alloc(&dcur, 2 * sizeof(uint64_t)));
+    const uint64_t cur0[2] = {0, job->traj0};
+    HIP_OK(hipMemcpyAsync(dcur, cur0, sizeof cur0, hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    struct GraphRes {
+      hipStream_t q = nullptr;
+      hipGraph_t g = nullptr;
+      hipGraphExec_t x = nullptr;
+      hipEvent_t a = nullptr, b = nullptr;
+      ~GraphRes() {
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        if (q) (void)hipStreamDestroy(q);
+      }
+    } G;
+    HIP_OK(hipStreamCreateWithFlags(&G.q, hipStreamNonBlocking));
+    HIP_OK(hipEventCreate(&G.a));
+    HIP_OK(hipEventCreate(&G.b));
+    HIP_OK(hipStreamBeginCapture(G.q, hipStreamCaptureModeThreadLocal));
+    sv_status cst = SV_OK;
+    {
+      hipLaunchKernelGGL(k_prepare, dim3((unsigned)((per_traj + 127) / 128)), dim3(128), 0, G.q,
+                         dblocks, ns, R, draws_round, job->seed, job->traj0, 1, job->p, deps, rt_s,
+                         derr, (const uint64_t*)(dcur + 1));
+      cst = traj_passes(G.q, rt_s, rec_s, p1_s, false);
+      if (cst == SV_OK) {
+        traj_final(G.q, bits_s, 0, dcur + 1);
+        hipLaunchKernelGGL(k_commit, dim3(1), dim3(256), 0, G.q, rec_s, p1_s, bits_s, drec, dp1, dbits,
+                           per_traj, n, dcur, dcur + 1, job->traj0);
+      }
+    }
+    const hipError_t ce = hipStreamEndCapture(G.q, &G.g);
+    if (cst != SV_OK) return cst;
+    HIP_OK(ce);
+    HIP_OK(hipGraphInstantiate(&G.x, G.g, nullptr, nullptr, 0));
+    HIP_OK(hipEventRecord(ev0, G.q));
+    for (int t = 0; t < job->n_traj; ++t) {
       if (cancel && cancel->load(std::memory_order_relaxed)) {
-        (void)hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(G.q);
         return fail(SV_EBUSY, "cancelled");
       }
-      const int tg = c0 + ti;
-      const BlockRT* rt = drt + (size_t)ti * per_traj;
-      uint8_t* rec = drec + (size_t)tg * per_traj;
-      double* p1 = dp1 ? dp1 + (size_t)tg * per_traj : nullptr;
-      // block instance of the first member of unit instance ui
-      auto inst = [&](int ui) { return (ui / nu) * ns + units[ui % nu].first; };
-      auto decide = [&](int ui) {
-        const int bi = inst(ui);
-        const int lb = units[ui % nu].len;
-        hipLaunchKernelGGL(k_udecide, dim3((2 << lb) - 2), dim3(256), 0, s, partials, (int)n_tiles,
-                           lb, rt + bi, &ddec[ui], rec + bi, p1 ? p1 + bi : nullptr, ss0, (size_t)0,
-                           dacc, dticket, 1);
-      };
-      SV_OK_OR_RETURN(launch_upass<T>(pds[0], grid, block, s, st, &dpass[0], djc, nullptr,
-                                      rt + inst(0), nullptr, &ddec[0], partials, 0));
-      decide(0);
-      const bool timed = (tg == last_t);
-      for (int ui = 0; ui < per_units; ++ui) {
-        const int u = ui % nu;
-        const bool last = (ui == per_units - 1);
-        const int pidx = last ? nu + 1 : 1 + u;
-        if (timed) HIP_OK(hipEventRecord(evs[2 * ui], s));
-        SV_OK_OR_RETURN(launch_upass<T>(pds[pidx], grid, block, s, st, &dpass[pidx], djc,
-                                        rt + inst(ui), last ? nullptr : rt + inst(ui + 1),
-                                        &ddec[ui], &ddec[ui + 1], partials,
-                                        snake ? ((ui + 1) & 1) : 0));
-        if (timed) HIP_OK(hipEventRecord(evs[2 * ui + 1], s));
-        if (!last) decide(ui + 1);
-      }
-      HIP_OK(hipGetLastError());
-      if (res->final_states) {
-        HIP_OK(hipMemcpyAsync((char*)res->final_states + (size_t)tg * sizeof(T) * 2 * na, st,
-                              sizeof(T) * 2 * na, hipMemcpyDeviceToHost, s));
-        Decision fin{};
-        HIP_OK(hipMemcpyAsync(&fin, &ddec[per_units], sizeof fin, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-        phi_host[tg] = fin.phi;
-      }
-      hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb)), dim3(256), 0, s, st, cb, dsums,
-                         (size_t)0);
-      hipLaunchKernelGGL(k_final_measure<T>, dim3(1), dim3(1024), 0, s, st, n, cb, dsums,
-                         job->seed, job->traj0 + (uint64_t)tg,
-                         (uint64_t)R * (uint64_t)draws_round, dbits + (size_t)tg * n, (size_t)0,
-                         (const uint64_t*)nullptr, (const uint64_t*)nullptr, (const int*)nullptr,
-                         (uint64_t)0, (const Decision*)&ddec[per_units], (size_t)0);
-      HIP_OK(hipGetLastError());
+      if (t == last_t) HIP_OK(hipEventRecord(G.a, G.q));
+      HIP_OK(hipGraphLaunch(G.x, G.q));
+      if (t == last_t) HIP_OK(hipEventRecord(G.b, G.q));
     }
+    HIP_OK(hipEventRecord(ev1, G.q));
+    HIP_OK(hipStreamSynchronize(G.q));
+    float tm = 0.f;
+    HIP_OK(hipEventElapsedTime(&tm, G.a, G.b));
+    pass_ms_graph = tm / (per_units + 1);
+  } else {
+    for (int c0 = 0; c0 < job->n_traj; c0 += chunk) {
+      const int cn = std::min(chunk, job->n_traj - c0);
+      const int64_t nthreads = (int64_t)cn * per_traj;
+      hipLaunchKernelGGL(k_prepare, dim3((unsigned)((nthreads + 127) / 128)), dim3(128), 0, s, dblocks,
+                         ns, R, draws_round, job->seed, job->traj0 + (uint64_t)c0, cn, job->p, deps,
+                         drt, derr, (const uint64_t*)nullptr);
+      HIP_OK(hipGetLastError());
+      for (int ti = 0; ti < cn; ++ti) {
+        if (cancel && cancel->load(std::memory_order_relaxed)) {
+          (void)hipStreamSynchronize(s);
+          return fail(SV_EBUSY, "cancelled");
+        }
+        const int tg = c0 + ti;
+        SV_OK_OR_RETURN(traj_passes(s, drt + (size_t)ti * per_traj, drec + (size_t)tg * per_traj,
+                                    dp1 ? dp1 + (size_t)tg * per_traj : nullptr, tg == last_t));
+        if (res->final_states) {
+          HIP_OK(hipMemcpyAsync((char*)res->final_states + (size_t)tg * sizeof(T) * 2 * na, st,
+                                sizeof(T) * 2 * na, hipMemcpyDeviceToHost, s));
+          Decision fin{};
+          HIP_OK(hipMemcpyAsync(&fin, &ddec[per_units], sizeof fin, hipMemcpyDeviceToHost, s));
+          HIP_OK(hipStreamSynchronize(s));
+          phi_host[tg] = fin.phi;
+        }
+        traj_final(s, dbits + (size_t)tg * n, job->traj0 + (uint64_t)tg, nullptr);
+        HIP_OK(hipGetLastError());
+      }
+    }
+    HIP_OK(hipEventRecord(ev1, s));
   }
-  HIP_OK(hipEventRecord(ev1, s));
   int herr = 0;
   HIP_OK(hipMemcpyAsync(&herr, derr, sizeof herr, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
@@ -762,13 +833,17 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, ev0, ev1));
   double pass_sum = 0.0;
-  for (int ui = 0; ui < per_units; ++ui) {
-    float pm = 0.f;
-    HIP_OK(hipEventElapsedTime(&pm, evs[2 * ui], evs[2 * ui + 1]));
-    pass_sum += pm;
+  if (pass_ms_graph < 0.0) {
+    for (int ui = 0; ui < per_units; ++ui) {
+      float pm = 0.f;
+      HIP_OK(hipEventElapsedTime(&pm, evs[2 * ui], evs[2 * ui + 1]));
+      pass_sum += pm;
+    }
   }
   res->gpu_ms = ms;
-  res->pass_ms = pass_sum / per_units;
+  // replayed graphs: the last trajectory's device time per pass (an upper
+  // bound that includes its decisions, draws and final measurement)
+  res->pass_ms = pass_ms_graph >= 0.0 ? pass_ms_graph : pass_sum / per_units;
   res->passes_per_round = nu;
   return SV_OK;
 }
@@ -1492,10 +1567,12 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
   if (job->rounds < 1 || job->rounds > 100000) return fail(SV_EINVAL, "rounds=%d", job->rounds);
   if (job->dtype != SV_C64 && job->dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
   if (job->n_traj < 0) return fail(SV_EINVAL, "n_traj < 0");
-  if (job->flags != 0) return fail(SV_EINVAL, "flags must be 0");
+  if (job->flags & ~SV_RUN_GRAPH) return fail(SV_EINVAL, "unknown flags 0x%x", job->flags);
   if (!(job->p >= 0.0 && job->p <= 1.0)) return fail(SV_EINVAL, "p out of [0, 1]");
   if (!std::isfinite(job->eps) || !std::isfinite(job->zeta)) return fail(SV_EINVAL, "non-finite eps/zeta");
   if (!res->records || !res->final_bits) return fail(SV_EINVAL, "records and final_bits are required");
+  if ((job->flags & SV_RUN_GRAPH) && res->final_states)
+    return fail(SV_EINVAL, "final_states cannot be returned with SV_RUN_GRAPH");
   const Template tp = build_template(job->d, job->gateset);
   if (job->eps_site)
     for (int i = 0; i < tp.n_sites; ++i)

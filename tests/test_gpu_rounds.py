@@ -142,3 +142,28 @@ def test_high_noise_frames_d4():
     as a frame); the register handed back and the final bits are in the
     logical frame."""
     _compare(4, "textbook", 2, 3, seed=33, p=0.08, eps=0.02, zeta=0.01)
+
+
+@pytest.mark.parametrize("d,dtype", [(3, "c128"), (4, "c64"), (5, "c128")])
+def test_graph_replay_matches_stream_launches(d, dtype):
+    """SV_RUN_GRAPH (one trajectory's launch sequence captured once, replayed
+    per trajectory with a device-side trajectory counter) gives the records,
+    p1 and final bits of the stream launches, for every replay; an eager run
+    sits between two graph runs."""
+    n_sites = oracle.template_counts(d, oracle.GATESET_CR)[1]
+    eps = workloads.eps_sites(n_sites, (0.0, 0.05), 8)
+    n = {3: 24, 4: 6, 5: 2}[d]
+    kw = dict(d=d, gateset="cr", rounds=2, n_traj=n, seed=8, p=0.01 if d < 5 else 2e-3,
+              eps_site=eps, zeta=0.01, dtype=dtype, traj0=3, want_p1=True)
+    g1 = qs.run_rounds(graph=True, **kw)
+    e = qs.run_rounds(**kw)
+    g2 = qs.run_rounds(graph=True, **kw)
+    for g in (g1, g2):
+        assert np.array_equal(g["records"], e["records"])
+        assert np.array_equal(g["final_bits"], e["final_bits"])
+        assert np.array_equal(g["p1"], e["p1"])
+
+
+def test_graph_rejects_final_states():
+    with pytest.raises(qs.SvError):
+        qs.run_rounds(3, "cr", 1, 1, 0, 0.01, graph=True, want_states=True)
