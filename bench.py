@@ -130,13 +130,14 @@ def batch_run(qs, d, n_traj, dtype, seed=7):
     import workloads
     n_stab, n_sites, _ = qs.template_info(d, "cr")
     R, p, eps = workloads.batch_params(n_traj, n_sites, seed)
+    tuning, _ = qs.autotune(d, dtype)          # untimed: launch parameters for this shape
     qs.run_batch(d, "cr", R[:256], p[:256], seed, eps_site=eps[:256], dtype=dtype)
     g = qs.run_batch(d, "cr", R, p, seed, eps_site=eps, dtype=dtype, max_rounds=9)
     amp = 8 if dtype == "c64" else 16
     alg = (int(R.sum()) * n_stab + n_traj) * 2 * (1 << (d * d)) * amp
     return {"d": d, "trajectories": n_traj, "dtype": dtype, "launch_ms": g["gpu_ms"],
             "trajectories_per_s": n_traj / (g["gpu_ms"] * 1e-3),
-            "alg_gbs": alg / (g["gpu_ms"] * 1e-3) / 1e9}
+            "alg_gbs": alg / (g["gpu_ms"] * 1e-3) / 1e9, "tuning": tuning}
 
 
 def precision_run(qs, n_traj, thetas=(0.01, 0.03, 0.05)):
@@ -217,6 +218,7 @@ def main():
     kw = dict(d=d, gateset="cr", rounds=R, seed=c["seed"], p=c["p"], eps_site=eps,
               zeta=c["zeta"], dtype=args.dtype)
 
+    tuning, _ = qs.autotune(d, args.dtype)   # untimed: launch parameters for this shape
     if args.warmup > 0:
         qs.run_rounds(n_traj=args.warmup, traj0=1_000_000, **kw)
     torch.cuda.synchronize()
@@ -252,6 +254,7 @@ def main():
         # per-circuit byte model (one read + write of the register per
         # stabilizer circuit); exceeds the bytes moved when passes apply chains
         "hbm_gbs_algorithmic": alg_gbs,
+        "tuning": tuning,
         "gpu_ms_device": r["gpu_ms"],
         "trajectories_per_s": args.steps / wall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",

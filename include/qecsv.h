@@ -197,6 +197,37 @@ typedef struct sv_result {
  * final data measurement.  Synchronous.  Records are the raw ancilla bits. */
 sv_status sv_run_rounds(const sv_job* job, sv_result* res);
 
+/* Launch parameters of the trajectory engine for (d, dtype) on the current
+ * device.  They change speed only: results agree up to the order of
+ * floating-point sums.  The environment variables QECSV_ZCHAIN, QECSV_SNAKE,
+ * QECSV_BATCH_WAVES_PER_CU and QECSV_LOCKSTEP_MIB override them. */
+typedef struct sv_tuning {
+  int zchain;             /* longest chain of Z checks applied per register pass, 1..4 */
+  int snake;              /* 1: consecutive passes walk the tiles in opposite orders */
+  int batch_waves_per_cu; /* sv_run_batch, d <= 3: resident waves per compute unit, 1..32 */
+  int lockstep_mib;       /* sv_run_batch, d = 4: MiB of registers run in lockstep */
+} sv_tuning;
+
+/* Effective parameters (set, tuned or built-in, then the environment). */
+sv_status sv_tuning_get(int d, int dtype, sv_tuning* out);
+/* Replace the parameters for (d, dtype) on the current device; SV_EINVAL if
+ * a field is out of range. */
+sv_status sv_tuning_set(int d, int dtype, const sv_tuning* in);
+/* Time candidate parameters on synthetic work of this shape (tens of ms of
+ * device time) and keep the fastest for (d, dtype) on the current device:
+ * d = 5, sv_run_rounds (one trajectory, one round): zchain x snake;
+ * d = 4, sv_run_batch (512 trajectories, 3 rounds): zchain x lockstep_mib;
+ * d <= 3, sv_run_batch (16384 trajectories, 3 rounds): batch_waves_per_cu.
+ * Writes the winner to *best and its device time to *best_ms (either may be
+ * NULL).  Synchronous, on the default stream; call it before serving, not
+ * while other threads run jobs of the same shape. */
+sv_status sv_autotune(int d, int dtype, int gateset, sv_tuning* best, double* best_ms);
+/* Write / read the parameters of the current device's architecture as text
+ * lines "arch d dtype zchain snake batch_waves_per_cu lockstep_mib"; load
+ * keeps only lines for this architecture.  SV_EINVAL on I/O or parse errors. */
+sv_status sv_tuning_save(const char* path);
+sv_status sv_tuning_load(const char* path);
+
 /* Batched small-distance trajectories: one persistent launch runs n_traj
  * trajectories, each with its own round count, depolarizing probability and
  * per-site over-rotation exponents.  Trajectory i uses draw stream traj0 + i

@@ -66,6 +66,11 @@ class BatchResult(ctypes.Structure):
     ]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("zchain", ctypes.c_int), ("snake", ctypes.c_int),
+                ("batch_waves_per_cu", ctypes.c_int), ("lockstep_mib", ctypes.c_int)]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("big_streams", ctypes.c_int),
                 ("max_batch_traj", ctypes.c_int), ("flags", ctypes.c_int)]
@@ -122,6 +127,12 @@ _SIGS = {
     "sv_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
     "sv_server_clock": (ctypes.c_double, [ctypes.c_void_p]),
     "sv_server_destroy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "sv_tuning_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "sv_tuning_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "sv_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_double)]),
+    "sv_tuning_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "sv_tuning_load": (ctypes.c_int, [ctypes.c_char_p]),
     "sv_uniform": (ctypes.c_double, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]),
     "sv_block_kraus": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
@@ -430,3 +441,38 @@ class Server:
             self.close(cancel=True)
         except Exception:
             pass
+
+
+def _tuning_dict(t):
+    return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+
+def tuning_get(d, dtype):
+    """sv_tuning_get: effective launch parameters for (d, dtype)."""
+    t = Tuning()
+    _check(lib().sv_tuning_get(d, _DTYPES[dtype], ctypes.byref(t)))
+    return _tuning_dict(t)
+
+
+def tuning_set(d, dtype, **kw):
+    """sv_tuning_set: replace fields of the current parameters for (d, dtype)."""
+    cur = tuning_get(d, dtype)
+    cur.update(kw)
+    t = Tuning(**cur)
+    _check(lib().sv_tuning_set(d, _DTYPES[dtype], ctypes.byref(t)))
+
+
+def autotune(d, dtype, gateset="cr"):
+    """sv_autotune: time candidate launch parameters and keep the fastest;
+    returns (parameters, device ms of the winning trial)."""
+    t, ms = Tuning(), ctypes.c_double()
+    _check(lib().sv_autotune(d, _DTYPES[dtype], _GATESETS[gateset], ctypes.byref(t), ctypes.byref(ms)))
+    return _tuning_dict(t), ms.value
+
+
+def tuning_save(path):
+    _check(lib().sv_tuning_save(os.fsencode(path)))
+
+
+def tuning_load(path):
+    _check(lib().sv_tuning_load(os.fsencode(path)))

@@ -297,11 +297,58 @@ struct Unit {
   int len;    // members (1 for an X check)
 };
 
-// Longest Z chain per pass: QECSV_ZCHAIN (1..kChainMax), default kChainMax.
-int zchain_max() {
-  int L = kChainMax;
-  if (const char* e = std::getenv("QECSV_ZCHAIN")) L = std::atoi(e);
-  return std::max(1, std::min(kChainMax, L));
+// ---------------------------------------------------------------- tuning --
+// Launch parameters per (device, d, dtype): built-in defaults, replaced by
+// values set with sv_tuning_set or found by sv_autotune, in turn overridden by
+// the QECSV_* environment variables.  None of them changes what is computed
+// beyond the order of floating-point sums.
+struct TuneKey {
+  int dev, d, dtype;
+  bool operator<(const TuneKey& o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (d != o.d) return d < o.d;
+    return dtype < o.dtype;
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, sv_tuning> g_tune;
+
+sv_tuning default_tuning() {
+  sv_tuning t{};
+  t.zchain = kChainMax;
+  t.snake = 1;
+  t.batch_waves_per_cu = 8;
+  t.lockstep_mib = 4096;
+  return t;
+}
+
+int current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  return dev;
+}
+
+sv_status check_tuning(const sv_tuning& t) {
+  if (t.zchain < 1 || t.zchain > kChainMax) return fail(SV_EINVAL, "zchain %d out of 1..%d", t.zchain, kChainMax);
+  if (t.snake != 0 && t.snake != 1) return fail(SV_EINVAL, "snake must be 0 or 1");
+  if (t.batch_waves_per_cu < 1 || t.batch_waves_per_cu > 32)
+    return fail(SV_EINVAL, "batch_waves_per_cu %d out of 1..32", t.batch_waves_per_cu);
+  if (t.lockstep_mib < 1 || t.lockstep_mib > (1 << 20)) return fail(SV_EINVAL, "lockstep_mib out of range");
+  return SV_OK;
+}
+
+sv_tuning tuning_for(int d, int dtype) {
+  sv_tuning t = default_tuning();
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_tune.find(TuneKey{current_device(), d, dtype});
+    if (it != g_tune.end()) t = it->second;
+  }
+  if (const char* e = std::getenv("QECSV_ZCHAIN")) t.zchain = std::max(1, std::min(kChainMax, std::atoi(e)));
+  if (const char* e = std::getenv("QECSV_SNAKE")) t.snake = std::atoi(e) != 0;
+  if (const char* e = std::getenv("QECSV_BATCH_WAVES_PER_CU")) t.batch_waves_per_cu = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("QECSV_LOCKSTEP_MIB")) t.lockstep_mib = std::max(1, std::atoi(e));
+  return t;
 }
 
 // Units of one round: every X check alone, runs of consecutive Z checks cut
@@ -545,14 +592,6 @@ PassDesc make_pass(int n, int tb_max, const TBlock* A, const TBlock* B, int ia, 
   return pd;
 }
 
-// Alternate the tile traversal direction between consecutive passes so that a
-// pass starts on the lines its predecessor wrote last (QECSV_SNAKE=0 turns it
-// off).
-int pass_snake_order() {
-  if (const char* e = std::getenv("QECSV_SNAKE")) return std::atoi(e) != 0;
-  return 1;
-}
-
 // Launches the pass kernel instantiated for the descriptor's unit kinds.
 template <typename T>
 sv_status launch_upass(const UnitPass& h, dim3 g, dim3 b, hipStream_t s, T* st, const UnitPass* pd,
@@ -602,7 +641,8 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   const int d = job->d, n = d * d, ns = (int)tp.blocks.size(), R = job->rounds;
   const int tb = std::min(kTileMax, n);
   const int per_traj = R * ns;  // block instances (records) per trajectory
-  const std::vector<Unit> units = make_units(tp, zchain_max());
+  const sv_tuning tune = tuning_for(d, job->dtype);
+  const std::vector<Unit> units = make_units(tp, tune.zchain);
   const int nu = (int)units.size();
   const int per_units = R * nu;  // passes per trajectory after the first
   hipStream_t s = (hipStream_t)job->hip_stream;
@@ -672,7 +712,9 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   hipEvent_t* evs = E.ev.data() + 2;
   HIP_OK(hipEventRecord(ev0, s));
 
-  const int snake = pass_snake_order();
+  // alternate the tile traversal between consecutive passes: a pass starts on
+  // the lines its predecessor wrote last
+  const int snake = tune.snake;
   const dim3 grid((unsigned)n_tiles), block((unsigned)std::max(64, 1 << (tb - 4)));
   const SlotStrides ss0{0, 0, 0};
   const int draws_round = tp.n_draws;
@@ -971,7 +1013,7 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   HIP_OK(hipEventCreate(&ev.a));
   HIP_OK(hipEventCreate(&ev.b));
   if (small) {
-    const int per_cu = std::max(1, env_int("QECSV_BATCH_WAVES_PER_CU", 8));
+    const int per_cu = tuning_for(in.d, sizeof(T) == 8 ? SV_C128 : SV_C64).batch_waves_per_cu;
     const int max_wg = device_cu_count() * per_cu;
     const int grid = std::max(1, std::min((nt + 1) / 2, max_wg));
     HIP_OK(hipEventRecord(ev.a, s));
@@ -1025,10 +1067,11 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
   const int cb = std::min(12, n);
   const size_t reg = (size_t)2 << n;  // T elements per register
   const size_t per_reg_bytes = reg * sizeof(T);
-  const size_t cap = (size_t)std::max(1, env_int("QECSV_LOCKSTEP_MIB", 4096)) << 20;
+  const sv_tuning tune = tuning_for(d, sizeof(T) == 8 ? SV_C128 : SV_C64);
+  const size_t cap = (size_t)tune.lockstep_mib << 20;
   const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)nt, cap / per_reg_bytes));
   const int per_traj = in.max_rounds * ns;
-  const std::vector<Unit> units = make_units(tp, zchain_max());
+  const std::vector<Unit> units = make_units(tp, tune.zchain);
   const int nu = (int)units.size();
   const size_t dec_stride = (size_t)in.max_rounds * nu + 1;
   const int n_sites = std::max(1, tp.n_sites);
@@ -1210,9 +1253,17 @@ size_t batch_footprint(int d, int dtype, int n_traj, int max_rounds, int n_sites
   const size_t elem = dtype == SV_C128 ? 16 : 8;
   size_t b = (size_t)n_traj * ((size_t)max_rounds * (n + 1) + n + 40 + 8 * (size_t)n_sites);
   if (n > kSmallBits) {
-    const int per_cu = std::max(1, env_int("QECSV_TILED_WG_PER_CU", 2));
-    const size_t grid = std::min<size_t>((size_t)n_traj, (size_t)device_cu_count() * per_cu);
-    b += (grid << n) * elem;
+    if (env_int("QECSV_D4_PERSISTENT", 0)) {  // one register per resident workgroup
+      const int per_cu = std::max(1, env_int("QECSV_TILED_WG_PER_CU", 2));
+      const size_t grid = std::min<size_t>((size_t)n_traj, (size_t)device_cu_count() * per_cu);
+      b += (grid << n) * elem;
+    } else {  // lockstep: G registers with their partial sums and decisions
+      const size_t reg = elem << n;
+      const size_t cap = (size_t)tuning_for(d, dtype).lockstep_mib << 20;
+      const size_t G = std::max<size_t>(1, std::min<size_t>((size_t)n_traj, cap / reg));
+      const size_t n_tiles = (size_t)1 << (n - std::min(kTileMax, n));
+      b += G * (reg + sizeof(double) * kChainAcc * n_tiles + sizeof(Decision) * (size_t)max_rounds * n);
+    }
   }
   return b + (1 << 20);
 }
@@ -1619,6 +1670,176 @@ sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res) {
   const sv_status st = job->dtype == SV_C128 ? run_batch_core<double>(in, tp) : run_batch_core<float>(in, tp);
   res->gpu_ms = in.gpu_ms;
   return st;
+}
+
+sv_status sv_tuning_get(int d, int dtype, sv_tuning* out) {
+  if (!out) return fail(SV_EINVAL, "NULL output");
+  if (d < 2 || d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", d);
+  if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
+  *out = tuning_for(d, dtype);
+  return SV_OK;
+}
+
+sv_status sv_tuning_set(int d, int dtype, const sv_tuning* in) {
+  if (!in) return fail(SV_EINVAL, "NULL tuning");
+  if (d < 2 || d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", d);
+  if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
+  SV_OK_OR_RETURN(check_tuning(*in));
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[TuneKey{current_device(), d, dtype}] = *in;
+  return SV_OK;
+}
+
+sv_status sv_autotune(int d, int dtype, int gateset, sv_tuning* best, double* best_ms) {
+  if (d < 2 || d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", d);
+  if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
+  if (gateset != SV_GATESET_CR && gateset != SV_GATESET_TEXTBOOK) return fail(SV_EINVAL, "bad gateset");
+  const Template tp = build_template(d, gateset);
+  const TuneKey key{current_device(), d, dtype};
+  sv_tuning base = default_tuning();
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_tune.find(key);
+    if (it != g_tune.end()) base = it->second;
+  }
+  std::vector<sv_tuning> cands;
+  if (d == 5) {
+    for (int z = 2; z <= kChainMax; ++z)
+      for (int sn = 0; sn <= 1; ++sn) {
+        sv_tuning c = base;
+        c.zchain = z;
+        c.snake = sn;
+        cands.push_back(c);
+      }
+  } else if (d == 4) {
+    for (int z = 2; z <= kChainMax; ++z)
+      for (int mib : {256, 1024, 4096}) {
+        sv_tuning c = base;
+        c.zchain = z;
+        c.lockstep_mib = mib;
+        cands.push_back(c);
+      }
+  } else {
+    for (int w : {2, 4, 8, 12, 16}) {
+      sv_tuning c = base;
+      c.batch_waves_per_cu = w;
+      cands.push_back(c);
+    }
+  }
+  // synthetic trials of the tuned shape
+  const int n = d * d, ns = (int)tp.blocks.size();
+  const int nt = d == 5 ? 1 : (d == 4 ? 512 : 16384);
+  const int R = d == 5 ? 1 : 3;
+  std::vector<uint8_t> rec((size_t)nt * R * ns), bits((size_t)nt * n);
+  std::vector<int> rounds(nt, R);
+  std::vector<double> pv(nt, 2e-3), eps(std::max(1, tp.n_sites), 0.0125);
+  std::vector<uint64_t> seeds(nt, 0x7E57), streams(nt);
+  for (int i = 0; i < nt; ++i) streams[i] = (uint64_t)i;
+  auto trial = [&](const sv_tuning& c, double* ms) -> sv_status {
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key] = c;
+    }
+    if (d == 5) {
+      sv_job job{};
+      job.d = d;
+      job.gateset = gateset;
+      job.rounds = R;
+      job.dtype = dtype;
+      job.n_traj = nt;
+      job.seed = 0x7E57;
+      job.p = 2e-3;
+      job.eps = 0.0125;
+      job.zeta = 0.01;
+      sv_result res{};
+      res.records = rec.data();
+      res.final_bits = bits.data();
+      SV_OK_OR_RETURN(dtype == SV_C128 ? run_rounds_t<double>(&job, &res, tp)
+                                       : run_rounds_t<float>(&job, &res, tp));
+      *ms = res.gpu_ms;
+    } else {
+      BatchInputs in{d, gateset, nt, R, 0.0, seeds.data(), streams.data(), rounds.data(), pv.data(),
+                     eps.data(), 0, rec.data(), bits.data(), (hipStream_t)nullptr, 0.0};
+      SV_OK_OR_RETURN(dtype == SV_C128 ? run_batch_core<double>(in, tp) : run_batch_core<float>(in, tp));
+      *ms = in.gpu_ms;
+    }
+    return SV_OK;
+  };
+  double warm = 0.0;
+  sv_status st = trial(base, &warm);
+  int win = -1;
+  double win_ms = 0.0;
+  for (size_t i = 0; i < cands.size() && st == SV_OK; ++i) {
+    double a = 0.0, b = 0.0;
+    st = trial(cands[i], &a);
+    if (st == SV_OK) st = trial(cands[i], &b);
+    const double t = std::min(a, b);
+    if (st == SV_OK && (win < 0 || t < win_ms)) {
+      win = (int)i;
+      win_ms = t;
+    }
+  }
+  const sv_tuning chosen = (st == SV_OK && win >= 0) ? cands[win] : base;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = chosen;
+  }
+  if (st != SV_OK) return st;
+  if (best) *best = chosen;
+  if (best_ms) *best_ms = win_ms;
+  return SV_OK;
+}
+
+static std::string device_arch() {
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, current_device()) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+sv_status sv_tuning_save(const char* path) {
+  if (!path) return fail(SV_EINVAL, "NULL path");
+  const std::string arch = device_arch();
+  const int dev = current_device();
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(SV_EINVAL, "cannot write %s", path);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune)
+      if (kv.first.dev == dev)
+        std::fprintf(f, "%s %d %d %d %d %d %d\n", arch.c_str(), kv.first.d, kv.first.dtype, kv.second.zchain,
+                     kv.second.snake, kv.second.batch_waves_per_cu, kv.second.lockstep_mib);
+  }
+  return std::fclose(f) == 0 ? SV_OK : fail(SV_EINVAL, "cannot write %s", path);
+}
+
+sv_status sv_tuning_load(const char* path) {
+  if (!path) return fail(SV_EINVAL, "NULL path");
+  const std::string arch = device_arch();
+  const int dev = current_device();
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(SV_EINVAL, "cannot read %s", path);
+  char a[128];
+  int d, dt;
+  sv_tuning t{};
+  std::vector<std::pair<TuneKey, sv_tuning>> got;
+  int k;
+  while ((k = std::fscanf(f, "%127s %d %d %d %d %d %d", a, &d, &dt, &t.zchain, &t.snake,
+                          &t.batch_waves_per_cu, &t.lockstep_mib)) == 7) {
+    if (arch != a) continue;
+    if (d < 2 || d > 5 || (dt != SV_C64 && dt != SV_C128) || check_tuning(t) != SV_OK) {
+      std::fclose(f);
+      return fail(SV_EINVAL, "bad tuning line in %s", path);
+    }
+    got.push_back({TuneKey{dev, d, dt}, t});
+  }
+  const bool eof = std::feof(f) != 0;
+  std::fclose(f);
+  if (!eof || k != EOF) return fail(SV_EINVAL, "cannot parse %s", path);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : got) g_tune[kv.first] = kv.second;
+  return SV_OK;
 }
 
 }  // extern "C"
