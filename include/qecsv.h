@@ -197,6 +197,23 @@ typedef struct sv_result {
  * final data measurement.  Synchronous.  Records are the raw ancilla bits. */
 sv_status sv_run_rounds(const sv_job* job, sv_result* res);
 
+/* Decoding of the Z-basis memory experiment (Sec. III.B; host only).
+ * Detection events: Z-check syndromes (raw record XOR its trivial bit, which
+ * is (w/2) mod 2 for a weight-w check of the cross-resonance circuit and 0
+ * for the textbook circuit) compared between consecutive rounds, plus a last
+ * layer recomputed from the final data bits.  They are paired by an exact
+ * minimum-weight perfect matching on the unit-weight space-time graph with one
+ * boundary node (dynamic programming over subsets, at most 22 events per
+ * trajectory).  records: host [n_traj][rounds][d^2-1] raw bits as written by
+ * sv_run_rounds; final_bits: host [n_traj][d^2].  Outputs (host, n_traj
+ * entries): failed = 1 if the corrected Z_L = Z_1...Z_d reads -1, else 0 (2
+ * if the trajectory has too many events); ambiguous (optional) = 1 if
+ * minimum-weight corrections of both logical parities exist; weight
+ * (optional) = the matching's total weight (-1 if undecoded).  SV_ENUMERIC if
+ * any trajectory has more than 22 events (the others are still decoded). */
+sv_status sv_decode_z(int d, int gateset, int rounds, int n_traj, const uint8_t* records,
+                      const uint8_t* final_bits, uint8_t* failed, uint8_t* ambiguous, int* weight);
+
 /* Launch parameters of the trajectory engine for (d, dtype) on the current
  * device.  They change speed only: results agree up to the order of
  * floating-point sums.  The environment variables QECSV_ZCHAIN, QECSV_SNAKE,

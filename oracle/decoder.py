@@ -75,9 +75,14 @@ class ZDecoder:
 
     def correction(self, det):
         """Parity of the matched recovery on the logical Z support."""
+        return self.matching(det)[0]
+
+    def matching(self, det):
+        """(parity of the matched recovery on Z_L, total path length of the
+        matching)."""
         ev = [(k, r) for k, r in zip(*np.nonzero(det))]
         if not ev:
-            return 0
+            return 0, 0
         g = nx.Graph()
         big = 10 * (len(ev) + 1) * (self.d + self.R + 2)
         for a, b in itertools.combinations(range(len(ev)), 2):
@@ -87,7 +92,7 @@ class ZDecoder:
         for a, b in itertools.combinations(range(len(ev)), 2):
             g.add_edge(("b", a), ("b", b), weight=big)
         m = nx.max_weight_matching(g, maxcardinality=True)
-        p = 0
+        p, w = 0, 0
         for u, v in m:
             if u[0] == "b" and v[0] == "b":
                 continue
@@ -95,9 +100,11 @@ class ZDecoder:
                 u, v = v, u
             if v[0] == "b":
                 p ^= self.par[ev[u[1]], "B"]
+                w += self.dist[ev[u[1]], "B"]
             else:
                 p ^= self.par[ev[u[1]], ev[v[1]]]
-        return p
+                w += self.dist[ev[u[1]], ev[v[1]]]
+        return p, w
 
     def failed(self, records, final_bits):
         """1 if the corrected logical Z reads -1."""

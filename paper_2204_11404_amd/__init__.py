@@ -127,6 +127,9 @@ _SIGS = {
     "sv_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
     "sv_server_clock": (ctypes.c_double, [ctypes.c_void_p]),
     "sv_server_destroy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "sv_decode_z": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
     "sv_tuning_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "sv_tuning_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "sv_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -476,3 +479,22 @@ def tuning_save(path):
 
 def tuning_load(path):
     _check(lib().sv_tuning_load(os.fsencode(path)))
+
+
+def decode_z(d, gateset, records, final_bits):
+    """sv_decode_z: records [n_traj, rounds, d*d-1] raw bits, final_bits
+    [n_traj, d*d].  Returns dict(failed, ambiguous, weight) arrays; failed is
+    2 for trajectories with too many detection events (then `overflow` > 0)."""
+    rec = np.ascontiguousarray(records, dtype=np.uint8)
+    fb = np.ascontiguousarray(final_bits, dtype=np.uint8)
+    n_traj, rounds, n_stab = rec.shape
+    if n_stab != d * d - 1 or fb.shape != (n_traj, d * d):
+        raise ValueError("records / final_bits shape does not match d")
+    failed = np.zeros(n_traj, dtype=np.uint8)
+    amb = np.zeros(n_traj, dtype=np.uint8)
+    w = np.zeros(n_traj, dtype=np.int32)
+    st = lib().sv_decode_z(d, _GATESETS[gateset], rounds, n_traj, rec.ctypes.data, fb.ctypes.data,
+                           failed.ctypes.data, amb.ctypes.data, w.ctypes.data)
+    if st not in (SV_OK, SV_ENUMERIC):
+        _check(st)
+    return dict(failed=failed, ambiguous=amb, weight=w, overflow=int(np.sum(failed == 2)))

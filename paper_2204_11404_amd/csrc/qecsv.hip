@@ -1844,4 +1844,5 @@ sv_status sv_tuning_load(const char* path) {
 
 }  // extern "C"
 
+#include "decoder.hip"
 #include "server.hip"

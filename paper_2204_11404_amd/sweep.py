@@ -1,0 +1,93 @@
+"""Logical error rate of the Z-basis memory experiment against the physical
+error rate (Sec. III.B, Fig. 5), and the power-law fit p_L = A p^xi.
+
+A point (p, c) runs n trajectories of logical |0>, `rounds` noisy rounds and
+the final data measurement on the GPU (sv_run_rounds), every gate over-rotated
+by the exponent eps = c sqrt(p) (Sec. III.A: the over-rotation angle is
+theta = 2 c sqrt(p)), then decodes them with the library's minimum-weight
+matching (sv_decode_z).  p_L is the fraction of trajectories whose corrected
+Z_L reads -1; its error bar is the binomial standard deviation.  The fit is a
+weighted least-squares line through (log p, log p_L), weights from the
+binomial variance (points without failures are left out).
+
+    python -m paper_2204_11404_amd.sweep --d 5 --c 0 --traj 10000 \\
+        --p 1e-3 1.5e-3 2e-3 2.5e-3 3e-3
+"""
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from . import decode_z, run_rounds
+
+
+def run_point(d, p, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, zeta=0.0,
+              chunk=1000, log=None):
+    eps = c * math.sqrt(p)
+    fails = amb = over = 0
+    gpu_ms = dec_s = 0.0
+    t0 = time.perf_counter()
+    for first in range(0, n_traj, chunk):
+        n = min(chunk, n_traj - first)
+        r = run_rounds(d, gateset, rounds, n, seed, p, eps=eps, zeta=zeta, dtype=dtype, traj0=first)
+        gpu_ms += r["gpu_ms"]
+        t1 = time.perf_counter()
+        out = decode_z(d, gateset, r["records"], r["final_bits"])
+        dec_s += time.perf_counter() - t1
+        fails += int(np.sum(out["failed"] == 1))
+        amb += int(np.sum(out["ambiguous"]))
+        over += out["overflow"]
+        if log:
+            log(f"  p={p:g} c={c:g}: {first + n}/{n_traj} trajectories, {fails} failures")
+    n_ok = n_traj - over
+    pl = fails / n_ok if n_ok else float("nan")
+    return {"d": d, "p": p, "c": c, "eps": eps, "rounds": rounds, "dtype": dtype,
+            "trajectories": n_traj, "failures": fails, "p_L": pl,
+            "p_L_err": math.sqrt(pl * (1 - pl) / n_ok) if n_ok else float("nan"),
+            "ambiguous": amb, "undecoded": over, "gpu_s": gpu_ms * 1e-3, "decode_s": dec_s,
+            "wall_s": time.perf_counter() - t0}
+
+
+def fit_power_law(points):
+    """Weighted fit of log p_L = log A + xi log p; returns (A, xi, sigma_logA,
+    sigma_xi) or None with fewer than two usable points."""
+    use = [q for q in points if q["failures"] > 0 and q["failures"] < q["trajectories"]]
+    if len(use) < 2:
+        return None
+    x = np.log([q["p"] for q in use])
+    y = np.log([q["p_L"] for q in use])
+    # var(log p_L) ~ (1 - p_L) / (n p_L)
+    w = np.array([q["trajectories"] * q["p_L"] / (1.0 - q["p_L"]) for q in use])
+    X = np.stack([np.ones_like(x), x], axis=1)
+    cov = np.linalg.inv(X.T @ (w[:, None] * X))
+    beta = cov @ (X.T @ (w * y))
+    return {"A": float(math.exp(beta[0])), "xi": float(beta[1]),
+            "sigma_log_A": float(math.sqrt(cov[0, 0])), "sigma_xi": float(math.sqrt(cov[1, 1]))}
+
+
+def sweep(d, ps, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, zeta=0.0, log=None):
+    points = [run_point(d, p, c, n_traj, rounds, gateset, dtype, seed, zeta, log=log) for p in ps]
+    return {"points": points, "fit": fit_power_law(points)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--d", type=int, default=5)
+    ap.add_argument("--p", type=float, nargs="+", default=[1e-3, 1.5e-3, 2e-3, 2.5e-3, 3e-3])
+    ap.add_argument("--c", type=float, default=0.0)
+    ap.add_argument("--traj", type=int, default=10000)
+    ap.add_argument("--rounds", type=int, default=5)
+    ap.add_argument("--gateset", default="cr", choices=["cr", "textbook"])
+    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--seed", type=int, default=2022)
+    ap.add_argument("--zeta", type=float, default=0.0)
+    a = ap.parse_args()
+    res = sweep(a.d, a.p, a.c, a.traj, a.rounds, a.gateset, a.dtype, a.seed, a.zeta,
+                log=lambda m: print(m, flush=True))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
