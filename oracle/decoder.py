@@ -16,7 +16,12 @@ Conventions (the readings used throughout the tests):
     rounds plus layer R for the Z checks recomputed from the final data bits;
     a data qubit in two Z checks joins them within a layer, a data qubit in one
     Z check joins it to the boundary; consecutive layers of a check are joined
-    (measurement errors); unit weights.
+    (measurement errors); unit weights;
+  * the checks of a round are measured one after another with the single
+    ancilla (Sec. II.B), so an X error on a data qubit shared by Z checks A
+    (measured first) and B that occurs between their measurements in round r
+    flips B in layer r and A in layer r + 1: such a data qubit also joins
+    (B, r) and (A, r + 1).
 """
 import itertools
 
@@ -46,6 +51,8 @@ class ZDecoder:
                 flip = 1 if q in self.zl else 0
                 if len(ks) == 2:
                     g.add_edge((ks[0], r), (ks[1], r), flip=flip)
+                    if r < rounds:  # ks[0] is measured before ks[1]
+                        g.add_edge((ks[0], r + 1), (ks[1], r), flip=flip)
                 else:
                     g.add_edge((ks[0], r), B, flip=flip)
             if r < rounds:

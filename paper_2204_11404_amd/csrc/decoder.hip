@@ -9,8 +9,12 @@
 // for the Z checks recomputed from the final data bits, plus one boundary
 // node.  A data qubit in two Z checks joins them within a layer, a data qubit
 // in one Z check joins it to the boundary, consecutive layers of a check are
-// joined (measurement errors).  Every edge has weight 1 and flips the logical
-// parity iff its data qubit lies on Z_L = Z_1 ... Z_d (the top row).
+// joined (measurement errors).  The checks of a round are measured one after
+// another with the single ancilla (Sec. II.B): an X error on a data qubit
+// shared by checks A (measured first) and B between their measurements in
+// round r flips B in layer r and A in layer r + 1, so that qubit also joins
+// (B, r) and (A, r + 1).  Every edge has weight 1 and flips the logical parity
+// iff its data qubit lies on Z_L = Z_1 ... Z_d (the top row).
 //
 // Matching: exact, by dynamic programming over subsets of the events (the
 // lowest unmatched event goes to the boundary or to another event).  Besides
@@ -67,8 +71,13 @@ ZGraph make_zgraph(int d, int rounds, int gateset) {
   for (int r = 0; r <= rounds; ++r) {
     for (const auto& kv : owners) {
       const int flip = kv.first <= d ? 1 : 0;
-      if (kv.second.size() == 2) add(kv.second[0] + g.nz * r, kv.second[1] + g.nz * r, flip);
-      else add(kv.second[0] + g.nz * r, B, flip);
+      if (kv.second.size() == 2) {
+        add(kv.second[0] + g.nz * r, kv.second[1] + g.nz * r, flip);
+        // owners are listed in measurement order
+        if (r < rounds) add(kv.second[0] + g.nz * (r + 1), kv.second[1] + g.nz * r, flip);
+      } else {
+        add(kv.second[0] + g.nz * r, B, flip);
+      }
     }
     if (r < rounds)
       for (int k = 0; k < g.nz; ++k) add(k + g.nz * r, k + g.nz * (r + 1), 0);

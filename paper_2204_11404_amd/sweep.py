@@ -68,7 +68,14 @@ def fit_power_law(points):
 
 
 def sweep(d, ps, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, zeta=0.0, log=None):
-    points = [run_point(d, p, c, n_traj, rounds, gateset, dtype, seed, zeta, log=log) for p in ps]
+    """n_traj: one count for every p, or a list with one count per p."""
+    counts = list(n_traj) if isinstance(n_traj, (list, tuple)) else [n_traj]
+    if len(counts) == 1:
+        counts = counts * len(ps)
+    if len(counts) != len(ps):
+        raise ValueError("give one trajectory count, or one per p")
+    points = [run_point(d, p, c, n, rounds, gateset, dtype, seed, zeta, log=log)
+              for p, n in zip(ps, counts)]
     return {"points": points, "fit": fit_power_law(points)}
 
 
@@ -77,7 +84,8 @@ def main():
     ap.add_argument("--d", type=int, default=5)
     ap.add_argument("--p", type=float, nargs="+", default=[1e-3, 1.5e-3, 2e-3, 2.5e-3, 3e-3])
     ap.add_argument("--c", type=float, default=0.0)
-    ap.add_argument("--traj", type=int, default=10000)
+    ap.add_argument("--traj", type=int, nargs="+", default=[10000],
+                    help="trajectories per point (one value, or one per p)")
     ap.add_argument("--rounds", type=int, default=5)
     ap.add_argument("--gateset", default="cr", choices=["cr", "textbook"])
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])

@@ -61,3 +61,31 @@ def test_distance_helps_below_threshold():
         rates[d] = fails / rec.shape[0]
         assert rates[d] < raw / 5
     assert rates[5] < rates[3]
+
+
+@pytest.mark.parametrize("gateset", [oracle.GATESET_CR, oracle.GATESET_TEXTBOOK])
+def test_error_between_two_checks_of_a_round_is_one_fault(gateset):
+    """Checks of a round are measured one after another: an X error on a data
+    qubit shared by Z checks a (measured first) and b, striking between their
+    measurements of round 0, shows in b from round 0 and in a from round 1 --
+    one fault, matched at weight 1 and corrected."""
+    d, R = 3, 3
+    dec = decoder.ZDecoder(d, R, gateset)
+    owners = {}
+    for k, sup in enumerate(dec.zsup):
+        for q in sup:
+            owners.setdefault(q, []).append(k)
+    for q, ks in owners.items():
+        if len(ks) != 2:
+            continue
+        a, b = ks
+        rec = np.zeros((R, d * d - 1), dtype=np.uint8)
+        rec[:, dec.zidx] = dec.r0
+        rec[0:, dec.zidx[b]] ^= 1
+        rec[1:, dec.zidx[a]] ^= 1
+        fin = np.zeros(d * d, dtype=np.uint8)
+        fin[q - 1] = 1
+        det = dec.detectors(rec, fin)
+        assert sorted(zip(*np.nonzero(det))) == sorted([(b, 0), (a, 1)])
+        assert dec.matching(det)[1] == 1
+        assert dec.failed(rec, fin) == 0
