@@ -67,6 +67,32 @@ def fit_power_law(points):
             "sigma_log_A": float(math.sqrt(cov[0, 0])), "sigma_xi": float(math.sqrt(cov[1, 1]))}
 
 
+def fit_effective_model(points, A, xi):
+    """Effective-error-rate model of Sec. III.B: with A, xi fixed from c = 0,
+    fit p_L = A (B p)^xi at each c for B (weighted least squares in log p_L),
+    then B = 1 + alpha c^2 over the c > 0 values.  Returns
+    {"B": {c: (B, sigma_B)}, "alpha": alpha, "sigma_alpha": ...}."""
+    byc = {}
+    for q in points:
+        if 0 < q["failures"] < q["trajectories"]:
+            byc.setdefault(q["c"], []).append(q)
+    out_b = {}
+    for c, qs_ in sorted(byc.items()):
+        # log p_L - log A - xi log p = xi log B: weighted mean of the residual
+        r = np.array([(math.log(q["p_L"]) - math.log(A) - xi * math.log(q["p"])) / xi for q in qs_])
+        w = np.array([q["trajectories"] * q["p_L"] / (1.0 - q["p_L"]) for q in qs_]) * xi * xi
+        logb = float(np.sum(w * r) / np.sum(w))
+        out_b[c] = (math.exp(logb), math.exp(logb) / math.sqrt(np.sum(w)))
+    cs = [c for c in out_b if c > 0]
+    if not cs:
+        return {"B": out_b, "alpha": None, "sigma_alpha": None}
+    x = np.array([c * c for c in cs])
+    y = np.array([out_b[c][0] - 1.0 for c in cs])
+    wv = np.array([1.0 / out_b[c][1] ** 2 for c in cs])
+    alpha = float(np.sum(wv * x * y) / np.sum(wv * x * x))
+    return {"B": out_b, "alpha": alpha, "sigma_alpha": float(1.0 / math.sqrt(np.sum(wv * x * x)))}
+
+
 def sweep(d, ps, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, zeta=0.0, log=None):
     """n_traj: one count for every p, or a list with one count per p."""
     counts = list(n_traj) if isinstance(n_traj, (list, tuple)) else [n_traj]

@@ -96,3 +96,16 @@ def test_sweep_point_runs():
     q = run_point(3, 5e-3, 0.5, 400, rounds=3, chunk=150)
     assert q["trajectories"] == 400 and q["undecoded"] == 0
     assert 0.0 <= q["p_L"] < 0.2
+
+
+def test_effective_model_fit_recovers_alpha():
+    from paper_2204_11404_amd.sweep import fit_effective_model
+    A, xi, alpha = 2e5, 3.0, 0.8
+    pts = []
+    for c in (0.0, 0.5, 1.0):
+        for p in (1.5e-3, 3e-3):
+            pl = A * ((1 + alpha * c * c) * p) ** xi
+            pts.append({"p": p, "c": c, "p_L": pl, "trajectories": 10 ** 6, "failures": int(pl * 1e6)})
+    f = fit_effective_model(pts, A, xi)
+    assert abs(f["B"][0.0][0] - 1.0) < 1e-9
+    assert abs(f["alpha"] - alpha) < 1e-9
