@@ -72,6 +72,14 @@ typedef enum {
                           passes, decisions, final measurement, record copy)
                           in a HIP graph once and replay it per trajectory;
                           results are identical to the stream launches */
+#define SV_RUN_TWIRL 2 /* Pauli-twirled over-rotations: every rotation turns by
+                          its base angle only, and one draw right after it
+                          applies its generator (Rx: X, Rz: Z, Rzx: Z x X, the
+                          textbook exp(-i eps X): X) with probability sin^2 of
+                          the site's exponent -- the Pauli channel with the
+                          same error probability as the coherent error
+                          (Sec. III.A); the draw enumeration gains one draw per
+                          rotation, placed before that gate's noise draw */
 
 typedef struct sv_state_s* sv_state;
 
@@ -162,8 +170,8 @@ typedef struct sv_job {
   int rounds;          /* noisy rounds, >= 1 */
   int dtype;           /* sv_dtype of the state */
   int n_traj;          /* trajectories */
-  int flags;           /* 0 or SV_RUN_GRAPH (sv_run_rounds only; with it,
-                          final_states must be NULL) */
+  int flags;           /* SV_RUN_GRAPH | SV_RUN_TWIRL (sv_run_rounds only;
+                          with SV_RUN_GRAPH final_states must be NULL) */
   uint64_t traj0;      /* first trajectory index (draw stream id) */
   uint64_t seed;       /* Philox key */
   double p;            /* depolarizing probability, [0, 1] */

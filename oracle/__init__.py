@@ -33,7 +33,7 @@ class _Job(ctypes.Structure):
         ("d", ctypes.c_int),
         ("gateset", ctypes.c_int),
         ("rounds", ctypes.c_int),
-        ("pad_", ctypes.c_int),
+        ("twirl", ctypes.c_int),
         ("seed", ctypes.c_ulonglong),
         ("p", ctypes.c_double),
         ("zeta", ctypes.c_double),
@@ -116,7 +116,7 @@ def template_counts(d, gateset):
 
 
 def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=None,
-                   want_state=False):
+                   want_state=False, twirl=False):
     """One Monte Carlo trajectory.
 
     Returns dict(records=uint8[rounds, n_stab], final_bits=uint8[d*d],
@@ -126,6 +126,7 @@ def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=N
     job = _Job()
     job.d, job.gateset, job.rounds = d, gateset, rounds
     job.seed, job.p, job.zeta, job.eps = int(seed), float(p), float(zeta), float(eps)
+    job.twirl = 1 if twirl else 0
     keep = None
     if eps_site is not None:
         keep = np.ascontiguousarray(eps_site, dtype=np.float64)

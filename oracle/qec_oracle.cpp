@@ -334,6 +334,7 @@ struct Job {
   double zeta;
   const double* eps_site;  // per gate site (length = sites per round) or null
   double eps;              // used for every site when eps_site is null
+  int twirl;               // 1: Pauli-twirled over-rotations (see site_rot1)
 };
 
 struct Ctx {
@@ -348,6 +349,39 @@ double next_eps(Ctx& cx) {
   const int s = cx.site++;
   if (!cx.noisy) return 0.0;
   return cx.job->eps_site ? cx.job->eps_site[s] : cx.job->eps;
+}
+
+// Rotation exp(-i sign (base + eps) P) of the next gate site.  Twirled model
+// (Sec. III.A: the coherent error exp(-i eps P) next to its Pauli channel):
+// the rotation by sign*base only, then one draw u and the Pauli P when
+// u < sin^2 eps.  Outside the noisy part (state preparation) nothing is drawn.
+void site_rot1(State& s, Ctx& cx, int q, int P, double sign, double base) {
+  const double e = next_eps(cx);
+  if (!cx.job->twirl || !cx.noisy) {
+    if (base != 0.0 || e != 0.0) rot1(s, q, P, sign * (base + e));
+    return;
+  }
+  if (base != 0.0) rot1(s, q, P, sign * base);
+  const double u = uniform01(cx.job->seed, cx.t, cx.k++);
+  const double sn = std::sin(e);
+  if (u < sn * sn) apply_pauli(s, q, P);
+}
+
+// exp(-i (base + eps) Z_qc X_qt); twirled: Z on qc and X on qt with
+// probability sin^2 eps after the base rotation.
+void site_rzx(State& s, Ctx& cx, int qc, int qt, double base) {
+  const double e = next_eps(cx);
+  if (!cx.job->twirl || !cx.noisy) {
+    rot_zx(s, qc, qt, base + e);
+    return;
+  }
+  rot_zx(s, qc, qt, base);
+  const double u = uniform01(cx.job->seed, cx.t, cx.k++);
+  const double sn = std::sin(e);
+  if (u < sn * sn) {
+    apply_pauli(s, qc, 3);
+    apply_pauli(s, qt, 1);
+  }
 }
 
 // One-qubit depolarizing channel (Sec. III.A): with probability p/3 each, X, Y
@@ -386,30 +420,30 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
   if (gateset == 0) {
     if (st.type == 0) {
       // Rx^dag(pi/2) on the ancilla: rotation about -X.
-      rot1(s, anc, 1, -(q4 + next_eps(cx)));
+      site_rot1(s, cx, anc, 1, -1.0, q4);
       noise1(s, cx, anc);
       for (int j = 0; j < 4; ++j) {
         const int q = st.slot[j];
         if (q) {
-          rot_zx(s, anc, q - 1, q4 + next_eps(cx));
+          site_rzx(s, cx, anc, q - 1, q4);
           noise2(s, cx, anc, q - 1);
         } else {
           noise1(s, cx, anc);
         }
       }
-      rot1(s, anc, 1, q4 + next_eps(cx));
+      site_rot1(s, cx, anc, 1, 1.0, q4);
       noise1(s, cx, anc);
       for (int j = 0; j < 4; ++j) {
         const int q = st.slot[j];
         if (!q) continue;
-        rot1(s, q - 1, 1, q4 + next_eps(cx));
+        site_rot1(s, cx, q - 1, 1, 1.0, q4);
         noise1(s, cx, q - 1);
       }
     } else {
       for (int j = 0; j < 4; ++j) {
         const int q = st.slot[j];
         if (q) {
-          rot_zx(s, q - 1, anc, q4 + next_eps(cx));
+          site_rzx(s, cx, q - 1, anc, q4);
           noise2(s, cx, q - 1, anc);
         } else {
           noise1(s, cx, anc);
@@ -418,7 +452,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
       for (int j = 0; j < 4; ++j) {
         const int q = st.slot[j];
         if (!q) continue;
-        rot1(s, q - 1, 3, q4 + next_eps(cx));
+        site_rot1(s, cx, q - 1, 3, 1.0, q4);
         noise1(s, cx, q - 1);
       }
     }
@@ -426,10 +460,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
     // Textbook circuit: H, entangling gates, H on the ancilla; each H is
     // followed by the coherent error exp(-i eps X) on the ancilla.
     hadamard(s, anc);
-    {
-      const double e = next_eps(cx);
-      if (e != 0.0) rot1(s, anc, 1, e);
-    }
+    site_rot1(s, cx, anc, 1, 1.0, 0.0);
     noise1(s, cx, anc);
     for (int j = 0; j < 4; ++j) {
       const int q = st.slot[j];
@@ -438,10 +469,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
       noise2(s, cx, anc, q - 1);
     }
     hadamard(s, anc);
-    {
-      const double e = next_eps(cx);
-      if (e != 0.0) rot1(s, anc, 1, e);
-    }
+    site_rot1(s, cx, anc, 1, 1.0, 0.0);
     noise1(s, cx, anc);
   }
 }
@@ -566,7 +594,7 @@ typedef struct {
   int d;
   int gateset;
   int rounds;
-  int pad_;
+  int twirl;  // 1: Pauli-twirled over-rotations
   unsigned long long seed;
   double p;
   double zeta;
@@ -603,7 +631,7 @@ int orc_template_counts(int d, int gateset, int* n_stab, int* n_sites, int* n_dr
 int orc_run_trajectory(const orc_job* j, unsigned long long t, uint8_t* records,
                        uint8_t* final_bits, double* p1_trace, double* final_state) {
   if (!j || j->d < 2 || j->d > 5 || j->rounds < 0) return -1;
-  Job job{j->d, j->gateset, j->rounds, j->seed, j->p, j->zeta, j->eps_site, j->eps};
+  Job job{j->d, j->gateset, j->rounds, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl};
   Output out{records, final_bits, p1_trace, final_state};
   return run_trajectory(job, t, out);
 }
@@ -611,7 +639,7 @@ int orc_run_trajectory(const orc_job* j, unsigned long long t, uint8_t* records,
 // Logical |0> on the data register (ancilla 0), 2^(d*d) interleaved complex.
 int orc_logical_zero(int d, int gateset, double* out) {
   if (d < 2 || d > 5) return -1;
-  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0};
+  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0, 0};
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);
   if (prepare_logical_zero(s, job, stabs) != 0) return -1;
@@ -646,7 +674,7 @@ int orc_apply_gate(double* state, int n, int k, const int* qubits, const double*
 // the corresponding part of a trajectory.
 double orc_time_blocks(const orc_job* j, unsigned long long t, int n_blocks, int* threads) {
   if (!j || j->d < 2 || j->d > 5 || n_blocks < 1) return -1.0;
-  Job job{j->d, j->gateset, 1, j->seed, j->p, j->zeta, j->eps_site, j->eps};
+  Job job{j->d, j->gateset, 1, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl};
   const int d = job.d, anc = d * d;
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);

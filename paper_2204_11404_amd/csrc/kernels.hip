@@ -123,12 +123,14 @@ __device__ __forceinline__ double clamp_p1(double p1) {
 
 // ---------------------------------------------------------------- prepare --
 // Draws and Kraus pairs of every block instance of n_traj trajectories
-// (draw streams traj0 + i, or *stream for a single trajectory when given).
+// (draw streams traj0 + i, or *stream for a single trajectory when given);
+// twirl_thr: per-site sin^2 eps of the Pauli-twirled model, or null.
 __global__ void k_prepare(const TBlock* __restrict__ blocks, int n_stab, int rounds,
                           int draws_per_round, uint64_t seed, uint64_t traj0, int n_traj,
                           double p, const double* __restrict__ eps_site,
                           BlockRT* __restrict__ out, int* __restrict__ err,
-                          const uint64_t* __restrict__ stream) {
+                          const uint64_t* __restrict__ stream,
+                          const double* __restrict__ twirl_thr) {
   const int per_traj = rounds * n_stab;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)per_traj * n_traj) return;
@@ -140,7 +142,7 @@ __global__ void k_prepare(const TBlock* __restrict__ blocks, int n_stab, int rou
   BlockRT rt;
   const uint64_t k0 = (uint64_t)r * (uint64_t)draws_per_round + (uint64_t)b.draw_off;
   const uint64_t t = stream ? *stream : traj0 + (uint64_t)ti;
-  draw_block(b, seed, t, k0, p, pauli, &rt.u);
+  draw_block(b, seed, t, k0, p, pauli, &rt.u, twirl_thr);
   if (!build_block(b, eps_site, pauli, rt)) atomicOr(err, 1);
   rt.pad = 0;
   out[gid] = rt;

@@ -179,9 +179,17 @@ QEC_HD void anc_rot_cs(int axis, double c, double s, cd& v0, cd& v1) {
 }
 
 // Angle of a rotation op: pi/4 (cross-resonance gate set) or 0 (textbook
-// over-rotation gate) plus the over-rotation exponent of its site.
+// over-rotation gate) plus the over-rotation exponent of its site.  A
+// rotation op that carries a draw belongs to the Pauli-twirled model (its
+// over-rotation is replaced by the generator applied with probability
+// sin^2 eps, Sec. III.A): it rotates by the base angle only.
 QEC_HD double op_angle(const TOp& op, const double* eps_site) {
-  return (op.quarter ? 0.78539816339744830962 : 0.0) + (op.site >= 0 ? eps_site[op.site] : 0.0);
+  return (op.quarter ? 0.78539816339744830962 : 0.0) +
+         (op.site >= 0 && op.draw < 0 ? eps_site[op.site] : 0.0);
+}
+
+QEC_HD bool is_rotation(uint8_t kind) {
+  return kind == OP_ROT_ANC || kind == OP_ROT_DATA || kind == OP_CR_AD || kind == OP_CR_DA;
 }
 
 // Accessor evaluating cos/sin of each op's angle on the fly.
@@ -219,6 +227,7 @@ QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd
       case OP_ROT_ANC: {
         const cd c = cs(op);
         anc_rot_cs(op.axis, c.re, c.im * (double)op.sgn, v0, v1);
+        if (pauli[i]) anc_pauli(op.axis, v0, v1);  // twirled: the generator
         break;
       }
       case OP_ROT_DATA: {
@@ -228,6 +237,11 @@ QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd
         const cd ph{c.re, -c.im * e * (double)op.sgn};  // exp(-i beta e sgn)
         v0 = cmul(v0, ph);
         v1 = cmul(v1, ph);
+        if (pauli[i]) {
+          const cd g = data_pauli(op.axis, xb, op.j, cur);
+          v0 = cmul(v0, g);
+          v1 = cmul(v1, g);
+        }
         break;
       }
       case OP_CR_AD: {
@@ -236,6 +250,12 @@ QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd
         const cd c = cs(op);
         v0 = cmul(v0, cd{c.re, -c.im * e});
         v1 = cmul(v1, cd{c.re, c.im * e});
+        if (pauli[i]) {  // Z on the ancilla, X on data j
+          anc_pauli(3, v0, v1);
+          const cd g = data_pauli(1, xb, op.j, cur);
+          v0 = cmul(v0, g);
+          v1 = cmul(v1, g);
+        }
         break;
       }
       case OP_CR_DA: {
@@ -243,6 +263,12 @@ QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd
         const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
         const cd c = cs(op);
         anc_rot_cs(1, c.re, c.im * e, v0, v1);
+        if (pauli[i]) {  // Z on data j, X on the ancilla
+          const cd g = data_pauli(3, xb, op.j, cur);
+          v0 = cmul(v0, g);
+          v1 = cmul(v1, g);
+          anc_pauli(1, v0, v1);
+        }
         break;
       }
       case OP_H_ANC: {
@@ -323,15 +349,19 @@ QEC_HD bool build_block(const TBlock& b, const double* eps_site, const uint8_t* 
   return true;
 }
 
-// Draws of one block instance: Pauli choices per op, measurement uniform.
+// Draws of one block instance: Pauli choices per op (for a twirled rotation:
+// 1 if its generator is applied, u < twirl_thr[site] = sin^2 eps),
+// measurement uniform.
 QEC_HD void draw_block(const TBlock& b, uint64_t seed, uint64_t t, uint64_t k0, double p,
-                       uint8_t* pauli, double* u_meas) {
+                       uint8_t* pauli, double* u_meas, const double* twirl_thr = nullptr) {
   for (int i = 0; i < b.n_ops; ++i) {
     const TOp& op = b.ops[i];
     pauli[i] = 0;
     if (op.draw < 0) continue;
     const double u = uniform(seed, t, k0 + (uint64_t)op.draw);
-    if (op.kind == OP_N1_ANC || op.kind == OP_N1_DATA)
+    if (is_rotation(op.kind))
+      pauli[i] = (uint8_t)(twirl_thr && u < twirl_thr[op.site] ? 1 : 0);
+    else if (op.kind == OP_N1_ANC || op.kind == OP_N1_DATA)
       pauli[i] = (uint8_t)pick_pauli1(u, p);
     else
       pauli[i] = (uint8_t)pick_pauli2(u, p);

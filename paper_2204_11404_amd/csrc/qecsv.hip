@@ -144,6 +144,7 @@ struct Template {
 struct OpSink {
   TBlock& b;
   int site_base;
+  bool twirl;  // rotations draw their twirled over-rotation
   int sites = 0;
   int draws = 0;
   void gate(uint8_t kind, int j, int axis, int sgn, int quarter) {
@@ -152,7 +153,7 @@ struct OpSink {
     o.kind = kind; o.j = (uint8_t)j; o.axis = (uint8_t)axis; o.sgn = (int8_t)sgn;
     o.quarter = (uint8_t)quarter;
     o.site = (int16_t)(site_base + sites++);
-    o.draw = -1;
+    o.draw = twirl ? (int16_t)draws++ : (int16_t)-1;
   }
   void plain(uint8_t kind, int j) {
     TOp& o = b.ops[b.n_ops++];
@@ -168,7 +169,10 @@ struct OpSink {
   }
 };
 
-Template build_template(int d, int gateset) {
+// twirl: Pauli-twirled over-rotations -- each rotation by its base angle,
+// then one draw deciding whether its generator is applied (probability
+// sin^2 eps of its site), drawn right after the rotation.
+Template build_template(int d, int gateset, bool twirl = false) {
   Template T;
   for (const Stab& st : code_layout(d)) {
     TBlock b{};
@@ -184,7 +188,7 @@ Template build_template(int d, int gateset) {
     }
     b.draw_off = T.n_draws;
     b.site_off = T.n_sites;
-    OpSink o{b, T.n_sites};
+    OpSink o{b, T.n_sites, twirl};
     if (gateset == SV_GATESET_CR) {
       if (st.type == 0) {
         o.gate(OP_ROT_ANC, 0, 1, -1, 1);  // Rx^dag(pi/2)
@@ -698,6 +702,19 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   HIP_OK(hipMemcpyAsync(deps, eps.data(), sizeof(double) * eps.size(), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
   HIP_OK(hipMemsetAsync(ddec, 0, sizeof(Decision) * (per_units + 1), s));
+  // Pauli-twirled over-rotations: per-site probability sin^2 eps, computed
+  // here so that every implementation compares its draws with the same value
+  double* dthr = nullptr;
+  std::vector<double> thr;
+  if (job->flags & SV_RUN_TWIRL) {
+    thr.resize(eps.size());
+    for (size_t i = 0; i < eps.size(); ++i) {
+      const double sn = std::sin(eps[i]);
+      thr[i] = sn * sn;
+    }
+    HIP_OK(M.alloc(&dthr, sizeof(double) * thr.size()));
+    HIP_OK(hipMemcpyAsync(dthr, thr.data(), sizeof(double) * thr.size(), hipMemcpyHostToDevice, s));
+  }
 
   // whole-run events plus one pair around every pass of the last trajectory
   struct Events {
@@ -795,7 +812,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
     {
       hipLaunchKernelGGL(k_prepare, dim3((unsigned)((per_traj + 127) / 128)), dim3(128), 0, G.q,
                          dblocks, ns, R, draws_round, job->seed, job->traj0, 1, job->p, deps, rt_s,
-                         derr, (const uint64_t*)(dcur + 1));
+                         derr, (const uint64_t*)(dcur + 1), (const double*)dthr);
       cst = traj_passes(G.q, rt_s, rec_s, p1_s, false);
       if (cst == SV_OK) {
         traj_final(G.q, bits_s, 0, dcur + 1);
@@ -828,7 +845,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       const int64_t nthreads = (int64_t)cn * per_traj;
       hipLaunchKernelGGL(k_prepare, dim3((unsigned)((nthreads + 127) / 128)), dim3(128), 0, s, dblocks,
                          ns, R, draws_round, job->seed, job->traj0 + (uint64_t)c0, cn, job->p, deps,
-                         drt, derr, (const uint64_t*)nullptr);
+                         drt, derr, (const uint64_t*)nullptr, (const double*)dthr);
       HIP_OK(hipGetLastError());
       for (int ti = 0; ti < cn; ++ti) {
         if (cancel && cancel->load(std::memory_order_relaxed)) {
@@ -1618,13 +1635,13 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
   if (job->rounds < 1 || job->rounds > 100000) return fail(SV_EINVAL, "rounds=%d", job->rounds);
   if (job->dtype != SV_C64 && job->dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
   if (job->n_traj < 0) return fail(SV_EINVAL, "n_traj < 0");
-  if (job->flags & ~SV_RUN_GRAPH) return fail(SV_EINVAL, "unknown flags 0x%x", job->flags);
+  if (job->flags & ~(SV_RUN_GRAPH | SV_RUN_TWIRL)) return fail(SV_EINVAL, "unknown flags 0x%x", job->flags);
   if (!(job->p >= 0.0 && job->p <= 1.0)) return fail(SV_EINVAL, "p out of [0, 1]");
   if (!std::isfinite(job->eps) || !std::isfinite(job->zeta)) return fail(SV_EINVAL, "non-finite eps/zeta");
   if (!res->records || !res->final_bits) return fail(SV_EINVAL, "records and final_bits are required");
   if ((job->flags & SV_RUN_GRAPH) && res->final_states)
     return fail(SV_EINVAL, "final_states cannot be returned with SV_RUN_GRAPH");
-  const Template tp = build_template(job->d, job->gateset);
+  const Template tp = build_template(job->d, job->gateset, (job->flags & SV_RUN_TWIRL) != 0);
   if (job->eps_site)
     for (int i = 0; i < tp.n_sites; ++i)
       if (!std::isfinite(job->eps_site[i])) return fail(SV_EINVAL, "non-finite eps_site[%d]", i);

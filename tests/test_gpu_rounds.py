@@ -23,14 +23,14 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "d5_cr_oracle.npz")
 
 
 def _compare(d, gateset, R, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0, dtype="c128",
-             traj0=0, atol=1e-10):
-    print(f"case rounds d={d} {gateset} R={R} n={n_traj} p={p} eps={eps} zeta={zeta} {dtype}",
-          flush=True)
+             traj0=0, atol=1e-10, twirl=False):
+    print(f"case rounds d={d} {gateset} R={R} n={n_traj} p={p} eps={eps} zeta={zeta} {dtype}"
+          f" twirl={twirl}", flush=True)
     g = qs.run_rounds(d, gateset, R, n_traj, seed, p, eps=eps, eps_site=eps_site, zeta=zeta,
-                      dtype=dtype, traj0=traj0, want_p1=True, want_states=True)
+                      dtype=dtype, traj0=traj0, want_p1=True, want_states=True, twirl=twirl)
     for i in range(n_traj):
         o = oracle.run_trajectory(d, GS[gateset], R, seed, traj0 + i, p, eps=eps, eps_site=eps_site,
-                                  zeta=zeta, want_state=True)
+                                  zeta=zeta, want_state=True, twirl=twirl)
         assert np.array_equal(g["records"][i], o["records"]), f"trajectory {i}"
         assert np.array_equal(g["final_bits"][i], o["final_bits"]), f"trajectory {i}"
         assert np.max(np.abs(g["p1"][i] - o["p1"])) < atol
@@ -167,3 +167,14 @@ def test_graph_replay_matches_stream_launches(d, dtype):
 def test_graph_rejects_final_states():
     with pytest.raises(qs.SvError):
         qs.run_rounds(3, "cr", 1, 1, 0, 0.01, graph=True, want_states=True)
+
+
+@pytest.mark.parametrize("gateset", ["cr", "textbook"])
+@pytest.mark.parametrize("d", [3, 4])
+def test_twirled_over_rotation_parity(gateset, d):
+    """SV_RUN_TWIRL: every rotation by its base angle plus its generator with
+    probability sin^2 eps (one extra draw per rotation)."""
+    n_sites = oracle.template_counts(d, GS[gateset])[1]
+    eps = workloads.eps_sites(n_sites, (0.1, 0.5), 5)
+    _compare(d, gateset, 2, 3 if d == 4 else 12, seed=41, p=0.01, eps_site=eps, zeta=0.01, twirl=True)
+

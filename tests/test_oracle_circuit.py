@@ -170,7 +170,7 @@ def test_final_measurement_is_born_sampling():
 
 # ---- dense brute force of a whole d=2 trajectory with the same draws ------
 
-def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta):
+def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta, twirl=False):
     nd = d * d
     n = nd + 1
     anc = nd
@@ -210,6 +210,17 @@ def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta):
                 psi = g([q1, q2], np.kron(P[j & 3], P[j >> 2])) @ psi
                 return
 
+    def site(qs, M, sign, base):
+        """Gate site: exp(-i sign (base + eps) M), or in the twirled model the
+        base rotation and then, on one draw u < sin^2 eps, the Pauli M."""
+        nonlocal psi
+        if not twirl:
+            psi = g(qs, rot(M, sign * (base + eps))) @ psi
+            return
+        psi = g(qs, rot(M, sign * base)) @ psi
+        if draw() < np.sin(eps) ** 2:
+            psi = g(qs, M) @ psi
+
     # ZX with bit0 = control (Z), bit1 = target (X): kron(X, Z)
     ZX = np.kron(X, Z)
     edges = []
@@ -230,27 +241,27 @@ def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta):
         for i, (typ, slots) in enumerate(oracle.layout(d)):
             if gateset == CR:
                 if typ == "X":
-                    psi = g([anc], rot(X, -(q4 + eps))) @ psi; n1(anc)
+                    site([anc], X, -1, q4); n1(anc)
                     for q in slots:
                         if q:
-                            psi = g([anc, q - 1], rot(ZX, q4 + eps)) @ psi; n2(anc, q - 1)
+                            site([anc, q - 1], ZX, 1, q4); n2(anc, q - 1)
                         else:
                             n1(anc)
-                    psi = g([anc], rot(X, q4 + eps)) @ psi; n1(anc)
+                    site([anc], X, 1, q4); n1(anc)
                     for q in slots:
                         if q:
-                            psi = g([q - 1], rot(X, q4 + eps)) @ psi; n1(q - 1)
+                            site([q - 1], X, 1, q4); n1(q - 1)
                 else:
                     for q in slots:
                         if q:
-                            psi = g([q - 1, anc], rot(ZX, q4 + eps)) @ psi; n2(q - 1, anc)
+                            site([q - 1, anc], ZX, 1, q4); n2(q - 1, anc)
                         else:
                             n1(anc)
                     for q in slots:
                         if q:
-                            psi = g([q - 1], rot(Z, q4 + eps)) @ psi; n1(q - 1)
+                            site([q - 1], Z, 1, q4); n1(q - 1)
             else:
-                psi = g([anc], rot(X, eps) @ H) @ psi; n1(anc)
+                psi = g([anc], H) @ psi; site([anc], X, 1, 0.0); n1(anc)
                 for q in slots:
                     if q:
                         if typ == "X":
@@ -258,7 +269,7 @@ def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta):
                         else:
                             m = np.diag([1, 1, 1, -1]).astype(float)
                         psi = g([anc, q - 1], m) @ psi; n2(anc, q - 1)
-                psi = g([anc], rot(X, eps) @ H) @ psi; n1(anc)
+                psi = g([anc], H) @ psi; site([anc], X, 1, 0.0); n1(anc)
             psi = zzphase * psi
             m, _, psi = sv.measure_reset(psi, anc, u=draw())
             rec[r, i] = m
@@ -286,3 +297,31 @@ def test_dense_brute_force_d2_trajectories(gateset):
         assert np.array_equal(o["records"], rec)
         assert np.array_equal(o["final_bits"], fb)
         assert np.allclose(o["state"], st, atol=1e-12)
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+def test_dense_brute_force_d2_twirled_trajectories(gateset):
+    """Pauli-twirled over-rotations (one draw after each rotation; its
+    generator with probability sin^2 eps) against the dense brute force."""
+    d, R = 2, 3
+    hits = 0
+    for t, (p, eps, zeta) in enumerate([(0.05, 0.3, 0.0), (0.1, 0.25, 0.05), (0.0, 0.4, 0.02)]):
+        rec, fb, st = _dense_trajectory(d, gateset, R, 23, t, p, eps, zeta, twirl=True)
+        o = oracle.run_trajectory(d, gateset, R, seed=23, t=t, p=p, eps=eps, zeta=zeta,
+                                  want_state=True, twirl=True)
+        assert np.array_equal(o["records"], rec)
+        assert np.array_equal(o["final_bits"], fb)
+        assert np.allclose(o["state"], st, atol=1e-12)
+        hits += int(np.any(rec != trivial_bits(d, gateset)))
+    assert hits > 0
+
+
+def test_twirled_textbook_first_check_flips_with_sin2_eps():
+    """Twirled textbook circuit, no other noise: the X after the last H of the
+    first check flips its outcome with probability sin^2 eps, the same as the
+    coherent error (whose p1 is sin^2 eps exactly)."""
+    eps, n = 0.2, 4000
+    flips = sum(int(oracle.run_trajectory(2, TB, 1, seed=3, t=t, p=0.0, eps=eps,
+                                          twirl=True)["records"][0, 0]) for t in range(n))
+    q = np.sin(eps) ** 2
+    assert abs(flips / n - q) < 4 * np.sqrt(q * (1 - q) / n)
