@@ -39,6 +39,8 @@ class _Job(ctypes.Structure):
         ("zeta", ctypes.c_double),
         ("eps_site", ctypes.POINTER(ctypes.c_double)),
         ("eps", ctypes.c_double),
+        ("xbasis", ctypes.c_int),
+        ("pad_", ctypes.c_int),
     ]
 
 
@@ -66,8 +68,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.orc_run_trajectory.argtypes = [ctypes.POINTER(_Job), ctypes.c_ulonglong, u8p, u8p, dp, dp]
         L.orc_run_trajectory.restype = ctypes.c_int
-        L.orc_logical_zero.argtypes = [ctypes.c_int, ctypes.c_int, dp]
-        L.orc_logical_zero.restype = ctypes.c_int
+        L.orc_logical_state.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_logical_state.restype = ctypes.c_int
         L.orc_apply_gate.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip, dp]
         L.orc_apply_gate.restype = ctypes.c_int
         L.orc_time_blocks.argtypes = [ctypes.POINTER(_Job), ctypes.c_ulonglong, ctypes.c_int, ip]
@@ -116,17 +118,20 @@ def template_counts(d, gateset):
 
 
 def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=None,
-                   want_state=False, twirl=False):
+                   want_state=False, twirl=False, xbasis=False):
     """One Monte Carlo trajectory.
 
-    Returns dict(records=uint8[rounds, n_stab], final_bits=uint8[d*d],
+    twirl: Pauli-twirled over-rotations; xbasis: X-basis memory (logical |+>,
+    final X measurement of the data qubits).  Returns
+    dict(records=uint8[rounds, n_stab], final_bits=uint8[d*d],
     p1=float64[rounds, n_stab], state=complex128[2^(d*d)] or None) where
-    `state` is the data register just before the final Z measurement."""
+    `state` is the data register just before the final measurement."""
     n_stab, n_sites, _ = template_counts(d, gateset)
     job = _Job()
     job.d, job.gateset, job.rounds = d, gateset, rounds
     job.seed, job.p, job.zeta, job.eps = int(seed), float(p), float(zeta), float(eps)
     job.twirl = 1 if twirl else 0
+    job.xbasis = 1 if xbasis else 0
     keep = None
     if eps_site is not None:
         keep = np.ascontiguousarray(eps_site, dtype=np.float64)
@@ -150,7 +155,16 @@ def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=N
 def logical_zero(d, gateset=GATESET_CR):
     """Logical |0> of the data register after the noise-free projection."""
     out = np.zeros(2 << (d * d), dtype=np.float64)
-    if lib().orc_logical_zero(d, gateset, _ptr(out, ctypes.c_double)) != 0:
+    if lib().orc_logical_state(d, gateset, 0, _ptr(out, ctypes.c_double)) != 0:
+        raise RuntimeError("projection failed")
+    return out.view(np.complex128)
+
+
+def logical_plus(d, gateset=GATESET_CR):
+    """Logical |+> of the data register: |+...+> after the noise-free
+    projection onto the trivial syndromes."""
+    out = np.zeros(2 << (d * d), dtype=np.float64)
+    if lib().orc_logical_state(d, gateset, 1, _ptr(out, ctypes.c_double)) != 0:
         raise RuntimeError("projection failed")
     return out.view(np.complex128)
 

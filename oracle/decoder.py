@@ -1,5 +1,6 @@
 """Detection events and minimum-weight perfect-matching decoding of the logical
-Z readout (test infrastructure).
+readout of the memory experiment, Z basis (logical |0>) or X basis (logical
+|+>) (test infrastructure).
 
 Follows the decoding procedure of Sec. III.B: syndromes of adjacent rounds
 are XORed to locate flips, the flips are paired by minimum-weight perfect
@@ -31,14 +32,19 @@ import numpy as np
 from . import layout as _layout
 
 
-class ZDecoder:
-    def __init__(self, d, rounds, gateset):
+class MemoryDecoder:
+    """basis "Z": Z-check events, Z_L on the top row (logical |0> memory);
+    basis "X": X-check events, X_L on the first column (logical |+> memory,
+    final bits are X-basis outcomes).  The attribute names say z for the
+    checks of the decoded type."""
+
+    def __init__(self, d, rounds, gateset, basis="Z"):
         self.d, self.R = d, rounds
         stabs = _layout(d)
-        self.zidx = [i for i, (t, _) in enumerate(stabs) if t == "Z"]
+        self.zidx = [i for i, (t, _) in enumerate(stabs) if t == basis]
         self.zsup = [[q for q in stabs[i][1] if q] for i in self.zidx]
         self.r0 = np.array([(len(s) // 2) % 2 if gateset == 0 else 0 for s in self.zsup], dtype=np.uint8)
-        self.zl = set(range(1, d + 1))
+        self.zl = set(range(1, d + 1)) if basis == "Z" else set(1 + d * r for r in range(d))
         nz = len(self.zidx)
         B = "B"
         g = nx.Graph()
@@ -114,14 +120,18 @@ class ZDecoder:
         return p, w
 
     def failed(self, records, final_bits):
-        """1 if the corrected logical Z reads -1."""
+        """1 if the corrected logical reads -1."""
         det = self.detectors(records, final_bits)
         return self.logical_raw(final_bits) ^ self.correction(det)
 
 
-def logical_error_rate(d, gateset, records, final_bits):
-    """Fraction of trajectories whose corrected logical Z is -1."""
+ZDecoder = MemoryDecoder
+
+
+def logical_error_rate(d, gateset, records, final_bits, basis="Z"):
+    """Fraction of trajectories whose corrected logical (Z_L, or X_L for the
+    X-basis memory) is -1."""
     R = records.shape[1]
-    dec = ZDecoder(d, R, gateset)
+    dec = MemoryDecoder(d, R, gateset, basis)
     fails = [dec.failed(records[i], final_bits[i]) for i in range(records.shape[0])]
     return float(np.mean(fails)), int(np.sum(fails))

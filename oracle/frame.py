@@ -143,18 +143,21 @@ class FrameSampler:
         self.z[:, a] = 0
         return flip
 
-    def run(self, rounds, p):
-        """Returns (record flips [shots, rounds, n_stab], final data flips [shots, d*d])."""
+    def run(self, rounds, p, basis="Z"):
+        """Returns (record flips [shots, rounds, n_stab], final data flips
+        [shots, d*d]); basis "X": the data are measured in the X basis, which
+        flips where the frame has a Z component."""
         ns = len(self.stabs)
         rec = np.zeros((self.shots, rounds, ns), dtype=np.uint8)
         for r in range(rounds):
             for i, (typ, slots) in enumerate(self.stabs):
                 rec[:, r, i] = self.stabilizer(typ, slots, p)
-        final = self.x[:, : self.d * self.d].copy()
+        frame_bits = self.x if basis == "Z" else self.z
+        final = frame_bits[:, : self.d * self.d].copy()
         return rec, final
 
 
-def sample(d, gateset, rounds, p, shots, seed=0):
+def sample(d, gateset, rounds, p, shots, seed=0, basis="Z"):
     """Record flips and final-bit flips relative to the noiseless reference."""
     fs = FrameSampler(d, gateset, shots, np.random.default_rng(seed))
-    return fs.run(rounds, p)
+    return fs.run(rounds, p, basis)

@@ -335,6 +335,7 @@ struct Job {
   const double* eps_site;  // per gate site (length = sites per round) or null
   double eps;              // used for every site when eps_site is null
   int twirl;               // 1: Pauli-twirled over-rotations (see site_rot1)
+  int xbasis;              // 1: X-basis memory (logical |+>, final X measurement)
 };
 
 struct Ctx {
@@ -494,8 +495,13 @@ void apply_measure_clamp(double* p1) {
 // trivial outcome forced (Sec. III.B).  The global phase is fixed so that the
 // amplitude of |0...0> is real and positive.  Returns 0 or -1 if a forced
 // outcome has probability below the clamp.
+// Logical |0> (|+> for the X-basis memory): from |0...0> (|+...+>), run every
+// stabilizer circuit noise-free with its outcome forced to the trivial bit;
+// the global phase makes the amplitude of |0...0> real and positive.
 int prepare_logical_zero(State& s, const Job& job, const std::vector<Stab>& stabs) {
   const int d = job.d, anc = d * d;
+  if (job.xbasis)
+    for (int q = 0; q < d * d; ++q) hadamard(s, q);
   Ctx cx{&job, 0, 0, false, 0};
   for (const Stab& st : stabs) {
     run_stabilizer_gates(s, cx, st, anc);
@@ -551,7 +557,10 @@ int run_trajectory(const Job& job, uint64_t t, const Output& out) {
       out.final_state[2 * x + 1] = s.a[x].imag();
     }
   }
-  // Final Z measurement of every data qubit, highest label first.
+  // Final Z (X-basis memory: X) measurement of every data qubit, highest label
+  // first; an X measurement is a Z measurement after a Hadamard.
+  if (job.xbasis)
+    for (int q = 0; q < nd; ++q) hadamard(s, q);
   for (int q = nd; q >= 1; --q) {
     double S0, S1;
     half_norms(s, q - 1, &S0, &S1);
@@ -600,6 +609,8 @@ typedef struct {
   double zeta;
   const double* eps_site;
   double eps;
+  int xbasis;  // 1: X-basis memory
+  int pad_;
 } orc_job;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
@@ -631,15 +642,16 @@ int orc_template_counts(int d, int gateset, int* n_stab, int* n_sites, int* n_dr
 int orc_run_trajectory(const orc_job* j, unsigned long long t, uint8_t* records,
                        uint8_t* final_bits, double* p1_trace, double* final_state) {
   if (!j || j->d < 2 || j->d > 5 || j->rounds < 0) return -1;
-  Job job{j->d, j->gateset, j->rounds, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl};
+  Job job{j->d, j->gateset, j->rounds, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl, j->xbasis};
   Output out{records, final_bits, p1_trace, final_state};
   return run_trajectory(job, t, out);
 }
 
-// Logical |0> on the data register (ancilla 0), 2^(d*d) interleaved complex.
-int orc_logical_zero(int d, int gateset, double* out) {
+// Logical |0> (xbasis = 1: logical |+>) on the data register (ancilla 0),
+// 2^(d*d) interleaved complex.
+int orc_logical_state(int d, int gateset, int xbasis, double* out) {
   if (d < 2 || d > 5) return -1;
-  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0, 0};
+  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0, 0, xbasis};
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);
   if (prepare_logical_zero(s, job, stabs) != 0) return -1;
@@ -674,7 +686,7 @@ int orc_apply_gate(double* state, int n, int k, const int* qubits, const double*
 // the corresponding part of a trajectory.
 double orc_time_blocks(const orc_job* j, unsigned long long t, int n_blocks, int* threads) {
   if (!j || j->d < 2 || j->d > 5 || n_blocks < 1) return -1.0;
-  Job job{j->d, j->gateset, 1, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl};
+  Job job{j->d, j->gateset, 1, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl, j->xbasis};
   const int d = job.d, anc = d * d;
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);

@@ -325,3 +325,73 @@ def test_twirled_textbook_first_check_flips_with_sin2_eps():
                                           twirl=True)["records"][0, 0]) for t in range(n))
     q = np.sin(eps) ** 2
     assert abs(flips / n - q) < 4 * np.sqrt(q * (1 - q) / n)
+
+
+# ---- X-basis memory ---------------------------------------------------------
+
+def closed_form_logical_plus(d):
+    """Uniform superposition over the data strings with even parity on every
+    Z check: |+...+> projected onto the trivial Z syndromes."""
+    n = d * d
+    zs = [[q - 1 for q in s if q] for t, s in oracle.layout(d) if t == "Z"]
+    idx = np.arange(1 << n)
+    ok = np.ones(1 << n, dtype=bool)
+    for sup in zs:
+        par = np.zeros(1 << n, dtype=np.int64)
+        for q in sup:
+            par ^= (idx >> q) & 1
+        ok &= par == 0
+    v = ok.astype(np.complex128)
+    return v / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+@pytest.mark.parametrize("d", [2, 3])
+def test_logical_plus_closed_form(d, gateset):
+    ref = closed_form_logical_plus(d)
+    assert int(np.count_nonzero(ref)) == 1 << (d * d - (d * d - 1) // 2)
+    assert np.allclose(oracle.logical_plus(d, gateset), ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+def test_noiseless_x_memory_is_trivial(gateset):
+    """Logical |+>: every X check reads its trivial bit from round 1, every
+    Z check stays constant after round 1, and the final X outcomes have even
+    parity on every X check and on X_L (the first column)."""
+    d, R = 3, 3
+    for t in range(4):
+        o = oracle.run_trajectory(d, gateset, R, seed=2, t=t, p=0.0, xbasis=True)
+        r0 = trivial_bits(d, gateset)
+        layout = oracle.layout(d)
+        xi = [i for i, (typ, _) in enumerate(layout) if typ == "X"]
+        zi = [i for i, (typ, _) in enumerate(layout) if typ == "Z"]
+        assert np.array_equal(o["records"][:, xi], np.broadcast_to(r0[xi], (R, len(xi))))
+        assert np.array_equal(o["records"][1:, zi], np.broadcast_to(o["records"][0, zi], (R - 1, len(zi))))
+        fb = o["final_bits"]
+        for i in xi:
+            assert sum(int(fb[q - 1]) for q in layout[i][1] if q) % 2 == 0
+        assert sum(int(fb[d * r]) for r in range(d)) % 2 == 0
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+def test_x_memory_pauli_only_matches_frame_sampler(gateset):
+    """X-basis memory with Pauli-only noise: X-check detector rates and the X_L
+    flip rate (final X outcomes on the first column) agree with the
+    Pauli-frame sampler read out in the X basis."""
+    d, R, N, p = 3, 3, 2500, 0.01
+    layout = oracle.layout(d)
+    xi = [i for i, (typ, _) in enumerate(layout) if typ == "X"]
+    tb = trivial_bits(d, gateset)
+    recs, xl = [], []
+    for t in range(N):
+        r = oracle.run_trajectory(d, gateset, R, seed=13, t=t, p=p, xbasis=True)
+        recs.append((r["records"] ^ tb)[:, xi])
+        xl.append(sum(int(r["final_bits"][d * k]) for k in range(d)) % 2)
+    recs = np.array(recs)
+    frec, ffin = frame.sample(d, gateset, R, p, 200000, seed=3, basis="X")
+    a = _detectors(recs).mean(0)
+    b = _detectors(frec[:, :, xi]).mean(0)
+    sig = np.sqrt(np.maximum(b * (1 - b), 1.0 / N) / N)
+    assert np.max(np.abs((a - b) / sig)) < 4.0
+    xl_f = np.bitwise_xor.reduce(ffin[:, 0:d * d:d], axis=1).mean()
+    assert abs(np.mean(xl) - xl_f) < 4.0 * np.sqrt(max(xl_f * (1 - xl_f), 1.0 / N) / N)
