@@ -72,6 +72,12 @@ typedef enum {
                           passes, decisions, final measurement, record copy)
                           in a HIP graph once and replay it per trajectory;
                           results are identical to the stream launches */
+#define SV_RUN_XBASIS 4 /* X-basis memory: logical |+> instead of |0> (the
+                           2^(n - n_z) strings with even parity on every Z
+                           check, equal amplitudes), and the data qubits
+                           measured in the X basis at the end (final_bits =
+                           X outcomes, 1 for eigenvalue -1); final_states is
+                           the register before that measurement */
 #define SV_RUN_TWIRL 2 /* Pauli-twirled over-rotations: every rotation turns by
                           its base angle only, and one draw right after it
                           applies its generator (Rx: X, Rz: Z, Rzx: Z x X, the
@@ -170,8 +176,9 @@ typedef struct sv_job {
   int rounds;          /* noisy rounds, >= 1 */
   int dtype;           /* sv_dtype of the state */
   int n_traj;          /* trajectories */
-  int flags;           /* SV_RUN_GRAPH | SV_RUN_TWIRL (sv_run_rounds only;
-                          with SV_RUN_GRAPH final_states must be NULL) */
+  int flags;           /* SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS
+                          (sv_run_rounds only; with SV_RUN_GRAPH
+                          final_states must be NULL) */
   uint64_t traj0;      /* first trajectory index (draw stream id) */
   uint64_t seed;       /* Philox key */
   double p;            /* depolarizing probability, [0, 1] */
@@ -220,6 +227,11 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res);
  * (optional) = the matching's total weight (-1 if undecoded).  SV_ENUMERIC if
  * any trajectory has more than 22 events (the others are still decoded). */
 sv_status sv_decode_z(int d, int gateset, int rounds, int n_traj, const uint8_t* records,
+                      const uint8_t* final_bits, uint8_t* failed, uint8_t* ambiguous, int* weight);
+/* The same for the X-basis memory (SV_RUN_XBASIS): X-check events, final_bits
+ * are X outcomes, failed = 1 if the corrected X_L (X on the first column,
+ * labels 1, d+1, ..., (d-1)d+1) reads -1. */
+sv_status sv_decode_x(int d, int gateset, int rounds, int n_traj, const uint8_t* records,
                       const uint8_t* final_bits, uint8_t* failed, uint8_t* ambiguous, int* weight);
 
 /* Launch parameters of the trajectory engine for (d, dtype) on the current

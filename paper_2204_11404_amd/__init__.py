@@ -130,6 +130,9 @@ _SIGS = {
     "sv_decode_z": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "sv_decode_x": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
     "sv_tuning_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "sv_tuning_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "sv_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -305,18 +308,20 @@ class State:
 
 SV_RUN_GRAPH = 1
 SV_RUN_TWIRL = 2
+SV_RUN_XBASIS = 4
 
 
 def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0,
                dtype="c128", traj0=0, want_p1=False, want_states=False, stream=None, graph=False,
-               twirl=False):
+               twirl=False, xbasis=False):
     """sv_run_rounds: returns dict(records[n_traj, rounds, n_stab], final_bits[n_traj, d*d],
     p1 or None, states or None, gpu_ms, pass_ms, passes_per_round)."""
     n_stab, n_sites, _ = template_info(d, gateset)
     job = Job()
     job.d, job.gateset, job.rounds = d, _GATESETS[gateset], rounds
     job.dtype, job.n_traj = _DTYPES[dtype], n_traj
-    job.flags = (SV_RUN_GRAPH if graph else 0) | (SV_RUN_TWIRL if twirl else 0)
+    job.flags = ((SV_RUN_GRAPH if graph else 0) | (SV_RUN_TWIRL if twirl else 0)
+                 | (SV_RUN_XBASIS if xbasis else 0))
     job.traj0, job.seed, job.p, job.eps, job.zeta = int(traj0), int(seed), float(p), float(eps), float(zeta)
     job.hip_stream = _stream_ptr(stream)
     keep = None
@@ -484,10 +489,16 @@ def tuning_load(path):
     _check(lib().sv_tuning_load(os.fsencode(path)))
 
 
-def decode_z(d, gateset, records, final_bits):
-    """sv_decode_z: records [n_traj, rounds, d*d-1] raw bits, final_bits
-    [n_traj, d*d].  Returns dict(failed, ambiguous, weight) arrays; failed is
-    2 for trajectories with too many detection events (then `overflow` > 0)."""
+def decode_x(d, gateset, records, final_bits):
+    """sv_decode_x: the X-basis memory's records and final X outcomes."""
+    return decode_z(d, gateset, records, final_bits, basis="X")
+
+
+def decode_z(d, gateset, records, final_bits, basis="Z"):
+    """sv_decode_z (basis "X": sv_decode_x): records [n_traj, rounds, d*d-1]
+    raw bits, final_bits [n_traj, d*d].  Returns dict(failed, ambiguous,
+    weight) arrays; failed is 2 for trajectories with too many detection
+    events (then `overflow` > 0)."""
     rec = np.ascontiguousarray(records, dtype=np.uint8)
     fb = np.ascontiguousarray(final_bits, dtype=np.uint8)
     n_traj, rounds, n_stab = rec.shape
@@ -496,8 +507,9 @@ def decode_z(d, gateset, records, final_bits):
     failed = np.zeros(n_traj, dtype=np.uint8)
     amb = np.zeros(n_traj, dtype=np.uint8)
     w = np.zeros(n_traj, dtype=np.int32)
-    st = lib().sv_decode_z(d, _GATESETS[gateset], rounds, n_traj, rec.ctypes.data, fb.ctypes.data,
-                           failed.ctypes.data, amb.ctypes.data, w.ctypes.data)
+    fn = lib().sv_decode_z if basis == "Z" else lib().sv_decode_x
+    st = fn(d, _GATESETS[gateset], rounds, n_traj, rec.ctypes.data, fb.ctypes.data,
+            failed.ctypes.data, amb.ctypes.data, w.ctypes.data)
     if st not in (SV_OK, SV_ENUMERIC):
         _check(st)
     return dict(failed=failed, ambiguous=amb, weight=w, overflow=int(np.sum(failed == 2)))

@@ -1,12 +1,15 @@
-// Decoding of the Z-basis memory experiment (Sec. III.B): syndromes of
-// consecutive rounds are compared to find detection events, the events are
-// paired by a minimum-weight perfect matching, and the logical Z is read from
-// the final Z measurement of the data qubits after the recovery.
+// Decoding of the memory experiment (Sec. III.B): syndromes of consecutive
+// rounds are compared to find detection events, the events are paired by a
+// minimum-weight perfect matching, and the logical is read from the final
+// measurement of the data qubits after the recovery.  Z basis (logical |0>):
+// Z checks and Z_L; X basis (logical |+>, X-basis final outcomes): the same
+// construction with the X checks and X_L.
 //
 // Host code (no kernels).  Included by qecsv.hip after the layout builder.
 //
-// Graph: one node per (Z check, layer), layers 0..R-1 for the rounds and R
-// for the Z checks recomputed from the final data bits, plus one boundary
+// Graph (Z basis; the X basis swaps the check type): one node per (Z check,
+// layer), layers 0..R-1 for the rounds and R for the Z checks recomputed
+// from the final data bits, plus one boundary
 // node.  A data qubit in two Z checks joins them within a layer, a data qubit
 // in one Z check joins it to the boundary, consecutive layers of a check are
 // joined (measurement errors).  The checks of a round are measured one after
@@ -36,18 +39,23 @@ struct ZGraph {
   std::vector<uint8_t> r0;             // trivial raw bit of each Z check
   std::vector<int> dist;               // [nodes][nodes]
   std::vector<uint8_t> par;            // [nodes][nodes] parity set: bit v = parity v reachable
+  int basis = 1;                       // type of the decoded checks (1 = Z)
+  bool on_logical(int label) const { return basis == 1 ? label <= d : (label - 1) % d == 0; }
 };
 
 // Builds the graph and all-pairs shortest-path lengths and parity sets (BFS:
 // unit weights, the parity set of a node at distance k is the union over its
 // neighbours at distance k - 1 of their sets shifted by the edge's flip set).
-ZGraph make_zgraph(int d, int rounds, int gateset) {
+// basis 1: Z checks and Z_L = Z_1 ... Z_d (top row); basis 0: X checks and
+// X_L on the first column (labels 1, d + 1, ...), for the X-basis memory.
+ZGraph make_zgraph(int d, int rounds, int gateset, int basis) {
   ZGraph g;
   g.d = d;
   g.R = rounds;
+  g.basis = basis;
   const std::vector<Stab> st = code_layout(d);
   for (int i = 0; i < (int)st.size(); ++i) {
-    if (st[i].type != 1) continue;
+    if (st[i].type != basis) continue;
     std::vector<int> sup;
     for (int q : st[i].slot)
       if (q) sup.push_back(q);
@@ -70,7 +78,7 @@ ZGraph make_zgraph(int d, int rounds, int gateset) {
     for (int q : g.zsup[k]) owners[q].push_back(k);
   for (int r = 0; r <= rounds; ++r) {
     for (const auto& kv : owners) {
-      const int flip = kv.first <= d ? 1 : 0;
+      const int flip = g.on_logical(kv.first) ? 1 : 0;
       if (kv.second.size() == 2) {
         add(kv.second[0] + g.nz * r, kv.second[1] + g.nz * r, flip);
         // owners are listed in measurement order
@@ -143,7 +151,8 @@ DecodeOut decode_one(const ZGraph& g, int n_stab, const uint8_t* rec, const uint
       prev[k] = s;
     }
   int raw = 0;
-  for (int q = 1; q <= g.d; ++q) raw ^= bits[q - 1];
+  for (int q = 1; q <= g.d * g.d; ++q)
+    if (g.on_logical(q)) raw ^= bits[q - 1];
   const int ne = (int)ev.size();
   if (ne > kDecodeMaxEvents) {
     out.ok = 0;
@@ -190,17 +199,13 @@ DecodeOut decode_one(const ZGraph& g, int n_stab, const uint8_t* rec, const uint
   return out;
 }
 
-}  // namespace
-
-extern "C" {
-
-sv_status sv_decode_z(int d, int gateset, int rounds, int n_traj, const uint8_t* records,
-                      const uint8_t* final_bits, uint8_t* failed, uint8_t* ambiguous, int* weight) {
+sv_status decode_memory(int basis, int d, int gateset, int rounds, int n_traj, const uint8_t* records,
+                        const uint8_t* final_bits, uint8_t* failed, uint8_t* ambiguous, int* weight) {
   if (d < 2 || d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", d);
   if (gateset != SV_GATESET_CR && gateset != SV_GATESET_TEXTBOOK) return fail(SV_EINVAL, "bad gateset");
   if (rounds < 1 || n_traj < 0) return fail(SV_EINVAL, "bad rounds / n_traj");
   if (n_traj > 0 && (!records || !final_bits || !failed)) return fail(SV_EINVAL, "NULL buffer");
-  const ZGraph g = make_zgraph(d, rounds, gateset);
+  const ZGraph g = make_zgraph(d, rounds, gateset, basis);
   const int n_stab = d * d - 1, n = d * d;
   std::atomic<int> next{0}, overflow{0};
   auto work = [&] {
@@ -225,6 +230,20 @@ sv_status sv_decode_z(int d, int gateset, int rounds, int n_traj, const uint8_t*
   if (overflow.load()) return fail(SV_ENUMERIC, "%d trajectories with more than %d detection events", overflow.load(),
                                    kDecodeMaxEvents);
   return SV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sv_status sv_decode_z(int d, int gateset, int rounds, int n_traj, const uint8_t* records,
+                      const uint8_t* final_bits, uint8_t* failed, uint8_t* ambiguous, int* weight) {
+  return decode_memory(1, d, gateset, rounds, n_traj, records, final_bits, failed, ambiguous, weight);
+}
+
+sv_status sv_decode_x(int d, int gateset, int rounds, int n_traj, const uint8_t* records,
+                      const uint8_t* final_bits, uint8_t* failed, uint8_t* ambiguous, int* weight) {
+  return decode_memory(0, d, gateset, rounds, n_traj, records, final_bits, failed, ambiguous, weight);
 }
 
 }  // extern "C"

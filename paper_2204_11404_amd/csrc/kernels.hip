@@ -471,11 +471,17 @@ __global__ __launch_bounds__(256) void k_upass(
   C2<T> o[16];
   if (active) {
     if constexpr (AK == U_INIT) {
-      // g is in the X-stabilizer orbit of 0 iff its reduction against the
-      // echelon basis vanishes; the reduction is linear, so it splits into
-      // the thread's part and the slot's part
+      // logical |0>: g is in the X-stabilizer orbit of 0 iff its reduction
+      // against the echelon basis vanishes; logical |+>: g has even parity on
+      // every Z check.  Both tests are linear in g, so they split into the
+      // thread's part and the slot's part.
       const T amp = (T)jc->amp0;
       auto reduce = [&](uint32_t x) {
+        if (jc->init_plus) {
+          uint32_t syn = 0;
+          for (int i = 0; i < jc->n_zc; ++i) syn |= (uint32_t)(__popc(x & jc->zc_mask[i]) & 1) << i;
+          return syn;
+        }
         for (int i = 0; i < jc->n_x; ++i)
           if (x & jc->span_piv[i]) x ^= jc->span_vec[i];
         return x;
@@ -999,6 +1005,43 @@ __global__ __launch_bounds__(256) void k_fused(T* __restrict__ st, uint64_t n_gr
     }
     st2(st, off[r], C2<T>{re, im});
   }
+}
+
+// Walsh-Hadamard transform over K qubits (bits q[0..K)) of the register, one
+// group of 2^K amplitudes per thread, times `scale` (the X-basis readout
+// applies H to every data qubit as ceil(n / 5) such passes).
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_wht_group(T* __restrict__ st, uint64_t n_groups, int q0,
+                                                   int q1, int q2, int q3, int q4, double scale) {
+  constexpr int N = 1 << K;
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_groups) return;
+  const int qs[5] = {q0, q1, q2, q3, q4};
+  int sorted[5];
+  for (int j = 0; j < K; ++j) sorted[j] = qs[j];
+  for (int a = 1; a < K; ++a)
+    for (int b = a; b > 0 && sorted[b - 1] > sorted[b]; --b) {
+      const int t = sorted[b];
+      sorted[b] = sorted[b - 1];
+      sorted[b - 1] = t;
+    }
+  uint64_t base = g;
+  for (int j = 0; j < K; ++j) base = insert_zero(base, sorted[j]);
+  uint64_t off[N];
+  C2<T> v[N];
+#pragma unroll
+  for (int x = 0; x < N; ++x) {
+    uint64_t o = base;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if ((x >> j) & 1) o |= 1ull << qs[j];
+    off[x] = o;
+    v[x] = ld2(st, o);
+  }
+  wht<T, K>(v);
+#pragma unroll
+  for (int x = 0; x < N; ++x)
+    st2(st, off[x], C2<T>{(T)((double)v[x].re * scale), (T)((double)v[x].im * scale)});
 }
 
 // S0 / S1 over bit q: per-workgroup partial sums (fixed order).

@@ -406,9 +406,11 @@ struct JobConst {
   uint32_t span_piv[16];   // pivot bit of each basis vector
   double zz[2 * 64];       // exp(-i zeta (|E| - 2k)), k = 0..|E|
   int use_zz;
-  int pad;
+  int init_plus;           // 1: the first pass writes logical |+> (X-basis memory)
   // L consecutive ZZ layers: exp(-i zeta (L |E| - 2K)), K = 0..L|E|, L = 1..kChainMax
   double zzl[4][2 * (4 * 40 + 1)];
+  int n_zc;                // Z checks
+  uint32_t zc_mask[16];    // data bits of each Z check
 };
 
 // Outcome of one pass unit (a single check, or a chain of Z checks: bit i of

@@ -243,10 +243,18 @@ Template build_template(int d, int gateset, bool twirl = false) {
 }
 
 // ------------------------------------------------------- job constants --
-JobConst make_job_const(int d, double zeta) {
+JobConst make_job_const(int d, double zeta, bool init_plus = false) {
   JobConst jc{};
   jc.d = d;
   jc.n = d * d;
+  jc.init_plus = init_plus ? 1 : 0;
+  for (const Stab& st : code_layout(d)) {
+    if (st.type != 1) continue;
+    uint32_t m = 0;
+    for (int q : st.slot)
+      if (q) m |= 1u << (q - 1);
+    jc.zc_mask[jc.n_zc++] = m;
+  }
   // reduced echelon basis of the X-stabilizer supports over GF(2)
   std::vector<uint32_t> basis;
   for (const Stab& st : code_layout(d)) {
@@ -269,7 +277,9 @@ JobConst make_job_const(int d, double zeta) {
     jc.span_vec[i] = basis[i];
     jc.span_piv[i] = 1u << (31 - __builtin_clz(basis[i]));
   }
-  jc.amp0 = std::pow(2.0, -0.5 * jc.n_x);
+  // logical |0>: 2^n_x strings of the X-stabilizer orbit of 0; logical |+>:
+  // the 2^(n - n_z) strings with even parity on every Z check
+  jc.amp0 = init_plus ? std::pow(2.0, -0.5 * (d * d - jc.n_zc)) : std::pow(2.0, -0.5 * jc.n_x);
   uint32_t hm = 0, vm = 0;
   int ne = 0;
   for (int i = 0; i < d * d; ++i) {
@@ -596,6 +606,24 @@ PassDesc make_pass(int n, int tb_max, const TBlock* A, const TBlock* B, int ia, 
   return pd;
 }
 
+// H on every one of the n register qubits, in groups of up to five, scaled
+// by 2^(-n/2) in the last group.
+template <typename T>
+void launch_wht_all(hipStream_t s, T* st, int n) {
+  for (int q0 = 0; q0 < n; q0 += 5) {
+    const int K = std::min(5, n - q0);
+    const double scale = (q0 + K == n) ? std::pow(2.0, -0.5 * n) : 1.0;
+    const uint64_t groups = 1ull << (n - K);
+    const dim3 grid((unsigned)((groups + 255) / 256)), block(256);
+    const int q[5] = {q0, q0 + 1, q0 + 2, q0 + 3, q0 + 4};
+#define QEC_WHT(KK)                                                                              \
+  if (K == KK) hipLaunchKernelGGL((k_wht_group<T, KK>), grid, block, 0, s, st, groups, q[0], q[1], \
+                                  q[2], q[3], q[4], scale);
+    QEC_WHT(1) QEC_WHT(2) QEC_WHT(3) QEC_WHT(4) QEC_WHT(5)
+#undef QEC_WHT
+  }
+}
+
 // Launches the pass kernel instantiated for the descriptor's unit kinds.
 template <typename T>
 sv_status launch_upass(const UnitPass& h, dim3 g, dim3 b, hipStream_t s, T* st, const UnitPass* pd,
@@ -691,7 +719,8 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   HIP_OK(M.alloc(&drt, rt_per_traj * chunk));
 
   const std::vector<UnitPass> pds = make_unit_passes(n, tb, tp, units);
-  const JobConst jc = make_job_const(d, job->zeta);
+  const bool xbasis = (job->flags & SV_RUN_XBASIS) != 0;
+  const JobConst jc = make_job_const(d, job->zeta, xbasis);
   std::vector<double> eps(std::max(1, tp.n_sites), job->eps);
   if (job->eps_site)
     for (int i = 0; i < tp.n_sites; ++i) eps[i] = job->eps_site[i];
@@ -765,13 +794,17 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
     HIP_OK(hipGetLastError());
     return SV_OK;
   };
-  // final Z measurement of the data register (draw stream t, or *tptr)
+  // final Z measurement of the data register (draw stream t, or *tptr); in
+  // the X basis a Walsh-Hadamard transform of the whole register first, which
+  // removes the Pauli-X frame from the outcome probabilities
   auto traj_final = [&](hipStream_t q, uint8_t* bits, uint64_t t, const uint64_t* tptr) {
+    if (xbasis) launch_wht_all<T>(q, st, n);
     hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb)), dim3(256), 0, q, st, cb, dsums,
                        (size_t)0);
     hipLaunchKernelGGL(k_final_measure<T>, dim3(1), dim3(1024), 0, q, st, n, cb, dsums, job->seed, t,
                        (uint64_t)R * (uint64_t)draws_round, bits, (size_t)0, (const uint64_t*)nullptr,
-                       tptr, (const int*)nullptr, (uint64_t)0, (const Decision*)&ddec[per_units],
+                       tptr, (const int*)nullptr, (uint64_t)0,
+                       xbasis ? (const Decision*)nullptr : (const Decision*)&ddec[per_units],
                        (size_t)0);
   };
   double pass_ms_graph = -1.0;
@@ -1635,7 +1668,8 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
   if (job->rounds < 1 || job->rounds > 100000) return fail(SV_EINVAL, "rounds=%d", job->rounds);
   if (job->dtype != SV_C64 && job->dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
   if (job->n_traj < 0) return fail(SV_EINVAL, "n_traj < 0");
-  if (job->flags & ~(SV_RUN_GRAPH | SV_RUN_TWIRL)) return fail(SV_EINVAL, "unknown flags 0x%x", job->flags);
+  if (job->flags & ~(SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS))
+    return fail(SV_EINVAL, "unknown flags 0x%x", job->flags);
   if (!(job->p >= 0.0 && job->p <= 1.0)) return fail(SV_EINVAL, "p out of [0, 1]");
   if (!std::isfinite(job->eps) || !std::isfinite(job->zeta)) return fail(SV_EINVAL, "non-finite eps/zeta");
   if (!res->records || !res->final_bits) return fail(SV_EINVAL, "records and final_bits are required");

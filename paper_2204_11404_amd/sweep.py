@@ -24,17 +24,20 @@ from . import decode_z, run_rounds
 
 
 def run_point(d, p, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, zeta=0.0,
-              chunk=1000, log=None):
+              chunk=1000, log=None, twirl=False, basis="Z"):
+    """twirl: Pauli-twirled over-rotations instead of coherent ones; basis
+    "X": the X-basis memory (logical |+>, X_L decoded from X checks)."""
     eps = c * math.sqrt(p)
     fails = amb = over = 0
     gpu_ms = dec_s = 0.0
     t0 = time.perf_counter()
     for first in range(0, n_traj, chunk):
         n = min(chunk, n_traj - first)
-        r = run_rounds(d, gateset, rounds, n, seed, p, eps=eps, zeta=zeta, dtype=dtype, traj0=first)
+        r = run_rounds(d, gateset, rounds, n, seed, p, eps=eps, zeta=zeta, dtype=dtype, traj0=first,
+                       twirl=twirl, xbasis=(basis == "X"))
         gpu_ms += r["gpu_ms"]
         t1 = time.perf_counter()
-        out = decode_z(d, gateset, r["records"], r["final_bits"])
+        out = decode_z(d, gateset, r["records"], r["final_bits"], basis=basis)
         dec_s += time.perf_counter() - t1
         fails += int(np.sum(out["failed"] == 1))
         amb += int(np.sum(out["ambiguous"]))
@@ -44,6 +47,7 @@ def run_point(d, p, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, z
     n_ok = n_traj - over
     pl = fails / n_ok if n_ok else float("nan")
     return {"d": d, "p": p, "c": c, "eps": eps, "rounds": rounds, "dtype": dtype,
+            "twirl": twirl, "basis": basis,
             "trajectories": n_traj, "failures": fails, "p_L": pl,
             "p_L_err": math.sqrt(pl * (1 - pl) / n_ok) if n_ok else float("nan"),
             "ambiguous": amb, "undecoded": over, "gpu_s": gpu_ms * 1e-3, "decode_s": dec_s,
@@ -93,15 +97,16 @@ def fit_effective_model(points, A, xi):
     return {"B": out_b, "alpha": alpha, "sigma_alpha": float(1.0 / math.sqrt(np.sum(wv * x * x)))}
 
 
-def sweep(d, ps, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, zeta=0.0, log=None):
+def sweep(d, ps, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, zeta=0.0, log=None,
+          twirl=False, basis="Z"):
     """n_traj: one count for every p, or a list with one count per p."""
     counts = list(n_traj) if isinstance(n_traj, (list, tuple)) else [n_traj]
     if len(counts) == 1:
         counts = counts * len(ps)
     if len(counts) != len(ps):
         raise ValueError("give one trajectory count, or one per p")
-    points = [run_point(d, p, c, n, rounds, gateset, dtype, seed, zeta, log=log)
-              for p, n in zip(ps, counts)]
+    points = [run_point(d, p, c, n, rounds, gateset, dtype, seed, zeta, log=log, twirl=twirl,
+                        basis=basis) for p, n in zip(ps, counts)]
     return {"points": points, "fit": fit_power_law(points)}
 
 
@@ -117,9 +122,11 @@ def main():
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
     ap.add_argument("--seed", type=int, default=2022)
     ap.add_argument("--zeta", type=float, default=0.0)
+    ap.add_argument("--twirl", action="store_true", help="Pauli-twirled over-rotations")
+    ap.add_argument("--basis", default="Z", choices=["Z", "X"], help="memory basis")
     a = ap.parse_args()
     res = sweep(a.d, a.p, a.c, a.traj, a.rounds, a.gateset, a.dtype, a.seed, a.zeta,
-                log=lambda m: print(m, flush=True))
+                log=lambda m: print(m, flush=True), twirl=a.twirl, basis=a.basis)
     print(json.dumps(res), flush=True)
 
 

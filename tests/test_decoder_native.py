@@ -40,6 +40,24 @@ def test_matches_oracle_decoder(d, p, shots, gateset):
     assert shots - n_amb >= shots // 2
 
 
+@pytest.mark.parametrize("gateset", [0, 1])
+def test_x_basis_matches_oracle_decoder(gateset):
+    d, R, p, shots = 3, 4, 2e-2, 400
+    flips, fin = frame.sample(d, gateset, R, p, shots, seed=21, basis="X")
+    rec = flips ^ _r0(d, gateset)
+    out = qs.decode_x(d, "cr" if gateset == 0 else "textbook", rec, fin)
+    dec = decoder.MemoryDecoder(d, R, gateset, basis="X")
+    n_amb = 0
+    for i in range(shots):
+        par, w = dec.matching(dec.detectors(rec[i], fin[i]))
+        assert out["weight"][i] == w, f"trajectory {i}"
+        if out["ambiguous"][i]:
+            n_amb += 1
+            continue
+        assert out["failed"][i] == dec.logical_raw(fin[i]) ^ par, f"trajectory {i}"
+    assert shots - n_amb >= shots // 2
+
+
 def test_no_events_reads_the_raw_logical():
     d, R = 3, 2
     rec = np.broadcast_to(_r0(d, 0), (2, R, d * d - 1)).copy()

@@ -23,14 +23,15 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "d5_cr_oracle.npz")
 
 
 def _compare(d, gateset, R, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0, dtype="c128",
-             traj0=0, atol=1e-10, twirl=False):
+             traj0=0, atol=1e-10, twirl=False, xbasis=False):
     print(f"case rounds d={d} {gateset} R={R} n={n_traj} p={p} eps={eps} zeta={zeta} {dtype}"
-          f" twirl={twirl}", flush=True)
+          f" twirl={twirl} xbasis={xbasis}", flush=True)
     g = qs.run_rounds(d, gateset, R, n_traj, seed, p, eps=eps, eps_site=eps_site, zeta=zeta,
-                      dtype=dtype, traj0=traj0, want_p1=True, want_states=True, twirl=twirl)
+                      dtype=dtype, traj0=traj0, want_p1=True, want_states=True, twirl=twirl,
+                      xbasis=xbasis)
     for i in range(n_traj):
         o = oracle.run_trajectory(d, GS[gateset], R, seed, traj0 + i, p, eps=eps, eps_site=eps_site,
-                                  zeta=zeta, want_state=True, twirl=twirl)
+                                  zeta=zeta, want_state=True, twirl=twirl, xbasis=xbasis)
         assert np.array_equal(g["records"][i], o["records"]), f"trajectory {i}"
         assert np.array_equal(g["final_bits"][i], o["final_bits"]), f"trajectory {i}"
         assert np.max(np.abs(g["p1"][i] - o["p1"])) < atol
@@ -178,3 +179,27 @@ def test_twirled_over_rotation_parity(gateset, d):
     eps = workloads.eps_sites(n_sites, (0.1, 0.5), 5)
     _compare(d, gateset, 2, 3 if d == 4 else 12, seed=41, p=0.01, eps_site=eps, zeta=0.01, twirl=True)
 
+
+@pytest.mark.parametrize("gateset,d,dtype", [("cr", 3, "c128"), ("textbook", 3, "c128"),
+                                             ("cr", 4, "c128"), ("cr", 3, "c64")])
+def test_x_basis_memory_parity(gateset, d, dtype):
+    """SV_RUN_XBASIS: logical |+> written by the first pass, the data measured
+    in the X basis after a Walsh-Hadamard transform of the register."""
+    n_sites = oracle.template_counts(d, GS[gateset])[1]
+    eps = workloads.eps_sites(n_sites, (0.0, 0.05), 12)
+    _compare(d, gateset, 2, 3 if d == 4 else 12, seed=12, p=0.02, eps_site=eps, zeta=0.01,
+             dtype=dtype, atol=1e-10 if dtype == "c128" else 1e-5, xbasis=True)
+
+
+def test_x_basis_noiseless_reads_trivial_logical():
+    g = qs.run_rounds(3, "cr", 3, 8, 0, 0.0, xbasis=True)
+    d = 3
+    xl = np.bitwise_xor.reduce(g["final_bits"][:, 0:d * d:d], axis=1)
+    assert not xl.any()
+    assert not qs.decode_x(d, "cr", g["records"], g["final_bits"])["failed"].any()
+
+
+def test_x_basis_twirled_parity():
+    n_sites = oracle.template_counts(3, oracle.GATESET_CR)[1]
+    eps = workloads.eps_sites(n_sites, (0.1, 0.4), 13)
+    _compare(3, "cr", 2, 10, seed=13, p=0.01, eps_site=eps, twirl=True, xbasis=True)
