@@ -78,6 +78,10 @@ typedef enum {
                            measured in the X basis at the end (final_bits =
                            X outcomes, 1 for eigenvalue -1); final_states is
                            the register before that measurement */
+#define SV_RUN_VIRTUAL_Z 8 /* the Rz(pi/2) restores after cross-resonance Z
+                              checks are virtual Z gates without
+                              over-rotation (their sites keep their place in
+                              eps_site but are not used) */
 #define SV_RUN_TWIRL 2 /* Pauli-twirled over-rotations: every rotation turns by
                           its base angle only, and one draw right after it
                           applies its generator (Rx: X, Rz: Z, Rzx: Z x X, the
@@ -176,9 +180,9 @@ typedef struct sv_job {
   int rounds;          /* noisy rounds, >= 1 */
   int dtype;           /* sv_dtype of the state */
   int n_traj;          /* trajectories */
-  int flags;           /* SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS
-                          (sv_run_rounds only; with SV_RUN_GRAPH
-                          final_states must be NULL) */
+  int flags;           /* SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS |
+                          SV_RUN_VIRTUAL_Z (sv_run_rounds only; with
+                          SV_RUN_GRAPH final_states must be NULL) */
   uint64_t traj0;      /* first trajectory index (draw stream id) */
   uint64_t seed;       /* Philox key */
   double p;            /* depolarizing probability, [0, 1] */

@@ -40,7 +40,7 @@ class _Job(ctypes.Structure):
         ("eps_site", ctypes.POINTER(ctypes.c_double)),
         ("eps", ctypes.c_double),
         ("xbasis", ctypes.c_int),
-        ("pad_", ctypes.c_int),
+        ("virtual_z", ctypes.c_int),
     ]
 
 
@@ -118,11 +118,12 @@ def template_counts(d, gateset):
 
 
 def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=None,
-                   want_state=False, twirl=False, xbasis=False):
+                   want_state=False, twirl=False, xbasis=False, virtual_z=False):
     """One Monte Carlo trajectory.
 
     twirl: Pauli-twirled over-rotations; xbasis: X-basis memory (logical |+>,
-    final X measurement of the data qubits).  Returns
+    final X measurement of the data qubits); virtual_z: the Rz restores of the
+    cross-resonance Z checks without over-rotation.  Returns
     dict(records=uint8[rounds, n_stab], final_bits=uint8[d*d],
     p1=float64[rounds, n_stab], state=complex128[2^(d*d)] or None) where
     `state` is the data register just before the final measurement."""
@@ -132,6 +133,7 @@ def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=N
     job.seed, job.p, job.zeta, job.eps = int(seed), float(p), float(zeta), float(eps)
     job.twirl = 1 if twirl else 0
     job.xbasis = 1 if xbasis else 0
+    job.virtual_z = 1 if virtual_z else 0
     keep = None
     if eps_site is not None:
         keep = np.ascontiguousarray(eps_site, dtype=np.float64)

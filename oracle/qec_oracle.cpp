@@ -336,6 +336,7 @@ struct Job {
   double eps;              // used for every site when eps_site is null
   int twirl;               // 1: Pauli-twirled over-rotations (see site_rot1)
   int xbasis;              // 1: X-basis memory (logical |+>, final X measurement)
+  int virtual_z;           // 1: Rz restores are exact (virtual Z, Fig. 4)
 };
 
 struct Ctx {
@@ -453,7 +454,12 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
       for (int j = 0; j < 4; ++j) {
         const int q = st.slot[j];
         if (!q) continue;
-        site_rot1(s, cx, q - 1, 3, 1.0, q4);
+        if (cx.job->virtual_z) {  // a frame change: no over-rotation, no draw
+          next_eps(cx);
+          rot1(s, q - 1, 3, q4);
+        } else {
+          site_rot1(s, cx, q - 1, 3, 1.0, q4);
+        }
         noise1(s, cx, q - 1);
       }
     }
@@ -609,8 +615,8 @@ typedef struct {
   double zeta;
   const double* eps_site;
   double eps;
-  int xbasis;  // 1: X-basis memory
-  int pad_;
+  int xbasis;     // 1: X-basis memory
+  int virtual_z;  // 1: Rz restores exact
 } orc_job;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
@@ -642,7 +648,7 @@ int orc_template_counts(int d, int gateset, int* n_stab, int* n_sites, int* n_dr
 int orc_run_trajectory(const orc_job* j, unsigned long long t, uint8_t* records,
                        uint8_t* final_bits, double* p1_trace, double* final_state) {
   if (!j || j->d < 2 || j->d > 5 || j->rounds < 0) return -1;
-  Job job{j->d, j->gateset, j->rounds, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl, j->xbasis};
+  Job job{j->d, j->gateset, j->rounds, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl, j->xbasis, j->virtual_z};
   Output out{records, final_bits, p1_trace, final_state};
   return run_trajectory(job, t, out);
 }
@@ -651,7 +657,7 @@ int orc_run_trajectory(const orc_job* j, unsigned long long t, uint8_t* records,
 // 2^(d*d) interleaved complex.
 int orc_logical_state(int d, int gateset, int xbasis, double* out) {
   if (d < 2 || d > 5) return -1;
-  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0, 0, xbasis};
+  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0, 0, xbasis, 0};
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);
   if (prepare_logical_zero(s, job, stabs) != 0) return -1;
@@ -686,7 +692,8 @@ int orc_apply_gate(double* state, int n, int k, const int* qubits, const double*
 // the corresponding part of a trajectory.
 double orc_time_blocks(const orc_job* j, unsigned long long t, int n_blocks, int* threads) {
   if (!j || j->d < 2 || j->d > 5 || n_blocks < 1) return -1.0;
-  Job job{j->d, j->gateset, 1, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl, j->xbasis};
+  Job job{j->d, j->gateset, 1, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl, j->xbasis,
+          j->virtual_z};
   const int d = job.d, anc = d * d;
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);

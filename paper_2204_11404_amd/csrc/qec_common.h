@@ -79,7 +79,7 @@ struct TOp {
   uint8_t axis;     // 1 = X, 2 = Y, 3 = Z
   int8_t sgn;       // +1 / -1 generator sign
   uint8_t quarter;  // 1: angle base pi/4; 0: base 0
-  uint8_t pad;
+  uint8_t exact;    // 1: no over-rotation at this site (virtual Z)
   int16_t site;     // gate site within the round, -1 if none
   int16_t draw;     // local draw index, -1 if none
   int16_t pad2;
@@ -185,7 +185,7 @@ QEC_HD void anc_rot_cs(int axis, double c, double s, cd& v0, cd& v1) {
 // sin^2 eps, Sec. III.A): it rotates by the base angle only.
 QEC_HD double op_angle(const TOp& op, const double* eps_site) {
   return (op.quarter ? 0.78539816339744830962 : 0.0) +
-         (op.site >= 0 && op.draw < 0 ? eps_site[op.site] : 0.0);
+         (op.site >= 0 && op.draw < 0 && !op.exact ? eps_site[op.site] : 0.0);
 }
 
 QEC_HD bool is_rotation(uint8_t kind) {

@@ -145,6 +145,7 @@ struct OpSink {
   TBlock& b;
   int site_base;
   bool twirl;  // rotations draw their twirled over-rotation
+  bool vz;     // Rz restores are virtual: exact, no draw
   int sites = 0;
   int draws = 0;
   void gate(uint8_t kind, int j, int axis, int sgn, int quarter) {
@@ -153,7 +154,8 @@ struct OpSink {
     o.kind = kind; o.j = (uint8_t)j; o.axis = (uint8_t)axis; o.sgn = (int8_t)sgn;
     o.quarter = (uint8_t)quarter;
     o.site = (int16_t)(site_base + sites++);
-    o.draw = twirl ? (int16_t)draws++ : (int16_t)-1;
+    o.exact = (uint8_t)(vz && kind == OP_ROT_DATA && axis == 3);
+    o.draw = (twirl && !o.exact) ? (int16_t)draws++ : (int16_t)-1;
   }
   void plain(uint8_t kind, int j) {
     TOp& o = b.ops[b.n_ops++];
@@ -172,7 +174,9 @@ struct OpSink {
 // twirl: Pauli-twirled over-rotations -- each rotation by its base angle,
 // then one draw deciding whether its generator is applied (probability
 // sin^2 eps of its site), drawn right after the rotation.
-Template build_template(int d, int gateset, bool twirl = false) {
+// vz: the Rz restores of the cross-resonance Z checks are virtual Z gates
+// (frame changes, Fig. 4): no over-rotation; their sites stay in the table.
+Template build_template(int d, int gateset, bool twirl = false, bool vz = false) {
   Template T;
   for (const Stab& st : code_layout(d)) {
     TBlock b{};
@@ -188,7 +192,7 @@ Template build_template(int d, int gateset, bool twirl = false) {
     }
     b.draw_off = T.n_draws;
     b.site_off = T.n_sites;
-    OpSink o{b, T.n_sites, twirl};
+    OpSink o{b, T.n_sites, twirl, vz};
     if (gateset == SV_GATESET_CR) {
       if (st.type == 0) {
         o.gate(OP_ROT_ANC, 0, 1, -1, 1);  // Rx^dag(pi/2)
@@ -1668,14 +1672,15 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
   if (job->rounds < 1 || job->rounds > 100000) return fail(SV_EINVAL, "rounds=%d", job->rounds);
   if (job->dtype != SV_C64 && job->dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
   if (job->n_traj < 0) return fail(SV_EINVAL, "n_traj < 0");
-  if (job->flags & ~(SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS))
+  if (job->flags & ~(SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS | SV_RUN_VIRTUAL_Z))
     return fail(SV_EINVAL, "unknown flags 0x%x", job->flags);
   if (!(job->p >= 0.0 && job->p <= 1.0)) return fail(SV_EINVAL, "p out of [0, 1]");
   if (!std::isfinite(job->eps) || !std::isfinite(job->zeta)) return fail(SV_EINVAL, "non-finite eps/zeta");
   if (!res->records || !res->final_bits) return fail(SV_EINVAL, "records and final_bits are required");
   if ((job->flags & SV_RUN_GRAPH) && res->final_states)
     return fail(SV_EINVAL, "final_states cannot be returned with SV_RUN_GRAPH");
-  const Template tp = build_template(job->d, job->gateset, (job->flags & SV_RUN_TWIRL) != 0);
+  const Template tp = build_template(job->d, job->gateset, (job->flags & SV_RUN_TWIRL) != 0,
+                                     (job->flags & SV_RUN_VIRTUAL_Z) != 0);
   if (job->eps_site)
     for (int i = 0; i < tp.n_sites; ++i)
       if (!std::isfinite(job->eps_site[i])) return fail(SV_EINVAL, "non-finite eps_site[%d]", i);

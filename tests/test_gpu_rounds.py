@@ -23,15 +23,16 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "d5_cr_oracle.npz")
 
 
 def _compare(d, gateset, R, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0, dtype="c128",
-             traj0=0, atol=1e-10, twirl=False, xbasis=False):
+             traj0=0, atol=1e-10, twirl=False, xbasis=False, virtual_z=False):
     print(f"case rounds d={d} {gateset} R={R} n={n_traj} p={p} eps={eps} zeta={zeta} {dtype}"
           f" twirl={twirl} xbasis={xbasis}", flush=True)
     g = qs.run_rounds(d, gateset, R, n_traj, seed, p, eps=eps, eps_site=eps_site, zeta=zeta,
                       dtype=dtype, traj0=traj0, want_p1=True, want_states=True, twirl=twirl,
-                      xbasis=xbasis)
+                      xbasis=xbasis, virtual_z=virtual_z)
     for i in range(n_traj):
         o = oracle.run_trajectory(d, GS[gateset], R, seed, traj0 + i, p, eps=eps, eps_site=eps_site,
-                                  zeta=zeta, want_state=True, twirl=twirl, xbasis=xbasis)
+                                  zeta=zeta, want_state=True, twirl=twirl, xbasis=xbasis,
+                                  virtual_z=virtual_z)
         assert np.array_equal(g["records"][i], o["records"]), f"trajectory {i}"
         assert np.array_equal(g["final_bits"][i], o["final_bits"]), f"trajectory {i}"
         assert np.max(np.abs(g["p1"][i] - o["p1"])) < atol
@@ -203,3 +204,11 @@ def test_x_basis_twirled_parity():
     n_sites = oracle.template_counts(3, oracle.GATESET_CR)[1]
     eps = workloads.eps_sites(n_sites, (0.1, 0.4), 13)
     _compare(3, "cr", 2, 10, seed=13, p=0.01, eps_site=eps, twirl=True, xbasis=True)
+
+
+@pytest.mark.parametrize("twirl", [False, True])
+def test_virtual_z_parity(twirl):
+    """SV_RUN_VIRTUAL_Z: exact Rz restores after the Z checks."""
+    n_sites = oracle.template_counts(3, oracle.GATESET_CR)[1]
+    eps = workloads.eps_sites(n_sites, (0.05, 0.3), 14)
+    _compare(3, "cr", 2, 10, seed=14, p=0.01, eps_site=eps, zeta=0.01, twirl=twirl, virtual_z=True)

@@ -395,3 +395,19 @@ def test_x_memory_pauli_only_matches_frame_sampler(gateset):
     assert np.max(np.abs((a - b) / sig)) < 4.0
     xl_f = np.bitwise_xor.reduce(ffin[:, 0:d * d:d], axis=1).mean()
     assert abs(np.mean(xl) - xl_f) < 4.0 * np.sqrt(max(xl_f * (1 - xl_f), 1.0 / N) / N)
+
+
+def test_virtual_z_restores_carry_no_over_rotation():
+    """virtual_z: over-rotation placed only on the Rz restores of the Z checks
+    changes nothing -- p1, records and register equal the eps = 0 run."""
+    d = 3
+    kinds = []
+    for t, s in oracle.layout(d):
+        w = sum(1 for q in s if q)
+        kinds += (["anc"] + ["cr"] * w + ["anc"] + ["restore"] * w) if t == "X" else (["cr"] * w + ["rz"] * w)
+    es = np.array([0.07 if k == "rz" else 0.0 for k in kinds])
+    a = oracle.run_trajectory(d, CR, 2, seed=4, t=0, p=0.0, eps_site=es, virtual_z=True, want_state=True)
+    b = oracle.run_trajectory(d, CR, 2, seed=4, t=0, p=0.0, want_state=True)
+    c = oracle.run_trajectory(d, CR, 2, seed=4, t=0, p=0.0, eps_site=es, want_state=True)
+    assert np.array_equal(a["p1"], b["p1"]) and np.allclose(a["state"], b["state"], atol=1e-14)
+    assert np.max(np.abs(c["p1"] - b["p1"])) > 1e-6   # without the flag they do act
