@@ -225,10 +225,6 @@ __global__ __launch_bounds__(256) void k_prepare_round(
 // -------------------------------------------------------------------- pass --
 constexpr int kTileMax = 12;  // 4096 amplitudes per tile
 
-// What follows the applied block in a pass of the persistent d = 4 kernel:
-// nothing, a Z check (pointwise sums) or an X check (regrouped through LDS).
-enum : int { B_NONE = 0, B_ZCHECK = 1, B_XCHECK = 2 };
-
 // Several trajectories in one launch: blockIdx.y selects a trajectory slot;
 // its register, Kraus tables and decisions sit at these strides (all zero for
 // a single trajectory).

@@ -369,32 +369,6 @@ QEC_HD void draw_block(const TBlock& b, uint64_t seed, uint64_t t, uint64_t k0, 
   *u_meas = uniform(seed, t, k0 + (uint64_t)(b.n_draws - 1));
 }
 
-// ------------------------------------------------------------ pass layout --
-// A pass applies block a (K_m of its decided outcome, then the ZZ layer and
-// the 1/sqrt(S_m) renormalisation) and accumulates S_0, S_1 of block b, over
-// tiles of 2^TB amplitudes that contain every data qubit of a and b.  In
-// phase 1 a thread owns 16 amplitudes: the 2^wa combinations of block a's
-// qubits times 2^(4-wa) further tile bits; in phase 2 (through LDS) it owns
-// the 2^wb combinations of block b's qubits times 2^(4-wb) tile bits.
-struct PassDesc {
-  int wa, wb;          // 0 = none (init / last pass)
-  int typea, typeb;    // 0 = X, 1 = Z
-  int blk_a, blk_b;    // template block indices
-  int tb;              // tile bits
-  int n_outer;         // bits outside the tile
-  uint32_t outer_bit[32];  // value (1 << position) of each outer bit
-  uint32_t a_tid_g[8], a_tid_l[8];
-  uint32_t a_j_g[16], a_j_l[16];
-  uint32_t a_q_g[4], a_q_l[4];  // global / LDS bit of block a's local bit
-  uint32_t b_tid_l[8];
-  uint32_t b_j_l[16];
-  // local index on block b's qubits carried by each phase-1 bit (pointwise
-  // S_m of a following Z check)
-  uint32_t a_tid_lb[8];
-  uint32_t a_j_lb[16];
-  uint32_t a_q_lb[4];
-};
-
 struct JobConst {
   int d;
   int n;               // data qubits

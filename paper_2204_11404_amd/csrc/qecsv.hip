@@ -26,7 +26,6 @@
 #include "qec_common.h"
 #include "kernels.hip"
 #include "kernels_batch.hip"
-#include "kernels_tiled.hip"
 
 using namespace qec;
 
@@ -538,77 +537,6 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
   return pd;
 }
 
-// ------------------------------------------------------ pass descriptors --
-PassDesc make_pass(int n, int tb_max, const TBlock* A, const TBlock* B, int ia, int ib) {
-  PassDesc pd{};
-  const int tb = std::min(tb_max, n);
-  pd.tb = tb;
-  pd.wa = A ? A->w : 0;
-  pd.wb = B ? B->w : 0;
-  pd.typea = A ? A->type : 0;
-  pd.typeb = B ? B->type : 0;
-  pd.blk_a = ia;
-  pd.blk_b = ib;
-  std::vector<int> qa, qb;
-  for (int l = 0; l < pd.wa; ++l) qa.push_back(A->qubit[l]);
-  for (int l = 0; l < pd.wb; ++l) qb.push_back(B->qubit[l]);
-  std::vector<bool> in_t(n, false);
-  int cnt = 0;
-  for (int x : qa) if (!in_t[x]) { in_t[x] = true; ++cnt; }
-  for (int x : qb) if (!in_t[x]) { in_t[x] = true; ++cnt; }
-  for (int bit = 0; bit < n && cnt < tb; ++bit)
-    if (!in_t[bit]) { in_t[bit] = true; ++cnt; }
-  std::vector<int> rank(n, -1);
-  int r = 0;
-  pd.n_outer = 0;
-  for (int bit = 0; bit < n; ++bit) {
-    if (in_t[bit]) rank[bit] = r++;
-    else pd.outer_bit[pd.n_outer++] = 1u << bit;
-  }
-  auto fill = [&](const std::vector<int>& qs, uint32_t* tid_g, uint32_t* tid_l, uint32_t* j_g,
-                  uint32_t* j_l, uint32_t* q_g, uint32_t* q_l) {
-    std::vector<int> rest;
-    for (int bit = 0; bit < n; ++bit)
-      if (in_t[bit] && std::find(qs.begin(), qs.end(), bit) == qs.end()) rest.push_back(bit);
-    const int w = (int)qs.size();
-    const int ntid = tb - 4;
-    for (int i = 0; i < ntid; ++i) {
-      if (tid_g) tid_g[i] = 1u << rest[i];
-      tid_l[i] = 1u << rank[rest[i]];
-    }
-    for (int j = 0; j < 16; ++j) {
-      uint32_t g = 0, l = 0;
-      for (int b = 0; b < w; ++b)
-        if ((j >> b) & 1) { g |= 1u << qs[b]; l |= 1u << rank[qs[b]]; }
-      for (int h = 0; h < 4 - w; ++h)
-        if ((j >> (w + h)) & 1) {
-          const int bit = rest[ntid + h];
-          g |= 1u << bit;
-          l |= 1u << rank[bit];
-        }
-      if (j_g) j_g[j] = g;
-      j_l[j] = l;
-    }
-    if (q_g)
-      for (int b = 0; b < w; ++b) {
-        q_g[b] = 1u << qs[b];
-        q_l[b] = 1u << rank[qs[b]];
-      }
-  };
-  fill(qa, pd.a_tid_g, pd.a_tid_l, pd.a_j_g, pd.a_j_l, pd.a_q_g, pd.a_q_l);
-  if (B) fill(qb, nullptr, pd.b_tid_l, nullptr, pd.b_j_l, nullptr, nullptr);
-  // block-b local index carried by each phase-1 bit
-  auto lb = [&](uint32_t gbits) {
-    uint32_t x = 0;
-    for (int l = 0; l < pd.wb; ++l)
-      if (gbits & (1u << qb[l])) x |= 1u << l;
-    return x;
-  };
-  for (int i = 0; i < tb - 4; ++i) pd.a_tid_lb[i] = lb(pd.a_tid_g[i]);
-  for (int j = 0; j < 16; ++j) pd.a_j_lb[j] = lb(pd.a_j_g[j]);
-  for (int l = 0; l < pd.wa; ++l) pd.a_q_lb[l] = lb(pd.a_q_g[l]);
-  return pd;
-}
 
 // H on every one of the n register qubits, in groups of up to five, scaled
 // by 2^(-n/2) in the last group.
@@ -1013,9 +941,10 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   const int d = in.d, n = d * d, ns = (int)tp.blocks.size();
   const int nt = in.n_traj;
   const bool small = n <= kSmallBits && ns <= kSmallStab && tp.n_sites <= kSmallSites;
-  const bool tiled = !small && n <= 16 && ns <= kTiledStab && tp.n_sites <= kTiledSites;
-  if (!small && !tiled) return fail(SV_EINVAL, "d=%d batch path not available", d);
-  if (tiled && env_int("QECSV_D4_PERSISTENT", 0) == 0) return run_batch_lockstep<T>(in, tp);
+  if (!small) {
+    if (n > 16) return fail(SV_EINVAL, "d=%d batch path not available", d);
+    return run_batch_lockstep<T>(in, tp);
+  }
   hipStream_t s = in.hs;
   DevBufs M(s);
   TBlock* dblocks = nullptr;
@@ -1066,7 +995,7 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   } ev;
   HIP_OK(hipEventCreate(&ev.a));
   HIP_OK(hipEventCreate(&ev.b));
-  if (small) {
+  {
     const int per_cu = tuning_for(in.d, sizeof(T) == 8 ? SV_C128 : SV_C64).batch_waves_per_cu;
     const int max_wg = device_cu_count() * per_cu;
     const int grid = std::max(1, std::min((nt + 1) / 2, max_wg));
@@ -1074,25 +1003,6 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
     hipLaunchKernelGGL(k_batch_small<T>, dim3(grid), dim3(64), 0, s, dblocks, dsd, ns, n, tp.n_draws,
                        djc, dseed, dstream, dorder, nt, drounds, dp, deps, in.eps_stride, drec,
                        in.max_rounds, dbits, derr);
-  } else {
-    // one workgroup per trajectory, each with its own 2^n-amplitude slice
-    const int per_cu = std::max(1, env_int("QECSV_TILED_WG_PER_CU", sizeof(T) == 8 ? 2 : 2));
-    const int grid = std::max(1, std::min(nt, device_cu_count() * per_cu));
-    T* work = nullptr;
-    PassDesc* dpass = nullptr;
-    HIP_OK(M.alloc(&work, ((size_t)grid << n) * 2 * sizeof(T)));
-    HIP_OK(M.alloc(&dpass, sizeof(PassDesc) * (ns + 2)));
-    const int tb = std::min(kTileMax, n);
-    std::vector<PassDesc> pds(ns + 2);
-    pds[0] = make_pass(n, tb, nullptr, &tp.blocks[0], -1, 0);
-    for (int i = 0; i < ns; ++i)
-      pds[1 + i] = make_pass(n, tb, &tp.blocks[i], &tp.blocks[(i + 1) % ns], i, (i + 1) % ns);
-    pds[ns + 1] = make_pass(n, tb, &tp.blocks[ns - 1], nullptr, ns - 1, -1);
-    HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(PassDesc) * (ns + 2), hipMemcpyHostToDevice, s));
-    HIP_OK(hipEventRecord(ev.a, s));
-    hipLaunchKernelGGL(k_batch_tiled<T>, dim3(grid), dim3(256), 0, s, dblocks, dpass, ns, n,
-                       tp.n_draws, djc, dseed, dstream, dorder, nt, drounds, dp, deps,
-                       in.eps_stride, drec, in.max_rounds, dbits, work, derr);
   }
   HIP_OK(hipGetLastError());
   HIP_OK(hipEventRecord(ev.b, s));
@@ -1307,17 +1217,12 @@ size_t batch_footprint(int d, int dtype, int n_traj, int max_rounds, int n_sites
   const size_t elem = dtype == SV_C128 ? 16 : 8;
   size_t b = (size_t)n_traj * ((size_t)max_rounds * (n + 1) + n + 40 + 8 * (size_t)n_sites);
   if (n > kSmallBits) {
-    if (env_int("QECSV_D4_PERSISTENT", 0)) {  // one register per resident workgroup
-      const int per_cu = std::max(1, env_int("QECSV_TILED_WG_PER_CU", 2));
-      const size_t grid = std::min<size_t>((size_t)n_traj, (size_t)device_cu_count() * per_cu);
-      b += (grid << n) * elem;
-    } else {  // lockstep: G registers with their partial sums and decisions
-      const size_t reg = elem << n;
-      const size_t cap = (size_t)tuning_for(d, dtype).lockstep_mib << 20;
-      const size_t G = std::max<size_t>(1, std::min<size_t>((size_t)n_traj, cap / reg));
-      const size_t n_tiles = (size_t)1 << (n - std::min(kTileMax, n));
-      b += G * (reg + sizeof(double) * kChainAcc * n_tiles + sizeof(Decision) * (size_t)max_rounds * n);
-    }
+    // lockstep: G registers with their partial sums and decisions
+    const size_t reg = elem << n;
+    const size_t cap = (size_t)tuning_for(d, dtype).lockstep_mib << 20;
+    const size_t G = std::max<size_t>(1, std::min<size_t>((size_t)n_traj, cap / reg));
+    const size_t n_tiles = (size_t)1 << (n - std::min(kTileMax, n));
+    b += G * (reg + sizeof(double) * kChainAcc * n_tiles + sizeof(Decision) * (size_t)max_rounds * n);
   }
   return b + (1 << 20);
 }
