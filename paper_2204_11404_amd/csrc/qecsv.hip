@@ -3,9 +3,11 @@
 // Host side of the trajectory engine: the code layout of Sec. II.A (Table I
 // order, CNOT slot order, boundary waits), the encoded stabilizer-circuit
 // template of Sec. III.A (cross-resonance or textbook gate set, noise
-// locations, over-rotation sites), tile descriptors for the fused passes, and
-// the launch sequence of one trajectory (Sec. III.B).  All simulation
-// arithmetic runs in the kernels of kernels.hip.
+// locations, over-rotation sites), the units and tile descriptors of the
+// register passes, the launch sequence of one trajectory (Sec. III.B), the
+// batched and served runs, the launch-parameter table and the decoder.  All
+// simulation arithmetic runs in the kernels of kernels.hip and
+// kernels_batch.hip.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -1019,8 +1021,8 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
 }
 
 // Batched trajectories too large for LDS, run in lockstep: every launch of
-// the fused pass covers (tile, trajectory) pairs, so thousands of 2^16-amplitude
-// registers fill the GPU like one 2^25-amplitude register does.  Slots are the
+// the register pass covers (tile, trajectory) pairs, so thousands of
+// 2^16-amplitude registers fill the GPU like one 2^25-amplitude register does.  Slots are the
 // trajectories sorted by round count (longest first), so the trajectories still
 // running in round r are always the first A(r) slots.
 template <typename T>
