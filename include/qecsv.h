@@ -247,6 +247,9 @@ typedef struct sv_tuning {
   int snake;              /* 1: consecutive passes walk the tiles in opposite orders */
   int batch_waves_per_cu; /* sv_run_batch, d <= 3: resident waves per compute unit, 1..32 */
   int lockstep_mib;       /* sv_run_batch, d = 4: MiB of registers run in lockstep */
+  int pass_wgs_per_cu;    /* sv_run_rounds: workgroups per compute unit of a register
+                             pass, each taking tiles grid-stride; 0 = one tile
+                             per workgroup (0..64) */
 } sv_tuning;
 
 /* Effective parameters (set, tuned or built-in, then the environment). */
@@ -256,7 +259,8 @@ sv_status sv_tuning_get(int d, int dtype, sv_tuning* out);
 sv_status sv_tuning_set(int d, int dtype, const sv_tuning* in);
 /* Time candidate parameters on synthetic work of this shape (tens of ms of
  * device time) and keep the fastest for (d, dtype) on the current device:
- * d = 5, sv_run_rounds (one trajectory, one round): zchain x snake;
+ * d = 5, sv_run_rounds (one trajectory, one round): zchain x snake x
+ *   pass_wgs_per_cu;
  * d = 4, sv_run_batch (512 trajectories, 3 rounds): zchain x lockstep_mib;
  * d <= 3, sv_run_batch (16384 trajectories, 3 rounds): batch_waves_per_cu.
  * Writes the winner to *best and its device time to *best_ms (either may be
@@ -264,7 +268,8 @@ sv_status sv_tuning_set(int d, int dtype, const sv_tuning* in);
  * while other threads run jobs of the same shape. */
 sv_status sv_autotune(int d, int dtype, int gateset, sv_tuning* best, double* best_ms);
 /* Write / read the parameters of the current device's architecture as text
- * lines "arch d dtype zchain snake batch_waves_per_cu lockstep_mib"; load
+ * lines "arch d dtype zchain snake batch_waves_per_cu lockstep_mib
+ * pass_wgs_per_cu"; load
  * keeps only lines for this architecture.  SV_EINVAL on I/O or parse errors. */
 sv_status sv_tuning_save(const char* path);
 sv_status sv_tuning_load(const char* path);

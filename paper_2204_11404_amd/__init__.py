@@ -68,7 +68,8 @@ class BatchResult(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("zchain", ctypes.c_int), ("snake", ctypes.c_int),
-                ("batch_waves_per_cu", ctypes.c_int), ("lockstep_mib", ctypes.c_int)]
+                ("batch_waves_per_cu", ctypes.c_int), ("lockstep_mib", ctypes.c_int),
+                ("pass_wgs_per_cu", ctypes.c_int)]
 
 
 class ServerConfig(ctypes.Structure):

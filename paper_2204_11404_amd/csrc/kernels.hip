@@ -342,7 +342,7 @@ __device__ __forceinline__ void chain_tree(double a2, const uint32_t* x,
 // still on chip.  B an X check: S_0, S_1 over the check's Hadamard basis.
 // B a chain of L Z checks: S[l][h] for l < L and every outcome string h of
 // members 0..l (bit i = outcome of member i), at index 2^(l+1) - 2 + h.
-// One tile per workgroup; `reverse` walks the tiles backwards (consecutive
+// Tiles are taken grid-stride; `reverse` walks them backwards (consecutive
 // passes alternate, so a pass starts on the lines its predecessor wrote
 // last).  Workgroup 0 records the frame after A in dec_b.
 // AP: weight of an X check A, or the length of a Z chain A (BP likewise).
@@ -357,7 +357,8 @@ __global__ __launch_bounds__(256) void k_upass(
   if (rtb) rtb += (size_t)blockIdx.y * ss.rt;
   if (dec_a) dec_a += (size_t)blockIdx.y * ss.dec;
   dec_b += (size_t)blockIdx.y * ss.dec;
-  partials += (size_t)blockIdx.y * kChainAcc * gridDim.x;
+  const int n_tiles = 1 << pd->n_outer;
+  partials += (size_t)blockIdx.y * kChainAcc * n_tiles;
   __shared__ C2<T> da[kChainMax][16];
   __shared__ double wt[kChainMax][2][16];
   __shared__ C2<T> zzt[4 * 40 + 1];
@@ -455,7 +456,10 @@ __global__ __launch_bounds__(256) void k_upass(
       gt |= pd->tid_g[i];
       lt |= pd->tid_l[i];
     }
-  const int wg = reverse ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+  // grid-stride over the tiles (one tile per workgroup when the grid covers
+  // them all); the tables above are loaded once per workgroup
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+  const int wg = reverse ? n_tiles - 1 - tile : tile;
   uint32_t base = 0;
   for (int i = 0; i < pd->n_outer; ++i)
     if ((wg >> i) & 1) base |= pd->outer_bit[i];
@@ -635,25 +639,28 @@ __global__ __launch_bounds__(256) void k_upass(
       }
     }
   }
-  if constexpr (BK == U_NONE) return;
-  constexpr int nacc = (2 << lb) - 2;
-  const int lane = tid & 63, wid = tid >> 6;
-  const int nw = (int)(blockDim.x + 63) >> 6;
-  if constexpr (nacc <= 6) {
+  if constexpr (BK != U_NONE) {
+    constexpr int nacc = (2 << lb) - 2;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int nw = (int)(blockDim.x + 63) >> 6;
+    if constexpr (nacc <= 6) {
 #pragma unroll
-    for (int a = 0; a < nacc; ++a) {
-      const double s = wave_sum(acc[a]);
-      if (lane == 0) red[a][wid] = s;
+      for (int a = 0; a < nacc; ++a) {
+        const double s = wave_sum(acc[a]);
+        if (lane == 0) red[a][wid] = s;
+      }
+    } else {
+      const double s = wave_reduce32(acc);
+      if ((lane & 1) == 0 && (lane >> 1) < nacc) red[lane >> 1][wid] = s;
     }
-  } else {
-    const double s = wave_reduce32(acc);
-    if ((lane & 1) == 0 && (lane >> 1) < nacc) red[lane >> 1][wid] = s;
+    __syncthreads();
+    if (tid < nacc) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[tid][w];
+      partials[(size_t)tid * n_tiles + wg] = s;
+    }
   }
-  __syncthreads();
-  if (tid < nacc) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += red[tid][w];
-    partials[(size_t)tid * gridDim.x + wg] = s;
+  __syncthreads();  // LDS buffers are reused by the next tile
   }
 }
 

@@ -338,6 +338,7 @@ sv_tuning default_tuning() {
   t.snake = 1;
   t.batch_waves_per_cu = 8;
   t.lockstep_mib = 4096;
+  t.pass_wgs_per_cu = 0;
   return t;
 }
 
@@ -353,7 +354,16 @@ sv_status check_tuning(const sv_tuning& t) {
   if (t.batch_waves_per_cu < 1 || t.batch_waves_per_cu > 32)
     return fail(SV_EINVAL, "batch_waves_per_cu %d out of 1..32", t.batch_waves_per_cu);
   if (t.lockstep_mib < 1 || t.lockstep_mib > (1 << 20)) return fail(SV_EINVAL, "lockstep_mib out of range");
+  if (t.pass_wgs_per_cu < 0 || t.pass_wgs_per_cu > 64) return fail(SV_EINVAL, "pass_wgs_per_cu out of 0..64");
   return SV_OK;
+}
+
+int device_cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 256;
+  return cus;
 }
 
 sv_tuning tuning_for(int d, int dtype) {
@@ -367,6 +377,8 @@ sv_tuning tuning_for(int d, int dtype) {
   if (const char* e = std::getenv("QECSV_SNAKE")) t.snake = std::atoi(e) != 0;
   if (const char* e = std::getenv("QECSV_BATCH_WAVES_PER_CU")) t.batch_waves_per_cu = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("QECSV_LOCKSTEP_MIB")) t.lockstep_mib = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("QECSV_PASS_WGS_PER_CU"))
+    t.pass_wgs_per_cu = std::max(0, std::min(64, std::atoi(e)));
   return t;
 }
 
@@ -695,7 +707,10 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   // alternate the tile traversal between consecutive passes: a pass starts on
   // the lines its predecessor wrote last
   const int snake = tune.snake;
-  const dim3 grid((unsigned)n_tiles), block((unsigned)std::max(64, 1 << (tb - 4)));
+  const size_t pass_wgs = tune.pass_wgs_per_cu == 0
+                              ? n_tiles
+                              : std::min<size_t>(n_tiles, (size_t)device_cu_count() * tune.pass_wgs_per_cu);
+  const dim3 grid((unsigned)pass_wgs), block((unsigned)std::max(64, 1 << (tb - 4)));
   const SlotStrides ss0{0, 0, 0};
   const int draws_round = tp.n_draws;
   const int last_t = job->n_traj - 1;
@@ -905,13 +920,6 @@ std::vector<SmallDesc> make_small_descs(int n, const Template& tp) {
   return out;
 }
 
-int device_cu_count() {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 256;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-    return 256;
-  return cus;
-}
 
 int env_int(const char* name, int dflt) {
   if (const char* e = std::getenv(name)) return std::atoi(e);
@@ -1668,12 +1676,14 @@ sv_status sv_autotune(int d, int dtype, int gateset, sv_tuning* best, double* be
   std::vector<sv_tuning> cands;
   if (d == 5) {
     for (int z = 2; z <= kChainMax; ++z)
-      for (int sn = 0; sn <= 1; ++sn) {
-        sv_tuning c = base;
-        c.zchain = z;
-        c.snake = sn;
-        cands.push_back(c);
-      }
+      for (int sn = 0; sn <= 1; ++sn)
+        for (int wpc : {0, 8, 16}) {
+          sv_tuning c = base;
+          c.zchain = z;
+          c.snake = sn;
+          c.pass_wgs_per_cu = wpc;
+          cands.push_back(c);
+        }
   } else if (d == 4) {
     for (int z = 2; z <= kChainMax; ++z)
       for (int mib : {256, 1024, 4096}) {
@@ -1771,8 +1781,9 @@ sv_status sv_tuning_save(const char* path) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& kv : g_tune)
       if (kv.first.dev == dev)
-        std::fprintf(f, "%s %d %d %d %d %d %d\n", arch.c_str(), kv.first.d, kv.first.dtype, kv.second.zchain,
-                     kv.second.snake, kv.second.batch_waves_per_cu, kv.second.lockstep_mib);
+        std::fprintf(f, "%s %d %d %d %d %d %d %d\n", arch.c_str(), kv.first.d, kv.first.dtype,
+                     kv.second.zchain, kv.second.snake, kv.second.batch_waves_per_cu, kv.second.lockstep_mib,
+                     kv.second.pass_wgs_per_cu);
   }
   return std::fclose(f) == 0 ? SV_OK : fail(SV_EINVAL, "cannot write %s", path);
 }
@@ -1788,8 +1799,8 @@ sv_status sv_tuning_load(const char* path) {
   sv_tuning t{};
   std::vector<std::pair<TuneKey, sv_tuning>> got;
   int k;
-  while ((k = std::fscanf(f, "%127s %d %d %d %d %d %d", a, &d, &dt, &t.zchain, &t.snake,
-                          &t.batch_waves_per_cu, &t.lockstep_mib)) == 7) {
+  while ((k = std::fscanf(f, "%127s %d %d %d %d %d %d %d", a, &d, &dt, &t.zchain, &t.snake,
+                          &t.batch_waves_per_cu, &t.lockstep_mib, &t.pass_wgs_per_cu)) == 8) {
     if (arch != a) continue;
     if (d < 2 || d > 5 || (dt != SV_C64 && dt != SV_C128) || check_tuning(t) != SV_OK) {
       std::fclose(f);

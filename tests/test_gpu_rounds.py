@@ -212,3 +212,19 @@ def test_virtual_z_parity(twirl):
     n_sites = oracle.template_counts(3, oracle.GATESET_CR)[1]
     eps = workloads.eps_sites(n_sites, (0.05, 0.3), 14)
     _compare(3, "cr", 2, 10, seed=14, p=0.01, eps_site=eps, zeta=0.01, twirl=twirl, virtual_z=True)
+
+
+def test_grid_stride_passes_match(monkeypatch):
+    """Register passes with fewer workgroups than tiles (each takes tiles
+    grid-stride) compute the same records, p1 and final bits bit for bit."""
+    n_sites = oracle.template_counts(5, oracle.GATESET_CR)[1]
+    eps = workloads.eps_sites(n_sites, (0.0, 0.05), 1)
+    kw = dict(d=5, gateset="cr", rounds=1, n_traj=1, seed=3, p=5e-3, eps_site=eps, zeta=0.01,
+              dtype="c64", want_p1=True)
+    monkeypatch.setenv("QECSV_PASS_WGS_PER_CU", "0")
+    a = qs.run_rounds(**kw)
+    monkeypatch.setenv("QECSV_PASS_WGS_PER_CU", "1")
+    b = qs.run_rounds(**kw)
+    assert np.array_equal(a["records"], b["records"])
+    assert np.array_equal(a["p1"], b["p1"])
+    assert np.array_equal(a["final_bits"], b["final_bits"])

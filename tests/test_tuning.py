@@ -12,7 +12,7 @@ import oracle
 import paper_2204_11404_amd as qs
 import workloads
 
-FIELDS = {"zchain", "snake", "batch_waves_per_cu", "lockstep_mib"}
+FIELDS = {"zchain", "snake", "batch_waves_per_cu", "lockstep_mib", "pass_wgs_per_cu"}
 
 
 @pytest.fixture(autouse=True)
@@ -24,7 +24,8 @@ def _restore_tuning():
 
 
 def test_defaults_and_roundtrip(monkeypatch):
-    for var in ("QECSV_ZCHAIN", "QECSV_SNAKE", "QECSV_BATCH_WAVES_PER_CU", "QECSV_LOCKSTEP_MIB"):
+    for var in ("QECSV_ZCHAIN", "QECSV_SNAKE", "QECSV_BATCH_WAVES_PER_CU", "QECSV_LOCKSTEP_MIB",
+                "QECSV_PASS_WGS_PER_CU"):
         monkeypatch.delenv(var, raising=False)
     t = qs.tuning_get(5, "c128")
     assert set(t) == FIELDS and 1 <= t["zchain"] <= 4
@@ -42,7 +43,8 @@ def test_environment_overrides(monkeypatch):
 
 @pytest.mark.parametrize("bad", [dict(zchain=0), dict(zchain=5), dict(snake=2),
                                  dict(batch_waves_per_cu=0), dict(batch_waves_per_cu=33),
-                                 dict(lockstep_mib=0)])
+                                 dict(lockstep_mib=0), dict(pass_wgs_per_cu=-1),
+                                 dict(pass_wgs_per_cu=65)])
 def test_rejects_out_of_range(bad):
     with pytest.raises(qs.SvError):
         qs.tuning_set(3, "c64", **bad)
@@ -70,7 +72,8 @@ def test_save_load(tmp_path, monkeypatch):
 @pytest.mark.gpu
 @pytest.mark.parametrize("d,dtype", [(3, "c64"), (4, "c64"), (5, "c128")])
 def test_autotune_then_parity(d, dtype, monkeypatch):
-    for var in ("QECSV_ZCHAIN", "QECSV_SNAKE", "QECSV_BATCH_WAVES_PER_CU", "QECSV_LOCKSTEP_MIB"):
+    for var in ("QECSV_ZCHAIN", "QECSV_SNAKE", "QECSV_BATCH_WAVES_PER_CU", "QECSV_LOCKSTEP_MIB",
+                "QECSV_PASS_WGS_PER_CU"):
         monkeypatch.delenv(var, raising=False)
     print(f"case autotune d={d} {dtype}", flush=True)
     best, ms = qs.autotune(d, dtype)
@@ -78,6 +81,7 @@ def test_autotune_then_parity(d, dtype, monkeypatch):
     assert qs.tuning_get(d, dtype) == best
     if d == 5:
         assert best["zchain"] in (2, 3, 4) and best["snake"] in (0, 1)
+        assert best["pass_wgs_per_cu"] in (0, 8, 16)
         return
     if d == 4:
         assert best["lockstep_mib"] in (256, 1024, 4096)
