@@ -140,6 +140,33 @@ def batch_run(qs, d, n_traj, dtype, seed=7):
             "alg_gbs": alg / (g["gpu_ms"] * 1e-3) / 1e9, "tuning": tuning}
 
 
+def d3_textbook_run(qs):
+    """The d=3 workload: 9 data qubits + 1 ancilla, textbook H/CNOT/CZ
+    circuit, complex128, 3 rounds of 8 stabilizers, p = 1e-3 after every gate,
+    exp(-i 0.02 X) after each H, 1000 trajectories, seed 0 -- one batched
+    launch (registers in LDS).  Algorithmic bytes by the per-circuit model:
+    one read and one write of the 2^9-amplitude register per circuit, plus
+    the initial write and the final read."""
+    import numpy as np
+    import workloads
+    c = workloads.CONFIGS["d3_textbook_c128"]
+    d, R, n = c["d"], c["rounds"], c["n_traj"]
+    n_stab = qs.template_info(d, "textbook")[0]
+    tuning, _ = qs.autotune(d, "c128", "textbook")      # untimed
+    rounds = np.full(n, R, dtype=np.int32)
+    p = np.full(n, c["p"])
+    kw = dict(eps=c["eps"], zeta=c["zeta"], dtype="c128", max_rounds=R)
+    qs.run_batch(d, "textbook", rounds, p, c["seed"], traj0=10 ** 6, **kw)   # warm-up
+    ms = []
+    for _ in range(5):
+        ms.append(qs.run_batch(d, "textbook", rounds, p, c["seed"], **kw)["gpu_ms"])
+    t = float(np.median(ms))
+    alg = (R * n_stab + 1) * 2 * (1 << (d * d)) * 16 * n
+    return {"workload": "d3_textbook_c128", "trajectories": n, "launch_ms": t,
+            "trajectories_per_s": n / (t * 1e-3), "alg_gbs": alg / (t * 1e-3) / 1e9,
+            "frac_of_hbm_peak": alg / (t * 1e-3) / 1e9 / PEAK_HBM_GBS, "tuning": tuning}
+
+
 def precision_run(qs, n_traj, thetas=(0.01, 0.03, 0.05)):
     """Complex64 amplitudes (FP64 probabilities and renormalisation) against
     complex128 on the same draws: d=5 cross-resonance circuit, p=1e-3,
@@ -203,7 +230,8 @@ def main():
         copy_calibration(qs, torch, args.steps)
         return
     if args.only == "batch":
-        print(json.dumps({"batched": [batch_run(qs, 3, 65536, "c64"), batch_run(qs, 4, 4096, "c64")]}))
+        print(json.dumps({"d3": d3_textbook_run(qs),
+                          "batched": [batch_run(qs, 3, 65536, "c64"), batch_run(qs, 4, 4096, "c64")]}))
         return
     if args.only == "serving":
         print(json.dumps({"serving": [serving_run(qs, "companion", 5.0, 8.0)]}))
@@ -265,8 +293,9 @@ def main():
                      "circuits_per_pass": n_stab / r["passes_per_round"]},
     }
     if not args.no_extras:
+        out["d3"] = d3_textbook_run(qs)
+        out["d3_trajectories_per_s"] = out["d3"]["trajectories_per_s"]
         out["batched"] = [batch_run(qs, 3, 65536, "c64"), batch_run(qs, 4, 4096, "c64")]
-        out["d3_trajectories_per_s"] = out["batched"][0]["trajectories_per_s"]
         out["serving"] = [serving_run(qs, "companion", 5.0, 8.0), serving_run(qs, "spec", 2.0, 4.0)]
         out["p99_latency_ms"] = out["serving"][0]["p99_ms"]
         out["precision"] = precision_run(qs, args.precision_traj)

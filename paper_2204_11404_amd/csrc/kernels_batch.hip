@@ -124,6 +124,22 @@ __global__ __launch_bounds__(64) void k_batch_small(
     const double* __restrict__ pvec, const double* __restrict__ eps, int eps_stride,
     uint8_t* __restrict__ rec, int max_rounds, uint8_t* __restrict__ bits, int* __restrict__ err) {
   __shared__ SmallSlot<T> slots[2];
+  // the round template, the lane maps and the ZZ phases are read at every
+  // circuit: keep them in LDS rather than behind global-load latency
+  __shared__ TBlock lblocks[kSmallStab];
+  __shared__ SmallDesc lsd[kSmallStab];
+  __shared__ C2<T> lzz[kSmallBits * 2 + 1];
+  for (int i = threadIdx.x; i < ns * (int)(sizeof(TBlock) / 4); i += blockDim.x)
+    reinterpret_cast<uint32_t*>(lblocks)[i] = reinterpret_cast<const uint32_t*>(blocks)[i];
+  for (int i = threadIdx.x; i < ns * (int)(sizeof(SmallDesc) / 4); i += blockDim.x)
+    reinterpret_cast<uint32_t*>(lsd)[i] = reinterpret_cast<const uint32_t*>(sdesc)[i];
+  for (int i = threadIdx.x; i <= jc->n_edges && i <= 2 * kSmallBits; i += blockDim.x)
+    lzz[i] = C2<T>{(T)jc->zz[2 * i], (T)jc->zz[2 * i + 1]};
+  __syncthreads();
+  blocks = lblocks;
+  const int use_zz = jc->use_zz, zd = jc->d;
+  const uint32_t hmask = jc->hmask, vmask = jc->vmask;
+
   const int h = threadIdx.x >> 5;
   const int lane = threadIdx.x & 31;
   SmallSlot<T>& S = slots[h];
@@ -137,6 +153,7 @@ __global__ __launch_bounds__(64) void k_batch_small(
   int R = active ? rounds[t] : 0;
   int r = 0;
   double p = active ? pvec[t] : 0.0;
+  uint64_t tg = tstream[t], seed = tseed[t];  // draw stream of the current trajectory
   small_setup_tables(S, lane, n, ns, blocks, jc, eps + (size_t)t * eps_stride, p);
   __syncthreads();
   small_setup_kraus(S, lane, ns, blocks, err);
@@ -144,9 +161,8 @@ __global__ __launch_bounds__(64) void k_batch_small(
 
   while (__any(active)) {
     for (int s = 0; s < ns; ++s) {
-      const TBlock& b = blocks[s];
-      const SmallDesc& sd = sdesc[s];
-      const uint64_t tg = tstream[t], seed = tseed[t];
+      const TBlock& b = lblocks[s];
+      const SmallDesc& sd = lsd[s];
       const uint64_t k0 = (uint64_t)r * (uint64_t)draws_round + (uint64_t)b.draw_off;
       // 1. draws; did any noise location pick a Pauli?
       bool hit = false;
@@ -247,15 +263,14 @@ __global__ __launch_bounds__(64) void k_batch_small(
           for (int l = 0; l < b.w; ++l)
             if ((F >> l) & 1) fo |= sd.q_bit[l];
         const T sc = (T)scale;
-        const int use_zz = jc->use_zz;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           C2<T> o = v[j];
           if (xb && (__popc((uint32_t)(j & wmask) & F) & 1)) o = {-o.re, -o.im};
           const uint32_t g = (lb | sd.j_off[j]) ^ fo;
           if (use_zz) {
-            const int k = __popc((g ^ (g >> 1)) & jc->hmask) + __popc((g ^ (g >> jc->d)) & jc->vmask);
-            o = mulc(o, (T)jc->zz[2 * k], (T)jc->zz[2 * k + 1]);
+            const int k = __popc((g ^ (g >> 1)) & hmask) + __popc((g ^ (g >> zd)) & vmask);
+            o = mulc(o, lzz[k].re, lzz[k].im);
           }
           o.re *= sc;
           o.im *= sc;
@@ -277,7 +292,6 @@ __global__ __launch_bounds__(64) void k_batch_small(
           L += (double)a.re * (double)a.re + (double)a.im * (double)a.im;
         }
       }
-      const uint64_t tg = tstream[t], seed = tseed[t];
       const uint64_t kf = (uint64_t)R * (uint64_t)draws_round;
       const double uf = lane < n ? uniform(seed, tg, kf + (uint64_t)lane) : 0.0;
       int lo = 0, size = groups, level = 0;
@@ -320,6 +334,8 @@ __global__ __launch_bounds__(64) void k_batch_small(
           R = rounds[t];
           p = pvec[t];
           r = 0;
+          tg = tstream[t];
+          seed = tseed[t];
         }
       }
       // set-up of the next trajectory (barriers in wave-uniform control flow;
