@@ -11,8 +11,8 @@
 //                  outcomes of unit B's checks, on the device.
 //   k_final_sums / k_final_measure   sequential Z measurement of the data
 //                  register (highest label first) from a two-level sum tree.
-// General register ops behind sv_apply_gate / sv_apply_diag / sv_apply_fused /
-// sv_measure_reset_ancilla.
+//   k_commit       staged results of a replayed (graph) trajectory.
+// General register ops are in kernels_ops.hip.
 #include "qec_common.h"
 
 namespace qec {
@@ -868,241 +868,6 @@ __global__ void k_commit(const uint8_t* __restrict__ rec_s, const double* __rest
     *cur = c + 1;
     *stream = traj0 + c + 1;
   }
-}
-
-// --------------------------------------------------------- register ops --
-// Plain streaming copy, 16-byte elements, four per thread per iteration.
-__global__ __launch_bounds__(256) void k_copy16(double2* __restrict__ dst,
-                                                const double2* __restrict__ src, uint64_t n) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 4;
-  for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x) * 4 + threadIdx.x; i < n; i += stride) {
-    double2 v[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (i + (uint64_t)k * blockDim.x < n) v[k] = src[i + (uint64_t)k * blockDim.x];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (i + (uint64_t)k * blockDim.x < n) dst[i + (uint64_t)k * blockDim.x] = v[k];
-  }
-}
-
-struct Mat2 { double m[8]; };
-struct Mat4 { double m[32]; };
-struct Diag32 { double ph[64]; };
-
-template <typename T>
-__global__ void k_fill_basis(T* __restrict__ st, uint64_t n_amp, uint64_t idx) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_amp) return;
-  st2(st, i, C2<T>{(T)(i == idx ? 1 : 0), (T)0});
-}
-
-template <typename T>
-__global__ void k_logical0(T* __restrict__ st, uint64_t n_amp, const JobConst* __restrict__ jc) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_amp) return;
-  bool in = (i >> jc->n) == 0;
-  uint32_t x = (uint32_t)(i & ((1ull << jc->n) - 1));
-  for (int k = 0; k < jc->n_x; ++k)
-    if (x & jc->span_piv[k]) x ^= jc->span_vec[k];
-  in = in && (x == 0);
-  st2(st, i, C2<T>{in ? (T)jc->amp0 : (T)0, (T)0});
-}
-
-__device__ __forceinline__ uint64_t insert_zero(uint64_t x, int q) {
-  const uint64_t lo = x & ((1ull << q) - 1);
-  return ((x >> q) << (q + 1)) | lo;
-}
-
-template <typename T>
-__global__ void k_gate1(T* __restrict__ st, uint64_t n_pairs, int q, Mat2 M) {
-  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
-  const uint64_t i0 = insert_zero(p, q), i1 = i0 | (1ull << q);
-  const C2<T> a = ld2(st, i0), b = ld2(st, i1);
-  C2<T> o0, o1;
-  o0.re = (T)M.m[0] * a.re - (T)M.m[1] * a.im + (T)M.m[2] * b.re - (T)M.m[3] * b.im;
-  o0.im = (T)M.m[0] * a.im + (T)M.m[1] * a.re + (T)M.m[2] * b.im + (T)M.m[3] * b.re;
-  o1.re = (T)M.m[4] * a.re - (T)M.m[5] * a.im + (T)M.m[6] * b.re - (T)M.m[7] * b.im;
-  o1.im = (T)M.m[4] * a.im + (T)M.m[5] * a.re + (T)M.m[6] * b.im + (T)M.m[7] * b.re;
-  st2(st, i0, o0);
-  st2(st, i1, o1);
-}
-
-// qlo < qhi; local index bit 0 = q0 (first listed), bit 1 = q1.
-template <typename T>
-__global__ void k_gate2(T* __restrict__ st, uint64_t n_quads, int q0, int q1, Mat4 M) {
-  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_quads) return;
-  const int qlo = q0 < q1 ? q0 : q1, qhi = q0 < q1 ? q1 : q0;
-  const uint64_t i00 = insert_zero(insert_zero(p, qlo), qhi);
-  const uint64_t b0 = 1ull << q0, b1 = 1ull << q1;
-  const uint64_t idx[4] = {i00, i00 | b0, i00 | b1, i00 | b0 | b1};
-  C2<T> v[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) v[r] = ld2(st, idx[r]);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    T re = 0, im = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const T mr = (T)M.m[8 * r + 2 * c], mi = (T)M.m[8 * r + 2 * c + 1];
-      re += mr * v[c].re - mi * v[c].im;
-      im += mr * v[c].im + mi * v[c].re;
-    }
-    st2(st, idx[r], C2<T>{re, im});
-  }
-}
-
-template <typename T>
-__global__ void k_diag(T* __restrict__ st, uint64_t n_amp, int k, int q0, int q1, int q2, int q3, int q4, Diag32 D) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_amp) return;
-  const int qs[5] = {q0, q1, q2, q3, q4};
-  int loc = 0;
-  for (int j = 0; j < k; ++j) loc |= (int)((i >> qs[j]) & 1) << j;
-  const C2<T> a = ld2(st, i);
-  st2(st, i, mulc(a, (T)D.ph[2 * loc], (T)D.ph[2 * loc + 1]));
-}
-
-// Dense K-qubit matrix on sorted-insert groups; matrix staged in LDS.
-template <typename T, int K>
-__global__ __launch_bounds__(256) void k_fused(T* __restrict__ st, uint64_t n_groups,
-                                               const double* __restrict__ mat, int q0, int q1,
-                                               int q2, int q3, int q4) {
-  constexpr int N = 1 << K;
-  __shared__ T sm[2 * N * N];
-  for (int i = threadIdx.x; i < 2 * N * N; i += blockDim.x) sm[i] = (T)mat[i];
-  __syncthreads();
-  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n_groups) return;
-  const int qs[5] = {q0, q1, q2, q3, q4};
-  // insert zeros at the sorted qubit positions
-  int sorted[5];
-  for (int j = 0; j < K; ++j) sorted[j] = qs[j];
-  for (int a = 1; a < K; ++a)
-    for (int b = a; b > 0 && sorted[b - 1] > sorted[b]; --b) {
-      const int t = sorted[b]; sorted[b] = sorted[b - 1]; sorted[b - 1] = t;
-    }
-  uint64_t base = g;
-  for (int j = 0; j < K; ++j) base = insert_zero(base, sorted[j]);
-  uint64_t off[N];
-  C2<T> v[N];
-#pragma unroll
-  for (int x = 0; x < N; ++x) {
-    uint64_t o = base;
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-      if ((x >> j) & 1) o |= 1ull << qs[j];
-    off[x] = o;
-    v[x] = ld2(st, o);
-  }
-#pragma unroll
-  for (int r = 0; r < N; ++r) {
-    T re = 0, im = 0;
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-      const T mr = sm[2 * (N * r + c)], mi = sm[2 * (N * r + c) + 1];
-      re += mr * v[c].re - mi * v[c].im;
-      im += mr * v[c].im + mi * v[c].re;
-    }
-    st2(st, off[r], C2<T>{re, im});
-  }
-}
-
-// Walsh-Hadamard transform over K qubits (bits q[0..K)) of the register, one
-// group of 2^K amplitudes per thread, times `scale` (the X-basis readout
-// applies H to every data qubit as ceil(n / 5) such passes).
-template <typename T, int K>
-__global__ __launch_bounds__(256) void k_wht_group(T* __restrict__ st, uint64_t n_groups, int q0,
-                                                   int q1, int q2, int q3, int q4, double scale) {
-  constexpr int N = 1 << K;
-  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n_groups) return;
-  const int qs[5] = {q0, q1, q2, q3, q4};
-  int sorted[5];
-  for (int j = 0; j < K; ++j) sorted[j] = qs[j];
-  for (int a = 1; a < K; ++a)
-    for (int b = a; b > 0 && sorted[b - 1] > sorted[b]; --b) {
-      const int t = sorted[b];
-      sorted[b] = sorted[b - 1];
-      sorted[b - 1] = t;
-    }
-  uint64_t base = g;
-  for (int j = 0; j < K; ++j) base = insert_zero(base, sorted[j]);
-  uint64_t off[N];
-  C2<T> v[N];
-#pragma unroll
-  for (int x = 0; x < N; ++x) {
-    uint64_t o = base;
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-      if ((x >> j) & 1) o |= 1ull << qs[j];
-    off[x] = o;
-    v[x] = ld2(st, o);
-  }
-  wht<T, K>(v);
-#pragma unroll
-  for (int x = 0; x < N; ++x)
-    st2(st, off[x], C2<T>{(T)((double)v[x].re * scale), (T)((double)v[x].im * scale)});
-}
-
-// S0 / S1 over bit q: per-workgroup partial sums (fixed order).
-struct MeasOut {
-  double S0, S1, p1;
-  int m;
-  int pad;
-};
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_measure_sums(const T* __restrict__ st, uint64_t n_amp, int q,
-                                                      double2* __restrict__ partials) {
-  __shared__ double red[16];
-  double s0 = 0.0, s1 = 0.0;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_amp; i += stride) {
-    const C2<T> a = ld2(st, i);
-    const double w = (double)a.re * (double)a.re + (double)a.im * (double)a.im;
-    if ((i >> q) & 1) s1 += w; else s0 += w;
-  }
-  block_sum2(s0, s1, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = make_double2(s0, s1);
-}
-
-// Reduce the partials in a fixed order and decide (forced >= 0 overrides u).
-__global__ __launch_bounds__(256) void k_measure_decide(const double2* __restrict__ partials, int n,
-                                                        double u, int forced,
-                                                        MeasOut* __restrict__ out) {
-  __shared__ double red[16];
-  double a0 = 0.0, a1 = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double2 v = partials[i];
-    a0 += v.x;
-    a1 += v.y;
-  }
-  block_sum2(a0, a1, red);
-  if (threadIdx.x == 0) {
-    const double p1 = clamp_p1(a1 / (a0 + a1));
-    out->S0 = a0;
-    out->S1 = a1;
-    out->p1 = p1;
-    out->m = forced >= 0 ? forced : ((u < p1) ? 1 : 0);
-  }
-}
-
-template <typename T>
-__global__ void k_project(T* __restrict__ st, uint64_t n_pairs, int q, const MeasOut* __restrict__ mo) {
-  const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
-  const int m = mo->m;
-  const double Sm = m ? mo->S1 : mo->S0;
-  const double scale = 1.0 / sqrt(Sm);
-  const uint64_t i0 = insert_zero(p, q), i1 = i0 | (1ull << q);
-  C2<T> a = ld2(st, m ? i1 : i0);
-  a.re = (T)((double)a.re * scale);
-  a.im = (T)((double)a.im * scale);
-  st2(st, i0, a);
-  st2(st, i1, C2<T>{(T)0, (T)0});
 }
 
 }  // namespace qec

@@ -27,6 +27,7 @@
 #include "qecsv.h"
 #include "qec_common.h"
 #include "kernels.hip"
+#include "kernels_ops.hip"
 #include "kernels_batch.hip"
 
 using namespace qec;
