@@ -59,6 +59,20 @@ def counted_traffic():
         return None
 
 
+_TUNING_FILE = None
+
+
+def tune(qs, d, dtype, gateset="cr"):
+    """Launch parameters for (d, dtype): from the --tuning file when it was
+    loaded, else autotuned (and appended to the file)."""
+    if _TUNING_FILE and os.path.exists(_TUNING_FILE):
+        return qs.tuning_get(d, dtype)
+    best, _ = qs.autotune(d, dtype, gateset)
+    if _TUNING_FILE:
+        qs.tuning_save(_TUNING_FILE)
+    return best
+
+
 def cpu_baseline(c, eps, n_blocks):
     """Oracle (complex128, gate by gate on 26 qubits) on the first n_blocks
     noisy circuits of a round; scaled to ms per 24-circuit round."""
@@ -130,7 +144,7 @@ def batch_run(qs, d, n_traj, dtype, seed=7):
     import workloads
     n_stab, n_sites, _ = qs.template_info(d, "cr")
     R, p, eps = workloads.batch_params(n_traj, n_sites, seed)
-    tuning, _ = qs.autotune(d, dtype)          # untimed: launch parameters for this shape
+    tuning = tune(qs, d, dtype)          # untimed: launch parameters for this shape
     qs.run_batch(d, "cr", R[:256], p[:256], seed, eps_site=eps[:256], dtype=dtype)
     g = qs.run_batch(d, "cr", R, p, seed, eps_site=eps, dtype=dtype, max_rounds=9)
     amp = 8 if dtype == "c64" else 16
@@ -152,7 +166,7 @@ def d3_textbook_run(qs):
     c = workloads.CONFIGS["d3_textbook_c128"]
     d, R, n = c["d"], c["rounds"], c["n_traj"]
     n_stab = qs.template_info(d, "textbook")[0]
-    tuning, _ = qs.autotune(d, "c128", "textbook")      # untimed
+    tuning = tune(qs, d, "c128", "textbook")      # untimed
     rounds = np.full(n, R, dtype=np.int32)
     p = np.full(n, c["p"])
     kw = dict(eps=c["eps"], zeta=c["zeta"], dtype="c128", max_rounds=R)
@@ -216,6 +230,9 @@ def main():
                     help="skip the batched-launch, serving and precision measurements")
     ap.add_argument("--precision-traj", type=int, default=4,
                     help="trajectories per angle in the complex64 vs complex128 comparison")
+    ap.add_argument("--tuning", default=None,
+                    help="launch-parameter file: load it instead of autotuning if it exists, "
+                         "else autotune and write it (profiled runs then contain no trials)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -226,6 +243,10 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
+    global _TUNING_FILE
+    _TUNING_FILE = args.tuning
+    if args.tuning and os.path.exists(args.tuning):
+        qs.tuning_load(args.tuning)
     if args.copy_only:
         copy_calibration(qs, torch, args.steps)
         return
@@ -246,7 +267,7 @@ def main():
     kw = dict(d=d, gateset="cr", rounds=R, seed=c["seed"], p=c["p"], eps_site=eps,
               zeta=c["zeta"], dtype=args.dtype)
 
-    tuning, _ = qs.autotune(d, args.dtype)   # untimed: launch parameters for this shape
+    tuning = tune(qs, d, args.dtype)   # untimed: launch parameters for this shape
     if args.warmup > 0:
         qs.run_rounds(n_traj=args.warmup, traj0=1_000_000, **kw)
     torch.cuda.synchronize()

@@ -124,19 +124,12 @@ __global__ __launch_bounds__(64) void k_batch_small(
     const double* __restrict__ pvec, const double* __restrict__ eps, int eps_stride,
     uint8_t* __restrict__ rec, int max_rounds, uint8_t* __restrict__ bits, int* __restrict__ err) {
   __shared__ SmallSlot<T> slots[2];
-  // the round template, the lane maps and the ZZ phases are read at every
-  // circuit: keep them in LDS rather than behind global-load latency
-  __shared__ TBlock lblocks[kSmallStab];
-  __shared__ SmallDesc lsd[kSmallStab];
+  // ZZ phases are read per amplitude: keep them in LDS (the round template
+  // stays in global memory: more LDS per workgroup would cost occupancy)
   __shared__ C2<T> lzz[kSmallBits * 2 + 1];
-  for (int i = threadIdx.x; i < ns * (int)(sizeof(TBlock) / 4); i += blockDim.x)
-    reinterpret_cast<uint32_t*>(lblocks)[i] = reinterpret_cast<const uint32_t*>(blocks)[i];
-  for (int i = threadIdx.x; i < ns * (int)(sizeof(SmallDesc) / 4); i += blockDim.x)
-    reinterpret_cast<uint32_t*>(lsd)[i] = reinterpret_cast<const uint32_t*>(sdesc)[i];
   for (int i = threadIdx.x; i <= jc->n_edges && i <= 2 * kSmallBits; i += blockDim.x)
     lzz[i] = C2<T>{(T)jc->zz[2 * i], (T)jc->zz[2 * i + 1]};
   __syncthreads();
-  blocks = lblocks;
   const int use_zz = jc->use_zz, zd = jc->d;
   const uint32_t hmask = jc->hmask, vmask = jc->vmask;
 
@@ -161,8 +154,8 @@ __global__ __launch_bounds__(64) void k_batch_small(
 
   while (__any(active)) {
     for (int s = 0; s < ns; ++s) {
-      const TBlock& b = lblocks[s];
-      const SmallDesc& sd = lsd[s];
+      const TBlock& b = blocks[s];
+      const SmallDesc& sd = sdesc[s];
       const uint64_t k0 = (uint64_t)r * (uint64_t)draws_round + (uint64_t)b.draw_off;
       // 1. draws; did any noise location pick a Pauli?
       bool hit = false;
