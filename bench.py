@@ -60,12 +60,13 @@ def counted_traffic():
 
 
 _TUNING_FILE = None
+_TUNING_LOADED = False
 
 
 def tune(qs, d, dtype, gateset="cr"):
-    """Launch parameters for (d, dtype): from the --tuning file when it was
-    loaded, else autotuned (and appended to the file)."""
-    if _TUNING_FILE and os.path.exists(_TUNING_FILE):
+    """Launch parameters for (d, dtype): from the --tuning file when it
+    existed at start-up, else autotuned (and written to the file)."""
+    if _TUNING_LOADED:
         return qs.tuning_get(d, dtype)
     best, _ = qs.autotune(d, dtype, gateset)
     if _TUNING_FILE:
@@ -243,10 +244,11 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
-    global _TUNING_FILE
+    global _TUNING_FILE, _TUNING_LOADED
     _TUNING_FILE = args.tuning
     if args.tuning and os.path.exists(args.tuning):
         qs.tuning_load(args.tuning)
+        _TUNING_LOADED = True
     if args.copy_only:
         copy_calibration(qs, torch, args.steps)
         return
@@ -304,6 +306,7 @@ def main():
         # stabilizer circuit); exceeds the bytes moved when passes apply chains
         "hbm_gbs_algorithmic": alg_gbs,
         "tuning": tuning,
+        "kernel_sources_sha256": kernel_source_hash(),
         "gpu_ms_device": r["gpu_ms"],
         "trajectories_per_s": args.steps / wall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
