@@ -41,6 +41,7 @@ class _Job(ctypes.Structure):
         ("eps", ctypes.c_double),
         ("xbasis", ctypes.c_int),
         ("virtual_z", ctypes.c_int),
+        ("idle", ctypes.c_int),
     ]
 
 
@@ -118,12 +119,13 @@ def template_counts(d, gateset):
 
 
 def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=None,
-                   want_state=False, twirl=False, xbasis=False, virtual_z=False):
+                   want_state=False, twirl=False, xbasis=False, virtual_z=False, idle=False):
     """One Monte Carlo trajectory.
 
     twirl: Pauli-twirled over-rotations; xbasis: X-basis memory (logical |+>,
     final X measurement of the data qubits); virtual_z: the Rz restores of the
-    cross-resonance Z checks without over-rotation.  Returns
+    cross-resonance Z checks without over-rotation; idle: one-qubit noise on
+    the waiting qubits of the circuit at every step.  Returns
     dict(records=uint8[rounds, n_stab], final_bits=uint8[d*d],
     p1=float64[rounds, n_stab], state=complex128[2^(d*d)] or None) where
     `state` is the data register just before the final measurement."""
@@ -134,6 +136,7 @@ def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=N
     job.twirl = 1 if twirl else 0
     job.xbasis = 1 if xbasis else 0
     job.virtual_z = 1 if virtual_z else 0
+    job.idle = 1 if idle else 0
     keep = None
     if eps_site is not None:
         keep = np.ascontiguousarray(eps_site, dtype=np.float64)

@@ -27,8 +27,9 @@ _PAULI_XZ = {1: (1, 0), 2: (1, 1), 3: (0, 1)}  # X, Y, Z -> (x, z)
 
 
 class FrameSampler:
-    def __init__(self, d, gateset, shots, rng):
+    def __init__(self, d, gateset, shots, rng, idle=False):
         self.d = d
+        self.idle = idle
         self.gateset = gateset
         self.stabs = _layout(d)
         self.nq = d * d + 1
@@ -97,18 +98,28 @@ class FrameSampler:
                     self.z[:, qq] ^= hit
 
     # --- circuit ------------------------------------------------------------
+    def waiting(self, slots, busy, p):
+        """Idle noise of one step: N1 on the check's data qubits other than
+        `busy` (a label, or 0), in slot order."""
+        if self.idle:
+            for q in slots:
+                if q and q != busy:
+                    self.noise1(q - 1, p)
+
     def stabilizer(self, typ, slots, p):
         a = self.anc
         if self.gateset == 0:
             if typ == "X":
                 self.rx(a)          # Rx^dag: same Clifford frame action as Rx
                 self.noise1(a, p)
+                self.waiting(slots, 0, p)
                 for q in slots:
                     if q:
                         self.rzx(a, q - 1)
                         self.noise2(a, q - 1, p)
                     else:
                         self.noise1(a, p)
+                    self.waiting(slots, q, p)
                 self.rx(a)
                 self.noise1(a, p)
                 for q in slots:
@@ -122,13 +133,17 @@ class FrameSampler:
                         self.noise2(q - 1, a, p)
                     else:
                         self.noise1(a, p)
+                    self.waiting(slots, q, p)
                 for q in slots:
                     if q:
                         self.rz(q - 1)
                         self.noise1(q - 1, p)
+                if self.idle:
+                    self.noise1(a, p)
         else:
             self.h(a)
             self.noise1(a, p)
+            self.waiting(slots, 0, p)
             for q in slots:
                 if q:
                     if typ == "X":
@@ -136,8 +151,10 @@ class FrameSampler:
                     else:
                         self.cz(a, q - 1)
                     self.noise2(a, q - 1, p)
+                    self.waiting(slots, q, p)
             self.h(a)
             self.noise1(a, p)
+            self.waiting(slots, 0, p)
         flip = self.x[:, a].copy()
         self.x[:, a] = 0
         self.z[:, a] = 0
@@ -157,7 +174,8 @@ class FrameSampler:
         return rec, final
 
 
-def sample(d, gateset, rounds, p, shots, seed=0, basis="Z"):
-    """Record flips and final-bit flips relative to the noiseless reference."""
-    fs = FrameSampler(d, gateset, shots, np.random.default_rng(seed))
+def sample(d, gateset, rounds, p, shots, seed=0, basis="Z", idle=False):
+    """Record flips and final-bit flips relative to the noiseless reference;
+    idle: one-qubit noise on the waiting qubits of every step."""
+    fs = FrameSampler(d, gateset, shots, np.random.default_rng(seed), idle)
     return fs.run(rounds, p, basis)

@@ -337,6 +337,7 @@ struct Job {
   int twirl;               // 1: Pauli-twirled over-rotations (see site_rot1)
   int xbasis;              // 1: X-basis memory (logical |+>, final X measurement)
   int virtual_z;           // 1: Rz restores are exact (virtual Z, Fig. 4)
+  int idle;                // 1: one-qubit noise on the circuit's waiting qubits at each step
 };
 
 struct Ctx {
@@ -415,7 +416,23 @@ void noise2(State& s, Ctx& cx, int q1, int q2) {
   }
 }
 
-// Gates and noise of one stabilizer circuit on ancilla `anc`.
+// Idle noise of one step (Sec. III.A: the one-qubit channel acts on every
+// qubit of the measurement circuit at each step, waiting qubits included):
+// N1 on each data qubit of the check, in slot order, except `busy` (the label
+// of the data qubit the step's gate acts on, or 0).  Only with job.idle.
+void idle_data(State& s, Ctx& cx, const Stab& st, int busy) {
+  if (!cx.job->idle) return;
+  for (int j = 0; j < 4; ++j) {
+    const int q = st.slot[j];
+    if (q && q != busy) noise1(s, cx, q - 1);
+  }
+}
+
+// Gates and noise of one stabilizer circuit on ancilla `anc`.  With job.idle
+// the circuit runs in steps (cross-resonance X check: Rx^dag | one per slot |
+// Rx with the restores; Z check: one per slot | the restores; textbook: H |
+// one per data qubit | H) and after each step the check's data qubits that
+// the step leaves alone get N1, and in the Z check's restore step the ancilla.
 void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
   const double q4 = kPi / 4.0;
   const int gateset = cx.job->gateset;
@@ -424,6 +441,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
       // Rx^dag(pi/2) on the ancilla: rotation about -X.
       site_rot1(s, cx, anc, 1, -1.0, q4);
       noise1(s, cx, anc);
+      idle_data(s, cx, st, 0);
       for (int j = 0; j < 4; ++j) {
         const int q = st.slot[j];
         if (q) {
@@ -432,6 +450,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
         } else {
           noise1(s, cx, anc);
         }
+        idle_data(s, cx, st, q);
       }
       site_rot1(s, cx, anc, 1, 1.0, q4);
       noise1(s, cx, anc);
@@ -450,6 +469,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
         } else {
           noise1(s, cx, anc);
         }
+        idle_data(s, cx, st, q);
       }
       for (int j = 0; j < 4; ++j) {
         const int q = st.slot[j];
@@ -462,6 +482,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
         }
         noise1(s, cx, q - 1);
       }
+      if (cx.job->idle) noise1(s, cx, anc);  // the ancilla waits during the restores
     }
   } else {
     // Textbook circuit: H, entangling gates, H on the ancilla; each H is
@@ -469,15 +490,18 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
     hadamard(s, anc);
     site_rot1(s, cx, anc, 1, 1.0, 0.0);
     noise1(s, cx, anc);
+    idle_data(s, cx, st, 0);
     for (int j = 0; j < 4; ++j) {
       const int q = st.slot[j];
       if (!q) continue;
       if (st.type == 0) cnot(s, anc, q - 1); else cz(s, anc, q - 1);
       noise2(s, cx, anc, q - 1);
+      idle_data(s, cx, st, q);
     }
     hadamard(s, anc);
     site_rot1(s, cx, anc, 1, 1.0, 0.0);
     noise1(s, cx, anc);
+    idle_data(s, cx, st, 0);
   }
 }
 
@@ -617,6 +641,7 @@ typedef struct {
   double eps;
   int xbasis;     // 1: X-basis memory
   int virtual_z;  // 1: Rz restores exact
+  int idle;       // 1: idle noise on the waiting qubits of every step
 } orc_job;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
@@ -648,7 +673,8 @@ int orc_template_counts(int d, int gateset, int* n_stab, int* n_sites, int* n_dr
 int orc_run_trajectory(const orc_job* j, unsigned long long t, uint8_t* records,
                        uint8_t* final_bits, double* p1_trace, double* final_state) {
   if (!j || j->d < 2 || j->d > 5 || j->rounds < 0) return -1;
-  Job job{j->d, j->gateset, j->rounds, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl, j->xbasis, j->virtual_z};
+  Job job{j->d,     j->gateset, j->rounds, j->seed,   j->p,         j->zeta,
+          j->eps_site, j->eps,   j->twirl,  j->xbasis, j->virtual_z, j->idle};
   Output out{records, final_bits, p1_trace, final_state};
   return run_trajectory(job, t, out);
 }
@@ -657,7 +683,7 @@ int orc_run_trajectory(const orc_job* j, unsigned long long t, uint8_t* records,
 // 2^(d*d) interleaved complex.
 int orc_logical_state(int d, int gateset, int xbasis, double* out) {
   if (d < 2 || d > 5) return -1;
-  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0, 0, xbasis, 0};
+  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0, 0, xbasis, 0, 0};
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);
   if (prepare_logical_zero(s, job, stabs) != 0) return -1;
@@ -692,8 +718,8 @@ int orc_apply_gate(double* state, int n, int k, const int* qubits, const double*
 // the corresponding part of a trajectory.
 double orc_time_blocks(const orc_job* j, unsigned long long t, int n_blocks, int* threads) {
   if (!j || j->d < 2 || j->d > 5 || n_blocks < 1) return -1.0;
-  Job job{j->d, j->gateset, 1, j->seed, j->p, j->zeta, j->eps_site, j->eps, j->twirl, j->xbasis,
-          j->virtual_z};
+  Job job{j->d,     j->gateset, 1,         j->seed,   j->p,         j->zeta,
+          j->eps_site, j->eps,     j->twirl, j->xbasis, j->virtual_z, j->idle};
   const int d = job.d, anc = d * d;
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);

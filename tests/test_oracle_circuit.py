@@ -170,7 +170,7 @@ def test_final_measurement_is_born_sampling():
 
 # ---- dense brute force of a whole d=2 trajectory with the same draws ------
 
-def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta, twirl=False):
+def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta, twirl=False, idle=False):
     nd = d * d
     n = nd + 1
     anc = nd
@@ -221,6 +221,13 @@ def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta, twirl=False):
         if draw() < np.sin(eps) ** 2:
             psi = g(qs, M) @ psi
 
+    def wait(slots, busy):
+        """Idle step noise: N1 on the check's other data qubits, slot order."""
+        if idle:
+            for q in slots:
+                if q and q != busy:
+                    n1(q - 1)
+
     # ZX with bit0 = control (Z), bit1 = target (X): kron(X, Z)
     ZX = np.kron(X, Z)
     edges = []
@@ -241,12 +248,13 @@ def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta, twirl=False):
         for i, (typ, slots) in enumerate(oracle.layout(d)):
             if gateset == CR:
                 if typ == "X":
-                    site([anc], X, -1, q4); n1(anc)
+                    site([anc], X, -1, q4); n1(anc); wait(slots, 0)
                     for q in slots:
                         if q:
                             site([anc, q - 1], ZX, 1, q4); n2(anc, q - 1)
                         else:
                             n1(anc)
+                        wait(slots, q)
                     site([anc], X, 1, q4); n1(anc)
                     for q in slots:
                         if q:
@@ -257,19 +265,22 @@ def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta, twirl=False):
                             site([q - 1, anc], ZX, 1, q4); n2(q - 1, anc)
                         else:
                             n1(anc)
+                        wait(slots, q)
                     for q in slots:
                         if q:
                             site([q - 1], Z, 1, q4); n1(q - 1)
+                    if idle:
+                        n1(anc)
             else:
-                psi = g([anc], H) @ psi; site([anc], X, 1, 0.0); n1(anc)
+                psi = g([anc], H) @ psi; site([anc], X, 1, 0.0); n1(anc); wait(slots, 0)
                 for q in slots:
                     if q:
                         if typ == "X":
                             m = np.zeros((4, 4)); m[0, 0] = m[2, 2] = m[3, 1] = m[1, 3] = 1
                         else:
                             m = np.diag([1, 1, 1, -1]).astype(float)
-                        psi = g([anc, q - 1], m) @ psi; n2(anc, q - 1)
-                psi = g([anc], H) @ psi; site([anc], X, 1, 0.0); n1(anc)
+                        psi = g([anc, q - 1], m) @ psi; n2(anc, q - 1); wait(slots, q)
+                psi = g([anc], H) @ psi; site([anc], X, 1, 0.0); n1(anc); wait(slots, 0)
             psi = zzphase * psi
             m, _, psi = sv.measure_reset(psi, anc, u=draw())
             rec[r, i] = m
@@ -411,3 +422,66 @@ def test_virtual_z_restores_carry_no_over_rotation():
     c = oracle.run_trajectory(d, CR, 2, seed=4, t=0, p=0.0, eps_site=es, want_state=True)
     assert np.array_equal(a["p1"], b["p1"]) and np.allclose(a["state"], b["state"], atol=1e-14)
     assert np.max(np.abs(c["p1"] - b["p1"])) > 1e-6   # without the flag they do act
+
+
+# ---- idle noise on the waiting qubits of each step --------------------------
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+def test_dense_brute_force_d2_idle_trajectories(gateset):
+    """Idle noise (N1 on the check's data qubits that a step leaves alone, and
+    on the ancilla during the Z check's restores) against the dense brute force
+    with the same draws, also with twirled over-rotations."""
+    d, R = 2, 2
+    for t, (p, eps, zeta, tw) in enumerate([(0.1, 0.0, 0.0, False), (0.15, 0.05, 0.03, False),
+                                            (0.12, 0.2, 0.02, True)]):
+        rec, fb, st = _dense_trajectory(d, gateset, R, 29, t, p, eps, zeta, twirl=tw, idle=True)
+        o = oracle.run_trajectory(d, gateset, R, seed=29, t=t, p=p, eps=eps, zeta=zeta,
+                                  want_state=True, twirl=tw, idle=True)
+        assert np.array_equal(o["records"], rec)
+        assert np.array_equal(o["final_bits"], fb)
+        assert np.allclose(o["state"], st, atol=1e-12)
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+def test_idle_noise_first_check_flip_probability(gateset):
+    """First check of round 1 (X1X2, slots 2, 1, wait, wait) on logical |0>,
+    Pauli noise only.  Propagating the measured Z of the ancilla back through
+    the circuit gives the operator each location must anticommute with to flip
+    the outcome: a one-qubit location flips with probability 2p/3, a two-qubit
+    one with 8p/15.  Cross-resonance circuit: four one-qubit and two two-qubit
+    flipping locations, plus three idle ones (data 1 and 2 waiting during
+    Rx^dag, data 1 waiting during the first cross-resonance gate).  Textbook:
+    two and two, plus three idle ones (data 1 and 2 after the first H, data 1
+    during the first CNOT).  P(flip) = (1 - prod(1 - 2 q)) / 2."""
+    p, n = 0.03, 20000
+    r0 = trivial_bits(2, gateset)[0]
+    k1 = 4 if gateset == CR else 2
+    for idle, extra in ((False, 0), (True, 3)):
+        flips = sum(int(oracle.run_trajectory(2, gateset, 1, seed=31, t=t, p=p, idle=idle)["records"][0, 0]) ^ int(r0)
+                    for t in range(n))
+        q = 0.5 * (1.0 - (1 - 4 * p / 3) ** (k1 + extra) * (1 - 16 * p / 15) ** 2)
+        assert abs(flips / n - q) < 4 * np.sqrt(q * (1 - q) / n), (idle, flips / n, q)
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+def test_idle_noise_pauli_only_matches_frame_sampler(gateset):
+    """Idle noise in a Pauli-only d=3 run: detector and logical-Z flip rates
+    agree with the Pauli-frame sampler run with the same step schedule."""
+    d, R, N, p = 3, 2, 2500, 0.008
+    tb = trivial_bits(d, gateset)
+    recs, zl = [], []
+    for t in range(N):
+        r = oracle.run_trajectory(d, gateset, R, seed=37, t=t, p=p, idle=True)
+        recs.append(r["records"] ^ tb)
+        zl.append(sum(int(r["final_bits"][q]) for q in range(d)) % 2)
+    recs = np.array(recs)
+    frec, ffin = frame.sample(d, gateset, R, p, 200000, seed=5, idle=True)
+    a = _detectors(recs).mean(0)
+    b = _detectors(frec).mean(0)
+    sig = np.sqrt(np.maximum(b * (1 - b), 1.0 / N) / N)
+    assert np.max(np.abs((a - b) / sig)) < 4.0
+    zl_f = np.bitwise_xor.reduce(ffin[:, :d], axis=1).mean()
+    assert abs(np.mean(zl) - zl_f) < 4.0 * np.sqrt(max(zl_f * (1 - zl_f), 1.0 / N) / N)
+    # idle noise raises the detector rates over the run without it
+    f0, _ = frame.sample(d, gateset, R, p, 200000, seed=5)
+    assert _detectors(frec).mean() > 1.2 * _detectors(f0).mean()
