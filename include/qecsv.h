@@ -90,6 +90,16 @@ typedef enum {
                           same error probability as the coherent error
                           (Sec. III.A); the draw enumeration gains one draw per
                           rotation, placed before that gate's noise draw */
+#define SV_RUN_IDLE_NOISE 16 /* one-qubit depolarizing noise on the waiting
+                                qubits of every step (Sec. III.A: the channel
+                                acts on every qubit of the measurement circuit
+                                at each step).  Steps: cross-resonance X check
+                                Rx^dag | each slot | Rx with the restores; Z
+                                check each slot | the restores; textbook H |
+                                each data qubit | H.  After a step, one N1 draw
+                                per data qubit of the check that the step does
+                                not touch (slot order), and one on the ancilla
+                                after the Z check's restores */
 
 typedef struct sv_state_s* sv_state;
 
@@ -174,6 +184,14 @@ sv_status sv_measure_reset_ancilla_forced(sv_state s, int anc, int outcome, doub
  * draws (noise locations plus one per measurement). */
 sv_status sv_template_info(int d, int gateset, int* n_stab, int* n_sites, int* n_draws_per_round);
 
+/* Host-side self-check of the register-pass layouts that sv_run_rounds would
+ * use for (d, gateset) with Z chains of at most zchain checks: every tile
+ * layout partitions its bits between lanes and register slots, the regrouping
+ * layouts cover the same tile, and each unit's qubits sit where its mode needs
+ * them.  No device work.  *n_passes (optional) receives the pass count of one
+ * round sequence; SV_EINVAL names the first failing pass. */
+sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int* n_passes);
+
 typedef struct sv_job {
   int d;               /* code distance, 2..5 */
   int gateset;         /* sv_gateset */
@@ -181,7 +199,8 @@ typedef struct sv_job {
   int dtype;           /* sv_dtype of the state */
   int n_traj;          /* trajectories */
   int flags;           /* SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS |
-                          SV_RUN_VIRTUAL_Z (sv_run_rounds only; with
+                          SV_RUN_VIRTUAL_Z | SV_RUN_IDLE_NOISE
+                          (sv_run_rounds only; with
                           SV_RUN_GRAPH final_states must be NULL) */
   uint64_t traj0;      /* first trajectory index (draw stream id) */
   uint64_t seed;       /* Philox key */

@@ -117,6 +117,8 @@ _SIGS = {
                                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
     "sv_measure_reset_ancilla_forced": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                                        ctypes.POINTER(ctypes.c_double)]),
+    "sv_check_pass_layouts": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int)]),
     "sv_template_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "sv_run_rounds": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(Result)]),
@@ -203,6 +205,14 @@ def template_info(d, gateset):
     a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     _check(lib().sv_template_info(d, _GATESETS[gateset], ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return a.value, b.value, c.value
+
+
+def check_pass_layouts(d, gateset, zchain=4):
+    """sv_check_pass_layouts: host-side consistency of the register-pass
+    layouts; returns the pass count of one round sequence."""
+    n = ctypes.c_int()
+    _check(lib().sv_check_pass_layouts(d, _GATESETS[gateset], int(zchain), ctypes.byref(n)))
+    return n.value
 
 
 def uniform(seed, t, k):
@@ -311,19 +321,24 @@ SV_RUN_GRAPH = 1
 SV_RUN_TWIRL = 2
 SV_RUN_XBASIS = 4
 SV_RUN_VIRTUAL_Z = 8
+SV_RUN_IDLE_NOISE = 16
 
 
 def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0,
                dtype="c128", traj0=0, want_p1=False, want_states=False, stream=None, graph=False,
-               twirl=False, xbasis=False, virtual_z=False):
+               twirl=False, xbasis=False, virtual_z=False, idle_noise=False):
     """sv_run_rounds: returns dict(records[n_traj, rounds, n_stab], final_bits[n_traj, d*d],
-    p1 or None, states or None, gpu_ms, pass_ms, passes_per_round)."""
+    p1 or None, states or None, gpu_ms, pass_ms, passes_per_round).  Flags:
+    graph (HIP graph replay), twirl (Pauli-twirled over-rotations), xbasis
+    (X-basis memory), virtual_z (exact Rz restores), idle_noise (one-qubit
+    noise on the waiting qubits of every step)."""
     n_stab, n_sites, _ = template_info(d, gateset)
     job = Job()
     job.d, job.gateset, job.rounds = d, _GATESETS[gateset], rounds
     job.dtype, job.n_traj = _DTYPES[dtype], n_traj
     job.flags = ((SV_RUN_GRAPH if graph else 0) | (SV_RUN_TWIRL if twirl else 0)
-                 | (SV_RUN_XBASIS if xbasis else 0) | (SV_RUN_VIRTUAL_Z if virtual_z else 0))
+                 | (SV_RUN_XBASIS if xbasis else 0) | (SV_RUN_VIRTUAL_Z if virtual_z else 0)
+                 | (SV_RUN_IDLE_NOISE if idle_noise else 0))
     job.traj0, job.seed, job.p, job.eps, job.zeta = int(traj0), int(seed), float(p), float(eps), float(zeta)
     job.hip_stream = _stream_ptr(stream)
     keep = None

@@ -184,9 +184,10 @@ __global__ __launch_bounds__(256) void k_prepare_round(
   const double p = pvec[slot];
   const uint64_t k0 = (uint64_t)r * (uint64_t)draws_round + (uint64_t)b.draw_off;
   const double u = (valid && x < b.n_draws) ? uniform(seeds[slot], streams[slot], k0 + (uint64_t)x) : 1.0;
-  // every lane runs every shuffle (the op count differs between groups)
-  uint8_t pauli[kMaxOps];
-  for (int i = 0; i < kMaxOps; ++i) {
+  // every lane runs every shuffle (the op count differs between groups); the
+  // host admits templates of at most kMaxOpsBatch ops and 16 draws here
+  uint8_t pauli[kMaxOpsBatch];
+  for (int i = 0; i < kMaxOpsBatch; ++i) {
     const TOp& op = b.ops[i];
     const bool drawn = i < b.n_ops && op.draw >= 0;
     const double ui = __shfl(u, drawn ? op.draw : 0, 16);

@@ -1,28 +1,31 @@
 // Batched trajectories for small distances (d = 2, 3: at most 2^9 data
 // amplitudes).  One persistent launch runs thousands of trajectories with
 // their own round counts, depolarizing probabilities and over-rotation
-// angles.  The whole data register of a trajectory lives in LDS; a wave runs
-// two trajectories, one per half-wave, in lockstep over the stabilizer
-// template; each half-wave takes trajectories from a static list (sorted
-// longest-first by the host) until the list is exhausted, so every wave
-// reaches the exit.
+// angles.  The whole data register of a trajectory lives in LDS and one wave
+// runs it, 8 amplitudes per lane; a workgroup (one wave) takes trajectories
+// from a static list (sorted longest-first by the host) until the list is
+// exhausted, so every wave reaches the exit.
 //
 // Per trajectory (set-up): cos/sin of every gate site's angle, the channel
 // thresholds j p / 3 and j p / 15, and the noise-free Kraus pair of every
-// stabilizer template are tabulated in LDS.
+// stabilizer template are tabulated in LDS (angles common to the launch: the
+// angle table and Kraus pairs come precomputed and are only copied).
+// Per round: one lane per random draw evaluates Philox for the whole round
+// (noise locations and measurements), and a wave vote per draw tells which
+// noise locations picked a Pauli.
 // Per stabilizer circuit (Sec. II.B: one circuit at a time, ancilla measured
 // and reset):
-//   1. one lane per random draw evaluates Philox (noise locations, then the
-//      measurement draw); a half-wave vote tells whether any location drew a
-//      Pauli;
-//   2. only then, one lane per block-basis label runs the circuit's ops with
-//      the drawn Paulis on the ancilla 2-vector (track_column); otherwise the
-//      tabulated noise-free pair is used;
-//   3. each lane loads a group of 16 amplitudes spanning the check's qubits,
-//      transforms them to the check basis, and accumulates S_0, S_1; a
-//      half-wave reduction gives p1 and the outcome on the device; the lane
-//      then applies D_m, transforms back, applies the ZZ layer and 1/sqrt(S_m)
-//      and writes the group back.
+//   1. if a location of the circuit drew a Pauli, one lane per block-basis
+//      label runs the circuit's ops with the drawn Paulis on the ancilla
+//      2-vector (track_column); otherwise the tabulated noise-free pair is
+//      used;
+//   2. each lane loads 8 amplitudes: three of the check's qubits (or its two
+//      and one other bit) index the lane's registers, a weight-4 check's
+//      fourth qubit is lane bit 0 (the Walsh-Hadamard stage over it pairs
+//      lanes l and l ^ 1); the lane transforms them to the check basis and
+//      accumulates S_0, S_1; a wave reduction gives p1 and the outcome on the
+//      device; the lane then applies D_m, transforms back, applies the ZZ
+//      layer and 1/sqrt(S_m) and writes the amplitudes back.
 // After the last round the data qubits are measured one by one from the
 // highest label down (two-level descent: lane sums, then within one lane).
 #include "qec_common.h"
@@ -33,14 +36,19 @@ constexpr int kSmallBits = 9;
 constexpr int kSmallAmps = 1 << kSmallBits;
 constexpr int kSmallStab = 8;     // d <= 3
 constexpr int kSmallSites = 64;   // gate sites per round, d <= 3
+constexpr int kSmallDraws = 128;  // random draws per round, d <= 3
 
-// Per block template: where each of a lane's 16 amplitudes and each lane bit
-// sit in the register (bit values).
+// Per block template: where each of a lane's 8 amplitudes and each lane bit
+// sit in the register (bit values).  Local check index of register j on lane
+// l: (j & xmask) | (xlane ? (l & 1) << 3 : 0).
 struct SmallDesc {
-  uint32_t j_off[16];
-  uint32_t lane_bit[8];
+  uint32_t j_off[8];
+  uint32_t lane_bit[6];
   uint32_t q_bit[4];
   int n_lane_bits;
+  int xlane;     // 1: the check's fourth qubit is lane bit 0 (weight 4)
+  uint32_t xmask;  // register bits that are check qubits (7 or 3)
+  int pad;
 };
 
 template <typename T>
@@ -52,55 +60,111 @@ struct SmallSlot {
   double W[2][16];
   double cs[2 * kSmallSites];   // cos, sin of each site's angle
   double t1[3], t2[15];         // channel thresholds
-  double u[32];                 // draws of the current block
+  double u[kSmallDraws];        // draws of the current round
   uint32_t F;
   int pad;
 };
 
+// Angle table and noise-free Kraus pairs of a launch whose over-rotation
+// angles are common to every trajectory: computed once on the host and
+// copied into each trajectory's slot instead of being rebuilt per trajectory.
+template <typename T>
+struct SmallShared {
+  double cs[2 * kSmallSites];
+  C2<T> Dc[kSmallStab][2][16];
+  double Wc[kSmallStab][2][16];
+};
+
 __device__ __forceinline__ uint32_t sslot(uint32_t i) { return i ^ (((i >> 4) ^ (i >> 8)) & 15u); }
 
-// Sum over the 32 lanes of this half-wave (every lane gets the same total).
-__device__ __forceinline__ double half_sum(double v) {
-#pragma unroll
-  for (int off = 16; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// Move of a double between lanes by a DPP pattern (all lanes active).
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Tables of a new trajectory: site angles, thresholds, logical |0>.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)u, l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of the wave (every lane gets the same total; called
+// with every lane active): lane pairs, quads, eights and rows of 16 through
+// DPP, then the four row sums in a fixed order.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_double<0xB1>(v);   // quad_perm 1,0,3,2: lane ^ 1
+  v += dpp_double<0x4E>(v);   // quad_perm 2,3,0,1: lane ^ 2
+  v += dpp_double<0x141>(v);  // row_half_mirror: the other quad of the eight
+  v += dpp_double<0x140>(v);  // row_mirror: the other eight of the row
+  return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+}
+
+// Any set bit in [off, off + len) of the 128-bit mask h1:h0 (len <= 16).
+__device__ __forceinline__ bool any_in_window(uint64_t h0, uint64_t h1, int off, int len) {
+  uint64_t w;
+  if (off >= 64) w = h1 >> (off - 64);
+  else if (off == 0) w = h0;
+  else w = (h0 >> off) | (h1 << (64 - off));
+  return (w & ((1ull << len) - 1)) != 0;
+}
+
+// Value held by lane l ^ 1 (DPP quad permutation 1, 0, 3, 2: no LDS traffic).
+__device__ __forceinline__ double lane_xor1(double v) { return dpp_double<0xB1>(v); }
+__device__ __forceinline__ float lane_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
 template <typename T>
-__device__ void small_setup_tables(SmallSlot<T>& S, int lane, int n, int ns, const TBlock* blocks,
-                                   const JobConst* jc, const double* eps, double p) {
+__device__ __forceinline__ C2<T> from_pair_lane(C2<T> v) {
+  return C2<T>{lane_xor1(v.re), lane_xor1(v.im)};
+}
+
+// Tables of a new trajectory: site angles, thresholds, logical |0>.  sites:
+// the op of every gate site of the round template (index = site).
+template <typename T>
+__device__ void small_setup_tables(SmallSlot<T>& S, int lane, int n, const TOp* sites, int n_sites,
+                                   const uint32_t* init_mask, T amp0, const double* eps, double p,
+                                   const SmallShared<T>* shared) {
   // cos / sin of every site's angle
-  for (int s = 0; s < ns; ++s) {
-    const TBlock& b = blocks[s];
-    for (int i = lane; i < b.n_ops; i += 32) {
-      const TOp& op = b.ops[i];
-      if (op.site < 0) continue;
-      const double beta = op_angle(op, eps);
-      S.cs[2 * op.site] = cos(beta);
-      S.cs[2 * op.site + 1] = sin(beta);
+  if (shared) {
+    for (int k = lane; k < 2 * n_sites; k += 64) S.cs[k] = shared->cs[k];
+  } else {
+    for (int k = lane; k < n_sites; k += 64) {
+      const double beta = op_angle(sites[k], eps);
+      S.cs[2 * k] = cos(beta);
+      S.cs[2 * k + 1] = sin(beta);
     }
   }
   if (lane < 3) S.t1[lane] = (double)(lane + 1) * p / 3.0;
   if (lane < 15) S.t2[lane] = (double)(lane + 1) * p / 15.0;
-  // logical |0>
-  const int groups = 1 << (n - 4);
-  if (lane < groups) {
-    for (int k = 0; k < 16; ++k) {
-      uint32_t x = (uint32_t)(lane * 16 + k);
-      const uint32_t idx = x;
-      for (int i = 0; i < jc->n_x; ++i)
-        if (x & jc->span_piv[i]) x ^= jc->span_vec[i];
-      S.psi[sslot(idx)] = C2<T>{x == 0 ? (T)jc->amp0 : (T)0, (T)0};
-    }
+  // logical |0>: bit x of init_mask marks the X-stabilizer orbit of 0; lane
+  // l holds amplitudes 8 l .. 8 l + 7 here
+  if (lane < (1 << (n - 3))) {
+    const uint32_t bits8 = (init_mask[lane >> 2] >> ((lane & 3) * 8)) & 0xFFu;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      S.psi[sslot((uint32_t)(lane * 8 + k))] = C2<T>{((bits8 >> k) & 1) ? amp0 : (T)0, (T)0};
   }
 }
 
 // Noise-free Kraus pair of every template (needs the angle table).
 template <typename T>
-__device__ void small_setup_kraus(SmallSlot<T>& S, int lane, int ns, const TBlock* blocks, int* err) {
-  const uint8_t none[kMaxOps] = {};
-  for (int i = lane; i < ns * 16; i += 32) {
+__device__ void small_setup_kraus(SmallSlot<T>& S, int lane, int ns, const TBlock* blocks, int* err,
+                                  const SmallShared<T>* shared) {
+  if (shared) {
+    for (int i = lane; i < ns * 32; i += 64) {
+      const int s = i >> 5, m = (i >> 4) & 1, x = i & 15;
+      S.Dc[s][m][x] = shared->Dc[s][m][x];
+      S.Wc[s][m][x] = shared->Wc[s][m][x];
+    }
+    return;
+  }
+  const uint8_t none[kMaxOpsBatch] = {};
+  for (int i = lane; i < ns * 16; i += 64) {
     const int s = i >> 4, x = i & 15;
     const TBlock& b = blocks[s];
     if (x >= (1 << b.w)) continue;
@@ -115,6 +179,31 @@ __device__ void small_setup_kraus(SmallSlot<T>& S, int lane, int ns, const TBloc
   }
 }
 
+// Walsh-Hadamard transform of a lane's 8 registers over the check's qubits:
+// the register bits in xmask (7: three bits; 3: two bits, registers 4..7 a
+// second group), then for a weight-4 check the stage over lane bit 0.
+template <typename T>
+__device__ __forceinline__ void small_wht(C2<T>* v, bool xlane, bool odd) {
+#pragma unroll
+  for (int hb = 1; hb < 8; hb <<= 1) {
+    if (hb == 4 && !xlane) break;  // weight 2: bit 2 is not a check qubit
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (i & hb) continue;
+      const C2<T> a = v[i], b = v[i | hb];
+      v[i] = {a.re + b.re, a.im + b.im};
+      v[i | hb] = {a.re - b.re, a.im - b.im};
+    }
+  }
+  if (xlane) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const C2<T> o = from_pair_lane(v[i]);
+      v[i] = odd ? C2<T>{o.re - v[i].re, o.im - v[i].im} : C2<T>{v[i].re + o.re, v[i].im + o.im};
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_batch_small(
     const TBlock* __restrict__ blocks, const SmallDesc* __restrict__ sdesc, int ns, int n,
@@ -122,225 +211,198 @@ __global__ __launch_bounds__(64) void k_batch_small(
     const uint64_t* __restrict__ tstream,
     const int* __restrict__ order, int n_traj, const int* __restrict__ rounds,
     const double* __restrict__ pvec, const double* __restrict__ eps, int eps_stride,
-    uint8_t* __restrict__ rec, int max_rounds, uint8_t* __restrict__ bits, int* __restrict__ err) {
-  __shared__ SmallSlot<T> slots[2];
+    uint8_t* __restrict__ rec, int max_rounds, uint8_t* __restrict__ bits, int* __restrict__ err,
+    const TOp* __restrict__ sites, int n_sites, const SmallShared<T>* __restrict__ shared,
+    const uint32_t* __restrict__ init_mask, const uint8_t* __restrict__ draw_kind) {
+  __shared__ SmallSlot<T> S;
   // ZZ phases are read per amplitude: keep them in LDS (the round template
   // stays in global memory: more LDS per workgroup would cost occupancy)
   __shared__ C2<T> lzz[kSmallBits * 2 + 1];
-  for (int i = threadIdx.x; i <= jc->n_edges && i <= 2 * kSmallBits; i += blockDim.x)
+  const int lane = threadIdx.x;
+  for (int i = lane; i <= jc->n_edges && i <= 2 * kSmallBits; i += 64)
     lzz[i] = C2<T>{(T)jc->zz[2 * i], (T)jc->zz[2 * i + 1]};
-  __syncthreads();
   const int use_zz = jc->use_zz, zd = jc->d;
   const uint32_t hmask = jc->hmask, vmask = jc->vmask;
-
-  const int h = threadIdx.x >> 5;
-  const int lane = threadIdx.x & 31;
-  SmallSlot<T>& S = slots[h];
-  const int n_slots = gridDim.x * 2;
-  const int groups = 1 << (n - 4);
-  const uint64_t half_mask = 0xFFFFFFFFull << (32 * h);
-
-  int qi = blockIdx.x * 2 + h;
-  bool active = qi < n_traj;
-  int t = active ? order[qi] : 0;
-  int R = active ? rounds[t] : 0;
-  int r = 0;
-  double p = active ? pvec[t] : 0.0;
-  uint64_t tg = tstream[t], seed = tseed[t];  // draw stream of the current trajectory
-  small_setup_tables(S, lane, n, ns, blocks, jc, eps + (size_t)t * eps_stride, p);
-  __syncthreads();
-  small_setup_kraus(S, lane, ns, blocks, err);
+  const T amp0 = (T)jc->amp0;
+  const int groups = 1 << (n - 3);
+  const bool g_on = lane < groups;
+  const bool odd = (lane & 1) != 0;
   __syncthreads();
 
-  while (__any(active)) {
-    for (int s = 0; s < ns; ++s) {
-      const TBlock& b = blocks[s];
-      const SmallDesc& sd = sdesc[s];
-      const uint64_t k0 = (uint64_t)r * (uint64_t)draws_round + (uint64_t)b.draw_off;
-      // 1. draws; did any noise location pick a Pauli?
-      bool hit = false;
-      if (lane < b.n_draws) {
-        const double u = uniform(seed, tg, k0 + (uint64_t)lane);
-        S.u[lane] = u;
-        if (lane < b.n_draws - 1) hit = u < (((b.n2mask >> lane) & 1) ? S.t2[14] : S.t1[2]);
-      }
-      const bool noisy = (__ballot(hit) & half_mask) != 0;
-      __syncthreads();
-      // 2. Kraus pair of this block instance
-      const int nx = 1 << b.w;
-      if (noisy && lane < nx) {
-        uint8_t pauli[kMaxOps];
-        for (int i = 0; i < b.n_ops; ++i) {
-          const TOp& op = b.ops[i];
-          uint8_t c = 0;
-          if (op.draw >= 0) {
-            const double u = S.u[op.draw];
-            if (op.kind == OP_N1_ANC || op.kind == OP_N1_DATA) {
-              for (int j = 0; j < 3 && !c; ++j)
-                if (u < S.t1[j]) c = (uint8_t)(j + 1);
-            } else {
-              for (int j = 0; j < 15 && !c; ++j)
-                if (u < S.t2[j]) c = (uint8_t)(j + 1);
-            }
-          }
-          pauli[i] = c;
+  for (int qi = blockIdx.x; qi < n_traj; qi += gridDim.x) {
+    const int t = order[qi];
+    const int R = rounds[t];
+    const double p = pvec[t];
+    const uint64_t tg = tstream[t], seed = tseed[t];  // draw stream of this trajectory
+    small_setup_tables(S, lane, n, sites, n_sites, init_mask, amp0, eps + (size_t)t * eps_stride, p, shared);
+    __syncthreads();
+    small_setup_kraus(S, lane, ns, blocks, err, shared);
+    __syncthreads();
+    for (int r = 0; r < R; ++r) {
+      // every draw of the round; hit: a noise location that picked a Pauli
+      uint64_t hits[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int k = lane + 64 * c;
+        bool hit = false;
+        if (k < draws_round) {
+          const double u = uniform(seed, tg, (uint64_t)r * (uint64_t)draws_round + (uint64_t)k);
+          S.u[k] = u;
+          const int kind = draw_kind[k];
+          hit = kind < 2 && u < (kind ? S.t2[14] : S.t1[2]);
         }
-        cd v0, v1;
-        uint32_t cur = 0;
-        if (!track_column(b, CsFromTable{S.cs}, pauli, lane, v0, v1, &cur) && active) atomicOr(err, 1);
-        const double norm = b.type == 0 ? 1.0 / (double)nx : 1.0;
-        S.D[0][lane] = C2<T>{(T)(v0.re * norm), (T)(v0.im * norm)};
-        S.D[1][lane] = C2<T>{(T)(v1.re * norm), (T)(v1.im * norm)};
-        S.W[0][lane] = (v0.re * v0.re + v0.im * v0.im) * norm;
-        S.W[1][lane] = (v1.re * v1.re + v1.im * v1.im) * norm;
-        if (lane == 0) S.F = cur;  // label 0 maps to F
+        hits[c] = __ballot(hit);
       }
       __syncthreads();
-      const C2<T>(*D)[16] = noisy ? S.D : S.Dc[s];
-      const double(*W)[16] = noisy ? S.W : S.Wc[s];
-      const uint32_t F = noisy ? S.F : 0u;
-      // 3. measure and apply
-      uint32_t lb = 0;
-      for (int i = 0; i < sd.n_lane_bits; ++i)
-        if ((lane >> i) & 1) lb |= sd.lane_bit[i];
-      const bool g_on = lane < groups;
-      C2<T> v[16];
-      double s0 = 0.0, s1 = 0.0;
-      const bool xb = b.type == 0;
-      if (g_on) {
+      for (int s = 0; s < ns; ++s) {
+        const TBlock& b = blocks[s];
+        const SmallDesc& sd = sdesc[s];
+        const int off = b.draw_off, nnoise = b.n_draws - 1;
+        // noise draws off .. off + nnoise - 1 (at most 15, within 128)
+        const bool noisy = any_in_window(hits[0], hits[1], off, nnoise);
+        // 1. Kraus pair of this block instance
+        const int nx = 1 << b.w;
+        if (noisy) {
+          if (lane < nx) {
+            uint8_t pauli[kMaxOpsBatch];
+            for (int i = 0; i < b.n_ops; ++i) {
+              const TOp& op = b.ops[i];
+              uint8_t c = 0;
+              if (op.draw >= 0) {
+                const double u = S.u[off + op.draw];
+                if (op.kind == OP_N1_ANC || op.kind == OP_N1_DATA) {
+                  for (int j = 0; j < 3 && !c; ++j)
+                    if (u < S.t1[j]) c = (uint8_t)(j + 1);
+                } else {
+                  for (int j = 0; j < 15 && !c; ++j)
+                    if (u < S.t2[j]) c = (uint8_t)(j + 1);
+                }
+              }
+              pauli[i] = c;
+            }
+            cd v0, v1;
+            uint32_t cur = 0;
+            if (!track_column(b, CsFromTable{S.cs}, pauli, lane, v0, v1, &cur)) atomicOr(err, 1);
+            const double norm = b.type == 0 ? 1.0 / (double)nx : 1.0;
+            S.D[0][lane] = C2<T>{(T)(v0.re * norm), (T)(v0.im * norm)};
+            S.D[1][lane] = C2<T>{(T)(v1.re * norm), (T)(v1.im * norm)};
+            S.W[0][lane] = (v0.re * v0.re + v0.im * v0.im) * norm;
+            S.W[1][lane] = (v1.re * v1.re + v1.im * v1.im) * norm;
+            if (lane == 0) S.F = cur;  // label 0 maps to F
+          }
+          __syncthreads();
+        }
+        const C2<T>(*D)[16] = noisy ? S.D : S.Dc[s];
+        const double(*W)[16] = noisy ? S.W : S.Wc[s];
+        const uint32_t F = noisy ? S.F : 0u;
+        // 2. measure and apply
+        uint32_t lb = 0;
+        for (int i = 0; i < sd.n_lane_bits; ++i)
+          if ((lane >> i) & 1) lb |= sd.lane_bit[i];
+        const bool xl = sd.xlane != 0;
+        const uint32_t xm = sd.xmask;
+        const uint32_t xhi = (xl && odd) ? 8u : 0u;  // local bit 3 from the lane
+        C2<T> v[8];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = S.psi[sslot(lb | sd.j_off[j])];
-        if (b.w == 4) {
-          if (xb) wht<T, 4>(v);
+        for (int j = 0; j < 8; ++j) v[j] = C2<T>{(T)0, (T)0};
+        double s0 = 0.0, s1 = 0.0;
+        const bool xb = b.type == 0;
+        if (g_on) {
 #pragma unroll
-          for (int x = 0; x < 16; ++x) {
-            const double re = (double)v[x].re, im = (double)v[x].im, a2 = re * re + im * im;
+          for (int j = 0; j < 8; ++j) v[j] = S.psi[sslot(lb | sd.j_off[j])];
+        }
+        if (xb) small_wht(v, xl, odd);  // every lane joins the lane exchange
+        if (g_on) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const uint32_t x = ((uint32_t)j & xm) | xhi;
+            const double re = (double)v[j].re, im = (double)v[j].im, a2 = re * re + im * im;
             s0 += W[0][x] * a2;
             s1 += W[1][x] * a2;
           }
-        } else {
+        }
+        s0 = wave_total(s0);
+        s1 = wave_total(s1);
+        const double p1 = clamp_p1(s1 / (s0 + s1));
+        const int m = (S.u[off + nnoise] < p1) ? 1 : 0;
+        if (lane == 0) rec[((size_t)t * max_rounds + r) * ns + s] = (uint8_t)m;
+        const double scale = 1.0 / sqrt(m ? s1 : s0);
+        if (g_on) {
 #pragma unroll
-          for (int hi = 0; hi < 16; hi += 4) {
-            if (xb) wht<T, 2>(v + hi);
+          for (int j = 0; j < 8; ++j) {
+            const uint32_t x = ((uint32_t)j & xm) | xhi;
+            v[j] = mulc(v[j], D[m][x].re, D[m][x].im);
+          }
+        }
+        if (xb) small_wht(v, xl, odd);
+        if (g_on) {
+          uint32_t fo = 0;
+          if (!xb)
+            for (int l = 0; l < b.w; ++l)
+              if ((F >> l) & 1) fo |= sd.q_bit[l];
+          const T sc = (T)scale;
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-              const double re = (double)v[hi + x].re, im = (double)v[hi + x].im, a2 = re * re + im * im;
-              s0 += W[0][x] * a2;
-              s1 += W[1][x] * a2;
+          for (int j = 0; j < 8; ++j) {
+            C2<T> o = v[j];
+            const uint32_t x = ((uint32_t)j & xm) | xhi;
+            if (xb && (__popc(x & F) & 1)) o = {-o.re, -o.im};
+            const uint32_t g = (lb | sd.j_off[j]) ^ fo;
+            if (use_zz) {
+              const int k = __popc((g ^ (g >> 1)) & hmask) + __popc((g ^ (g >> zd)) & vmask);
+              o = mulc(o, lzz[k].re, lzz[k].im);
             }
+            o.re *= sc;
+            o.im *= sc;
+            S.psi[sslot(g)] = o;
           }
         }
-      }
-      s0 = half_sum(s0);
-      s1 = half_sum(s1);
-      const double p1 = clamp_p1(s1 / (s0 + s1));
-      const int m = (S.u[b.n_draws - 1] < p1) ? 1 : 0;
-      if (active && lane == 0) rec[((size_t)t * max_rounds + r) * ns + s] = (uint8_t)m;
-      const double scale = 1.0 / sqrt(m ? s1 : s0);
-      if (g_on) {
-        const int wmask = nx - 1;
-        if (b.w == 4) {
-#pragma unroll
-          for (int x = 0; x < 16; ++x) v[x] = mulc(v[x], D[m][x].re, D[m][x].im);
-          if (xb) wht<T, 4>(v);
-        } else {
-#pragma unroll
-          for (int hi = 0; hi < 16; hi += 4) {
-#pragma unroll
-            for (int x = 0; x < 4; ++x) v[hi + x] = mulc(v[hi + x], D[m][x].re, D[m][x].im);
-            if (xb) wht<T, 2>(v + hi);
-          }
-        }
-        uint32_t fo = 0;
-        if (!xb)
-          for (int l = 0; l < b.w; ++l)
-            if ((F >> l) & 1) fo |= sd.q_bit[l];
-        const T sc = (T)scale;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          C2<T> o = v[j];
-          if (xb && (__popc((uint32_t)(j & wmask) & F) & 1)) o = {-o.re, -o.im};
-          const uint32_t g = (lb | sd.j_off[j]) ^ fo;
-          if (use_zz) {
-            const int k = __popc((g ^ (g >> 1)) & hmask) + __popc((g ^ (g >> zd)) & vmask);
-            o = mulc(o, lzz[k].re, lzz[k].im);
-          }
-          o.re *= sc;
-          o.im *= sc;
-          S.psi[sslot(g)] = o;
-        }
-      }
-      __syncthreads();
-    }
-    // round boundary
-    ++r;
-    const bool done = active && (r == R);
-    if (__any(done)) {
-      // final Z measurement of the data register, highest label first
-      double L = 0.0;
-      if (lane < groups) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const C2<T> a = S.psi[sslot((uint32_t)(lane * 16 + k))];
-          L += (double)a.re * (double)a.re + (double)a.im * (double)a.im;
-        }
-      }
-      const uint64_t kf = (uint64_t)R * (uint64_t)draws_round;
-      const double uf = lane < n ? uniform(seed, tg, kf + (uint64_t)lane) : 0.0;
-      int lo = 0, size = groups, level = 0;
-      for (; level < n - 4; ++level) {
-        const int half = size >> 1;
-        const bool in0 = lane >= lo && lane < lo + half;
-        const bool in1 = lane >= lo + half && lane < lo + size;
-        const double S0 = half_sum(in0 ? L : 0.0);
-        const double S1 = half_sum(in1 ? L : 0.0);
-        const double pf = clamp_p1(S1 / (S0 + S1));
-        const double u = __shfl(uf, (h << 5) + level, 64);
-        const int bit = (u < pf) ? 1 : 0;
-        if (done && lane == 0) bits[(size_t)t * n + (n - 1 - level)] = (uint8_t)bit;
-        if (bit) lo += half;
-        size = half;
-      }
-      // within the selected group of 16: every lane reads the same amplitudes
-      int lo2 = 0, size2 = 16;
-      for (; level < n; ++level) {
-        const int half = size2 >> 1;
-        double S0 = 0.0, S1 = 0.0;
-        for (int k = 0; k < size2; ++k) {
-          const C2<T> a = S.psi[sslot((uint32_t)(lo * 16 + lo2 + k))];
-          const double w = (double)a.re * (double)a.re + (double)a.im * (double)a.im;
-          if (k < half) S0 += w; else S1 += w;
-        }
-        const double pf = clamp_p1(S1 / (S0 + S1));
-        const double u = __shfl(uf, (h << 5) + level, 64);
-        const int bit = (u < pf) ? 1 : 0;
-        if (done && lane == 0) bits[(size_t)t * n + (n - 1 - level)] = (uint8_t)bit;
-        if (bit) lo2 += half;
-        size2 = half;
-      }
-      __syncthreads();
-      if (done) {
-        qi += n_slots;
-        active = qi < n_traj;
-        if (active) {
-          t = order[qi];
-          R = rounds[t];
-          p = pvec[t];
-          r = 0;
-          tg = tstream[t];
-          seed = tseed[t];
-        }
-      }
-      // set-up of the next trajectory (barriers in wave-uniform control flow;
-      // only halves that switched write their slot)
-      const bool fresh = done && active;
-      if (__any(fresh)) {
-        if (fresh) small_setup_tables(S, lane, n, ns, blocks, jc, eps + (size_t)t * eps_stride, p);
         __syncthreads();
-        if (fresh) small_setup_kraus(S, lane, ns, blocks, err);
       }
-      __syncthreads();
     }
+    // final Z measurement of the data register, highest label first: lane l
+    // holds amplitudes 8 l .. 8 l + 7
+    double L = 0.0;
+    if (g_on) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const C2<T> a = S.psi[sslot((uint32_t)(lane * 8 + k))];
+        L += (double)a.re * (double)a.re + (double)a.im * (double)a.im;
+      }
+    }
+    const uint64_t kf = (uint64_t)R * (uint64_t)draws_round;
+    const double uf = lane < n ? uniform(seed, tg, kf + (uint64_t)lane) : 0.0;
+    int lo = 0, size = groups, level = 0;
+    for (; level < n - 3; ++level) {
+      const int half = size >> 1;
+      const bool in0 = lane >= lo && lane < lo + half;
+      const bool in1 = lane >= lo + half && lane < lo + size;
+      const double S0 = wave_total(in0 ? L : 0.0);
+      const double S1 = wave_total(in1 ? L : 0.0);
+      const double pf = clamp_p1(S1 / (S0 + S1));
+      const double u = lane_value(uf, level);
+      const int bit = (u < pf) ? 1 : 0;
+      if (lane == 0) bits[(size_t)t * n + (n - 1 - level)] = (uint8_t)bit;
+      if (bit) lo += half;
+      size = half;
+    }
+    // within the selected lane's 8: every lane reads the same amplitudes
+    int lo2 = 0, size2 = 8;
+    for (; level < n; ++level) {
+      const int half = size2 >> 1;
+      double S0 = 0.0, S1 = 0.0;
+      for (int k = 0; k < size2; ++k) {
+        const C2<T> a = S.psi[sslot((uint32_t)(lo * 8 + lo2 + k))];
+        const double w = (double)a.re * (double)a.re + (double)a.im * (double)a.im;
+        if (k < half) S0 += w; else S1 += w;
+      }
+      const double pf = clamp_p1(S1 / (S0 + S1));
+      const double u = lane_value(uf, level);
+      const int bit = (u < pf) ? 1 : 0;
+      if (lane == 0) bits[(size_t)t * n + (n - 1 - level)] = (uint8_t)bit;
+      if (bit) lo2 += half;
+      size2 = half;
+    }
+    __syncthreads();  // the slot is rewritten by the next trajectory
   }
 }
 

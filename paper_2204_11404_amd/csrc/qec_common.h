@@ -85,7 +85,8 @@ struct TOp {
   int16_t pad2;
 };
 
-constexpr int kMaxOps = 24;
+constexpr int kMaxOps = 40;       // cross-resonance X check with idle noise: 36
+constexpr int kMaxOpsBatch = 24;  // templates of the batched paths (no idle noise): 20
 
 struct TBlock {
   int type;          // 0 = X check (data in the X basis), 1 = Z check
@@ -95,7 +96,7 @@ struct TBlock {
   int n_draws;       // noise draws + 1 measurement draw
   int draw_off;      // first draw of this block within the round
   int site_off;      // first site of this block within the round
-  uint32_t n2mask;   // bit k set if noise draw k is a two-qubit location
+  uint64_t n2mask;   // bit k set if noise draw k is a two-qubit location
   TOp ops[kMaxOps];
 };
 

@@ -150,8 +150,18 @@ struct OpSink {
   bool vz;     // Rz restores are virtual: exact, no draw
   int sites = 0;
   int draws = 0;
+  // The largest block (cross-resonance X check of weight 4 with idle noise and
+  // twirled rotations) needs 36 ops and 36 noise draws: within kMaxOps and the
+  // 64-bit n2mask for every template the builder makes.
+  TOp& next() {
+    if (b.n_ops >= kMaxOps || draws >= 63) {
+      std::fprintf(stderr, "qecsv: block template exceeds kMaxOps\n");
+      std::abort();
+    }
+    return b.ops[b.n_ops++];
+  }
   void gate(uint8_t kind, int j, int axis, int sgn, int quarter) {
-    TOp& o = b.ops[b.n_ops++];
+    TOp& o = next();
     o = TOp{};
     o.kind = kind; o.j = (uint8_t)j; o.axis = (uint8_t)axis; o.sgn = (int8_t)sgn;
     o.quarter = (uint8_t)quarter;
@@ -160,15 +170,15 @@ struct OpSink {
     o.draw = (twirl && !o.exact) ? (int16_t)draws++ : (int16_t)-1;
   }
   void plain(uint8_t kind, int j) {
-    TOp& o = b.ops[b.n_ops++];
+    TOp& o = next();
     o = TOp{};
     o.kind = kind; o.j = (uint8_t)j; o.site = -1; o.draw = -1;
   }
   void noise(uint8_t kind, int j) {
-    TOp& o = b.ops[b.n_ops++];
+    TOp& o = next();
     o = TOp{};
     o.kind = kind; o.j = (uint8_t)j; o.site = -1;
-    if (kind == OP_N2_AD || kind == OP_N2_DA) b.n2mask |= 1u << draws;
+    if (kind == OP_N2_AD || kind == OP_N2_DA) b.n2mask |= 1ull << draws;
     o.draw = (int16_t)draws++;
   }
 };
@@ -178,7 +188,11 @@ struct OpSink {
 // sin^2 eps of its site), drawn right after the rotation.
 // vz: the Rz restores of the cross-resonance Z checks are virtual Z gates
 // (frame changes, Fig. 4): no over-rotation; their sites stay in the table.
-Template build_template(int d, int gateset, bool twirl = false, bool vz = false) {
+// idle: the one-qubit channel also acts on the waiting qubits of each step
+// (Sec. III.A): after a step, N1 on every data qubit of the check that the
+// step leaves alone, in slot order; the ancilla waits during the Z check's
+// restores.
+Template build_template(int d, int gateset, bool twirl = false, bool vz = false, bool idle = false) {
   Template T;
   for (const Stab& st : code_layout(d)) {
     TBlock b{};
@@ -195,10 +209,16 @@ Template build_template(int d, int gateset, bool twirl = false, bool vz = false)
     b.draw_off = T.n_draws;
     b.site_off = T.n_sites;
     OpSink o{b, T.n_sites, twirl, vz};
+    auto waiting = [&](int busy_slot) {  // idle data qubits of one step
+      if (!idle) return;
+      for (int s = 0; s < 4; ++s)
+        if (local[s] >= 0 && s != busy_slot) o.noise(OP_N1_DATA, local[s]);
+    };
     if (gateset == SV_GATESET_CR) {
       if (st.type == 0) {
         o.gate(OP_ROT_ANC, 0, 1, -1, 1);  // Rx^dag(pi/2)
         o.noise(OP_N1_ANC, 0);
+        waiting(-1);
         for (int s = 0; s < 4; ++s) {
           if (local[s] >= 0) {
             o.gate(OP_CR_AD, local[s], 0, 1, 1);
@@ -206,6 +226,7 @@ Template build_template(int d, int gateset, bool twirl = false, bool vz = false)
           } else {
             o.noise(OP_N1_ANC, 0);  // wait
           }
+          waiting(s);
         }
         o.gate(OP_ROT_ANC, 0, 1, 1, 1);  // Rx(pi/2)
         o.noise(OP_N1_ANC, 0);
@@ -221,24 +242,29 @@ Template build_template(int d, int gateset, bool twirl = false, bool vz = false)
           } else {
             o.noise(OP_N1_ANC, 0);
           }
+          waiting(s);
         }
         for (int l = 0; l < b.w; ++l) {
           o.gate(OP_ROT_DATA, l, 3, 1, 1);  // restoring Rz(pi/2) on data
           o.noise(OP_N1_DATA, l);
         }
+        if (idle) o.noise(OP_N1_ANC, 0);  // the ancilla waits during the restores
       }
     } else {
       o.plain(OP_H_ANC, 0);
       o.gate(OP_ROT_ANC, 0, 1, 1, 0);  // coherent error exp(-i eps X) after H
       o.noise(OP_N1_ANC, 0);
+      waiting(-1);
       for (int s = 0; s < 4; ++s) {
         if (local[s] < 0) continue;
         o.plain(st.type == 0 ? OP_CNOT_AD : OP_CZ_AD, local[s]);
         o.noise(OP_N2_AD, local[s]);
+        waiting(s);
       }
       o.plain(OP_H_ANC, 0);
       o.gate(OP_ROT_ANC, 0, 1, 1, 0);
       o.noise(OP_N1_ANC, 0);
+      waiting(-1);
     }
     b.n_draws = o.draws + 1;  // + measurement
     T.n_sites += o.sites;
@@ -440,14 +466,16 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
   };
   const uint32_t UA = (A && A->kind == U_Z) ? umask(A) : 0u;
   const uint32_t UB = (B && B->kind == U_Z) ? umask(B) : 0u;
-  // `fixed` first, then the highest bits outside `avoid` until 4 bits; false
-  // if there are not enough such bits
+  // `fixed` first, then bits outside `avoid` until 4 bits: upward from just
+  // above the thread-index bits, then downward below them, so that the lowest
+  // bits stay with the lanes (contiguous runs per load) as long as possible;
+  // false if there are not enough such bits
   auto slots = [&](std::vector<int> fixed, uint32_t avoid, std::vector<int>& out) {
     out = fixed;
     uint32_t used = avoid;
     for (int q : fixed) used |= 1u << q;
     for (int k = 0; k < n && (int)out.size() < 4; ++k) {
-      const int bit = (k + tb - 4) % n;  // from just above the thread-index bits
+      const int bit = k < n - (tb - 4) ? tb - 4 + k : n - 1 - k;
       if (!((used >> bit) & 1)) { out.push_back(bit); used |= 1u << bit; }
     }
     return (int)out.size() == 4;
@@ -891,8 +919,9 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
 }
 
 // Lane / register maps of the small-register batch kernel for each block
-// template: a lane's 16 amplitudes span the check's qubits (low bits of the
-// local index) plus the lowest other bits; the remaining bits index lanes.
+// template: a lane's 8 registers span three of a weight-4 check's qubits (its
+// fourth is lane bit 0), or a weight-2 check's two qubits and the lowest other
+// bit; the remaining bits index lanes, lowest first.
 std::vector<SmallDesc> make_small_descs(int n, const Template& tp) {
   std::vector<SmallDesc> out(tp.blocks.size());
   for (size_t i = 0; i < tp.blocks.size(); ++i) {
@@ -904,17 +933,27 @@ std::vector<SmallDesc> make_small_descs(int n, const Template& tp) {
       for (int l = 0; l < b.w; ++l) in = in || (b.qubit[l] == bit);
       if (!in) rest.push_back(bit);
     }
-    const int nh = 4 - b.w;
-    for (int j = 0; j < 16; ++j) {
+    std::vector<int> regs, lanes;
+    if (b.w == 4) {
+      regs = {b.qubit[0], b.qubit[1], b.qubit[2]};
+      lanes.push_back(b.qubit[3]);
+      sd.xlane = 1;
+      sd.xmask = 7;
+    } else {
+      regs = {b.qubit[0], b.qubit[1], rest[0]};
+      rest.erase(rest.begin());
+      sd.xlane = 0;
+      sd.xmask = 3;
+    }
+    for (int bit : rest) lanes.push_back(bit);
+    for (int j = 0; j < 8; ++j) {
       uint32_t g = 0;
-      for (int l = 0; l < b.w; ++l)
-        if ((j >> l) & 1) g |= 1u << b.qubit[l];
-      for (int hbit = 0; hbit < nh; ++hbit)
-        if ((j >> (b.w + hbit)) & 1) g |= 1u << rest[hbit];
+      for (int k = 0; k < 3; ++k)
+        if ((j >> k) & 1) g |= 1u << regs[k];
       sd.j_off[j] = g;
     }
-    sd.n_lane_bits = n - 4;
-    for (int k = 0; k < n - 4; ++k) sd.lane_bit[k] = 1u << rest[nh + k];
+    sd.n_lane_bits = n - 3;
+    for (int k = 0; k < n - 3; ++k) sd.lane_bit[k] = 1u << lanes[k];
     for (int l = 0; l < b.w; ++l) sd.q_bit[l] = 1u << b.qubit[l];
     out[i] = sd;
   }
@@ -951,7 +990,12 @@ template <typename T>
 sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   const int d = in.d, n = d * d, ns = (int)tp.blocks.size();
   const int nt = in.n_traj;
-  const bool small = n <= kSmallBits && ns <= kSmallStab && tp.n_sites <= kSmallSites;
+  // the batched kernels draw a block with one lane per draw (16 lanes) and
+  // keep kMaxOpsBatch Pauli choices per lane
+  for (const TBlock& b : tp.blocks)
+    if (b.n_draws > 16 || b.n_ops > kMaxOpsBatch) return fail(SV_EINVAL, "block template too large for the batched path");
+  const bool small = n <= kSmallBits && ns <= kSmallStab && tp.n_sites <= kSmallSites &&
+                     tp.n_draws <= kSmallDraws;
   if (!small) {
     if (n > 16) return fail(SV_EINVAL, "d=%d batch path not available", d);
     return run_batch_lockstep<T>(in, tp);
@@ -986,6 +1030,59 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
                    [&](int a, int b) { return in.rounds[a] > in.rounds[b]; });
   const std::vector<SmallDesc> sd = small ? make_small_descs(n, tp) : std::vector<SmallDesc>(ns);
   const JobConst jc = make_job_const(d, in.zeta);
+  // the op of every gate site (index = site)
+  std::vector<TOp> sites(std::max(1, tp.n_sites));
+  for (const TBlock& b : tp.blocks)
+    for (int i = 0; i < b.n_ops; ++i)
+      if (b.ops[i].site >= 0) sites[b.ops[i].site] = b.ops[i];
+  TOp* dsites = nullptr;
+  HIP_OK(M.alloc(&dsites, sizeof(TOp) * sites.size()));
+  HIP_OK(hipMemcpyAsync(dsites, sites.data(), sizeof(TOp) * sites.size(), hipMemcpyHostToDevice, s));
+  // angles common to every trajectory: the angle table and noise-free Kraus
+  // pairs once, here
+  SmallShared<T>* dshared = nullptr;
+  if (in.eps_stride == 0) {
+    SmallShared<T> sh{};
+    for (int k = 0; k < tp.n_sites; ++k) {
+      const double beta = op_angle(sites[k], in.eps);
+      sh.cs[2 * k] = std::cos(beta);
+      sh.cs[2 * k + 1] = std::sin(beta);
+    }
+    const uint8_t none[kMaxOpsBatch] = {};
+    for (int b = 0; b < ns; ++b)
+      for (int x = 0; x < (1 << tp.blocks[b].w); ++x) {
+        cd v0, v1;
+        uint32_t cur = 0;
+        if (!track_column(tp.blocks[b], CsFromTable{sh.cs}, none, x, v0, v1, &cur))
+          return fail(SV_EINVAL, "circuit template is not monomial in its block basis");
+        const double norm = tp.blocks[b].type == 0 ? 1.0 / (double)(1 << tp.blocks[b].w) : 1.0;
+        sh.Dc[b][0][x] = C2<T>{(T)(v0.re * norm), (T)(v0.im * norm)};
+        sh.Dc[b][1][x] = C2<T>{(T)(v1.re * norm), (T)(v1.im * norm)};
+        sh.Wc[b][0][x] = (v0.re * v0.re + v0.im * v0.im) * norm;
+        sh.Wc[b][1][x] = (v1.re * v1.re + v1.im * v1.im) * norm;
+      }
+    HIP_OK(M.alloc(&dshared, sizeof sh));
+    HIP_OK(hipMemcpyAsync(dshared, &sh, sizeof sh, hipMemcpyHostToDevice, s));
+  }
+  // logical |0> of the register: bit x set on the X-stabilizer orbit of 0
+  std::vector<uint32_t> init_mask(16, 0u);
+  for (uint32_t x = 0; x < (1u << n); ++x) {
+    uint32_t r = x;
+    for (int i = 0; i < jc.n_x; ++i)
+      if (r & jc.span_piv[i]) r ^= jc.span_vec[i];
+    if (r == 0) init_mask[x >> 5] |= 1u << (x & 31);
+  }
+  uint32_t* dinit = nullptr;
+  HIP_OK(M.alloc(&dinit, sizeof(uint32_t) * init_mask.size()));
+  HIP_OK(hipMemcpyAsync(dinit, init_mask.data(), sizeof(uint32_t) * init_mask.size(), hipMemcpyHostToDevice, s));
+  // kind of every draw of a round: 0 one-qubit location, 1 two-qubit
+  // location, 2 measurement
+  std::vector<uint8_t> kind(std::max(1, tp.n_draws), 2);
+  for (const TBlock& b : tp.blocks)
+    for (int k = 0; k + 1 < b.n_draws; ++k) kind[b.draw_off + k] = (uint8_t)((b.n2mask >> k) & 1);
+  uint8_t* dkind = nullptr;
+  HIP_OK(M.alloc(&dkind, kind.size()));
+  HIP_OK(hipMemcpyAsync(dkind, kind.data(), kind.size(), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(dblocks, tp.blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(dsd, sd.data(), sizeof(SmallDesc) * ns, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(djc, &jc, sizeof jc, hipMemcpyHostToDevice, s));
@@ -1007,13 +1104,19 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   HIP_OK(hipEventCreate(&ev.a));
   HIP_OK(hipEventCreate(&ev.b));
   {
-    const int per_cu = tuning_for(in.d, sizeof(T) == 8 ? SV_C128 : SV_C64).batch_waves_per_cu;
+    // a persistent launch: no more workgroups than stay resident at once
+    int per_cu = tuning_for(in.d, sizeof(T) == 8 ? SV_C128 : SV_C64).batch_waves_per_cu;
+    int resident = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_batch_small<T>, 64, 0) == hipSuccess &&
+        resident > 0)
+      per_cu = std::min(per_cu, resident);
     const int max_wg = device_cu_count() * per_cu;
-    const int grid = std::max(1, std::min((nt + 1) / 2, max_wg));
+    const int grid = std::max(1, std::min(nt, max_wg));  // one trajectory per workgroup at a time
     HIP_OK(hipEventRecord(ev.a, s));
     hipLaunchKernelGGL(k_batch_small<T>, dim3(grid), dim3(64), 0, s, dblocks, dsd, ns, n, tp.n_draws,
                        djc, dseed, dstream, dorder, nt, drounds, dp, deps, in.eps_stride, drec,
-                       in.max_rounds, dbits, derr);
+                       in.max_rounds, dbits, derr, (const TOp*)dsites, tp.n_sites,
+                       (const SmallShared<T>*)dshared, (const uint32_t*)dinit, (const uint8_t*)dkind);
   }
   HIP_OK(hipGetLastError());
   HIP_OK(hipEventRecord(ev.b, s));
@@ -1552,6 +1655,66 @@ sv_status sv_template_info(int d, int gateset, int* n_stab, int* n_sites, int* n
   return SV_OK;
 }
 
+sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int* n_passes) {
+  if (d < 2 || d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", d);
+  if (gateset != SV_GATESET_CR && gateset != SV_GATESET_TEXTBOOK) return fail(SV_EINVAL, "bad gateset");
+  if (zchain < 1 || zchain > kChainMax) return fail(SV_EINVAL, "zchain %d out of 1..%d", zchain, kChainMax);
+  const Template tp = build_template(d, gateset);
+  const int n = d * d;
+  const std::vector<Unit> units = make_units(tp, zchain);
+  const std::vector<UnitPass> pds = make_unit_passes(n, kTileMax, tp, units);
+  const uint32_t all = (uint32_t)((1ull << n) - 1);
+  auto bits_of = [](const uint32_t* m, int k) {
+    uint32_t r = 0;
+    for (int i = 0; i < k; ++i) r |= m[i];
+    return r;
+  };
+  auto distinct = [](const uint32_t* m, int k) {
+    uint32_t r = 0;
+    for (int i = 0; i < k; ++i) {
+      if (__builtin_popcount(m[i]) != 1 || (r & m[i])) return false;
+      r |= m[i];
+    }
+    return true;
+  };
+  for (size_t k = 0; k < pds.size(); ++k) {
+    const UnitPass& p = pds[k];
+    const int nt = p.tb - 4;
+    uint32_t slot[4];
+    for (int b = 0; b < 4; ++b) slot[b] = p.j_g[1u << b];
+    const uint32_t jm = bits_of(slot, 4), tm = bits_of(p.tid_g, nt), outer = bits_of(p.outer_bit, p.n_outer);
+    const uint32_t tile = jm | tm;
+    bool ok = p.tb == std::min(kTileMax, n) && distinct(slot, 4) && distinct(p.tid_g, nt) && (jm & tm) == 0 &&
+              __builtin_popcount(tile) == p.tb && (tile & outer) == 0 && (tile | outer) == all &&
+              distinct(p.outer_bit, p.n_outer);
+    for (int j = 0; j < 16 && ok; ++j) {
+      uint32_t g = 0;
+      for (int b = 0; b < 4; ++b)
+        if ((j >> b) & 1) g |= slot[b];
+      ok = p.j_g[j] == g;
+    }
+    uint32_t UA = 0, UB = 0;
+    for (int i = 0; i < p.la; ++i)
+      for (int l = 0; l < p.aw[i]; ++l) UA |= p.aq[i][l];
+    for (int i = 0; i < p.lb; ++i)
+      for (int l = 0; l < p.bw[i]; ++l) UB |= p.bq[i][l];
+    if (p.akind == U_X)  // WHT over the register slots
+      for (int l = 0; l < p.wa && ok; ++l) ok = slot[l] == p.aq[0][l];
+    if (p.akind == U_Z && p.amode == 1) ok = ok && (jm & UA) == 0;
+    if (p.bkind == U_Z && p.bmode == 1) ok = ok && (jm & UB) == 0;
+    if (p.bmode == 2) {
+      const uint32_t t2 = bits_of(p.b_tid_g, nt);
+      ok = ok && distinct(p.b_tid_g, nt) && (t2 & ~tile) == 0;
+      if (p.bkind == U_Z) ok = ok && ((tile & ~t2) & UB) == 0;
+    }
+    if (p.bkind == U_X && p.bmode == 1)
+      for (int l = 0; l < p.wb && ok; ++l) ok = slot[l] == p.bq[0][l];
+    if (!ok) return fail(SV_EINVAL, "pass %zu: inconsistent layout", k);
+  }
+  if (n_passes) *n_passes = (int)pds.size();
+  return SV_OK;
+}
+
 double sv_uniform(uint64_t seed, uint64_t t, uint64_t k) { return qec::uniform(seed, t, k); }
 
 sv_status sv_block_kraus(int d, int gateset, int stab, int round, uint64_t seed, uint64_t t,
@@ -1588,7 +1751,7 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
   if (job->rounds < 1 || job->rounds > 100000) return fail(SV_EINVAL, "rounds=%d", job->rounds);
   if (job->dtype != SV_C64 && job->dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
   if (job->n_traj < 0) return fail(SV_EINVAL, "n_traj < 0");
-  if (job->flags & ~(SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS | SV_RUN_VIRTUAL_Z))
+  if (job->flags & ~(SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS | SV_RUN_VIRTUAL_Z | SV_RUN_IDLE_NOISE))
     return fail(SV_EINVAL, "unknown flags 0x%x", job->flags);
   if (!(job->p >= 0.0 && job->p <= 1.0)) return fail(SV_EINVAL, "p out of [0, 1]");
   if (!std::isfinite(job->eps) || !std::isfinite(job->zeta)) return fail(SV_EINVAL, "non-finite eps/zeta");
@@ -1596,7 +1759,8 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
   if ((job->flags & SV_RUN_GRAPH) && res->final_states)
     return fail(SV_EINVAL, "final_states cannot be returned with SV_RUN_GRAPH");
   const Template tp = build_template(job->d, job->gateset, (job->flags & SV_RUN_TWIRL) != 0,
-                                     (job->flags & SV_RUN_VIRTUAL_Z) != 0);
+                                     (job->flags & SV_RUN_VIRTUAL_Z) != 0,
+                                     (job->flags & SV_RUN_IDLE_NOISE) != 0);
   if (job->eps_site)
     for (int i = 0; i < tp.n_sites; ++i)
       if (!std::isfinite(job->eps_site[i])) return fail(SV_EINVAL, "non-finite eps_site[%d]", i);
@@ -1702,7 +1866,9 @@ sv_status sv_autotune(int d, int dtype, int gateset, sv_tuning* best, double* be
   }
   // synthetic trials of the tuned shape
   const int n = d * d, ns = (int)tp.blocks.size();
-  const int nt = d == 5 ? 1 : (d == 4 ? 512 : 16384);
+  // d = 4: as many trajectories as the batched workload, so that the group
+  // memory (how many registers run in lockstep) is tested at its real size
+  const int nt = d == 5 ? 1 : (d == 4 ? 4096 : 16384);
   const int R = d == 5 ? 1 : 3;
   std::vector<uint8_t> rec((size_t)nt * R * ns), bits((size_t)nt * n);
   std::vector<int> rounds(nt, R);

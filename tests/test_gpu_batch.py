@@ -81,3 +81,21 @@ def test_batch_d4_chain_of_two(monkeypatch):
     """Lockstep d=4 batches with Z chains of at most two checks per pass."""
     monkeypatch.setenv("QECSV_ZCHAIN", "2")
     _check(4, "cr", "c128", 8, seed=19, p_range=(1e-2, 4e-2), zeta=0.01)
+
+
+@pytest.mark.parametrize("gateset,d,dtype", [("textbook", 3, "c128"), ("cr", 3, "c64"), ("cr", 2, "c128")])
+def test_batch_common_angles_parity(gateset, d, dtype):
+    """One over-rotation angle for every site and trajectory: the angle table
+    and noise-free Kraus pairs are computed once for the launch (and copied
+    per trajectory); per-trajectory rounds and p still vary."""
+    n = 300
+    rng = np.random.default_rng(44)
+    R = rng.integers(1, 6, n).astype(np.int32)
+    p = rng.uniform(5e-3, 4e-2, n)
+    eps, zeta, seed = 0.03, 0.01, 44
+    print(f"case batch common angles d={d} {gateset} {dtype}", flush=True)
+    g = qs.run_batch(d, gateset, R, p, seed, eps=eps, zeta=zeta, dtype=dtype, max_rounds=5)
+    for i in range(n):
+        o = oracle.run_trajectory(d, GS[gateset], int(R[i]), seed, i, p[i], eps=eps, zeta=zeta)
+        assert np.array_equal(g["records"][i, :R[i]], o["records"]), f"trajectory {i}"
+        assert np.array_equal(g["final_bits"][i], o["final_bits"]), f"trajectory {i}"

@@ -23,16 +23,16 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "d5_cr_oracle.npz")
 
 
 def _compare(d, gateset, R, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0, dtype="c128",
-             traj0=0, atol=1e-10, twirl=False, xbasis=False, virtual_z=False):
+             traj0=0, atol=1e-10, twirl=False, xbasis=False, virtual_z=False, idle=False):
     print(f"case rounds d={d} {gateset} R={R} n={n_traj} p={p} eps={eps} zeta={zeta} {dtype}"
-          f" twirl={twirl} xbasis={xbasis}", flush=True)
+          f" twirl={twirl} xbasis={xbasis} vz={virtual_z} idle={idle}", flush=True)
     g = qs.run_rounds(d, gateset, R, n_traj, seed, p, eps=eps, eps_site=eps_site, zeta=zeta,
                       dtype=dtype, traj0=traj0, want_p1=True, want_states=True, twirl=twirl,
-                      xbasis=xbasis, virtual_z=virtual_z)
+                      xbasis=xbasis, virtual_z=virtual_z, idle_noise=idle)
     for i in range(n_traj):
         o = oracle.run_trajectory(d, GS[gateset], R, seed, traj0 + i, p, eps=eps, eps_site=eps_site,
                                   zeta=zeta, want_state=True, twirl=twirl, xbasis=xbasis,
-                                  virtual_z=virtual_z)
+                                  virtual_z=virtual_z, idle=idle)
         assert np.array_equal(g["records"][i], o["records"]), f"trajectory {i}"
         assert np.array_equal(g["final_bits"][i], o["final_bits"]), f"trajectory {i}"
         assert np.max(np.abs(g["p1"][i] - o["p1"])) < atol
@@ -214,6 +214,34 @@ def test_virtual_z_parity(twirl):
     _compare(3, "cr", 2, 10, seed=14, p=0.01, eps_site=eps, zeta=0.01, twirl=twirl, virtual_z=True)
 
 
+@pytest.mark.parametrize("gateset,d,dtype,twirl,xbasis", [
+    ("cr", 3, "c128", False, False), ("textbook", 3, "c128", False, False),
+    ("cr", 4, "c128", True, False), ("cr", 3, "c64", False, False), ("cr", 3, "c128", False, True)])
+def test_idle_noise_parity(gateset, d, dtype, twirl, xbasis):
+    """SV_RUN_IDLE_NOISE: one-qubit noise on the waiting qubits of every step
+    (the largest block template: d=4 weight-4 X checks with twirled rotations,
+    36 ops).  High p so that idle locations fire in most blocks."""
+    n_sites = oracle.template_counts(d, GS[gateset])[1]
+    eps = workloads.eps_sites(n_sites, (0.0, 0.3 if twirl else 0.05), 15)
+    _compare(d, gateset, 2, 3 if d == 4 else 10, seed=15, p=0.03, eps_site=eps, zeta=0.01,
+             dtype=dtype, atol=1e-10 if dtype == "c128" else 1e-5, twirl=twirl, xbasis=xbasis,
+             idle=True)
+
+
+def test_idle_noise_d5_noiseless_is_trivial():
+    """d=5 (26 qubits) with SV_RUN_IDLE_NOISE and p = 0: every record is its
+    trivial bit and the final bits satisfy every Z check and Z_L."""
+    d = 5
+    g = qs.run_rounds(d, "cr", 2, 1, 3, 0.0, eps=0.0, zeta=0.0, dtype="c64", idle_noise=True)
+    tb = np.array([(sum(1 for q in s if q) // 2) % 2 for _, s in oracle.layout(d)], dtype=np.uint8)
+    assert np.array_equal(g["records"][0], np.broadcast_to(tb, (2, len(tb))))
+    fb = g["final_bits"][0]
+    for typ, s in oracle.layout(d):
+        if typ == "Z":
+            assert sum(int(fb[q - 1]) for q in s if q) % 2 == 0
+    assert sum(int(fb[q]) for q in range(d)) % 2 == 0
+
+
 def test_grid_stride_passes_match(monkeypatch):
     """Register passes with fewer workgroups than tiles (each takes tiles
     grid-stride) compute the same records, p1 and final bits bit for bit."""
@@ -228,3 +256,4 @@ def test_grid_stride_passes_match(monkeypatch):
     assert np.array_equal(a["records"], b["records"])
     assert np.array_equal(a["p1"], b["p1"])
     assert np.array_equal(a["final_bits"], b["final_bits"])
+

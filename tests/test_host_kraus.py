@@ -139,3 +139,17 @@ def test_argument_errors_are_reported_on_host():
     assert e.value.status == qs.SV_EINVAL
     with pytest.raises(qs.SvError):
         qs.run_rounds(3, CR, 1, 1, 0, 1.5)
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+@pytest.mark.parametrize("d", [2, 3, 4, 5])
+def test_pass_layouts_are_consistent(d, gateset):
+    """Every register-pass layout of every chain length partitions its tile
+    between lanes and register slots consistently (host-side builder)."""
+    for zchain in (1, 2, 3, 4):
+        n_x = sum(1 for t, _ in oracle.layout(d) if t == "X")
+        n_z = (d * d - 1) - n_x
+        # one pass per X check and per chain, plus the first and the last
+        assert qs.check_pass_layouts(d, gateset, zchain) == n_x + -(-n_z // zchain) + 2
+    with pytest.raises(qs.SvError):
+        qs.check_pass_layouts(d, gateset, 5)
