@@ -59,9 +59,6 @@ __device__ __forceinline__ void wht(C2<T>* v) {
   }
 }
 
-// LDS slot of compressed tile index l: XOR-swizzle of the low 4 bits with
-// higher bits so strided lane patterns spread over the banks.
-__device__ __forceinline__ uint32_t lslot(uint32_t l) { return l ^ (((l >> 4) ^ (l >> 8)) & 15u); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -265,16 +262,16 @@ __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const
   __shared__ XposeLds<T> sh;
   if (active) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) st2(sh.v, lslot(lt_a | pd->j_l[j]), o[j]);
+    for (int j = 0; j < 16; ++j) st2(sh.v, lt_a ^ pd->j_l[j], o[j]);
   }
   __syncthreads();
   if (active) {
     uint32_t lt = 0;
     for (int i = 0; i < pd->tb - 4; ++i)
-      if ((threadIdx.x >> i) & 1) lt |= pd->b_tid_l[i];
+      if ((threadIdx.x >> i) & 1) lt ^= pd->b_tid_l[i];
     C2<T> v[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = ld2(sh.v, lslot(lt | pd->b_j_l[j]));
+    for (int j = 0; j < 16; ++j) v[j] = ld2(sh.v, lt ^ pd->b_j_l[j]);
     constexpr int NB = 1 << WB;
 #pragma unroll
     for (int hi = 0; hi < 16; hi += NB) {
@@ -297,16 +294,16 @@ __device__ __forceinline__ double xpose_norms(const double* a2, uint32_t lt_a, c
   __shared__ double buf[1 << kTileMax];
   if (active) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) buf[lslot(lt_a | pd->j_l[j])] = a2[j];
+    for (int j = 0; j < 16; ++j) buf[lt_a ^ pd->j_l[j]] = a2[j];
   }
   __syncthreads();
   double s = 0.0;
   if (active) {
     uint32_t lt = 0;
     for (int i = 0; i < pd->tb - 4; ++i)
-      if ((threadIdx.x >> i) & 1) lt |= pd->b_tid_l[i];
+      if ((threadIdx.x >> i) & 1) lt ^= pd->b_tid_l[i];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) s += buf[lslot(lt | pd->b_j_l[j])];
+    for (int j = 0; j < 16; ++j) s += buf[lt ^ pd->b_j_l[j]];
   }
   return s;
 }
@@ -455,7 +452,7 @@ __global__ __launch_bounds__(256) void k_upass(
   for (int i = 0; i < tb - 4; ++i)
     if ((tid >> i) & 1) {
       gt |= pd->tid_g[i];
-      lt |= pd->tid_l[i];
+      lt ^= pd->tid_l[i];
     }
   // grid-stride over the tiles (one tile per workgroup when the grid covers
   // them all); the tables above are loaded once per workgroup

@@ -431,10 +431,13 @@ struct UnitPass {
   int bkind, lb, wb;       // B: U_NONE / U_X / U_Z
   int amode, bmode;
   uint32_t outer_bit[32];
-  uint32_t tid_g[8], tid_l[8];     // layout 1: global / LDS bit of each thread-index bit
-  uint32_t j_g[16], j_l[16];       // layout 1: global / LDS bits of slot j
+  // LDS slots (tid_l, j_l, b_tid_l, b_j_l) are already swizzled: the slot of
+  // a thread's value is the XOR of its thread-index bits' and its slot's entries
+  uint32_t tid_g[8], tid_l[8];     // layout 1: global bit / LDS slot of each thread-index bit
+  uint32_t j_g[16], j_l[16];       // layout 1: global bits / LDS slot of register slot j
   uint32_t b_tid_g[8], b_tid_l[8];  // layout 2
   uint32_t b_j_l[16];
+  uint32_t b_j_g[16];               // layout 2: global bits of slot j (host checks)
   uint32_t aq[kChainMax][4];     // global bit of local bit l of A's member i
   uint32_t bq[kChainMax][4];
   int aw[kChainMax], bw[kChainMax];

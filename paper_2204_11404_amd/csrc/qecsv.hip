@@ -566,7 +566,53 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
     }
   };
   fill(J1, pd.tid_g, pd.tid_l, pd.j_g, pd.j_l);
-  if (have2) fill(J2, pd.b_tid_g, pd.b_tid_l, nullptr, pd.b_j_l);
+  if (have2) {
+    fill(J2, pd.b_tid_g, pd.b_tid_l, pd.b_j_g, pd.b_j_l);
+    // LDS swizzle for the regrouping: slot = l ^ f(l), where f folds each tile
+    // bit i >= 4 onto one of the four lowest bits (mask M[i]).  A wave's 64
+    // lanes then spread over the 16-byte bank groups when their lane bits map
+    // to four independent low bits, in both layouts; search the foldings for
+    // one that does that (the first candidate is the plain fold i -> i mod 4).
+    const int nl = std::min(6, tb - 4);
+    auto rank_ok = [&](const uint32_t* tl, const uint32_t* M) {
+      uint32_t basis[4] = {0, 0, 0, 0};
+      int r = 0;
+      for (int k = 0; k < nl; ++k) {
+        const int b = __builtin_ctz(tl[k]);
+        uint32_t v = b < 4 ? 1u << b : M[b];
+        for (int q = 0; q < r; ++q) v = std::min(v, v ^ basis[q]);
+        if (v) basis[r++] = v;
+      }
+      return r >= std::min(4, nl);
+    };
+    uint32_t M[32] = {};
+    uint32_t best[32] = {};
+    bool found = false;
+    for (uint32_t code = 0; code < (1u << (2 * 8)) && !found; ++code) {
+      // M[i] = one low bit for i = 4..11; code 0 is the plain fold
+      for (int i = 4; i < 12; ++i) M[i] = 1u << (((i & 3) + ((code >> (2 * (i - 4))) & 3)) & 3);
+      if (rank_ok(pd.tid_l, M) && rank_ok(pd.b_tid_l, M)) {
+        found = true;
+        std::copy(M, M + 32, best);
+      }
+    }
+    if (!found)
+      for (int i = 4; i < 12; ++i) best[i] = 1u << (i & 3);
+    auto swz = [&](uint32_t l) {
+      uint32_t f = 0;
+      for (int i = 4; i < 12; ++i)
+        if ((l >> i) & 1) f ^= best[i];
+      return l ^ f;
+    };
+    for (int i = 0; i < tb - 4; ++i) {
+      pd.tid_l[i] = swz(pd.tid_l[i]);
+      pd.b_tid_l[i] = swz(pd.b_tid_l[i]);
+    }
+    for (int j = 0; j < 16; ++j) {
+      pd.j_l[j] = swz(pd.j_l[j]);
+      pd.b_j_l[j] = swz(pd.b_j_l[j]);
+    }
+  }
   auto loc = [](uint32_t g, const uint32_t* q, int w) {
     uint32_t x = 0;
     for (int l = 0; l < w; ++l)
@@ -1709,6 +1755,27 @@ sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int* n_passes) {
     }
     if (p.bkind == U_X && p.bmode == 1)
       for (int l = 0; l < p.wb && ok; ++l) ok = slot[l] == p.bq[0][l];
+    if (p.bmode == 2 && ok) {
+      // both layouts put every tile element in the same LDS slot, one each
+      std::map<uint32_t, uint32_t> at;  // global index -> slot (layout 1)
+      std::vector<uint8_t> used((size_t)1 << p.tb, 0);
+      for (int t = 0; t < (1 << nt) && ok; ++t)
+        for (int j = 0; j < 16 && ok; ++j) {
+          uint32_t g = p.j_g[j], l = p.j_l[j];
+          for (int i = 0; i < nt; ++i)
+            if ((t >> i) & 1) { g |= p.tid_g[i]; l ^= p.tid_l[i]; }
+          ok = l < used.size() && !used[l];
+          if (ok) { used[l] = 1; at[g] = l; }
+        }
+      for (int t = 0; t < (1 << nt) && ok; ++t)
+        for (int j = 0; j < 16 && ok; ++j) {
+          uint32_t g = p.b_j_g[j], l = p.b_j_l[j];
+          for (int i = 0; i < nt; ++i)
+            if ((t >> i) & 1) { g |= p.b_tid_g[i]; l ^= p.b_tid_l[i]; }
+          const auto it = at.find(g);
+          ok = it != at.end() && it->second == l;
+        }
+    }
     if (!ok) return fail(SV_EINVAL, "pass %zu: inconsistent layout", k);
   }
   if (n_passes) *n_passes = (int)pds.size();
