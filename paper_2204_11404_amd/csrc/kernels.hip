@@ -60,6 +60,67 @@ __device__ __forceinline__ void wht(C2<T>* v) {
 }
 
 
+// Lane exchanges by DPP (every lane of the row of 16 active).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mv(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mv(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// Value of lane l ^ (1 << B), B = 0..3; upper: bit B of l is set.
+template <int B, typename T>
+__device__ __forceinline__ T lane_partner(T v, bool upper) {
+  if constexpr (B == 0) {
+    return dpp_mv<0xB1>(v);  // quad_perm 1,0,3,2
+  } else if constexpr (B == 1) {
+    return dpp_mv<0x4E>(v);  // quad_perm 2,3,0,1
+  } else {
+    const T from_above = dpp_mv<0x100 + (1 << B)>(v);  // row_shl: lane l reads l + 2^B
+    const T from_below = dpp_mv<0x110 + (1 << B)>(v);  // row_shr: lane l reads l - 2^B
+    return upper ? from_below : from_above;
+  }
+}
+
+// Walsh-Hadamard stage over lane bit B for the thread's 16 amplitudes.
+template <int B, typename T>
+__device__ __forceinline__ void wht_lane(C2<T>* v, int tid) {
+  const bool upper = (tid >> B) & 1;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const C2<T> o{lane_partner<B>(v[j].re, upper), lane_partner<B>(v[j].im, upper)};
+    v[j] = upper ? C2<T>{o.re - v[j].re, o.im - v[j].im} : C2<T>{v[j].re + o.re, v[j].im + o.im};
+  }
+}
+
+// Walsh-Hadamard transform of an X check A held partly on lane bits 0..3
+// (mask lanes) and partly on the lowest r register slots.
+template <int H, typename T>
+__device__ __forceinline__ void wht_reg_stage(C2<T>* v) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (i & H) continue;
+    const C2<T> a = v[i], b = v[i | H];
+    v[i] = {a.re + b.re, a.im + b.im};
+    v[i | H] = {a.re - b.re, a.im - b.im};
+  }
+}
+template <typename T>
+__device__ __forceinline__ void wht_mixed(C2<T>* v, int r, int lanes, int tid) {
+  if (r > 0) wht_reg_stage<1>(v);
+  if (r > 1) wht_reg_stage<2>(v);
+  if (r > 2) wht_reg_stage<4>(v);
+  if (r > 3) wht_reg_stage<8>(v);
+  if (lanes & 1) wht_lane<0>(v, tid);
+  if (lanes & 2) wht_lane<1>(v, tid);
+  if (lanes & 4) wht_lane<2>(v, tid);
+  if (lanes & 8) wht_lane<3>(v, tid);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -356,7 +417,8 @@ __global__ __launch_bounds__(256) void k_upass(
   if (dec_a) dec_a += (size_t)blockIdx.y * ss.dec;
   dec_b += (size_t)blockIdx.y * ss.dec;
   const int n_tiles = 1 << pd->n_outer;
-  partials += (size_t)blockIdx.y * kChainAcc * n_tiles;
+  // one partial sum per workgroup (over its tiles, in tile order): [acc][gridDim.x]
+  partials += (size_t)blockIdx.y * kChainAcc * gridDim.x;
   __shared__ C2<T> da[kChainMax][16];
   __shared__ double wt[kChainMax][2][16];
   __shared__ C2<T> zzt[4 * 40 + 1];
@@ -412,6 +474,9 @@ __global__ __launch_bounds__(256) void k_upass(
   if (blockIdx.x == 0 && tid == 0) dec_b->phi = phi_new;
 
   // tables (the workgroup may have only 64 threads)
+  if constexpr (AK == U_X) {
+    if (pd->amix && tid < 16) da[0][tid] = C2<T>{(T)rta->D[mbits][tid][0], (T)rta->D[mbits][tid][1]};
+  }
   if constexpr (AK == U_Z) {
     for (int k = tid; k < kChainMax * 16; k += blockDim.x) {
       const int i = k >> 4, x = k & 15;
@@ -455,7 +520,11 @@ __global__ __launch_bounds__(256) void k_upass(
       lt ^= pd->tid_l[i];
     }
   // grid-stride over the tiles (one tile per workgroup when the grid covers
-  // them all); the tables above are loaded once per workgroup
+  // them all); the tables above are loaded once per workgroup, the sums of B
+  // accumulate over the workgroup's tiles
+  double acc[32];
+#pragma unroll
+  for (int a = 0; a < 32; ++a) acc[a] = 0.0;
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
   const int wg = reverse ? n_tiles - 1 - tile : tile;
   uint32_t base = 0;
@@ -463,9 +532,6 @@ __global__ __launch_bounds__(256) void k_upass(
     if ((wg >> i) & 1) base |= pd->outer_bit[i];
   const uint32_t gb = base | gt;
 
-  double acc[32];
-#pragma unroll
-  for (int a = 0; a < 32; ++a) acc[a] = 0.0;
   C2<T> o[16];
   if (active) {
     if constexpr (AK == U_INIT) {
@@ -496,17 +562,33 @@ __global__ __launch_bounds__(256) void k_upass(
 #pragma unroll
       for (int j = 0; j < 16; ++j) v[j] = ld2(st, gb | pd->j_g[j]);
       if constexpr (AK == U_X) {
-        const double* D = &rta->D[mbits][0][0];
-        constexpr int NA = 1 << WA;
+        if (pd->amix) {
+          uint32_t xl = 0;  // A's local index bits carried by this thread's lanes
+          for (int i = 0; i < 4; ++i)
+            if ((tid >> i) & 1) xl |= pd->a_tx[i];
+          wht_mixed(v, pd->amix_r, pd->amix_lanes, tid);
 #pragma unroll
-        for (int hi = 0; hi < 16; hi += NA) {
-          wht<T, WA>(v + hi);
+          for (int j = 0; j < 16; ++j) {
+            const C2<T> e = da[0][xl ^ pd->a_jx[j]];
+            v[j] = mulc(v[j], e.re, e.im);
+          }
+          wht_mixed(v, pd->amix_r, pd->amix_lanes, tid);
 #pragma unroll
-          for (int x = 0; x < NA; ++x) v[hi + x] = mulc(v[hi + x], (T)D[2 * x], (T)D[2 * x + 1]);
-          wht<T, WA>(v + hi);
+          for (int j = 0; j < 16; ++j)
+            if (__popc((xl ^ pd->a_jx[j]) & Fa) & 1) v[j] = {-v[j].re, -v[j].im};
+        } else {
+          const double* D = &rta->D[mbits][0][0];
+          constexpr int NA = 1 << WA;
 #pragma unroll
-          for (int x = 0; x < NA; ++x)
-            if (__popc((uint32_t)x & Fa) & 1) v[hi + x] = {-v[hi + x].re, -v[hi + x].im};
+          for (int hi = 0; hi < 16; hi += NA) {
+            wht<T, WA>(v + hi);
+#pragma unroll
+            for (int x = 0; x < NA; ++x) v[hi + x] = mulc(v[hi + x], (T)D[2 * x], (T)D[2 * x + 1]);
+            wht<T, WA>(v + hi);
+#pragma unroll
+            for (int x = 0; x < NA; ++x)
+              if (__popc((uint32_t)x & Fa) & 1) v[hi + x] = {-v[hi + x].re, -v[hi + x].im};
+          }
         }
       } else {
         uint32_t oa[kChainMax];
@@ -637,6 +719,8 @@ __global__ __launch_bounds__(256) void k_upass(
       }
     }
   }
+  __syncthreads();  // LDS buffers are reused by the next tile
+  }
   if constexpr (BK != U_NONE) {
     constexpr int nacc = (2 << lb) - 2;
     const int lane = tid & 63, wid = tid >> 6;
@@ -655,10 +739,8 @@ __global__ __launch_bounds__(256) void k_upass(
     if (tid < nacc) {
       double s = 0.0;
       for (int w = 0; w < nw; ++w) s += red[tid][w];
-      partials[(size_t)tid * n_tiles + wg] = s;
+      partials[(size_t)tid * gridDim.x + blockIdx.x] = s;
     }
-  }
-  __syncthreads();  // LDS buffers are reused by the next tile
   }
 }
 

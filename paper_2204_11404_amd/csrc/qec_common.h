@@ -438,6 +438,13 @@ struct UnitPass {
   uint32_t b_tid_g[8], b_tid_l[8];  // layout 2
   uint32_t b_j_l[16];
   uint32_t b_j_g[16];               // layout 2: global bits of slot j (host checks)
+  // amix = 1: X check A on bit 0 or 1 keeps its qubits below bit 4 on the
+  // lanes (so lanes still run over the lowest bits) and the others in the low
+  // amix_r register slots; its local index is the XOR of a_tx[i] over the
+  // thread's index bits i and a_jx[j] of register slot j; amix_lanes: the
+  // lane bits (0..3) that carry qubits of A
+  int amix, amix_r, amix_lanes, pad_amix;
+  uint32_t a_tx[8], a_jx[16];
   uint32_t aq[kChainMax][4];     // global bit of local bit l of A's member i
   uint32_t bq[kChainMax][4];
   int aw[kChainMax], bw[kChainMax];

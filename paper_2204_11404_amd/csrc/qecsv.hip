@@ -493,8 +493,17 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
   // an X check's qubits serve as layout-1 slot bits only if that keeps the
   // four lowest bits for the thread index (runs of >= 256 bytes)
   const bool bx_high = bx && disjoint(xqubits(B), 0xFu);
+  pd.amix = 0;
+  std::vector<int> a_high;  // amix: A's qubits held in register slots
   if (ax) {
-    if (!slots(xqubits(A), UB, J1)) slots(xqubits(A), 0u, J1);
+    uint32_t am = 0;
+    for (int q : xqubits(A)) am |= 1u << q;
+    if ((am & 0x3u) && tb >= 8) {
+      for (int q : xqubits(A))
+        if (q >= 4) a_high.push_back(q);
+      if (slots(a_high, UB | 0xFu, J1) || slots(a_high, 0xFu, J1)) pd.amix = 1;
+    }
+    if (!pd.amix && !slots(xqubits(A), UB, J1)) slots(xqubits(A), 0u, J1);
   } else if (az) {
     if (bx_high && disjoint(xqubits(B), UA) && slots(xqubits(B), UA, J1)) {
       pd.amode = 1;
@@ -566,6 +575,23 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
     }
   };
   fill(J1, pd.tid_g, pd.tid_l, pd.j_g, pd.j_l);
+  if (pd.amix) {
+    // local index of A: bit l for A's qubit l, from lanes or register slots
+    const std::vector<int> aq = xqubits(A);
+    pd.amix_r = (int)a_high.size();
+    pd.amix_lanes = 0;
+    for (int i = 0; i < tb - 4; ++i) {
+      pd.a_tx[i] = 0;
+      for (size_t l = 0; l < aq.size(); ++l)
+        if (pd.tid_g[i] == (1u << aq[l])) pd.a_tx[i] = 1u << l;
+      if (pd.a_tx[i]) pd.amix_lanes |= 1 << i;
+    }
+    for (int j = 0; j < 16; ++j) {
+      pd.a_jx[j] = 0;
+      for (size_t l = 0; l < aq.size(); ++l)
+        if (pd.j_g[j] & (1u << aq[l])) pd.a_jx[j] |= 1u << l;
+    }
+  }
   if (have2) {
     fill(J2, pd.b_tid_g, pd.b_tid_l, pd.b_j_g, pd.b_j_l);
     // LDS swizzle for the regrouping: slot = l ^ f(l), where f folds each tile
@@ -797,7 +823,8 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
     auto decide = [&](int ui) {
       const int bi = inst(ui);
       const int lb = units[ui % nu].len;
-      hipLaunchKernelGGL(k_udecide, dim3((2 << lb) - 2), dim3(256), 0, q, partials, (int)n_tiles, lb,
+      // one partial per pass workgroup
+      hipLaunchKernelGGL(k_udecide, dim3((2 << lb) - 2), dim3(256), 0, q, partials, (int)grid.x, lb,
                          rt + bi, &ddec[ui], rec + bi, p1 ? p1 + bi : nullptr, ss0, (size_t)0, dacc,
                          dticket, 1);
     };
@@ -1744,8 +1771,24 @@ sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int* n_passes) {
       for (int l = 0; l < p.aw[i]; ++l) UA |= p.aq[i][l];
     for (int i = 0; i < p.lb; ++i)
       for (int l = 0; l < p.bw[i]; ++l) UB |= p.bq[i][l];
-    if (p.akind == U_X)  // WHT over the register slots
+    if (p.akind == U_X && !p.amix)  // WHT over the register slots
       for (int l = 0; l < p.wa && ok; ++l) ok = slot[l] == p.aq[0][l];
+    if (p.akind == U_X && p.amix) {
+      // A's qubits: lane bits among the thread's lowest four index bits, or
+      // the lowest amix_r register slots; the local index tables match
+      uint32_t seen = 0;
+      for (int i = 0; i < nt && ok; ++i)
+        if (p.a_tx[i]) {
+          ok = i < 4 && ((p.amix_lanes >> i) & 1) && p.tid_g[i] == p.aq[0][__builtin_ctz(p.a_tx[i])];
+          seen |= p.a_tx[i];
+        }
+      for (int b = 0; b < 4 && ok; ++b) {
+        const uint32_t x = p.a_jx[1u << b];
+        ok = b < p.amix_r ? (x != 0 && p.aq[0][__builtin_ctz(x)] == slot[b]) : x == 0;
+        seen |= x;
+      }
+      ok = ok && seen == (1u << p.wa) - 1 && (tm & 0xFu) == 0xFu;
+    }
     if (p.akind == U_Z && p.amode == 1) ok = ok && (jm & UA) == 0;
     if (p.bkind == U_Z && p.bmode == 1) ok = ok && (jm & UB) == 0;
     if (p.bmode == 2) {
@@ -1909,7 +1952,7 @@ sv_status sv_autotune(int d, int dtype, int gateset, sv_tuning* best, double* be
   if (d == 5) {
     for (int z = 2; z <= kChainMax; ++z)
       for (int sn = 0; sn <= 1; ++sn)
-        for (int wpc : {0, 8, 16}) {
+        for (int wpc : {0, 4, 8, 16}) {
           sv_tuning c = base;
           c.zchain = z;
           c.snake = sn;

@@ -244,7 +244,9 @@ def test_idle_noise_d5_noiseless_is_trivial():
 
 def test_grid_stride_passes_match(monkeypatch):
     """Register passes with fewer workgroups than tiles (each takes tiles
-    grid-stride) compute the same records, p1 and final bits bit for bit."""
+    grid-stride and sums its tiles before the fixed-order reduction) give the
+    same records and final bits, and p1 up to the rounding of the different
+    summation order."""
     n_sites = oracle.template_counts(5, oracle.GATESET_CR)[1]
     eps = workloads.eps_sites(n_sites, (0.0, 0.05), 1)
     kw = dict(d=5, gateset="cr", rounds=1, n_traj=1, seed=3, p=5e-3, eps_site=eps, zeta=0.01,
@@ -254,6 +256,6 @@ def test_grid_stride_passes_match(monkeypatch):
     monkeypatch.setenv("QECSV_PASS_WGS_PER_CU", "1")
     b = qs.run_rounds(**kw)
     assert np.array_equal(a["records"], b["records"])
-    assert np.array_equal(a["p1"], b["p1"])
+    assert np.max(np.abs(a["p1"] - b["p1"])) < 1e-12
     assert np.array_equal(a["final_bits"], b["final_bits"])
 
