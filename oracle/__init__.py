@@ -42,6 +42,7 @@ class _Job(ctypes.Structure):
         ("xbasis", ctypes.c_int),
         ("virtual_z", ctypes.c_int),
         ("idle", ctypes.c_int),
+        ("zzp", ctypes.c_int),
     ]
 
 
@@ -119,13 +120,16 @@ def template_counts(d, gateset):
 
 
 def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=None,
-                   want_state=False, twirl=False, xbasis=False, virtual_z=False, idle=False):
+                   want_state=False, twirl=False, xbasis=False, virtual_z=False, idle=False,
+                   zz_plaquette=False):
     """One Monte Carlo trajectory.
 
     twirl: Pauli-twirled over-rotations; xbasis: X-basis memory (logical |+>,
     final X measurement of the data qubits); virtual_z: the Rz restores of the
     cross-resonance Z checks without over-rotation; idle: one-qubit noise on
-    the waiting qubits of the circuit at every step.  Returns
+    the waiting qubits of the circuit at every step; zz_plaquette: the
+    crosstalk exp(-i zeta Z_anc Z_q) between the ancilla and every data qubit
+    of the running check after each step.  Returns
     dict(records=uint8[rounds, n_stab], final_bits=uint8[d*d],
     p1=float64[rounds, n_stab], state=complex128[2^(d*d)] or None) where
     `state` is the data register just before the final measurement."""
@@ -137,6 +141,7 @@ def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=N
     job.xbasis = 1 if xbasis else 0
     job.virtual_z = 1 if virtual_z else 0
     job.idle = 1 if idle else 0
+    job.zzp = 1 if zz_plaquette else 0
     keep = None
     if eps_site is not None:
         keep = np.ascontiguousarray(eps_site, dtype=np.float64)

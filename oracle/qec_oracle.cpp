@@ -338,6 +338,7 @@ struct Job {
   int xbasis;              // 1: X-basis memory (logical |+>, final X measurement)
   int virtual_z;           // 1: Rz restores are exact (virtual Z, Fig. 4)
   int idle;                // 1: one-qubit noise on the circuit's waiting qubits at each step
+  int zzp;                 // 1: exp(-i zeta Z_anc Z_q) on the check's data qubits after each step
 };
 
 struct Ctx {
@@ -428,11 +429,28 @@ void idle_data(State& s, Ctx& cx, const Stab& st, int busy) {
   }
 }
 
+// Crosstalk between the ancilla and the plaquette's data qubits (only with
+// job.zzp): exp(-i zeta Z_anc Z_q) for every data qubit q of the running
+// check, after each step of its circuit (after the step's noise).  Diagonal:
+// phase exp(-i zeta) where the two bits agree, exp(+i zeta) where they differ.
+void zz_plaquette(State& s, const Ctx& cx, const Stab& st, int anc) {
+  if (!cx.job->zzp || !cx.noisy || cx.job->zeta == 0.0) return;
+  const cplx same = std::exp(cplx(0.0, -cx.job->zeta)), diff = std::exp(cplx(0.0, cx.job->zeta));
+  for (int j = 0; j < 4; ++j) {
+    const int q = st.slot[j] - 1;
+    if (q < 0) continue;
+    cplx* a = s.a.data();
+    const int64_t N = s.size();
+    for (int64_t i = 0; i < N; ++i) a[i] *= (((i >> anc) ^ (i >> q)) & 1) ? diff : same;
+  }
+}
+
 // Gates and noise of one stabilizer circuit on ancilla `anc`.  With job.idle
 // the circuit runs in steps (cross-resonance X check: Rx^dag | one per slot |
 // Rx with the restores; Z check: one per slot | the restores; textbook: H |
 // one per data qubit | H) and after each step the check's data qubits that
 // the step leaves alone get N1, and in the Z check's restore step the ancilla.
+// With job.zzp the ancilla-plaquette crosstalk follows every step.
 void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
   const double q4 = kPi / 4.0;
   const int gateset = cx.job->gateset;
@@ -442,6 +460,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
       site_rot1(s, cx, anc, 1, -1.0, q4);
       noise1(s, cx, anc);
       idle_data(s, cx, st, 0);
+      zz_plaquette(s, cx, st, anc);
       for (int j = 0; j < 4; ++j) {
         const int q = st.slot[j];
         if (q) {
@@ -451,6 +470,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
           noise1(s, cx, anc);
         }
         idle_data(s, cx, st, q);
+        zz_plaquette(s, cx, st, anc);
       }
       site_rot1(s, cx, anc, 1, 1.0, q4);
       noise1(s, cx, anc);
@@ -460,6 +480,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
         site_rot1(s, cx, q - 1, 1, 1.0, q4);
         noise1(s, cx, q - 1);
       }
+      zz_plaquette(s, cx, st, anc);
     } else {
       for (int j = 0; j < 4; ++j) {
         const int q = st.slot[j];
@@ -470,6 +491,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
           noise1(s, cx, anc);
         }
         idle_data(s, cx, st, q);
+        zz_plaquette(s, cx, st, anc);
       }
       for (int j = 0; j < 4; ++j) {
         const int q = st.slot[j];
@@ -483,6 +505,7 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
         noise1(s, cx, q - 1);
       }
       if (cx.job->idle) noise1(s, cx, anc);  // the ancilla waits during the restores
+      zz_plaquette(s, cx, st, anc);
     }
   } else {
     // Textbook circuit: H, entangling gates, H on the ancilla; each H is
@@ -491,17 +514,20 @@ void run_stabilizer_gates(State& s, Ctx& cx, const Stab& st, int anc) {
     site_rot1(s, cx, anc, 1, 1.0, 0.0);
     noise1(s, cx, anc);
     idle_data(s, cx, st, 0);
+    zz_plaquette(s, cx, st, anc);
     for (int j = 0; j < 4; ++j) {
       const int q = st.slot[j];
       if (!q) continue;
       if (st.type == 0) cnot(s, anc, q - 1); else cz(s, anc, q - 1);
       noise2(s, cx, anc, q - 1);
       idle_data(s, cx, st, q);
+      zz_plaquette(s, cx, st, anc);
     }
     hadamard(s, anc);
     site_rot1(s, cx, anc, 1, 1.0, 0.0);
     noise1(s, cx, anc);
     idle_data(s, cx, st, 0);
+    zz_plaquette(s, cx, st, anc);
   }
 }
 
@@ -642,6 +668,7 @@ typedef struct {
   int xbasis;     // 1: X-basis memory
   int virtual_z;  // 1: Rz restores exact
   int idle;       // 1: idle noise on the waiting qubits of every step
+  int zzp;        // 1: ancilla-plaquette ZZ crosstalk after every step
 } orc_job;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
@@ -674,7 +701,7 @@ int orc_run_trajectory(const orc_job* j, unsigned long long t, uint8_t* records,
                        uint8_t* final_bits, double* p1_trace, double* final_state) {
   if (!j || j->d < 2 || j->d > 5 || j->rounds < 0) return -1;
   Job job{j->d,     j->gateset, j->rounds, j->seed,   j->p,         j->zeta,
-          j->eps_site, j->eps,   j->twirl,  j->xbasis, j->virtual_z, j->idle};
+          j->eps_site, j->eps,   j->twirl,  j->xbasis, j->virtual_z, j->idle, j->zzp};
   Output out{records, final_bits, p1_trace, final_state};
   return run_trajectory(job, t, out);
 }
@@ -683,7 +710,7 @@ int orc_run_trajectory(const orc_job* j, unsigned long long t, uint8_t* records,
 // 2^(d*d) interleaved complex.
 int orc_logical_state(int d, int gateset, int xbasis, double* out) {
   if (d < 2 || d > 5) return -1;
-  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0, 0, xbasis, 0, 0};
+  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0, 0, xbasis, 0, 0, 0};
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);
   if (prepare_logical_zero(s, job, stabs) != 0) return -1;
@@ -719,7 +746,7 @@ int orc_apply_gate(double* state, int n, int k, const int* qubits, const double*
 double orc_time_blocks(const orc_job* j, unsigned long long t, int n_blocks, int* threads) {
   if (!j || j->d < 2 || j->d > 5 || n_blocks < 1) return -1.0;
   Job job{j->d,     j->gateset, 1,         j->seed,   j->p,         j->zeta,
-          j->eps_site, j->eps,     j->twirl, j->xbasis, j->virtual_z, j->idle};
+          j->eps_site, j->eps,     j->twirl, j->xbasis, j->virtual_z, j->idle, j->zzp};
   const int d = job.d, anc = d * d;
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);

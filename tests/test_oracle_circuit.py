@@ -170,7 +170,7 @@ def test_final_measurement_is_born_sampling():
 
 # ---- dense brute force of a whole d=2 trajectory with the same draws ------
 
-def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta, twirl=False, idle=False):
+def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta, twirl=False, idle=False, zzp=False):
     nd = d * d
     n = nd + 1
     anc = nd
@@ -222,11 +222,18 @@ def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta, twirl=False, id
             psi = g(qs, M) @ psi
 
     def wait(slots, busy):
-        """Idle step noise: N1 on the check's other data qubits, slot order."""
-        if idle:
+        """End of a step: idle noise (N1 on the check's other data qubits, slot
+        order), then the ancilla-plaquette crosstalk exp(-i zeta Z_anc Z_q) on
+        each of the check's data qubits."""
+        nonlocal psi
+        if idle and busy is not None:
             for q in slots:
                 if q and q != busy:
                     n1(q - 1)
+        if zzp:
+            for q in slots:
+                if q:
+                    psi = g([anc, q - 1], np.diag(np.exp(-1j * zeta * np.array([1, -1, -1, 1])))) @ psi
 
     # ZX with bit0 = control (Z), bit1 = target (X): kron(X, Z)
     ZX = np.kron(X, Z)
@@ -259,6 +266,7 @@ def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta, twirl=False, id
                     for q in slots:
                         if q:
                             site([q - 1], X, 1, q4); n1(q - 1)
+                    wait(slots, None)  # no waiting qubit in the last step
                 else:
                     for q in slots:
                         if q:
@@ -271,6 +279,7 @@ def _dense_trajectory(d, gateset, rounds, seed, t, p, eps, zeta, twirl=False, id
                             site([q - 1], Z, 1, q4); n1(q - 1)
                     if idle:
                         n1(anc)
+                    wait(slots, None)
             else:
                 psi = g([anc], H) @ psi; site([anc], X, 1, 0.0); n1(anc); wait(slots, 0)
                 for q in slots:
@@ -485,3 +494,37 @@ def test_idle_noise_pauli_only_matches_frame_sampler(gateset):
     # idle noise raises the detector rates over the run without it
     f0, _ = frame.sample(d, gateset, R, p, 200000, seed=5)
     assert _detectors(frec).mean() > 1.2 * _detectors(f0).mean()
+
+
+
+# ---- ancilla-plaquette ZZ crosstalk after every step ------------------------
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+def test_dense_brute_force_d2_zz_plaquette_trajectories(gateset):
+    """Per-step crosstalk exp(-i zeta Z_anc Z_q) on the running check's data
+    qubits (with the once-per-circuit data ZZ layer), also with idle noise and
+    twirled over-rotations, against the dense brute force with the same draws."""
+    d, R = 2, 2
+    for t, (p, eps, zeta, tw, idle) in enumerate([(0.0, 0.0, 0.15, False, False),
+                                                  (0.08, 0.05, 0.1, False, False),
+                                                  (0.1, 0.2, 0.07, True, True)]):
+        rec, fb, st = _dense_trajectory(d, gateset, R, 43, t, p, eps, zeta, twirl=tw, idle=idle, zzp=True)
+        o = oracle.run_trajectory(d, gateset, R, seed=43, t=t, p=p, eps=eps, zeta=zeta, want_state=True,
+                                  twirl=tw, idle=idle, zz_plaquette=True)
+        assert np.array_equal(o["records"], rec)
+        assert np.array_equal(o["final_bits"], fb)
+        assert np.allclose(o["state"], st, atol=1e-12)
+
+
+def test_zz_plaquette_acts_on_the_first_check():
+    """The crosstalk alone changes the first X check's outcome probability
+    (the data ZZ layer does not: it commutes with that measurement); zeta = 0
+    leaves every trajectory unchanged."""
+    d = 3
+    a = oracle.run_trajectory(d, CR, 1, seed=5, t=0, p=0.0, zeta=0.2, zz_plaquette=True)
+    b = oracle.run_trajectory(d, CR, 1, seed=5, t=0, p=0.0, zeta=0.2)
+    assert abs(a["p1"][0, 0] - b["p1"][0, 0]) > 1e-4
+    c = oracle.run_trajectory(d, CR, 2, seed=5, t=1, p=0.02, eps=0.03, zeta=0.0, zz_plaquette=True,
+                              want_state=True)
+    e = oracle.run_trajectory(d, CR, 2, seed=5, t=1, p=0.02, eps=0.03, zeta=0.0, want_state=True)
+    assert np.array_equal(c["records"], e["records"]) and np.allclose(c["state"], e["state"], atol=1e-14)
