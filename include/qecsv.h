@@ -100,6 +100,14 @@ typedef enum {
                                 per data qubit of the check that the step does
                                 not touch (slot order), and one on the ancilla
                                 after the Z check's restores */
+#define SV_RUN_ZZ_PLAQUETTE 32 /* crosstalk between the ancilla and the running
+                                  check's data qubits: after every step (as
+                                  for SV_RUN_IDLE_NOISE, after its noise),
+                                  exp(-i zeta Z_anc Z_q) for each data qubit
+                                  q of the check, in addition to the
+                                  once-per-circuit data ZZ layer; X checks
+                                  then get dense Kraus pairs (no effect when
+                                  zeta = 0) */
 
 typedef struct sv_state_s* sv_state;
 
@@ -199,7 +207,8 @@ typedef struct sv_job {
   int dtype;           /* sv_dtype of the state */
   int n_traj;          /* trajectories */
   int flags;           /* SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS |
-                          SV_RUN_VIRTUAL_Z | SV_RUN_IDLE_NOISE
+                          SV_RUN_VIRTUAL_Z | SV_RUN_IDLE_NOISE |
+                          SV_RUN_ZZ_PLAQUETTE
                           (sv_run_rounds only; with
                           SV_RUN_GRAPH final_states must be NULL) */
   uint64_t traj0;      /* first trajectory index (draw stream id) */

@@ -322,23 +322,26 @@ SV_RUN_TWIRL = 2
 SV_RUN_XBASIS = 4
 SV_RUN_VIRTUAL_Z = 8
 SV_RUN_IDLE_NOISE = 16
+SV_RUN_ZZ_PLAQUETTE = 32
 
 
 def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0,
                dtype="c128", traj0=0, want_p1=False, want_states=False, stream=None, graph=False,
-               twirl=False, xbasis=False, virtual_z=False, idle_noise=False):
+               twirl=False, xbasis=False, virtual_z=False, idle_noise=False, zz_plaquette=False):
     """sv_run_rounds: returns dict(records[n_traj, rounds, n_stab], final_bits[n_traj, d*d],
     p1 or None, states or None, gpu_ms, pass_ms, passes_per_round).  Flags:
     graph (HIP graph replay), twirl (Pauli-twirled over-rotations), xbasis
     (X-basis memory), virtual_z (exact Rz restores), idle_noise (one-qubit
-    noise on the waiting qubits of every step)."""
+    noise on the waiting qubits of every step), zz_plaquette (crosstalk
+    exp(-i zeta Z_anc Z_q) with the check's data qubits after every step)."""
     n_stab, n_sites, _ = template_info(d, gateset)
     job = Job()
     job.d, job.gateset, job.rounds = d, _GATESETS[gateset], rounds
     job.dtype, job.n_traj = _DTYPES[dtype], n_traj
     job.flags = ((SV_RUN_GRAPH if graph else 0) | (SV_RUN_TWIRL if twirl else 0)
                  | (SV_RUN_XBASIS if xbasis else 0) | (SV_RUN_VIRTUAL_Z if virtual_z else 0)
-                 | (SV_RUN_IDLE_NOISE if idle_noise else 0))
+                 | (SV_RUN_IDLE_NOISE if idle_noise else 0)
+                 | (SV_RUN_ZZ_PLAQUETTE if zz_plaquette else 0))
     job.traj0, job.seed, job.p, job.eps, job.zeta = int(traj0), int(seed), float(p), float(eps), float(zeta)
     job.hip_stream = _stream_ptr(stream)
     keep = None

@@ -201,9 +201,58 @@ __global__ void k_prepare(const TBlock* __restrict__ blocks, int n_stab, int rou
   const uint64_t k0 = (uint64_t)r * (uint64_t)draws_per_round + (uint64_t)b.draw_off;
   const uint64_t t = stream ? *stream : traj0 + (uint64_t)ti;
   draw_block(b, seed, t, k0, p, pauli, &rt.u, twirl_thr);
-  if (!build_block(b, eps_site, pauli, rt)) atomicOr(err, 1);
+  if (b.dense) {  // the Kraus pair comes from k_prepare_dense
+    for (int m = 0; m < 2; ++m)
+      for (int x = 0; x < 16; ++x) {
+        rt.D[m][x][0] = rt.D[m][x][1] = 0.0;
+        rt.W[m][x] = 0.0;
+      }
+    rt.F = 0;
+  } else if (!build_block(b, eps_site, pauli, rt)) {
+    atomicOr(err, 1);
+  }
   rt.pad = 0;
   out[gid] = rt;
+}
+
+// Dense Kraus pairs of the blocks that are not monomial in their basis: one
+// thread per (trajectory, block instance, input label x) runs the circuit on
+// |anc 0, data x> with the instance's drawn Paulis and writes column x of K_0
+// and K_1 (the same draws as k_prepare).
+__global__ __launch_bounds__(128) void k_prepare_dense(
+    const TBlock* __restrict__ blocks, int n_stab, int rounds, int draws_per_round, uint64_t seed,
+    uint64_t traj0, int n_traj, double p, const double* __restrict__ eps_site,
+    BlockDense* __restrict__ out, int* __restrict__ err, const uint64_t* __restrict__ stream,
+    const double* __restrict__ twirl_thr) {
+  const int per_traj = rounds * n_stab;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)per_traj * n_traj * 16) return;
+  const int x = (int)(gid & 15);
+  const int64_t inst = gid >> 4;
+  const int ti = (int)(inst / per_traj);
+  const int bi = (int)(inst % per_traj);
+  const int r = bi / n_stab, s = bi % n_stab;
+  const TBlock& b = blocks[s];
+  if (!b.dense) return;
+  BlockDense& o = out[inst];
+  if (x >= (1 << b.w)) {
+    for (int m = 0; m < 2; ++m)
+      for (int i = 0; i < 16; ++i) o.K[m][i][x][0] = o.K[m][i][x][1] = 0.0;
+    return;
+  }
+  uint8_t pauli[kMaxOps];
+  double u;
+  const uint64_t k0 = (uint64_t)r * (uint64_t)draws_per_round + (uint64_t)b.draw_off;
+  const uint64_t t = stream ? *stream : traj0 + (uint64_t)ti;
+  draw_block(b, seed, t, k0, p, pauli, &u, twirl_thr);
+  cd psi[32];
+  if (!dense_column(b, CsFromEps{eps_site}, pauli, x, psi)) atomicOr(err, 1);
+  for (int m = 0; m < 2; ++m)
+    for (int i = 0; i < 16; ++i) {
+      const cd v = i < (1 << b.w) ? psi[(m << 4) | i] : cd{0.0, 0.0};
+      o.K[m][i][x][0] = v.re;
+      o.K[m][i][x][1] = v.im;
+    }
 }
 
 // cos / sin of every gate site's angle for each trajectory slot (one thread
@@ -313,13 +362,60 @@ struct XposeLds {
   T v[2 << kTileMax];
 };
 
+// Dense Kraus pair in the register's frame: with f the Pauli-X frame on the
+// check's qubits, the physical operator is X^f K X^f, entry K[r ^ f][c ^ f].
+// S_0, S_1 of one group of 2^W amplitudes: |K_0 v|^2, |K_1 v|^2.
+template <typename T, int W>
+__device__ __forceinline__ void dense_sums(const C2<T>* v, const BlockDense* __restrict__ dn, uint32_t f,
+                                           double& s0, double& s1) {
+  constexpr int N = 1 << W;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      double yr = 0.0, yi = 0.0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const double kr = dn->K[m][r ^ f][c ^ f][0], ki = dn->K[m][r ^ f][c ^ f][1];
+        const double vr = (double)v[c].re, vi = (double)v[c].im;
+        yr += kr * vr - ki * vi;
+        yi += kr * vi + ki * vr;
+      }
+      s += yr * yr + yi * yi;
+    }
+    if (m == 0) s0 += s; else s1 += s;
+  }
+}
+
+// v <- K_m v for one group of 2^W amplitudes (frame f as above).
+template <typename T, int W>
+__device__ __forceinline__ void dense_apply(C2<T>* v, const BlockDense* __restrict__ dn, int m, uint32_t f) {
+  constexpr int N = 1 << W;
+  C2<T> y[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    double yr = 0.0, yi = 0.0;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      const double kr = dn->K[m][r ^ f][c ^ f][0], ki = dn->K[m][r ^ f][c ^ f][1];
+      const double vr = (double)v[c].re, vi = (double)v[c].im;
+      yr += kr * vr - ki * vi;
+      yi += kr * vi + ki * vr;
+    }
+    y[r] = C2<T>{(T)yr, (T)yi};
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] = y[r];
+}
+
 // Sums of an X check from a tile held in layout 1: regroup it through LDS
 // into layout 2, where a lane holds the 16 amplitudes spanning the check's
 // qubits.
-template <typename T, int WB>
+template <typename T, int WB, bool DN>
 __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const UnitPass* pd,
                                             const double* w0, const double* w1, bool active,
-                                            double& s0, double& s1) {
+                                            double& s0, double& s1, const BlockDense* dn, uint32_t fb) {
   __shared__ XposeLds<T> sh;
   if (active) {
 #pragma unroll
@@ -334,6 +430,13 @@ __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = ld2(sh.v, lt ^ pd->b_j_l[j]);
     constexpr int NB = 1 << WB;
+    if constexpr (DN) {
+      if (dn) {
+#pragma unroll
+        for (int hi = 0; hi < 16; hi += NB) dense_sums<T, WB>(v + hi, dn, fb, s0, s1);
+        return;
+      }
+    }
 #pragma unroll
     for (int hi = 0; hi < 16; hi += NB) {
       wht<T, WB>(v + hi);
@@ -405,15 +508,20 @@ __device__ __forceinline__ void chain_tree(double a2, const uint32_t* x,
 // passes alternate, so a pass starts on the lines its predecessor wrote
 // last).  Workgroup 0 records the frame after A in dec_b.
 // AP: weight of an X check A, or the length of a Z chain A (BP likewise).
-template <typename T, int AK, int AP, int BK, int BP>
+// DN: the instantiation that also handles dense Kraus pairs (kept apart so
+// that the dense code does not weigh on the other passes' registers).
+template <typename T, int AK, int AP, int BK, int BP, bool DN>
 __global__ __launch_bounds__(256) void k_upass(
     T* __restrict__ st, const UnitPass* __restrict__ pd, const JobConst* __restrict__ jc,
     const BlockRT* __restrict__ rta, const BlockRT* __restrict__ rtb,
     const Decision* __restrict__ dec_a, Decision* __restrict__ dec_b,
-    double* __restrict__ partials, int reverse, SlotStrides ss) {
+    double* __restrict__ partials, int reverse, SlotStrides ss,
+    const BlockDense* __restrict__ dna, const BlockDense* __restrict__ dnb) {
   st += (size_t)blockIdx.y * ss.st;
   if (rta) rta += (size_t)blockIdx.y * ss.rt;
   if (rtb) rtb += (size_t)blockIdx.y * ss.rt;
+  if (dna) dna += (size_t)blockIdx.y * ss.rt;
+  if (dnb) dnb += (size_t)blockIdx.y * ss.rt;
   if (dec_a) dec_a += (size_t)blockIdx.y * ss.dec;
   dec_b += (size_t)blockIdx.y * ss.dec;
   const int n_tiles = 1 << pd->n_outer;
@@ -562,7 +670,14 @@ __global__ __launch_bounds__(256) void k_upass(
 #pragma unroll
       for (int j = 0; j < 16; ++j) v[j] = ld2(st, gb | pd->j_g[j]);
       if constexpr (AK == U_X) {
-        if (pd->amix) {
+        if (DN && pd->adense) {  // dense Kraus pair (crosstalk inside the check)
+          if constexpr (DN) {
+            const uint32_t fa = gather_loc(phi, pd->aq[0], WA);
+            constexpr int NA = 1 << WA;
+#pragma unroll
+            for (int hi = 0; hi < 16; hi += NA) dense_apply<T, WA>(v + hi, dna, mbits & 1, fa);
+          }
+        } else if (pd->amix) {
           uint32_t xl = 0;  // A's local index bits carried by this thread's lanes
           for (int i = 0; i < 4; ++i)
             if ((tid >> i) & 1) xl |= pd->a_tx[i];
@@ -657,8 +772,16 @@ __global__ __launch_bounds__(256) void k_upass(
     }
   }
   if constexpr (BK == U_X) {
+    const bool bd = DN && pd->bdense;
+    const uint32_t fb = bd ? gather_loc(phi_new, pd->bq[0], WB) : 0u;
     if (pd->bmode == 2) {
-      xpose_xsums<T, WB>(o, lt, pd, wt[0][0], wt[0][1], active, acc[0], acc[1]);
+      xpose_xsums<T, WB, DN>(o, lt, pd, wt[0][0], wt[0][1], active, acc[0], acc[1], bd ? dnb : nullptr, fb);
+    } else if (active && bd) {
+      if constexpr (DN) {
+        constexpr int NB = 1 << WB;
+#pragma unroll
+        for (int hi = 0; hi < 16; hi += NB) dense_sums<T, WB>(o + hi, dnb, fb, acc[0], acc[1]);
+      }
     } else if (active) {
       constexpr int NB = 1 << WB;
 #pragma unroll

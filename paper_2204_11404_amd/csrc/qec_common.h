@@ -71,6 +71,7 @@ enum OpKind : uint8_t {
   OP_N1_DATA = 9,   // ... on data j
   OP_N2_AD = 10,    // two-qubit location, first qubit ancilla, second data j
   OP_N2_DA = 11,    // two-qubit location, first qubit data j, second ancilla
+  OP_ZZ_AD = 12,    // exp(-i beta Z_anc Z_j): ancilla-plaquette crosstalk (beta from its site)
 };
 
 struct TOp {
@@ -85,7 +86,7 @@ struct TOp {
   int16_t pad2;
 };
 
-constexpr int kMaxOps = 40;       // cross-resonance X check with idle noise: 36
+constexpr int kMaxOps = 64;       // cross-resonance X check with idle noise and per-step ZZ: 60
 constexpr int kMaxOpsBatch = 24;  // templates of the batched paths (no idle noise): 20
 
 struct TBlock {
@@ -94,6 +95,7 @@ struct TBlock {
   int qubit[4];      // data qubit (bit index) per local index
   int n_ops;
   int n_draws;       // noise draws + 1 measurement draw
+  int dense;         // 1: not monomial in the block basis (dense Kraus pair, BlockDense)
   int draw_off;      // first draw of this block within the round
   int site_off;      // first site of this block within the round
   uint64_t n2mask;   // bit k set if noise draw k is a two-qubit location
@@ -114,6 +116,13 @@ struct BlockRT {
   double u;       // measurement draw
   uint32_t F;     // XOR pattern (local data bits)
   uint32_t pad;
+};
+
+// Dense Kraus pair of a block that is not monomial in its basis:
+// K[m][i][x] = <anc m, data i| U |anc 0, data x>, data labels in the
+// computational basis of the block's qubits (bit l = block qubit l).
+struct BlockDense {
+  double K[2][16][16][2];
 };
 
 // Thresholds of the depolarizing channels: Pauli j is chosen for the first
@@ -314,6 +323,14 @@ QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd
         anc_pauli(pj & 3, v0, v1);
         break;
       }
+      case OP_ZZ_AD: {  // diagonal only in the computational basis of the data
+        if (xb) return false;
+        const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
+        const cd c = cs(op);
+        v0 = cmul(v0, cd{c.re, -c.im * e});
+        v1 = cmul(v1, cd{c.re, c.im * e});
+        break;
+      }
       default:
         return false;
     }
@@ -347,6 +364,126 @@ QEC_HD bool build_block(const TBlock& b, const double* eps_site, const uint8_t* 
     out.W[0][x] = out.W[1][x] = 0.0;
   }
   out.F = F;
+  return true;
+}
+
+// ---- dense Kraus pairs (blocks that are not monomial in their basis) ------
+// The circuit's ops on the 32-amplitude register of the ancilla (bit 4) and
+// the block's data qubits (bits 0..3, bit l = block qubit l), computational
+// basis.
+QEC_HD void dn_gate1(cd* psi, uint32_t mask, cd m00, cd m01, cd m10, cd m11) {
+  for (uint32_t i = 0; i < 32; ++i) {
+    if (i & mask) continue;
+    const cd a = psi[i], b = psi[i | mask];
+    psi[i] = cd{m00.re * a.re - m00.im * a.im + m01.re * b.re - m01.im * b.im,
+                m00.re * a.im + m00.im * a.re + m01.re * b.im + m01.im * b.re};
+    psi[i | mask] = cd{m10.re * a.re - m10.im * a.im + m11.re * b.re - m11.im * b.im,
+                       m10.re * a.im + m10.im * a.re + m11.re * b.im + m11.im * b.re};
+  }
+}
+
+// exp(-i theta P) (P = 1 X, 2 Y, 3 Z) with c = cos theta, s = sin theta.
+QEC_HD void dn_rot(cd* psi, uint32_t mask, int axis, double c, double s) {
+  if (axis == 1) dn_gate1(psi, mask, {c, 0}, {0, -s}, {0, -s}, {c, 0});
+  else if (axis == 2) dn_gate1(psi, mask, {c, 0}, {-s, 0}, {s, 0}, {c, 0});
+  else dn_gate1(psi, mask, {c, -s}, {0, 0}, {0, 0}, {c, s});
+}
+
+// Pauli P (1 X, 2 Y = [[0,-i],[i,0]], 3 Z).
+QEC_HD void dn_pauli(cd* psi, uint32_t mask, int P) {
+  if (P == 1) dn_gate1(psi, mask, {0, 0}, {1, 0}, {1, 0}, {0, 0});
+  else if (P == 2) dn_gate1(psi, mask, {0, 0}, {0, -1}, {0, 1}, {0, 0});
+  else if (P == 3) dn_gate1(psi, mask, {1, 0}, {0, 0}, {0, 0}, {-1, 0});
+}
+
+// exp(-i theta Z_c X_t): on qubit t, [[c, -i z s], [-i z s, c]] with z = +-1
+// the eigenvalue of Z_c.
+QEC_HD void dn_zx(cd* psi, uint32_t cmask, uint32_t tmask, double c, double s) {
+  for (uint32_t i = 0; i < 32; ++i) {
+    if (i & tmask) continue;
+    const double z = (i & cmask) ? -1.0 : 1.0;
+    const cd a = psi[i], b = psi[i | tmask];
+    // c a - i z s b,  -i z s a + c b
+    psi[i] = cd{c * a.re + z * s * b.im, c * a.im - z * s * b.re};
+    psi[i | tmask] = cd{z * s * a.im + c * b.re, -z * s * a.re + c * b.im};
+  }
+}
+
+// Column x of the dense Kraus pair: runs the block's ops on |anc 0, data x>
+// and returns the final 32 amplitudes (ancilla bit 4).  Returns false for an
+// op kind it does not know.
+template <typename CS>
+QEC_HD bool dense_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd* psi) {
+  for (int i = 0; i < 32; ++i) psi[i] = {0.0, 0.0};
+  psi[x] = {1.0, 0.0};
+  const uint32_t A = 16u;
+  for (int i = 0; i < b.n_ops; ++i) {
+    const TOp& op = b.ops[i];
+    const uint32_t Q = 1u << op.j;
+    switch (op.kind) {
+      case OP_ROT_ANC: {
+        const cd c = cs(op);
+        dn_rot(psi, A, op.axis, c.re, c.im * (double)op.sgn);
+        if (pauli[i]) dn_pauli(psi, A, op.axis);
+        break;
+      }
+      case OP_ROT_DATA: {
+        const cd c = cs(op);
+        dn_rot(psi, Q, op.axis, c.re, c.im * (double)op.sgn);
+        if (pauli[i]) dn_pauli(psi, Q, op.axis);
+        break;
+      }
+      case OP_CR_AD: {
+        const cd c = cs(op);
+        dn_zx(psi, A, Q, c.re, c.im);
+        if (pauli[i]) { dn_pauli(psi, A, 3); dn_pauli(psi, Q, 1); }
+        break;
+      }
+      case OP_CR_DA: {
+        const cd c = cs(op);
+        dn_zx(psi, Q, A, c.re, c.im);
+        if (pauli[i]) { dn_pauli(psi, Q, 3); dn_pauli(psi, A, 1); }
+        break;
+      }
+      case OP_H_ANC: {
+        const double h = 0.70710678118654752440;
+        dn_gate1(psi, A, {h, 0}, {h, 0}, {h, 0}, {-h, 0});
+        break;
+      }
+      case OP_CNOT_AD:
+        for (uint32_t k = 0; k < 32; ++k)
+          if ((k & A) && !(k & Q)) { const cd t = psi[k]; psi[k] = psi[k | Q]; psi[k | Q] = t; }
+        break;
+      case OP_CZ_AD:
+        for (uint32_t k = 0; k < 32; ++k)
+          if ((k & A) && (k & Q)) psi[k] = {-psi[k].re, -psi[k].im};
+        break;
+      case OP_N1_ANC:
+        dn_pauli(psi, A, pauli[i]);
+        break;
+      case OP_N1_DATA:
+        dn_pauli(psi, Q, pauli[i]);
+        break;
+      case OP_N2_AD:
+        dn_pauli(psi, A, pauli[i] >> 2);
+        dn_pauli(psi, Q, pauli[i] & 3);
+        break;
+      case OP_N2_DA:
+        dn_pauli(psi, Q, pauli[i] >> 2);
+        dn_pauli(psi, A, pauli[i] & 3);
+        break;
+      case OP_ZZ_AD: {
+        const cd c = cs(op);
+        for (uint32_t k = 0; k < 32; ++k) {
+          const double z = (((k >> 4) ^ (k >> op.j)) & 1) ? -1.0 : 1.0;  // Z_anc Z_j eigenvalue
+          psi[k] = cmul(psi[k], cd{c.re, -c.im * z});
+        }
+        break;
+      }
+      default:
+        return false;
+    }
+  }
   return true;
 }
 
@@ -444,6 +581,7 @@ struct UnitPass {
   // thread's index bits i and a_jx[j] of register slot j; amix_lanes: the
   // lane bits (0..3) that carry qubits of A
   int amix, amix_r, amix_lanes, pad_amix;
+  int adense, bdense;  // the X check A / B has a dense Kraus pair (BlockDense)
   uint32_t a_tx[8], a_jx[16];
   uint32_t aq[kChainMax][4];     // global bit of local bit l of A's member i
   uint32_t bq[kChainMax][4];

@@ -139,8 +139,10 @@ std::vector<Stab> code_layout(int d) {
 // ------------------------------------------------------------- template --
 struct Template {
   std::vector<TBlock> blocks;
-  int n_sites = 0;
+  int n_sites = 0;   // gate sites of the round (the per-site over-rotation table)
   int n_draws = 0;
+  int zz_site = -1;  // >= 0: angle-table entry n_sites holds the per-step crosstalk zeta
+  bool any_dense = false;
 };
 
 struct OpSink {
@@ -150,9 +152,9 @@ struct OpSink {
   bool vz;     // Rz restores are virtual: exact, no draw
   int sites = 0;
   int draws = 0;
-  // The largest block (cross-resonance X check of weight 4 with idle noise and
-  // twirled rotations) needs 36 ops and 36 noise draws: within kMaxOps and the
-  // 64-bit n2mask for every template the builder makes.
+  // The largest block (cross-resonance X check of weight 4 with idle noise,
+  // twirled rotations and per-step crosstalk) needs 60 ops and 36 noise draws:
+  // within kMaxOps and the 64-bit n2mask for every template the builder makes.
   TOp& next() {
     if (b.n_ops >= kMaxOps || draws >= 63) {
       std::fprintf(stderr, "qecsv: block template exceeds kMaxOps\n");
@@ -174,6 +176,12 @@ struct OpSink {
     o = TOp{};
     o.kind = kind; o.j = (uint8_t)j; o.site = -1; o.draw = -1;
   }
+  // exp(-i zeta Z_anc Z_j); its angle is the angle-table entry zz_site
+  void zz(int j, int zz_site) {
+    TOp& o = next();
+    o = TOp{};
+    o.kind = OP_ZZ_AD; o.j = (uint8_t)j; o.site = (int16_t)zz_site; o.draw = -1;
+  }
   void noise(uint8_t kind, int j) {
     TOp& o = next();
     o = TOp{};
@@ -192,8 +200,15 @@ struct OpSink {
 // (Sec. III.A): after a step, N1 on every data qubit of the check that the
 // step leaves alone, in slot order; the ancilla waits during the Z check's
 // restores.
-Template build_template(int d, int gateset, bool twirl = false, bool vz = false, bool idle = false) {
+// zzp: after each step (after its noise), the crosstalk exp(-i zeta Z_anc Z_q)
+// between the ancilla and every data qubit of the check; its angle sits in
+// the angle table after the n_sites gate sites.  X checks then stop being
+// monomial in their Hadamard basis and get dense Kraus pairs.
+Template build_template(int d, int gateset, bool twirl = false, bool vz = false, bool idle = false,
+                        bool zzp = false) {
   Template T;
+  if (zzp)  // the crosstalk entry follows every gate site
+    T.zz_site = build_template(d, gateset, twirl, vz, idle, false).n_sites;
   for (const Stab& st : code_layout(d)) {
     TBlock b{};
     b.type = st.type;
@@ -209,10 +224,12 @@ Template build_template(int d, int gateset, bool twirl = false, bool vz = false,
     b.draw_off = T.n_draws;
     b.site_off = T.n_sites;
     OpSink o{b, T.n_sites, twirl, vz};
-    auto waiting = [&](int busy_slot) {  // idle data qubits of one step
-      if (!idle) return;
-      for (int s = 0; s < 4; ++s)
-        if (local[s] >= 0 && s != busy_slot) o.noise(OP_N1_DATA, local[s]);
+    auto waiting = [&](int busy_slot) {  // end of a step: idle data qubits, crosstalk
+      if (idle && busy_slot != -2)
+        for (int s = 0; s < 4; ++s)
+          if (local[s] >= 0 && s != busy_slot) o.noise(OP_N1_DATA, local[s]);
+      if (zzp)
+        for (int l = 0; l < b.w; ++l) o.zz(l, T.zz_site);
     };
     if (gateset == SV_GATESET_CR) {
       if (st.type == 0) {
@@ -234,6 +251,7 @@ Template build_template(int d, int gateset, bool twirl = false, bool vz = false,
           o.gate(OP_ROT_DATA, l, 1, 1, 1);  // restoring Rx(pi/2) on data
           o.noise(OP_N1_DATA, l);
         }
+        waiting(-2);  // nobody waits in this step
       } else {
         for (int s = 0; s < 4; ++s) {
           if (local[s] >= 0) {
@@ -249,6 +267,7 @@ Template build_template(int d, int gateset, bool twirl = false, bool vz = false,
           o.noise(OP_N1_DATA, l);
         }
         if (idle) o.noise(OP_N1_ANC, 0);  // the ancilla waits during the restores
+        waiting(-2);
       }
     } else {
       o.plain(OP_H_ANC, 0);
@@ -269,6 +288,15 @@ Template build_template(int d, int gateset, bool twirl = false, bool vz = false,
     b.n_draws = o.draws + 1;  // + measurement
     T.n_sites += o.sites;
     T.n_draws += b.n_draws;
+    // not monomial in the block basis (an X check with crosstalk): dense Kraus pair
+    {
+      const std::vector<double> zero(T.zz_site + 2 + T.n_sites, 0.0);
+      const uint8_t none[kMaxOps] = {};
+      cd v0, v1;
+      uint32_t cur = 0;
+      b.dense = track_column(b, CsFromEps{zero.data()}, none, 0, v0, v1, &cur) ? 0 : 1;
+      T.any_dense = T.any_dense || b.dense;
+    }
     T.blocks.push_back(b);
   }
   return T;
@@ -494,11 +522,13 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
   // four lowest bits for the thread index (runs of >= 256 bytes)
   const bool bx_high = bx && disjoint(xqubits(B), 0xFu);
   pd.amix = 0;
+  pd.adense = ax && tp.blocks[A->first].dense;
+  pd.bdense = bx && tp.blocks[B->first].dense;
   std::vector<int> a_high;  // amix: A's qubits held in register slots
   if (ax) {
     uint32_t am = 0;
     for (int q : xqubits(A)) am |= 1u << q;
-    if ((am & 0x3u) && tb >= 8) {
+    if ((am & 0x3u) && tb >= 8 && !pd.adense) {
       for (int q : xqubits(A))
         if (q >= 4) a_high.push_back(q);
       if (slots(a_high, UB | 0xFu, J1) || slots(a_high, 0xFu, J1)) pd.amix = 1;
@@ -671,21 +701,40 @@ void launch_wht_all(hipStream_t s, T* st, int n) {
   }
 }
 
+// One pass kernel launch; the instantiation with the dense Kraus code exists
+// only for unit pairs with an X check.
+template <typename T, int AK, int AP, int BK, int BP>
+void launch_pass(bool dense, dim3 g, dim3 b, hipStream_t s, T* st, const UnitPass* pd, const JobConst* jc,
+                 const BlockRT* rta, const BlockRT* rtb, const Decision* da, Decision* db, double* part,
+                 int rev, SlotStrides ss, const BlockDense* dna, const BlockDense* dnb) {
+  if constexpr (AK == U_X || BK == U_X) {
+    if (dense) {
+      hipLaunchKernelGGL((k_upass<T, AK, AP, BK, BP, true>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, part,
+                         rev, ss, dna, dnb);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_upass<T, AK, AP, BK, BP, false>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, part, rev,
+                     ss, dna, dnb);
+}
+
 // Launches the pass kernel instantiated for the descriptor's unit kinds.
 template <typename T>
 sv_status launch_upass(const UnitPass& h, dim3 g, dim3 b, hipStream_t s, T* st, const UnitPass* pd,
                        const JobConst* jc, const BlockRT* rta, const BlockRT* rtb,
                        const Decision* da, Decision* db, double* part, int rev,
-                       SlotStrides ss = SlotStrides{0, 0, 0}) {
-#define QEC_UP(AK, AP, BK, BP)                                                                  \
-  if (h.akind == AK && ap == AP && h.bkind == BK && bp == BP) {                                 \
-    hipLaunchKernelGGL((k_upass<T, AK, AP, BK, BP>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, \
-                       part, rev, ss);                                                          \
-    return SV_OK;                                                                               \
+                       SlotStrides ss = SlotStrides{0, 0, 0}, const BlockDense* dna = nullptr,
+                       const BlockDense* dnb = nullptr) {
+#define QEC_UP(AK, AP, BK, BP)                                                                      \
+  if (h.akind == AK && ap == AP && h.bkind == BK && bp == BP) {                                     \
+    launch_pass<T, AK, AP, BK, BP>(h.adense || h.bdense, g, b, s, st, pd, jc, rta, rtb, da, db, part, \
+                                   rev, ss, dna, dnb);                                              \
+    return SV_OK;                                                                                   \
   }
 #define QEC_UP_B(AK, AP) \
   QEC_UP(AK, AP, U_X, 2) QEC_UP(AK, AP, U_X, 4) QEC_UP(AK, AP, U_Z, 1) QEC_UP(AK, AP, U_Z, 2) \
   QEC_UP(AK, AP, U_Z, 3) QEC_UP(AK, AP, U_Z, 4)
+  if ((h.adense && !dna) || (h.bdense && !dnb)) return fail(SV_EINVAL, "dense unit without its Kraus table");
   const int ap = h.akind == U_X ? h.wa : (h.akind == U_Z ? h.la : 0);
   const int bp = h.bkind == U_X ? h.wb : (h.bkind == U_Z ? h.lb : 0);
   QEC_UP_B(U_INIT, 0)
@@ -696,6 +745,7 @@ sv_status launch_upass(const UnitPass& h, dim3 g, dim3 b, hipStream_t s, T* st, 
 #undef QEC_UP
   return fail(SV_EINVAL, "no pass kernel for units (%d,%d)->(%d,%d)", h.akind, h.wa, h.bkind, h.wb);
 }
+
 
 // Passes of a round sequence: [0] writes logical |0> and sums unit 0;
 // [1 + u] applies unit u and sums unit u + 1 (unit 0 of the next round after
@@ -742,9 +792,12 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   const uint64_t na = 1ull << n;
   const int cb = std::min(12, n);
   const size_t n_tiles = (size_t)1 << (n - tb);
-  // trajectories per prepare chunk: keep the block table under 64 MiB
+  // trajectories per prepare chunk: keep the block tables under 64 MiB
   const size_t rt_per_traj = sizeof(BlockRT) * (size_t)per_traj;
-  const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)job->n_traj, ((size_t)64 << 20) / rt_per_traj));
+  const size_t dn_per_traj = tp.any_dense ? sizeof(BlockDense) * (size_t)per_traj : 0;
+  const int chunk = (int)std::max<size_t>(
+      1, std::min<size_t>((size_t)job->n_traj, ((size_t)64 << 20) / (rt_per_traj + dn_per_traj)));
+  const int n_angles = std::max(1, tp.zz_site >= 0 ? tp.zz_site + 1 : tp.n_sites);
   const size_t nrec = (size_t)job->n_traj * per_traj;
   HIP_OK(M.alloc(&st, sizeof(T) * 2 * na));
   HIP_OK(M.alloc(&partials, sizeof(double) * kChainAcc * n_tiles));
@@ -756,7 +809,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   HIP_OK(M.alloc(&dblocks, sizeof(TBlock) * ns));
   HIP_OK(M.alloc(&dpass, sizeof(UnitPass) * (nu + 2)));
   HIP_OK(M.alloc(&djc, sizeof(JobConst)));
-  HIP_OK(M.alloc(&deps, sizeof(double) * std::max(1, tp.n_sites)));
+  HIP_OK(M.alloc(&deps, sizeof(double) * n_angles));
   HIP_OK(M.alloc(&ddec, sizeof(Decision) * (per_units + 1)));
   HIP_OK(M.alloc(&drec, nrec));
   HIP_OK(M.alloc(&dbits, (size_t)job->n_traj * n));
@@ -764,13 +817,16 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   HIP_OK(M.alloc(&dsums, sizeof(double) << (n - cb)));
   HIP_OK(M.alloc(&derr, sizeof(int)));
   HIP_OK(M.alloc(&drt, rt_per_traj * chunk));
+  BlockDense* ddn = nullptr;  // dense Kraus pairs (blocks with crosstalk inside)
+  if (tp.any_dense) HIP_OK(M.alloc(&ddn, dn_per_traj * chunk));
 
   const std::vector<UnitPass> pds = make_unit_passes(n, tb, tp, units);
   const bool xbasis = (job->flags & SV_RUN_XBASIS) != 0;
   const JobConst jc = make_job_const(d, job->zeta, xbasis);
-  std::vector<double> eps(std::max(1, tp.n_sites), job->eps);
+  std::vector<double> eps(n_angles, job->eps);
   if (job->eps_site)
     for (int i = 0; i < tp.n_sites; ++i) eps[i] = job->eps_site[i];
+  if (tp.zz_site >= 0) eps[tp.zz_site] = job->zeta;  // the per-step crosstalk angle
 
   HIP_OK(hipMemcpyAsync(dblocks, tp.blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(UnitPass) * (nu + 2), hipMemcpyHostToDevice, s));
@@ -818,8 +874,9 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   // block instance of the first member of unit instance ui
   auto inst = [&](int ui) { return (ui / nu) * ns + units[ui % nu].first; };
   // passes and decisions of one trajectory whose block tables are at rt
-  auto traj_passes = [&](hipStream_t q, const BlockRT* rt, uint8_t* rec, double* p1,
+  auto traj_passes = [&](hipStream_t q, const BlockRT* rt, const BlockDense* dn, uint8_t* rec, double* p1,
                          bool timed) -> sv_status {
+    auto dense = [&](int ui) { return dn ? dn + inst(ui) : (const BlockDense*)nullptr; };
     auto decide = [&](int ui) {
       const int bi = inst(ui);
       const int lb = units[ui % nu].len;
@@ -829,7 +886,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
                          dticket, 1);
     };
     SV_OK_OR_RETURN(launch_upass<T>(pds[0], grid, block, q, st, &dpass[0], djc, nullptr, rt + inst(0),
-                                    nullptr, &ddec[0], partials, 0));
+                                    nullptr, &ddec[0], partials, 0, ss0, nullptr, dense(0)));
     decide(0);
     for (int ui = 0; ui < per_units; ++ui) {
       const int u = ui % nu;
@@ -838,7 +895,8 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       if (timed) HIP_OK(hipEventRecord(evs[2 * ui], q));
       SV_OK_OR_RETURN(launch_upass<T>(pds[pidx], grid, block, q, st, &dpass[pidx], djc, rt + inst(ui),
                                       last ? nullptr : rt + inst(ui + 1), &ddec[ui], &ddec[ui + 1],
-                                      partials, snake ? ((ui + 1) & 1) : 0));
+                                      partials, snake ? ((ui + 1) & 1) : 0, ss0, dense(ui),
+                                      last ? nullptr : dense(ui + 1)));
       if (timed) HIP_OK(hipEventRecord(evs[2 * ui + 1], q));
       if (!last) decide(ui + 1);
     }
@@ -864,10 +922,12 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
     // one trajectory's sequence, staged through fixed buffers and a device
     // trajectory counter, captured once and replayed n_traj times
     BlockRT* rt_s = nullptr;
+    BlockDense* dn_s = nullptr;
     uint8_t *rec_s = nullptr, *bits_s = nullptr;
     double* p1_s = nullptr;
     uint64_t* dcur = nullptr;  // [0] trajectory counter, [1] its draw stream
     HIP_OK(M.alloc(&rt_s, rt_per_traj));
+    if (tp.any_dense) HIP_OK(M.alloc(&dn_s, dn_per_traj));
     HIP_OK(M.alloc(&rec_s, (size_t)per_traj));
     HIP_OK(M.alloc(&bits_s, (size_t)n));
     if (dp1) HIP_OK(M.alloc(&p1_s, sizeof(double) * per_traj));
@@ -897,7 +957,11 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       hipLaunchKernelGGL(k_prepare, dim3((unsigned)((per_traj + 127) / 128)), dim3(128), 0, G.q,
                          dblocks, ns, R, draws_round, job->seed, job->traj0, 1, job->p, deps, rt_s,
                          derr, (const uint64_t*)(dcur + 1), (const double*)dthr);
-      cst = traj_passes(G.q, rt_s, rec_s, p1_s, false);
+      if (dn_s)
+        hipLaunchKernelGGL(k_prepare_dense, dim3((unsigned)((per_traj * 16 + 127) / 128)), dim3(128), 0, G.q,
+                           dblocks, ns, R, draws_round, job->seed, job->traj0, 1, job->p, deps, dn_s, derr,
+                           (const uint64_t*)(dcur + 1), (const double*)dthr);
+      cst = traj_passes(G.q, rt_s, dn_s, rec_s, p1_s, false);
       if (cst == SV_OK) {
         traj_final(G.q, bits_s, 0, dcur + 1);
         hipLaunchKernelGGL(k_commit, dim3(1), dim3(256), 0, G.q, rec_s, p1_s, bits_s, drec, dp1, dbits,
@@ -930,6 +994,10 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       hipLaunchKernelGGL(k_prepare, dim3((unsigned)((nthreads + 127) / 128)), dim3(128), 0, s, dblocks,
                          ns, R, draws_round, job->seed, job->traj0 + (uint64_t)c0, cn, job->p, deps,
                          drt, derr, (const uint64_t*)nullptr, (const double*)dthr);
+      if (ddn)
+        hipLaunchKernelGGL(k_prepare_dense, dim3((unsigned)((nthreads * 16 + 127) / 128)), dim3(128), 0, s,
+                           dblocks, ns, R, draws_round, job->seed, job->traj0 + (uint64_t)c0, cn, job->p, deps,
+                           ddn, derr, (const uint64_t*)nullptr, (const double*)dthr);
       HIP_OK(hipGetLastError());
       for (int ti = 0; ti < cn; ++ti) {
         if (cancel && cancel->load(std::memory_order_relaxed)) {
@@ -937,7 +1005,8 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
           return fail(SV_EBUSY, "cancelled");
         }
         const int tg = c0 + ti;
-        SV_OK_OR_RETURN(traj_passes(s, drt + (size_t)ti * per_traj, drec + (size_t)tg * per_traj,
+        SV_OK_OR_RETURN(traj_passes(s, drt + (size_t)ti * per_traj, ddn ? ddn + (size_t)ti * per_traj : nullptr,
+                                    drec + (size_t)tg * per_traj,
                                     dp1 ? dp1 + (size_t)tg * per_traj : nullptr, tg == last_t));
         if (res->final_states) {
           HIP_OK(hipMemcpyAsync((char*)res->final_states + (size_t)tg * sizeof(T) * 2 * na, st,
@@ -1861,7 +1930,8 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
   if (job->rounds < 1 || job->rounds > 100000) return fail(SV_EINVAL, "rounds=%d", job->rounds);
   if (job->dtype != SV_C64 && job->dtype != SV_C128) return fail(SV_EINVAL, "bad dtype");
   if (job->n_traj < 0) return fail(SV_EINVAL, "n_traj < 0");
-  if (job->flags & ~(SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS | SV_RUN_VIRTUAL_Z | SV_RUN_IDLE_NOISE))
+  if (job->flags & ~(SV_RUN_GRAPH | SV_RUN_TWIRL | SV_RUN_XBASIS | SV_RUN_VIRTUAL_Z | SV_RUN_IDLE_NOISE |
+                     SV_RUN_ZZ_PLAQUETTE))
     return fail(SV_EINVAL, "unknown flags 0x%x", job->flags);
   if (!(job->p >= 0.0 && job->p <= 1.0)) return fail(SV_EINVAL, "p out of [0, 1]");
   if (!std::isfinite(job->eps) || !std::isfinite(job->zeta)) return fail(SV_EINVAL, "non-finite eps/zeta");
@@ -1870,7 +1940,8 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
     return fail(SV_EINVAL, "final_states cannot be returned with SV_RUN_GRAPH");
   const Template tp = build_template(job->d, job->gateset, (job->flags & SV_RUN_TWIRL) != 0,
                                      (job->flags & SV_RUN_VIRTUAL_Z) != 0,
-                                     (job->flags & SV_RUN_IDLE_NOISE) != 0);
+                                     (job->flags & SV_RUN_IDLE_NOISE) != 0,
+                                     (job->flags & SV_RUN_ZZ_PLAQUETTE) != 0 && job->zeta != 0.0);
   if (job->eps_site)
     for (int i = 0; i < tp.n_sites; ++i)
       if (!std::isfinite(job->eps_site[i])) return fail(SV_EINVAL, "non-finite eps_site[%d]", i);

@@ -24,11 +24,13 @@ from . import decode_z, run_rounds
 
 
 def run_point(d, p, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, zeta=0.0,
-              chunk=1000, log=None, twirl=False, basis="Z", virtual_z=False, idle_noise=False):
+              chunk=1000, log=None, twirl=False, basis="Z", virtual_z=False, idle_noise=False,
+              zz_plaquette=False):
     """twirl: Pauli-twirled over-rotations instead of coherent ones; basis
     "X": the X-basis memory (logical |+>, X_L decoded from X checks);
     virtual_z: no over-rotation on the Rz restores of the Z checks;
-    idle_noise: one-qubit noise on the waiting qubits of every step."""
+    idle_noise: one-qubit noise on the waiting qubits of every step;
+    zz_plaquette: ancilla-plaquette crosstalk after every step (zeta)."""
     eps = c * math.sqrt(p)
     fails = amb = over = 0
     gpu_ms = dec_s = 0.0
@@ -36,7 +38,8 @@ def run_point(d, p, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, z
     for first in range(0, n_traj, chunk):
         n = min(chunk, n_traj - first)
         r = run_rounds(d, gateset, rounds, n, seed, p, eps=eps, zeta=zeta, dtype=dtype, traj0=first,
-                       twirl=twirl, xbasis=(basis == "X"), virtual_z=virtual_z, idle_noise=idle_noise)
+                       twirl=twirl, xbasis=(basis == "X"), virtual_z=virtual_z, idle_noise=idle_noise,
+                       zz_plaquette=zz_plaquette)
         gpu_ms += r["gpu_ms"]
         t1 = time.perf_counter()
         out = decode_z(d, gateset, r["records"], r["final_bits"], basis=basis)
@@ -50,6 +53,7 @@ def run_point(d, p, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, z
     pl = fails / n_ok if n_ok else float("nan")
     return {"d": d, "p": p, "c": c, "eps": eps, "rounds": rounds, "dtype": dtype,
             "twirl": twirl, "basis": basis, "virtual_z": virtual_z, "idle_noise": idle_noise,
+            "zz_plaquette": zz_plaquette, "zeta": zeta,
             "trajectories": n_traj, "failures": fails, "p_L": pl,
             "p_L_err": math.sqrt(pl * (1 - pl) / n_ok) if n_ok else float("nan"),
             "ambiguous": amb, "undecoded": over, "gpu_s": gpu_ms * 1e-3, "decode_s": dec_s,
@@ -100,7 +104,7 @@ def fit_effective_model(points, A, xi):
 
 
 def sweep(d, ps, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, zeta=0.0, log=None,
-          twirl=False, basis="Z", virtual_z=False, idle_noise=False):
+          twirl=False, basis="Z", virtual_z=False, idle_noise=False, zz_plaquette=False):
     """n_traj: one count for every p, or a list with one count per p."""
     counts = list(n_traj) if isinstance(n_traj, (list, tuple)) else [n_traj]
     if len(counts) == 1:
@@ -108,7 +112,7 @@ def sweep(d, ps, c, n_traj, rounds=5, gateset="cr", dtype="c64", seed=2022, zeta
     if len(counts) != len(ps):
         raise ValueError("give one trajectory count, or one per p")
     points = [run_point(d, p, c, n, rounds, gateset, dtype, seed, zeta, log=log, twirl=twirl,
-                        basis=basis, virtual_z=virtual_z, idle_noise=idle_noise)
+                        basis=basis, virtual_z=virtual_z, idle_noise=idle_noise, zz_plaquette=zz_plaquette)
               for p, n in zip(ps, counts)]
     return {"points": points, "fit": fit_power_law(points)}
 
@@ -129,10 +133,11 @@ def main():
     ap.add_argument("--basis", default="Z", choices=["Z", "X"], help="memory basis")
     ap.add_argument("--virtual-z", action="store_true", help="exact Rz restores (virtual Z)")
     ap.add_argument("--idle-noise", action="store_true", help="noise on the waiting qubits of each step")
+    ap.add_argument("--zz-plaquette", action="store_true", help="ancilla-plaquette ZZ after each step")
     a = ap.parse_args()
     res = sweep(a.d, a.p, a.c, a.traj, a.rounds, a.gateset, a.dtype, a.seed, a.zeta,
                 log=lambda m: print(m, flush=True), twirl=a.twirl, basis=a.basis,
-                virtual_z=a.virtual_z, idle_noise=a.idle_noise)
+                virtual_z=a.virtual_z, idle_noise=a.idle_noise, zz_plaquette=a.zz_plaquette)
     print(json.dumps(res), flush=True)
 
 

@@ -23,16 +23,16 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "d5_cr_oracle.npz")
 
 
 def _compare(d, gateset, R, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0, dtype="c128",
-             traj0=0, atol=1e-10, twirl=False, xbasis=False, virtual_z=False, idle=False):
+             traj0=0, atol=1e-10, twirl=False, xbasis=False, virtual_z=False, idle=False, zzp=False):
     print(f"case rounds d={d} {gateset} R={R} n={n_traj} p={p} eps={eps} zeta={zeta} {dtype}"
-          f" twirl={twirl} xbasis={xbasis} vz={virtual_z} idle={idle}", flush=True)
+          f" twirl={twirl} xbasis={xbasis} vz={virtual_z} idle={idle} zzp={zzp}", flush=True)
     g = qs.run_rounds(d, gateset, R, n_traj, seed, p, eps=eps, eps_site=eps_site, zeta=zeta,
                       dtype=dtype, traj0=traj0, want_p1=True, want_states=True, twirl=twirl,
-                      xbasis=xbasis, virtual_z=virtual_z, idle_noise=idle)
+                      xbasis=xbasis, virtual_z=virtual_z, idle_noise=idle, zz_plaquette=zzp)
     for i in range(n_traj):
         o = oracle.run_trajectory(d, GS[gateset], R, seed, traj0 + i, p, eps=eps, eps_site=eps_site,
                                   zeta=zeta, want_state=True, twirl=twirl, xbasis=xbasis,
-                                  virtual_z=virtual_z, idle=idle)
+                                  virtual_z=virtual_z, idle=idle, zz_plaquette=zzp)
         assert np.array_equal(g["records"][i], o["records"]), f"trajectory {i}"
         assert np.array_equal(g["final_bits"][i], o["final_bits"]), f"trajectory {i}"
         assert np.max(np.abs(g["p1"][i] - o["p1"])) < atol
@@ -259,3 +259,30 @@ def test_grid_stride_passes_match(monkeypatch):
     assert np.max(np.abs(a["p1"] - b["p1"])) < 1e-12
     assert np.array_equal(a["final_bits"], b["final_bits"])
 
+
+
+@pytest.mark.parametrize("gateset,d,dtype,twirl,idle,xbasis", [
+    ("cr", 3, "c128", False, False, False), ("textbook", 3, "c128", False, False, False),
+    ("cr", 4, "c128", False, True, False), ("cr", 3, "c64", True, False, False),
+    ("cr", 3, "c128", False, False, True)])
+def test_zz_plaquette_parity(gateset, d, dtype, twirl, idle, xbasis):
+    """SV_RUN_ZZ_PLAQUETTE: the ancilla-plaquette crosstalk after every step
+    makes the X checks' Kraus pairs dense (k_prepare_dense, dense pass
+    kernels); records, p1 and register against the oracle."""
+    n_sites = oracle.template_counts(d, GS[gateset])[1]
+    eps = workloads.eps_sites(n_sites, (0.0, 0.3 if twirl else 0.05), 17)
+    _compare(d, gateset, 2, 3 if d == 4 else 8, seed=17, p=0.02, eps_site=eps, zeta=0.08,
+             dtype=dtype, atol=1e-10 if dtype == "c128" else 1e-5, twirl=twirl, idle=idle,
+             xbasis=xbasis, zzp=True)
+
+
+def test_zz_plaquette_graph_and_d5():
+    """The crosstalk runs under graph replay (same records as the stream) and
+    at d=5 (26 qubits)."""
+    kw = dict(d=3, gateset="cr", rounds=2, n_traj=6, seed=18, p=0.01, eps=0.02, zeta=0.05,
+              dtype="c128", want_p1=True, zz_plaquette=True)
+    a = qs.run_rounds(**kw)
+    b = qs.run_rounds(graph=True, **kw)
+    assert np.array_equal(a["records"], b["records"]) and np.array_equal(a["p1"], b["p1"])
+    g = qs.run_rounds(5, "cr", 1, 1, 18, 1e-3, eps=0.01, zeta=0.01, dtype="c64", zz_plaquette=True)
+    assert g["records"].shape == (1, 1, 24)
