@@ -362,25 +362,26 @@ struct XposeLds {
   T v[2 << kTileMax];
 };
 
-// Dense Kraus pair in the register's frame: with f the Pauli-X frame on the
-// check's qubits, the physical operator is X^f K X^f, entry K[r ^ f][c ^ f].
-// S_0, S_1 of one group of 2^W amplitudes: |K_0 v|^2, |K_1 v|^2.
+// Dense Kraus pairs in the register's frame: with f the Pauli-X frame on the
+// check's qubits, the physical operator is X^f K X^f, entry K[r ^ f][c ^ f];
+// the pass stages those entries in LDS once per workgroup.
 template <typename T, int W>
-__device__ __forceinline__ void dense_sums(const C2<T>* v, const BlockDense* __restrict__ dn, uint32_t f,
-                                           double& s0, double& s1) {
+__device__ __forceinline__ void dense_sums(const C2<T>* v, const C2<double> (*K0)[16],
+                                           const C2<double> (*K1)[16], double& s0, double& s1) {
   constexpr int N = 1 << W;
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
+    const C2<double>(*K)[16] = m ? K1 : K0;
     double s = 0.0;
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
+#pragma unroll 1
+    for (int r = 0; r < N; ++r) {  // one row at a time: few live registers
       double yr = 0.0, yi = 0.0;
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        const double kr = dn->K[m][r ^ f][c ^ f][0], ki = dn->K[m][r ^ f][c ^ f][1];
+        const C2<double> k = K[r][c];
         const double vr = (double)v[c].re, vi = (double)v[c].im;
-        yr += kr * vr - ki * vi;
-        yi += kr * vi + ki * vr;
+        yr += k.re * vr - k.im * vi;
+        yi += k.re * vi + k.im * vr;
       }
       s += yr * yr + yi * yi;
     }
@@ -388,9 +389,21 @@ __device__ __forceinline__ void dense_sums(const C2<T>* v, const BlockDense* __r
   }
 }
 
-// v <- K_m v for one group of 2^W amplitudes (frame f as above).
+// LDS for the staged dense Kraus pairs (A's decided one, B's two); only the
+// dense instantiation of the pass kernel allocates it.
+template <bool DN>
+__device__ __forceinline__ C2<double> (*dense_lds())[16][16] {
+  if constexpr (DN) {
+    __shared__ C2<double> k[3][16][16];
+    return k;
+  } else {
+    return nullptr;
+  }
+}
+
+// v <- K v for one group of 2^W amplitudes.
 template <typename T, int W>
-__device__ __forceinline__ void dense_apply(C2<T>* v, const BlockDense* __restrict__ dn, int m, uint32_t f) {
+__device__ __forceinline__ void dense_apply(C2<T>* v, const C2<double> (*K)[16]) {
   constexpr int N = 1 << W;
   C2<T> y[N];
 #pragma unroll
@@ -398,10 +411,10 @@ __device__ __forceinline__ void dense_apply(C2<T>* v, const BlockDense* __restri
     double yr = 0.0, yi = 0.0;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
-      const double kr = dn->K[m][r ^ f][c ^ f][0], ki = dn->K[m][r ^ f][c ^ f][1];
+      const C2<double> k = K[r][c];
       const double vr = (double)v[c].re, vi = (double)v[c].im;
-      yr += kr * vr - ki * vi;
-      yi += kr * vi + ki * vr;
+      yr += k.re * vr - k.im * vi;
+      yi += k.re * vi + k.im * vr;
     }
     y[r] = C2<T>{(T)yr, (T)yi};
   }
@@ -415,7 +428,8 @@ __device__ __forceinline__ void dense_apply(C2<T>* v, const BlockDense* __restri
 template <typename T, int WB, bool DN>
 __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const UnitPass* pd,
                                             const double* w0, const double* w1, bool active,
-                                            double& s0, double& s1, const BlockDense* dn, uint32_t fb) {
+                                            double& s0, double& s1, const C2<double> (*K0)[16],
+                                            const C2<double> (*K1)[16]) {
   __shared__ XposeLds<T> sh;
   if (active) {
 #pragma unroll
@@ -431,9 +445,9 @@ __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const
     for (int j = 0; j < 16; ++j) v[j] = ld2(sh.v, lt ^ pd->b_j_l[j]);
     constexpr int NB = 1 << WB;
     if constexpr (DN) {
-      if (dn) {
+      if (K0) {
 #pragma unroll
-        for (int hi = 0; hi < 16; hi += NB) dense_sums<T, WB>(v + hi, dn, fb, s0, s1);
+        for (int hi = 0; hi < 16; hi += NB) dense_sums<T, WB>(v + hi, K0, K1, s0, s1);
         return;
       }
     }
@@ -585,6 +599,24 @@ __global__ __launch_bounds__(256) void k_upass(
   if constexpr (AK == U_X) {
     if (pd->amix && tid < 16) da[0][tid] = C2<T>{(T)rta->D[mbits][tid][0], (T)rta->D[mbits][tid][1]};
   }
+  // dense Kraus pairs in the register's frame (passes with a dense unit)
+  C2<double>(*kdn)[16][16] = dense_lds<DN>();
+  if constexpr (DN) {
+    if (pd->adense) {
+      const uint32_t fa = gather_loc(phi, pd->aq[0], WA);
+      for (int k = tid; k < 256; k += blockDim.x) {
+        const int r = k >> 4, c = k & 15;
+        kdn[0][r][c] = C2<double>{dna->K[mbits & 1][r ^ fa][c ^ fa][0], dna->K[mbits & 1][r ^ fa][c ^ fa][1]};
+      }
+    }
+    if (pd->bdense) {
+      const uint32_t fb = gather_loc(phi_new, pd->bq[0], WB);
+      for (int k = tid; k < 512; k += blockDim.x) {
+        const int m = k >> 8, r = (k >> 4) & 15, c = k & 15;
+        kdn[1 + m][r][c] = C2<double>{dnb->K[m][r ^ fb][c ^ fb][0], dnb->K[m][r ^ fb][c ^ fb][1]};
+      }
+    }
+  }
   if constexpr (AK == U_Z) {
     for (int k = tid; k < kChainMax * 16; k += blockDim.x) {
       const int i = k >> 4, x = k & 15;
@@ -672,10 +704,9 @@ __global__ __launch_bounds__(256) void k_upass(
       if constexpr (AK == U_X) {
         if (DN && pd->adense) {  // dense Kraus pair (crosstalk inside the check)
           if constexpr (DN) {
-            const uint32_t fa = gather_loc(phi, pd->aq[0], WA);
             constexpr int NA = 1 << WA;
 #pragma unroll
-            for (int hi = 0; hi < 16; hi += NA) dense_apply<T, WA>(v + hi, dna, mbits & 1, fa);
+            for (int hi = 0; hi < 16; hi += NA) dense_apply<T, WA>(v + hi, kdn[0]);
           }
         } else if (pd->amix) {
           uint32_t xl = 0;  // A's local index bits carried by this thread's lanes
@@ -773,14 +804,21 @@ __global__ __launch_bounds__(256) void k_upass(
   }
   if constexpr (BK == U_X) {
     const bool bd = DN && pd->bdense;
-    const uint32_t fb = bd ? gather_loc(phi_new, pd->bq[0], WB) : 0u;
+    const C2<double>(*K0p)[16] = nullptr;
+    const C2<double>(*K1p)[16] = nullptr;
+    if constexpr (DN) {
+      if (bd) {
+        K0p = kdn[1];
+        K1p = kdn[2];
+      }
+    }
     if (pd->bmode == 2) {
-      xpose_xsums<T, WB, DN>(o, lt, pd, wt[0][0], wt[0][1], active, acc[0], acc[1], bd ? dnb : nullptr, fb);
+      xpose_xsums<T, WB, DN>(o, lt, pd, wt[0][0], wt[0][1], active, acc[0], acc[1], K0p, K1p);
     } else if (active && bd) {
       if constexpr (DN) {
         constexpr int NB = 1 << WB;
 #pragma unroll
-        for (int hi = 0; hi < 16; hi += NB) dense_sums<T, WB>(o + hi, dnb, fb, acc[0], acc[1]);
+        for (int hi = 0; hi < 16; hi += NB) dense_sums<T, WB>(o + hi, kdn[1], kdn[2], acc[0], acc[1]);
       }
     } else if (active) {
       constexpr int NB = 1 << WB;
