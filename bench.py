@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# dense matrix-core peaks of MI355X: FP64 (complex128) and FP32 (complex64)
+PEAK_MFMA_TFS = {"c128": 78.6, "c64": 157.3}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_upass_d5_c128_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2204_11404_amd", "csrc", f)
                   for f in ("kernels.hip", "qec_common.h")]
@@ -102,6 +104,40 @@ def copy_calibration(qs, torch, steps):
     ms = e0.elapsed_time(e1) / steps
     print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30,
                       "copy_ms": ms, "copy_gbs": 2 * (1 << 30) / (ms * 1e-3) / 1e9}), flush=True)
+
+
+def fused_run(qs, torch, reps=10):
+    """Dense k-qubit matrices on the 26-qubit register through sv_apply_fused
+    (k = 4, 5 run on the matrix cores).  Per call: one read and one write of
+    the register, 8 * 4^k flops per group of 2^k amplitudes; time per call
+    from HIP events on the state's stream (each call also uploads its
+    matrix, 16 KB at most)."""
+    import workloads
+    out = []
+    stream = torch.cuda.current_stream()
+    for dt in ("c128", "c64"):
+        s = qs.State(26, dt, stream=stream)
+        s.set_basis(0)
+        for k, qubits in ((5, [20, 21, 22, 23, 24]), (5, [0, 1, 2, 3, 4]), (4, [20, 21, 22, 23])):
+            m = workloads.random_matrix(k, 11)
+            s.apply_fused(qubits, m)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                s.apply_fused(qubits, m)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            nbytes = 2 * s.nbytes
+            flops = 8 * 4 ** k * (1 << (26 - k))
+            peak_tf = PEAK_MFMA_TFS[dt]
+            out.append({"dtype": dt, "k": k, "qubits": qubits, "ms_per_call": ms,
+                        "gbs": nbytes / (ms * 1e-3) / 1e9, "tflops": flops / (ms * 1e-3) / 1e12,
+                        "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                        "mfma_frac": flops / (ms * 1e-3) / 1e12 / peak_tf})
+        s.free()
+    return out
 
 
 def serving_run(qs, kind, window_s, horizon_s, budget_gib=256):
@@ -225,7 +261,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="time only the library's plain register copy (HBM calibration)")
-    ap.add_argument("--only", choices=["batch", "serving", "precision"], default=None,
+    ap.add_argument("--only", choices=["batch", "serving", "precision", "fused"], default=None,
                     help="run one side measurement alone and print it (for profiling)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-launch, serving and precision measurements")
@@ -255,6 +291,9 @@ def main():
     if args.only == "batch":
         print(json.dumps({"d3": d3_textbook_run(qs),
                           "batched": [batch_run(qs, 3, 65536, "c64"), batch_run(qs, 4, 4096, "c64")]}))
+        return
+    if args.only == "fused":
+        print(json.dumps({"fused": fused_run(qs, torch)}))
         return
     if args.only == "serving":
         print(json.dumps({"serving": [serving_run(qs, "companion", 5.0, 8.0)]}))

@@ -147,6 +147,110 @@ __global__ __launch_bounds__(256) void k_fused(T* __restrict__ st, uint64_t n_gr
   }
 }
 
+// Dense K-qubit matrix (K = 4 or 5) on the matrix cores: for every group of
+// 2^K amplitudes (the groups are the columns of V), Y = M V as 16x16x4 MFMA
+// tiles, FP64 for complex128 and FP32 for complex64.  The real and imaginary
+// parts are separate products: Yr = Mr Vr - Mi Vi, Yi = Mr Vi + Mi Vr.
+//
+// One wave owns 16 groups at a time (the 16 columns of a B/D tile).  Operand
+// layout of the 16x16x4 instructions: A[i][k] in lane (i + 16 k), B[k][j] in
+// lane (j + 16 k); the result D[i][j] sits in lane (j + 16 (i % 4)), register
+// i / 4 for FP64 and in lane (j + 16 (i / 4)), register i % 4 for FP32 (both
+// checked on gfx950).  So lane (c, q) = (lane % 16, lane / 16) loads element
+// 4 s + q of group c for K step s, and for FP32 the rows of M are permuted
+// (row 16 t + 4 q + r holds element 16 t + 4 r + q), so that for either type
+// register r of row tile t holds element 16 t + 4 r + q: a store writes the
+// same bit pattern a load reads.  The matrix stays in registers for the
+// whole (persistent) launch.
+template <typename T> struct Mfma16;
+template <> struct Mfma16<double> {
+  static constexpr bool kPermuteRows = false;
+  typedef double V4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V4 op(double a, double b, V4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma16<float> {
+  static constexpr bool kPermuteRows = true;
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V4 op(float a, float b, V4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_fused_mfma(T* __restrict__ st, uint64_t n_tiles,
+                                                    const double* __restrict__ mat, int q0, int q1,
+                                                    int q2, int q3, int q4) {
+  static_assert(K == 4 || K == 5, "MFMA tiles need 16 or 32 rows");
+  constexpr int N = 1 << K, RT = N / 16, KS = N / 4;
+  using V4 = typename Mfma16<T>::V4;
+  const int lane = threadIdx.x & 63, c = lane & 15, q = lane >> 4;
+  const int qs[5] = {q0, q1, q2, q3, q4};
+  int sorted[5];
+#pragma unroll
+  for (int j = 0; j < K; ++j) sorted[j] = qs[j];
+#pragma unroll
+  for (int a = 1; a < K; ++a)
+#pragma unroll
+    for (int b = a; b > 0; --b)
+      if (sorted[b - 1] > sorted[b]) {
+        const int t = sorted[b]; sorted[b] = sorted[b - 1]; sorted[b - 1] = t;
+      }
+  // register offset of local element bits 0,1 (this lane's q) and of bits
+  // 2.. (K step s, or 4 t + r on the store side)
+  const uint64_t xq = ((q & 1) ? 1ull << q0 : 0) | ((q & 2) ? 1ull << q1 : 0);
+  uint64_t xh[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    uint64_t o = 0;
+#pragma unroll
+    for (int j = 2; j < K; ++j)
+      if ((s >> (j - 2)) & 1) o |= 1ull << qs[j];
+    xh[s] = o;
+  }
+  T ar[RT][KS], ai[RT][KS];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int row = 16 * t + (Mfma16<T>::kPermuteRows ? 4 * (c & 3) + (c >> 2) : c);
+      const int col = 4 * s + q;
+      ar[t][s] = (T)mat[2 * (N * row + col)];
+      ai[t][s] = (T)mat[2 * (N * row + col) + 1];
+    }
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint64_t n_waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t tl = wave; tl < n_tiles; tl += n_waves) {
+    uint64_t base = tl * 16 + c;
+#pragma unroll
+    for (int j = 0; j < K; ++j) base = insert_zero(base, sorted[j]);
+    base |= xq;
+    C2<T> v[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) v[s] = ld2(st, base | xh[s]);
+    V4 yr[RT], yi[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      yr[t] = V4{0, 0, 0, 0};
+      yi[t] = V4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        yr[t] = Mfma16<T>::op(ar[t][s], v[s].re, yr[t]);
+        yi[t] = Mfma16<T>::op(ar[t][s], v[s].im, yi[t]);
+        yi[t] = Mfma16<T>::op(ai[t][s], v[s].re, yi[t]);
+        yr[t] = Mfma16<T>::op(ai[t][s], -v[s].im, yr[t]);
+      }
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) st2(st, base | xh[4 * t + r], C2<T>{yr[t][r], yi[t][r]});
+  }
+}
+
 // Walsh-Hadamard transform over K qubits (bits q[0..K)) of the register, one
 // group of 2^K amplitudes per thread, times `scale` (the X-basis readout
 // applies H to every data qubit as ceil(n / 5) such passes).

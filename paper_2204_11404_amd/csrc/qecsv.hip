@@ -1495,9 +1495,18 @@ struct sv_state_s {
   bool owned = false;
   double2* partials = nullptr;
   MeasOut* mo = nullptr;
+  // Matrix uploads of sv_apply_fused: a ring of pinned host slots and device
+  // slots; a slot is reused once the event recorded after its kernel fired.
+  double* mat_host = nullptr;
+  double* mat_dev = nullptr;
+  hipEvent_t mat_ev[8] = {};
+  bool mat_used[8] = {};
+  int mat_next = 0;
 };
 
 static constexpr int kMeasGrid = 1024;
+static constexpr int kMatSlots = 8;
+static constexpr size_t kMatDoubles = 2 * 32 * 32;
 
 extern "C" {
 
@@ -1560,6 +1569,11 @@ sv_status sv_free(sv_state s) {
   (void)hipStreamSynchronize(s->stream);
   if (s->owned) (void)hipFree(s->ptr);
   (void)hipFree(s->partials);
+  if (s->mat_dev) {
+    for (int i = 0; i < kMatSlots; ++i) (void)hipEventDestroy(s->mat_ev[i]);
+    (void)hipHostFree(s->mat_host);
+    (void)hipFree(s->mat_dev);
+  }
   delete s;
   return SV_OK;
 }
@@ -1704,17 +1718,70 @@ sv_status sv_apply_diag(sv_state s, int k, const int* qubits, const double* phas
   return SV_OK;
 }
 
+}  // extern "C"
+
+// Persistent grid for the MFMA fused kernel: every resident workgroup, at
+// most one wave per 16-group tile.
+template <typename T, int K>
+static unsigned fused_mfma_grid(uint64_t n_tiles) {
+  static const int per_cu = [] {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fused_mfma<T, K>, 256, 0) != hipSuccess || b < 1)
+      b = 1;
+    return b;
+  }();
+  const uint64_t want = (n_tiles + 3) / 4, cap = (uint64_t)device_cu_count() * per_cu;
+  return (unsigned)std::min(want, cap);
+}
+
+extern "C" {
+
+static sv_status fused_slots(sv_state s) {
+  if (s->mat_dev) return SV_OK;
+  const size_t bytes = sizeof(double) * kMatDoubles * kMatSlots;
+  if (hipHostMalloc((void**)&s->mat_host, bytes, hipHostMallocDefault) != hipSuccess) {
+    s->mat_host = nullptr;
+    return fail(SV_ENOMEM, "pinned matrix slots (%zu bytes) failed", bytes);
+  }
+  if (hipMalloc((void**)&s->mat_dev, bytes) != hipSuccess) {
+    (void)hipHostFree(s->mat_host);
+    s->mat_host = nullptr;
+    s->mat_dev = nullptr;
+    return fail(SV_ENOMEM, "device matrix slots (%zu bytes) failed", bytes);
+  }
+  for (int i = 0; i < kMatSlots; ++i) {
+    if (hipEventCreateWithFlags(&s->mat_ev[i], hipEventDisableTiming) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(s->mat_ev[j]);
+      (void)hipHostFree(s->mat_host);
+      (void)hipFree(s->mat_dev);
+      s->mat_host = nullptr;
+      s->mat_dev = nullptr;
+      return fail(SV_EDEVICE, "event creation failed");
+    }
+    s->mat_used[i] = false;
+  }
+  return SV_OK;
+}
+
 sv_status sv_apply_fused(sv_state s, int k, const int* qubits, const double* m) {
   sv_status st = check_qubits(s, k, qubits, 5);
   if (st != SV_OK) return st;
   if (!m) return fail(SV_EINVAL, "NULL matrix");
-  const size_t mb = sizeof(double) * 2 * (1u << (2 * k));
-  double* dm = nullptr;
-  HIP_OK(hipMalloc(&dm, mb));
-  hipError_t e = hipMemcpyAsync(dm, m, mb, hipMemcpyHostToDevice, s->stream);
+  st = fused_slots(s);
+  if (st != SV_OK) return st;
+  const size_t nd = 2u << (2 * k), mb = sizeof(double) * nd;
+  const int slot = s->mat_next;
+  // the slot's previous copy and kernel must be done before it is rewritten
+  if (s->mat_used[slot]) HIP_OK(hipEventSynchronize(s->mat_ev[slot]));
+  double* hm = s->mat_host + kMatDoubles * slot;
+  double* dm = s->mat_dev + kMatDoubles * slot;
+  std::memcpy(hm, m, mb);
+  HIP_OK(hipMemcpyAsync(dm, hm, mb, hipMemcpyHostToDevice, s->stream));
   int q[5] = {0, 0, 0, 0, 0};
   for (int i = 0; i < k; ++i) q[i] = qubits[i];
   const uint64_t ng = 1ull << (s->n - k);
+  // 16x16 MFMA tiles need 16 rows (k >= 4) and 16 groups per tile
+  const bool mfma = k >= 4 && s->n - k >= 4;
   const dim3 g(grid_for(ng, 256)), b(256);
 #define QEC_FUSED(K)                                                                             \
   case K:                                                                                       \
@@ -1725,17 +1792,28 @@ sv_status sv_apply_fused(sv_state s, int k, const int* qubits, const double* m) 
       hipLaunchKernelGGL((k_fused<float, K>), g, b, 0, s->stream, (float*)s->ptr, ng, dm, q[0],   \
                          q[1], q[2], q[3], q[4]);                                               \
     break;
-  if (e == hipSuccess) {
-    switch (k) {
-      QEC_FUSED(1) QEC_FUSED(2) QEC_FUSED(3) QEC_FUSED(4) QEC_FUSED(5)
-    }
-    e = hipGetLastError();
+#define QEC_FUSED_MFMA(K)                                                                        \
+  case K:                                                                                       \
+    if (s->dt == SV_C128)                                                                       \
+      hipLaunchKernelGGL((k_fused_mfma<double, K>), dim3(fused_mfma_grid<double, K>(ng / 16)),   \
+                         b, 0, s->stream, (double*)s->ptr, ng / 16, dm, q[0], q[1], q[2], q[3],   \
+                         q[4]);                                                                 \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_fused_mfma<float, K>), dim3(fused_mfma_grid<float, K>(ng / 16)), b,  \
+                         0, s->stream, (float*)s->ptr, ng / 16, dm, q[0], q[1], q[2], q[3], q[4]); \
+    break;
+  if (mfma) {
+    switch (k) { QEC_FUSED_MFMA(4) QEC_FUSED_MFMA(5) }
+  } else {
+    switch (k) { QEC_FUSED(1) QEC_FUSED(2) QEC_FUSED(3) QEC_FUSED(4) QEC_FUSED(5) }
   }
 #undef QEC_FUSED
-  // the matrix buffer must outlive the kernel
-  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  (void)hipFree(dm);
+#undef QEC_FUSED_MFMA
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(s->mat_ev[slot], s->stream);
   if (e != hipSuccess) return fail(SV_EDEVICE, "apply_fused: %s", hipGetErrorString(e));
+  s->mat_used[slot] = true;
+  s->mat_next = (slot + 1) % kMatSlots;
   return SV_OK;
 }
 

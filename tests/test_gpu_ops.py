@@ -73,6 +73,49 @@ def test_apply_fused(dtype, k):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("k,n,qubits", [
+    (5, 9, [4, 0, 8, 2, 6]),          # one 16-group MFMA tile
+    (4, 8, [7, 1, 0, 5]),
+    (5, 8, [0, 1, 2, 3, 4]),          # fewer than 16 groups: scalar kernel
+    (5, 22, [0, 1, 2, 3, 4]),         # contiguous low block, many tiles per wave
+    (5, 22, [21, 17, 20, 18, 19]),    # high block, unsorted
+    (4, 22, [3, 12, 0, 21]),
+])
+def test_apply_fused_tiles(dtype, k, n, qubits):
+    """The matrix-core path (k = 4, 5 with at least 16 groups) at the tile
+    edge, with low, high and scattered target qubits, and the scalar kernel
+    below one tile; three calls in a row reuse the matrix slots."""
+    print(f"case fused tiles k={k} n={n} {dtype} qubits={qubits}", flush=True)
+    s, ref = _state(n, dtype, 500 + n + k)
+    want = ref
+    for rep in range(3):
+        m = workloads.random_matrix(k, 700 + 10 * n + rep)
+        s.apply_fused(qubits, m)
+        want = sv.apply_gate(want, qubits, m)
+    assert np.max(np.abs(s.get() - want)) < 3 * TOL[dtype] * (1 << k)
+    s.free()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_apply_fused_many_calls(dtype):
+    """More calls than matrix slots without a synchronisation in between:
+    each call's matrix must be the one its kernel reads."""
+    n, k = 12, 5
+    print(f"case fused ring {dtype}", flush=True)
+    s, ref = _state(n, dtype, 77)
+    want = ref
+    rng = np.random.default_rng(5)
+    for rep in range(20):
+        qubits = [int(x) for x in rng.choice(n, size=k, replace=False)]
+        m = workloads.random_matrix(k, 1000 + rep)
+        s.apply_fused(qubits, m)
+        m[:] = 0.0       # the caller may reuse its buffer once the call returns
+        want = sv.apply_gate(want, qubits, workloads.random_matrix(k, 1000 + rep))
+    assert np.max(np.abs(s.get() - want)) < 20 * TOL[dtype] * (1 << k)
+    s.free()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_measure_reset(dtype):
     n = 16
     for anc in (0, 7, n - 1):
