@@ -362,6 +362,7 @@ def main():
         out["serving"] = [serving_run(qs, "companion", 5.0, 8.0), serving_run(qs, "spec", 2.0, 4.0)]
         out["p99_latency_ms"] = out["serving"][0]["p99_ms"]
         out["precision"] = precision_run(qs, args.precision_traj)
+        out["fused"] = fused_run(qs, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, eps, args.cpu_blocks)
     print(json.dumps(out), flush=True)

@@ -168,8 +168,14 @@ sv_status sv_apply_gate(sv_state s, int k, const int* qubits, const double* m);
 sv_status sv_apply_diag(sv_state s, int k, const int* qubits, const double* phases);
 
 /* Dense fused k-qubit matrix, 1 <= k <= 5 (up to 32 x 32 complex) applied to
- * all 2^(n-k) vectors; same layout as sv_apply_gate.  Used for runs of gates
- * multiplied on the host into one matrix. */
+ * all 2^(n-k) vectors (the gate action of Sec. II.B written as one matrix);
+ * same layout as sv_apply_gate.  Used for runs of gates multiplied on the host
+ * into one matrix.  k = 4, 5 run on the matrix cores when n - k >= 4.  m is a
+ * host pointer, copied before return (the caller may reuse it at once); the
+ * call is stream-ordered and returns without waiting for the kernel, except
+ * when eight earlier calls on this state are still in flight.  Errors:
+ * SV_EINVAL (qubits, k, NULL m), SV_ENOMEM (the 128 KiB of matrix slots, on
+ * the first call), SV_EDEVICE (launch or copy failure). */
 sv_status sv_apply_fused(sv_state s, int k, const int* qubits, const double* m);
 
 /* ------------------------------------------------------------- measurement */

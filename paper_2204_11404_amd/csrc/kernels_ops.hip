@@ -178,7 +178,7 @@ template <> struct Mfma16<float> {
   }
 };
 
-template <typename T, int K>
+template <typename T, int K, bool PF>
 __global__ __launch_bounds__(256) void k_fused_mfma(T* __restrict__ st, uint64_t n_tiles,
                                                     const double* __restrict__ mat, int q0, int q1,
                                                     int q2, int q3, int q4) {
@@ -221,14 +221,33 @@ __global__ __launch_bounds__(256) void k_fused_mfma(T* __restrict__ st, uint64_t
     }
   const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint64_t n_waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-  for (uint64_t tl = wave; tl < n_tiles; tl += n_waves) {
-    uint64_t base = tl * 16 + c;
+  auto tile_base = [&](uint64_t tl) {
+    uint64_t b = tl * 16 + c;
 #pragma unroll
-    for (int j = 0; j < K; ++j) base = insert_zero(base, sorted[j]);
-    base |= xq;
-    C2<T> v[KS];
+    for (int j = 0; j < K; ++j) b = insert_zero(b, sorted[j]);
+    return b | xq;
+  };
+  // PF: the next tile's loads are issued before this tile's products
+  C2<T> v[KS];
+  uint64_t tl = wave, base = 0;
+  if (PF && tl < n_tiles) {
+    base = tile_base(tl);
 #pragma unroll
     for (int s = 0; s < KS; ++s) v[s] = ld2(st, base | xh[s]);
+  }
+  for (; tl < n_tiles; tl += n_waves) {
+    if (!PF) {
+      base = tile_base(tl);
+#pragma unroll
+      for (int s = 0; s < KS; ++s) v[s] = ld2(st, base | xh[s]);
+    }
+    C2<T> vn[PF ? KS : 1];
+    uint64_t base_n = 0;
+    if (PF && tl + n_waves < n_tiles) {
+      base_n = tile_base(tl + n_waves);
+#pragma unroll
+      for (int s = 0; s < (PF ? KS : 1); ++s) vn[s] = ld2(st, base_n | xh[s]);
+    }
     V4 yr[RT], yi[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
@@ -248,6 +267,11 @@ __global__ __launch_bounds__(256) void k_fused_mfma(T* __restrict__ st, uint64_t
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) st2(st, base | xh[4 * t + r], C2<T>{yr[t][r], yi[t][r]});
+    if (PF) {
+#pragma unroll
+      for (int s = 0; s < (PF ? KS : 1); ++s) v[s] = vn[s];
+      base = base_n;
+    }
   }
 }
 

@@ -1720,13 +1720,23 @@ sv_status sv_apply_diag(sv_state s, int k, const int* qubits, const double* phas
 
 }  // extern "C"
 
+// Whether the MFMA fused kernel prefetches the next tile (more loads in
+// flight per wave, more registers).  Measured on the 26-qubit register: it
+// pays only for complex64 with k = 5 (254 -> 245 us); for complex128, k = 5 it
+// costs a wave per SIMD of occupancy (441 -> 457 us).
+template <typename T, int K> struct FusedPF {
+  static constexpr bool value = sizeof(T) == 4 && K == 5;
+};
+
 // Persistent grid for the MFMA fused kernel: every resident workgroup, at
 // most one wave per 16-group tile.
 template <typename T, int K>
 static unsigned fused_mfma_grid(uint64_t n_tiles) {
   static const int per_cu = [] {
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fused_mfma<T, K>, 256, 0) != hipSuccess || b < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fused_mfma<T, K, FusedPF<T, K>::value>, 256, 0) !=
+            hipSuccess ||
+        b < 1)
       b = 1;
     return b;
   }();
@@ -1795,11 +1805,11 @@ sv_status sv_apply_fused(sv_state s, int k, const int* qubits, const double* m) 
 #define QEC_FUSED_MFMA(K)                                                                        \
   case K:                                                                                       \
     if (s->dt == SV_C128)                                                                       \
-      hipLaunchKernelGGL((k_fused_mfma<double, K>), dim3(fused_mfma_grid<double, K>(ng / 16)),   \
+      hipLaunchKernelGGL((k_fused_mfma<double, K, FusedPF<double, K>::value>), dim3(fused_mfma_grid<double, K>(ng / 16)),   \
                          b, 0, s->stream, (double*)s->ptr, ng / 16, dm, q[0], q[1], q[2], q[3],   \
                          q[4]);                                                                 \
     else                                                                                        \
-      hipLaunchKernelGGL((k_fused_mfma<float, K>), dim3(fused_mfma_grid<float, K>(ng / 16)), b,  \
+      hipLaunchKernelGGL((k_fused_mfma<float, K, FusedPF<float, K>::value>), dim3(fused_mfma_grid<float, K>(ng / 16)), b,  \
                          0, s->stream, (float*)s->ptr, ng / 16, dm, q[0], q[1], q[2], q[3], q[4]); \
     break;
   if (mfma) {
