@@ -32,6 +32,9 @@
 
 namespace qec {
 
+static_assert(sizeof(TOp) == 12 && offsetof(TBlock, ops) % 4 == 0,
+              "an op is read as three 32-bit words");
+
 constexpr int kSmallBits = 9;
 constexpr int kSmallAmps = 1 << kSmallBits;
 constexpr int kSmallStab = 8;     // d <= 3
@@ -122,6 +125,32 @@ template <typename T>
 __device__ __forceinline__ C2<T> from_pair_lane(C2<T> v) {
   return C2<T>{lane_xor1(v.re), lane_xor1(v.im)};
 }
+
+// Op source of track_ops for a block whose op i, Pauli code and angle sit in
+// lane i: the walk reads them with readlane (op index uniform over the wave).
+struct LaneOps {
+  uint32_t w0, w1, w2;  // the TOp's three words
+  uint32_t c;           // Pauli code
+  double cos, sin;      // angle of a rotation op
+  __device__ __forceinline__ TOp op_here() const {
+    const uint32_t w[3] = {w0, w1, w2};
+    TOp o;
+    __builtin_memcpy(&o, w, sizeof(TOp));
+    return o;
+  }
+  __device__ __forceinline__ TOp op(int i) const {
+    const uint32_t w[3] = {(uint32_t)__builtin_amdgcn_readlane((int)w0, i),
+                           (uint32_t)__builtin_amdgcn_readlane((int)w1, i),
+                           (uint32_t)__builtin_amdgcn_readlane((int)w2, i)};
+    TOp o;
+    __builtin_memcpy(&o, w, sizeof(TOp));
+    return o;
+  }
+  __device__ __forceinline__ int code(int i) const { return __builtin_amdgcn_readlane((int)c, i); }
+  __device__ __forceinline__ cd angle(int i, const TOp&) const {
+    return cd{lane_value(cos, i), lane_value(sin, i)};
+  }
+};
 
 // Tables of a new trajectory: site angles, thresholds, logical |0>.  sites:
 // the op of every gate site of the round template (index = site).
@@ -263,26 +292,40 @@ __global__ __launch_bounds__(64) void k_batch_small(
         // 1. Kraus pair of this block instance
         const int nx = 1 << b.w;
         if (noisy) {
-          if (lane < nx) {
-            uint8_t pauli[kMaxOpsBatch];
-            for (int i = 0; i < b.n_ops; ++i) {
-              const TOp& op = b.ops[i];
-              uint8_t c = 0;
-              if (op.draw >= 0) {
-                const double u = S.u[off + op.draw];
-                if (op.kind == OP_N1_ANC || op.kind == OP_N1_DATA) {
-                  for (int j = 0; j < 3 && !c; ++j)
-                    if (u < S.t1[j]) c = (uint8_t)(j + 1);
-                } else {
-                  for (int j = 0; j < 15 && !c; ++j)
-                    if (u < S.t2[j]) c = (uint8_t)(j + 1);
-                }
+          // op i of the block, its Pauli code and its angle's (cos, sin) go
+          // to lane i (one load and one table lookup in parallel); the lanes
+          // of the block-basis labels then walk the ops reading them with
+          // readlane
+          const int nops = b.n_ops;
+          LaneOps lo{};
+          if (lane < nops) {
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(&b.ops[lane]);
+            lo.w0 = w[0];
+            lo.w1 = w[1];
+            lo.w2 = w[2];
+            const TOp op = lo.op_here();
+            int c = 0;
+            if (op.draw >= 0) {
+              const double u = S.u[off + op.draw];
+              // first threshold above u (thresholds increase with j)
+              if (op.kind == OP_N1_ANC || op.kind == OP_N1_DATA) {
+                if (u < S.t1[2]) c = 1 + (u >= S.t1[0]) + (u >= S.t1[1]);
+              } else if (u < S.t2[14]) {
+                c = 1;
+#pragma unroll
+                for (int j = 0; j < 14; ++j) c += u >= S.t2[j];
               }
-              pauli[i] = c;
             }
+            lo.c = (uint32_t)c;
+            if (is_rotation(op.kind)) {
+              lo.cos = S.cs[2 * op.site];
+              lo.sin = S.cs[2 * op.site + 1];
+            }
+          }
+          if (lane < nx) {
             cd v0, v1;
             uint32_t cur = 0;
-            if (!track_column(b, CsFromTable{S.cs}, pauli, lane, v0, v1, &cur)) atomicOr(err, 1);
+            if (!track_ops(b.type == 0, nops, lo, lane, v0, v1, &cur)) atomicOr(err, 1);
             const double norm = b.type == 0 ? 1.0 / (double)nx : 1.0;
             S.D[0][lane] = C2<T>{(T)(v0.re * norm), (T)(v0.im * norm)};
             S.D[1][lane] = C2<T>{(T)(v1.re * norm), (T)(v1.im * norm)};

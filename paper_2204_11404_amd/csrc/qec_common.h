@@ -217,37 +217,38 @@ struct CsFromTable {
   QEC_HD cd operator()(const TOp& op) const { return {cs[2 * op.site], cs[2 * op.site + 1]}; }
 };
 
-// Runs the ops of block b on the ancilla 2-vector for the block-basis input
-// label x (ancilla starting in |0>), with pauli[i] the Pauli code drawn for op
-// i (0 = none; for two-qubit locations the pair index 1..15).  Returns the
-// ancilla amplitudes (v0, v1) = (D_0(x), D_1(x)) before normalisation and the
-// output label in *cur; false if an op is not monomial in the block basis.
-// `cs(op)` returns (cos beta, sin beta) of a rotation op's angle beta = base +
-// eps of its site; rotations by +-beta only flip the sine.
-template <class CS>
-QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd& v0, cd& v1,
-                         uint32_t* cur_out) {
-  const bool xb = (b.type == 0);
+// Runs the ops of a block (type xb: X check; n_ops ops) on the ancilla
+// 2-vector for the block-basis input label x (ancilla starting in |0>).  The
+// op source `src` gives op i (src.op(i)), the Pauli code drawn for it
+// (src.code(i): 0 = none; for two-qubit locations the pair index 1..15) and,
+// for a rotation, (cos beta, sin beta) of its angle beta = base + eps of its
+// site (src.angle(i, op)); rotations by +-beta only flip the sine.  Returns
+// the ancilla amplitudes (v0, v1) = (D_0(x), D_1(x)) before normalisation
+// and the output label in *cur; false if an op is not monomial in the block
+// basis.
+template <class SRC>
+QEC_HD bool track_ops(bool xb, int n_ops, const SRC& src, int x, cd& v0, cd& v1, uint32_t* cur_out) {
   v0 = {1.0, 0.0};
   v1 = {0.0, 0.0};
   uint32_t cur = (uint32_t)x;
-  for (int i = 0; i < b.n_ops; ++i) {
-    const TOp& op = b.ops[i];
+  for (int i = 0; i < n_ops; ++i) {
+    const TOp op = src.op(i);
+    const int code = src.code(i);
     switch (op.kind) {
       case OP_ROT_ANC: {
-        const cd c = cs(op);
+        const cd c = src.angle(i, op);
         anc_rot_cs(op.axis, c.re, c.im * (double)op.sgn, v0, v1);
-        if (pauli[i]) anc_pauli(op.axis, v0, v1);  // twirled: the generator
+        if (code) anc_pauli(op.axis, v0, v1);  // twirled: the generator
         break;
       }
       case OP_ROT_DATA: {
         if ((xb && op.axis != 1) || (!xb && op.axis != 3)) return false;
         const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
-        const cd c = cs(op);
+        const cd c = src.angle(i, op);
         const cd ph{c.re, -c.im * e * (double)op.sgn};  // exp(-i beta e sgn)
         v0 = cmul(v0, ph);
         v1 = cmul(v1, ph);
-        if (pauli[i]) {
+        if (code) {
           const cd g = data_pauli(op.axis, xb, op.j, cur);
           v0 = cmul(v0, g);
           v1 = cmul(v1, g);
@@ -257,10 +258,10 @@ QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd
       case OP_CR_AD: {
         if (!xb) return false;
         const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
-        const cd c = cs(op);
+        const cd c = src.angle(i, op);
         v0 = cmul(v0, cd{c.re, -c.im * e});
         v1 = cmul(v1, cd{c.re, c.im * e});
-        if (pauli[i]) {  // Z on the ancilla, X on data j
+        if (code) {  // Z on the ancilla, X on data j
           anc_pauli(3, v0, v1);
           const cd g = data_pauli(1, xb, op.j, cur);
           v0 = cmul(v0, g);
@@ -271,9 +272,9 @@ QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd
       case OP_CR_DA: {
         if (xb) return false;
         const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
-        const cd c = cs(op);
+        const cd c = src.angle(i, op);
         anc_rot_cs(1, c.re, c.im * e, v0, v1);
-        if (pauli[i]) {  // Z on data j, X on the ancilla
+        if (code) {  // Z on data j, X on the ancilla
           const cd g = data_pauli(3, xb, op.j, cur);
           v0 = cmul(v0, g);
           v1 = cmul(v1, g);
@@ -299,16 +300,16 @@ QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd
         break;
       }
       case OP_N1_ANC:
-        anc_pauli(pauli[i], v0, v1);
+        anc_pauli(code, v0, v1);
         break;
       case OP_N1_DATA: {
-        const cd ph = data_pauli(pauli[i], xb, op.j, cur);
+        const cd ph = data_pauli(code, xb, op.j, cur);
         v0 = cmul(v0, ph);
         v1 = cmul(v1, ph);
         break;
       }
       case OP_N2_AD: {
-        const int pj = pauli[i];
+        const int pj = code;
         anc_pauli(pj >> 2, v0, v1);
         const cd ph = data_pauli(pj & 3, xb, op.j, cur);
         v0 = cmul(v0, ph);
@@ -316,7 +317,7 @@ QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd
         break;
       }
       case OP_N2_DA: {
-        const int pj = pauli[i];
+        const int pj = code;
         const cd ph = data_pauli(pj >> 2, xb, op.j, cur);
         v0 = cmul(v0, ph);
         v1 = cmul(v1, ph);
@@ -326,7 +327,7 @@ QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd
       case OP_ZZ_AD: {  // diagonal only in the computational basis of the data
         if (xb) return false;
         const double e = ((cur >> op.j) & 1) ? -1.0 : 1.0;
-        const cd c = cs(op);
+        const cd c = src.angle(i, op);
         v0 = cmul(v0, cd{c.re, -c.im * e});
         v1 = cmul(v1, cd{c.re, c.im * e});
         break;
@@ -337,6 +338,25 @@ QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd
   }
   *cur_out = cur;
   return true;
+}
+
+// Op source of track_ops over an op array, a Pauli-code array and an angle
+// accessor `cs(op)`.
+template <class CS>
+struct OpList {
+  const TOp* ops;
+  const uint8_t* pauli;
+  CS cs;
+  QEC_HD TOp op(int i) const { return ops[i]; }
+  QEC_HD int code(int i) const { return pauli[i]; }
+  QEC_HD cd angle(int, const TOp& o) const { return cs(o); }
+};
+
+// track_ops over the op list of block b with Pauli codes pauli[i].
+template <class CS>
+QEC_HD bool track_column(const TBlock& b, CS cs, const uint8_t* pauli, int x, cd& v0, cd& v1,
+                         uint32_t* cur_out) {
+  return track_ops(b.type == 0, b.n_ops, OpList<CS>{b.ops, pauli, cs}, x, v0, v1, cur_out);
 }
 
 // Builds BlockRT for one block instance from the Pauli codes of its noise
