@@ -1064,7 +1064,14 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
 // template: a lane's 8 registers span three of a weight-4 check's qubits (its
 // fourth is lane bit 0), or a weight-2 check's two qubits and the lowest other
 // bit; the remaining bits index lanes, lowest first.
-std::vector<SmallDesc> make_small_descs(int n, const Template& tp) {
+// Register layout of every block template for a trajectory run by nw waves:
+// 2^rb amplitudes per thread (rb = 3, 2, 1 for nw = 1, 2, 4).  The check's
+// first qubits go to register bits (at most rb, and at most 2 for a weight-2
+// check when rb >= 2), its other qubits to the lowest thread-index bits (lane
+// bits: their Walsh-Hadamard stages are lane exchanges); the remaining
+// register bits fill the free register slots, then the higher thread bits.
+std::vector<SmallDesc> make_small_descs(int n, const Template& tp, int nw) {
+  const int rb = nw == 1 ? 3 : nw == 2 ? 2 : 1;
   std::vector<SmallDesc> out(tp.blocks.size());
   for (size_t i = 0; i < tp.blocks.size(); ++i) {
     const TBlock& b = tp.blocks[i];
@@ -1075,33 +1082,29 @@ std::vector<SmallDesc> make_small_descs(int n, const Template& tp) {
       for (int l = 0; l < b.w; ++l) in = in || (b.qubit[l] == bit);
       if (!in) rest.push_back(bit);
     }
+    const int xreg = std::min(rb, b.w == 4 ? 4 : 2);
     std::vector<int> regs, lanes;
-    if (b.w == 4) {
-      regs = {b.qubit[0], b.qubit[1], b.qubit[2]};
-      lanes.push_back(b.qubit[3]);
-      sd.xlane = 1;
-      sd.xmask = 7;
-    } else {
-      regs = {b.qubit[0], b.qubit[1], rest[0]};
-      rest.erase(rest.begin());
-      sd.xlane = 0;
-      sd.xmask = 3;
-    }
-    for (int bit : rest) lanes.push_back(bit);
-    for (int j = 0; j < 8; ++j) {
+    for (int l = 0; l < xreg; ++l) regs.push_back(b.qubit[l]);
+    for (int l = xreg; l < b.w; ++l) lanes.push_back(b.qubit[l]);
+    size_t r = 0;
+    while ((int)regs.size() < rb) regs.push_back(rest[r++]);
+    for (; r < rest.size(); ++r) lanes.push_back(rest[r]);
+    sd.xreg = xreg;
+    sd.xlanes = b.w - xreg;
+    sd.xmask = (1u << xreg) - 1u;
+    for (int j = 0; j < (1 << rb); ++j) {
       uint32_t g = 0;
-      for (int k = 0; k < 3; ++k)
+      for (int k = 0; k < rb; ++k)
         if ((j >> k) & 1) g |= 1u << regs[k];
       sd.j_off[j] = g;
     }
-    sd.n_lane_bits = n - 3;
-    for (int k = 0; k < n - 3; ++k) sd.lane_bit[k] = 1u << lanes[k];
+    sd.n_lane_bits = n - rb;
+    for (int k = 0; k < n - rb; ++k) sd.lane_bit[k] = 1u << lanes[k];
     for (int l = 0; l < b.w; ++l) sd.q_bit[l] = 1u << b.qubit[l];
     out[i] = sd;
   }
   return out;
 }
-
 
 int env_int(const char* name, int dflt) {
   if (const char* e = std::getenv(name)) return std::atoi(e);
@@ -1170,7 +1173,16 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   for (int i = 0; i < nt; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return in.rounds[a] > in.rounds[b]; });
-  const std::vector<SmallDesc> sd = small ? make_small_descs(n, tp) : std::vector<SmallDesc>(ns);
+  // waves per trajectory: a launch of at most two trajectories per SIMD
+  // splits each one over 2 waves (more waves hide the latency of the
+  // per-circuit chain: 1000 d=3 trajectories 0.090 -> 0.085 ms; 4 waves take
+  // 0.138 ms, the per-circuit reduction and decision then dominate);
+  // QECSV_BATCH_SPLIT forces 1, 2 or 4
+  const int simds = 4 * device_cu_count();
+  int nw = nt <= 2 * simds ? 2 : 1;
+  const int forced = env_int("QECSV_BATCH_SPLIT", 0);
+  if (forced == 1 || forced == 2 || forced == 4) nw = forced;
+  const std::vector<SmallDesc> sd = make_small_descs(n, tp, nw);
   const JobConst jc = make_job_const(d, in.zeta);
   // the op of every gate site (index = site)
   std::vector<TOp> sites(std::max(1, tp.n_sites));
@@ -1247,18 +1259,26 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   HIP_OK(hipEventCreate(&ev.b));
   {
     // a persistent launch: no more workgroups than stay resident at once
-    int per_cu = tuning_for(in.d, sizeof(T) == 8 ? SV_C128 : SV_C64).batch_waves_per_cu;
-    int resident = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, k_batch_small<T>, 64, 0) == hipSuccess &&
-        resident > 0)
-      per_cu = std::min(per_cu, resident);
-    const int max_wg = device_cu_count() * per_cu;
-    const int grid = std::max(1, std::min(nt, max_wg));  // one trajectory per workgroup at a time
-    HIP_OK(hipEventRecord(ev.a, s));
-    hipLaunchKernelGGL(k_batch_small<T>, dim3(grid), dim3(64), 0, s, dblocks, dsd, ns, n, tp.n_draws,
-                       djc, dseed, dstream, dorder, nt, drounds, dp, deps, in.eps_stride, drec,
-                       in.max_rounds, dbits, derr, (const TOp*)dsites, tp.n_sites,
-                       (const SmallShared<T>*)dshared, (const uint32_t*)dinit, (const uint8_t*)dkind);
+    // (the tuned waves per CU, nw waves per workgroup)
+    auto launch = [&](auto kernel, int nwv) -> hipError_t {
+      int per_cu = std::max(1, tuning_for(in.d, sizeof(T) == 8 ? SV_C128 : SV_C64).batch_waves_per_cu / nwv);
+      int resident = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kernel, 64 * nwv, 0) == hipSuccess &&
+          resident > 0)
+        per_cu = std::min(per_cu, resident);
+      const int max_wg = device_cu_count() * per_cu;
+      const int grid = std::max(1, std::min(nt, max_wg));  // one trajectory per workgroup at a time
+      hipError_t e = hipEventRecord(ev.a, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(64 * nwv), 0, s, dblocks, dsd, ns, n, tp.n_draws, djc,
+                         dseed, dstream, dorder, nt, drounds, dp, deps, in.eps_stride, drec,
+                         in.max_rounds, dbits, derr, (const TOp*)dsites, tp.n_sites,
+                         (const SmallShared<T>*)dshared, (const uint32_t*)dinit, (const uint8_t*)dkind);
+      return hipGetLastError();
+    };
+    if (nw == 4) HIP_OK(launch(k_batch_small<T, 4>, 4));
+    else if (nw == 2) HIP_OK(launch(k_batch_small<T, 2>, 2));
+    else HIP_OK(launch(k_batch_small<T, 1>, 1));
   }
   HIP_OK(hipGetLastError());
   HIP_OK(hipEventRecord(ev.b, s));

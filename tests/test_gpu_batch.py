@@ -30,14 +30,26 @@ def _check(d, gateset, dtype, n_traj, seed, p_range, zeta=0.0, traj0=0):
     return g
 
 
+# waves per trajectory of the LDS-resident kernel (1: eight amplitudes per
+# lane, one check qubit on a lane bit; 2 and 4: four and two amplitudes per
+# lane, two and three check qubits on lane bits); the default picks by size
+SPLITS = ["1", "2", "4"]
+
+
+@pytest.mark.parametrize("split", SPLITS)
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("gateset", ["cr", "textbook"])
-def test_batch_d3_parity(gateset, dtype):
+def test_batch_d3_parity(gateset, dtype, split, monkeypatch):
+    monkeypatch.setenv("QECSV_BATCH_SPLIT", split)
+    print(f"waves per trajectory {split}", flush=True)
     _check(3, gateset, dtype, 400, seed=31, p_range=(5e-3, 5e-2), zeta=0.01)
 
 
+@pytest.mark.parametrize("split", SPLITS)
 @pytest.mark.parametrize("gateset", ["cr", "textbook"])
-def test_batch_d2_parity(gateset):
+def test_batch_d2_parity(gateset, split, monkeypatch):
+    monkeypatch.setenv("QECSV_BATCH_SPLIT", split)
+    print(f"waves per trajectory {split}", flush=True)
     _check(2, gateset, "c128", 200, seed=5, p_range=(1e-2, 1e-1), zeta=0.02)
 
 
@@ -83,17 +95,19 @@ def test_batch_d4_chain_of_two(monkeypatch):
     _check(4, "cr", "c128", 8, seed=19, p_range=(1e-2, 4e-2), zeta=0.01)
 
 
+@pytest.mark.parametrize("split", SPLITS)
 @pytest.mark.parametrize("gateset,d,dtype", [("textbook", 3, "c128"), ("cr", 3, "c64"), ("cr", 2, "c128")])
-def test_batch_common_angles_parity(gateset, d, dtype):
+def test_batch_common_angles_parity(gateset, d, dtype, split, monkeypatch):
     """One over-rotation angle for every site and trajectory: the angle table
     and noise-free Kraus pairs are computed once for the launch (and copied
     per trajectory); per-trajectory rounds and p still vary."""
+    monkeypatch.setenv("QECSV_BATCH_SPLIT", split)
     n = 300
     rng = np.random.default_rng(44)
     R = rng.integers(1, 6, n).astype(np.int32)
     p = rng.uniform(5e-3, 4e-2, n)
     eps, zeta, seed = 0.03, 0.01, 44
-    print(f"case batch common angles d={d} {gateset} {dtype}", flush=True)
+    print(f"case batch common angles d={d} {gateset} {dtype} waves per trajectory {split}", flush=True)
     g = qs.run_batch(d, gateset, R, p, seed, eps=eps, zeta=zeta, dtype=dtype, max_rounds=5)
     for i in range(n):
         o = oracle.run_trajectory(d, GS[gateset], int(R[i]), seed, i, p[i], eps=eps, zeta=zeta)
