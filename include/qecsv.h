@@ -295,7 +295,7 @@ sv_status sv_tuning_set(int d, int dtype, const sv_tuning* in);
  * device time) and keep the fastest for (d, dtype) on the current device:
  * d = 5, sv_run_rounds (one trajectory, one round): zchain x snake x
  *   pass_wgs_per_cu;
- * d = 4, sv_run_batch (512 trajectories, 3 rounds): zchain x lockstep_mib;
+ * d = 4, sv_run_batch (4096 trajectories, 3 rounds): zchain x lockstep_mib;
  * d <= 3, sv_run_batch (16384 trajectories, 3 rounds): batch_waves_per_cu.
  * Writes the winner to *best and its device time to *best_ms (either may be
  * NULL).  Synchronous, on the default stream; call it before serving, not
@@ -313,9 +313,12 @@ sv_status sv_tuning_load(const char* path);
  * per-site over-rotation exponents.  Trajectory i uses draw stream traj0 + i
  * and is the same trajectory sv_run_rounds computes for those parameters
  * (same draw enumeration, same records and final bits).  d = 2 or 3 keep the
- * whole data register in LDS (one persistent launch); d = 4 keeps the
- * registers in HBM and runs the trajectories in lockstep through the register
- * passes, the trajectory being a grid dimension.  Synchronous. */
+ * whole data register in LDS (one persistent launch, a workgroup of one or
+ * two waves per trajectory: two when the launch has at most two trajectories
+ * per SIMD; the environment variable QECSV_BATCH_SPLIT = 1, 2 or 4 forces the
+ * count); d = 4 keeps the registers in HBM and runs the trajectories in
+ * lockstep through the register passes, the trajectory being a grid
+ * dimension.  Synchronous. */
 typedef struct sv_batch_job {
   int d;                    /* 2..4 */
   int gateset;              /* sv_gateset */
