@@ -364,26 +364,28 @@ struct XposeLds {
 
 // Dense Kraus pairs in the register's frame: with f the Pauli-X frame on the
 // check's qubits, the physical operator is X^f K X^f, entry K[r ^ f][c ^ f];
-// the pass stages those entries in LDS once per workgroup.
+// the pass stages those entries in LDS once per workgroup, in the register's
+// precision (complex64 registers: products in FP32, each |K v|^2 summed in
+// FP64; every amplitude read broadcasts one entry to the whole wave, so the
+// LDS bytes per entry set the pass time).
 template <typename T, int W>
-__device__ __forceinline__ void dense_sums(const C2<T>* v, const C2<double> (*K0)[16],
-                                           const C2<double> (*K1)[16], double& s0, double& s1) {
+__device__ __forceinline__ void dense_sums(const C2<T>* v, const C2<T> (*K0)[16],
+                                           const C2<T> (*K1)[16], double& s0, double& s1) {
   constexpr int N = 1 << W;
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
-    const C2<double>(*K)[16] = m ? K1 : K0;
+    const C2<T>(*K)[16] = m ? K1 : K0;
     double s = 0.0;
 #pragma unroll 1
     for (int r = 0; r < N; ++r) {  // one row at a time: few live registers
-      double yr = 0.0, yi = 0.0;
+      T yr = 0, yi = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        const C2<double> k = K[r][c];
-        const double vr = (double)v[c].re, vi = (double)v[c].im;
-        yr += k.re * vr - k.im * vi;
-        yi += k.re * vi + k.im * vr;
+        const C2<T> k = K[r][c];
+        yr += k.re * v[c].re - k.im * v[c].im;
+        yi += k.re * v[c].im + k.im * v[c].re;
       }
-      s += yr * yr + yi * yi;
+      s += (double)yr * (double)yr + (double)yi * (double)yi;
     }
     if (m == 0) s0 += s; else s1 += s;
   }
@@ -391,10 +393,10 @@ __device__ __forceinline__ void dense_sums(const C2<T>* v, const C2<double> (*K0
 
 // LDS for the staged dense Kraus pairs (A's decided one, B's two); only the
 // dense instantiation of the pass kernel allocates it.
-template <bool DN>
-__device__ __forceinline__ C2<double> (*dense_lds())[16][16] {
+template <typename T, bool DN>
+__device__ __forceinline__ C2<T> (*dense_lds())[16][16] {
   if constexpr (DN) {
-    __shared__ C2<double> k[3][16][16];
+    __shared__ C2<T> k[3][16][16];
     return k;
   } else {
     return nullptr;
@@ -403,20 +405,19 @@ __device__ __forceinline__ C2<double> (*dense_lds())[16][16] {
 
 // v <- K v for one group of 2^W amplitudes.
 template <typename T, int W>
-__device__ __forceinline__ void dense_apply(C2<T>* v, const C2<double> (*K)[16]) {
+__device__ __forceinline__ void dense_apply(C2<T>* v, const C2<T> (*K)[16]) {
   constexpr int N = 1 << W;
   C2<T> y[N];
 #pragma unroll
   for (int r = 0; r < N; ++r) {
-    double yr = 0.0, yi = 0.0;
+    T yr = 0, yi = 0;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
-      const C2<double> k = K[r][c];
-      const double vr = (double)v[c].re, vi = (double)v[c].im;
-      yr += k.re * vr - k.im * vi;
-      yi += k.re * vi + k.im * vr;
+      const C2<T> k = K[r][c];
+      yr += k.re * v[c].re - k.im * v[c].im;
+      yi += k.re * v[c].im + k.im * v[c].re;
     }
-    y[r] = C2<T>{(T)yr, (T)yi};
+    y[r] = C2<T>{yr, yi};
   }
 #pragma unroll
   for (int r = 0; r < N; ++r) v[r] = y[r];
@@ -428,8 +429,8 @@ __device__ __forceinline__ void dense_apply(C2<T>* v, const C2<double> (*K)[16])
 template <typename T, int WB, bool DN>
 __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const UnitPass* pd,
                                             const double* w0, const double* w1, bool active,
-                                            double& s0, double& s1, const C2<double> (*K0)[16],
-                                            const C2<double> (*K1)[16]) {
+                                            double& s0, double& s1, const C2<T> (*K0)[16],
+                                            const C2<T> (*K1)[16]) {
   __shared__ XposeLds<T> sh;
   if (active) {
 #pragma unroll
@@ -600,20 +601,20 @@ __global__ __launch_bounds__(256) void k_upass(
     if (pd->amix && tid < 16) da[0][tid] = C2<T>{(T)rta->D[mbits][tid][0], (T)rta->D[mbits][tid][1]};
   }
   // dense Kraus pairs in the register's frame (passes with a dense unit)
-  C2<double>(*kdn)[16][16] = dense_lds<DN>();
+  C2<T>(*kdn)[16][16] = dense_lds<T, DN>();
   if constexpr (DN) {
     if (pd->adense) {
       const uint32_t fa = gather_loc(phi, pd->aq[0], WA);
       for (int k = tid; k < 256; k += blockDim.x) {
         const int r = k >> 4, c = k & 15;
-        kdn[0][r][c] = C2<double>{dna->K[mbits & 1][r ^ fa][c ^ fa][0], dna->K[mbits & 1][r ^ fa][c ^ fa][1]};
+        kdn[0][r][c] = C2<T>{(T)dna->K[mbits & 1][r ^ fa][c ^ fa][0], (T)dna->K[mbits & 1][r ^ fa][c ^ fa][1]};
       }
     }
     if (pd->bdense) {
       const uint32_t fb = gather_loc(phi_new, pd->bq[0], WB);
       for (int k = tid; k < 512; k += blockDim.x) {
         const int m = k >> 8, r = (k >> 4) & 15, c = k & 15;
-        kdn[1 + m][r][c] = C2<double>{dnb->K[m][r ^ fb][c ^ fb][0], dnb->K[m][r ^ fb][c ^ fb][1]};
+        kdn[1 + m][r][c] = C2<T>{(T)dnb->K[m][r ^ fb][c ^ fb][0], (T)dnb->K[m][r ^ fb][c ^ fb][1]};
       }
     }
   }
@@ -804,8 +805,8 @@ __global__ __launch_bounds__(256) void k_upass(
   }
   if constexpr (BK == U_X) {
     const bool bd = DN && pd->bdense;
-    const C2<double>(*K0p)[16] = nullptr;
-    const C2<double>(*K1p)[16] = nullptr;
+    const C2<T>(*K0p)[16] = nullptr;
+    const C2<T>(*K1p)[16] = nullptr;
     if constexpr (DN) {
       if (bd) {
         K0p = kdn[1];
