@@ -396,10 +396,12 @@ __global__ __launch_bounds__(64 * NW) void k_batch_small(
             s1 += lsum[1][w];
           }
         }
+        // both renormalisations alongside p1 (the kept one has S_m > 0)
+        const double r0 = rsqrt(s0), r1 = rsqrt(s1);
         const double p1 = clamp_p1(s1 / (s0 + s1));
         const int m = (S.u[off + nnoise] < p1) ? 1 : 0;
         if (tid == 0) rec[((size_t)t * max_rounds + r) * ns + s] = (uint8_t)m;
-        const double scale = 1.0 / sqrt(m ? s1 : s0);
+        const double scale = m ? r1 : r0;
         if (g_on) {
 #pragma unroll
           for (int j = 0; j < NA; ++j) {
