@@ -99,15 +99,28 @@ __device__ __forceinline__ double lane_value(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// v of the last lane of the row before (row_bcast:15, rows in row_mask 0xA)
+// or of lane 31 (row_bcast:31, rows in 0xC); 0 in the other rows.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_bcast(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Sum over the 64 lanes of the wave (every lane gets the same total; called
 // with every lane active): lane pairs, quads, eights and rows of 16 through
-// DPP, then the four row sums in a fixed order.
+// DPP; then rows 1 and 3 add the sums of rows 0 and 2, and row 3 adds that of
+// rows 0 + 1, so lane 63 holds (S3 + S2) + (S1 + S0), a fixed order.
 __device__ __forceinline__ double wave_total(double v) {
   v += dpp_double<0xB1>(v);   // quad_perm 1,0,3,2: lane ^ 1
   v += dpp_double<0x4E>(v);   // quad_perm 2,3,0,1: lane ^ 2
   v += dpp_double<0x141>(v);  // row_half_mirror: the other quad of the eight
   v += dpp_double<0x140>(v);  // row_mirror: the other eight of the row
-  return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+  v += dpp_bcast<0x142, 0xA>(v);
+  v += dpp_bcast<0x143, 0xC>(v);
+  return lane_value(v, 63);
 }
 
 // Any set bit in [off, off + len) of the 128-bit mask h1:h0 (len <= 16).
