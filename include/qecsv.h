@@ -202,8 +202,10 @@ sv_status sv_template_info(int d, int gateset, int* n_stab, int* n_sites, int* n
  * use for (d, gateset) with Z chains of at most zchain checks: every tile
  * layout partitions its bits between lanes and register slots, the regrouping
  * layouts cover the same tile, and each unit's qubits sit where its mode needs
- * them.  No device work.  *n_passes (optional) receives the pass count of one
- * round sequence; SV_EINVAL names the first failing pass. */
+ * them; for d <= 3 also the layouts of sv_run_batch's LDS-resident kernel for
+ * one, two and four waves per trajectory.  No device work.  *n_passes
+ * (optional) receives the pass count of one round sequence; SV_EINVAL names
+ * the first failing pass or block. */
 sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int* n_passes);
 
 typedef struct sv_job {

@@ -1998,6 +1998,38 @@ sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int* n_passes) {
     }
     if (!ok) return fail(SV_EINVAL, "pass %zu: inconsistent layout", k);
   }
+  // layouts of the LDS-resident batched kernel (d <= 3), for 1, 2 and 4
+  // waves per trajectory: register and thread bits partition the register,
+  // the check's first qubits are register bits and the rest the lowest
+  // thread bits (lane bits of one wave)
+  if (n <= kSmallBits) {
+    for (int nw : {1, 2, 4}) {
+      const int rb = nw == 1 ? 3 : nw == 2 ? 2 : 1;
+      const std::vector<SmallDesc> sds = make_small_descs(n, tp, nw);
+      for (size_t i = 0; i < sds.size(); ++i) {
+        const SmallDesc& sd = sds[i];
+        const TBlock& b = tp.blocks[i];
+        uint32_t reg[3] = {0, 0, 0};
+        for (int k = 0; k < rb; ++k) reg[k] = sd.j_off[1u << k];
+        bool ok = sd.n_lane_bits == n - rb && sd.n_lane_bits <= 8 && distinct(reg, rb) &&
+                  distinct(sd.lane_bit, sd.n_lane_bits) &&
+                  (bits_of(reg, rb) & bits_of(sd.lane_bit, sd.n_lane_bits)) == 0 &&
+                  (bits_of(reg, rb) | bits_of(sd.lane_bit, sd.n_lane_bits)) == all &&
+                  sd.xreg + sd.xlanes == b.w && sd.xlanes <= 3 && sd.xmask == (1u << sd.xreg) - 1u;
+        for (int j = 0; j < (1 << rb) && ok; ++j) {
+          uint32_t g = 0;
+          for (int k = 0; k < rb; ++k)
+            if ((j >> k) & 1) g |= reg[k];
+          ok = sd.j_off[j] == g;
+        }
+        for (int l = 0; l < b.w && ok; ++l) {
+          const uint32_t q = 1u << b.qubit[l];
+          ok = sd.q_bit[l] == q && (l < sd.xreg ? reg[l] == q : sd.lane_bit[l - sd.xreg] == q);
+        }
+        if (!ok) return fail(SV_EINVAL, "batched layout of block %zu (%d waves): inconsistent", i, nw);
+      }
+    }
+  }
   if (n_passes) *n_passes = (int)pds.size();
   return SV_OK;
 }
