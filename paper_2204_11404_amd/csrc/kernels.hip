@@ -362,6 +362,131 @@ struct XposeLds {
   T v[2 << kTileMax];
 };
 
+// 16x16x4 matrix-core products (FP64 for complex128 registers, FP32 for
+// complex64).  Operand layout: A[i][k] in lane (i + 16 k), B[k][j] in lane
+// (j + 16 k); the result D[i][j] sits in lane (j + 16 (i % 4)), register i / 4
+// for FP64 and in lane (j + 16 (i / 4)), register i % 4 for FP32 (both
+// checked on gfx950).  kPermuteRows: the FP32 users permute A's rows so that
+// register r of lane row q holds output 4 r + q for either type.
+template <typename T> struct Mfma16;
+template <> struct Mfma16<double> {
+  static constexpr bool kPermuteRows = false;
+  typedef double V4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V4 op(double a, double b, V4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma16<float> {
+  static constexpr bool kPermuteRows = true;
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V4 op(float a, float b, V4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// Lane transpose for the matrix cores.  Lane l = 16 R + c holds the 16
+// amplitudes v[0..15] of its own group; afterwards v[4 s + b] of lane
+// 16 q + c holds element 4 s + q of the group of lane 16 b + c -- the B
+// operand of K step s for the tile of row b's groups.  Two 2x2 exchanges of
+// (row bit, register bit): lanes 32..63 <-> 0..31 for bit 1, odd <-> even
+// 16-lane rows for bit 0.  Applying it twice restores the layout.
+__device__ __forceinline__ void swap_rows32(uint32_t& x, uint32_t& y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+__device__ __forceinline__ void swap_rows16(uint32_t& x, uint32_t& y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+template <typename T, bool B32>
+__device__ __forceinline__ void swap_c2(C2<T>& a, C2<T>& b) {
+  constexpr int W = sizeof(C2<T>) / 4;
+  uint32_t x[W], y[W];
+  __builtin_memcpy(x, &a, sizeof(x));
+  __builtin_memcpy(y, &b, sizeof(y));
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    if constexpr (B32) swap_rows32(x[i], y[i]);
+    else swap_rows16(x[i], y[i]);
+  }
+  __builtin_memcpy(&a, x, sizeof(x));
+  __builtin_memcpy(&b, y, sizeof(y));
+}
+template <typename T>
+__device__ __forceinline__ void xpose_rows(C2<T>* v) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    swap_c2<T, true>(v[4 * s + 0], v[4 * s + 2]);
+    swap_c2<T, true>(v[4 * s + 1], v[4 * s + 3]);
+    swap_c2<T, false>(v[4 * s + 0], v[4 * s + 1]);
+    swap_c2<T, false>(v[4 * s + 2], v[4 * s + 3]);
+  }
+}
+
+// y_b = K x_b for the four 16-group tiles of a transposed wave (xpose_rows):
+// real and imaginary parts as four real products per K step; the result of
+// tile b lands in v[4 r + b], the layout it was read from.  K: 16 x 16 in
+// LDS.  Every lane of the wave must take part.
+template <typename T>
+__device__ __forceinline__ void mfma_tiles(C2<T>* v, const C2<T> (*K)[16], bool store,
+                                           double& ssq) {
+  using V4 = typename Mfma16<T>::V4;
+  const int lane = threadIdx.x & 63, c = lane & 15, q = lane >> 4;
+  const int row = Mfma16<T>::kPermuteRows ? 4 * (c & 3) + (c >> 2) : c;
+  T ar[4], ai[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const C2<T> k = K[row][4 * s + q];
+    ar[s] = k.re;
+    ai[s] = k.im;
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    V4 yr = V4{0, 0, 0, 0}, yi = V4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const C2<T> x = v[4 * s + b];
+      yr = Mfma16<T>::op(ar[s], x.re, yr);
+      yi = Mfma16<T>::op(ar[s], x.im, yi);
+      yi = Mfma16<T>::op(ai[s], x.re, yi);
+      yr = Mfma16<T>::op(ai[s], -x.im, yr);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (store) v[4 * r + b] = C2<T>{yr[r], yi[r]};
+      ssq += (double)yr[r] * (double)yr[r] + (double)yi[r] * (double)yi[r];
+    }
+  }
+}
+
+// Dense Kraus operator on the matrix cores: v <- K v for each lane's 16
+// amplitudes (the whole wave).
+template <typename T>
+__device__ __forceinline__ void mfma_dense_apply(C2<T>* v, const C2<T> (*K)[16]) {
+  double unused = 0.0;
+  xpose_rows(v);
+  mfma_tiles(v, K, true, unused);
+  xpose_rows(v);
+}
+
+// S_0, S_1 contributions of the wave's groups on the matrix cores (this
+// lane's share of the sum over the wave; v is left unchanged).
+template <typename T>
+__device__ __forceinline__ void mfma_dense_sums(const C2<T>* v, const C2<T> (*K0)[16],
+                                                const C2<T> (*K1)[16], double& s0, double& s1) {
+  C2<T> w[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) w[j] = v[j];
+  xpose_rows(w);
+  double a = 0.0, b = 0.0;
+  mfma_tiles(w, K0, false, a);
+  mfma_tiles(w, K1, false, b);
+  s0 += a;
+  s1 += b;
+}
+
 // Dense Kraus pairs in the register's frame: with f the Pauli-X frame on the
 // check's qubits, the physical operator is X^f K X^f, entry K[r ^ f][c ^ f];
 // the pass stages those entries in LDS once per workgroup, in the register's
@@ -447,6 +572,12 @@ __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const
     constexpr int NB = 1 << WB;
     if constexpr (DN) {
       if (K0) {
+        if constexpr (WB == 4) {
+          if (pd->tb >= 10) {  // whole waves of lanes: the matrix cores
+            mfma_dense_sums<T>(v, K0, K1, s0, s1);
+            return;
+          }
+        }
 #pragma unroll
         for (int hi = 0; hi < 16; hi += NB) dense_sums<T, WB>(v + hi, K0, K1, s0, s1);
         return;
@@ -706,8 +837,12 @@ __global__ __launch_bounds__(256) void k_upass(
         if (DN && pd->adense) {  // dense Kraus pair (crosstalk inside the check)
           if constexpr (DN) {
             constexpr int NA = 1 << WA;
+            if (WA == 4 && tb >= 10) {  // whole waves of lanes: the matrix cores
+              mfma_dense_apply<T>(v, kdn[0]);
+            } else {
 #pragma unroll
-            for (int hi = 0; hi < 16; hi += NA) dense_apply<T, WA>(v + hi, kdn[0]);
+              for (int hi = 0; hi < 16; hi += NA) dense_apply<T, WA>(v + hi, kdn[0]);
+            }
           }
         } else if (pd->amix) {
           uint32_t xl = 0;  // A's local index bits carried by this thread's lanes
@@ -818,8 +953,12 @@ __global__ __launch_bounds__(256) void k_upass(
     } else if (active && bd) {
       if constexpr (DN) {
         constexpr int NB = 1 << WB;
+        if (WB == 4 && tb >= 10) {  // whole waves of lanes: the matrix cores
+          mfma_dense_sums<T>(o, kdn[1], kdn[2], acc[0], acc[1]);
+        } else {
 #pragma unroll
-        for (int hi = 0; hi < 16; hi += NB) dense_sums<T, WB>(o + hi, kdn[1], kdn[2], acc[0], acc[1]);
+          for (int hi = 0; hi < 16; hi += NB) dense_sums<T, WB>(o + hi, kdn[1], kdn[2], acc[0], acc[1]);
+        }
       }
     } else if (active) {
       constexpr int NB = 1 << WB;

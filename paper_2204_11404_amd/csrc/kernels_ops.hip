@@ -152,32 +152,13 @@ __global__ __launch_bounds__(256) void k_fused(T* __restrict__ st, uint64_t n_gr
 // tiles, FP64 for complex128 and FP32 for complex64.  The real and imaginary
 // parts are separate products: Yr = Mr Vr - Mi Vi, Yi = Mr Vi + Mi Vr.
 //
-// One wave owns 16 groups at a time (the 16 columns of a B/D tile).  Operand
-// layout of the 16x16x4 instructions: A[i][k] in lane (i + 16 k), B[k][j] in
-// lane (j + 16 k); the result D[i][j] sits in lane (j + 16 (i % 4)), register
-// i / 4 for FP64 and in lane (j + 16 (i / 4)), register i % 4 for FP32 (both
-// checked on gfx950).  So lane (c, q) = (lane % 16, lane / 16) loads element
-// 4 s + q of group c for K step s, and for FP32 the rows of M are permuted
-// (row 16 t + 4 q + r holds element 16 t + 4 r + q), so that for either type
-// register r of row tile t holds element 16 t + 4 r + q: a store writes the
-// same bit pattern a load reads.  The matrix stays in registers for the
-// whole (persistent) launch.
-template <typename T> struct Mfma16;
-template <> struct Mfma16<double> {
-  static constexpr bool kPermuteRows = false;
-  typedef double V4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ V4 op(double a, double b, V4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
-template <> struct Mfma16<float> {
-  static constexpr bool kPermuteRows = true;
-  typedef float V4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ V4 op(float a, float b, V4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-
+// One wave owns 16 groups at a time (the 16 columns of a B/D tile), with the
+// operand layouts of Mfma16: lane (c, q) = (lane % 16, lane / 16) loads
+// element 4 s + q of group c for K step s, and for FP32 the rows of M are
+// permuted (row 16 t + 4 q + r holds element 16 t + 4 r + q), so that for
+// either type register r of row tile t holds element 16 t + 4 r + q: a store
+// writes the same bit pattern a load reads.  The matrix stays in registers
+// for the whole (persistent) launch.
 template <typename T, int K, bool PF>
 __global__ __launch_bounds__(256) void k_fused_mfma(T* __restrict__ st, uint64_t n_tiles,
                                                     const double* __restrict__ mat, int q0, int q1,

@@ -264,7 +264,11 @@ def test_grid_stride_passes_match(monkeypatch):
 @pytest.mark.parametrize("gateset,d,dtype,twirl,idle,xbasis", [
     ("cr", 3, "c128", False, False, False), ("textbook", 3, "c128", False, False, False),
     ("cr", 4, "c128", False, True, False), ("cr", 3, "c64", True, False, False),
-    ("cr", 3, "c128", False, False, True)])
+    ("cr", 3, "c128", False, False, True),
+    # d = 4: whole waves of lanes, so the dense products run on the matrix
+    # cores (FP64 and FP32 operand layouts)
+    ("cr", 4, "c64", False, False, False), ("textbook", 4, "c128", False, False, False),
+    ("cr", 4, "c128", True, False, True)])
 def test_zz_plaquette_parity(gateset, d, dtype, twirl, idle, xbasis):
     """SV_RUN_ZZ_PLAQUETTE: the ancilla-plaquette crosstalk after every step
     makes the X checks' Kraus pairs dense (k_prepare_dense, dense pass
