@@ -140,6 +140,35 @@ def fused_run(qs, torch, reps=10):
     return out
 
 
+def gate_run(qs, torch, reps=10):
+    """One- and two-qubit gates (sv_apply_gate: one strided-pair or
+    quadruple pass over the register) on 26 qubits, on low and high qubits;
+    per call one read and one write of the register, time from HIP events on
+    the state's stream."""
+    import workloads
+    out = []
+    stream = torch.cuda.current_stream()
+    for dt in ("c128", "c64"):
+        s = qs.State(26, dt, stream=stream)
+        s.set_basis(0)
+        for qubits in ([0], [25], [0, 1], [12, 25]):
+            m = workloads.random_matrix(len(qubits), 3)
+            s.apply_gate(qubits, m)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                s.apply_gate(qubits, m)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = 2 * s.nbytes / (ms * 1e-3) / 1e9
+            out.append({"dtype": dt, "qubits": qubits, "ms_per_call": ms, "gbs": gbs,
+                        "hbm_frac": gbs / PEAK_HBM_GBS})
+        s.free()
+    return out
+
+
 def serving_run(qs, kind, window_s, horizon_s, budget_gib=256):
     """Replay a Poisson job stream against the server in real time; at
     `horizon_s` cancel what is left.  Latency = completion - submission on the
@@ -261,7 +290,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="time only the library's plain register copy (HBM calibration)")
-    ap.add_argument("--only", choices=["batch", "serving", "precision", "fused"], default=None,
+    ap.add_argument("--only", choices=["batch", "serving", "precision", "fused", "gates"], default=None,
                     help="run one side measurement alone and print it (for profiling)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-launch, serving and precision measurements")
@@ -294,6 +323,9 @@ def main():
         return
     if args.only == "fused":
         print(json.dumps({"fused": fused_run(qs, torch)}))
+        return
+    if args.only == "gates":
+        print(json.dumps({"gates": gate_run(qs, torch)}))
         return
     if args.only == "serving":
         print(json.dumps({"serving": [serving_run(qs, "companion", 5.0, 8.0)]}))
@@ -363,6 +395,7 @@ def main():
         out["p99_latency_ms"] = out["serving"][0]["p99_ms"]
         out["precision"] = precision_run(qs, args.precision_traj)
         out["fused"] = fused_run(qs, torch)
+        out["gates"] = gate_run(qs, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, eps, args.cpu_blocks)
     print(json.dumps(out), flush=True)

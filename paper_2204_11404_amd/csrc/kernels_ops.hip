@@ -91,6 +91,37 @@ __global__ void k_gate2(T* __restrict__ st, uint64_t n_quads, int q0, int q1, Ma
   }
 }
 
+// Two-qubit gate on qubits 0 and 1: thread i holds amplitude i (every load
+// and store is one contiguous wave-wide access); the other three amplitudes
+// of its quadruple are in the lanes of its DPP quad (quad_perm xor 1, 2, 3).
+// Lane i computes row r(i) of M, read from LDS.  Needs whole 256-thread
+// blocks.  swap: qubits listed as (1, 0).
+template <typename T>
+__device__ __forceinline__ T quad_xor(T v, int d) {  // lane ^ d within the quad
+  return d == 1 ? dpp_mv<0xB1>(v) : d == 2 ? dpp_mv<0x4E>(v) : dpp_mv<0x1B>(v);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_gate2_quad(T* __restrict__ st, int swap, Mat4 M) {
+  __shared__ T sm[32];
+  if (threadIdx.x < 32) sm[threadIdx.x] = (T)M.m[threadIdx.x];
+  __syncthreads();
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const C2<T> a = ld2(st, i);
+  const int x = (int)(i & 3);                               // address bits 0, 1
+  auto local = [&](int y) { return swap ? ((y >> 1) & 1) | ((y & 1) << 1) : y; };
+  const int r = local(x);
+  T re = 0, im = 0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const C2<T> v = d == 0 ? a : C2<T>{quad_xor(a.re, d), quad_xor(a.im, d)};
+    const int c = local(x ^ d);
+    const T mr = sm[2 * (4 * r + c)], mi = sm[2 * (4 * r + c) + 1];
+    re += mr * v.re - mi * v.im;
+    im += mr * v.im + mi * v.re;
+  }
+  st2(st, i, C2<T>{re, im});
+}
+
 template <typename T>
 __global__ void k_diag(T* __restrict__ st, uint64_t n_amp, int k, int q0, int q1, int q2, int q3, int q4, Diag32 D) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -46,6 +46,24 @@ def test_apply_gate_every_position(dtype, n):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_apply_gate_low_pairs(dtype):
+    """Two-qubit gates on low qubits: every ordered pair below 4, on registers
+    of 8 (one block) and 12 qubits; (0, 1) and (1, 0) run with one amplitude
+    per lane and the quadruple exchanged within DPP quads."""
+    for n in (8, 12):
+        for q0 in range(4):
+            for q1 in range(4):
+                if q0 == q1:
+                    continue
+                print(f"case gate low pair n={n} {dtype} qubits={[q0, q1]}", flush=True)
+                s, ref = _state(n, dtype, 300 + 10 * q0 + q1)
+                m = workloads.random_matrix(2, 400 + 10 * q0 + q1)
+                s.apply_gate([q0, q1], m)
+                assert np.max(np.abs(s.get() - sv.apply_gate(ref, [q0, q1], m))) < TOL[dtype]
+                s.free()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("k", [1, 3, 5])
 def test_apply_diag(dtype, k):
     n = 14
