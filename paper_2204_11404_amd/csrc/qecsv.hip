@@ -1851,10 +1851,18 @@ sv_status sv_apply_fused(sv_state s, int k, const int* qubits, const double* m) 
 #undef QEC_FUSED
 #undef QEC_FUSED_MFMA
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipEventRecord(s->mat_ev[slot], s->stream);
-  if (e != hipSuccess) return fail(SV_EDEVICE, "apply_fused: %s", hipGetErrorString(e));
-  s->mat_used[slot] = true;
+  // the copy is queued whatever the launch did: the slot stays busy until
+  // the stream has passed this point
   s->mat_next = (slot + 1) % kMatSlots;
+  const hipError_t er = hipEventRecord(s->mat_ev[slot], s->stream);
+  if (er == hipSuccess) {
+    s->mat_used[slot] = true;
+  } else {
+    s->mat_used[slot] = false;
+    (void)hipStreamSynchronize(s->stream);
+  }
+  if (e == hipSuccess) e = er;
+  if (e != hipSuccess) return fail(SV_EDEVICE, "apply_fused: %s", hipGetErrorString(e));
   return SV_OK;
 }
 
