@@ -357,11 +357,6 @@ __device__ __forceinline__ uint32_t scatter_loc(uint32_t F, const uint32_t* q, i
   return g;
 }
 
-template <typename T>
-struct XposeLds {
-  T v[2 << kTileMax];
-};
-
 // 16x16x4 matrix-core products (FP64 for complex128 registers, FP32 for
 // complex64).  Operand layout: A[i][k] in lane (i + 16 k), B[k][j] in lane
 // (j + 16 k); the result D[i][j] sits in lane (j + 16 (i % 4)), register i / 4
@@ -556,19 +551,31 @@ __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const
                                             const double* w0, const double* w1, bool active,
                                             double& s0, double& s1, const C2<T> (*K0)[16],
                                             const C2<T> (*K1)[16]) {
-  __shared__ XposeLds<T> sh;
+  // real parts, then imaginary parts, through one buffer of a tile's size
+  // (half the LDS of a complex buffer: one more workgroup fits per CU)
+  __shared__ T buf[1 << kTileMax];
+  uint32_t lt = 0;
+  for (int i = 0; i < pd->tb - 4; ++i)
+    if ((threadIdx.x >> i) & 1) lt ^= pd->b_tid_l[i];
+  C2<T> v[16];
   if (active) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) st2(sh.v, lt_a ^ pd->j_l[j], o[j]);
+    for (int j = 0; j < 16; ++j) buf[lt_a ^ pd->j_l[j]] = o[j].re;
   }
   __syncthreads();
   if (active) {
-    uint32_t lt = 0;
-    for (int i = 0; i < pd->tb - 4; ++i)
-      if ((threadIdx.x >> i) & 1) lt ^= pd->b_tid_l[i];
-    C2<T> v[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = ld2(sh.v, lt ^ pd->b_j_l[j]);
+    for (int j = 0; j < 16; ++j) v[j].re = buf[lt ^ pd->b_j_l[j]];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) buf[lt_a ^ pd->j_l[j]] = o[j].im;
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j].im = buf[lt ^ pd->b_j_l[j]];
     constexpr int NB = 1 << WB;
     if constexpr (DN) {
       if (K0) {
@@ -656,8 +663,17 @@ __device__ __forceinline__ void chain_tree(double a2, const uint32_t* x,
 // AP: weight of an X check A, or the length of a Z chain A (BP likewise).
 // DN: the instantiation that also handles dense Kraus pairs (kept apart so
 // that the dense code does not weigh on the other passes' registers).
+// Occupancy of a pass kernel: complex128 passes other than the dense ones and
+// those summing a Z chain of three or four checks fit 168 registers without
+// spilling, i.e. three waves per SIMD (measured on d=5: X-check passes
+// 200 -> 186 us); the others keep the registers they need.
+template <typename T, int BK, int BP, bool DN>
+struct UpassWaves {
+  static constexpr int value = (sizeof(T) == 8 && !DN && !(BK == U_Z && BP >= 3)) ? 3 : 1;
+};
+
 template <typename T, int AK, int AP, int BK, int BP, bool DN>
-__global__ __launch_bounds__(256) void k_upass(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<T, BK, BP, DN>::value))) void k_upass(
     T* __restrict__ st, const UnitPass* __restrict__ pd, const JobConst* __restrict__ jc,
     const BlockRT* __restrict__ rta, const BlockRT* __restrict__ rtb,
     const Decision* __restrict__ dec_a, Decision* __restrict__ dec_b,
