@@ -2182,7 +2182,7 @@ sv_status sv_autotune(int d, int dtype, int gateset, sv_tuning* best, double* be
   if (d == 5) {
     for (int z = 2; z <= kChainMax; ++z)
       for (int sn = 0; sn <= 1; ++sn)
-        for (int wpc : {0, 4, 8, 16}) {
+        for (int wpc : {0, 3, 4, 6, 8, 12, 16}) {  // multiples of 2 and 3 resident workgroups
           sv_tuning c = base;
           c.zchain = z;
           c.snake = sn;

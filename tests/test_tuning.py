@@ -81,7 +81,7 @@ def test_autotune_then_parity(d, dtype, monkeypatch):
     assert qs.tuning_get(d, dtype) == best
     if d == 5:
         assert best["zchain"] in (2, 3, 4) and best["snake"] in (0, 1)
-        assert best["pass_wgs_per_cu"] in (0, 4, 8, 16)
+        assert best["pass_wgs_per_cu"] in (0, 3, 4, 6, 8, 12, 16)
         return
     if d == 4:
         assert best["lockstep_mib"] in (256, 1024, 4096)
