@@ -109,18 +109,27 @@ __device__ __forceinline__ double dpp_bcast(double v) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Sum over the 64 lanes of the wave (every lane gets the same total; called
-// with every lane active): lane pairs, quads, eights and rows of 16 through
-// DPP; then rows 1 and 3 add the sums of rows 0 and 2, and row 3 adds that of
-// rows 0 + 1, so lane 63 holds (S3 + S2) + (S1 + S0), a fixed order.
-__device__ __forceinline__ double wave_total(double v) {
-  v += dpp_double<0xB1>(v);   // quad_perm 1,0,3,2: lane ^ 1
-  v += dpp_double<0x4E>(v);   // quad_perm 2,3,0,1: lane ^ 2
-  v += dpp_double<0x141>(v);  // row_half_mirror: the other quad of the eight
-  v += dpp_double<0x140>(v);  // row_mirror: the other eight of the row
-  v += dpp_bcast<0x142, 0xA>(v);
-  v += dpp_bcast<0x143, 0xC>(v);
-  return lane_value(v, 63);
+// Sums over the 64 lanes of the wave of two values (every lane gets the same
+// totals; called with every lane active): lane pairs, quads, eights and rows
+// of 16 through DPP; then rows 1 and 3 add the sums of rows 0 and 2, and row
+// 3 adds that of rows 0 + 1, so lane 63 holds (S3 + S2) + (S1 + S0), a fixed
+// order.  The two reductions' steps are interleaved (two independent chains
+// between dependent DPP moves).
+__device__ __forceinline__ void wave_total2(double& a, double& b) {
+  a += dpp_double<0xB1>(a);
+  b += dpp_double<0xB1>(b);
+  a += dpp_double<0x4E>(a);
+  b += dpp_double<0x4E>(b);
+  a += dpp_double<0x141>(a);
+  b += dpp_double<0x141>(b);
+  a += dpp_double<0x140>(a);
+  b += dpp_double<0x140>(b);
+  a += dpp_bcast<0x142, 0xA>(a);
+  b += dpp_bcast<0x142, 0xA>(b);
+  a += dpp_bcast<0x143, 0xC>(a);
+  b += dpp_bcast<0x143, 0xC>(b);
+  a = lane_value(a, 63);
+  b = lane_value(b, 63);
 }
 
 // Any set bit in [off, off + len) of the 128-bit mask h1:h0 (len <= 16).
@@ -392,8 +401,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_small(
             s1 += W[1][x] * a2;
           }
         }
-        s0 = wave_total(s0);
-        s1 = wave_total(s1);
+        wave_total2(s0, s1);
         if constexpr (NW > 1) {
           // the waves' totals in wave order (the same sum on every wave)
           if (lane == 0) {
@@ -466,8 +474,8 @@ __global__ __launch_bounds__(64 * NW) void k_batch_small(
         const int half = size >> 1;
         const bool in0 = lane >= lo && lane < lo + half;
         const bool in1 = lane >= lo + half && lane < lo + size;
-        const double S0 = wave_total(in0 ? L : 0.0);
-        const double S1 = wave_total(in1 ? L : 0.0);
+        double S0 = in0 ? L : 0.0, S1 = in1 ? L : 0.0;
+        wave_total2(S0, S1);
         const double pf = clamp_p1(S1 / (S0 + S1));
         const double u = lane_value(uf, level);
         const int bit = (u < pf) ? 1 : 0;
