@@ -14,3 +14,17 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_traffic_summary_matches_sources_and_guards_changes(tmp_path, monkeypatch):
+    """The committed counter summary carries the hash of the pass kernel's
+    sources: bench.py reports its HBM bytes only while they agree."""
+    sys.path.insert(0, ROOT)
+    import bench
+    got = bench.counted_traffic()
+    assert got is not None and abs(got / (1 << 30) - 1.0) < 0.01   # ~1 GiB per pass
+    text = open(bench.TRAFFIC_SUMMARY).read()
+    stale = tmp_path / "summary.md"
+    stale.write_text(text.replace(bench.kernel_source_hash(), "0" * 64))
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(stale))
+    assert bench.counted_traffic() is None
