@@ -287,6 +287,112 @@ __global__ __launch_bounds__(256) void k_fused_mfma(T* __restrict__ st, uint64_t
   }
 }
 
+// The same product when the K target qubits are the register's K lowest bits
+// (in any order): the 16 groups of a wave tile are 16 N consecutive
+// amplitudes, so the wave moves them with 16-byte loads and stores that each
+// cover a contiguous block, and regroups them through its own LDS region
+// (rows of N + 1 amplitudes, so that the 16 groups of an MFMA operand fall
+// on different banks).  q[j]: register bit of local bit j.  The library runs
+// it for complex64 registers, whose 8-byte amplitudes the direct kernel
+// reads in 32-byte pieces on these bits.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_fused_mfma_low(T* __restrict__ st, uint64_t n_tiles,
+                                                        const double* __restrict__ mat, int q0,
+                                                        int q1, int q2, int q3, int q4) {
+  static_assert(K == 4 || K == 5, "MFMA tiles need 16 or 32 rows");
+  constexpr int N = 1 << K, RT = N / 16, KS = N / 4, P = N + 1;
+  constexpr int AMPS = 16 * N;                          // amplitudes of a wave tile
+  constexpr int PER16 = 16 / (2 * sizeof(T));           // amplitudes per 16-byte access
+  constexpr int ACC = AMPS / (64 * PER16);              // 16-byte accesses per lane
+  using V4 = typename Mfma16<T>::V4;
+  __shared__ C2<T> lds[4][16 * P];
+  const int lane = threadIdx.x & 63, c = lane & 15, q = lane >> 4, w = threadIdx.x >> 6;
+  C2<T>* reg = lds[w];
+  const int qs[5] = {q0, q1, q2, q3, q4};
+  auto perm = [&](int x) {
+    int o = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if ((x >> j) & 1) o |= 1 << qs[j];
+    return o;
+  };
+  int xo[KS];  // in-group offset of element 4 s + q (bits 0, 1 from q)
+#pragma unroll
+  for (int s = 0; s < KS; ++s) xo[s] = perm(4 * s + q);
+  T ar[RT][KS], ai[RT][KS];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int row = 16 * t + (Mfma16<T>::kPermuteRows ? 4 * (c & 3) + (c >> 2) : c);
+      const int col = 4 * s + q;
+      ar[t][s] = (T)mat[2 * (N * row + col)];
+      ai[t][s] = (T)mat[2 * (N * row + col) + 1];
+    }
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + w;
+  const uint64_t n_waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t tl = wave; tl < n_tiles; tl += n_waves) {
+    const uint64_t base = tl * AMPS;
+    // contiguous 16-byte loads into the padded rows
+#pragma unroll
+    for (int a = 0; a < ACC; ++a) {
+      const int e = (a * 64 + lane) * PER16;  // first amplitude of this access
+      C2<T> v[PER16];
+      if constexpr (sizeof(T) == 8) {
+        const double2 d = reinterpret_cast<const double2*>(st)[base + e];
+        v[0] = {d.x, d.y};
+      } else {
+        const float4 f = reinterpret_cast<const float4*>(st)[(base + e) >> 1];
+        v[0] = {f.x, f.y};
+        v[PER16 - 1] = {f.z, f.w};
+      }
+#pragma unroll
+      for (int i = 0; i < PER16; ++i) reg[((e + i) >> K) * P + ((e + i) & (N - 1))] = v[i];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's LDS writes are done
+    V4 yr[RT], yi[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      yr[t] = V4{0, 0, 0, 0};
+      yi[t] = V4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const C2<T> x = reg[c * P + xo[s]];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        yr[t] = Mfma16<T>::op(ar[t][s], x.re, yr[t]);
+        yi[t] = Mfma16<T>::op(ar[t][s], x.im, yi[t]);
+        yi[t] = Mfma16<T>::op(ai[t][s], x.re, yi[t]);
+        yr[t] = Mfma16<T>::op(ai[t][s], -x.im, yr[t]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();  // every lane has read its operands
+    // register r of row tile t holds element 16 t + 4 r + q of group c
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) reg[c * P + perm(16 * t + 4 * r + q)] = C2<T>{yr[t][r], yi[t][r]};
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+#pragma unroll
+    for (int a = 0; a < ACC; ++a) {
+      const int e = (a * 64 + lane) * PER16;
+      C2<T> v[PER16];
+#pragma unroll
+      for (int i = 0; i < PER16; ++i) v[i] = reg[((e + i) >> K) * P + ((e + i) & (N - 1))];
+      if constexpr (sizeof(T) == 8) {
+        reinterpret_cast<double2*>(st)[base + e] = make_double2(v[0].re, v[0].im);
+      } else {
+        reinterpret_cast<float4*>(st)[(base + e) >> 1] =
+            make_float4(v[0].re, v[0].im, v[PER16 - 1].re, v[PER16 - 1].im);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();  // the next tile overwrites the rows
+  }
+}
+
 // Walsh-Hadamard transform over K qubits (bits q[0..K)) of the register, one
 // group of 2^K amplitudes per thread, times `scale` (the X-basis readout
 // applies H to every data qubit as ceil(n / 5) such passes).

@@ -1759,16 +1759,18 @@ template <typename T, int K> struct FusedPF {
   static constexpr bool value = sizeof(T) == 4 && K == 5;
 };
 
-// Persistent grid for the MFMA fused kernel: every resident workgroup, at
+// Persistent grid for the MFMA fused kernels: every resident workgroup, at
 // most one wave per 16-group tile.
-template <typename T, int K>
+template <typename T, int K, bool LOW>
 static unsigned fused_mfma_grid(uint64_t n_tiles) {
   static const int per_cu = [] {
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fused_mfma<T, K, FusedPF<T, K>::value>, 256, 0) !=
-            hipSuccess ||
-        b < 1)
-      b = 1;
+    hipError_t e;
+    if constexpr (LOW)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fused_mfma_low<T, K>, 256, 0);
+    else
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fused_mfma<T, K, FusedPF<T, K>::value>, 256, 0);
+    if (e != hipSuccess || b < 1) b = 1;
     return b;
   }();
   const uint64_t want = (n_tiles + 3) / 4, cap = (uint64_t)device_cu_count() * per_cu;
@@ -1823,6 +1825,11 @@ sv_status sv_apply_fused(sv_state s, int k, const int* qubits, const double* m) 
   const uint64_t ng = 1ull << (s->n - k);
   // 16x16 MFMA tiles need 16 rows (k >= 4) and 16 groups per tile
   const bool mfma = k >= 4 && s->n - k >= 4;
+  // complex64, targets = the k lowest bits: contiguous groups, staged through
+  // LDS (26 qubits, k = 5: 298 -> 222 us; complex128 gains nothing there,
+  // 436 -> 472 us, and keeps the direct kernel)
+  bool low = mfma && s->dt == SV_C64;
+  for (int i = 0; i < k; ++i) low = low && q[i] < k;
   const dim3 g(grid_for(ng, 256)), b(256);
 #define QEC_FUSED(K)                                                                             \
   case K:                                                                                       \
@@ -1835,13 +1842,17 @@ sv_status sv_apply_fused(sv_state s, int k, const int* qubits, const double* m) 
     break;
 #define QEC_FUSED_MFMA(K)                                                                        \
   case K:                                                                                       \
-    if (s->dt == SV_C128)                                                                       \
-      hipLaunchKernelGGL((k_fused_mfma<double, K, FusedPF<double, K>::value>), dim3(fused_mfma_grid<double, K>(ng / 16)),   \
-                         b, 0, s->stream, (double*)s->ptr, ng / 16, dm, q[0], q[1], q[2], q[3],   \
-                         q[4]);                                                                 \
+    if (low)                                                                                    \
+      hipLaunchKernelGGL((k_fused_mfma_low<float, K>), dim3(fused_mfma_grid<float, K, true>(ng / 16)), \
+                         b, 0, s->stream, (float*)s->ptr, ng / 16, dm, q[0], q[1], q[2], q[3], q[4]); \
+    else if (s->dt == SV_C128)                                                                  \
+      hipLaunchKernelGGL((k_fused_mfma<double, K, FusedPF<double, K>::value>),                  \
+                         dim3(fused_mfma_grid<double, K, false>(ng / 16)), b, 0, s->stream,       \
+                         (double*)s->ptr, ng / 16, dm, q[0], q[1], q[2], q[3], q[4]);            \
     else                                                                                        \
-      hipLaunchKernelGGL((k_fused_mfma<float, K, FusedPF<float, K>::value>), dim3(fused_mfma_grid<float, K>(ng / 16)), b,  \
-                         0, s->stream, (float*)s->ptr, ng / 16, dm, q[0], q[1], q[2], q[3], q[4]); \
+      hipLaunchKernelGGL((k_fused_mfma<float, K, FusedPF<float, K>::value>),                    \
+                         dim3(fused_mfma_grid<float, K, false>(ng / 16)), b, 0, s->stream,        \
+                         (float*)s->ptr, ng / 16, dm, q[0], q[1], q[2], q[3], q[4]);             \
     break;
   if (mfma) {
     switch (k) { QEC_FUSED_MFMA(4) QEC_FUSED_MFMA(5) }

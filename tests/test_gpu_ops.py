@@ -98,6 +98,12 @@ def test_apply_fused(dtype, k):
     (5, 22, [0, 1, 2, 3, 4]),         # contiguous low block, many tiles per wave
     (5, 22, [21, 17, 20, 18, 19]),    # high block, unsorted
     (4, 22, [3, 12, 0, 21]),
+    # targets = the k lowest bits in any order: contiguous groups staged
+    # through LDS
+    (5, 9, [2, 4, 0, 3, 1]),          # exactly one tile
+    (5, 16, [3, 0, 4, 1, 2]),
+    (4, 12, [2, 0, 3, 1]),
+    (4, 20, [0, 1, 2, 3]),
 ])
 def test_apply_fused_tiles(dtype, k, n, qubits):
     """The matrix-core path (k = 4, 5 with at least 16 groups) at the tile
