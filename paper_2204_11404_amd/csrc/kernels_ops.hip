@@ -122,6 +122,41 @@ __global__ __launch_bounds__(256) void k_gate2_quad(T* __restrict__ st, int swap
   st2(st, i, C2<T>{re, im});
 }
 
+// The same gate for complex64 registers: thread i holds amplitudes 2 i and
+// 2 i + 1 (one 16-byte access), its pair lane i ^ 1 the other half of the
+// quadruple (DPP quad_perm xor 1); each thread computes its two rows.
+__global__ __launch_bounds__(256) void k_gate2_pair_f32(float* __restrict__ st, int swap, Mat4 M) {
+  __shared__ float sm[32];
+  if (threadIdx.x < 32) sm[threadIdx.x] = (float)M.m[threadIdx.x];
+  __syncthreads();
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const float4 a = reinterpret_cast<const float4*>(st)[i];
+  const float4 b{dpp_mv<0xB1>(a.x), dpp_mv<0xB1>(a.y), dpp_mv<0xB1>(a.z), dpp_mv<0xB1>(a.w)};
+  const int hi = (int)(i & 1);  // address bit 1 of this thread's pair
+  // address-local amplitudes 0..3 of the quadruple
+  C2<float> v[4];
+  v[2 * hi] = {a.x, a.y};
+  v[2 * hi + 1] = {a.z, a.w};
+  v[2 * (1 - hi)] = {b.x, b.y};
+  v[2 * (1 - hi) + 1] = {b.z, b.w};
+  auto local = [&](int y) { return swap ? ((y >> 1) & 1) | ((y & 1) << 1) : y; };
+  C2<float> out[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int r = local(2 * hi + k);
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int c = local(x);
+      const float mr = sm[2 * (4 * r + c)], mi = sm[2 * (4 * r + c) + 1];
+      re += mr * v[x].re - mi * v[x].im;
+      im += mr * v[x].im + mi * v[x].re;
+    }
+    out[k] = {re, im};
+  }
+  reinterpret_cast<float4*>(st)[i] = make_float4(out[0].re, out[0].im, out[1].re, out[1].im);
+}
+
 template <typename T>
 __global__ void k_diag(T* __restrict__ st, uint64_t n_amp, int k, int q0, int q1, int q2, int q3, int q4, Diag32 D) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -1704,7 +1704,7 @@ sv_status sv_apply_gate(sv_state s, int k, const int* qubits, const double* m) {
     else
       hipLaunchKernelGGL(k_gate1<float>, dim3(grid_for(np, 256)), dim3(256), 0, s->stream,
                          (float*)s->ptr, np, qubits[0], M);
-  } else if (qubits[0] + qubits[1] == 1 && s->n >= 8) {
+  } else if (qubits[0] + qubits[1] == 1 && s->n >= 9) {
     // qubits 0 and 1: one amplitude per thread, quadruples exchanged within
     // DPP quads (whole 256-thread blocks)
     Mat4 M;
@@ -1713,8 +1713,9 @@ sv_status sv_apply_gate(sv_state s, int k, const int* qubits, const double* m) {
     const int swap = qubits[0] == 1;
     if (s->dt == SV_C128)
       hipLaunchKernelGGL(k_gate2_quad<double>, g, b, 0, s->stream, (double*)s->ptr, swap, M);
-    else
-      hipLaunchKernelGGL(k_gate2_quad<float>, g, b, 0, s->stream, (float*)s->ptr, swap, M);
+    else  // two amplitudes per thread: half the threads
+      hipLaunchKernelGGL(k_gate2_pair_f32, dim3((unsigned)(na / 512)), b, 0, s->stream, (float*)s->ptr,
+                         swap, M);
   } else {
     Mat4 M;
     std::memcpy(M.m, m, sizeof M.m);

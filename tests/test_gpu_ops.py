@@ -48,9 +48,10 @@ def test_apply_gate_every_position(dtype, n):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_apply_gate_low_pairs(dtype):
     """Two-qubit gates on low qubits: every ordered pair below 4, on registers
-    of 8 (one block) and 12 qubits; (0, 1) and (1, 0) run with one amplitude
-    per lane and the quadruple exchanged within DPP quads."""
-    for n in (8, 12):
+    of 8, 9 (one block of the lane kernels) and 12 qubits; (0, 1) and (1, 0)
+    exchange the quadruple between lanes (complex128: one amplitude per lane,
+    DPP quads; complex64: two per lane, DPP lane pairs)."""
+    for n in (8, 9, 12):
         for q0 in range(4):
             for q1 in range(4):
                 if q0 == q1:
