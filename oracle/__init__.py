@@ -16,6 +16,7 @@ Parts:
   * :mod:`oracle.decoder`: detection events and a minimum-weight matching
     decoder for the logical Z readout.
 """
+import contextlib
 import ctypes
 import os
 
@@ -43,6 +44,7 @@ class _Job(ctypes.Structure):
         ("virtual_z", ctypes.c_int),
         ("idle", ctypes.c_int),
         ("zzp", ctypes.c_int),
+        ("max_blocks", ctypes.c_int),
     ]
 
 
@@ -55,29 +57,48 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"oracle library missing: {LIB_PATH}; run oracle/build.py")
-        L = ctypes.CDLL(LIB_PATH)
-        u32p = ctypes.POINTER(ctypes.c_uint32)
-        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
-        L.orc_philox4x32_10.restype = None
-        L.orc_uniform.argtypes = [ctypes.c_ulonglong] * 3
-        L.orc_uniform.restype = ctypes.c_double
-        ip = ctypes.POINTER(ctypes.c_int)
-        L.orc_layout.argtypes = [ctypes.c_int, ip, ip, ctypes.c_int]
-        L.orc_layout.restype = ctypes.c_int
-        L.orc_template_counts.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, ip]
-        L.orc_template_counts.restype = ctypes.c_int
-        u8p = ctypes.POINTER(ctypes.c_uint8)
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.orc_run_trajectory.argtypes = [ctypes.POINTER(_Job), ctypes.c_ulonglong, u8p, u8p, dp, dp]
-        L.orc_run_trajectory.restype = ctypes.c_int
-        L.orc_logical_state.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
-        L.orc_logical_state.restype = ctypes.c_int
-        L.orc_apply_gate.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip, dp]
-        L.orc_apply_gate.restype = ctypes.c_int
-        L.orc_time_blocks.argtypes = [ctypes.POINTER(_Job), ctypes.c_ulonglong, ctypes.c_int, ip]
-        L.orc_time_blocks.restype = ctypes.c_double
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+@contextlib.contextmanager
+def library_override(path):
+    """Route this module's calls to another build of qec_oracle.cpp for the
+    duration of the block (the pins' own check that a mistake planted in an
+    edited copy of the oracle is caught); the usual library is back after."""
+    global _lib
+    saved = lib()
+    _lib = _load(path)
+    try:
+        yield _lib
+    finally:
+        _lib = saved
+
+
+def _load(path):
+    """Open a build of qec_oracle.cpp and declare its entry points."""
+    L = ctypes.CDLL(path)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    L.orc_philox4x32_10.restype = None
+    L.orc_uniform.argtypes = [ctypes.c_ulonglong] * 3
+    L.orc_uniform.restype = ctypes.c_double
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.orc_layout.argtypes = [ctypes.c_int, ip, ip, ctypes.c_int]
+    L.orc_layout.restype = ctypes.c_int
+    L.orc_template_counts.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, ip]
+    L.orc_template_counts.restype = ctypes.c_int
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.orc_run_trajectory.argtypes = [ctypes.POINTER(_Job), ctypes.c_ulonglong, u8p, u8p, dp, dp]
+    L.orc_run_trajectory.restype = ctypes.c_int
+    L.orc_logical_state.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    L.orc_logical_state.restype = ctypes.c_int
+    L.orc_apply_gate.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip, dp]
+    L.orc_apply_gate.restype = ctypes.c_int
+    L.orc_time_blocks.argtypes = [ctypes.POINTER(_Job), ctypes.c_ulonglong, ctypes.c_int, ip]
+    L.orc_time_blocks.restype = ctypes.c_double
+    return L
 
 
 def _ptr(a, ctype):
@@ -121,7 +142,7 @@ def template_counts(d, gateset):
 
 def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=None,
                    want_state=False, twirl=False, xbasis=False, virtual_z=False, idle=False,
-                   zz_plaquette=False):
+                   zz_plaquette=False, max_blocks=0):
     """One Monte Carlo trajectory.
 
     twirl: Pauli-twirled over-rotations; xbasis: X-basis memory (logical |+>,
@@ -129,7 +150,9 @@ def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=N
     cross-resonance Z checks without over-rotation; idle: one-qubit noise on
     the waiting qubits of the circuit at every step; zz_plaquette: the
     crosstalk exp(-i zeta Z_anc Z_q) between the ancilla and every data qubit
-    of the running check after each step.  Returns
+    of the running check after each step; max_blocks > 0: stop after that
+    many noisy circuits (records and p1 beyond them stay 0, no final
+    measurement, `state` is the register at that point).  Returns
     dict(records=uint8[rounds, n_stab], final_bits=uint8[d*d],
     p1=float64[rounds, n_stab], state=complex128[2^(d*d)] or None) where
     `state` is the data register just before the final measurement."""
@@ -142,6 +165,7 @@ def run_trajectory(d, gateset, rounds, seed, t, p, zeta=0.0, eps=0.0, eps_site=N
     job.virtual_z = 1 if virtual_z else 0
     job.idle = 1 if idle else 0
     job.zzp = 1 if zz_plaquette else 0
+    job.max_blocks = int(max_blocks)
     keep = None
     if eps_site is not None:
         keep = np.ascontiguousarray(eps_site, dtype=np.float64)

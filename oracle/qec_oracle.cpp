@@ -339,6 +339,7 @@ struct Job {
   int virtual_z;           // 1: Rz restores are exact (virtual Z, Fig. 4)
   int idle;                // 1: one-qubit noise on the circuit's waiting qubits at each step
   int zzp;                 // 1: exp(-i zeta Z_anc Z_q) on the check's data qubits after each step
+  int max_blocks;          // > 0: stop after this many noisy circuits (no final measurement)
 };
 
 struct Ctx {
@@ -590,9 +591,16 @@ int run_trajectory(const Job& job, uint64_t t, const Output& out) {
   if (prepare_logical_zero(s, job, stabs) != 0) return -1;
 
   Ctx cx{&job, t, 0, true, 0};
-  for (int r = 0; r < job.rounds; ++r) {
+  int done = 0;  // noisy circuits run so far
+  bool stopped = false;
+  for (int r = 0; r < job.rounds && !stopped; ++r) {
     cx.site = 0;
     for (int i = 0; i < ns; ++i) {
+      if (job.max_blocks > 0 && done == job.max_blocks) {
+        stopped = true;
+        break;
+      }
+      ++done;
       const Stab& st = stabs[i];
       run_stabilizer_gates(s, cx, st, anc);
       if (job.zeta != 0.0) zz_layer(s, d, job.zeta);
@@ -613,6 +621,7 @@ int run_trajectory(const Job& job, uint64_t t, const Output& out) {
       out.final_state[2 * x + 1] = s.a[x].imag();
     }
   }
+  if (job.max_blocks > 0 && done == job.max_blocks) return 0;  // a partial trajectory
   // Final Z (X-basis memory: X) measurement of every data qubit, highest label
   // first; an X measurement is a Z measurement after a Hadamard.
   if (job.xbasis)
@@ -669,6 +678,7 @@ typedef struct {
   int virtual_z;  // 1: Rz restores exact
   int idle;       // 1: idle noise on the waiting qubits of every step
   int zzp;        // 1: ancilla-plaquette ZZ crosstalk after every step
+  int max_blocks; // > 0: only the first max_blocks noisy circuits (then no final measurement)
 } orc_job;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
@@ -701,7 +711,8 @@ int orc_run_trajectory(const orc_job* j, unsigned long long t, uint8_t* records,
                        uint8_t* final_bits, double* p1_trace, double* final_state) {
   if (!j || j->d < 2 || j->d > 5 || j->rounds < 0) return -1;
   Job job{j->d,     j->gateset, j->rounds, j->seed,   j->p,         j->zeta,
-          j->eps_site, j->eps,   j->twirl,  j->xbasis, j->virtual_z, j->idle, j->zzp};
+          j->eps_site, j->eps,   j->twirl,  j->xbasis, j->virtual_z, j->idle, j->zzp,
+          j->max_blocks};
   Output out{records, final_bits, p1_trace, final_state};
   return run_trajectory(job, t, out);
 }
@@ -710,7 +721,7 @@ int orc_run_trajectory(const orc_job* j, unsigned long long t, uint8_t* records,
 // 2^(d*d) interleaved complex.
 int orc_logical_state(int d, int gateset, int xbasis, double* out) {
   if (d < 2 || d > 5) return -1;
-  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0, 0, xbasis, 0, 0, 0};
+  Job job{d, gateset, 0, 0, 0.0, 0.0, nullptr, 0.0, 0, xbasis, 0, 0, 0, 0};
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);
   if (prepare_logical_zero(s, job, stabs) != 0) return -1;
@@ -746,7 +757,7 @@ int orc_apply_gate(double* state, int n, int k, const int* qubits, const double*
 double orc_time_blocks(const orc_job* j, unsigned long long t, int n_blocks, int* threads) {
   if (!j || j->d < 2 || j->d > 5 || n_blocks < 1) return -1.0;
   Job job{j->d,     j->gateset, 1,         j->seed,   j->p,         j->zeta,
-          j->eps_site, j->eps,     j->twirl, j->xbasis, j->virtual_z, j->idle, j->zzp};
+          j->eps_site, j->eps,     j->twirl, j->xbasis, j->virtual_z, j->idle, j->zzp, 0};
   const int d = job.d, anc = d * d;
   const std::vector<Stab> stabs = build_layout(d);
   State s(d * d + 1);
