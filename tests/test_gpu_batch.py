@@ -113,3 +113,89 @@ def test_batch_common_angles_parity(gateset, d, dtype, split, monkeypatch):
         o = oracle.run_trajectory(d, GS[gateset], int(R[i]), seed, i, p[i], eps=eps, zeta=zeta)
         assert np.array_equal(g["records"][i, :R[i]], o["records"]), f"trajectory {i}"
         assert np.array_equal(g["final_bits"][i], o["final_bits"]), f"trajectory {i}"
+
+
+# -------------------------------------------------- the batched launch's real shape
+# 16 384 d=3 trajectories: far more than the persistent grid holds at once
+# (at most CUs * 32 waves), so every workgroup runs several trajectories one
+# after another and reuses its LDS slot, angle tables and cached noise-free
+# Kraus pairs.  The oracle runs a spread sample (every 16th trajectory and the
+# last 64) once per parameter set; every launch variant is compared with it.
+N_REAL = 16384
+_ORACLE_CACHE = {}
+
+
+def _real_shape_sample(n):
+    return np.unique(np.concatenate([np.arange(0, n, 16), np.arange(n - 64, n)]))
+
+
+def _oracle_sample(d, gateset, n, seed, p_range):
+    key = (d, gateset, n, seed, p_range)
+    if key not in _ORACLE_CACHE:
+        n_sites = qs.template_info(d, gateset)[1]
+        R, p, eps = workloads.batch_params(n, n_sites, seed, p=p_range)
+        idx = _real_shape_sample(n) if d == 3 else np.unique(np.concatenate(
+            [np.arange(0, n, n // 48), np.arange(n - 16, n)]))
+        print(f"oracle sample d={d} {gateset} n={n}: {idx.size} trajectories", flush=True)
+        out = {}
+        for i in idx:
+            o = oracle.run_trajectory(d, GS[gateset], int(R[i]), seed, int(i), p[i], eps_site=eps[i])
+            out[int(i)] = (o["records"], o["final_bits"])
+        _ORACLE_CACHE[key] = (R, p, eps, out)
+    return _ORACLE_CACHE[key]
+
+
+def _grid_bound(d, dtype, nw):
+    """Most workgroups the persistent launch can have: CUs x the tuned waves
+    per CU / waves per trajectory."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    per_cu = max(1, qs.tuning_get(d, dtype)["batch_waves_per_cu"] // nw)
+    return cus * per_cu
+
+
+def _check_sample(d, gateset, dtype, n, seed, p_range):
+    R, p, eps, ref = _oracle_sample(d, gateset, n, seed, p_range)
+    g = qs.run_batch(d, gateset, R, p, seed, eps_site=eps, dtype=dtype, max_rounds=9)
+    for i, (rec, fb) in ref.items():
+        assert np.array_equal(g["records"][i, :R[i]], rec), f"trajectory {i}"
+        assert not g["records"][i, R[i]:].any(), f"trajectory {i}"
+        assert np.array_equal(g["final_bits"][i], fb), f"trajectory {i}"
+    return g
+
+
+@pytest.mark.parametrize("waves_per_cu", [None, "1"])
+@pytest.mark.parametrize("split", SPLITS)
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batch_d3_persistent_real_shape(dtype, split, waves_per_cu, monkeypatch):
+    """The batched workload's shape (rounds 1..9, p in [5e-4, 5e-3), theta in
+    [0, 0.05) per site and trajectory) at 16 384 trajectories per launch, with
+    the tuned occupancy and with one resident workgroup per CU (each then runs
+    at least 64 trajectories)."""
+    monkeypatch.setenv("QECSV_BATCH_SPLIT", split)
+    if waves_per_cu:
+        monkeypatch.setenv("QECSV_BATCH_WAVES_PER_CU", waves_per_cu)
+    print(f"case batch real shape d=3 {dtype} split={split} waves_per_cu={waves_per_cu}", flush=True)
+    assert N_REAL > 2 * _grid_bound(3, dtype, int(split))
+    _check_sample(3, "cr", dtype, N_REAL, seed=61, p_range=(5e-4, 5e-3))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_d4_lockstep_groups(dtype, monkeypatch):
+    """d=4 registers run in lockstep groups of QECSV_LOCKSTEP_MIB; 2 MiB holds
+    two complex128 or four complex64 registers, so 24 trajectories take 12 or
+    6 consecutive groups (slots, tables and decisions reused from group to
+    group)."""
+    monkeypatch.setenv("QECSV_LOCKSTEP_MIB", "2")
+    per_reg = (2 << 16) * (8 if dtype == "c128" else 4)
+    assert 24 // ((2 << 20) // per_reg) >= 3
+    print(f"case batch d=4 lockstep groups {dtype}", flush=True)
+    _check(4, "cr", dtype, 24, seed=63, p_range=(5e-3, 3e-2), zeta=0.01)
+
+
+def test_batch_d4_real_shape_sample():
+    """4096 d=4 complex64 trajectories in one launch with the tuned lockstep
+    groups, a spread sample of 64 (including the last 16) against the
+    oracle."""
+    print("case batch real shape d=4 c64 n=4096", flush=True)
+    _check_sample(4, "cr", "c64", 4096, seed=65, p_range=(5e-4, 5e-3))

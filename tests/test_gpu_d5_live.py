@@ -1,0 +1,99 @@
+"""d=5 parity (26 qubits: 25 data qubits and the reused ancilla) against the
+oracle run live on the host, in the launch configurations that are timed.
+
+Each case runs 2 trajectories x 2 noisy rounds of the cross-resonance circuit
+with p = 1e-2 (a few Pauli hits per round, so Pauli-X frames occur in X and Z
+checks), per-site over-rotation theta ~ U[0, 0.05) and the data ZZ layer at
+zeta = 0.01 (Sec. II.B, III.A-B).  Records and final bits must agree bit for
+bit, p1 and every one of the 2^25 amplitudes of the register before the final
+measurement to 1e-10 (complex128) or 1e-5 (complex64).  The oracle computes
+each parameter set once (about 20-40 s per trajectory on the host) and every
+launch variant of that set is compared with it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2204_11404_amd as qs
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+D, R, N_TRAJ, SEED, P, ZETA = 5, 2, 2, 1, 1e-2, 0.01
+# the pass launch parameters the benchmark's autotuner picks on MI355X
+BENCH_TUNING = {"QECSV_PASS_WGS_PER_CU": "16", "QECSV_ZCHAIN": "4", "QECSV_SNAKE": "1"}
+DEFAULT_TUNING = {"QECSV_PASS_WGS_PER_CU": "0", "QECSV_ZCHAIN": "4", "QECSV_SNAKE": "1"}
+_ORACLE = {}
+
+
+def _eps():
+    return workloads.eps_sites(oracle.template_counts(D, oracle.GATESET_CR)[1], (0.0, 0.05), SEED)
+
+
+def _oracle_runs(variant):
+    """The oracle's trajectories for one noise variant, computed once."""
+    if variant not in _ORACLE:
+        kw = dict(xbasis=variant == "xbasis", idle=variant == "idle", zz_plaquette=variant == "zzp")
+        print(f"oracle d=5 {variant}: {N_TRAJ} trajectories x {R} rounds", flush=True)
+        _ORACLE[variant] = [oracle.run_trajectory(D, oracle.GATESET_CR, R, SEED, t, P, zeta=ZETA,
+                                                  eps_site=_eps(), want_state=True, **kw)
+                            for t in range(N_TRAJ)]
+    return _ORACLE[variant]
+
+
+def _compare(variant, dtype, tuning, monkeypatch):
+    for k, v in tuning.items():
+        monkeypatch.setenv(k, v)
+    ref = _oracle_runs(variant)
+    print(f"case d5 live {variant} {dtype} {tuning}", flush=True)
+    g = qs.run_rounds(D, "cr", R, N_TRAJ, SEED, P, eps_site=_eps(), zeta=ZETA, dtype=dtype,
+                      want_p1=True, want_states=True, xbasis=variant == "xbasis",
+                      idle_noise=variant == "idle", zz_plaquette=variant == "zzp")
+    atol = 1e-10 if dtype == "c128" else 1e-5
+    hits = 0
+    for t, o in enumerate(ref):
+        assert np.array_equal(g["records"][t], o["records"]), f"trajectory {t}"
+        assert np.array_equal(g["final_bits"][t], o["final_bits"]), f"trajectory {t}"
+        assert np.max(np.abs(g["p1"][t] - o["p1"])) < atol, f"trajectory {t}"
+        diff = np.abs(g["states"][t].astype(np.complex128) - o["state"])
+        assert diff.size == 1 << 25
+        assert np.max(diff) < atol, f"trajectory {t}: largest amplitude error {np.max(diff):.3g}"
+        # outcomes that are not the noiseless ones: Pauli hits did reach checks
+        hits += int(np.sum((o["p1"] > 1e-9) & (o["p1"] < 1 - 1e-9)))
+    assert hits > 0
+    return g
+
+
+def test_d5_live_c128_bench_tuning(monkeypatch):
+    """The benchmark's configuration: 16 pass workgroups per CU, each taking
+    tiles grid-stride, Z chains of four, alternating traversal."""
+    g = _compare("base", "c128", BENCH_TUNING, monkeypatch)
+    assert qs.tuning_get(5, "c128")["pass_wgs_per_cu"] == 16
+    assert g["passes_per_round"] == 15
+
+
+def test_d5_live_c128_default_tuning(monkeypatch):
+    _compare("base", "c128", DEFAULT_TUNING, monkeypatch)
+
+
+def test_d5_live_c64_bench_tuning(monkeypatch):
+    """complex64 amplitudes with FP64 sums, p1 and renormalisation (the
+    precision workload's storage type)."""
+    _compare("base", "c64", BENCH_TUNING, monkeypatch)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_d5_live_zz_plaquette(dtype, monkeypatch):
+    """Ancilla-plaquette crosstalk after every step: dense Kraus pairs for the
+    X checks, applied on the matrix cores."""
+    _compare("zzp", dtype, BENCH_TUNING, monkeypatch)
+
+
+def test_d5_live_x_basis(monkeypatch):
+    """X-basis memory: logical |+> written by the first pass, X readout."""
+    _compare("xbasis", "c128", BENCH_TUNING, monkeypatch)
+
+
+def test_d5_live_idle_noise(monkeypatch):
+    """One-qubit noise on the waiting qubits of every step, p = 1e-2."""
+    _compare("idle", "c64", BENCH_TUNING, monkeypatch)
