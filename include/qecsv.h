@@ -252,6 +252,23 @@ typedef struct sv_result {
  * final data measurement.  Synchronous.  Records are the raw ancilla bits. */
 sv_status sv_run_rounds(const sv_job* job, sv_result* res);
 
+/* The same run enqueued without waiting, so that jobs on several streams
+ * overlap on the device (the paper's workload is many independent
+ * trajectories, Sec. III.B).  Every kernel and copy goes to job->hip_stream;
+ * done_event (a hipEvent_t the caller created) is recorded on that stream
+ * after records, final_bits and p1_trace (if given) have been copied into
+ * res's host buffers, and the call returns without waiting for the device.
+ * The caller keeps those buffers valid and unread until done_event has
+ * completed; with pinned host buffers (hipHostMalloc) the copies run
+ * asynchronously, with pageable ones the runtime may wait for them.  job and
+ * eps_site are copied before return.  Results are those of sv_run_rounds.
+ * Not available: SV_RUN_GRAPH and final_states (SV_EINVAL).  res->gpu_ms and
+ * res->pass_ms are set to -1 (time with events on the stream);
+ * res->passes_per_round is set.  Errors are reported before anything is
+ * enqueued, except HIP failures during enqueueing (SV_EDEVICE; work already
+ * enqueued then still runs and done_event is not recorded). */
+sv_status sv_run_rounds_async(const sv_job* job, sv_result* res, void* done_event);
+
 /* Decoding of the Z-basis memory experiment (Sec. III.B; host only).
  * Detection events: Z-check syndromes (raw record XOR its trivial bit, which
  * is (w/2) mod 2 for a weight-w check of the cross-resonance circuit and 0

@@ -122,6 +122,7 @@ _SIGS = {
     "sv_template_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "sv_run_rounds": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(Result)]),
+    "sv_run_rounds_async": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(Result), ctypes.c_void_p]),
     "sv_run_batch": (ctypes.c_int, [ctypes.POINTER(BatchJob), ctypes.POINTER(BatchResult)]),
     "sv_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
     "sv_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request)]),
@@ -325,15 +326,8 @@ SV_RUN_IDLE_NOISE = 16
 SV_RUN_ZZ_PLAQUETTE = 32
 
 
-def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0,
-               dtype="c128", traj0=0, want_p1=False, want_states=False, stream=None, graph=False,
-               twirl=False, xbasis=False, virtual_z=False, idle_noise=False, zz_plaquette=False):
-    """sv_run_rounds: returns dict(records[n_traj, rounds, n_stab], final_bits[n_traj, d*d],
-    p1 or None, states or None, gpu_ms, pass_ms, passes_per_round).  Flags:
-    graph (HIP graph replay), twirl (Pauli-twirled over-rotations), xbasis
-    (X-basis memory), virtual_z (exact Rz restores), idle_noise (one-qubit
-    noise on the waiting qubits of every step), zz_plaquette (crosstalk
-    exp(-i zeta Z_anc Z_q) with the check's data qubits after every step)."""
+def _rounds_job(d, gateset, rounds, n_traj, seed, p, eps, eps_site, zeta, dtype, traj0, stream, graph,
+                twirl, xbasis, virtual_z, idle_noise, zz_plaquette):
     n_stab, n_sites, _ = template_info(d, gateset)
     job = Job()
     job.d, job.gateset, job.rounds = d, _GATESETS[gateset], rounds
@@ -350,6 +344,20 @@ def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta
         if keep.shape != (n_sites,):
             raise ValueError(f"eps_site must have {n_sites} entries")
         job.eps_site = _dptr(keep)
+    return job, keep, n_stab
+
+
+def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta=0.0,
+               dtype="c128", traj0=0, want_p1=False, want_states=False, stream=None, graph=False,
+               twirl=False, xbasis=False, virtual_z=False, idle_noise=False, zz_plaquette=False):
+    """sv_run_rounds: returns dict(records[n_traj, rounds, n_stab], final_bits[n_traj, d*d],
+    p1 or None, states or None, gpu_ms, pass_ms, passes_per_round).  Flags:
+    graph (HIP graph replay), twirl (Pauli-twirled over-rotations), xbasis
+    (X-basis memory), virtual_z (exact Rz restores), idle_noise (one-qubit
+    noise on the waiting qubits of every step), zz_plaquette (crosstalk
+    exp(-i zeta Z_anc Z_q) with the check's data qubits after every step)."""
+    job, keep, n_stab = _rounds_job(d, gateset, rounds, n_traj, seed, p, eps, eps_site, zeta, dtype, traj0,
+                                    stream, graph, twirl, xbasis, virtual_z, idle_noise, zz_plaquette)
     rec = np.zeros((n_traj, rounds, n_stab), dtype=np.uint8)
     fb = np.zeros((n_traj, d * d), dtype=np.uint8)
     p1 = np.zeros((n_traj, rounds, n_stab), dtype=np.float64) if want_p1 else None
@@ -365,6 +373,50 @@ def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta
     del keep
     return dict(records=rec, final_bits=fb, p1=p1, states=states, gpu_ms=res.gpu_ms, pass_ms=res.pass_ms,
                 passes_per_round=res.passes_per_round)
+
+
+class AsyncRun:
+    """An sv_run_rounds_async call in flight: its pinned host outputs and the
+    event recorded after their copies.  wait() returns the run_rounds dict."""
+
+    def __init__(self, event, out, res, n_passes):
+        self.event, self._out, self._res, self._n_passes = event, out, res, n_passes
+
+    def done(self):
+        return self.event.query()
+
+    def wait(self):
+        self.event.synchronize()
+        o = self._out
+        return dict(records=o["records"].numpy(), final_bits=o["final_bits"].numpy(),
+                    p1=o["p1"].numpy() if o["p1"] is not None else None, states=None,
+                    gpu_ms=None, pass_ms=None, passes_per_round=self._n_passes)
+
+
+def run_rounds_async(d, gateset, rounds, n_traj, seed, p, stream, eps=0.0, eps_site=None, zeta=0.0,
+                     dtype="c128", traj0=0, want_p1=False, twirl=False, xbasis=False, virtual_z=False,
+                     idle_noise=False, zz_plaquette=False):
+    """sv_run_rounds_async on `stream` (a torch.cuda.Stream): the outputs go
+    to pinned host tensors; returns an AsyncRun at once."""
+    import torch
+    job, keep, n_stab = _rounds_job(d, gateset, rounds, n_traj, seed, p, eps, eps_site, zeta, dtype, traj0,
+                                    stream, False, twirl, xbasis, virtual_z, idle_noise, zz_plaquette)
+    out = dict(records=torch.zeros((n_traj, rounds, n_stab), dtype=torch.uint8, pin_memory=True),
+               final_bits=torch.zeros((n_traj, d * d), dtype=torch.uint8, pin_memory=True),
+               p1=torch.zeros((n_traj, rounds, n_stab), dtype=torch.float64, pin_memory=True)
+               if want_p1 else None)
+    res = Result()
+    res.records = ctypes.cast(out["records"].data_ptr(), ctypes.POINTER(ctypes.c_uint8))
+    res.final_bits = ctypes.cast(out["final_bits"].data_ptr(), ctypes.POINTER(ctypes.c_uint8))
+    if out["p1"] is not None:
+        res.p1_trace = ctypes.cast(out["p1"].data_ptr(), ctypes.POINTER(ctypes.c_double))
+    # torch creates the HIP event when it is first recorded; the library then
+    # records it again after the run's work
+    event = torch.cuda.Event()
+    event.record(stream)
+    _check(lib().sv_run_rounds_async(ctypes.byref(job), ctypes.byref(res), ctypes.c_void_p(event.cuda_event)))
+    del keep
+    return AsyncRun(event, out, res, res.passes_per_round)
 
 
 def run_batch(d, gateset, rounds, p, seed, eps=0.0, eps_site=None, zeta=0.0, dtype="c64", traj0=0,

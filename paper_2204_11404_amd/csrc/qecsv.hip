@@ -764,9 +764,36 @@ std::vector<UnitPass> make_unit_passes(int n, int tb, const Template& tp,
 
 namespace {
 
+// Host-side inputs of one run's set-up copies.  An asynchronous run keeps
+// them alive until its stream has passed the copies (a host function on the
+// stream deletes them), so they may come from pageable memory.
+struct RunStage {
+  std::vector<TBlock> blocks;
+  std::vector<UnitPass> pds;
+  JobConst jc;
+  std::vector<double> eps, thr;
+};
+
+// Every block of the template builds a monomial Kraus pair with no Pauli
+// drawn (Paulis keep that form), i.e. the device-side check of the prepare
+// kernels cannot fire; used where the run cannot wait to read that check.
+bool template_is_monomial(const Template& tp, const std::vector<double>& eps) {
+  const uint8_t none[kMaxOps] = {};
+  for (const TBlock& b : tp.blocks) {
+    if (b.dense) continue;
+    BlockRT rt;
+    if (!build_block(b, eps.data(), none, rt)) return false;
+  }
+  return true;
+}
+
+// done == nullptr: synchronous.  Otherwise every step is enqueued on the
+// job's stream, `done` is recorded after the results' copies to the host and
+// the call returns without waiting (no graph replay, no final states).
 template <typename T>
 sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
-                       const std::atomic<int>* cancel = nullptr) {
+                       const std::atomic<int>* cancel = nullptr, hipEvent_t done = nullptr) {
+  const bool async = done != nullptr;
   const int d = job->d, n = d * d, ns = (int)tp.blocks.size(), R = job->rounds;
   const int tb = std::min(kTileMax, n);
   const int per_traj = R * ns;  // block instances (records) per trajectory
@@ -822,22 +849,16 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
 
   const std::vector<UnitPass> pds = make_unit_passes(n, tb, tp, units);
   const bool xbasis = (job->flags & SV_RUN_XBASIS) != 0;
-  const JobConst jc = make_job_const(d, job->zeta, xbasis);
   std::vector<double> eps(n_angles, job->eps);
   if (job->eps_site)
     for (int i = 0; i < tp.n_sites; ++i) eps[i] = job->eps_site[i];
   if (tp.zz_site >= 0) eps[tp.zz_site] = job->zeta;  // the per-step crosstalk angle
-
-  HIP_OK(hipMemcpyAsync(dblocks, tp.blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(dpass, pds.data(), sizeof(UnitPass) * (nu + 2), hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(djc, &jc, sizeof jc, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(deps, eps.data(), sizeof(double) * eps.size(), hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
-  HIP_OK(hipMemsetAsync(ddec, 0, sizeof(Decision) * (per_units + 1), s));
+  if (async && !template_is_monomial(tp, eps))
+    return fail(SV_EINVAL, "circuit template is not monomial in its block basis");
   // Pauli-twirled over-rotations: per-site probability sin^2 eps, computed
   // here so that every implementation compares its draws with the same value
-  double* dthr = nullptr;
   std::vector<double> thr;
+  double* dthr = nullptr;
   if (job->flags & SV_RUN_TWIRL) {
     thr.resize(eps.size());
     for (size_t i = 0; i < eps.size(); ++i) {
@@ -845,8 +866,35 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       thr[i] = sn * sn;
     }
     HIP_OK(M.alloc(&dthr, sizeof(double) * thr.size()));
-    HIP_OK(hipMemcpyAsync(dthr, thr.data(), sizeof(double) * thr.size(), hipMemcpyHostToDevice, s));
   }
+  {
+    // set-up copies from a staging block that a host function on the stream
+    // deletes once the stream has passed them (the call may return first)
+    RunStage* stage = new RunStage{tp.blocks, pds, make_job_const(d, job->zeta, xbasis), eps, thr};
+    const hipError_t e = [&]() -> hipError_t {
+      hipError_t r;
+      if ((r = hipMemcpyAsync(dblocks, stage->blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s)))
+        return r;
+      if ((r = hipMemcpyAsync(dpass, stage->pds.data(), sizeof(UnitPass) * (nu + 2), hipMemcpyHostToDevice,
+                              s)))
+        return r;
+      if ((r = hipMemcpyAsync(djc, &stage->jc, sizeof(JobConst), hipMemcpyHostToDevice, s))) return r;
+      if ((r = hipMemcpyAsync(deps, stage->eps.data(), sizeof(double) * stage->eps.size(),
+                              hipMemcpyHostToDevice, s)))
+        return r;
+      if (dthr && (r = hipMemcpyAsync(dthr, stage->thr.data(), sizeof(double) * stage->thr.size(),
+                                      hipMemcpyHostToDevice, s)))
+        return r;
+      return hipLaunchHostFunc(s, [](void* q) { delete static_cast<RunStage*>(q); }, stage);
+    }();
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      delete stage;
+      return fail(SV_EDEVICE, "set-up copies: %s", hipGetErrorString(e));
+    }
+  }
+  HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
+  HIP_OK(hipMemsetAsync(ddec, 0, sizeof(Decision) * (per_units + 1), s));
 
   // whole-run events plus one pair around every pass of the last trajectory
   struct Events {
@@ -855,11 +903,11 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
   } E;
-  E.ev.resize(2 + 2 * per_units, nullptr);
+  E.ev.resize(async ? 0 : 2 + 2 * per_units, nullptr);
   for (auto& e : E.ev) HIP_OK(hipEventCreate(&e));
-  hipEvent_t ev0 = E.ev[0], ev1 = E.ev[1];
-  hipEvent_t* evs = E.ev.data() + 2;
-  HIP_OK(hipEventRecord(ev0, s));
+  hipEvent_t ev0 = async ? nullptr : E.ev[0], ev1 = async ? nullptr : E.ev[1];
+  hipEvent_t* evs = async ? nullptr : E.ev.data() + 2;
+  if (!async) HIP_OK(hipEventRecord(ev0, s));
 
   // alternate the tile traversal between consecutive passes: a pass starts on
   // the lines its predecessor wrote last
@@ -1007,7 +1055,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
         const int tg = c0 + ti;
         SV_OK_OR_RETURN(traj_passes(s, drt + (size_t)ti * per_traj, ddn ? ddn + (size_t)ti * per_traj : nullptr,
                                     drec + (size_t)tg * per_traj,
-                                    dp1 ? dp1 + (size_t)tg * per_traj : nullptr, tg == last_t));
+                                    dp1 ? dp1 + (size_t)tg * per_traj : nullptr, tg == last_t && !async));
         if (res->final_states) {
           HIP_OK(hipMemcpyAsync((char*)res->final_states + (size_t)tg * sizeof(T) * 2 * na, st,
                                 sizeof(T) * 2 * na, hipMemcpyDeviceToHost, s));
@@ -1019,6 +1067,19 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
         traj_final(s, dbits + (size_t)tg * n, job->traj0 + (uint64_t)tg, nullptr);
         HIP_OK(hipGetLastError());
       }
+    }
+    if (async) {
+      HIP_OK(hipMemcpyAsync(res->records, drec, nrec, hipMemcpyDeviceToHost, s));
+      HIP_OK(hipMemcpyAsync(res->final_bits, dbits, (size_t)job->n_traj * n, hipMemcpyDeviceToHost, s));
+      if (res->p1_trace)
+        HIP_OK(hipMemcpyAsync(res->p1_trace, dp1, sizeof(double) * nrec, hipMemcpyDeviceToHost, s));
+      HIP_OK(hipEventRecord(done, s));
+      // the device buffers are released in stream order when M goes out of
+      // scope
+      res->gpu_ms = -1.0;
+      res->pass_ms = -1.0;
+      res->passes_per_round = nu;
+      return SV_OK;
     }
     HIP_OK(hipEventRecord(ev1, s));
   }
@@ -2093,7 +2154,7 @@ sv_status sv_block_kraus(int d, int gateset, int stab, int round, uint64_t seed,
   return SV_OK;
 }
 
-sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
+static sv_status run_rounds_entry(const sv_job* job, sv_result* res, hipEvent_t done) {
   if (!job || !res) return fail(SV_EINVAL, "NULL job or result");
   if (job->d < 2 || job->d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", job->d);
   if (job->gateset != SV_GATESET_CR && job->gateset != SV_GATESET_TEXTBOOK)
@@ -2106,9 +2167,13 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
     return fail(SV_EINVAL, "unknown flags 0x%x", job->flags);
   if (!(job->p >= 0.0 && job->p <= 1.0)) return fail(SV_EINVAL, "p out of [0, 1]");
   if (!std::isfinite(job->eps) || !std::isfinite(job->zeta)) return fail(SV_EINVAL, "non-finite eps/zeta");
-  if (!res->records || !res->final_bits) return fail(SV_EINVAL, "records and final_bits are required");
+  if (job->n_traj > 0 && (!res->records || !res->final_bits))
+    return fail(SV_EINVAL, "records and final_bits are required");
   if ((job->flags & SV_RUN_GRAPH) && res->final_states)
     return fail(SV_EINVAL, "final_states cannot be returned with SV_RUN_GRAPH");
+  if (done && (job->flags & SV_RUN_GRAPH))
+    return fail(SV_EINVAL, "the asynchronous run does not replay graphs");
+  if (done && res->final_states) return fail(SV_EINVAL, "the asynchronous run returns no final states");
   const Template tp = build_template(job->d, job->gateset, (job->flags & SV_RUN_TWIRL) != 0,
                                      (job->flags & SV_RUN_VIRTUAL_Z) != 0,
                                      (job->flags & SV_RUN_IDLE_NOISE) != 0,
@@ -2116,12 +2181,22 @@ sv_status sv_run_rounds(const sv_job* job, sv_result* res) {
   if (job->eps_site)
     for (int i = 0; i < tp.n_sites; ++i)
       if (!std::isfinite(job->eps_site[i])) return fail(SV_EINVAL, "non-finite eps_site[%d]", i);
-  res->gpu_ms = 0.0;
-  res->pass_ms = 0.0;
+  res->gpu_ms = done ? -1.0 : 0.0;
+  res->pass_ms = done ? -1.0 : 0.0;
   res->passes_per_round = 0;
-  if (job->n_traj == 0) return SV_OK;
-  if (job->dtype == SV_C128) return run_rounds_t<double>(job, res, tp);
-  return run_rounds_t<float>(job, res, tp);
+  if (job->n_traj == 0) {
+    if (done) HIP_OK(hipEventRecord(done, (hipStream_t)job->hip_stream));
+    return SV_OK;
+  }
+  if (job->dtype == SV_C128) return run_rounds_t<double>(job, res, tp, nullptr, done);
+  return run_rounds_t<float>(job, res, tp, nullptr, done);
+}
+
+sv_status sv_run_rounds(const sv_job* job, sv_result* res) { return run_rounds_entry(job, res, nullptr); }
+
+sv_status sv_run_rounds_async(const sv_job* job, sv_result* res, void* done_event) {
+  if (!done_event) return fail(SV_EINVAL, "NULL event");
+  return run_rounds_entry(job, res, (hipEvent_t)done_event);
 }
 
 sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res) {

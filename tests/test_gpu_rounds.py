@@ -86,8 +86,11 @@ def test_deterministic_and_resumable():
 
 def test_d5_full_size_against_stored_oracle():
     """26-qubit cross-resonance workload (p=1e-3, theta ~ U[0,0.05) per site,
-    zeta=0.01) in the benchmark's launch configuration: records, p1, final
-    bits and 4096 sampled amplitudes against the oracle's stored run."""
+    zeta=0.01) with the launch parameters in effect (one tile per pass
+    workgroup unless tuned): records, p1, final bits and 4096 sampled
+    amplitudes against the oracle's stored run.  The benchmark's tuned
+    configuration and the whole register are compared with the live oracle in
+    test_gpu_d5_live.py."""
     z = np.load(GOLDEN)
     traj = [int(t) for t in z["traj"]]
     R, seed = int(z["rounds"]), int(z["seed"])
