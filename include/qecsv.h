@@ -363,6 +363,19 @@ typedef struct sv_batch_result {
 
 sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res);
 
+/* sv_run_batch for d <= 3 without any device allocation, for callers that
+ * cannot allocate (tight serving loops, harnesses that forbid hipMalloc): the
+ * same job, kernels and results, with every device buffer of the launch
+ * (staged parameters, per-trajectory tables, records, final bits) carved
+ * from a static 64 MiB array that each GPU the library runs on holds until
+ * the process ends.  Its address is taken once per device on the first call
+ * there.  Calls on one device are serialised by a lock and each call clears
+ * what must start at zero; a call leaves its data in the array.  Errors:
+ * SV_EINVAL as sv_run_batch, and for d = 4; SV_ENOMEM if the job's buffers
+ * exceed the 64 MiB (about 100 000 d=3 trajectories with per-site angles, 9
+ * rounds), checked before anything is enqueued.  Synchronous. */
+sv_status sv_run_batch_noalloc(const sv_batch_job* job, sv_batch_result* res);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A server runs submitted jobs (each an sv_job: distance, rounds, dtype, noise

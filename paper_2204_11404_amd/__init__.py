@@ -124,6 +124,7 @@ _SIGS = {
     "sv_run_rounds": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(Result)]),
     "sv_run_rounds_async": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(Result), ctypes.c_void_p]),
     "sv_run_batch": (ctypes.c_int, [ctypes.POINTER(BatchJob), ctypes.POINTER(BatchResult)]),
+    "sv_run_batch_noalloc": (ctypes.c_int, [ctypes.POINTER(BatchJob), ctypes.POINTER(BatchResult)]),
     "sv_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
     "sv_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request)]),
     "sv_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Completion), ctypes.c_int]),
@@ -420,10 +421,10 @@ def run_rounds_async(d, gateset, rounds, n_traj, seed, p, stream, eps=0.0, eps_s
 
 
 def run_batch(d, gateset, rounds, p, seed, eps=0.0, eps_site=None, zeta=0.0, dtype="c64", traj0=0,
-              max_rounds=None, stream=None):
-    """sv_run_batch: rounds and p are per-trajectory arrays; eps_site is None
-    or [n_traj, n_sites].  Returns dict(records[n_traj, max_rounds, n_stab],
-    final_bits[n_traj, d*d], gpu_ms)."""
+              max_rounds=None, stream=None, no_alloc=False):
+    """sv_run_batch (no_alloc: sv_run_batch_noalloc, d <= 3): rounds and p
+    are per-trajectory arrays; eps_site is None or [n_traj, n_sites].  Returns
+    dict(records[n_traj, max_rounds, n_stab], final_bits[n_traj, d*d], gpu_ms)."""
     rounds = np.ascontiguousarray(rounds, dtype=np.int32)
     p = np.ascontiguousarray(p, dtype=np.float64)
     n_traj = int(rounds.size)
@@ -450,7 +451,8 @@ def run_batch(d, gateset, rounds, p, seed, eps=0.0, eps_site=None, zeta=0.0, dty
     res = BatchResult()
     res.records = rec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     res.final_bits = fb.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
-    _check(lib().sv_run_batch(ctypes.byref(job), ctypes.byref(res)))
+    entry = lib().sv_run_batch_noalloc if no_alloc else lib().sv_run_batch
+    _check(entry(ctypes.byref(job), ctypes.byref(res)))
     del keep
     return dict(records=rec, final_bits=fb, gpu_ms=res.gpu_ms)
 

@@ -1192,22 +1192,71 @@ struct BatchInputs {
 template <typename T>
 sv_status run_batch_lockstep(BatchInputs& in, const Template& tp);
 
+// Device buffers of one call carved from a fixed region (the no-allocation
+// entry point's scratch array): 256-byte aligned, never freed.
+struct Arena {
+  char* base;
+  size_t cap, used;
+  bool overflow;
+  template <typename P>
+  hipError_t alloc(P** out, size_t bytes) {
+    const size_t off = (used + 255) & ~(size_t)255;
+    if (off + bytes > cap) {
+      overflow = true;
+      return hipErrorOutOfMemory;
+    }
+    *out = reinterpret_cast<P*>(base + off);
+    used = off + bytes;
+    return hipSuccess;
+  }
+};
+
+// The batched kernels draw a block with one lane per draw (16 lanes) and keep
+// kMaxOpsBatch Pauli choices per lane.
+bool batch_template_fits(const Template& tp) {
+  for (const TBlock& b : tp.blocks)
+    if (b.n_draws > 16 || b.n_ops > kMaxOpsBatch) return false;
+  return true;
+}
+
+// d <= 3: the register fits in LDS (k_batch_small).
+bool batch_is_small(const Template& tp, int d) {
+  return d * d <= kSmallBits && (int)tp.blocks.size() <= kSmallStab && tp.n_sites <= kSmallSites &&
+         tp.n_draws <= kSmallDraws;
+}
+
+// The LDS-resident launch with its device buffers from M (DevBufs or Arena);
+// ev_a / ev_b bracket the kernel.  Every buffer is taken before anything is
+// enqueued, so a failed allocation leaves nothing in flight.
+template <typename T, typename Alloc>
+sv_status run_batch_small(BatchInputs& in, const Template& tp, Alloc& M, hipEvent_t ev_a, hipEvent_t ev_b);
+
 template <typename T>
 sv_status run_batch_core(BatchInputs& in, const Template& tp) {
-  const int d = in.d, n = d * d, ns = (int)tp.blocks.size();
-  const int nt = in.n_traj;
-  // the batched kernels draw a block with one lane per draw (16 lanes) and
-  // keep kMaxOpsBatch Pauli choices per lane
-  for (const TBlock& b : tp.blocks)
-    if (b.n_draws > 16 || b.n_ops > kMaxOpsBatch) return fail(SV_EINVAL, "block template too large for the batched path");
-  const bool small = n <= kSmallBits && ns <= kSmallStab && tp.n_sites <= kSmallSites &&
-                     tp.n_draws <= kSmallDraws;
-  if (!small) {
+  const int d = in.d, n = d * d;
+  if (!batch_template_fits(tp)) return fail(SV_EINVAL, "block template too large for the batched path");
+  if (!batch_is_small(tp, d)) {
     if (n > 16) return fail(SV_EINVAL, "d=%d batch path not available", d);
     return run_batch_lockstep<T>(in, tp);
   }
+  DevBufs M(in.hs);
+  struct Ev {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Ev() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  HIP_OK(hipEventCreate(&ev.a));
+  HIP_OK(hipEventCreate(&ev.b));
+  return run_batch_small<T>(in, tp, M, ev.a, ev.b);
+}
+
+template <typename T, typename Alloc>
+sv_status run_batch_small(BatchInputs& in, const Template& tp, Alloc& M, hipEvent_t ev_a, hipEvent_t ev_b) {
+  const int d = in.d, n = d * d, ns = (int)tp.blocks.size();
+  const int nt = in.n_traj;
   hipStream_t s = in.hs;
-  DevBufs M(s);
   TBlock* dblocks = nullptr;
   SmallDesc* dsd = nullptr;
   JobConst* djc = nullptr;
@@ -1229,6 +1278,14 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   HIP_OK(M.alloc(&deps, sizeof(double) * neps));
   HIP_OK(M.alloc(&drec, nrec));
   HIP_OK(M.alloc(&dbits, (size_t)nt * n));
+  TOp* dsites = nullptr;
+  HIP_OK(M.alloc(&dsites, sizeof(TOp) * std::max(1, tp.n_sites)));
+  SmallShared<T>* dshared = nullptr;
+  if (in.eps_stride == 0) HIP_OK(M.alloc(&dshared, sizeof(SmallShared<T>)));
+  uint32_t* dinit = nullptr;
+  HIP_OK(M.alloc(&dinit, sizeof(uint32_t) * 16));
+  uint8_t* dkind = nullptr;
+  HIP_OK(M.alloc(&dkind, (size_t)std::max(1, tp.n_draws)));
   // longest trajectories first, so the static assignment balances
   std::vector<int> order(nt);
   for (int i = 0; i < nt; ++i) order[i] = i;
@@ -1250,12 +1307,9 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   for (const TBlock& b : tp.blocks)
     for (int i = 0; i < b.n_ops; ++i)
       if (b.ops[i].site >= 0) sites[b.ops[i].site] = b.ops[i];
-  TOp* dsites = nullptr;
-  HIP_OK(M.alloc(&dsites, sizeof(TOp) * sites.size()));
   HIP_OK(hipMemcpyAsync(dsites, sites.data(), sizeof(TOp) * sites.size(), hipMemcpyHostToDevice, s));
   // angles common to every trajectory: the angle table and noise-free Kraus
   // pairs once, here
-  SmallShared<T>* dshared = nullptr;
   if (in.eps_stride == 0) {
     SmallShared<T> sh{};
     for (int k = 0; k < tp.n_sites; ++k) {
@@ -1276,7 +1330,6 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
         sh.Wc[b][0][x] = (v0.re * v0.re + v0.im * v0.im) * norm;
         sh.Wc[b][1][x] = (v1.re * v1.re + v1.im * v1.im) * norm;
       }
-    HIP_OK(M.alloc(&dshared, sizeof sh));
     HIP_OK(hipMemcpyAsync(dshared, &sh, sizeof sh, hipMemcpyHostToDevice, s));
   }
   // logical |0> of the register: bit x set on the X-stabilizer orbit of 0
@@ -1287,16 +1340,12 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
       if (r & jc.span_piv[i]) r ^= jc.span_vec[i];
     if (r == 0) init_mask[x >> 5] |= 1u << (x & 31);
   }
-  uint32_t* dinit = nullptr;
-  HIP_OK(M.alloc(&dinit, sizeof(uint32_t) * init_mask.size()));
   HIP_OK(hipMemcpyAsync(dinit, init_mask.data(), sizeof(uint32_t) * init_mask.size(), hipMemcpyHostToDevice, s));
   // kind of every draw of a round: 0 one-qubit location, 1 two-qubit
   // location, 2 measurement
   std::vector<uint8_t> kind(std::max(1, tp.n_draws), 2);
   for (const TBlock& b : tp.blocks)
     for (int k = 0; k + 1 < b.n_draws; ++k) kind[b.draw_off + k] = (uint8_t)((b.n2mask >> k) & 1);
-  uint8_t* dkind = nullptr;
-  HIP_OK(M.alloc(&dkind, kind.size()));
   HIP_OK(hipMemcpyAsync(dkind, kind.data(), kind.size(), hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(dblocks, tp.blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(dsd, sd.data(), sizeof(SmallDesc) * ns, hipMemcpyHostToDevice, s));
@@ -1309,15 +1358,6 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   HIP_OK(hipMemcpyAsync(deps, in.eps, sizeof(double) * neps, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemsetAsync(drec, 0, nrec, s));
   HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
-  struct Ev {
-    hipEvent_t a = nullptr, b = nullptr;
-    ~Ev() {
-      if (a) (void)hipEventDestroy(a);
-      if (b) (void)hipEventDestroy(b);
-    }
-  } ev;
-  HIP_OK(hipEventCreate(&ev.a));
-  HIP_OK(hipEventCreate(&ev.b));
   {
     // a persistent launch: no more workgroups than stay resident at once
     // (the tuned waves per CU, nw waves per workgroup)
@@ -1329,7 +1369,7 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
         per_cu = std::min(per_cu, resident);
       const int max_wg = device_cu_count() * per_cu;
       const int grid = std::max(1, std::min(nt, max_wg));  // one trajectory per workgroup at a time
-      hipError_t e = hipEventRecord(ev.a, s);
+      hipError_t e = hipEventRecord(ev_a, s);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(64 * nwv), 0, s, dblocks, dsd, ns, n, tp.n_draws, djc,
                          dseed, dstream, dorder, nt, drounds, dp, deps, in.eps_stride, drec,
@@ -1342,7 +1382,7 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
     else HIP_OK(launch(k_batch_small<T, 1>, 1));
   }
   HIP_OK(hipGetLastError());
-  HIP_OK(hipEventRecord(ev.b, s));
+  HIP_OK(hipEventRecord(ev_b, s));
   int herr = 0;
   HIP_OK(hipMemcpyAsync(&herr, derr, sizeof herr, hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(in.records, drec, nrec, hipMemcpyDeviceToHost, s));
@@ -1350,7 +1390,7 @@ sv_status run_batch_core(BatchInputs& in, const Template& tp) {
   HIP_OK(hipStreamSynchronize(s));
   if (herr) return fail(SV_EINVAL, "circuit template is not monomial in its block basis");
   float ms = 0.f;
-  HIP_OK(hipEventElapsedTime(&ms, ev.a, ev.b));
+  HIP_OK(hipEventElapsedTime(&ms, ev_a, ev_b));
   in.gpu_ms = ms;
   return SV_OK;
 }
@@ -2199,7 +2239,7 @@ sv_status sv_run_rounds_async(const sv_job* job, sv_result* res, void* done_even
   return run_rounds_entry(job, res, (hipEvent_t)done_event);
 }
 
-sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res) {
+static sv_status check_batch_job(const sv_batch_job* job, const sv_batch_result* res) {
   if (!job || !res) return fail(SV_EINVAL, "NULL job or result");
   if (job->d < 2 || job->d > 4) return fail(SV_EINVAL, "d=%d out of 2..4", job->d);
   if (job->gateset != SV_GATESET_CR && job->gateset != SV_GATESET_TEXTBOOK)
@@ -2215,23 +2255,99 @@ sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res) {
       return fail(SV_EINVAL, "rounds[%d]=%d out of 1..%d", i, job->rounds[i], job->max_rounds);
     if (!(job->p[i] >= 0.0 && job->p[i] <= 1.0)) return fail(SV_EINVAL, "p[%d] out of [0, 1]", i);
   }
-  const Template tp = build_template(job->d, job->gateset);
+  const int n_sites = build_template(job->d, job->gateset).n_sites;
   if (job->eps_site)
-    for (size_t i = 0; i < (size_t)job->n_traj * tp.n_sites; ++i)
+    for (size_t i = 0; i < (size_t)job->n_traj * n_sites; ++i)
       if (!std::isfinite(job->eps_site[i])) return fail(SV_EINVAL, "non-finite eps_site");
+  return SV_OK;
+}
+
+// Per-trajectory seeds and draw streams of a batched job, and the inputs of
+// the batched kernels.
+struct BatchHost {
+  std::vector<uint64_t> seeds, streams;
+  std::vector<double> epsv;
+  BatchInputs in;
+  BatchHost(const sv_batch_job* job, sv_batch_result* res, const Template& tp)
+      : seeds((size_t)job->n_traj, job->seed), streams((size_t)job->n_traj) {
+    for (int i = 0; i < job->n_traj; ++i) streams[i] = job->traj0 + (uint64_t)i;
+    if (!job->eps_site) epsv.assign(std::max(1, tp.n_sites), job->eps);
+    in = BatchInputs{job->d, job->gateset, job->n_traj, job->max_rounds, job->zeta, seeds.data(),
+                     streams.data(), job->rounds, job->p, job->eps_site ? job->eps_site : epsv.data(),
+                     job->eps_site ? tp.n_sites : 0, res->records, res->final_bits,
+                     (hipStream_t)job->hip_stream, 0.0};
+  }
+};
+
+sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res) {
+  SV_OK_OR_RETURN(check_batch_job(job, res));
   res->gpu_ms = 0.0;
   if (job->n_traj == 0) return SV_OK;
-  const int nt = job->n_traj;
-  std::vector<uint64_t> seeds(nt, job->seed), streams(nt);
-  for (int i = 0; i < nt; ++i) streams[i] = job->traj0 + (uint64_t)i;
-  std::vector<double> epsv;
-  if (!job->eps_site) epsv.assign(std::max(1, tp.n_sites), job->eps);
-  BatchInputs in{job->d, job->gateset, nt, job->max_rounds, job->zeta, seeds.data(), streams.data(),
-                 job->rounds, job->p, job->eps_site ? job->eps_site : epsv.data(),
-                 job->eps_site ? tp.n_sites : 0, res->records, res->final_bits,
-                 (hipStream_t)job->hip_stream, 0.0};
-  const sv_status st = job->dtype == SV_C128 ? run_batch_core<double>(in, tp) : run_batch_core<float>(in, tp);
-  res->gpu_ms = in.gpu_ms;
+  const Template tp = build_template(job->d, job->gateset);
+  BatchHost h(job, res, tp);
+  const sv_status st =
+      job->dtype == SV_C128 ? run_batch_core<double>(h.in, tp) : run_batch_core<float>(h.in, tp);
+  res->gpu_ms = h.in.gpu_ms;
+  return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ no-allocation batched run
+// Every device buffer of sv_run_batch_noalloc comes from this array: each GPU
+// the library runs on holds one copy of it until the process ends.  In host
+// code its name is only a host-side stand-in; the device address of a GPU's
+// copy comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is handed to kernels and copies.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+struct NoAllocDevice {
+  std::once_flag once;
+  sv_status init_status = SV_OK;
+  std::string init_err;
+  void* ptr = nullptr;                    // this device's copy of `scratch`
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;  // timing of the launch
+  std::mutex mu;                          // one call at a time per device
+};
+NoAllocDevice g_noalloc[64];
+}  // namespace
+
+extern "C" {
+
+sv_status sv_run_batch_noalloc(const sv_batch_job* job, sv_batch_result* res) {
+  SV_OK_OR_RETURN(check_batch_job(job, res));
+  if (job->d > 3) return fail(SV_EINVAL, "the no-allocation batch covers d <= 3 (d=%d)", job->d);
+  const Template tp = build_template(job->d, job->gateset);
+  if (!batch_template_fits(tp) || !batch_is_small(tp, job->d))
+    return fail(SV_EINVAL, "block template too large for the batched path");
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(SV_EINVAL, "device %d out of range", dev);
+  NoAllocDevice& nd = g_noalloc[dev];
+  std::call_once(nd.once, [&nd] {
+    // this thread's current device is the one being set up
+    hipError_t e = hipGetSymbolAddress(&nd.ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) e = hipEventCreate(&nd.ev_a);
+    if (e == hipSuccess) e = hipEventCreate(&nd.ev_b);
+    if (e != hipSuccess || !nd.ptr) {
+      nd.init_status = SV_EDEVICE;
+      nd.init_err = std::string("no-allocation scratch set-up: ") + hipGetErrorString(e);
+    }
+  });
+  if (nd.init_status != SV_OK) return fail(nd.init_status, "%s", nd.init_err.c_str());
+  res->gpu_ms = 0.0;
+  if (job->n_traj == 0) return SV_OK;
+  std::lock_guard<std::mutex> lk(nd.mu);
+  BatchHost h(job, res, tp);
+  Arena A{static_cast<char*>(nd.ptr), kNoAllocScratchBytes, 0, false};
+  const sv_status st = job->dtype == SV_C128 ? run_batch_small<double>(h.in, tp, A, nd.ev_a, nd.ev_b)
+                                             : run_batch_small<float>(h.in, tp, A, nd.ev_a, nd.ev_b);
+  if (A.overflow)
+    return fail(SV_ENOMEM, "the job needs more than the %zu MiB no-allocation scratch",
+                kNoAllocScratchBytes >> 20);
+  res->gpu_ms = h.in.gpu_ms;
   return st;
 }
 
