@@ -62,31 +62,84 @@ def counted_traffic():
 
 
 _TUNING_FILE = None
-_TUNING_LOADED = False
+_TUNED = set()   # (d, dtype code) whose parameters came from the file or a tuning run
+
+
+def tuned_shapes(path):
+    """(d, dtype code) of the lines of a tuning file ("arch d dtype ...")."""
+    out = set()
+    with open(path) as f:
+        for line in f:
+            w = line.split()
+            if len(w) >= 3:
+                out.add((int(w[1]), int(w[2])))
+    return out
 
 
 def tune(qs, d, dtype, gateset="cr"):
-    """Launch parameters for (d, dtype): from the --tuning file when it
-    existed at start-up, else autotuned (and written to the file)."""
-    if _TUNING_LOADED:
+    """Launch parameters for (d, dtype): from the --tuning file when it holds
+    this shape, else autotuned (and added to the file)."""
+    key = (d, qs._DTYPES[dtype])
+    if key in _TUNED:
         return qs.tuning_get(d, dtype)
     best, _ = qs.autotune(d, dtype, gateset)
+    _TUNED.add(key)
     if _TUNING_FILE:
         qs.tuning_save(_TUNING_FILE)
     return best
 
 
-def cpu_baseline(c, eps, n_blocks):
-    """Oracle (complex128, gate by gate on 26 qubits) on the first n_blocks
-    noisy circuits of a round; scaled to ms per 24-circuit round."""
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def oracle_trajectory_rate(workload, threads):
+    """The oracle's trajectories/s on a small-distance workload, trajectory-
+    parallel over `threads` host threads with single-threaded amplitude loops
+    (a child process, so the OpenMP setting is its own)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "oracle.timing", workload, "--threads", str(threads)],
+                       cwd=ROOT, env=env, capture_output=True, text=True, check=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(c, eps, st_blocks=2):
+    """The oracle (complex128, gate by gate on the 26-qubit register) timed on
+    the host: one whole noisy round of the d=5 workload on every core
+    (amplitude-parallel), a single-threaded sample of an X and a Z check
+    scaled to a round, and the small-distance workloads trajectory-parallel
+    (d=3 textbook: 1000 trajectories; batched d=4: 64 trajectories)."""
     import oracle
-    sec, threads = oracle.time_blocks(c["d"], oracle.GATESET_CR, c["seed"], 0, c["p"], n_blocks,
-                                      zeta=c["zeta"], eps_site=eps)
+    cores = host_cores()
     n_stab = c["d"] ** 2 - 1
-    ms_round = sec * 1e3 * n_stab / n_blocks
-    return {"value": ms_round, "unit": "ms/round", "cores": threads, "kind": "oracle",
-            "sample": f"{n_blocks} of the {n_stab} noisy stabilizer circuits of round 1 "
-                      f"(26 qubits, complex128, gate by gate), {sec:.1f} s, scaled to one round"}
+    oracle.set_threads(cores)
+    sec, threads = oracle.time_blocks(c["d"], oracle.GATESET_CR, c["seed"], 0, c["p"], n_stab,
+                                      zeta=c["zeta"], eps_site=eps)
+    # single thread: the last X check and the first Z check of the round
+    oracle.set_threads(1)
+    first = n_stab // 2 - st_blocks // 2
+    sec1, _ = oracle.time_blocks(c["d"], oracle.GATESET_CR, c["seed"], 0, c["p"], st_blocks,
+                                 zeta=c["zeta"], eps_site=eps, first=first)
+    oracle.set_threads(cores)
+    d3 = oracle_trajectory_rate("d3", cores)
+    d3_1 = oracle_trajectory_rate("d3", 1)
+    d4 = oracle_trajectory_rate("d4", cores)
+    return {"value": sec * 1e3, "unit": "ms/round", "cores": threads, "kind": "oracle",
+            "sample": f"one whole noisy round (all {n_stab} stabilizer circuits, 26 qubits, complex128, "
+                      f"gate by gate) of the d=5 workload, {sec:.1f} s on {threads} threads",
+            "single_thread": {"value": sec1 * 1e3 * n_stab / st_blocks, "unit": "ms/round", "cores": 1,
+                              "sample": f"circuits {first + 1}..{first + st_blocks} of the round "
+                                        f"(X and Z checks), {sec1:.1f} s, scaled to {n_stab} circuits"},
+            "d3_textbook": {"trajectories_per_s": d3["trajectories_per_s"], "cores": d3["threads"],
+                            "trajectories_per_s_1_core": d3_1["trajectories_per_s"],
+                            "sample": "the whole d=3 textbook workload (1000 trajectories, 3 rounds)"},
+            "d4_batch": {"trajectories_per_s": d4["trajectories_per_s"], "cores": d4["threads"],
+                         "trajectory_rounds_per_s": d4["trajectory_rounds"] / d4["seconds"],
+                         "sample": "64 trajectories of the batched d=4 workload"}}
 
 
 def copy_calibration(qs, torch, steps):
@@ -172,35 +225,50 @@ def gate_run(qs, torch, reps=10):
 def serving_run(qs, kind, window_s, horizon_s, budget_gib=256):
     """Replay a Poisson job stream against the server in real time; at
     `horizon_s` cancel what is left.  Latency = completion - submission on the
-    server clock (queueing included)."""
+    server clock (queueing included).  Jobs still unfinished at the horizon
+    are counted as censored at (horizon - submission): percentiles over the
+    completed jobs alone understate the tail, the ones with the censored
+    values included are lower bounds of the true percentiles."""
     import numpy as np
     import workloads
     stream = workloads.serving_stream(window_s, seed=2, companion=(kind == "companion"),
                                       n_sites=lambda d: qs.template_info(d, "cr")[1])
     srv = qs.Server(hbm_budget=budget_gib << 30, big_streams=2, max_batch_traj=65536)
     done, t0 = [], time.perf_counter()
-    meta = {}
+    meta, submitted = {}, {}
     for arr, job in stream:
         while time.perf_counter() - t0 < arr:
             done += srv.poll()
             time.sleep(0.0005)
         srv.submit(**job)
+        submitted[job["tag"]] = srv.clock()
         meta[job["tag"]] = job
     while time.perf_counter() - t0 < horizon_s and len(done) < len(stream):
         done += srv.poll()
         time.sleep(0.002)
+    t_end = srv.clock()
+    done += srv.poll()
     stats = srv.stats()
     srv.close(cancel=True)
-    ok = [c for c in done if c["status"] == 0]
+    ok = [c for c in done if c["status"] == 0 and c["t_done"] <= t_end]
     lat = np.array([c["t_done"] - c["t_submit"] for c in ok]) * 1e3
+    finished = {c["tag"] for c in ok}
+    cens = np.array([t_end - submitted[t] for t in meta if t not in finished]) * 1e3
+    allv = np.concatenate([lat, cens])
     traj_rounds = sum(meta[c["tag"]]["n_traj"] * meta[c["tag"]]["rounds"] for c in ok)
+    alg_bytes = sum(meta[c["tag"]]["n_traj"] * (meta[c["tag"]]["rounds"] * (meta[c["tag"]]["d"] ** 2 - 1) + 1)
+                    * 2 * (1 << meta[c["tag"]]["d"] ** 2) * (16 if meta[c["tag"]]["dtype"] == "c128" else 8)
+                    for c in ok)
     by_d = {d: int(sum(1 for c in ok if meta[c["tag"]]["d"] == d)) for d in (3, 4, 5)}
+    pct = lambda v, q: float(np.percentile(v, q)) if v.size else None
     return {"stream": kind, "arrival_window_s": window_s, "horizon_s": horizon_s,
             "jobs_offered": len(stream), "jobs_completed": len(ok), "completed_by_d": by_d,
             "backlog_at_horizon": len(stream) - len(ok),
-            "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
-            "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
-            "trajectory_rounds_per_s": traj_rounds / horizon_s,
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+            "p50_ms_with_censored_lower_bound": pct(allv, 50),
+            "p99_ms_with_censored_lower_bound": pct(allv, 99),
+            "trajectory_rounds_per_s": traj_rounds / t_end,
+            "per_circuit_equivalent_gbs_completed": alg_bytes / t_end / 1e9,
             "launches": stats["launches"], "hbm_high_water_gib": stats["hbm_high_water"] / (1 << 30)}
 
 
@@ -214,10 +282,21 @@ def batch_run(qs, d, n_traj, dtype, seed=7):
     qs.run_batch(d, "cr", R[:256], p[:256], seed, eps_site=eps[:256], dtype=dtype)
     g = qs.run_batch(d, "cr", R, p, seed, eps_site=eps, dtype=dtype, max_rounds=9)
     amp = 8 if dtype == "c64" else 16
-    alg = (int(R.sum()) * n_stab + n_traj) * 2 * (1 << (d * d)) * amp
-    return {"d": d, "trajectories": n_traj, "dtype": dtype, "launch_ms": g["gpu_ms"],
-            "trajectories_per_s": n_traj / (g["gpu_ms"] * 1e-3),
-            "alg_gbs": alg / (g["gpu_ms"] * 1e-3) / 1e9, "tuning": tuning}
+    reg = 2 * (1 << (d * d)) * amp          # one read + one write of a register
+    alg = (int(R.sum()) * n_stab + n_traj) * reg
+    out = {"d": d, "trajectories": n_traj, "dtype": dtype, "launch_ms": g["gpu_ms"],
+           "trajectories_per_s": n_traj / (g["gpu_ms"] * 1e-3),
+           "per_circuit_equivalent_gbs": alg / (g["gpu_ms"] * 1e-3) / 1e9, "tuning": tuning}
+    if d == 4:
+        # registers in HBM: one pass per X check and per chain of Z checks
+        n_x = (n_stab + 1) // 2            # X checks of the d=4 layout (8 of 15)
+        n_z = n_stab - n_x
+        passes = n_x + -(-n_z // tuning["zchain"])
+        moved = (int(R.sum()) * passes + n_traj) * reg
+        out["passes_per_round"] = passes
+        out["hbm_gbs_moved"] = moved / (g["gpu_ms"] * 1e-3) / 1e9
+        out["hbm_frac_moved"] = out["hbm_gbs_moved"] / PEAK_HBM_GBS
+    return out
 
 
 def d3_textbook_run(qs):
@@ -243,40 +322,53 @@ def d3_textbook_run(qs):
     t = float(np.median(ms))
     alg = (R * n_stab + 1) * 2 * (1 << (d * d)) * 16 * n
     return {"workload": "d3_textbook_c128", "trajectories": n, "launch_ms": t,
-            "trajectories_per_s": n / (t * 1e-3), "alg_gbs": alg / (t * 1e-3) / 1e9,
-            "frac_of_hbm_peak": alg / (t * 1e-3) / 1e9 / PEAK_HBM_GBS, "tuning": tuning}
+            "trajectories_per_s": n / (t * 1e-3), "per_circuit_equivalent_gbs": alg / (t * 1e-3) / 1e9,
+            "per_circuit_equivalent_frac": alg / (t * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "registers_in": "LDS", "tuning": tuning}
 
 
-def precision_run(qs, n_traj, thetas=(0.01, 0.03, 0.05)):
+def precision_run(qs, n_state, n_stat, thetas=(0.01, 0.03, 0.05)):
     """Complex64 amplitudes (FP64 probabilities and renormalisation) against
     complex128 on the same draws: d=5 cross-resonance circuit, p=1e-3,
     zeta=0.01, 5 rounds, every site over-rotated by theta (eps = theta/2).
-    Infidelity 1 - |<psi64|psi128>|^2 of the register before the final
-    measurement, per trajectory."""
+    The complex128 engine is the reference: it matches the oracle's register
+    to 1e-10.  Per angle: the infidelity 1 - |<psi64|psi128>|^2 of the
+    register before the final measurement for n_state trajectories; over
+    n_stat trajectories the number whose records differ and the logical
+    error rates of both types, decoded with the library's sv_decode_z, with
+    the paired standard error of their difference (sqrt of the discordant
+    trajectories / n) and the trajectories whose minimum-weight matchings
+    disagree on the logical (ambiguous)."""
     import numpy as np
-    from oracle import decoder
     out = []
+    kw = dict(d=5, gateset="cr", rounds=5, seed=1, p=1e-3, zeta=0.01)
     for theta in thetas:
-        inf, div = [], 0
-        recs = {"c64": [], "c128": []}
-        fins = {"c64": [], "c128": []}
-        for t in range(n_traj):
-            st = {}
-            for dt in ("c128", "c64"):
-                r = qs.run_rounds(5, "cr", 5, 1, seed=1, p=1e-3, eps=theta / 2, zeta=0.01, dtype=dt,
-                                  traj0=t, want_states=True)
-                st[dt] = r["states"][0]
-                recs[dt].append(r["records"][0])
-                fins[dt].append(r["final_bits"][0])
-            a = st["c64"].astype(np.complex128)
-            b = st["c128"]
-            inf.append(1.0 - abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real))
-            div += int(not np.array_equal(recs["c64"][-1], recs["c128"][-1]))
-        pl = {dt: decoder.logical_error_rate(5, 0, np.array(recs[dt]), np.array(fins[dt]))[0]
-              for dt in recs}
-        out.append({"theta": theta, "trajectories": n_traj, "infidelity_max": float(max(inf)),
-                    "infidelity_mean": float(np.mean(inf)), "diverged_trajectories": div,
-                    "p_L_c64": pl["c64"], "p_L_c128": pl["c128"], "delta_p_L": pl["c64"] - pl["c128"]})
+        inf = []
+        for t0 in range(0, n_state, 5):
+            k = min(5, n_state - t0)
+            a = qs.run_rounds(n_traj=k, traj0=t0, eps=theta / 2, dtype="c64", want_states=True, **kw)
+            b = qs.run_rounds(n_traj=k, traj0=t0, eps=theta / 2, dtype="c128", want_states=True, **kw)
+            for i in range(k):
+                x = a["states"][i].astype(np.complex128)
+                y = b["states"][i]
+                inf.append(1.0 - abs(np.vdot(x, y)) ** 2 / (np.vdot(x, x).real * np.vdot(y, y).real))
+            del a, b
+        runs = {dt: qs.run_rounds(n_traj=n_stat, traj0=0, eps=theta / 2, dtype=dt, **kw)
+                for dt in ("c64", "c128")}
+        dec = {dt: qs.decode_z(5, "cr", r["records"], r["final_bits"]) for dt, r in runs.items()}
+        f64, f128 = dec["c64"]["failed"].astype(int), dec["c128"]["failed"].astype(int)
+        div = int(np.sum(np.any(runs["c64"]["records"] != runs["c128"]["records"], axis=(1, 2))
+                         | np.any(runs["c64"]["final_bits"] != runs["c128"]["final_bits"], axis=1)))
+        pl = {dt: float(np.mean(dec[dt]["failed"] == 1)) for dt in dec}
+        disc = int(np.sum(f64 != f128))
+        out.append({"theta": theta, "reference": "complex128 engine (matches the oracle to 1e-10)",
+                    "trajectories_infidelity": n_state, "infidelity_max": float(max(inf)),
+                    "infidelity_mean": float(np.mean(inf)),
+                    "trajectories_stats": n_stat, "diverged_trajectories": div,
+                    "p_L_c64": pl["c64"], "p_L_c128": pl["c128"], "delta_p_L": pl["c64"] - pl["c128"],
+                    "delta_p_L_sigma_paired": float(np.sqrt(disc) / n_stat),
+                    "p_L_sigma_binomial": float(np.sqrt(pl["c128"] * (1 - pl["c128"]) / n_stat)),
+                    "ambiguous_c128": int(np.sum(dec["c128"]["ambiguous"])), "decoder": "sv_decode_z"})
     return out
 
 
@@ -286,7 +378,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
-    ap.add_argument("--cpu-blocks", type=int, default=6)
+    ap.add_argument("--cpu-blocks", type=int, default=2,
+                    help="circuits in the oracle's single-threaded d=5 sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="time only the library's plain register copy (HBM calibration)")
@@ -294,8 +387,10 @@ def main():
                     help="run one side measurement alone and print it (for profiling)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-launch, serving and precision measurements")
-    ap.add_argument("--precision-traj", type=int, default=4,
-                    help="trajectories per angle in the complex64 vs complex128 comparison")
+    ap.add_argument("--precision-traj", type=int, default=20,
+                    help="trajectories per angle for the complex64 vs complex128 infidelity")
+    ap.add_argument("--precision-stat-traj", type=int, default=500,
+                    help="trajectories per angle for diverged records and the p_L difference")
     ap.add_argument("--tuning", default=None,
                     help="launch-parameter file: load it instead of autotuning if it exists, "
                          "else autotune and write it (profiled runs then contain no trials)")
@@ -309,11 +404,11 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
-    global _TUNING_FILE, _TUNING_LOADED
+    global _TUNING_FILE
     _TUNING_FILE = args.tuning
     if args.tuning and os.path.exists(args.tuning):
         qs.tuning_load(args.tuning)
-        _TUNING_LOADED = True
+        _TUNED.update(tuned_shapes(args.tuning))
     if args.copy_only:
         copy_calibration(qs, torch, args.steps)
         return
@@ -331,7 +426,7 @@ def main():
         print(json.dumps({"serving": [serving_run(qs, "companion", 5.0, 8.0)]}))
         return
     if args.only == "precision":
-        print(json.dumps({"precision": precision_run(qs, args.precision_traj)}))
+        print(json.dumps({"precision": precision_run(qs, args.precision_traj, args.precision_stat_traj)}))
         return
     c = dict(workloads.CONFIGS["d5_cr_c128"])
     d, R = c["d"], c["rounds"]
@@ -353,7 +448,11 @@ def main():
     blk_bytes = 2 * (1 << (d * d)) * amp_bytes          # read + write of the live register
     rounds_total = args.steps * R
     ms_round = wall * 1e3 / rounds_total
-    alg_gbs = n_stab * blk_bytes / (ms_round * 1e-3) / 1e9
+    # per-circuit equivalent: the bytes a pass per stabilizer circuit would
+    # move, over the measured time (above the HBM peak when passes chain
+    # several circuits); moved: what the passes do move (one read and one
+    # write per pass, the initial write and the final read per trajectory)
+    per_circuit_gbs = n_stab * blk_bytes / (ms_round * 1e-3) / 1e9
     pass_ms = r["pass_ms"]
     achieved = blk_bytes / (pass_ms * 1e-3) / 1e9   # one read + one write per pass
     out = {
@@ -373,9 +472,8 @@ def main():
                                "gates, p=1e-3, theta~U[0,0.05) per site, zeta=0.01, 5 rounds",
                    "state": args.dtype, "trajectories_per_step": 1, "rounds": R,
                    "stabilizers_per_round": n_stab},
-        # per-circuit byte model (one read + write of the register per
-        # stabilizer circuit); exceeds the bytes moved when passes apply chains
-        "hbm_gbs_algorithmic": alg_gbs,
+        "per_circuit_equivalent_gbs": per_circuit_gbs,
+        "hbm_gbs_moved": (R * r["passes_per_round"] + 1) * blk_bytes / (ms_round * R * 1e-3) / 1e9,
         "tuning": tuning,
         "kernel_sources_sha256": kernel_source_hash(),
         "gpu_ms_device": r["gpu_ms"],
@@ -391,9 +489,13 @@ def main():
         out["d3"] = d3_textbook_run(qs)
         out["d3_trajectories_per_s"] = out["d3"]["trajectories_per_s"]
         out["batched"] = [batch_run(qs, 3, 65536, "c64"), batch_run(qs, 4, 4096, "c64")]
-        out["serving"] = [serving_run(qs, "companion", 5.0, 8.0), serving_run(qs, "spec", 2.0, 4.0)]
-        out["p99_latency_ms"] = out["serving"][0]["p99_ms"]
-        out["precision"] = precision_run(qs, args.precision_traj)
+        out["serving"] = [serving_run(qs, "companion", 5.0, 8.0), serving_run(qs, "spec", 10.0, 12.0)]
+        # the companion stream (d=4 jobs with a tenth of their trajectories,
+        # d=5 jobs with one) fits one GPU; the stream as specified offers far
+        # more work than one GPU can do and only bounds its tail from below
+        out["p99_latency_ms_companion"] = out["serving"][0]["p99_ms"]
+        out["p99_latency_ms_spec_lower_bound"] = out["serving"][1]["p99_ms_with_censored_lower_bound"]
+        out["precision"] = precision_run(qs, args.precision_traj, args.precision_stat_traj)
         out["fused"] = fused_run(qs, torch)
         out["gates"] = gate_run(qs, torch)
     if not args.no_cpu_baseline:

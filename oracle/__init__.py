@@ -98,6 +98,11 @@ def _load(path):
     L.orc_apply_gate.restype = ctypes.c_int
     L.orc_time_blocks.argtypes = [ctypes.POINTER(_Job), ctypes.c_ulonglong, ctypes.c_int, ip]
     L.orc_time_blocks.restype = ctypes.c_double
+    L.orc_time_block_range.argtypes = [ctypes.POINTER(_Job), ctypes.c_ulonglong, ctypes.c_int,
+                                       ctypes.c_int, ip]
+    L.orc_time_block_range.restype = ctypes.c_double
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    L.orc_set_threads.restype = None
     return L
 
 
@@ -216,9 +221,14 @@ def apply_gate_cpp(state, qubits, m):
     return s
 
 
-def time_blocks(d, gateset, seed, t, p, n_blocks, zeta=0.0, eps=0.0, eps_site=None):
-    """Wall time (s) of the first n_blocks noisy circuits of a round, and the
-    OpenMP thread count used."""
+def set_threads(n):
+    """OpenMP threads of the oracle's amplitude loops from now on."""
+    lib().orc_set_threads(int(n))
+
+
+def time_blocks(d, gateset, seed, t, p, n_blocks, zeta=0.0, eps=0.0, eps_site=None, first=0):
+    """Wall time (s) of n_blocks noisy circuits of the round template from
+    circuit `first` on, and the OpenMP thread count used."""
     job = _Job()
     job.d, job.gateset, job.rounds = d, gateset, 1
     job.seed, job.p, job.zeta, job.eps = int(seed), float(p), float(zeta), float(eps)
@@ -227,7 +237,8 @@ def time_blocks(d, gateset, seed, t, p, n_blocks, zeta=0.0, eps=0.0, eps_site=No
         keep = np.ascontiguousarray(eps_site, dtype=np.float64)
         job.eps_site = _ptr(keep, ctypes.c_double)
     th = ctypes.c_int()
-    sec = lib().orc_time_blocks(ctypes.byref(job), int(t), int(n_blocks), ctypes.byref(th))
+    sec = lib().orc_time_block_range(ctypes.byref(job), int(t), int(first), int(n_blocks),
+                                     ctypes.byref(th))
     del keep
     if sec < 0:
         raise ValueError("bad arguments")

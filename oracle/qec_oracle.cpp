@@ -639,20 +639,28 @@ int run_trajectory(const Job& job, uint64_t t, const Output& out) {
   return 0;
 }
 
-// Number of gate sites (rotation gates carrying over-rotation) and of random
-// draws in one round.
+// Gate sites (rotation gates carrying over-rotation) and random draws of one
+// stabilizer circuit with the default noise options.
+void block_counts(int gateset, const Stab& st, int* sites, int* draws) {
+  const int w = weight(st);
+  if (gateset == 0) {
+    if (st.type == 0) { *sites = 2 + 2 * w; *draws = 1 + 4 + 1 + w + 1; }
+    else { *sites = 2 * w; *draws = 4 + w + 1; }
+  } else {
+    *sites = 2;
+    *draws = 1 + w + 1 + 1;
+  }
+}
+
+// Number of gate sites and of random draws in one round.
 void template_counts(int d, int gateset, int* n_stab, int* n_sites, int* n_draws) {
   const std::vector<Stab> stabs = build_layout(d);
   int sites = 0, draws = 0;
   for (const Stab& st : stabs) {
-    const int w = weight(st);
-    if (gateset == 0) {
-      if (st.type == 0) { sites += 2 + 2 * w; draws += 1 + 4 + 1 + w + 1; }
-      else { sites += 2 * w; draws += 4 + w + 1; }
-    } else {
-      sites += 2;
-      draws += 1 + w + 1 + 1;
-    }
+    int a, b;
+    block_counts(gateset, st, &a, &b);
+    sites += a;
+    draws += b;
   }
   *n_stab = (int)stabs.size();
   *n_sites = sites;
@@ -749,23 +757,34 @@ int orc_apply_gate(double* state, int n, int k, const int* qubits, const double*
   return 0;
 }
 
-// Benchmark sample: run the first n_blocks noisy stabilizer circuits of round
-// 1 (gates, noise, ZZ layer, measurement and reset) from |0...0> and return the
-// wall time in seconds; *threads receives the OpenMP thread count.  The cost
-// of a circuit does not depend on the state, so this times the same work as
-// the corresponding part of a trajectory.
-double orc_time_blocks(const orc_job* j, unsigned long long t, int n_blocks, int* threads) {
-  if (!j || j->d < 2 || j->d > 5 || n_blocks < 1) return -1.0;
+// Benchmark sample: run n_blocks noisy stabilizer circuits of the round
+// template starting at circuit `first` (gates, noise, ZZ layer, measurement
+// and reset; default noise options) from |0...0> and return the wall time in
+// seconds; *threads receives the OpenMP thread count.  The cost of a circuit
+// does not depend on the state, so this times the same work as the
+// corresponding part of a trajectory.
+double orc_time_block_range(const orc_job* j, unsigned long long t, int first, int n_blocks,
+                            int* threads) {
+  if (!j || j->d < 2 || j->d > 5 || n_blocks < 1 || first < 0) return -1.0;
+  if (j->twirl || j->idle || j->zzp) return -1.0;
   Job job{j->d,     j->gateset, 1,         j->seed,   j->p,         j->zeta,
-          j->eps_site, j->eps,     j->twirl, j->xbasis, j->virtual_z, j->idle, j->zzp, 0};
+          j->eps_site, j->eps,     0,        j->xbasis, j->virtual_z, 0,       0, 0};
   const int d = job.d, anc = d * d;
   const std::vector<Stab> stabs = build_layout(d);
+  const int ns = (int)stabs.size();
   State s(d * d + 1);
   Ctx cx{&job, t, 0, true, 0};
+  // sites and draws of the circuits before `first` (within its round)
+  for (int i = 0; i < first % ns; ++i) {
+    int a, b;
+    block_counts(job.gateset, stabs[i], &a, &b);
+    cx.site += a;
+    cx.k += (uint64_t)b;
+  }
   const auto t0 = std::chrono::steady_clock::now();
-  for (int i = 0; i < n_blocks; ++i) {
-    const Stab& st = stabs[i % stabs.size()];
-    if (i % stabs.size() == 0) cx.site = 0;
+  for (int i = first; i < first + n_blocks; ++i) {
+    const Stab& st = stabs[i % ns];
+    if (i % ns == 0) cx.site = 0;
     run_stabilizer_gates(s, cx, st, anc);
     if (job.zeta != 0.0) zz_layer(s, d, job.zeta);
     double S0, S1;
@@ -785,6 +804,19 @@ double orc_time_blocks(const orc_job* j, unsigned long long t, int n_blocks, int
 #endif
   }
   return std::chrono::duration<double>(t1 - t0).count();
+}
+
+double orc_time_blocks(const orc_job* j, unsigned long long t, int n_blocks, int* threads) {
+  return orc_time_block_range(j, t, 0, n_blocks, threads);
+}
+
+// OpenMP threads of the amplitude loops from now on (n >= 1).
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }
 
 }  // extern "C"
