@@ -663,13 +663,14 @@ __device__ __forceinline__ void chain_tree(double a2, const uint32_t* x,
 // AP: weight of an X check A, or the length of a Z chain A (BP likewise).
 // DN: the instantiation that also handles dense Kraus pairs (kept apart so
 // that the dense code does not weigh on the other passes' registers).
-// Occupancy of a pass kernel: complex128 passes other than the dense ones and
-// those summing a Z chain of three or four checks fit 168 registers without
-// spilling, i.e. three waves per SIMD (measured on d=5: X-check passes
-// 200 -> 186 us); the others keep the registers they need.
+// Occupancy of a pass kernel: passes other than the dense ones and those
+// summing a Z chain of four checks are held to 168 registers, i.e. three
+// waves per SIMD (measured on d=5: complex128 X-check passes 200 -> 186 us);
+// the others keep the registers they need (a chain of four needs about 205 in
+// complex128 and spills 160 bytes per lane at 168).
 template <typename T, int BK, int BP, bool DN>
 struct UpassWaves {
-  static constexpr int value = (sizeof(T) == 8 && !DN && !(BK == U_Z && BP >= 3)) ? 3 : 1;
+  static constexpr int value = (!DN && !(BK == U_Z && BP >= 4)) ? 3 : 1;
 };
 
 template <typename T, int AK, int AP, int BK, int BP, bool DN>
@@ -810,9 +811,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   // grid-stride over the tiles (one tile per workgroup when the grid covers
   // them all); the tables above are loaded once per workgroup, the sums of B
   // accumulate over the workgroup's tiles
-  double acc[32];
+  // Z chains of three or four checks (14 or 30 sums): the tile's sums are
+  // reduced across the wave at once and each lane keeps one running total
+  // (lanes 2a, 2a + 1: sum a), so no 30-value accumulator stays live through
+  // the next tile's loads and transforms
+  constexpr bool kWaveAcc = BK == U_Z && LB >= 3;
+  double acc[kWaveAcc ? 1 : 32];
 #pragma unroll
-  for (int a = 0; a < 32; ++a) acc[a] = 0.0;
+  for (int a = 0; a < (kWaveAcc ? 1 : 32); ++a) acc[a] = 0.0;
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
   const int wg = reverse ? n_tiles - 1 - tile : tile;
   uint32_t base = 0;
@@ -995,6 +1001,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
     }
   }
   if constexpr (BK == U_Z) {
+    // this tile's sums (kWaveAcc) or the running per-thread sums
+    double tt_[kWaveAcc ? 32 : 1];
+    double* tt = kWaveAcc ? tt_ : acc;
+    if constexpr (kWaveAcc) {
+#pragma unroll
+      for (int a = 0; a < 32; ++a) tt_[a] = 0.0;
+    }
     double a2[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -1012,7 +1025,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
           uint32_t x[kChainMax];
 #pragma unroll
           for (int i = 0; i < kChainMax; ++i) x[i] = ob[i] ^ pd->b_j_loc[i][j];
-          chain_tree<LB>(a2[j], x, wt, acc);
+          chain_tree<LB>(a2[j], x, wt, tt);
         }
       }
     } else {
@@ -1032,9 +1045,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
 #pragma unroll
         for (int i = 0; i < kChainMax; ++i)
           x[i] = i < lb ? gather_loc(g2, pd->bq[i], pd->bw[i]) ^ cb[i] : 0u;
-        chain_tree<LB>(s, x, wt, acc);
+        chain_tree<LB>(s, x, wt, tt);
       }
     }
+    if constexpr (kWaveAcc) acc[0] += wave_reduce32(tt_);
   }
   __syncthreads();  // LDS buffers are reused by the next tile
   }
@@ -1048,6 +1062,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
         const double s = wave_sum(acc[a]);
         if (lane == 0) red[a][wid] = s;
       }
+    } else if constexpr (kWaveAcc) {
+      if ((lane & 1) == 0 && (lane >> 1) < nacc) red[lane >> 1][wid] = acc[0];
     } else {
       const double s = wave_reduce32(acc);
       if ((lane & 1) == 0 && (lane >> 1) < nacc) red[lane >> 1][wid] = s;
