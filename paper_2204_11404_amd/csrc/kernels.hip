@@ -130,8 +130,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Wave totals of 32 per-lane values in 32 shuffles (a reduce-scatter: each
 // step hands half of the remaining values to the partner lane): afterwards
 // lanes 2a and 2a + 1 hold the wave total of value a.  Fixed order.
-template <int K>
-__device__ __forceinline__ void reduce_half(double (&v)[32]) {
+template <int K, int N>
+__device__ __forceinline__ void reduce_half(double (&v)[N]) {
   const bool up = (threadIdx.x & (2 * K)) != 0;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
@@ -147,6 +147,16 @@ __device__ __forceinline__ double wave_reduce32(double (&v)[32]) {
   reduce_half<2>(v);
   reduce_half<1>(v);
   return v[0] + __shfl_xor(v[0], 1, 64);
+}
+// The same for 16 values: afterwards every lane l holds the wave total of
+// value (l >> 1) & 15.
+__device__ __forceinline__ double wave_reduce16(double (&v)[16]) {
+  reduce_half<8>(v);
+  reduce_half<4>(v);
+  reduce_half<2>(v);
+  reduce_half<1>(v);
+  const double r = v[0] + __shfl_xor(v[0], 1, 64);
+  return r + __shfl_xor(r, 32, 64);
 }
 
 // Deterministic block reduction of two doubles (fixed order).  `scratch`
@@ -651,6 +661,32 @@ __device__ __forceinline__ void chain_tree(double a2, const uint32_t* x,
   }
 }
 
+// Levels L0..L1-1 of the same tree: sum (l, h) goes to out[2^(l+1) - 2^(L0+1)
+// + h] (the prefix products of the lower levels are formed again).
+template <int L0, int L1>
+__device__ __forceinline__ void chain_levels(double a2, const uint32_t* x, const double (*wt)[2][16],
+                                             double* out) {
+  double pre[8];
+  pre[0] = a2;
+#pragma unroll
+  for (int l = 0; l < L1; ++l) {
+    const double w0 = wt[l][0][x[l]], w1 = wt[l][1][x[l]];
+    const int off = (2 << l) - (2 << L0);
+#pragma unroll
+    for (int h = 0; h < (1 << l); ++h) {
+      const double p0 = pre[h] * w0, p1 = pre[h] * w1;
+      if (l >= L0) {
+        out[off + h] += p0;
+        out[off + h + (1 << l)] += p1;
+      }
+      if (l + 1 < L1) {
+        pre[h] = p0;
+        pre[h + (1 << l)] = p1;
+      }
+    }
+  }
+}
+
 // One pass over the register: apply unit A with its decided outcomes (or
 // write logical |0> when A is U_INIT), each member's ZZ layer and the
 // renormalisation 1/sqrt(S_m); accumulate the sums of unit B from the values
@@ -663,14 +699,14 @@ __device__ __forceinline__ void chain_tree(double a2, const uint32_t* x,
 // AP: weight of an X check A, or the length of a Z chain A (BP likewise).
 // DN: the instantiation that also handles dense Kraus pairs (kept apart so
 // that the dense code does not weigh on the other passes' registers).
-// Occupancy of a pass kernel: passes other than the dense ones and those
-// summing a Z chain of four checks are held to 168 registers, i.e. three
-// waves per SIMD (measured on d=5: complex128 X-check passes 200 -> 186 us);
-// the others keep the registers they need (a chain of four needs about 205 in
-// complex128 and spills 160 bytes per lane at 168).
+// Occupancy of a pass kernel: passes other than the dense ones are held to
+// 168 registers, i.e. three waves per SIMD (measured on d=5: complex128
+// X-check passes 200 -> 186 us; a complex128 pass summing a Z chain of four
+// then keeps 16-24 bytes per lane in scratch); the dense ones keep the
+// registers they need.
 template <typename T, int BK, int BP, bool DN>
 struct UpassWaves {
-  static constexpr int value = (!DN && !(BK == U_Z && BP >= 4)) ? 3 : 1;
+  static constexpr int value = !DN ? 3 : 1;
 };
 
 template <typename T, int AK, int AP, int BK, int BP, bool DN>
@@ -811,14 +847,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   // grid-stride over the tiles (one tile per workgroup when the grid covers
   // them all); the tables above are loaded once per workgroup, the sums of B
   // accumulate over the workgroup's tiles
-  // Z chains of three or four checks (14 or 30 sums): the tile's sums are
-  // reduced across the wave at once and each lane keeps one running total
-  // (lanes 2a, 2a + 1: sum a), so no 30-value accumulator stays live through
-  // the next tile's loads and transforms
+  // Z chains of three or four checks (14 or 30 sums): the tile's sums of
+  // levels 0..2 (14) and of level 3 (16) are formed and reduced across the
+  // wave one group at a time; each lane keeps one running total per group
+  // (lane l: sum (l >> 1) & 15 of the group), so neither 30 accumulators nor
+  // a 30-value tree stays live
   constexpr bool kWaveAcc = BK == U_Z && LB >= 3;
-  double acc[kWaveAcc ? 1 : 32];
+  double acc[kWaveAcc ? 2 : 32];
 #pragma unroll
-  for (int a = 0; a < (kWaveAcc ? 1 : 32); ++a) acc[a] = 0.0;
+  for (int a = 0; a < (kWaveAcc ? 2 : 32); ++a) acc[a] = 0.0;
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
   const int wg = reverse ? n_tiles - 1 - tile : tile;
   uint32_t base = 0;
@@ -1001,54 +1038,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
     }
   }
   if constexpr (BK == U_Z) {
-    // this tile's sums (kWaveAcc) or the running per-thread sums
-    double tt_[kWaveAcc ? 32 : 1];
-    double* tt = kWaveAcc ? tt_ : acc;
-    if constexpr (kWaveAcc) {
-#pragma unroll
-      for (int a = 0; a < 32; ++a) tt_[a] = 0.0;
-    }
     double a2[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const double re = (double)o[j].re, im = (double)o[j].im;
       a2[j] = active ? re * re + im * im : 0.0;
     }
-    if (pd->bmode == 0) {
-      if (active) {
-        uint32_t ob[kChainMax];
+    // the chain's local indices of each amplitude (bmode 0), or of the
+    // thread's 16 amplitudes together with their norm (bmode 1, 2)
+    double s = 0.0;
+    uint32_t g2 = gb;
+    if (pd->bmode == 1) {
 #pragma unroll
-        for (int i = 0; i < kChainMax; ++i)
-          ob[i] = i < lb ? gather_loc(gb, pd->bq[i], pd->bw[i]) ^ cb[i] : 0u;
+      for (int j = 0; j < 16; ++j) s += a2[j];
+    } else if (pd->bmode == 2) {
+      s = xpose_norms(a2, lt, pd, active);
+      g2 = base;
+      for (int i = 0; i < tb - 4; ++i)
+        if ((tid >> i) & 1) g2 |= pd->b_tid_g[i];
+    }
+    uint32_t ob[kChainMax];
+#pragma unroll
+    for (int i = 0; i < kChainMax; ++i) ob[i] = i < lb ? gather_loc(g2, pd->bq[i], pd->bw[i]) ^ cb[i] : 0u;
+    // sums of levels L0..L1-1 into t
+    auto tree = [&](auto l0, auto l1, double* t) {
+      constexpr int L0 = decltype(l0)::value, L1 = decltype(l1)::value;
+      if (!active) return;
+      if (pd->bmode == 0) {
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           uint32_t x[kChainMax];
 #pragma unroll
           for (int i = 0; i < kChainMax; ++i) x[i] = ob[i] ^ pd->b_j_loc[i][j];
-          chain_tree<LB>(a2[j], x, wt, tt);
+          chain_levels<L0, L1>(a2[j], x, wt, t);
         }
+      } else {
+        chain_levels<L0, L1>(s, ob, wt, t);
+      }
+    };
+    if constexpr (kWaveAcc) {
+      double t[16];
+#pragma unroll
+      for (int a = 0; a < 16; ++a) t[a] = 0.0;
+      tree(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, t);
+      acc[0] += wave_reduce16(t);
+      if constexpr (LB == 4) {
+#pragma unroll
+        for (int a = 0; a < 16; ++a) t[a] = 0.0;
+        tree(std::integral_constant<int, 3>{}, std::integral_constant<int, 4>{}, t);
+        acc[1] += wave_reduce16(t);
       }
     } else {
-      double s = 0.0;
-      uint32_t g2 = gb;
-      if (pd->bmode == 1) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) s += a2[j];
-      } else {
-        s = xpose_norms(a2, lt, pd, active);
-        g2 = base;
-        for (int i = 0; i < tb - 4; ++i)
-          if ((tid >> i) & 1) g2 |= pd->b_tid_g[i];
-      }
-      if (active) {
-        uint32_t x[kChainMax];
-#pragma unroll
-        for (int i = 0; i < kChainMax; ++i)
-          x[i] = i < lb ? gather_loc(g2, pd->bq[i], pd->bw[i]) ^ cb[i] : 0u;
-        chain_tree<LB>(s, x, wt, tt);
-      }
+      tree(std::integral_constant<int, 0>{}, std::integral_constant<int, LB>{}, acc);
     }
-    if constexpr (kWaveAcc) acc[0] += wave_reduce32(tt_);
   }
   __syncthreads();  // LDS buffers are reused by the next tile
   }
@@ -1063,7 +1105,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
         if (lane == 0) red[a][wid] = s;
       }
     } else if constexpr (kWaveAcc) {
-      if ((lane & 1) == 0 && (lane >> 1) < nacc) red[lane >> 1][wid] = acc[0];
+      if ((lane & 1) == 0 && lane < 32) {
+        const int a = lane >> 1;
+        if (a < 14) red[a][wid] = acc[0];
+        if constexpr (LB == 4) red[14 + a][wid] = acc[1];
+      }
     } else {
       const double s = wave_reduce32(acc);
       if ((lane & 1) == 0 && (lane >> 1) < nacc) red[lane >> 1][wid] = s;
