@@ -699,18 +699,21 @@ __device__ __forceinline__ void chain_levels(double a2, const uint32_t* x, const
 // AP: weight of an X check A, or the length of a Z chain A (BP likewise).
 // DN: the instantiation that also handles dense Kraus pairs (kept apart so
 // that the dense code does not weigh on the other passes' registers).
-// Occupancy of a pass kernel: passes other than the dense ones are held to
-// 168 registers, i.e. three waves per SIMD (measured on d=5: complex128
-// X-check passes 200 -> 186 us; a complex128 pass summing a Z chain of four
-// then keeps 16-24 bytes per lane in scratch); the dense ones keep the
-// registers they need.
-template <typename T, int BK, int BP, bool DN>
+// Occupancy of a pass kernel: passes other than the dense ones and those
+// summing a Z chain amplitude by amplitude are held to 168 registers, i.e.
+// three waves per SIMD (measured on d=5: complex128 X-check passes
+// 200 -> 186 us); those keep the registers they need.
+// BM0: the instantiation that sums a Z chain B amplitude by amplitude (bmode
+// 0: registers too small for four slot bits outside the chain's qubits, d <=
+// 3); the others sum it once per thread (bmode 1, 2), which keeps a chain of
+// four within three waves per SIMD in complex128.
+template <typename T, int BK, int BP, bool DN, bool BM0>
 struct UpassWaves {
-  static constexpr int value = !DN ? 3 : 1;
+  static constexpr int value = (!DN && !BM0) ? 3 : 1;
 };
 
-template <typename T, int AK, int AP, int BK, int BP, bool DN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<T, BK, BP, DN>::value))) void k_upass(
+template <typename T, int AK, int AP, int BK, int BP, bool DN, bool BM0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<T, BK, BP, DN, BM0>::value))) void k_upass(
     T* __restrict__ st, const UnitPass* __restrict__ pd, const JobConst* __restrict__ jc,
     const BlockRT* __restrict__ rta, const BlockRT* __restrict__ rtb,
     const Decision* __restrict__ dec_a, Decision* __restrict__ dec_b,
@@ -1048,14 +1051,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
     // thread's 16 amplitudes together with their norm (bmode 1, 2)
     double s = 0.0;
     uint32_t g2 = gb;
-    if (pd->bmode == 1) {
+    if constexpr (!BM0) {
+      if (pd->bmode == 1) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) s += a2[j];
-    } else if (pd->bmode == 2) {
-      s = xpose_norms(a2, lt, pd, active);
-      g2 = base;
-      for (int i = 0; i < tb - 4; ++i)
-        if ((tid >> i) & 1) g2 |= pd->b_tid_g[i];
+        for (int j = 0; j < 16; ++j) s += a2[j];
+      } else {
+        s = xpose_norms(a2, lt, pd, active);
+        g2 = base;
+        for (int i = 0; i < tb - 4; ++i)
+          if ((tid >> i) & 1) g2 |= pd->b_tid_g[i];
+      }
     }
     uint32_t ob[kChainMax];
 #pragma unroll
@@ -1064,7 +1069,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
     auto tree = [&](auto l0, auto l1, double* t) {
       constexpr int L0 = decltype(l0)::value, L1 = decltype(l1)::value;
       if (!active) return;
-      if (pd->bmode == 0) {
+      if constexpr (BM0) {
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           uint32_t x[kChainMax];

@@ -702,20 +702,35 @@ void launch_wht_all(hipStream_t s, T* st, int n) {
 }
 
 // One pass kernel launch; the instantiation with the dense Kraus code exists
-// only for unit pairs with an X check.
+// only for unit pairs with an X check, the one summing a Z chain amplitude by
+// amplitude (bmode 0) only for a Z chain B.
 template <typename T, int AK, int AP, int BK, int BP>
-void launch_pass(bool dense, dim3 g, dim3 b, hipStream_t s, T* st, const UnitPass* pd, const JobConst* jc,
-                 const BlockRT* rta, const BlockRT* rtb, const Decision* da, Decision* db, double* part,
-                 int rev, SlotStrides ss, const BlockDense* dna, const BlockDense* dnb) {
-  if constexpr (AK == U_X || BK == U_X) {
-    if (dense) {
-      hipLaunchKernelGGL((k_upass<T, AK, AP, BK, BP, true>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, part,
-                         rev, ss, dna, dnb);
+void launch_pass(bool dense, bool bm0, dim3 g, dim3 b, hipStream_t s, T* st, const UnitPass* pd,
+                 const JobConst* jc, const BlockRT* rta, const BlockRT* rtb, const Decision* da, Decision* db,
+                 double* part, int rev, SlotStrides ss, const BlockDense* dna, const BlockDense* dnb) {
+#define QEC_K(DNV, BMV)                                                                                  \
+  hipLaunchKernelGGL((k_upass<T, AK, AP, BK, BP, DNV, BMV>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, part, \
+                     rev, ss, dna, dnb)
+  if constexpr (BK == U_Z) {
+    if (bm0) {
+      if constexpr (AK == U_X) {
+        if (dense) {
+          QEC_K(true, true);
+          return;
+        }
+      }
+      QEC_K(false, true);
       return;
     }
   }
-  hipLaunchKernelGGL((k_upass<T, AK, AP, BK, BP, false>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, part, rev,
-                     ss, dna, dnb);
+  if constexpr (AK == U_X || BK == U_X) {
+    if (dense) {
+      QEC_K(true, false);
+      return;
+    }
+  }
+  QEC_K(false, false);
+#undef QEC_K
 }
 
 // Launches the pass kernel instantiated for the descriptor's unit kinds.
@@ -727,7 +742,8 @@ sv_status launch_upass(const UnitPass& h, dim3 g, dim3 b, hipStream_t s, T* st, 
                        const BlockDense* dnb = nullptr) {
 #define QEC_UP(AK, AP, BK, BP)                                                                      \
   if (h.akind == AK && ap == AP && h.bkind == BK && bp == BP) {                                     \
-    launch_pass<T, AK, AP, BK, BP>(h.adense || h.bdense, g, b, s, st, pd, jc, rta, rtb, da, db, part, \
+    launch_pass<T, AK, AP, BK, BP>(h.adense || h.bdense, h.bkind == U_Z && h.bmode == 0, g, b, s, st, pd, jc, \
+                                   rta, rtb, da, db, part, \
                                    rev, ss, dna, dnb);                                              \
     return SV_OK;                                                                                   \
   }
