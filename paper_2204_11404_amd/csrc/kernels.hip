@@ -825,9 +825,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   }
   constexpr int nl = AK == U_Z ? la : 1;
   const int use_zz = (AK != U_INIT) && jc->use_zz;
+  // the phase table carries the renormalisation (and the sign of an X check
+  // A's frame), formed in FP64: one complex product per amplitude does both
   if (use_zz)
     for (int k = tid; k <= nl * jc->n_edges; k += blockDim.x)
-      zzt[k] = C2<T>{(T)jc->zzl[nl - 1][2 * k], (T)jc->zzl[nl - 1][2 * k + 1]};
+      zzt[k] = C2<T>{(T)(jc->zzl[nl - 1][2 * k] * scale), (T)(jc->zzl[nl - 1][2 * k + 1] * scale)};
   __syncthreads();
 
   const int d = jc->d;
@@ -964,26 +966,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
         }
       }
       // ZZ phase index: anti-aligned neighbour pairs summed over A's layers
-      // (one popcount pair when every layer sees the same frame)
+      // (one popcount pair when every layer sees the same frame).  The edge
+      // maps g ^ (g >> 1) and g ^ (g >> d) are linear over XOR and a slot's
+      // bits are disjoint from the thread's, so the thread's part of each
+      // masked map is formed once per tile and a slot adds its own part.
       auto finish = [&](auto layers) {
         constexpr int NZ = decltype(layers)::value;
+        constexpr int NE = NZ == 0 ? 1 : NZ;
+        uint32_t Et[NE], Vt[NE];
+        const uint32_t eb = gb ^ (gb >> 1), wb = gb ^ (gb >> d);
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+          Et[i] = (eb ^ eM[i]) & hm;
+          Vt[i] = (wb ^ vM[i]) & vm;
+        }
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          const uint32_t g = gb | pd->j_g[j];
+          const uint32_t jg = pd->j_g[j];
+          const uint32_t g = gb | jg;
           C2<T> r = v[j];
           if (use_zz) {
-            const uint32_t e = g ^ (g >> 1), w = g ^ (g >> d);
-            int K = __popc((e ^ eM[0]) & hm) + __popc((w ^ vM[0]) & vm);
-            if constexpr (NZ == 0) {
-              K *= nl;
-            } else {
+            const uint32_t je = (jg ^ (jg >> 1)) & hm, jw = (jg ^ (jg >> d)) & vm;
+            int K = 0;
 #pragma unroll
-              for (int i = 1; i < NZ; ++i) K += __popc((e ^ eM[i]) & hm) + __popc((w ^ vM[i]) & vm);
-            }
+            for (int i = 0; i < NE; ++i) K += __popc(Et[i] ^ je) + __popc(Vt[i] ^ jw);
+            if constexpr (NZ == 0) K *= nl;
             const C2<T> z = zzt[K];
             r = mulc(r, z.re, z.im);
-          }
-          if constexpr (sizeof(T) == 8) {
+          } else if constexpr (sizeof(T) == 8) {
             r.re *= scale;
             r.im *= scale;
           } else {
