@@ -288,10 +288,8 @@ def batch_run(qs, d, n_traj, dtype, seed=7):
            "trajectories_per_s": n_traj / (g["gpu_ms"] * 1e-3),
            "per_circuit_equivalent_gbs": alg / (g["gpu_ms"] * 1e-3) / 1e9, "tuning": tuning}
     if d == 4:
-        # registers in HBM: one pass per X check and per chain of Z checks
-        n_x = (n_stab + 1) // 2            # X checks of the d=4 layout (8 of 15)
-        n_z = n_stab - n_x
-        passes = n_x + -(-n_z // tuning["zchain"])
+        # registers in HBM: one pass per X check or pair and per chain of Z checks
+        passes = qs.check_pass_layouts(d, "cr", tuning["zchain"], tuning.get("xpair", 0)) - 2
         moved = (int(R.sum()) * passes + n_traj) * reg
         out["passes_per_round"] = passes
         out["hbm_gbs_moved"] = moved / (g["gpu_ms"] * 1e-3) / 1e9

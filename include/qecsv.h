@@ -199,14 +199,15 @@ sv_status sv_measure_reset_ancilla_forced(sv_state s, int anc, int outcome, doub
 sv_status sv_template_info(int d, int gateset, int* n_stab, int* n_sites, int* n_draws_per_round);
 
 /* Host-side self-check of the register-pass layouts that sv_run_rounds would
- * use for (d, gateset) with Z chains of at most zchain checks: every tile
- * layout partitions its bits between lanes and register slots, the regrouping
+ * use for (d, gateset) with Z chains of at most zchain checks and, when xpair
+ * is 1, pairs of consecutive X checks (sv_tuning.xpair): every tile layout
+ * partitions its bits between lanes and register slots, the regrouping
  * layouts cover the same tile, and each unit's qubits sit where its mode needs
  * them; for d <= 3 also the layouts of sv_run_batch's LDS-resident kernel for
  * one, two and four waves per trajectory.  No device work.  *n_passes
  * (optional) receives the pass count of one round sequence; SV_EINVAL names
  * the first failing pass or block. */
-sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int* n_passes);
+sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int xpair, int* n_passes);
 
 typedef struct sv_job {
   int d;               /* code distance, 2..5 */
@@ -294,7 +295,8 @@ sv_status sv_decode_x(int d, int gateset, int rounds, int n_traj, const uint8_t*
 /* Launch parameters of the trajectory engine for (d, dtype) on the current
  * device.  They change speed only: results agree up to the order of
  * floating-point sums.  The environment variables QECSV_ZCHAIN, QECSV_SNAKE,
- * QECSV_BATCH_WAVES_PER_CU and QECSV_LOCKSTEP_MIB override them. */
+ * QECSV_BATCH_WAVES_PER_CU, QECSV_LOCKSTEP_MIB, QECSV_PASS_WGS_PER_CU and
+ * QECSV_XPAIR override them. */
 typedef struct sv_tuning {
   int zchain;             /* longest chain of Z checks applied per register pass, 1..4 */
   int snake;              /* 1: consecutive passes walk the tiles in opposite orders */
@@ -303,6 +305,11 @@ typedef struct sv_tuning {
   int pass_wgs_per_cu;    /* sv_run_rounds: workgroups per compute unit of a register
                              pass, each taking tiles grid-stride; 0 = one tile
                              per workgroup (0..64) */
+  int xpair;              /* 1: d >= 4 register passes may sum two consecutive X
+                             checks at once (the second for each outcome of the
+                             first) and apply both in the next pass, wherever
+                             both units' qubits fit one tile of 2^12
+                             amplitudes; 0: one X check per pass */
 } sv_tuning;
 
 /* Effective parameters (set, tuned or built-in, then the environment). */
@@ -312,9 +319,10 @@ sv_status sv_tuning_get(int d, int dtype, sv_tuning* out);
 sv_status sv_tuning_set(int d, int dtype, const sv_tuning* in);
 /* Time candidate parameters on synthetic work of this shape (tens of ms of
  * device time) and keep the fastest for (d, dtype) on the current device:
- * d = 5, sv_run_rounds (one trajectory, one round): zchain x snake x
+ * d = 5, sv_run_rounds (one trajectory, one round): xpair x zchain x snake x
  *   pass_wgs_per_cu;
- * d = 4, sv_run_batch (4096 trajectories, 3 rounds): zchain x lockstep_mib;
+ * d = 4, sv_run_batch (4096 trajectories, 3 rounds): xpair x zchain x
+ *   lockstep_mib;
  * d <= 3, sv_run_batch (16384 trajectories, 3 rounds): batch_waves_per_cu.
  * Writes the winner to *best and its device time to *best_ms (either may be
  * NULL).  Synchronous, on the default stream; call it before serving, not
@@ -322,7 +330,7 @@ sv_status sv_tuning_set(int d, int dtype, const sv_tuning* in);
 sv_status sv_autotune(int d, int dtype, int gateset, sv_tuning* best, double* best_ms);
 /* Write / read the parameters of the current device's architecture as text
  * lines "arch d dtype zchain snake batch_waves_per_cu lockstep_mib
- * pass_wgs_per_cu"; load
+ * pass_wgs_per_cu xpair"; load (lines without the last field: xpair 0)
  * keeps only lines for this architecture.  SV_EINVAL on I/O or parse errors. */
 sv_status sv_tuning_save(const char* path);
 sv_status sv_tuning_load(const char* path);

@@ -69,7 +69,7 @@ class BatchResult(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("zchain", ctypes.c_int), ("snake", ctypes.c_int),
                 ("batch_waves_per_cu", ctypes.c_int), ("lockstep_mib", ctypes.c_int),
-                ("pass_wgs_per_cu", ctypes.c_int)]
+                ("pass_wgs_per_cu", ctypes.c_int), ("xpair", ctypes.c_int)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -117,7 +117,7 @@ _SIGS = {
                                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
     "sv_measure_reset_ancilla_forced": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                                        ctypes.POINTER(ctypes.c_double)]),
-    "sv_check_pass_layouts": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+    "sv_check_pass_layouts": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_int)]),
     "sv_template_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -209,11 +209,11 @@ def template_info(d, gateset):
     return a.value, b.value, c.value
 
 
-def check_pass_layouts(d, gateset, zchain=4):
+def check_pass_layouts(d, gateset, zchain=4, xpair=0):
     """sv_check_pass_layouts: host-side consistency of the register-pass
     layouts; returns the pass count of one round sequence."""
     n = ctypes.c_int()
-    _check(lib().sv_check_pass_layouts(d, _GATESETS[gateset], int(zchain), ctypes.byref(n)))
+    _check(lib().sv_check_pass_layouts(d, _GATESETS[gateset], int(zchain), int(xpair), ctypes.byref(n)))
     return n.value
 
 

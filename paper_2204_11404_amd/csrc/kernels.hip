@@ -342,6 +342,7 @@ __global__ __launch_bounds__(256) void k_prepare_round(
 
 // -------------------------------------------------------------------- pass --
 constexpr int kTileMax = 12;  // 4096 amplitudes per tile
+constexpr int kMaxEdges = 40;  // ZZ neighbour pairs of the largest layout (d = 5)
 
 // Several trajectories in one launch: blockIdx.y selects a trajectory slot;
 // its register, Kraus tables and decisions sit at these strides (all zero for
@@ -560,10 +561,9 @@ template <typename T, int WB, bool DN>
 __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const UnitPass* pd,
                                             const double* w0, const double* w1, bool active,
                                             double& s0, double& s1, const C2<T> (*K0)[16],
-                                            const C2<T> (*K1)[16]) {
+                                            const C2<T> (*K1)[16], T* buf) {
   // real parts, then imaginary parts, through one buffer of a tile's size
   // (half the LDS of a complex buffer: one more workgroup fits per CU)
-  __shared__ T buf[1 << kTileMax];
   uint32_t lt = 0;
   for (int i = 0; i < pd->tb - 4; ++i)
     if ((threadIdx.x >> i) & 1) lt ^= pd->b_tid_l[i];
@@ -617,8 +617,7 @@ __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const
 // Sum of |amplitude|^2 over the 16 layout-2 slots of this thread, from a tile
 // held in layout 1 (regrouped through LDS).
 __device__ __forceinline__ double xpose_norms(const double* a2, uint32_t lt_a, const UnitPass* pd,
-                                              bool active) {
-  __shared__ double buf[1 << kTileMax];
+                                              bool active, double* buf) {
   if (active) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) buf[lt_a ^ pd->j_l[j]] = a2[j];
@@ -633,6 +632,55 @@ __device__ __forceinline__ double xpose_norms(const double* a2, uint32_t lt_a, c
     for (int j = 0; j < 16; ++j) s += buf[lt ^ pd->b_j_l[j]];
   }
   return s;
+}
+
+// Regroup of a tile through LDS, real parts then imaginary parts through one
+// buffer of a tile's size: this thread's values src of one layout (LDS slot
+// lt_s ^ jl_s[j]) are written and those of another layout read into dst
+// (slot lt_d ^ jl_d[j]); src and dst may be the same array.  Every thread of
+// the workgroup takes part; it starts with a barrier, as the buffer may still
+// be read by an earlier regroup.
+template <typename T>
+__device__ __forceinline__ void regroup(const C2<T>* src, uint32_t lt_s, const uint32_t* jl_s, C2<T>* dst,
+                                        uint32_t lt_d, const uint32_t* jl_d, T* buf) {
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) buf[lt_s ^ jl_s[j]] = src[j].re;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) dst[j].re = buf[lt_d ^ jl_d[j]];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) buf[lt_s ^ jl_s[j]] = src[j].im;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) dst[j].im = buf[lt_d ^ jl_d[j]];
+}
+
+// LDS of the X-pair code (passes with a pair only): the first B member's
+// diagonals for both outcomes and the unscaled one-layer ZZ phase table.
+template <typename T, bool P>
+struct PairLds {
+  C2<T> (*db)[16];
+  C2<T>* zzu;
+};
+template <typename T, bool P>
+__device__ __forceinline__ PairLds<T, P> pair_lds() {
+  if constexpr (P) {
+    __shared__ C2<T> db[2][16];
+    __shared__ C2<T> zzu[kMaxEdges + 1];
+    return {db, zzu};
+  } else {
+    return {nullptr, nullptr};
+  }
+}
+
+// Entry x of a member table over 16 register-slot indices: a weight-w member
+// sits on the lowest w slots, so entry x is its table at x mod 2^w divided by
+// 2^(4 - w) (the unnormalised transforms over the other 4 - w slots square to
+// 2^(4 - w) times the identity).
+__device__ __forceinline__ double padded(const double* t, int stride, int w, int x) {
+  return t[(x & ((1 << w) - 1)) * stride] * (w == 4 ? 1.0 : (w == 3 ? 0.5 : (w == 2 ? 0.25 : 0.125)));
 }
 
 // Hypothesis-tree sums of a Z chain for one weight a2 whose local indices on
@@ -706,10 +754,12 @@ __device__ __forceinline__ void chain_levels(double a2, const uint32_t* x, const
 // BM0: the instantiation that sums a Z chain B amplitude by amplitude (bmode
 // 0: registers too small for four slot bits outside the chain's qubits, d <=
 // 3); the others sum it once per thread (bmode 1, 2), which keeps a chain of
-// four within three waves per SIMD in complex128.
+// four within three waves per SIMD in complex128.  Passes summing an X pair
+// hold two copies of the tile (the first member's transform and one branch)
+// and keep the registers they need.
 template <typename T, int BK, int BP, bool DN, bool BM0>
 struct UpassWaves {
-  static constexpr int value = (!DN && !BM0) ? 3 : 1;
+  static constexpr int value = (!DN && !BM0 && BK != U_XP) ? 3 : 1;
 };
 
 template <typename T, int AK, int AP, int BK, int BP, bool DN, bool BM0>
@@ -736,12 +786,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   const int tid = threadIdx.x;
   const int tb = pd->tb;
   const int nt = 1 << (tb - 4);
-  const bool active = tid < nt;
+  // passes with an X pair run whole tiles of 2^12 amplitudes (every thread
+  // active; the regroups between the members synchronise the workgroup)
+  constexpr bool kPair = AK == U_XP || BK == U_XP;
+  const bool active = kPair || tid < nt;
   constexpr int WA = AK == U_X ? AP : 0;
   constexpr int WB = BK == U_X ? BP : 0;
-  constexpr int la = AK == U_Z ? AP : (AK == U_X ? 1 : 0);
-  constexpr int lb = BK == U_Z ? BP : (BK == U_X ? 1 : 0);
+  constexpr int la = AK == U_Z ? AP : (AK == U_X ? 1 : (AK == U_XP ? 2 : 0));
+  constexpr int lb = BK == U_Z ? BP : (BK == U_X ? 1 : (BK == U_XP ? 2 : 0));
   constexpr int LB = lb;
+  // one LDS buffer of a tile's size for every regroup of the pass
+  using XB = std::conditional_t<BK == U_Z, double, T>;
+  __shared__ XB xbuf[1 << kTileMax];
+  T* const tbuf = reinterpret_cast<T*>(xbuf);
+  const PairLds<T, kPair> pl = pair_lds<T, kPair>();
 
   // frame and decided outcomes of A; frame-dependent offsets
   uint32_t phi = 0;
@@ -755,10 +813,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   uint32_t M[kChainMax] = {phi, phi, phi, phi};  // logical-index masks of A's ZZ layers
   uint32_t ca[kChainMax] = {0, 0, 0, 0};         // member-local input offsets
   uint32_t phi_new = phi;
-  uint32_t Fa = 0;
+  uint32_t Fa = 0, Fa1 = 0;
   if constexpr (AK == U_X) {
     Fa = rta->F;
     if (__popc(gather_loc(phi, pd->aq[0], WA) & Fa) & 1) scale = -scale;
+  }
+  if constexpr (AK == U_XP) {  // both members' frame signs
+    Fa = rta[0].F;
+    Fa1 = rta[1].F;
+    if ((__popc(gather_loc(phi, pd->aq[0], pd->aw[0]) & Fa) + __popc(gather_loc(phi, pd->aq[1], pd->aw[1]) & Fa1)) & 1)
+      scale = -scale;
   }
   if constexpr (AK == U_Z) {
     uint32_t G = 0;
@@ -786,6 +850,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   // tables (the workgroup may have only 64 threads)
   if constexpr (AK == U_X) {
     if (pd->amix && tid < 16) da[0][tid] = C2<T>{(T)rta->D[mbits][tid][0], (T)rta->D[mbits][tid][1]};
+  }
+  if constexpr (AK == U_XP) {  // members' decided diagonals over 16 register slots
+    if (tid < 32) {
+      const int i = tid >> 4, x = tid & 15, m = (mbits >> i) & 1, w = pd->aw[i];
+      if (i == 0 && pd->amix)  // first member partly on lanes: its own local index
+        da[0][x] = C2<T>{(T)rta[0].D[m][x][0], (T)rta[0].D[m][x][1]};
+      else
+        da[i][x] = C2<T>{(T)padded(&rta[i].D[m][0][0], 2, w, x), (T)padded(&rta[i].D[m][0][1], 2, w, x)};
+    }
+  }
+  if constexpr (BK == U_XP) {  // both members' weights, the first member's diagonals
+    if (tid < 64) {
+      const int i = tid >> 5, m = (tid >> 4) & 1, x = tid & 15;
+      wt[i][m][x] = padded(&rtb[i].W[m][0], 1, pd->bw[i], x);
+    }
+    if (tid < 32) {
+      const int m = tid >> 4, x = tid & 15, w = pd->bw[0];
+      pl.db[m][x] = C2<T>{(T)padded(&rtb[0].D[m][0][0], 2, w, x), (T)padded(&rtb[0].D[m][0][1], 2, w, x)};
+    }
+  }
+  if constexpr (kPair) {  // one unscaled ZZ layer (inside a pair)
+    if (jc->use_zz)
+      for (int k = tid; k <= jc->n_edges; k += blockDim.x)
+        pl.zzu[k] = C2<T>{(T)jc->zzl[0][2 * k], (T)jc->zzl[0][2 * k + 1]};
   }
   // dense Kraus pairs in the register's frame (passes with a dense unit)
   C2<T>(*kdn)[16][16] = dense_lds<T, DN>();
@@ -849,6 +937,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
       gt |= pd->tid_g[i];
       lt ^= pd->tid_l[i];
     }
+  // X pairs: this thread's part of layouts 2, p[0] and p[1]; the ZZ layer
+  // inside a pair (frame after A for a B pair)
+  uint32_t lt2 = 0, gt2 = 0, ltp0 = 0, ltp1 = 0;
+  if constexpr (kPair) {
+    for (int i = 0; i < tb - 4; ++i)
+      if ((tid >> i) & 1) {
+        lt2 ^= pd->b_tid_l[i];
+        gt2 |= pd->b_tid_g[i];
+        ltp0 ^= pd->p_tid_l[0][i];
+        ltp1 ^= pd->p_tid_l[1][i];
+      }
+  }
+  const int zz_on = jc->use_zz;
+  const uint32_t eMb = phi_new ^ (phi_new >> 1), vMb = phi_new ^ (phi_new >> d);
+  uint32_t Fb0 = 0;
+  if constexpr (BK == U_XP) Fb0 = rtb[0].F;
+  // one unscaled ZZ layer (frame masks eMx, vMx) on 16 values whose global
+  // indices are gbase | jg[j] (edge maps split as in `finish` below)
+  auto zz_layer = [&](C2<T>* w, uint32_t gbase, const uint32_t* jg, uint32_t eMx, uint32_t vMx) {
+    const uint32_t Et = ((gbase ^ (gbase >> 1)) ^ eMx) & hm, Vt = ((gbase ^ (gbase >> d)) ^ vMx) & vm;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const uint32_t x = jg[j];
+      const int K = __popc(Et ^ ((x ^ (x >> 1)) & hm)) + __popc(Vt ^ ((x ^ (x >> d)) & vm));
+      const C2<T> z = pl.zzu[K];
+      w[j] = mulc(w[j], z.re, z.im);
+    }
+  };
+  // Kraus operator of an X check on the register slots: transform, diagonal
+  // (16-slot table in LDS), transform, frame signs
+  auto x_slots = [&](C2<T>* w, const C2<T>* dg, uint32_t F) {
+    wht<T, 4>(w);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) w[j] = mulc(w[j], dg[j].re, dg[j].im);
+    wht<T, 4>(w);
+    if (F) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (__popc((uint32_t)j & F) & 1) w[j] = {-w[j].re, -w[j].im};
+    }
+  };
   // grid-stride over the tiles (one tile per workgroup when the grid covers
   // them all); the tables above are loaded once per workgroup, the sums of B
   // accumulate over the workgroup's tiles
@@ -867,6 +996,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   for (int i = 0; i < pd->n_outer; ++i)
     if ((wg >> i) & 1) base |= pd->outer_bit[i];
   const uint32_t gb = base | gt;
+  // the LDS slot offsets of the regroups are formed per tile, not kept in
+  // registers over the tile loop
+  if constexpr (kPair) asm volatile("" : "+v"(lt), "+v"(ltp0), "+v"(ltp1), "+v"(lt2));
 
   C2<T> o[16];
   if (active) {
@@ -936,6 +1068,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
               if (__popc((uint32_t)x & Fa) & 1) v[hi + x] = {-v[hi + x].re, -v[hi + x].im};
           }
         }
+      } else if constexpr (AK == U_XP) {
+        // first member in layout 1: its qubits on register slots, or partly
+        // on the lowest lanes (then its own local index)
+        if (pd->amix) {
+          uint32_t xl = 0;
+          for (int i = 0; i < 4; ++i)
+            if ((tid >> i) & 1) xl |= pd->a_tx[i];
+          wht_mixed(v, pd->amix_r, pd->amix_lanes, tid);
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            const C2<T> e = da[0][xl ^ pd->a_jx[j]];
+            v[j] = mulc(v[j], e.re, e.im);
+          }
+          wht_mixed(v, pd->amix_r, pd->amix_lanes, tid);
+          if (Fa) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+              if (__popc((xl ^ pd->a_jx[j]) & Fa) & 1) v[j] = {-v[j].re, -v[j].im};
+          }
+        } else {
+          x_slots(v, da[0], Fa);
+        }
+        if (zz_on) zz_layer(v, gb, pd->j_g, eM[0], vM[0]);
+        // second member on the register slots of layout p[0], then back
+        regroup<T>(v, lt, pd->j_l, v, ltp0, pd->p_j_l[0], tbuf);
+        x_slots(v, da[1], Fa1);
+        regroup<T>(v, ltp0, pd->p_j_l[0], v, lt, pd->j_l, tbuf);
       } else {
         uint32_t oa[kChainMax];
 #pragma unroll
@@ -1021,7 +1180,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
       }
     }
     if (pd->bmode == 2) {
-      xpose_xsums<T, WB, DN>(o, lt, pd, wt[0][0], wt[0][1], active, acc[0], acc[1], K0p, K1p);
+      xpose_xsums<T, WB, DN>(o, lt, pd, wt[0][0], wt[0][1], active, acc[0], acc[1], K0p, K1p, tbuf);
     } else if (active && bd) {
       if constexpr (DN) {
         constexpr int NB = 1 << WB;
@@ -1066,7 +1225,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
 #pragma unroll
         for (int j = 0; j < 16; ++j) s += a2[j];
       } else {
-        s = xpose_norms(a2, lt, pd, active);
+        s = xpose_norms(a2, lt, pd, active, reinterpret_cast<double*>(xbuf));
         g2 = base;
         for (int i = 0; i < tb - 4; ++i)
           if ((tid >> i) & 1) g2 |= pd->b_tid_g[i];
@@ -1105,6 +1264,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
       }
     } else {
       tree(std::integral_constant<int, 0>{}, std::integral_constant<int, LB>{}, acc);
+    }
+  }
+  if constexpr (BK == U_XP) {
+    // first member on the register slots of layout 2: its sums; then for each
+    // of its outcomes m0 the second member's sums (register slots of layout
+    // p[1]) after the first member's Kraus operator for m0 and its ZZ layer
+    C2<T> w[16];
+    regroup<T>(o, lt, pd->j_l, w, lt2, pd->b_j_l, tbuf);
+    wht<T, 4>(w);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double re = (double)w[j].re, im = (double)w[j].im;
+      const double a2 = re * re + im * im;
+      acc[0] += wt[0][0][j] * a2;
+      acc[1] += wt[0][1][j] * a2;
+    }
+#pragma unroll 1
+    for (int m0 = 0; m0 < 2; ++m0) {
+      // tables and slot offsets are read per outcome, not held over the loop
+      asm volatile("" : "+v"(lt2), "+v"(ltp1) : : "memory");
+      C2<T> u[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const C2<T> e = pl.db[m0][j];
+        u[j] = mulc(w[j], e.re, e.im);
+      }
+      wht<T, 4>(u);
+      if (Fb0) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (__popc((uint32_t)j & Fb0) & 1) u[j] = {-u[j].re, -u[j].im};
+      }
+      if (zz_on) zz_layer(u, base | gt2, pd->b_j_g, eMb, vMb);
+      regroup<T>(u, lt2, pd->b_j_l, u, ltp1, pd->p_j_l[1], tbuf);
+      wht<T, 4>(u);
+      double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double re = (double)u[j].re, im = (double)u[j].im;
+        const double a2 = re * re + im * im;
+        t0 += wt[1][0][j] * a2;
+        t1 += wt[1][1][j] * a2;
+      }
+      if (m0) {
+        acc[3] += t0;
+        acc[5] += t1;
+      } else {
+        acc[2] += t0;
+        acc[4] += t1;
+      }
     }
   }
   __syncthreads();  // LDS buffers are reused by the next tile

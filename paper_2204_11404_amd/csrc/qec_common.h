@@ -567,9 +567,17 @@ struct Decision {
 // up to the global sign (-1)^{popcount(phi_b & F)} (phi_b: phi on the check's
 // qubits); S_m of an X check does not depend on phi; the final measurement
 // reads logical bit q as physical bit q ^ phi_q.
+// Two consecutive X checks can also form one unit (U_XP, a pair): the pass
+// that sums the pair evaluates the first member's S_m and, for each outcome m
+// of the first member, the second member's sums after the first member's
+// Kraus operator for m and its ZZ layer (six sums laid out as a chain of two:
+// index 2 + m0 + 2 m1 for the second member); the next pass applies both.
+// A pair's members may have weight 2 or 4: a weight-2 member is handled as a
+// 16-element group over four register slots (its two qubits and two others)
+// with its tables repeated over the other two bits and divided by 4.
 constexpr int kChainMax = 4;
 constexpr int kChainAcc = (2 << kChainMax) - 2;  // sums of a full chain
-enum : int { U_NONE = 0, U_X = 1, U_Z = 2, U_INIT = 3 };
+enum : int { U_NONE = 0, U_X = 1, U_Z = 2, U_INIT = 3, U_XP = 4 };
 
 // Layout and unit description of one pass: apply unit A (decided), accumulate
 // the sums of unit B.  Tiles of 2^tb amplitudes; a thread owns 16 amplitudes
@@ -584,8 +592,8 @@ enum : int { U_NONE = 0, U_X = 1, U_Z = 2, U_INIT = 3 };
 // amplitude in layout 1 (bmode 0, when no 4 tile bits avoid B's qubits).
 struct UnitPass {
   int tb, n_outer;
-  int akind, la, wa;       // A: U_INIT / U_X / U_Z, chain length, X weight
-  int bkind, lb, wb;       // B: U_NONE / U_X / U_Z
+  int akind, la, wa;       // A: U_INIT / U_X / U_Z / U_XP, members, X weight (first member)
+  int bkind, lb, wb;       // B: U_NONE / U_X / U_Z / U_XP
   int amode, bmode;
   uint32_t outer_bit[32];
   // LDS slots (tid_l, j_l, b_tid_l, b_j_l) are already swizzled: the slot of
@@ -595,6 +603,10 @@ struct UnitPass {
   uint32_t b_tid_g[8], b_tid_l[8];  // layout 2
   uint32_t b_j_l[16];
   uint32_t b_j_g[16];               // layout 2: global bits of slot j (host checks)
+  // X pairs: layout of the second member's register slots, [0] for an A
+  // pair (the tile goes layout 1 -> p[0] -> layout 1), [1] for a B pair
+  // (layout 2 holds B's first member, p[1] its second)
+  uint32_t p_tid_g[2][8], p_tid_l[2][8], p_j_g[2][16], p_j_l[2][16];
   // amix = 1: X check A on bit 0 or 1 keeps its qubits below bit 4 on the
   // lanes (so lanes still run over the lowest bits) and the others in the low
   // amix_r register slots; its local index is the XOR of a_tx[i] over the

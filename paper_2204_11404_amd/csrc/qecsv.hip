@@ -9,6 +9,7 @@
 // simulation arithmetic runs in the kernels of kernels.hip and
 // kernels_batch.hip.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -394,6 +395,7 @@ sv_tuning default_tuning() {
   t.batch_waves_per_cu = 8;
   t.lockstep_mib = 4096;
   t.pass_wgs_per_cu = 0;
+  t.xpair = 0;
   return t;
 }
 
@@ -410,6 +412,7 @@ sv_status check_tuning(const sv_tuning& t) {
     return fail(SV_EINVAL, "batch_waves_per_cu %d out of 1..32", t.batch_waves_per_cu);
   if (t.lockstep_mib < 1 || t.lockstep_mib > (1 << 20)) return fail(SV_EINVAL, "lockstep_mib out of range");
   if (t.pass_wgs_per_cu < 0 || t.pass_wgs_per_cu > 64) return fail(SV_EINVAL, "pass_wgs_per_cu out of 0..64");
+  if (t.xpair != 0 && t.xpair != 1) return fail(SV_EINVAL, "xpair must be 0 or 1");
   return SV_OK;
 }
 
@@ -434,6 +437,7 @@ sv_tuning tuning_for(int d, int dtype) {
   if (const char* e = std::getenv("QECSV_LOCKSTEP_MIB")) t.lockstep_mib = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("QECSV_PASS_WGS_PER_CU"))
     t.pass_wgs_per_cu = std::max(0, std::min(64, std::atoi(e)));
+  if (const char* e = std::getenv("QECSV_XPAIR")) t.xpair = std::atoi(e) != 0;
   return t;
 }
 
@@ -459,7 +463,8 @@ std::vector<Unit> make_units(const Template& tp, int max_chain) {
 // evaluated per thread, taken from bit tb - 4 upwards so that the
 // thread-index bits are the lowest tile bits (coalesced runs).  The tile
 // holds both layouts' slot bits and then the lowest remaining bits.
-UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, const Unit* B) {
+UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, const Unit* B,
+                        bool* fits = nullptr) {
   UnitPass pd{};
   const int tb = std::min(tb_max, n);
   pd.tb = tb;
@@ -467,8 +472,10 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
   pd.la = A ? A->len : 0;
   pd.bkind = B ? B->kind : U_NONE;
   pd.lb = B ? B->len : 0;
-  pd.wa = (A && A->kind == U_X) ? tp.blocks[A->first].w : 0;
-  pd.wb = (B && B->kind == U_X) ? tp.blocks[B->first].w : 0;
+  const bool apair = A && A->kind == U_XP, bpair = B && B->kind == U_XP;
+  const bool pairpass = apair || bpair;
+  pd.wa = (A && (A->kind == U_X || apair)) ? tp.blocks[A->first].w : 0;
+  pd.wb = (B && (B->kind == U_X || bpair)) ? tp.blocks[B->first].w : 0;
   auto members = [&](const Unit* U, uint32_t (*q)[4], int* w) {
     if (!U) return;
     for (int i = 0; i < U->len; ++i) {
@@ -479,9 +486,9 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
   };
   members(A, pd.aq, pd.aw);
   members(B, pd.bq, pd.bw);
-  auto xqubits = [&](const Unit* U) {
+  auto xqubits = [&](const Unit* U, int i = 0) {  // qubits of X member i
     std::vector<int> qs;
-    const TBlock& b = tp.blocks[U->first];
+    const TBlock& b = tp.blocks[U->first + i];
     for (int l = 0; l < b.w; ++l) qs.push_back(b.qubit[l]);
     return qs;
   };
@@ -512,12 +519,47 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
     for (int q : qs) if ((m >> q) & 1) return false;
     return true;
   };
-  std::vector<int> J1, J2;
+  auto jmask_of = [](const std::vector<int>& J) {
+    uint32_t m = 0;
+    for (int q : J) m |= 1u << q;
+    return m;
+  };
+  // passes with an X pair: the qubits of every X member of A and B, where the
+  // fillers of the layouts' slots are taken first (from bit 4 upward, then
+  // below bit 4 unless avoided) so that the tile stays small and keeps the
+  // lowest bits for the lanes; then as `slots`
+  uint32_t UX = 0;
+  if (pairpass) {
+    for (const Unit* U : {A, B})
+      if (U && (U->kind == U_X || U->kind == U_XP))
+        for (int i = 0; i < U->len; ++i)
+          for (int q : xqubits(U, i)) UX |= 1u << q;
+  }
+  auto pslots = [&](std::vector<int> fixed, uint32_t avoid, uint32_t low_ok, std::vector<int>& out) {
+    out = fixed;
+    uint32_t used = avoid;
+    for (int q : fixed) used |= 1u << q;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int bit = 0; bit < n && (int)out.size() < 4; ++bit) {
+        const bool low = bit < 4;
+        if (pass == 0 ? low : !(low && ((low_ok >> bit) & 1))) continue;
+        if (((UX >> bit) & 1) && !((used >> bit) & 1)) {
+          out.push_back(bit);
+          used |= 1u << bit;
+        }
+      }
+    for (int k = 0; k < n && (int)out.size() < 4; ++k) {
+      const int bit = k < n - (tb - 4) ? tb - 4 + k : n - 1 - k;
+      if (!((used >> bit) & 1)) { out.push_back(bit); used |= 1u << bit; }
+    }
+    return (int)out.size() == 4;
+  };
+  std::vector<int> J1, J2, Jp[2];
   bool have2 = false;
   pd.amode = 0;
   pd.bmode = 0;
-  const bool ax = A && A->kind == U_X, az = A && A->kind == U_Z;
-  const bool bx = B && B->kind == U_X, bz = B && B->kind == U_Z;
+  const bool ax = A && (A->kind == U_X || apair), az = A && A->kind == U_Z;
+  const bool bx = B && (B->kind == U_X || bpair), bz = B && B->kind == U_Z;
   // an X check's qubits serve as layout-1 slot bits only if that keeps the
   // four lowest bits for the thread index (runs of >= 256 bytes)
   const bool bx_high = bx && disjoint(xqubits(B), 0xFu);
@@ -525,7 +567,16 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
   pd.adense = ax && tp.blocks[A->first].dense;
   pd.bdense = bx && tp.blocks[B->first].dense;
   std::vector<int> a_high;  // amix: A's qubits held in register slots
-  if (ax) {
+  if (ax && pairpass) {
+    uint32_t am = 0;
+    for (int q : xqubits(A)) am |= 1u << q;
+    if ((am & 0x3u) && tb >= 8) {
+      for (int q : xqubits(A))
+        if (q >= 4) a_high.push_back(q);
+      if (pslots(a_high, UB | 0xFu, 0u, J1) || pslots(a_high, 0xFu, 0u, J1)) pd.amix = 1;
+    }
+    if (!pd.amix && !pslots(xqubits(A), UB, 0u, J1)) pslots(xqubits(A), 0u, 0u, J1);
+  } else if (ax) {
     uint32_t am = 0;
     for (int q : xqubits(A)) am |= 1u << q;
     if ((am & 0x3u) && tb >= 8 && !pd.adense) {
@@ -534,6 +585,9 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
       if (slots(a_high, UB | 0xFu, J1) || slots(a_high, 0xFu, J1)) pd.amix = 1;
     }
     if (!pd.amix && !slots(xqubits(A), UB, J1)) slots(xqubits(A), 0u, J1);
+  } else if (az && bpair) {
+    if (!pslots({}, UA, 0u, J1)) slots({}, 0u, J1);
+    pd.amode = (jmask_of(J1) & UA) == 0;
   } else if (az) {
     if (bx_high && disjoint(xqubits(B), UA) && slots(xqubits(B), UA, J1)) {
       pd.amode = 1;
@@ -542,6 +596,8 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
     } else {
       slots({}, 0u, J1);
     }
+  } else if (bpair) {  // logical |0>, then the sums of a pair
+    pslots({}, 0u, 0u, J1);
   } else {  // logical |0>
     if (bx_high) slots(xqubits(B), 0u, J1);
     else if (!(bz && slots({}, UB, J1))) slots({}, 0u, J1);
@@ -551,7 +607,25 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
     for (int q : J) m |= 1u << q;
     return m;
   };
-  if (bx) {
+  if (pairpass) {
+    // second members: their qubits on the register slots (fillers anywhere)
+    if (apair) pslots(xqubits(A, 1), 0u, 0xFu, Jp[0]);
+    if (bpair) pslots(xqubits(B, 1), 0u, 0xFu, Jp[1]);
+  }
+  if (bx && pairpass) {
+    pslots(xqubits(B), 0u, 0xFu, J2);
+    have2 = true;
+    pd.bmode = 2;
+  } else if (bz && pairpass) {
+    if ((jmask(J1) & UB) == 0) {
+      pd.bmode = 1;
+    } else if (pslots({}, UB, 0xFu, J2)) {
+      have2 = true;
+      pd.bmode = 2;
+    } else {
+      pd.bmode = 0;
+    }
+  } else if (bx) {
     const std::vector<int> bq = xqubits(B);
     bool in_regs = !ax && J1.size() >= bq.size();
     for (size_t l = 0; l < bq.size() && in_regs; ++l) in_regs = J1[l] == bq[l];
@@ -578,8 +652,24 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
   for (int x : J1) if (!in_t[x]) { in_t[x] = true; ++cnt; }
   if (have2)
     for (int x : J2) if (!in_t[x]) { in_t[x] = true; ++cnt; }
+  for (const std::vector<int>& J : Jp)
+    for (int x : J) if (!in_t[x]) { in_t[x] = true; ++cnt; }
+  const bool over = cnt > tb;  // the slots alone exceed the tile
   for (int bit = 0; bit < n && cnt < tb; ++bit)
     if (!in_t[bit]) { in_t[bit] = true; ++cnt; }
+  {
+    // a pass fits when its slots leave room for the lowest three bits
+    // (lanes over runs of at least 8 amplitudes); one that does not is
+    // returned with tb = -1 (never launched)
+    bool ok = !over;
+    if (pairpass)
+      for (int bit = 0; bit < std::min(3, n) && ok; ++bit) ok = in_t[bit];
+    if (fits) *fits = ok;
+    if (!ok) {
+      pd.tb = -1;
+      return pd;
+    }
+  }
   std::vector<int> rank(n, -1);
   int r = 0;
   pd.n_outer = 0;
@@ -622,8 +712,10 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
         if (pd.j_g[j] & (1u << aq[l])) pd.a_jx[j] |= 1u << l;
     }
   }
-  if (have2) {
-    fill(J2, pd.b_tid_g, pd.b_tid_l, pd.b_j_g, pd.b_j_l);
+  for (int k = 0; k < 2; ++k)
+    if (!Jp[k].empty()) fill(Jp[k], pd.p_tid_g[k], pd.p_tid_l[k], pd.p_j_g[k], pd.p_j_l[k]);
+  if (have2) fill(J2, pd.b_tid_g, pd.b_tid_l, pd.b_j_g, pd.b_j_l);
+  if (have2 || pairpass) {
     // LDS swizzle for the regrouping: slot = l ^ f(l), where f folds each tile
     // bit i >= 4 onto one of the four lowest bits (mask M[i]).  A wave's 64
     // lanes then spread over the 16-byte bank groups when their lane bits map
@@ -647,7 +739,8 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
     for (uint32_t code = 0; code < (1u << (2 * 8)) && !found; ++code) {
       // M[i] = one low bit for i = 4..11; code 0 is the plain fold
       for (int i = 4; i < 12; ++i) M[i] = 1u << (((i & 3) + ((code >> (2 * (i - 4))) & 3)) & 3);
-      if (rank_ok(pd.tid_l, M) && rank_ok(pd.b_tid_l, M)) {
+      if (rank_ok(pd.tid_l, M) && (!have2 || rank_ok(pd.b_tid_l, M)) && (Jp[0].empty() || rank_ok(pd.p_tid_l[0], M)) &&
+          (Jp[1].empty() || rank_ok(pd.p_tid_l[1], M))) {
         found = true;
         std::copy(M, M + 32, best);
       }
@@ -663,10 +756,12 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
     for (int i = 0; i < tb - 4; ++i) {
       pd.tid_l[i] = swz(pd.tid_l[i]);
       pd.b_tid_l[i] = swz(pd.b_tid_l[i]);
+      for (int k = 0; k < 2; ++k) pd.p_tid_l[k][i] = swz(pd.p_tid_l[k][i]);
     }
     for (int j = 0; j < 16; ++j) {
       pd.j_l[j] = swz(pd.j_l[j]);
       pd.b_j_l[j] = swz(pd.b_j_l[j]);
+      for (int k = 0; k < 2; ++k) pd.p_j_l[k][j] = swz(pd.p_j_l[k][j]);
     }
   }
   auto loc = [](uint32_t g, const uint32_t* q, int w) {
@@ -723,7 +818,7 @@ void launch_pass(bool dense, bool bm0, dim3 g, dim3 b, hipStream_t s, T* st, con
       return;
     }
   }
-  if constexpr (AK == U_X || BK == U_X) {
+  if constexpr ((AK == U_X || BK == U_X) && AK != U_XP && BK != U_XP) {  // pairs are never dense
     if (dense) {
       QEC_K(true, false);
       return;
@@ -751,17 +846,104 @@ sv_status launch_upass(const UnitPass& h, dim3 g, dim3 b, hipStream_t s, T* st, 
   QEC_UP(AK, AP, U_X, 2) QEC_UP(AK, AP, U_X, 4) QEC_UP(AK, AP, U_Z, 1) QEC_UP(AK, AP, U_Z, 2) \
   QEC_UP(AK, AP, U_Z, 3) QEC_UP(AK, AP, U_Z, 4)
   if ((h.adense && !dna) || (h.bdense && !dnb)) return fail(SV_EINVAL, "dense unit without its Kraus table");
+  if (h.tb <= 0) return fail(SV_EINVAL, "pass layout does not fit a tile");
   const int ap = h.akind == U_X ? h.wa : (h.akind == U_Z ? h.la : 0);
   const int bp = h.bkind == U_X ? h.wb : (h.bkind == U_Z ? h.lb : 0);
   QEC_UP_B(U_INIT, 0)
   QEC_UP_B(U_X, 2) QEC_UP_B(U_X, 4) QEC_UP(U_X, 2, U_NONE, 0) QEC_UP(U_X, 4, U_NONE, 0)
   QEC_UP_B(U_Z, 1) QEC_UP_B(U_Z, 2) QEC_UP_B(U_Z, 3) QEC_UP_B(U_Z, 4)
   QEC_UP(U_Z, 1, U_NONE, 0) QEC_UP(U_Z, 2, U_NONE, 0) QEC_UP(U_Z, 3, U_NONE, 0) QEC_UP(U_Z, 4, U_NONE, 0)
+  // X pairs (weights handled at run time)
+  QEC_UP(U_INIT, 0, U_XP, 0) QEC_UP(U_X, 2, U_XP, 0) QEC_UP(U_X, 4, U_XP, 0)
+  QEC_UP(U_Z, 1, U_XP, 0) QEC_UP(U_Z, 2, U_XP, 0) QEC_UP(U_Z, 3, U_XP, 0) QEC_UP(U_Z, 4, U_XP, 0)
+  QEC_UP_B(U_XP, 0) QEC_UP(U_XP, 0, U_XP, 0) QEC_UP(U_XP, 0, U_NONE, 0)
 #undef QEC_UP_B
 #undef QEC_UP
   return fail(SV_EINVAL, "no pass kernel for units (%d,%d)->(%d,%d)", h.akind, h.wa, h.bkind, h.wb);
 }
 
+
+// Units of one round with X pairs (pairs on): each run of consecutive X
+// checks is cut into single checks and pairs of consecutive checks, the
+// fewest units whose passes fit a tile (a pass with a pair needs the qubits
+// of every X member of both its units, and the lowest three bits, in one tile
+// of 2^12 amplitudes), counting the passes from the unit before the run and
+// into the unit after it (around the round, and from logical |0>).  Dense
+// checks stay single; below 12 qubits no pairs.
+std::vector<Unit> make_units_paired(const Template& tp, int max_chain, int n, int xpair) {
+  const std::vector<Unit> base = make_units(tp, max_chain);
+  if (!xpair || n < kTileMax) return base;
+  const int nb = (int)base.size();
+  auto fit = [&](const Unit* a, const Unit* b) {
+    if (!((a && a->kind == U_XP) || (b && b->kind == U_XP))) return true;
+    bool ok = false;
+    (void)make_unit_pass(n, kTileMax, tp, a, b, &ok);
+    return ok;
+  };
+  std::vector<Unit> out;
+  for (int i = 0; i < nb;) {
+    if (base[i].kind != U_X) {
+      out.push_back(base[i++]);
+      continue;
+    }
+    int j = i;
+    while (j < nb && base[j].kind == U_X) ++j;  // X run [i, j)
+    const Unit* L = &base[(i + nb - 1) % nb];
+    const Unit* R = &base[j % nb];
+    const int len = j - i;
+    auto unit_at = [&](int p, int l) {
+      return l == 2 ? Unit{U_XP, base[i + p].first, 2} : base[i + p];
+    };
+    // best[p][k]: fewest units for checks p.. given the previous unit (k = 0:
+    // L, 1: single p - 1, 2: pair p - 2, p - 1); choice[p][k]: its first unit's length
+    const int INF = 1 << 20;
+    std::vector<std::array<int, 3>> best(len + 1), choice(len + 1);
+    for (int p = len; p >= 0; --p)
+      for (int k = 0; k < 3; ++k) {
+        best[p][k] = INF;
+        choice[p][k] = 0;
+        if ((k == 0) != (p == 0) || p < k) continue;
+        Unit prev_u{};
+        const Unit* prev = L;
+        if (k > 0) {
+          prev_u = unit_at(p - k, k);
+          prev = &prev_u;
+        }
+        if (p == len) {
+          if (fit(prev, R)) best[p][k] = 0;
+          continue;
+        }
+        for (int l = 1; l <= 2; ++l) {
+          if (p + l > len) continue;
+          if (l == 2 && (tp.blocks[base[i + p].first].dense || tp.blocks[base[i + p + 1].first].dense)) continue;
+          const Unit u = unit_at(p, l);
+          if (!fit(prev, &u)) continue;
+          if (i == 0 && p == 0 && !fit(nullptr, &u)) continue;
+          const int c = best[p + l][l];
+          if (c < INF && 1 + c < best[p][k]) {
+            best[p][k] = 1 + c;
+            choice[p][k] = l;
+          }
+        }
+      }
+    if (best[0][0] >= INF) {  // keep the run's single checks
+      for (int p = i; p < j; ++p) out.push_back(base[p]);
+    } else {
+      for (int p = 0, k = 0; p < len;) {
+        const int l = choice[p][k];
+        out.push_back(unit_at(p, l));
+        p += l;
+        k = l;
+      }
+    }
+    i = j;
+  }
+  // every pass of the sequence must fit (also around the round)
+  const int nu = (int)out.size();
+  bool ok = fit(nullptr, &out[0]) && fit(&out[nu - 1], nullptr);
+  for (int u = 0; u < nu && ok; ++u) ok = fit(&out[u], &out[(u + 1) % nu]);
+  return ok ? out : base;
+}
 
 // Passes of a round sequence: [0] writes logical |0> and sums unit 0;
 // [1 + u] applies unit u and sums unit u + 1 (unit 0 of the next round after
@@ -814,7 +996,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   const int tb = std::min(kTileMax, n);
   const int per_traj = R * ns;  // block instances (records) per trajectory
   const sv_tuning tune = tuning_for(d, job->dtype);
-  const std::vector<Unit> units = make_units(tp, tune.zchain);
+  const std::vector<Unit> units = make_units_paired(tp, tune.zchain, n, tune.xpair);
   const int nu = (int)units.size();
   const int per_units = R * nu;  // passes per trajectory after the first
   hipStream_t s = (hipStream_t)job->hip_stream;
@@ -1428,7 +1610,7 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
   const size_t cap = (size_t)tune.lockstep_mib << 20;
   const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)nt, cap / per_reg_bytes));
   const int per_traj = in.max_rounds * ns;
-  const std::vector<Unit> units = make_units(tp, tune.zchain);
+  const std::vector<Unit> units = make_units_paired(tp, tune.zchain, n, tune.xpair);
   const int nu = (int)units.size();
   const size_t dec_stride = (size_t)in.max_rounds * nu + 1;
   const int n_sites = std::max(1, tp.n_sites);
@@ -2053,13 +2235,14 @@ sv_status sv_template_info(int d, int gateset, int* n_stab, int* n_sites, int* n
   return SV_OK;
 }
 
-sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int* n_passes) {
+sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int xpair, int* n_passes) {
   if (d < 2 || d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", d);
   if (gateset != SV_GATESET_CR && gateset != SV_GATESET_TEXTBOOK) return fail(SV_EINVAL, "bad gateset");
   if (zchain < 1 || zchain > kChainMax) return fail(SV_EINVAL, "zchain %d out of 1..%d", zchain, kChainMax);
+  if (xpair != 0 && xpair != 1) return fail(SV_EINVAL, "xpair must be 0 or 1");
   const Template tp = build_template(d, gateset);
   const int n = d * d;
-  const std::vector<Unit> units = make_units(tp, zchain);
+  const std::vector<Unit> units = make_units_paired(tp, zchain, n, xpair);
   const std::vector<UnitPass> pds = make_unit_passes(n, kTileMax, tp, units);
   const uint32_t all = (uint32_t)((1ull << n) - 1);
   auto bits_of = [](const uint32_t* m, int k) {
@@ -2098,7 +2281,7 @@ sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int* n_passes) {
       for (int l = 0; l < p.bw[i]; ++l) UB |= p.bq[i][l];
     if (p.akind == U_X && !p.amix)  // WHT over the register slots
       for (int l = 0; l < p.wa && ok; ++l) ok = slot[l] == p.aq[0][l];
-    if (p.akind == U_X && p.amix) {
+    if ((p.akind == U_X || p.akind == U_XP) && p.amix) {
       // A's qubits: lane bits among the thread's lowest four index bits, or
       // the lowest amix_r register slots; the local index tables match
       uint32_t seen = 0;
@@ -2123,8 +2306,25 @@ sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int* n_passes) {
     }
     if (p.bkind == U_X && p.bmode == 1)
       for (int l = 0; l < p.wb && ok; ++l) ok = slot[l] == p.bq[0][l];
-    if (p.bmode == 2 && ok) {
-      // both layouts put every tile element in the same LDS slot, one each
+    const bool apair = p.akind == U_XP, bpair = p.bkind == U_XP;
+    // a pair: whole tiles of 2^12 amplitudes, members of weight 2 or 4, and
+    // each regrouped layout holds its member's qubits on the lowest slots
+    if (apair || bpair) ok = ok && p.tb == kTileMax;
+    auto member_slots = [&](const uint32_t* jg, const uint32_t* q, int w) {
+      bool good = w == 2 || w == 4;
+      for (int l = 0; l < w && good; ++l) good = jg[1u << l] == q[l];
+      return good;
+    };
+    if (apair && ok) {
+      ok = p.la == 2 && (p.amix || member_slots(p.j_g, p.aq[0], p.aw[0])) &&
+           member_slots(p.p_j_g[0], p.aq[1], p.aw[1]);
+      if (p.amix) ok = ok && p.aw[0] >= 2 && p.aw[0] <= 4;
+    }
+    if (bpair && ok)
+      ok = p.lb == 2 && p.bmode == 2 && member_slots(p.b_j_g, p.bq[0], p.bw[0]) &&
+           member_slots(p.p_j_g[1], p.bq[1], p.bw[1]);
+    if ((p.bmode == 2 || apair || bpair) && ok) {
+      // every layout puts every tile element in the same LDS slot, one each
       std::map<uint32_t, uint32_t> at;  // global index -> slot (layout 1)
       std::vector<uint8_t> used((size_t)1 << p.tb, 0);
       for (int t = 0; t < (1 << nt) && ok; ++t)
@@ -2135,14 +2335,21 @@ sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int* n_passes) {
           ok = l < used.size() && !used[l];
           if (ok) { used[l] = 1; at[g] = l; }
         }
-      for (int t = 0; t < (1 << nt) && ok; ++t)
-        for (int j = 0; j < 16 && ok; ++j) {
-          uint32_t g = p.b_j_g[j], l = p.b_j_l[j];
-          for (int i = 0; i < nt; ++i)
-            if ((t >> i) & 1) { g |= p.b_tid_g[i]; l ^= p.b_tid_l[i]; }
-          const auto it = at.find(g);
-          ok = it != at.end() && it->second == l;
-        }
+      auto same = [&](const uint32_t* tg, const uint32_t* tl, const uint32_t* jg, const uint32_t* jl) {
+        bool good = distinct(tg, nt);
+        for (int t = 0; t < (1 << nt) && good; ++t)
+          for (int j = 0; j < 16 && good; ++j) {
+            uint32_t g = jg[j], l = jl[j];
+            for (int i = 0; i < nt; ++i)
+              if ((t >> i) & 1) { g |= tg[i]; l ^= tl[i]; }
+            const auto it = at.find(g);
+            good = it != at.end() && it->second == l;
+          }
+        return good;
+      };
+      if (p.bmode == 2) ok = ok && same(p.b_tid_g, p.b_tid_l, p.b_j_g, p.b_j_l);
+      if (apair) ok = ok && same(p.p_tid_g[0], p.p_tid_l[0], p.p_j_g[0], p.p_j_l[0]);
+      if (bpair) ok = ok && same(p.p_tid_g[1], p.p_tid_l[1], p.p_j_g[1], p.p_j_l[1]);
     }
     if (!ok) return fail(SV_EINVAL, "pass %zu: inconsistent layout", k);
   }
@@ -2399,23 +2606,27 @@ sv_status sv_autotune(int d, int dtype, int gateset, sv_tuning* best, double* be
   }
   std::vector<sv_tuning> cands;
   if (d == 5) {
-    for (int z = 2; z <= kChainMax; ++z)
-      for (int sn = 0; sn <= 1; ++sn)
-        for (int wpc : {0, 3, 4, 6, 8, 12, 16}) {  // multiples of 2 and 3 resident workgroups
+    for (int xp = 0; xp <= 1; ++xp)
+      for (int z = 2; z <= kChainMax; ++z)
+        for (int sn = 0; sn <= 1; ++sn)
+          for (int wpc : {0, 3, 4, 6, 8, 12, 16}) {  // multiples of 2 and 3 resident workgroups
+            sv_tuning c = base;
+            c.xpair = xp;
+            c.zchain = z;
+            c.snake = sn;
+            c.pass_wgs_per_cu = wpc;
+            cands.push_back(c);
+          }
+  } else if (d == 4) {
+    for (int xp = 0; xp <= 1; ++xp)
+      for (int z = 2; z <= kChainMax; ++z)
+        for (int mib : {256, 1024, 4096}) {
           sv_tuning c = base;
+          c.xpair = xp;
           c.zchain = z;
-          c.snake = sn;
-          c.pass_wgs_per_cu = wpc;
+          c.lockstep_mib = mib;
           cands.push_back(c);
         }
-  } else if (d == 4) {
-    for (int z = 2; z <= kChainMax; ++z)
-      for (int mib : {256, 1024, 4096}) {
-        sv_tuning c = base;
-        c.zchain = z;
-        c.lockstep_mib = mib;
-        cands.push_back(c);
-      }
   } else {
     for (int w : {2, 4, 8, 12, 16}) {
       sv_tuning c = base;
@@ -2507,9 +2718,9 @@ sv_status sv_tuning_save(const char* path) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& kv : g_tune)
       if (kv.first.dev == dev)
-        std::fprintf(f, "%s %d %d %d %d %d %d %d\n", arch.c_str(), kv.first.d, kv.first.dtype,
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", arch.c_str(), kv.first.d, kv.first.dtype,
                      kv.second.zchain, kv.second.snake, kv.second.batch_waves_per_cu, kv.second.lockstep_mib,
-                     kv.second.pass_wgs_per_cu);
+                     kv.second.pass_wgs_per_cu, kv.second.xpair);
   }
   return std::fclose(f) == 0 ? SV_OK : fail(SV_EINVAL, "cannot write %s", path);
 }
@@ -2520,13 +2731,22 @@ sv_status sv_tuning_load(const char* path) {
   const int dev = current_device();
   FILE* f = std::fopen(path, "r");
   if (!f) return fail(SV_EINVAL, "cannot read %s", path);
-  char a[128];
+  char line[512], a[128];
   int d, dt;
-  sv_tuning t{};
   std::vector<std::pair<TuneKey, sv_tuning>> got;
-  int k;
-  while ((k = std::fscanf(f, "%127s %d %d %d %d %d %d %d", a, &d, &dt, &t.zchain, &t.snake,
-                          &t.batch_waves_per_cu, &t.lockstep_mib, &t.pass_wgs_per_cu)) == 8) {
+  bool bad = false;
+  // lines of eight fields (no xpair: 0) or nine
+  while (!bad && std::fgets(line, sizeof line, f)) {
+    sv_tuning t = default_tuning();
+    char extra[8];
+    const int k = std::sscanf(line, "%127s %d %d %d %d %d %d %d %d %7s", a, &d, &dt, &t.zchain, &t.snake,
+                              &t.batch_waves_per_cu, &t.lockstep_mib, &t.pass_wgs_per_cu, &t.xpair, extra);
+    if (k <= 0) continue;  // blank line
+    if (k == 8) t.xpair = 0;
+    if (k != 8 && k != 9) {
+      bad = true;
+      break;
+    }
     if (arch != a) continue;
     if (d < 2 || d > 5 || (dt != SV_C64 && dt != SV_C128) || check_tuning(t) != SV_OK) {
       std::fclose(f);
@@ -2536,7 +2756,7 @@ sv_status sv_tuning_load(const char* path) {
   }
   const bool eof = std::feof(f) != 0;
   std::fclose(f);
-  if (!eof || k != EOF) return fail(SV_EINVAL, "cannot parse %s", path);
+  if (bad || !eof) return fail(SV_EINVAL, "cannot parse %s", path);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (const auto& kv : got) g_tune[kv.first] = kv.second;
   return SV_OK;

@@ -199,3 +199,13 @@ def test_batch_d4_real_shape_sample():
     oracle."""
     print("case batch real shape d=4 c64 n=4096", flush=True)
     _check_sample(4, "cr", "c64", 4096, seed=65, p_range=(5e-4, 5e-3))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_d4_x_pairs(dtype, monkeypatch):
+    """Lockstep d=4 passes with pairs of X checks (QECSV_XPAIR=1), over
+    several lockstep groups."""
+    monkeypatch.setenv("QECSV_XPAIR", "1")
+    monkeypatch.setenv("QECSV_LOCKSTEP_MIB", "2")
+    print(f"case batch d=4 x pairs {dtype}", flush=True)
+    _check(4, "cr", dtype, 12, seed=67, p_range=(5e-3, 3e-2), zeta=0.01)

@@ -97,3 +97,12 @@ def test_d5_live_x_basis(monkeypatch):
 def test_d5_live_idle_noise(monkeypatch):
     """One-qubit noise on the waiting qubits of every step, p = 1e-2."""
     _compare("idle", "c64", BENCH_TUNING, monkeypatch)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_d5_live_x_pairs(dtype, monkeypatch):
+    """Pairs of X checks (QECSV_XPAIR=1: (X0,X1), (X2,X3), (X10,X11) of
+    Table I's order, 12 passes a round) in the benchmark's launch
+    configuration."""
+    g = _compare("base", dtype, dict(BENCH_TUNING, QECSV_XPAIR="1"), monkeypatch)
+    assert g["passes_per_round"] == 12

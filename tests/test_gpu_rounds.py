@@ -293,3 +293,42 @@ def test_zz_plaquette_graph_and_d5():
     assert np.array_equal(a["records"], b["records"]) and np.array_equal(a["p1"], b["p1"])
     g = qs.run_rounds(5, "cr", 1, 1, 18, 1e-3, eps=0.01, zeta=0.01, dtype="c64", zz_plaquette=True)
     assert g["records"].shape == (1, 1, 24)
+
+
+# ---------------------------------------------------- pairs of X checks
+# With QECSV_XPAIR=1 a pass sums two consecutive X checks (the second for
+# each outcome of the first, after the first's Kraus operator and ZZ layer)
+# wherever both units' qubits fit one tile; d=4 then runs 7 passes a round
+# (pairs (X0,X1), (X2,X3), (X6,X7)), d=5 12.  Enough noise that frames of the
+# pair members and Pauli-X frames occur.
+@pytest.mark.parametrize("chain", [1, 2, 4])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_x_pairs_parity_d4(monkeypatch, dtype, chain):
+    monkeypatch.setenv("QECSV_XPAIR", "1")
+    monkeypatch.setenv("QECSV_ZCHAIN", str(chain))
+    n_sites = oracle.template_counts(4, oracle.GATESET_CR)[1]
+    eps = workloads.eps_sites(n_sites, (0.0, 0.05), 71)
+    g = _compare(4, "cr", 3, 4, seed=71, p=0.03, eps_site=eps, zeta=0.02, dtype=dtype,
+                 atol=1e-10 if dtype == "c128" else 1e-5)
+    assert g["passes_per_round"] == qs.check_pass_layouts(4, "cr", chain, 1) - 2
+    assert g["passes_per_round"] < qs.check_pass_layouts(4, "cr", chain, 0) - 2
+
+
+@pytest.mark.parametrize("flags", ["textbook", "xbasis", "idle", "twirl", "virtual_z"])
+def test_x_pairs_parity_d4_flags(monkeypatch, flags):
+    """Pairs under the textbook gate set and the physical-schedule flags (the
+    X basis starts from logical |+> in the pass that sums the first pair)."""
+    monkeypatch.setenv("QECSV_XPAIR", "1")
+    gs = "textbook" if flags == "textbook" else "cr"
+    _compare(4, gs, 2, 3, seed=73, p=0.02, eps=0.03, zeta=0.01, xbasis=flags == "xbasis",
+             idle=flags == "idle", twirl=flags == "twirl", virtual_z=flags == "virtual_z")
+
+
+def test_x_pairs_graph_replay(monkeypatch):
+    monkeypatch.setenv("QECSV_XPAIR", "1")
+    kw = dict(d=4, gateset="cr", rounds=2, n_traj=3, seed=77, p=0.02, eps=0.02, zeta=0.01, want_p1=True)
+    a = qs.run_rounds(**kw)
+    b = qs.run_rounds(graph=True, **kw)
+    assert np.array_equal(a["records"], b["records"])
+    assert np.array_equal(a["final_bits"], b["final_bits"])
+    assert np.max(np.abs(a["p1"] - b["p1"])) < 1e-12

@@ -151,5 +151,49 @@ def test_pass_layouts_are_consistent(d, gateset):
         n_z = (d * d - 1) - n_x
         # one pass per X check and per chain, plus the first and the last
         assert qs.check_pass_layouts(d, gateset, zchain) == n_x + -(-n_z // zchain) + 2
+        assert qs.check_pass_layouts(d, gateset, zchain, 0) == n_x + -(-n_z // zchain) + 2
     with pytest.raises(qs.SvError):
         qs.check_pass_layouts(d, gateset, 5)
+
+
+def _pair_fits(qubit_sets):
+    """A pass with a pair needs the qubits of the X members of both its units
+    and the three lowest bits in one tile of 2^12 amplitudes."""
+    u = set(range(3))
+    for q in qubit_sets:
+        u |= q
+    return len(u) <= 12
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+@pytest.mark.parametrize("d", [2, 3, 4, 5])
+def test_x_pair_layouts(d, gateset):
+    """With pairs of consecutive X checks (xpair = 1) every pass layout still
+    checks out.  Below 12 qubits no pairs form.  At d = 4 and 5 the X checks
+    of a round take the fewest units whose passes fit one tile (brute force
+    over the cuts of Table I's X order into singles and pairs, with the
+    neighbouring Z chain and logical |0> around the run)."""
+    xs = [frozenset(q - 1 for q in s if q) for t, s in oracle.layout(d) if t == "X"]
+    n_x, n_z = len(xs), (d * d - 1) - len(xs)
+
+    def cuts(i):
+        if i == n_x:
+            yield []
+            return
+        for l in (1, 2):
+            if i + l <= n_x:
+                for rest in cuts(i + l):
+                    yield [xs[i:i + l]] + rest
+
+    best = n_x
+    if d * d >= 12:
+        for c in cuts(0):
+            ok = all(_pair_fits(a + b) for a, b in zip(c, c[1:]) if len(a) == 2 or len(b) == 2)
+            ok = ok and all(_pair_fits(u) for u in (c[0], c[-1]))  # from |0>, into the Z chain
+            if ok:
+                best = min(best, len(c))
+    assert best < n_x or d < 4
+    for zchain in (1, 2, 3, 4):
+        assert qs.check_pass_layouts(d, gateset, zchain, 1) == best + -(-n_z // zchain) + 2
+    with pytest.raises(qs.SvError):
+        qs.check_pass_layouts(d, gateset, 4, 2)

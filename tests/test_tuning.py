@@ -12,7 +12,9 @@ import oracle
 import paper_2204_11404_amd as qs
 import workloads
 
-FIELDS = {"zchain", "snake", "batch_waves_per_cu", "lockstep_mib", "pass_wgs_per_cu"}
+FIELDS = {"zchain", "snake", "batch_waves_per_cu", "lockstep_mib", "pass_wgs_per_cu", "xpair"}
+ENV = ("QECSV_ZCHAIN", "QECSV_SNAKE", "QECSV_BATCH_WAVES_PER_CU", "QECSV_LOCKSTEP_MIB",
+       "QECSV_PASS_WGS_PER_CU", "QECSV_XPAIR")
 
 
 @pytest.fixture(autouse=True)
@@ -24,11 +26,10 @@ def _restore_tuning():
 
 
 def test_defaults_and_roundtrip(monkeypatch):
-    for var in ("QECSV_ZCHAIN", "QECSV_SNAKE", "QECSV_BATCH_WAVES_PER_CU", "QECSV_LOCKSTEP_MIB",
-                "QECSV_PASS_WGS_PER_CU"):
+    for var in ENV:
         monkeypatch.delenv(var, raising=False)
     t = qs.tuning_get(5, "c128")
-    assert set(t) == FIELDS and 1 <= t["zchain"] <= 4
+    assert set(t) == FIELDS and 1 <= t["zchain"] <= 4 and t["xpair"] == 0
     qs.tuning_set(5, "c128", zchain=2, snake=0)
     assert qs.tuning_get(5, "c128")["zchain"] == 2
     assert qs.tuning_get(5, "c128")["snake"] == 0
@@ -36,15 +37,17 @@ def test_defaults_and_roundtrip(monkeypatch):
 
 
 def test_environment_overrides(monkeypatch):
-    qs.tuning_set(4, "c64", zchain=4)
+    qs.tuning_set(4, "c64", zchain=4, xpair=0)
     monkeypatch.setenv("QECSV_ZCHAIN", "1")
+    monkeypatch.setenv("QECSV_XPAIR", "1")
     assert qs.tuning_get(4, "c64")["zchain"] == 1
+    assert qs.tuning_get(4, "c64")["xpair"] == 1
 
 
 @pytest.mark.parametrize("bad", [dict(zchain=0), dict(zchain=5), dict(snake=2),
                                  dict(batch_waves_per_cu=0), dict(batch_waves_per_cu=33),
                                  dict(lockstep_mib=0), dict(pass_wgs_per_cu=-1),
-                                 dict(pass_wgs_per_cu=65)])
+                                 dict(pass_wgs_per_cu=65), dict(xpair=2), dict(xpair=-1)])
 def test_rejects_out_of_range(bad):
     with pytest.raises(qs.SvError):
         qs.tuning_set(3, "c64", **bad)
@@ -53,14 +56,22 @@ def test_rejects_out_of_range(bad):
 
 
 def test_save_load(tmp_path, monkeypatch):
-    monkeypatch.delenv("QECSV_ZCHAIN", raising=False)
-    qs.tuning_set(4, "c128", zchain=3, lockstep_mib=1024)
+    for var in ENV:
+        monkeypatch.delenv(var, raising=False)
+    qs.tuning_set(4, "c128", zchain=3, lockstep_mib=1024, xpair=1)
     path = str(tmp_path / "tune.txt")
     qs.tuning_save(path)
-    qs.tuning_set(4, "c128", zchain=4, lockstep_mib=4096)
+    qs.tuning_set(4, "c128", zchain=4, lockstep_mib=4096, xpair=0)
     qs.tuning_load(path)
     t = qs.tuning_get(4, "c128")
-    assert t["zchain"] == 3 and t["lockstep_mib"] == 1024
+    assert t["zchain"] == 3 and t["lockstep_mib"] == 1024 and t["xpair"] == 1
+    # a file written before the xpair field (eight fields a line) still loads
+    old = str(tmp_path / "old.txt")
+    with open(path) as f, open(old, "w") as g:
+        for line in f:
+            g.write(" ".join(line.split()[:8]) + "\n")
+    qs.tuning_load(old)
+    assert qs.tuning_get(4, "c128")["xpair"] == 0
     with open(path, "a") as f:
         f.write("garbage line\n")
     with pytest.raises(qs.SvError):
@@ -72,13 +83,13 @@ def test_save_load(tmp_path, monkeypatch):
 @pytest.mark.gpu
 @pytest.mark.parametrize("d,dtype", [(3, "c64"), (4, "c64"), (5, "c128")])
 def test_autotune_then_parity(d, dtype, monkeypatch):
-    for var in ("QECSV_ZCHAIN", "QECSV_SNAKE", "QECSV_BATCH_WAVES_PER_CU", "QECSV_LOCKSTEP_MIB",
-                "QECSV_PASS_WGS_PER_CU"):
+    for var in ENV:
         monkeypatch.delenv(var, raising=False)
     print(f"case autotune d={d} {dtype}", flush=True)
     best, ms = qs.autotune(d, dtype)
     assert ms > 0.0
     assert qs.tuning_get(d, dtype) == best
+    assert best["xpair"] in (0, 1)
     if d == 5:
         assert best["zchain"] in (2, 3, 4) and best["snake"] in (0, 1)
         assert best["pass_wgs_per_cu"] in (0, 3, 4, 6, 8, 12, 16)
