@@ -769,16 +769,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
     const Decision* __restrict__ dec_a, Decision* __restrict__ dec_b,
     double* __restrict__ partials, int reverse, SlotStrides ss,
     const BlockDense* __restrict__ dna, const BlockDense* __restrict__ dnb) {
-  st += (size_t)blockIdx.y * ss.st;
-  if (rta) rta += (size_t)blockIdx.y * ss.rt;
-  if (rtb) rtb += (size_t)blockIdx.y * ss.rt;
-  if (dna) dna += (size_t)blockIdx.y * ss.rt;
-  if (dnb) dnb += (size_t)blockIdx.y * ss.rt;
-  if (dec_a) dec_a += (size_t)blockIdx.y * ss.dec;
-  dec_b += (size_t)blockIdx.y * ss.dec;
+  // trajectory slot (lockstep launches): walked backwards with the tiles, so
+  // that a pass starts on the registers its predecessor wrote last
+  const size_t slot = reverse ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
+  st += slot * ss.st;
+  if (rta) rta += slot * ss.rt;
+  if (rtb) rtb += slot * ss.rt;
+  if (dna) dna += slot * ss.rt;
+  if (dnb) dnb += slot * ss.rt;
+  if (dec_a) dec_a += slot * ss.dec;
+  dec_b += slot * ss.dec;
   const int n_tiles = 1 << pd->n_outer;
   // one partial sum per workgroup (over its tiles, in tile order): [acc][gridDim.x]
-  partials += (size_t)blockIdx.y * kChainAcc * gridDim.x;
+  partials += slot * kChainAcc * gridDim.x;
   __shared__ C2<T> da[kChainMax][16];
   __shared__ double wt[kChainMax][2][16];
   __shared__ C2<T> zzt[4 * 40 + 1];

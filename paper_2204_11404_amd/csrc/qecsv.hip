@@ -607,6 +607,21 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
     for (int q : J) m |= 1u << q;
     return m;
   };
+  // slots of the regrouping layout 2: `fixed` first, then layout 1's slot
+  // bits, then the lowest bits, outside `avoid`.  Layout 2's slot bits join
+  // the tile and take the place of low bits among layout 1's thread bits, so
+  // reusing layout 1's bits, else low ones, keeps layout 1's lanes on the
+  // lowest bits (long contiguous runs per load and store)
+  auto slots2 = [&](std::vector<int> fixed, uint32_t avoid, std::vector<int>& out) {
+    out = fixed;
+    uint32_t used = avoid;
+    for (int q : fixed) used |= 1u << q;
+    for (int q : J1)
+      if ((int)out.size() < 4 && !((used >> q) & 1)) { out.push_back(q); used |= 1u << q; }
+    for (int bit = 0; bit < n && (int)out.size() < 4; ++bit)
+      if (!((used >> bit) & 1)) { out.push_back(bit); used |= 1u << bit; }
+    return (int)out.size() == 4;
+  };
   if (pairpass) {
     // second members: their qubits on the register slots (fillers anywhere)
     if (apair) pslots(xqubits(A, 1), 0u, 0xFu, Jp[0]);
@@ -632,14 +647,14 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
     if (in_regs) {
       pd.bmode = 1;
     } else {
-      slots(bq, 0u, J2);
+      slots2(bq, 0u, J2);
       have2 = true;
       pd.bmode = 2;
     }
   } else if (bz) {
     if ((jmask(J1) & UB) == 0) {
       pd.bmode = 1;
-    } else if (slots({}, UB, J2)) {
+    } else if (slots2({}, UB, J2)) {
       have2 = true;
       pd.bmode = 2;
     } else {
@@ -1674,6 +1689,15 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
   HIP_OK(hipEventCreate(&ev.b));
   const dim3 block((unsigned)std::max(64, 1 << (tb - 4)));
   const SlotStrides ss{reg, (size_t)ns, dec_stride};
+  // pass workgroups per slot, each taking tiles grid-stride: four tiles each
+  // for passes that sum a Z chain or write logical |0> (their tables - up to
+  // four chain members' weights, a phase table per layer count - are loaded
+  // once for four tiles: d=4 Z-chain passes 216-253 -> 201-202 ns per slot),
+  // one tile each for the X-check passes (183 ns per slot; 199 with four)
+  auto gx_of = [&](const UnitPass& p) {
+    const bool heavy = p.bkind == U_Z || p.akind == U_INIT;
+    return (unsigned)std::max<size_t>(1, heavy ? n_tiles / 4 : n_tiles);
+  };
   std::vector<uint64_t> hseed(G), hstream(G);
   std::vector<double> hp(G), heps((size_t)n_sites * G);
   std::vector<int> hrounds(G);
@@ -1714,17 +1738,18 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
                          ns, r, tp.n_draws, dseed, dstream, dp, dcs, n_sites, slots, out, derr);
     };
     // outcomes of unit u of round r (tables of that round at rt)
-    auto decide = [&](int slots, const BlockRT* rt, int r, int u) {
+    // outcomes from the partials of a pass of gx workgroups per slot
+    auto decide = [&](int slots, const BlockRT* rt, int r, int u, unsigned gx) {
       const int bi = r * ns + units[u].first;
       const int lb = units[u].len;
-      hipLaunchKernelGGL(k_udecide, dim3(slots), dim3(64), 0, s, partials, (int)n_tiles, lb,
+      hipLaunchKernelGGL(k_udecide, dim3(slots), dim3(64), 0, s, partials, (int)gx, lb,
                          rt + units[u].first, ddec + (size_t)r * nu + u, drec + bi, (double*)nullptr,
                          ss, (size_t)per_traj, dacc, dticket, 0);
     };
     prepare(0, rtA, gn);
-    SV_OK_OR_RETURN(launch_upass<T>(pds[0], dim3((unsigned)n_tiles, gn), block, s, st, &dpass[0], djc,
+    SV_OK_OR_RETURN(launch_upass<T>(pds[0], dim3(gx_of(pds[0]), gn), block, s, st, &dpass[0], djc,
                                     nullptr, rtA + units[0].first, nullptr, ddec, partials, 0, ss));
-    decide(gn, rtA, 0, 0);
+    decide(gn, rtA, 0, 0, gx_of(pds[0]));
     const int R0 = hrounds[0];
     for (int r = 0; r < R0; ++r) {
       const int Ar = active(r), An = active(r + 1);
@@ -1736,22 +1761,22 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
         const int rev = (++pass_no) & 1;
         const BlockRT* rta = rt_cur + units[u].first;
         if (u < nu - 1) {
-          SV_OK_OR_RETURN(launch_upass<T>(pds[1 + u], dim3((unsigned)n_tiles, Ar), block, s, st,
+          SV_OK_OR_RETURN(launch_upass<T>(pds[1 + u], dim3(gx_of(pds[1 + u]), Ar), block, s, st,
                                           &dpass[1 + u], djc, rta, rt_cur + units[u + 1].first,
                                           ddec + ui, ddec + ui + 1, partials, rev, ss));
-          decide(Ar, rt_cur, r, u + 1);
+          decide(Ar, rt_cur, r, u + 1, gx_of(pds[1 + u]));
           continue;
         }
         if (An > 0) {
-          SV_OK_OR_RETURN(launch_upass<T>(pds[1 + u], dim3((unsigned)n_tiles, An), block, s, st,
+          SV_OK_OR_RETURN(launch_upass<T>(pds[1 + u], dim3(gx_of(pds[1 + u]), An), block, s, st,
                                           &dpass[1 + u], djc, rta, rt_nxt + units[0].first,
                                           ddec + ui, ddec + ui + 1, partials, rev, ss));
-          decide(An, rt_nxt, r + 1, 0);
+          decide(An, rt_nxt, r + 1, 0, gx_of(pds[1 + u]));
         }
         if (Ar > An) {  // trajectories ending with this round
           const int cnt = Ar - An;
           Decision* dfin = ddec + (size_t)An * dec_stride + ui + 1;
-          SV_OK_OR_RETURN(launch_upass<T>(pds[nu + 1], dim3((unsigned)n_tiles, cnt), block, s,
+          SV_OK_OR_RETURN(launch_upass<T>(pds[nu + 1], dim3(gx_of(pds[nu + 1]), cnt), block, s,
                                           st + (size_t)An * reg, &dpass[nu + 1], djc,
                                           rta + (size_t)An * ns, nullptr,
                                           ddec + (size_t)An * dec_stride + ui, dfin, partials, rev, ss));
