@@ -1453,21 +1453,13 @@ __global__ __launch_bounds__(256) void k_final_sums(const T* __restrict__ st, in
   if (threadIdx.x == 0) sums[blockIdx.x] = s;
 }
 
-__device__ double range_sum(const double* buf, int lo, int len, double* red) {
-  double s = 0.0, dummy = 0.0;
-  for (int i = threadIdx.x; i < len; i += blockDim.x) s += buf[lo + i];
-  block_sum2(s, dummy, red);
-  __shared__ double bcast;
-  if (threadIdx.x == 0) bcast = s;
-  __syncthreads();
-  const double r = bcast;
-  __syncthreads();
-  return r;
-}
-
 // Sequential measurement of data qubits n-1 .. 0 (labels n .. 1) using the
 // chunk sums for the high n - cb bits and the selected chunk for the rest;
 // the register is read in the Pauli-X frame recorded in dfin (if given).
+// Each phase builds the pairwise sum tree of its leaves (the chunk sums, then
+// |psi|^2 over the selected chunk) in LDS, one level per step, and one thread
+// walks it from the root: at each level the two child sums give p1, the
+// qubit's draw picks a child.  The bottom level of leaves stays in memory.
 // Slot blockIdx.x: its register at st + slot * st_stride, its draw stream
 // (seed[slot], t[slot]) when the arrays are given, else (seed0, t0 + slot).
 template <typename T>
@@ -1490,51 +1482,49 @@ __global__ __launch_bounds__(1024) void k_final_measure(const T* __restrict__ st
   const uint64_t seed = seeds ? seeds[slot] : seed0;
   const uint64_t t = streams ? streams[slot] : t0 + (uint64_t)slot;
   if (rounds) k0 = (uint64_t)rounds[slot] * draws_round;
-  __shared__ double buf[8192];
-  __shared__ double red[32];
+  __shared__ double tree[8192];  // internal nodes of a tree of up to 2^13 leaves (node 1: root)
+  __shared__ int sel;
+  // qubits level0 .. level0 + h - 1 from a tree over the 2^h leaves leaf(i);
+  // returns the chosen leaf
+  auto descend = [&](int h, int level0, auto leaf) -> int {
+    if (h == 0) return 0;
+    const int N = 1 << h;
+    __syncthreads();
+    for (int k = N / 2 + (int)threadIdx.x; k < N; k += (int)blockDim.x) tree[k] = leaf(2 * k - N) + leaf(2 * k + 1 - N);
+    for (int lev = h - 2; lev >= 0; --lev) {
+      __syncthreads();
+      for (int k = (1 << lev) + (int)threadIdx.x; k < (2 << lev); k += (int)blockDim.x)
+        tree[k] = tree[2 * k] + tree[2 * k + 1];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int c = 1;
+      for (int i = 0; i < h; ++i) {
+        const int level = level0 + i;
+        const int fq = (phi >> (n - 1 - level)) & 1;
+        const bool bottom = i == h - 1;
+        const double P0 = bottom ? leaf(2 * c - N) : tree[2 * c];
+        const double P1 = bottom ? leaf(2 * c + 1 - N) : tree[2 * c + 1];
+        const double S0 = fq ? P1 : P0, S1 = fq ? P0 : P1;
+        const double p1 = clamp_p1(S1 / (S0 + S1));
+        const double u = uniform(seed, t, k0 + (uint64_t)level);
+        const int b = (u < p1) ? 1 : 0;
+        bits[n - 1 - level] = (uint8_t)b;
+        c = 2 * c + (b ^ fq);
+      }
+      sel = c - N;
+    }
+    __syncthreads();
+    return sel;
+  };
   const int hb = n - cb;  // bits resolved by chunk sums
-  const int nchunk = 1 << hb;
-  for (int i = threadIdx.x; i < nchunk; i += blockDim.x) buf[i] = sums[i];
-  __syncthreads();
-  int lo = 0, size = nchunk;
-  int level = 0;
-  for (; level < hb; ++level) {
-    const int half = size >> 1;
-    const double P0 = range_sum(buf, lo, half, red);
-    const double P1 = range_sum(buf, lo + half, half, red);
-    const int fq = (phi >> (n - 1 - level)) & 1;
-    const double S0 = fq ? P1 : P0, S1 = fq ? P0 : P1;
-    const double p1 = clamp_p1(S1 / (S0 + S1));
-    const double u = uniform(seed, t, k0 + (uint64_t)level);
-    const int b = (u < p1) ? 1 : 0;
-    if (threadIdx.x == 0) bits[n - 1 - level] = (uint8_t)b;
-    if (b ^ fq) lo += half;
-    size = half;
-  }
-  const uint64_t cbase = (uint64_t)lo << cb;
-  const int len = 1 << cb;
-  __syncthreads();
-  for (int i = threadIdx.x; i < len; i += blockDim.x) {
-    const C2<T> a = ld2(st, cbase + i);
+  const int chunk = descend(hb, 0, [&](int i) { return sums[i]; });
+  const uint64_t cbase = (uint64_t)chunk << cb;
+  descend(cb, hb, [&](int i) {
+    const C2<T> a = ld2(st, cbase + (uint64_t)i);
     const double re = (double)a.re, im = (double)a.im;
-    buf[i] = re * re + im * im;
-  }
-  __syncthreads();
-  lo = 0;
-  size = len;
-  for (; level < n; ++level) {
-    const int half = size >> 1;
-    const double P0 = range_sum(buf, lo, half, red);
-    const double P1 = range_sum(buf, lo + half, half, red);
-    const int fq = (phi >> (n - 1 - level)) & 1;
-    const double S0 = fq ? P1 : P0, S1 = fq ? P0 : P1;
-    const double p1 = clamp_p1(S1 / (S0 + S1));
-    const double u = uniform(seed, t, k0 + (uint64_t)level);
-    const int b = (u < p1) ? 1 : 0;
-    if (threadIdx.x == 0) bits[n - 1 - level] = (uint8_t)b;
-    if (b ^ fq) lo += half;
-    size = half;
-  }
+    return re * re + im * im;
+  });
 }
 
 // Replayed trajectories: copy the staged records, p1 trace and final bits of
