@@ -38,6 +38,37 @@ __device__ __forceinline__ void st2(T* p, uint64_t i, C2<T> v) {
   }
 }
 
+// The register through a buffer resource: an amplitude's byte offset is a
+// per-thread part (VGPR) plus a per-slot part shared by the wave (SGPR), so
+// a pass's 16 loads and stores per thread need no per-amplitude address
+// arithmetic.  Offsets past `bytes` read 0 and drop stores.
+template <typename T>
+struct RegBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ RegBuf(T* p, uint32_t bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)bytes, 0x00020000)) {}  // raw dwords (gfx9)
+  __device__ C2<T> ld(uint32_t voff, uint32_t soff) const {
+    if constexpr (sizeof(T) == 8) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+      return {__hiloint2double((int)v[1], (int)v[0]), __hiloint2double((int)v[3], (int)v[2])};
+    } else {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+      return {__uint_as_float(v[0]), __uint_as_float(v[1])};
+    }
+  }
+  __device__ void st(uint32_t voff, uint32_t soff, C2<T> a) const {
+    if constexpr (sizeof(T) == 8) {
+      const unsigned long long x = __double_as_longlong(a.re), y = __double_as_longlong(a.im);
+      __attribute__((ext_vector_type(4))) unsigned v = {(unsigned)x, (unsigned)(x >> 32), (unsigned)y,
+                                                        (unsigned)(y >> 32)};
+      __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 0);
+    } else {
+      __attribute__((ext_vector_type(2))) unsigned v = {__float_as_uint(a.re), __float_as_uint(a.im)};
+      __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+    }
+  }
+};
+
 template <typename T>
 __device__ __forceinline__ C2<T> mulc(C2<T> a, T br, T bi) {
   return {a.re * br - a.im * bi, a.re * bi + a.im * br};
@@ -773,6 +804,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   // that a pass starts on the registers its predecessor wrote last
   const size_t slot = reverse ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
   st += slot * ss.st;
+  constexpr uint32_t kAmp = 2 * sizeof(T);  // bytes per amplitude
+  const RegBuf<T> reg(st, (uint32_t)(kAmp << (pd->tb + pd->n_outer)));
   if (rta) rta += slot * ss.rt;
   if (rtb) rtb += slot * ss.rt;
   if (dna) dna += slot * ss.rt;
@@ -851,8 +884,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   if (blockIdx.x == 0 && tid == 0) dec_b->phi = phi_new;
 
   // tables (the workgroup may have only 64 threads)
+  // an X check A's decided diagonal: in LDS for the lane-mixed layout, and
+  // in complex64 (converted once per workgroup rather than per tile)
   if constexpr (AK == U_X) {
-    if (pd->amix && tid < 16) da[0][tid] = C2<T>{(T)rta->D[mbits][tid][0], (T)rta->D[mbits][tid][1]};
+    if ((pd->amix || sizeof(T) == 4) && tid < 16)
+      da[0][tid] = C2<T>{(T)rta->D[mbits][tid][0], (T)rta->D[mbits][tid][1]};
   }
   if constexpr (AK == U_XP) {  // members' decided diagonals over 16 register slots
     if (tid < 32) {
@@ -1024,14 +1060,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
       const uint32_t rb = reduce(gb);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const uint32_t g = gb | pd->j_g[j];
         o[j] = {(rb ^ reduce(pd->j_g[j])) == 0 ? amp : (T)0, (T)0};
-        st2(st, g, o[j]);
+        reg.st(gb * kAmp, pd->j_g[j] * kAmp, o[j]);
       }
     } else {
       C2<T> v[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) v[j] = ld2(st, gb | pd->j_g[j]);
+      for (int j = 0; j < 16; ++j) v[j] = reg.ld(gb * kAmp, pd->j_g[j] * kAmp);
       if constexpr (AK == U_X) {
         if (DN && pd->adense) {  // dense Kraus pair (crosstalk inside the check)
           if constexpr (DN) {
@@ -1054,9 +1089,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
             v[j] = mulc(v[j], e.re, e.im);
           }
           wht_mixed(v, pd->amix_r, pd->amix_lanes, tid);
+          if (Fa) {  // frame signs (a Z-type Pauli on the check's qubits; rare)
 #pragma unroll
-          for (int j = 0; j < 16; ++j)
-            if (__popc((xl ^ pd->a_jx[j]) & Fa) & 1) v[j] = {-v[j].re, -v[j].im};
+            for (int j = 0; j < 16; ++j)
+              if (__popc((xl ^ pd->a_jx[j]) & Fa) & 1) v[j] = {-v[j].re, -v[j].im};
+          }
         } else {
           const double* D = &rta->D[mbits][0][0];
           constexpr int NA = 1 << WA;
@@ -1064,11 +1101,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
           for (int hi = 0; hi < 16; hi += NA) {
             wht<T, WA>(v + hi);
 #pragma unroll
-            for (int x = 0; x < NA; ++x) v[hi + x] = mulc(v[hi + x], (T)D[2 * x], (T)D[2 * x + 1]);
+            for (int x = 0; x < NA; ++x) {
+              if constexpr (sizeof(T) == 4) {
+                const C2<T> e = da[0][x];
+                v[hi + x] = mulc(v[hi + x], e.re, e.im);
+              } else {
+                v[hi + x] = mulc(v[hi + x], D[2 * x], D[2 * x + 1]);
+              }
+            }
             wht<T, WA>(v + hi);
+            if (Fa) {
 #pragma unroll
-            for (int x = 0; x < NA; ++x)
-              if (__popc((uint32_t)x & Fa) & 1) v[hi + x] = {-v[hi + x].re, -v[hi + x].im};
+              for (int x = 0; x < NA; ++x)
+                if (__popc((uint32_t)x & Fa) & 1) v[hi + x] = {-v[hi + x].re, -v[hi + x].im};
+            }
           }
         }
       } else if constexpr (AK == U_XP) {
@@ -1145,7 +1191,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           const uint32_t jg = pd->j_g[j];
-          const uint32_t g = gb | jg;
           C2<T> r = v[j];
           if (use_zz) {
             const uint32_t je = (jg ^ (jg >> 1)) & hm, jw = (jg ^ (jg >> d)) & vm;
@@ -1162,7 +1207,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
             r.re = (T)((double)r.re * scale);
             r.im = (T)((double)r.im * scale);
           }
-          st2(st, g, r);
+          reg.st(gb * kAmp, jg * kAmp, r);
           o[j] = r;
         }
       };

@@ -1678,15 +1678,24 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
   for (int i = 0; i < nt; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return in.rounds[a] > in.rounds[b]; });
+  // a: start, b: end; fork/join: the next round's Kraus pairs are built on a
+  // second stream while the current round's passes run
   struct Ev {
-    hipEvent_t a = nullptr, b = nullptr;
+    hipEvent_t a = nullptr, b = nullptr, fork = nullptr, join = nullptr;
+    hipStream_t s2 = nullptr;
     ~Ev() {
       if (a) (void)hipEventDestroy(a);
       if (b) (void)hipEventDestroy(b);
+      if (fork) (void)hipEventDestroy(fork);
+      if (join) (void)hipEventDestroy(join);
+      if (s2) (void)hipStreamDestroy(s2);
     }
   } ev;
   HIP_OK(hipEventCreate(&ev.a));
   HIP_OK(hipEventCreate(&ev.b));
+  HIP_OK(hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming));
+  HIP_OK(hipEventCreateWithFlags(&ev.join, hipEventDisableTiming));
+  HIP_OK(hipStreamCreateWithFlags(&ev.s2, hipStreamNonBlocking));
   const dim3 block((unsigned)std::max(64, 1 << (tb - 4)));
   const SlotStrides ss{reg, (size_t)ns, dec_stride};
   // pass workgroups per slot, each taking tiles grid-stride: four tiles each
@@ -1732,13 +1741,13 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
       hipLaunchKernelGGL(k_site_cs, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, dblocks, ns,
                          deps, n_sites, n_sites, gn, dcs);
     }
-    auto prepare = [&](int r, BlockRT* out, int slots) {
+    auto prepare = [&](hipStream_t q, int r, BlockRT* out, int slots) {
       const int64_t nth = (int64_t)slots * ns * 16;
-      hipLaunchKernelGGL(k_prepare_round, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, s, dblocks,
+      hipLaunchKernelGGL(k_prepare_round, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, q, dblocks,
                          ns, r, tp.n_draws, dseed, dstream, dp, dcs, n_sites, slots, out, derr);
     };
-    // outcomes of unit u of round r (tables of that round at rt)
-    // outcomes from the partials of a pass of gx workgroups per slot
+    // outcomes of unit u of round r (tables of that round at rt) from the
+    // partials of a pass of gx workgroups per slot
     auto decide = [&](int slots, const BlockRT* rt, int r, int u, unsigned gx) {
       const int bi = r * ns + units[u].first;
       const int lb = units[u].len;
@@ -1746,7 +1755,7 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
                          rt + units[u].first, ddec + (size_t)r * nu + u, drec + bi, (double*)nullptr,
                          ss, (size_t)per_traj, dacc, dticket, 0);
     };
-    prepare(0, rtA, gn);
+    prepare(s, 0, rtA, gn);
     SV_OK_OR_RETURN(launch_upass<T>(pds[0], dim3(gx_of(pds[0]), gn), block, s, st, &dpass[0], djc,
                                     nullptr, rtA + units[0].first, nullptr, ddec, partials, 0, ss));
     decide(gn, rtA, 0, 0, gx_of(pds[0]));
@@ -1755,9 +1764,17 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
       const int Ar = active(r), An = active(r + 1);
       BlockRT* rt_cur = (r & 1) ? rtB : rtA;
       BlockRT* rt_nxt = (r & 1) ? rtA : rtB;
-      if (An > 0) prepare(r + 1, rt_nxt, An);
+      if (An > 0) {
+        // rt_nxt was last read by the previous round's passes, enqueued above
+        HIP_OK(hipEventRecord(ev.fork, s));
+        HIP_OK(hipStreamWaitEvent(ev.s2, ev.fork, 0));
+        prepare(ev.s2, r + 1, rt_nxt, An);
+        HIP_OK(hipEventRecord(ev.join, ev.s2));
+      }
       for (int u = 0; u < nu; ++u) {
         const int ui = r * nu + u;
+        // the round's last pass sums the next round's first unit
+        if (u == nu - 1 && An > 0) HIP_OK(hipStreamWaitEvent(s, ev.join, 0));
         const int rev = (++pass_no) & 1;
         const BlockRT* rta = rt_cur + units[u].first;
         if (u < nu - 1) {
