@@ -69,6 +69,20 @@ struct RegBuf {
   }
 };
 
+// LDS slot offsets in bytes: a thread's part (kept opaque, so the compiler
+// does not fold the XOR back into a shift per access) XOR a slot's part
+// (uniform: shifted on the scalar unit); one vector XOR per access.
+template <typename E>
+__device__ __forceinline__ uint32_t lds_bytes(uint32_t thread_slot) {
+  uint32_t b = thread_slot * (uint32_t)sizeof(E);
+  asm volatile("" : "+v"(b));
+  return b;
+}
+template <typename E>
+__device__ __forceinline__ E& lds_at(E* buf, uint32_t thread_bytes, uint32_t slot) {
+  return *reinterpret_cast<E*>(reinterpret_cast<char*>(buf) + (thread_bytes ^ (slot * (uint32_t)sizeof(E))));
+}
+
 template <typename T>
 __device__ __forceinline__ C2<T> mulc(C2<T> a, T br, T bi) {
   return {a.re * br - a.im * bi, a.re * bi + a.im * br};
@@ -599,24 +613,25 @@ __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const
   for (int i = 0; i < pd->tb - 4; ++i)
     if ((threadIdx.x >> i) & 1) lt ^= pd->b_tid_l[i];
   C2<T> v[16];
+  const uint32_t wa = lds_bytes<T>(lt_a), rb = lds_bytes<T>(lt);
   if (active) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) buf[lt_a ^ pd->j_l[j]] = o[j].re;
+    for (int j = 0; j < 16; ++j) lds_at(buf, wa, pd->j_l[j]) = o[j].re;
   }
   __syncthreads();
   if (active) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j].re = buf[lt ^ pd->b_j_l[j]];
+    for (int j = 0; j < 16; ++j) v[j].re = lds_at(buf, rb, pd->b_j_l[j]);
   }
   __syncthreads();
   if (active) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) buf[lt_a ^ pd->j_l[j]] = o[j].im;
+    for (int j = 0; j < 16; ++j) lds_at(buf, wa, pd->j_l[j]) = o[j].im;
   }
   __syncthreads();
   if (active) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j].im = buf[lt ^ pd->b_j_l[j]];
+    for (int j = 0; j < 16; ++j) v[j].im = lds_at(buf, rb, pd->b_j_l[j]);
     constexpr int NB = 1 << WB;
     if constexpr (DN) {
       if (K0) {
@@ -650,8 +665,9 @@ __device__ __forceinline__ void xpose_xsums(const C2<T>* o, uint32_t lt_a, const
 __device__ __forceinline__ double xpose_norms(const double* a2, uint32_t lt_a, const UnitPass* pd,
                                               bool active, double* buf) {
   if (active) {
+    const uint32_t wa = lds_bytes<double>(lt_a);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) buf[lt_a ^ pd->j_l[j]] = a2[j];
+    for (int j = 0; j < 16; ++j) lds_at(buf, wa, pd->j_l[j]) = a2[j];
   }
   __syncthreads();
   double s = 0.0;
@@ -659,8 +675,9 @@ __device__ __forceinline__ double xpose_norms(const double* a2, uint32_t lt_a, c
     uint32_t lt = 0;
     for (int i = 0; i < pd->tb - 4; ++i)
       if ((threadIdx.x >> i) & 1) lt ^= pd->b_tid_l[i];
+    const uint32_t rb = lds_bytes<double>(lt);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) s += buf[lt ^ pd->b_j_l[j]];
+    for (int j = 0; j < 16; ++j) s += lds_at(buf, rb, pd->b_j_l[j]);
   }
   return s;
 }
@@ -674,18 +691,19 @@ __device__ __forceinline__ double xpose_norms(const double* a2, uint32_t lt_a, c
 template <typename T>
 __device__ __forceinline__ void regroup(const C2<T>* src, uint32_t lt_s, const uint32_t* jl_s, C2<T>* dst,
                                         uint32_t lt_d, const uint32_t* jl_d, T* buf) {
+  const uint32_t ws = lds_bytes<T>(lt_s), rd = lds_bytes<T>(lt_d);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 16; ++j) buf[lt_s ^ jl_s[j]] = src[j].re;
+  for (int j = 0; j < 16; ++j) lds_at(buf, ws, jl_s[j]) = src[j].re;
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 16; ++j) dst[j].re = buf[lt_d ^ jl_d[j]];
+  for (int j = 0; j < 16; ++j) dst[j].re = lds_at(buf, rd, jl_d[j]);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 16; ++j) buf[lt_s ^ jl_s[j]] = src[j].im;
+  for (int j = 0; j < 16; ++j) lds_at(buf, ws, jl_s[j]) = src[j].im;
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 16; ++j) dst[j].im = buf[lt_d ^ jl_d[j]];
+  for (int j = 0; j < 16; ++j) dst[j].im = lds_at(buf, rd, jl_d[j]);
 }
 
 // LDS of the X-pair code (passes with a pair only): the first B member's
