@@ -298,7 +298,7 @@ sv_status sv_decode_x(int d, int gateset, int rounds, int n_traj, const uint8_t*
  * QECSV_BATCH_WAVES_PER_CU, QECSV_LOCKSTEP_MIB, QECSV_PASS_WGS_PER_CU and
  * QECSV_XPAIR override them. */
 typedef struct sv_tuning {
-  int zchain;             /* longest chain of Z checks applied per register pass, 1..4 */
+  int zchain;             /* longest chain of Z checks applied per register pass, 1..6 */
   int snake;              /* 1: consecutive passes walk the tiles in opposite orders */
   int batch_waves_per_cu; /* sv_run_batch, d <= 3: resident waves per compute unit, 1..32 */
   int lockstep_mib;       /* sv_run_batch, d = 4: MiB of registers run in lockstep */

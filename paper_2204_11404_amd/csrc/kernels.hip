@@ -784,6 +784,42 @@ __device__ __forceinline__ void chain_levels(double a2, const uint32_t* x, const
   }
 }
 
+// One 16-value group of the same tree at level L >= 3: sums (L, h) for
+// h = 16 G + i, i < 16 (members 0..3 take i's bits, member l >= 4 the fixed
+// outcome bit (G >> (l - 4)) & 1), added to out[i].
+template <int L, int G>
+__device__ __forceinline__ void chain_group(double a2, const uint32_t* x, const double (*wt)[2][16],
+                                            double* out) {
+  double f = a2;
+#pragma unroll
+  for (int l = 4; l <= L; ++l) f *= wt[l][(G >> (l - 4)) & 1][x[l]];
+  double p[16];
+  p[0] = f;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const double w0 = wt[l][0][x[l]], w1 = wt[l][1][x[l]];
+#pragma unroll
+    for (int h = 0; h < (1 << l); ++h) {
+      p[h + (1 << l)] = p[h] * w1;
+      p[h] *= w0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) out[i] += p[i];
+}
+
+// Sum groups of a chain of LB >= 3 members reduced across the wave: group 0
+// holds levels 0..2 (14 sums), then level 3 (16), level 4 (2 x 16), level 5
+// (4 x 16).
+template <int LB>
+struct ChainGroups {
+  static constexpr int value = 1 + (LB >= 4 ? 1 : 0) + (LB >= 5 ? 2 : 0) + (LB >= 6 ? 4 : 0);
+};
+// First sum index of group k (level L, group G: 2^(L+1) - 2 + 16 G).
+__host__ __device__ constexpr int chain_group_base(int k) {
+  return k == 0 ? 0 : (k == 1 ? 14 : (k < 4 ? 30 + 16 * (k - 2) : 62 + 16 * (k - 4)));
+}
+
 // One pass over the register: apply unit A with its decided outcomes (or
 // write logical |0> when A is U_INIT), each member's ZZ layer and the
 // renormalisation 1/sqrt(S_m); accumulate the sums of unit B from the values
@@ -835,8 +871,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   partials += slot * kChainAcc * gridDim.x;
   __shared__ C2<T> da[kChainMax][16];
   __shared__ double wt[kChainMax][2][16];
-  __shared__ C2<T> zzt[4 * 40 + 1];
-  __shared__ double red[kChainAcc][4];
+  // phase table of A's ZZ layers and the per-wave sums of B, sized for the
+  // units of this instantiation
+  constexpr int kLayers = AK == U_Z ? AP : 1;
+  constexpr int kSums = BK == U_Z ? (2 << BP) - 2 : (BK == U_XP ? 6 : 2);
+  __shared__ C2<T> zzt[kLayers * kMaxEdges + 1];
+  __shared__ double red[kSums][4];
   const int tid = threadIdx.x;
   const int tb = pd->tb;
   const int nt = 1 << (tb - 4);
@@ -864,8 +904,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
     mbits = dec_a->m;
     scale = 1.0 / sqrt(dec_a->Sm);
   }
-  uint32_t M[kChainMax] = {phi, phi, phi, phi};  // logical-index masks of A's ZZ layers
-  uint32_t ca[kChainMax] = {0, 0, 0, 0};         // member-local input offsets
+  uint32_t M[kChainMax];   // logical-index masks of A's ZZ layers
+  uint32_t ca[kChainMax];  // member-local input offsets
+#pragma unroll
+  for (int i = 0; i < kChainMax; ++i) {
+    M[i] = phi;
+    ca[i] = 0;
+  }
   uint32_t phi_new = phi;
   uint32_t Fa = 0, Fa1 = 0;
   if constexpr (AK == U_X) {
@@ -889,7 +934,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
       }
     phi_new = phi ^ G;
   }
-  uint32_t cb[kChainMax] = {0, 0, 0, 0};
+  uint32_t cb[kChainMax];
+#pragma unroll
+  for (int i = 0; i < kChainMax; ++i) cb[i] = 0;
   if constexpr (BK == U_Z) {
     uint32_t G = 0;
 #pragma unroll
@@ -1038,15 +1085,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   // grid-stride over the tiles (one tile per workgroup when the grid covers
   // them all); the tables above are loaded once per workgroup, the sums of B
   // accumulate over the workgroup's tiles
-  // Z chains of three or four checks (14 or 30 sums): the tile's sums of
-  // levels 0..2 (14) and of level 3 (16) are formed and reduced across the
-  // wave one group at a time; each lane keeps one running total per group
-  // (lane l: sum (l >> 1) & 15 of the group), so neither 30 accumulators nor
-  // a 30-value tree stays live
+  // Z chains of three to six checks (14 to 126 sums): the tile's sums are
+  // formed and reduced across the wave one 16-value group at a time (levels
+  // 0..2, then level 3, 4 and 5 in groups of 16); each lane keeps one running
+  // total per group (lane l: sum (l >> 1) & 15 of the group), so neither the
+  // accumulators of every sum nor a whole tree stays live
   constexpr bool kWaveAcc = BK == U_Z && LB >= 3;
-  double acc[kWaveAcc ? 2 : 32];
+  constexpr int kAcc = kWaveAcc ? ChainGroups<LB>::value : 32;
+  double acc[kAcc];
 #pragma unroll
-  for (int a = 0; a < (kWaveAcc ? 2 : 32); ++a) acc[a] = 0.0;
+  for (int a = 0; a < kAcc; ++a) acc[a] = 0.0;
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
   const int wg = reverse ? n_tiles - 1 - tile : tile;
   uint32_t base = 0;
@@ -1316,17 +1364,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
         chain_levels<L0, L1>(s, ob, wt, t);
       }
     };
+    // group G of level L >= 3 into t
+    auto group = [&](auto lv, auto gv, double* t) {
+      constexpr int L = decltype(lv)::value, G = decltype(gv)::value;
+      if (!active) return;
+      if constexpr (BM0) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          uint32_t x[kChainMax];
+#pragma unroll
+          for (int i = 0; i < kChainMax; ++i) x[i] = ob[i] ^ pd->b_j_loc[i][j];
+          chain_group<L, G>(a2[j], x, wt, t);
+        }
+      } else {
+        chain_group<L, G>(s, ob, wt, t);
+      }
+    };
     if constexpr (kWaveAcc) {
       double t[16];
-#pragma unroll
-      for (int a = 0; a < 16; ++a) t[a] = 0.0;
-      tree(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, t);
-      acc[0] += wave_reduce16(t);
-      if constexpr (LB == 4) {
+      auto one = [&](auto kv, auto lv, auto gv) {
+        constexpr int K = decltype(kv)::value;
 #pragma unroll
         for (int a = 0; a < 16; ++a) t[a] = 0.0;
-        tree(std::integral_constant<int, 3>{}, std::integral_constant<int, 4>{}, t);
-        acc[1] += wave_reduce16(t);
+        if constexpr (K == 0)
+          tree(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, t);
+        else
+          group(lv, gv, t);
+        acc[K] += wave_reduce16(t);
+      };
+      using std::integral_constant;
+      one(integral_constant<int, 0>{}, integral_constant<int, 0>{}, integral_constant<int, 0>{});
+      if constexpr (LB >= 4) one(integral_constant<int, 1>{}, integral_constant<int, 3>{}, integral_constant<int, 0>{});
+      if constexpr (LB >= 5) {
+        one(integral_constant<int, 2>{}, integral_constant<int, 4>{}, integral_constant<int, 0>{});
+        one(integral_constant<int, 3>{}, integral_constant<int, 4>{}, integral_constant<int, 1>{});
+      }
+      if constexpr (LB >= 6) {
+        one(integral_constant<int, 4>{}, integral_constant<int, 5>{}, integral_constant<int, 0>{});
+        one(integral_constant<int, 5>{}, integral_constant<int, 5>{}, integral_constant<int, 1>{});
+        one(integral_constant<int, 6>{}, integral_constant<int, 5>{}, integral_constant<int, 2>{});
+        one(integral_constant<int, 7>{}, integral_constant<int, 5>{}, integral_constant<int, 3>{});
       }
     } else {
       tree(std::integral_constant<int, 0>{}, std::integral_constant<int, LB>{}, acc);
@@ -1398,7 +1475,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
       if ((lane & 1) == 0 && lane < 32) {
         const int a = lane >> 1;
         if (a < 14) red[a][wid] = acc[0];
-        if constexpr (LB == 4) red[14 + a][wid] = acc[1];
+#pragma unroll
+        for (int k = 1; k < kAcc; ++k) red[chain_group_base(k) + a][wid] = acc[k];
       }
     } else {
       const double s = wave_reduce32(acc);

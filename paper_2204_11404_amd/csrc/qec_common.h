@@ -527,6 +527,11 @@ QEC_HD void draw_block(const TBlock& b, uint64_t seed, uint64_t t, uint64_t k0, 
   *u_meas = uniform(seed, t, k0 + (uint64_t)(b.n_draws - 1));
 }
 
+// Longest chain of Z checks one register pass applies or sums, and the sums
+// of a full chain (every outcome prefix: 2^(L+1) - 2).
+constexpr int kChainMax = 6;
+constexpr int kChainAcc = (2 << kChainMax) - 2;
+
 struct JobConst {
   int d;
   int n;               // data qubits
@@ -540,7 +545,7 @@ struct JobConst {
   int use_zz;
   int init_plus;           // 1: the first pass writes logical |+> (X-basis memory)
   // L consecutive ZZ layers: exp(-i zeta (L |E| - 2K)), K = 0..L|E|, L = 1..kChainMax
-  double zzl[4][2 * (4 * 40 + 1)];
+  double zzl[kChainMax][2 * (kChainMax * 40 + 1)];
   int n_zc;                // Z checks
   uint32_t zc_mask[16];    // data bits of each Z check
 };
@@ -556,7 +561,7 @@ struct Decision {
 
 // ------------------------------------------------------------ pass units --
 // The trajectory engine runs one HBM pass per "unit": a single X check, or a
-// chain of up to kChainMax consecutive Z checks.  Z checks are monomial in the
+// chain of up to kChainMax (six) consecutive Z checks.  Z checks are monomial in the
 // computational basis (diag(D_m), then an XOR permutation by F), so a chain is
 // pointwise on the amplitude index: its S_m for every prefix of outcomes
 // (a binary tree of 2^(L+1) - 2 sums) comes out of one read of the register,
@@ -575,8 +580,6 @@ struct Decision {
 // A pair's members may have weight 2 or 4: a weight-2 member is handled as a
 // 16-element group over four register slots (its two qubits and two others)
 // with its tables repeated over the other two bits and divided by 4.
-constexpr int kChainMax = 4;
-constexpr int kChainAcc = (2 << kChainMax) - 2;  // sums of a full chain
 enum : int { U_NONE = 0, U_X = 1, U_Z = 2, U_INIT = 3, U_XP = 4 };
 
 // Layout and unit description of one pass: apply unit A (decided), accumulate

@@ -390,7 +390,7 @@ std::map<TuneKey, sv_tuning> g_tune;
 
 sv_tuning default_tuning() {
   sv_tuning t{};
-  t.zchain = kChainMax;
+  t.zchain = 4;  // chains of five or six: the autotuner's choice
   t.snake = 1;
   t.batch_waves_per_cu = 8;
   t.lockstep_mib = 4096;
@@ -859,18 +859,20 @@ sv_status launch_upass(const UnitPass& h, dim3 g, dim3 b, hipStream_t s, T* st, 
   }
 #define QEC_UP_B(AK, AP) \
   QEC_UP(AK, AP, U_X, 2) QEC_UP(AK, AP, U_X, 4) QEC_UP(AK, AP, U_Z, 1) QEC_UP(AK, AP, U_Z, 2) \
-  QEC_UP(AK, AP, U_Z, 3) QEC_UP(AK, AP, U_Z, 4)
+  QEC_UP(AK, AP, U_Z, 3) QEC_UP(AK, AP, U_Z, 4) QEC_UP(AK, AP, U_Z, 5) QEC_UP(AK, AP, U_Z, 6)
   if ((h.adense && !dna) || (h.bdense && !dnb)) return fail(SV_EINVAL, "dense unit without its Kraus table");
   if (h.tb <= 0) return fail(SV_EINVAL, "pass layout does not fit a tile");
   const int ap = h.akind == U_X ? h.wa : (h.akind == U_Z ? h.la : 0);
   const int bp = h.bkind == U_X ? h.wb : (h.bkind == U_Z ? h.lb : 0);
   QEC_UP_B(U_INIT, 0)
   QEC_UP_B(U_X, 2) QEC_UP_B(U_X, 4) QEC_UP(U_X, 2, U_NONE, 0) QEC_UP(U_X, 4, U_NONE, 0)
-  QEC_UP_B(U_Z, 1) QEC_UP_B(U_Z, 2) QEC_UP_B(U_Z, 3) QEC_UP_B(U_Z, 4)
+  QEC_UP_B(U_Z, 1) QEC_UP_B(U_Z, 2) QEC_UP_B(U_Z, 3) QEC_UP_B(U_Z, 4) QEC_UP_B(U_Z, 5) QEC_UP_B(U_Z, 6)
   QEC_UP(U_Z, 1, U_NONE, 0) QEC_UP(U_Z, 2, U_NONE, 0) QEC_UP(U_Z, 3, U_NONE, 0) QEC_UP(U_Z, 4, U_NONE, 0)
+  QEC_UP(U_Z, 5, U_NONE, 0) QEC_UP(U_Z, 6, U_NONE, 0)
   // X pairs (weights handled at run time)
   QEC_UP(U_INIT, 0, U_XP, 0) QEC_UP(U_X, 2, U_XP, 0) QEC_UP(U_X, 4, U_XP, 0)
   QEC_UP(U_Z, 1, U_XP, 0) QEC_UP(U_Z, 2, U_XP, 0) QEC_UP(U_Z, 3, U_XP, 0) QEC_UP(U_Z, 4, U_XP, 0)
+  QEC_UP(U_Z, 5, U_XP, 0) QEC_UP(U_Z, 6, U_XP, 0)
   QEC_UP_B(U_XP, 0) QEC_UP(U_XP, 0, U_XP, 0) QEC_UP(U_XP, 0, U_NONE, 0)
 #undef QEC_UP_B
 #undef QEC_UP

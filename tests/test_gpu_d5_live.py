@@ -106,3 +106,11 @@ def test_d5_live_x_pairs(dtype, monkeypatch):
     configuration."""
     g = _compare("base", dtype, dict(BENCH_TUNING, QECSV_XPAIR="1"), monkeypatch)
     assert g["passes_per_round"] == 12
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_d5_live_z_chains_of_six(dtype, monkeypatch):
+    """Z checks in two chains of six (QECSV_ZCHAIN=6: 14 passes a round, 126
+    outcome-prefix sums per chain)."""
+    g = _compare("base", dtype, dict(BENCH_TUNING, QECSV_ZCHAIN="6"), monkeypatch)
+    assert g["passes_per_round"] == 14

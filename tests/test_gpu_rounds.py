@@ -130,10 +130,12 @@ def test_d5_bench_config_properties():
         assert np.max(np.abs(a["p1"][t, :2] - z[f"p1_{t}"])) < 1e-10
 
 
-@pytest.mark.parametrize("chain", [1, 2, 3])
+@pytest.mark.parametrize("chain", [1, 2, 3, 5, 6])
 @pytest.mark.parametrize("d", [3, 4])
 def test_z_chain_lengths_parity(monkeypatch, d, chain):
-    """Passes that apply and decide chains of 1..3 Z checks (QECSV_ZCHAIN)
+    """Passes that apply and decide chains of 1..3, 5 and 6 Z checks
+    (QECSV_ZCHAIN; d=4 has seven: chains (5, 2) and (6, 1), the six-chain
+    summed amplitude by amplitude as no four tile bits avoid its qubits)
     give the oracle's records, p1 and register, with enough noise that most
     Z checks carry an X-type Pauli (a non-trivial Pauli-X frame)."""
     monkeypatch.setenv("QECSV_ZCHAIN", str(chain))

@@ -146,14 +146,14 @@ def test_argument_errors_are_reported_on_host():
 def test_pass_layouts_are_consistent(d, gateset):
     """Every register-pass layout of every chain length partitions its tile
     between lanes and register slots consistently (host-side builder)."""
-    for zchain in (1, 2, 3, 4):
+    for zchain in (1, 2, 3, 4, 5, 6):
         n_x = sum(1 for t, _ in oracle.layout(d) if t == "X")
         n_z = (d * d - 1) - n_x
         # one pass per X check and per chain, plus the first and the last
         assert qs.check_pass_layouts(d, gateset, zchain) == n_x + -(-n_z // zchain) + 2
         assert qs.check_pass_layouts(d, gateset, zchain, 0) == n_x + -(-n_z // zchain) + 2
     with pytest.raises(qs.SvError):
-        qs.check_pass_layouts(d, gateset, 5)
+        qs.check_pass_layouts(d, gateset, 7)
 
 
 def _pair_fits(qubit_sets):
@@ -193,7 +193,7 @@ def test_x_pair_layouts(d, gateset):
             if ok:
                 best = min(best, len(c))
     assert best < n_x or d < 4
-    for zchain in (1, 2, 3, 4):
+    for zchain in (1, 2, 3, 4, 5, 6):
         assert qs.check_pass_layouts(d, gateset, zchain, 1) == best + -(-n_z // zchain) + 2
     with pytest.raises(qs.SvError):
         qs.check_pass_layouts(d, gateset, 4, 2)
