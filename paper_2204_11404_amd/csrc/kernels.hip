@@ -172,38 +172,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Wave totals of 32 per-lane values in 32 shuffles (a reduce-scatter: each
-// step hands half of the remaining values to the partner lane): afterwards
-// lanes 2a and 2a + 1 hold the wave total of value a.  Fixed order.
-template <int K, int N>
-__device__ __forceinline__ void reduce_half(double (&v)[N]) {
-  const bool up = (threadIdx.x & (2 * K)) != 0;
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const double send = up ? v[i] : v[K + i];
-    const double keep = up ? v[K + i] : v[i];
-    v[i] = keep + __shfl_xor(send, 2 * K, 64);
-  }
-}
-__device__ __forceinline__ double wave_reduce32(double (&v)[32]) {
-  reduce_half<16>(v);
-  reduce_half<8>(v);
-  reduce_half<4>(v);
-  reduce_half<2>(v);
-  reduce_half<1>(v);
-  return v[0] + __shfl_xor(v[0], 1, 64);
-}
-// The same for 16 values: afterwards every lane l holds the wave total of
-// value (l >> 1) & 15.
-__device__ __forceinline__ double wave_reduce16(double (&v)[16]) {
-  reduce_half<8>(v);
-  reduce_half<4>(v);
-  reduce_half<2>(v);
-  reduce_half<1>(v);
-  const double r = v[0] + __shfl_xor(v[0], 1, 64);
-  return r + __shfl_xor(r, 32, 64);
-}
-
 // Deterministic block reduction of two doubles (fixed order).  `scratch`
 // holds 2 * (blockDim/64) doubles.  Result valid in thread 0.
 __device__ __forceinline__ void block_sum2(double& a, double& b, double* scratch) {
@@ -450,6 +418,52 @@ __device__ __forceinline__ void swap_rows16(uint32_t& x, uint32_t& y) {
   const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
   x = r[0];
   y = r[1];
+}
+// The same swaps for doubles (two dwords each).
+template <bool B32>
+__device__ __forceinline__ void swap_d(double& a, double& b) {
+  uint32_t x[2], y[2];
+  __builtin_memcpy(x, &a, 8);
+  __builtin_memcpy(y, &b, 8);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if constexpr (B32) swap_rows32(x[i], y[i]);
+    else swap_rows16(x[i], y[i]);
+  }
+  __builtin_memcpy(&a, x, 8);
+  __builtin_memcpy(&b, y, 8);
+}
+
+// Wave totals of 16 per-lane values in a fixed order: afterwards lane l
+// holds the total of value (l >> 2) & 15.  A reduce-scatter: over lane bit 5
+// and bit 4 each pair of values is swapped between the halves (rows) with a
+// permlane swap and added (the lanes with the bit clear keep the lower
+// values), over bits 3 and 2 the value to hand over is picked and moved by
+// DPP; then butterflies over bits 1 and 0.  No LDS.
+__device__ __forceinline__ double wave_reduce16(double (&v)[16]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    swap_d<true>(v[i], v[8 + i]);
+    v[i] += v[8 + i];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    swap_d<false>(v[i], v[4 + i]);
+    v[i] += v[4 + i];
+  }
+  const int lane = threadIdx.x & 63;
+  const bool u3 = (lane >> 3) & 1, u2 = (lane >> 2) & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double send = u3 ? v[i] : v[2 + i], keep = u3 ? v[2 + i] : v[i];
+    v[i] = keep + dpp_mv<0x128>(send);  // row_ror:8 within the row of 16: lane l ^ 8
+  }
+  {
+    const double send = u2 ? v[0] : v[1], keep = u2 ? v[1] : v[0];
+    v[0] = keep + lane_partner<2>(send, u2);
+  }
+  const double r = v[0] + dpp_mv<0x4E>(v[0]);  // quad_perm 2,3,0,1: lane l ^ 2
+  return r + dpp_mv<0xB1>(r);                 // quad_perm 1,0,3,2: lane l ^ 1
 }
 template <typename T, bool B32>
 __device__ __forceinline__ void swap_c2(C2<T>& a, C2<T>& b) {
@@ -1088,7 +1102,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   // Z chains of three to six checks (14 to 126 sums): the tile's sums are
   // formed and reduced across the wave one 16-value group at a time (levels
   // 0..2, then level 3, 4 and 5 in groups of 16); each lane keeps one running
-  // total per group (lane l: sum (l >> 1) & 15 of the group), so neither the
+  // total per group (lane l: sum (l >> 2) & 15 of the group), so neither the
   // accumulators of every sum nor a whole tree stays live
   constexpr bool kWaveAcc = BK == U_Z && LB >= 3;
   constexpr int kAcc = kWaveAcc ? ChainGroups<LB>::value : 32;
@@ -1471,16 +1485,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
         const double s = wave_sum(acc[a]);
         if (lane == 0) red[a][wid] = s;
       }
-    } else if constexpr (kWaveAcc) {
-      if ((lane & 1) == 0 && lane < 32) {
-        const int a = lane >> 1;
+    } else {
+      static_assert(kWaveAcc, "more than six sums come from a chain of three or more");
+      if ((lane & 3) == 0) {
+        const int a = lane >> 2;
         if (a < 14) red[a][wid] = acc[0];
 #pragma unroll
         for (int k = 1; k < kAcc; ++k) red[chain_group_base(k) + a][wid] = acc[k];
       }
-    } else {
-      const double s = wave_reduce32(acc);
-      if ((lane & 1) == 0 && (lane >> 1) < nacc) red[lane >> 1][wid] = s;
     }
     __syncthreads();
     if (tid < nacc) {
