@@ -798,19 +798,25 @@ __device__ __forceinline__ void chain_levels(double a2, const uint32_t* x, const
   }
 }
 
-// One 16-value group of the same tree at level L >= 3: sums (L, h) for
-// h = 16 G + i, i < 16 (members 0..3 take i's bits, member l >= 4 the fixed
-// outcome bit (G >> (l - 4)) & 1), added to out[i].
-template <int L, int G>
-__device__ __forceinline__ void chain_group(double a2, const uint32_t* x, const double (*wt)[2][16],
-                                            double* out) {
-  double f = a2;
+// A chain of LB >= 3 members is summed at its last level only: S[h] for every
+// outcome string h of all LB members (2^LB sums).  The sums of the shorter
+// prefixes are its marginals, since every member's two outcome weights add up
+// to one (a complete Kraus pair), and the decision forms them.  The last level
+// goes in groups of 16: group G holds h = 16 G + i (members 0..3 take i's
+// bits, member l >= 4 the bit (G >> (l - 4)) & 1 of G).
+template <int LB>
+struct ChainGroups {
+  static constexpr int value = LB <= 4 ? 1 : (1 << (LB - 4));
+};
+// Products of the first min(LB, 4) members' weights for every outcome string
+// of them, times a2.
+template <int LB>
+__device__ __forceinline__ void chain_prefix(double a2, const uint32_t* x, const double (*wt)[2][16],
+                                             double* p) {
+  constexpr int LO = LB < 4 ? LB : 4;
+  p[0] = a2;
 #pragma unroll
-  for (int l = 4; l <= L; ++l) f *= wt[l][(G >> (l - 4)) & 1][x[l]];
-  double p[16];
-  p[0] = f;
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
+  for (int l = 0; l < LO; ++l) {
     const double w0 = wt[l][0][x[l]], w1 = wt[l][1][x[l]];
 #pragma unroll
     for (int h = 0; h < (1 << l); ++h) {
@@ -818,20 +824,14 @@ __device__ __forceinline__ void chain_group(double a2, const uint32_t* x, const 
       p[h] *= w0;
     }
   }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) out[i] += p[i];
 }
-
-// Sum groups of a chain of LB >= 3 members reduced across the wave: group 0
-// holds levels 0..2 (14 sums), then level 3 (16), level 4 (2 x 16), level 5
-// (4 x 16).
-template <int LB>
-struct ChainGroups {
-  static constexpr int value = 1 + (LB >= 4 ? 1 : 0) + (LB >= 5 ? 2 : 0) + (LB >= 6 ? 4 : 0);
-};
-// First sum index of group k (level L, group G: 2^(L+1) - 2 + 16 G).
-__host__ __device__ constexpr int chain_group_base(int k) {
-  return k == 0 ? 0 : (k == 1 ? 14 : (k < 4 ? 30 + 16 * (k - 2) : 62 + 16 * (k - 4)));
+// The factor of group G: the weights of members 4.. for G's outcome bits.
+template <int LB, int G>
+__device__ __forceinline__ double chain_group_factor(const uint32_t* x, const double (*wt)[2][16]) {
+  double f = 1.0;
+#pragma unroll
+  for (int l = 4; l < LB; ++l) f *= wt[l][(G >> (l - 4)) & 1][x[l]];
+  return f;
 }
 
 // One pass over the register: apply unit A with its decided outcomes (or
@@ -888,7 +888,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   // phase table of A's ZZ layers and the per-wave sums of B, sized for the
   // units of this instantiation
   constexpr int kLayers = AK == U_Z ? AP : 1;
-  constexpr int kSums = BK == U_Z ? (2 << BP) - 2 : (BK == U_XP ? 6 : 2);
+  constexpr int kSums = BK == U_Z ? unit_sums(BP) : (BK == U_XP ? 6 : 2);
   __shared__ C2<T> zzt[kLayers * kMaxEdges + 1];
   __shared__ double red[kSums][4];
   const int tid = threadIdx.x;
@@ -1099,11 +1099,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   // grid-stride over the tiles (one tile per workgroup when the grid covers
   // them all); the tables above are loaded once per workgroup, the sums of B
   // accumulate over the workgroup's tiles
-  // Z chains of three to six checks (14 to 126 sums): the tile's sums are
-  // formed and reduced across the wave one 16-value group at a time (levels
-  // 0..2, then level 3, 4 and 5 in groups of 16); each lane keeps one running
-  // total per group (lane l: sum (l >> 2) & 15 of the group), so neither the
-  // accumulators of every sum nor a whole tree stays live
+  // Z chains of three to six checks: the tile's last-level sums (8 to 64) are
+  // formed and reduced across the wave one 16-value group at a time; each
+  // lane keeps one running total per group (lane l: sum (l >> 2) & 15 of the
+  // group), so neither the accumulators of every sum nor a whole tree stays
+  // live
   constexpr bool kWaveAcc = BK == U_Z && LB >= 3;
   constexpr int kAcc = kWaveAcc ? ChainGroups<LB>::value : 32;
   double acc[kAcc];
@@ -1378,46 +1378,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
         chain_levels<L0, L1>(s, ob, wt, t);
       }
     };
-    // group G of level L >= 3 into t
-    auto group = [&](auto lv, auto gv, double* t) {
-      constexpr int L = decltype(lv)::value, G = decltype(gv)::value;
-      if (!active) return;
-      if constexpr (BM0) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          uint32_t x[kChainMax];
-#pragma unroll
-          for (int i = 0; i < kChainMax; ++i) x[i] = ob[i] ^ pd->b_j_loc[i][j];
-          chain_group<L, G>(a2[j], x, wt, t);
-        }
-      } else {
-        chain_group<L, G>(s, ob, wt, t);
-      }
-    };
     if constexpr (kWaveAcc) {
+      constexpr int kGroups = ChainGroups<LB>::value;
       double t[16];
-      auto one = [&](auto kv, auto lv, auto gv) {
-        constexpr int K = decltype(kv)::value;
+      if constexpr (BM0) {
+        // amplitude by amplitude: each group's products formed anew
+        auto one = [&](auto gv) {
+          constexpr int G = decltype(gv)::value;
 #pragma unroll
-        for (int a = 0; a < 16; ++a) t[a] = 0.0;
-        if constexpr (K == 0)
-          tree(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{}, t);
-        else
-          group(lv, gv, t);
-        acc[K] += wave_reduce16(t);
-      };
-      using std::integral_constant;
-      one(integral_constant<int, 0>{}, integral_constant<int, 0>{}, integral_constant<int, 0>{});
-      if constexpr (LB >= 4) one(integral_constant<int, 1>{}, integral_constant<int, 3>{}, integral_constant<int, 0>{});
-      if constexpr (LB >= 5) {
-        one(integral_constant<int, 2>{}, integral_constant<int, 4>{}, integral_constant<int, 0>{});
-        one(integral_constant<int, 3>{}, integral_constant<int, 4>{}, integral_constant<int, 1>{});
-      }
-      if constexpr (LB >= 6) {
-        one(integral_constant<int, 4>{}, integral_constant<int, 5>{}, integral_constant<int, 0>{});
-        one(integral_constant<int, 5>{}, integral_constant<int, 5>{}, integral_constant<int, 1>{});
-        one(integral_constant<int, 6>{}, integral_constant<int, 5>{}, integral_constant<int, 2>{});
-        one(integral_constant<int, 7>{}, integral_constant<int, 5>{}, integral_constant<int, 3>{});
+          for (int a = 0; a < 16; ++a) t[a] = 0.0;
+          if (active) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+              uint32_t x[kChainMax];
+#pragma unroll
+              for (int i = 0; i < kChainMax; ++i) x[i] = ob[i] ^ pd->b_j_loc[i][j];
+              double p[16];
+              chain_prefix<LB>(a2[j], x, wt, p);
+              const double f = chain_group_factor<LB, G>(x, wt);
+#pragma unroll
+              for (int a = 0; a < (LB < 4 ? (1 << LB) : 16); ++a) t[a] += p[a] * f;
+            }
+          }
+          acc[G] += wave_reduce16(t);
+        };
+        one(std::integral_constant<int, 0>{});
+        if constexpr (kGroups > 1) one(std::integral_constant<int, 1>{});
+        if constexpr (kGroups > 2) {
+          one(std::integral_constant<int, 2>{});
+          one(std::integral_constant<int, 3>{});
+        }
+        static_assert(kGroups <= 4, "chains of at most six checks");
+      } else {
+        // once per thread: the first members' products shared by the groups
+        double p[16];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) p[a] = 0.0;
+        if (active) chain_prefix<LB>(s, ob, wt, p);
+        auto one = [&](auto gv) {
+          constexpr int G = decltype(gv)::value;
+          const double f = active ? chain_group_factor<LB, G>(ob, wt) : 0.0;
+#pragma unroll
+          for (int a = 0; a < 16; ++a) t[a] = p[a] * f;
+          acc[G] += wave_reduce16(t);
+        };
+        one(std::integral_constant<int, 0>{});
+        if constexpr (kGroups > 1) one(std::integral_constant<int, 1>{});
+        if constexpr (kGroups > 2) {
+          one(std::integral_constant<int, 2>{});
+          one(std::integral_constant<int, 3>{});
+        }
+        static_assert(kGroups <= 4, "chains of at most six checks");
       }
     } else {
       tree(std::integral_constant<int, 0>{}, std::integral_constant<int, LB>{}, acc);
@@ -1476,7 +1487,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   __syncthreads();  // LDS buffers are reused by the next tile
   }
   if constexpr (BK != U_NONE) {
-    constexpr int nacc = (2 << lb) - 2;
+    constexpr int nacc = unit_sums(lb);
     const int lane = tid & 63, wid = tid >> 6;
     const int nw = (int)(blockDim.x + 63) >> 6;
     if constexpr (nacc <= 6) {
@@ -1489,9 +1500,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
       static_assert(kWaveAcc, "more than six sums come from a chain of three or more");
       if ((lane & 3) == 0) {
         const int a = lane >> 2;
-        if (a < 14) red[a][wid] = acc[0];
 #pragma unroll
-        for (int k = 1; k < kAcc; ++k) red[chain_group_base(k) + a][wid] = acc[k];
+        for (int k = 0; k < kAcc; ++k)
+          if (16 * k + a < nacc) red[16 * k + a][wid] = acc[k];
       }
     }
     __syncthreads();
@@ -1525,6 +1536,26 @@ __device__ void decide_chain(const volatile double* S, int lb, const BlockRT* rt
   dec_b->Sm = Sm;
 }
 
+// The full tree of prefix sums (index (2 << l) - 2 + h) in LDS from a unit's
+// sums v(a), a < unit_sums(lb): as they are for lb <= 2; for a longer chain
+// they are the last level, and each lower level is formed from the one above
+// as S[l][h] = S[l + 1][h] + S[l + 1][h | 1 << (l + 1)] (the later member's
+// two outcome weights add up to one).  Every thread of the workgroup takes
+// part.
+template <typename V>
+__device__ __forceinline__ void chain_tree_lds(int lb, V v, double* full) {
+  const int nacc = unit_sums(lb);
+  const int base = lb >= 3 ? (2 << (lb - 1)) - 2 : 0;
+  for (int a = threadIdx.x; a < nacc; a += blockDim.x) full[base + a] = v(a);
+  for (int l = lb - 2; l >= 0 && lb >= 3; --l) {
+    __syncthreads();
+    const int up = (2 << (l + 1)) - 2, off = (2 << l) - 2;
+    for (int h = threadIdx.x; h < (2 << l); h += blockDim.x)
+      full[off + h] = full[up + h] + full[up + h + (2 << l)];
+  }
+  __syncthreads();
+}
+
 // Outcomes of unit B (a chain of lb checks; lb = 1 for an X check), reducing
 // each sum over the n per-workgroup partials in a fixed order.
 // split = 1, grid (nacc, slots): workgroup a reduces sum a; the last
@@ -1538,22 +1569,21 @@ __global__ __launch_bounds__(256) void k_udecide(const double* __restrict__ part
                                                  double* __restrict__ p1_b, SlotStrides ss,
                                                  size_t rec_stride, double* __restrict__ sums,
                                                  unsigned* __restrict__ tickets, int split) {
-  const int nacc = (2 << lb) - 2;
+  const int nacc = unit_sums(lb);
   const int slot = split ? (int)blockIdx.y : (int)blockIdx.x;
   partials += (size_t)slot * kChainAcc * n;
   rtb += (size_t)slot * ss.rt;
   dec_b += (size_t)slot * ss.dec;
   rec_b += (size_t)slot * rec_stride;
   if (p1_b) p1_b += (size_t)slot * rec_stride;
+  __shared__ double full[kChainAcc];
   if (!split) {
-    __shared__ double S[kChainAcc];
-    if ((int)threadIdx.x < nacc) {
+    chain_tree_lds(lb, [&](int a) {
       double s = 0.0;
-      for (int i = 0; i < n; ++i) s += partials[(size_t)threadIdx.x * n + i];
-      S[threadIdx.x] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) decide_chain(S, lb, rtb, dec_b, rec_b, p1_b);
+      for (int i = 0; i < n; ++i) s += partials[(size_t)a * n + i];
+      return s;
+    }, full);
+    if (threadIdx.x == 0) decide_chain(full, lb, rtb, dec_b, rec_b, p1_b);
     return;
   }
   const int a = blockIdx.x;
@@ -1580,10 +1610,14 @@ __global__ __launch_bounds__(256) void k_udecide(const double* __restrict__ part
     last = atomicAdd(&tickets[slot], 1u) == (unsigned)(nacc - 1);
   }
   __syncthreads();
-  if (!last || threadIdx.x != 0) return;
+  if (!last) return;  // the slot's last workgroup decides
   __threadfence();
-  decide_chain(sums, lb, rtb, dec_b, rec_b, p1_b);
-  tickets[slot] = 0u;
+  const volatile double* vs = sums;
+  chain_tree_lds(lb, [&](int b) { return vs[b]; }, full);
+  if (threadIdx.x == 0) {
+    decide_chain(full, lb, rtb, dec_b, rec_b, p1_b);
+    tickets[slot] = 0u;
+  }
 }
 
 // ------------------------------------------------------ final measurement --

@@ -581,6 +581,11 @@ struct Decision {
 // 16-element group over four register slots (its two qubits and two others)
 // with its tables repeated over the other two bits and divided by 4.
 enum : int { U_NONE = 0, U_X = 1, U_Z = 2, U_INIT = 3, U_XP = 4 };
+// Sums a pass leaves for the decision of a unit of len members: every outcome
+// prefix (2^(len+1) - 2: an X check 2, a pair or a chain of two 6), or for a
+// chain of three or more only its last level (2^len; the prefixes are its
+// marginals, each member's outcome weights adding up to one).
+__host__ __device__ constexpr int unit_sums(int len) { return len >= 3 ? (1 << len) : (2 << len) - 2; }
 
 // Layout and unit description of one pass: apply unit A (decided), accumulate
 // the sums of unit B.  Tiles of 2^tb amplitudes; a thread owns 16 amplitudes

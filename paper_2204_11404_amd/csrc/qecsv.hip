@@ -1144,7 +1144,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       const int bi = inst(ui);
       const int lb = units[ui % nu].len;
       // one partial per pass workgroup
-      hipLaunchKernelGGL(k_udecide, dim3((2 << lb) - 2), dim3(256), 0, q, partials, (int)grid.x, lb,
+      hipLaunchKernelGGL(k_udecide, dim3(unit_sums(lb)), dim3(256), 0, q, partials, (int)grid.x, lb,
                          rt + bi, &ddec[ui], rec + bi, p1 ? p1 + bi : nullptr, ss0, (size_t)0, dacc,
                          dticket, 1);
     };
