@@ -297,6 +297,37 @@ def batch_run(qs, d, n_traj, dtype, seed=7):
     return out
 
 
+def d5_without_zz_run(qs, torch, kw, n_traj=5):
+    """The d=5 workload without the data ZZ layer (zeta = 0): outcomes then
+    repeat from round to round and the speculative units run (each X pair or
+    Z chain summed and applied in one pass, redone when a predicted outcome
+    fails); timed beside the plain passes on the same trajectories."""
+    import os
+    kw = dict(kw, zeta=0.0)
+    out = {"workload": "d5_cr without the data ZZ layer (zeta=0), otherwise as the headline",
+           "trajectories": n_traj}
+    saved = os.environ.get("QECSV_SPEC")
+    for name, env in (("speculative", None), ("plain", "0")):
+        if env is None:
+            os.environ.pop("QECSV_SPEC", None)
+        else:
+            os.environ["QECSV_SPEC"] = env
+        qs.run_rounds(n_traj=1, traj0=2_000_000, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = qs.run_rounds(n_traj=n_traj, traj0=0, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / (n_traj * kw["rounds"])
+        out[name] = {"ms_per_round": ms, "passes_per_round": g["passes_per_round"],
+                     "redo_passes_per_round": g["redo_passes"] / (n_traj * kw["rounds"]),
+                     "pass_ms": g["pass_ms"]}
+    if saved is None:
+        os.environ.pop("QECSV_SPEC", None)
+    else:
+        os.environ["QECSV_SPEC"] = saved
+    return out
+
+
 def d3_textbook_run(qs):
     """The d=3 workload: 9 data qubits + 1 ancilla, textbook H/CNOT/CZ
     circuit, complex128, 3 rounds of 8 stabilizers, p = 1e-3 after every gate,
@@ -484,6 +515,7 @@ def main():
                      "circuits_per_pass": n_stab / r["passes_per_round"]},
     }
     if not args.no_extras:
+        out["d5_without_zz_layer"] = d5_without_zz_run(qs, torch, kw)
         out["d3"] = d3_textbook_run(qs)
         out["d3_trajectories_per_s"] = out["d3"]["trajectories_per_s"]
         out["batched"] = [batch_run(qs, 3, 65536, "c64"), batch_run(qs, 4, 4096, "c64")]

@@ -237,10 +237,13 @@ typedef struct sv_result {
                            final measurement, or NULL */
   double gpu_ms;        /* out: device time of the whole run (hipEvents) */
   double pass_ms;       /* out: mean device time per register pass of the last
-                           trajectory (one pass applies an X check or a chain
-                           of up to four Z checks) */
-  int passes_per_round; /* out: register passes per round */
-  int pad;
+                           trajectory (one pass applies an X check, a pair of
+                           them or a chain of Z checks; with speculative
+                           units, their prediction passes) */
+  int passes_per_round; /* out: register passes per round (speculative units:
+                           prediction passes per round) */
+  int redo_passes;      /* out: speculative units' redo passes that ran, over
+                           the whole run (0 without speculative units) */
 } sv_result;
 
 /* Run job->n_traj trajectories (indices traj0 ..): logical |0>, `rounds`
@@ -250,7 +253,15 @@ typedef struct sv_result {
  * Draw k of trajectory t is uniform(seed, t, k) from Philox4x32-10; the draws
  * are enumerated in circuit order: per round, per stabilizer, one per noise
  * location and then one for the measurement; after the last round one per
- * final data measurement.  Synchronous.  Records are the raw ancilla bits. */
+ * final data measurement.  Synchronous.  Records are the raw ancilla bits.
+ * With zeta = 0 and d >= 4 (outcomes then mostly repeat from round to round)
+ * the register passes are speculative: a pair of X checks or a chain of Z
+ * checks is summed and applied in one pass with predicted outcomes (the
+ * trivial ones in the first round, the previous round's after that) and the
+ * pass runs again when a drawn outcome differs; records, p1 and states are
+ * those of the plain passes.  The environment variable QECSV_SPEC = 0 / 1
+ * turns this off / on whatever zeta is (not with SV_RUN_GRAPH, the dense
+ * crosstalk or asynchronous runs, which always use the plain passes). */
 sv_status sv_run_rounds(const sv_job* job, sv_result* res);
 
 /* The same run enqueued without waiting, so that jobs on several streams

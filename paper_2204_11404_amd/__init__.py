@@ -44,7 +44,7 @@ class Result(ctypes.Structure):
         ("records", ctypes.POINTER(ctypes.c_uint8)), ("final_bits", ctypes.POINTER(ctypes.c_uint8)),
         ("p1_trace", ctypes.POINTER(ctypes.c_double)), ("final_states", ctypes.c_void_p),
         ("gpu_ms", ctypes.c_double), ("pass_ms", ctypes.c_double),
-        ("passes_per_round", ctypes.c_int), ("pad", ctypes.c_int),
+        ("passes_per_round", ctypes.c_int), ("redo_passes", ctypes.c_int),
     ]
 
 
@@ -373,7 +373,7 @@ def run_rounds(d, gateset, rounds, n_traj, seed, p, eps=0.0, eps_site=None, zeta
     _check(lib().sv_run_rounds(ctypes.byref(job), ctypes.byref(res)))
     del keep
     return dict(records=rec, final_bits=fb, p1=p1, states=states, gpu_ms=res.gpu_ms, pass_ms=res.pass_ms,
-                passes_per_round=res.passes_per_round)
+                passes_per_round=res.passes_per_round, redo_passes=res.redo_passes)
 
 
 class AsyncRun:

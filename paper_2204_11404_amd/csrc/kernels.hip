@@ -861,19 +861,51 @@ struct UpassWaves {
   static constexpr int value = (!DN && !BM0 && BK != U_XP) ? 3 : 1;
 };
 
-template <typename T, int AK, int AP, int BK, int BP, bool DN, bool BM0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<T, BK, BP, DN, BM0>::value))) void k_upass(
+// Speculative passes (SP = 1: prediction, SP = 2: redo): the register they
+// write, the unit instance's control record, the predicted outcome of each
+// member (prediction pass), a counter of the redos that ran.
+struct SpecArgs {
+  void* out;
+  SpecCtl* ctl;
+  const uint8_t* pred;
+  int* redos;
+};
+
+template <typename T, int AK, int AP, int BK, int BP, bool DN, bool BM0, int SP>
+__device__ __forceinline__ void upass_body(
     T* __restrict__ st, const UnitPass* __restrict__ pd, const JobConst* __restrict__ jc,
     const BlockRT* __restrict__ rta, const BlockRT* __restrict__ rtb,
     const Decision* __restrict__ dec_a, Decision* __restrict__ dec_b,
     double* __restrict__ partials, int reverse, SlotStrides ss,
-    const BlockDense* __restrict__ dna, const BlockDense* __restrict__ dnb) {
+    const BlockDense* __restrict__ dna, const BlockDense* __restrict__ dnb, SpecArgs sa) {
+  // speculative unit: A (an X check or pair, summed along its applied
+  // outcomes), or B (a Z chain after the pending renormalisation)
+  constexpr bool kSpecA = SP != 0 && (AK == U_X || AK == U_XP);
+  constexpr bool kSpecB = SP != 0 && BK == U_Z;
+  static_assert(SP == 0 || (kSpecA && BK == U_NONE) || (kSpecB && AK == U_SC), "speculative unit kinds");
+  int sm = 0;  // outcome bits applied to the speculative unit
+  if constexpr (SP == 2) {
+    if (!sa.ctl->run) return;  // nothing to redo
+    sm = sa.ctl->m;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(sa.redos, 1);
+  } else if constexpr (SP == 1) {
+    constexpr int kLen = kSpecA ? (AK == U_XP ? 2 : 1) : BP;
+#pragma unroll
+    for (int l = 0; l < kLen; ++l) sm |= (sa.pred[l] & 1) << l;
+    // (byte loads go through the vector unit: the bits are uniform, and the
+    // tables they select must stay scalar loads)
+    sm = __builtin_amdgcn_readfirstlane(sm);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sa.ctl = SpecCtl{sm, 0, 1, 0};
+  }
   // trajectory slot (lockstep launches): walked backwards with the tiles, so
   // that a pass starts on the registers its predecessor wrote last
   const size_t slot = reverse ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
   st += slot * ss.st;
   constexpr uint32_t kAmp = 2 * sizeof(T);  // bytes per amplitude
   const RegBuf<T> reg(st, (uint32_t)(kAmp << (pd->tb + pd->n_outer)));
+  // speculative passes write the other register buffer (the redo reads the
+  // pass's input again)
+  const RegBuf<T> regw(SP != 0 ? static_cast<T*>(sa.out) : st, (uint32_t)(kAmp << (pd->tb + pd->n_outer)));
   if (rta) rta += slot * ss.rt;
   if (rtb) rtb += slot * ss.rt;
   if (dna) dna += slot * ss.rt;
@@ -887,8 +919,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   __shared__ double wt[kChainMax][2][16];
   // phase table of A's ZZ layers and the per-wave sums of B, sized for the
   // units of this instantiation
-  constexpr int kLayers = AK == U_Z ? AP : 1;
-  constexpr int kSums = BK == U_Z ? unit_sums(BP) : (BK == U_XP ? 6 : 2);
+  constexpr int kLayers = AK == U_Z ? AP : (kSpecB ? BP : 1);
+  constexpr int kSums = kSpecA ? (AK == U_XP ? 4 : 2) : (BK == U_Z ? unit_sums(BP) : (BK == U_XP ? 6 : 2));
   __shared__ C2<T> zzt[kLayers * kMaxEdges + 1];
   __shared__ double red[kSums][4];
   const int tid = threadIdx.x;
@@ -915,7 +947,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   double scale = 1.0;
   if constexpr (AK != U_INIT) {
     phi = dec_a->phi;
-    mbits = dec_a->m;
+    mbits = kSpecA ? sm : dec_a->m;
     scale = 1.0 / sqrt(dec_a->Sm);
   }
   uint32_t M[kChainMax];   // logical-index masks of A's ZZ layers
@@ -949,24 +981,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
     phi_new = phi ^ G;
   }
   uint32_t cb[kChainMax];
+  uint32_t Mb[kChainMax];  // frames of a speculative chain B's ZZ layers
 #pragma unroll
-  for (int i = 0; i < kChainMax; ++i) cb[i] = 0;
+  for (int i = 0; i < kChainMax; ++i) cb[i] = Mb[i] = 0;
+  uint32_t Gb = 0;
   if constexpr (BK == U_Z) {
-    uint32_t G = 0;
 #pragma unroll
     for (int i = 0; i < kChainMax; ++i)
       if (i < lb) {
-        cb[i] = gather_loc(phi_new ^ G, pd->bq[i], pd->bw[i]);
-        G ^= scatter_loc(rtb[i].F, pd->bq[i], pd->bw[i]);
+        cb[i] = gather_loc(phi_new ^ Gb, pd->bq[i], pd->bw[i]);
+        Gb ^= scatter_loc(rtb[i].F, pd->bq[i], pd->bw[i]);
+        Mb[i] = phi_new ^ Gb;
       }
   }
-  if (blockIdx.x == 0 && tid == 0) dec_b->phi = phi_new;
+  // frame after this pass's writes (a speculative chain B is applied here)
+  if (blockIdx.x == 0 && tid == 0) dec_b->phi = kSpecB ? phi_new ^ Gb : phi_new;
 
   // tables (the workgroup may have only 64 threads)
   // an X check A's decided diagonal: in LDS for the lane-mixed layout, and
   // in complex64 (converted once per workgroup rather than per tile)
+  // (speculative passes too: their second register's resource and the
+  // control arguments leave no scalar registers for the table)
   if constexpr (AK == U_X) {
-    if ((pd->amix || sizeof(T) == 4) && tid < 16)
+    if ((pd->amix || sizeof(T) == 4 || kSpecA) && tid < 16)
       da[0][tid] = C2<T>{(T)rta->D[mbits][tid][0], (T)rta->D[mbits][tid][1]};
   }
   if constexpr (AK == U_XP) {  // members' decided diagonals over 16 register slots
@@ -1029,8 +1066,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   if constexpr (BK == U_X) {
     if (tid < 32) wt[0][tid >> 4][tid & 15] = rtb->W[tid >> 4][tid & 15];
   }
+  if constexpr (kSpecA && AK == U_X) {  // the check's weights over its local index
+    if (tid < 32) wt[0][tid >> 4][tid & 15] = rta->W[tid >> 4][tid & 15];
+  }
+  if constexpr (kSpecA && AK == U_XP) {  // members' weights as their diagonals are laid out
+    if (tid < 64) {
+      const int i = tid >> 5, m = (tid >> 4) & 1, x = tid & 15;
+      wt[i][m][x] = (i == 0 && pd->amix) ? rta[0].W[m][x] : padded(&rta[i].W[m][0], 1, pd->aw[i], x);
+    }
+  }
+  if constexpr (kSpecB) {  // the chain's diagonals for its applied outcomes
+    for (int k = tid; k < kChainMax * 16; k += blockDim.x) {
+      const int i = k >> 4, x = k & 15;
+      if (i < lb) {
+        const int m = (sm >> i) & 1;
+        da[i][x] = C2<T>{(T)rtb[i].D[m][x][0], (T)rtb[i].D[m][x][1]};
+      }
+    }
+    if (jc->use_zz)  // B's layers, unscaled (the renormalisation comes first)
+      for (int k = tid; k <= lb * jc->n_edges; k += blockDim.x)
+        zzt[k] = C2<T>{(T)jc->zzl[lb - 1][2 * k], (T)jc->zzl[lb - 1][2 * k + 1]};
+  }
   constexpr int nl = AK == U_Z ? la : 1;
-  const int use_zz = (AK != U_INIT) && jc->use_zz;
+  const int use_zz = (AK != U_INIT && AK != U_SC) && jc->use_zz;
   // the phase table carries the renormalisation (and the sign of an X check
   // A's frame), formed in FP64: one complex product per amplitude does both
   if (use_zz)
@@ -1085,8 +1143,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   };
   // Kraus operator of an X check on the register slots: transform, diagonal
   // (16-slot table in LDS), transform, frame signs
-  auto x_slots = [&](C2<T>* w, const C2<T>* dg, uint32_t F) {
+  // (a speculative A: the member's sums over the transformed values first,
+  // weights ws)
+  auto x_slots = [&](C2<T>* w, const C2<T>* dg, uint32_t F, const double (*ws)[16], double* sp) {
     wht<T, 4>(w);
+    if constexpr (kSpecA) {
+      // weights read per tile (an opaque offset keeps them out of registers
+      // across the tile loop)
+      const uint32_t wz = lds_bytes<double>(0);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double re = (double)w[j].re, im = (double)w[j].im;
+        const double a2 = re * re + im * im;
+        sp[0] += lds_at(const_cast<double*>(ws[0]), wz, j) * a2;
+        sp[1] += lds_at(const_cast<double*>(ws[1]), wz, j) * a2;
+        if ((j & 3) == 3) asm volatile("" : "+v"(sp[0]), "+v"(sp[1]) : : "memory");
+      }
+    }
 #pragma unroll
     for (int j = 0; j < 16; ++j) w[j] = mulc(w[j], dg[j].re, dg[j].im);
     wht<T, 4>(w);
@@ -1094,6 +1167,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
 #pragma unroll
       for (int j = 0; j < 16; ++j)
         if (__popc((uint32_t)j & F) & 1) w[j] = {-w[j].re, -w[j].im};
+    }
+  };
+  // a speculative X check A partly on the lanes: its sums over the values
+  // after the first transform (local index xl ^ a_jx[j])
+  // (in groups of four values whose products are added at once: neither the
+  // weights nor the squared magnitudes stay live across the rest of the tile)
+  auto spec_mixed_sums = [&](const C2<T>* w, uint32_t xl, double& s0, double& s1) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const uint32_t x = xl ^ pd->a_jx[j];
+      const double re = (double)w[j].re, im = (double)w[j].im;
+      const double a2 = re * re + im * im;
+      s0 += wt[0][0][x] * a2;
+      s1 += wt[0][1][x] * a2;
+      if ((j & 3) == 3) asm volatile("" : "+v"(s0), "+v"(s1) : : "memory");
     }
   };
   // grid-stride over the tiles (one tile per workgroup when the grid covers
@@ -1163,6 +1251,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
           for (int i = 0; i < 4; ++i)
             if ((tid >> i) & 1) xl |= pd->a_tx[i];
           wht_mixed(v, pd->amix_r, pd->amix_lanes, tid);
+          if constexpr (kSpecA) spec_mixed_sums(v, xl, acc[0], acc[1]);
 #pragma unroll
           for (int j = 0; j < 16; ++j) {
             const C2<T> e = da[0][xl ^ pd->a_jx[j]];
@@ -1180,9 +1269,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
 #pragma unroll
           for (int hi = 0; hi < 16; hi += NA) {
             wht<T, WA>(v + hi);
+            if constexpr (kSpecA) {
+              const uint32_t wz = lds_bytes<double>(0);
+#pragma unroll
+              for (int x = 0; x < NA; ++x) {
+                const double re = (double)v[hi + x].re, im = (double)v[hi + x].im;
+                const double a2 = re * re + im * im;
+                acc[0] += lds_at(&wt[0][0][0], wz, x) * a2;
+                acc[1] += lds_at(&wt[0][1][0], wz, x) * a2;
+                if ((x & 3) == 3) asm volatile("" : "+v"(acc[0]), "+v"(acc[1]) : : "memory");
+              }
+            }
 #pragma unroll
             for (int x = 0; x < NA; ++x) {
-              if constexpr (sizeof(T) == 4) {
+              if constexpr (sizeof(T) == 4 || kSpecA) {
                 const C2<T> e = da[0][x];
                 v[hi + x] = mulc(v[hi + x], e.re, e.im);
               } else {
@@ -1205,6 +1305,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
           for (int i = 0; i < 4; ++i)
             if ((tid >> i) & 1) xl |= pd->a_tx[i];
           wht_mixed(v, pd->amix_r, pd->amix_lanes, tid);
+          if constexpr (kSpecA) spec_mixed_sums(v, xl, acc[0], acc[1]);
 #pragma unroll
           for (int j = 0; j < 16; ++j) {
             const C2<T> e = da[0][xl ^ pd->a_jx[j]];
@@ -1216,15 +1317,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
             for (int j = 0; j < 16; ++j)
               if (__popc((xl ^ pd->a_jx[j]) & Fa) & 1) v[j] = {-v[j].re, -v[j].im};
           }
+        } else if constexpr (kSpecA) {
+          x_slots(v, da[0], Fa, wt[0], &acc[0]);
         } else {
-          x_slots(v, da[0], Fa);
+          x_slots(v, da[0], Fa, wt[0], nullptr);
         }
         if (zz_on) zz_layer(v, gb, pd->j_g, eM[0], vM[0]);
         // second member on the register slots of layout p[0], then back
         regroup<T>(v, lt, pd->j_l, v, ltp0, pd->p_j_l[0], tbuf);
-        x_slots(v, da[1], Fa1);
-        regroup<T>(v, ltp0, pd->p_j_l[0], v, lt, pd->j_l, tbuf);
-      } else {
+        if constexpr (kSpecA)
+          x_slots(v, da[1], Fa1, wt[1], &acc[2]);
+        else
+          x_slots(v, da[1], Fa1, wt[1], nullptr);
+        if (!pd->pstore) regroup<T>(v, ltp0, pd->p_j_l[0], v, lt, pd->j_l, tbuf);
+      } else if constexpr (AK == U_Z) {
         uint32_t oa[kChainMax];
 #pragma unroll
         for (int i = 0; i < kChainMax; ++i)
@@ -1258,11 +1364,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
       // maps g ^ (g >> 1) and g ^ (g >> d) are linear over XOR and a slot's
       // bits are disjoint from the thread's, so the thread's part of each
       // masked map is formed once per tile and a slot adds its own part.
+      // (an X pair A stored from layout p[0]: that layout's base and slots)
+      uint32_t fgb = gb;
+      const uint32_t* fjg = pd->j_g;
+      if constexpr (AK == U_XP) {
+        if (pd->pstore) {
+          fgb = base;
+          for (int i = 0; i < tb - 4; ++i)
+            if ((tid >> i) & 1) fgb |= pd->p_tid_g[0][i];
+          fjg = pd->p_j_g[0];
+        }
+      }
       auto finish = [&](auto layers) {
         constexpr int NZ = decltype(layers)::value;
         constexpr int NE = NZ == 0 ? 1 : NZ;
         uint32_t Et[NE], Vt[NE];
-        const uint32_t eb = gb ^ (gb >> 1), wb = gb ^ (gb >> d);
+        const uint32_t eb = fgb ^ (fgb >> 1), wb = fgb ^ (fgb >> d);
 #pragma unroll
         for (int i = 0; i < NE; ++i) {
           Et[i] = (eb ^ eM[i]) & hm;
@@ -1270,7 +1387,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
         }
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          const uint32_t jg = pd->j_g[j];
+          const uint32_t jg = fjg[j];
           C2<T> r = v[j];
           if (use_zz) {
             const uint32_t je = (jg ^ (jg >> 1)) & hm, jw = (jg ^ (jg >> d)) & vm;
@@ -1287,7 +1404,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
             r.re = (T)((double)r.re * scale);
             r.im = (T)((double)r.im * scale);
           }
-          reg.st(gb * kAmp, jg * kAmp, r);
+          if constexpr (!kSpecB) regw.st(fgb * kAmp, jg * kAmp, r);
           o[j] = r;
         }
       };
@@ -1434,6 +1551,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
       tree(std::integral_constant<int, 0>{}, std::integral_constant<int, LB>{}, acc);
     }
   }
+  if constexpr (kSpecB) {
+    // the speculative chain applied after its sums: its diagonals for the
+    // applied outcomes (layout 1, the frame offsets of the sums), then one ZZ
+    // layer per member in the frame after that member, then the store
+    if (active) {
+      uint32_t o1[kChainMax];
+#pragma unroll
+      for (int i = 0; i < kChainMax; ++i) o1[i] = i < lb ? gather_loc(gb, pd->bq[i], pd->bw[i]) ^ cb[i] : 0u;
+      if (pd->bmode == 1) {  // no chain qubit on the register slots
+        C2<T> f = da[0][o1[0]];
+#pragma unroll
+        for (int i = 1; i < kChainMax; ++i)
+          if (i < lb) {
+            const C2<T> e = da[i][o1[i]];
+            f = mulc(f, e.re, e.im);
+          }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) o[j] = mulc(o[j], f.re, f.im);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          C2<T> f = da[0][o1[0] ^ pd->b_j_loc[0][j]];
+#pragma unroll
+          for (int i = 1; i < kChainMax; ++i)
+            if (i < lb) {
+              const C2<T> e = da[i][o1[i] ^ pd->b_j_loc[i][j]];
+              f = mulc(f, e.re, e.im);
+            }
+          o[j] = mulc(o[j], f.re, f.im);
+        }
+      }
+      bool same = true;
+#pragma unroll
+      for (int i = 1; i < kChainMax; ++i)
+        if (i < lb && Mb[i] != Mb[0]) same = false;
+      const uint32_t eb = gb ^ (gb >> 1), wb = gb ^ (gb >> d);
+      const int nz = same ? 1 : lb;  // layers with distinct frames
+      uint32_t Et[kChainMax], Vt[kChainMax];
+#pragma unroll
+      for (int i = 0; i < kChainMax; ++i) {
+        Et[i] = (eb ^ Mb[i] ^ (Mb[i] >> 1)) & hm;
+        Vt[i] = (wb ^ Mb[i] ^ (Mb[i] >> d)) & vm;
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t jg = pd->j_g[j];
+        C2<T> r = o[j];
+        if (zz_on) {
+          const uint32_t je = (jg ^ (jg >> 1)) & hm, jw = (jg ^ (jg >> d)) & vm;
+          int K = 0;
+#pragma unroll
+          for (int i = 0; i < kChainMax; ++i)
+            if (i < nz) K += __popc(Et[i] ^ je) + __popc(Vt[i] ^ jw);
+          if (same) K *= lb;
+          const C2<T> z = zzt[K];
+          r = mulc(r, z.re, z.im);
+        }
+        regw.st(gb * kAmp, jg * kAmp, r);
+      }
+    }
+  }
   if constexpr (BK == U_XP) {
     // first member on the register slots of layout 2: its sums; then for each
     // of its outcomes m0 the second member's sums (register slots of layout
@@ -1486,8 +1664,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
   }
   __syncthreads();  // LDS buffers are reused by the next tile
   }
-  if constexpr (BK != U_NONE) {
-    constexpr int nacc = unit_sums(lb);
+  if constexpr (BK != U_NONE || kSpecA) {
+    constexpr int nacc = kSpecA ? kSums : unit_sums(lb);
     const int lane = tid & 63, wid = tid >> 6;
     const int nw = (int)(blockDim.x + 63) >> 6;
     if constexpr (nacc <= 6) {
@@ -1512,6 +1690,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<
       partials[(size_t)tid * gridDim.x + blockIdx.x] = s;
     }
   }
+}
+
+// The pass kernel (SP = 0; SP = 1: a speculative unit's prediction pass) and
+// the redo of a speculative unit, under its own name (it mostly finds nothing
+// to do and returns at once).
+template <typename T, int AK, int AP, int BK, int BP, bool DN, bool BM0, int SP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<T, BK, BP, DN, BM0>::value))) void k_upass(
+    T* __restrict__ st, const UnitPass* __restrict__ pd, const JobConst* __restrict__ jc,
+    const BlockRT* __restrict__ rta, const BlockRT* __restrict__ rtb,
+    const Decision* __restrict__ dec_a, Decision* __restrict__ dec_b,
+    double* __restrict__ partials, int reverse, SlotStrides ss,
+    const BlockDense* __restrict__ dna, const BlockDense* __restrict__ dnb, SpecArgs sa) {
+  upass_body<T, AK, AP, BK, BP, DN, BM0, SP>(st, pd, jc, rta, rtb, dec_a, dec_b, partials, reverse, ss, dna, dnb, sa);
+}
+template <typename T, int AK, int AP, int BK, int BP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UpassWaves<T, BK, BP, false, false>::value))) void k_uredo(
+    T* __restrict__ st, const UnitPass* __restrict__ pd, const JobConst* __restrict__ jc,
+    const BlockRT* __restrict__ rta, const BlockRT* __restrict__ rtb,
+    const Decision* __restrict__ dec_a, Decision* __restrict__ dec_b,
+    double* __restrict__ partials, int reverse, SlotStrides ss,
+    const BlockDense* __restrict__ dna, const BlockDense* __restrict__ dnb, SpecArgs sa) {
+  upass_body<T, AK, AP, BK, BP, false, false, 2>(st, pd, jc, rta, rtb, dec_a, dec_b, partials, reverse, ss, dna, dnb, sa);
 }
 
 // Member-by-member outcomes of unit B from its sums S (see k_upass): each
@@ -1617,6 +1817,120 @@ __global__ __launch_bounds__(256) void k_udecide(const double* __restrict__ part
   if (threadIdx.x == 0) {
     decide_chain(full, lb, rtb, dec_b, rec_b, p1_b);
     tickets[slot] = 0u;
+  }
+}
+
+// Decision of a speculative unit instance of len members after a prediction
+// pass or a redo (grid: one workgroup per sum; the last to finish decides).
+// tree = 0: 2 len sums along the applied outcomes (S[2 l + m], taken before
+// the pass applied the pending renormalisation of dec_a->Sm); each member from
+// `known` on is decided as in a plain pass while the members before it match
+// what was applied; at the first mismatch the outcome is fixed and a redo is
+// due.  tree = 1: the chain's sums over every outcome string (after the
+// renormalisation): every member is decided, and a redo re-applies them if
+// any differs.  Once every member is decided, dec_b gets the outcome bits and
+// S_m, the squared norm of the register the unit's pass writes (its
+// renormalisation is applied by the next pass).  A redo that re-applied a
+// decided unit leaves nothing to decide (run is cleared); after a redo that
+// did not run the kernel returns at once.
+__global__ __launch_bounds__(256) void k_sdecide(const double* __restrict__ partials, int n, int len, int tree,
+                                                 const BlockRT* __restrict__ rtb, const Decision* __restrict__ dec_a,
+                                                 Decision* __restrict__ dec_b, uint8_t* __restrict__ rec_b,
+                                                 double* __restrict__ p1_b, SpecCtl* __restrict__ ctl,
+                                                 double* __restrict__ sums, unsigned* __restrict__ ticket) {
+  // the record as the workgroup sees it (workgroup 0 may clear run meanwhile)
+  __shared__ int c_run, c_known;
+  if (threadIdx.x == 0) {
+    const volatile SpecCtl* vc = ctl;
+    c_run = vc->run;
+    c_known = vc->known;
+  }
+  __syncthreads();
+  if (!c_run) return;
+  if (c_known >= len) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->run = 0;
+    return;
+  }
+  const int nacc = tree ? unit_sums(len) : 2 * len;
+  const int a = blockIdx.x;
+  if (a >= nacc) return;
+  partials += (size_t)a * n;
+  __shared__ double red[8];
+  __shared__ double full[kChainAcc];
+  __shared__ int last;
+  double s = 0.0, dummy = 0.0;
+  for (int i0 = 0; i0 < n; i0 += 8 * (int)blockDim.x) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = i0 + k * (int)blockDim.x + (int)threadIdx.x;
+      v[k] = i < n ? partials[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += v[k];
+  }
+  block_sum2(s, dummy, red);
+  if (threadIdx.x == 0) {
+    sums[a] = s;
+    __threadfence();
+    last = atomicAdd(ticket, 1u) == (unsigned)(nacc - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const volatile double* vs = sums;
+  if (tree) {
+    chain_tree_lds(len, [&](int b) { return vs[b]; }, full);
+    if (threadIdx.x == 0) {
+      const int applied = ctl->m;
+      decide_chain(full, len, rtb, dec_b, rec_b, p1_b);
+      ctl->m = dec_b->m;
+      ctl->known = len;
+      ctl->run = dec_b->m != applied;
+      *ticket = 0u;
+    }
+    return;
+  }
+  if (threadIdx.x == 0) {
+    const double sm_in = dec_a->Sm;
+    int m = ctl->m;
+    int l = ctl->known;
+    bool redo = false;
+    double Sm = 0.0;
+    for (; l < len; ++l) {
+      const double s0 = vs[2 * l], s1 = vs[2 * l + 1];
+      const double p1 = clamp_p1(s1 / (s0 + s1));
+      const int ml = (rtb[l].u < p1) ? 1 : 0;
+      rec_b[l] = (uint8_t)ml;
+      if (p1_b) p1_b[l] = p1;
+      Sm = (ml ? s1 : s0) / sm_in;
+      if (ml != ((m >> l) & 1)) {
+        m ^= 1 << l;
+        redo = true;
+        ++l;
+        break;
+      }
+    }
+    ctl->m = m;
+    ctl->known = l;
+    ctl->run = redo;
+    if (l == len) {
+      dec_b->m = m;
+      dec_b->Sm = Sm;
+    }
+    *ticket = 0u;
+  }
+}
+
+// The pending renormalisation 1 / sqrt(d->Sm) applied to a whole register.
+template <typename T>
+__global__ __launch_bounds__(256) void k_renorm(T* __restrict__ st, uint64_t na, const Decision* __restrict__ d) {
+  const double sc = 1.0 / sqrt(d->Sm);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na; i += (uint64_t)gridDim.x * blockDim.x) {
+    C2<T> a = ld2(st, i);
+    a.re = (T)((double)a.re * sc);
+    a.im = (T)((double)a.im * sc);
+    st2(st, i, a);
   }
 }
 

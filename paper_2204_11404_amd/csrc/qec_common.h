@@ -580,7 +580,30 @@ struct Decision {
 // A pair's members may have weight 2 or 4: a weight-2 member is handled as a
 // 16-element group over four register slots (its two qubits and two others)
 // with its tables repeated over the other two bits and divided by 4.
-enum : int { U_NONE = 0, U_X = 1, U_Z = 2, U_INIT = 3, U_XP = 4 };
+// Speculative units (the single-register trajectory, Sec. III.B): a unit
+// whose outcomes are predicted (the same check's outcome one round earlier,
+// the trivial outcome in the first round) is summed and applied in the same
+// pass, which writes the other of two register buffers.  An X check or pair
+// is summed along the predicted outcomes (its first member's S_0, S_1, then
+// the second member's after the first member's predicted Kraus operator and
+// ZZ layer: index 2 l + m for member l); a Z chain is summed over every
+// outcome string as a B unit is, after a U_SC "unit" that only applies the
+// pending renormalisation.  The decision confirms the members in order; at
+// the first member whose drawn outcome differs from the one applied it fixes
+// that outcome and has the pass run again from the untouched input (a redo).
+// Applied outcomes are never wrong in the register the next unit reads.
+enum : int { U_NONE = 0, U_X = 1, U_Z = 2, U_INIT = 3, U_XP = 4, U_SC = 5 };
+
+// Control record of one speculative unit instance: m, the outcome bits the
+// last pass applied (bit l: member l); the members below `known` are decided;
+// run = 1 while a redo is due.  The prediction pass writes it, the decision
+// updates it, a redo reads it.
+struct SpecCtl {
+  int m;
+  int known;
+  int run;
+  int pad;
+};
 // Sums a pass leaves for the decision of a unit of len members: every outcome
 // prefix (2^(len+1) - 2: an X check 2, a pair or a chain of two 6), or for a
 // chain of three or more only its last level (2^len; the prefixes are its
@@ -622,6 +645,10 @@ struct UnitPass {
   // lane bits (0..3) that carry qubits of A
   int amix, amix_r, amix_lanes, pad_amix;
   int adense, bdense;  // the X check A / B has a dense Kraus pair (BlockDense)
+  // an X pair A with no B: the tile is stored from layout p[0] (its lanes
+  // keep the three lowest bits: runs of at least 8 amplitudes), not
+  // regrouped back to layout 1 first
+  int pstore, pad_pstore;
   uint32_t a_tx[8], a_jx[16];
   uint32_t aq[kChainMax][4];     // global bit of local bit l of A's member i
   uint32_t bq[kChainMax][4];

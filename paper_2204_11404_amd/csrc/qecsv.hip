@@ -729,6 +729,8 @@ UnitPass make_unit_pass(int n, int tb_max, const Template& tp, const Unit* A, co
   }
   for (int k = 0; k < 2; ++k)
     if (!Jp[k].empty()) fill(Jp[k], pd.p_tid_g[k], pd.p_tid_l[k], pd.p_j_g[k], pd.p_j_l[k]);
+  pd.pstore = apair && !B && tb - 4 >= 3 && pd.p_tid_g[0][0] == 1u && pd.p_tid_g[0][1] == 2u &&
+              pd.p_tid_g[0][2] == 4u;
   if (have2) fill(J2, pd.b_tid_g, pd.b_tid_l, pd.b_j_g, pd.b_j_l);
   if (have2 || pairpass) {
     // LDS swizzle for the regrouping: slot = l ^ f(l), where f folds each tile
@@ -819,8 +821,8 @@ void launch_pass(bool dense, bool bm0, dim3 g, dim3 b, hipStream_t s, T* st, con
                  const JobConst* jc, const BlockRT* rta, const BlockRT* rtb, const Decision* da, Decision* db,
                  double* part, int rev, SlotStrides ss, const BlockDense* dna, const BlockDense* dnb) {
 #define QEC_K(DNV, BMV)                                                                                  \
-  hipLaunchKernelGGL((k_upass<T, AK, AP, BK, BP, DNV, BMV>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, part, \
-                     rev, ss, dna, dnb)
+  hipLaunchKernelGGL((k_upass<T, AK, AP, BK, BP, DNV, BMV, 0>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, part, \
+                     rev, ss, dna, dnb, SpecArgs{})
   if constexpr (BK == U_Z) {
     if (bm0) {
       if constexpr (AK == U_X) {
@@ -874,9 +876,40 @@ sv_status launch_upass(const UnitPass& h, dim3 g, dim3 b, hipStream_t s, T* st, 
   QEC_UP(U_Z, 1, U_XP, 0) QEC_UP(U_Z, 2, U_XP, 0) QEC_UP(U_Z, 3, U_XP, 0) QEC_UP(U_Z, 4, U_XP, 0)
   QEC_UP(U_Z, 5, U_XP, 0) QEC_UP(U_Z, 6, U_XP, 0)
   QEC_UP_B(U_XP, 0) QEC_UP(U_XP, 0, U_XP, 0) QEC_UP(U_XP, 0, U_NONE, 0)
+  QEC_UP(U_INIT, 0, U_NONE, 0)  // logical |0> alone (speculative runs)
 #undef QEC_UP_B
 #undef QEC_UP
   return fail(SV_EINVAL, "no pass kernel for units (%d,%d)->(%d,%d)", h.akind, h.wa, h.bkind, h.wb);
+}
+
+// A speculative unit's prediction pass (redo = false) or redo: reads st,
+// writes sa.out; the unit is A (an X check or pair, B none) or B (a Z chain,
+// A the pending renormalisation).
+template <typename T>
+sv_status launch_spass(const UnitPass& h, bool redo, dim3 g, dim3 b, hipStream_t s, T* st, const UnitPass* pd,
+                       const JobConst* jc, const BlockRT* rta, const BlockRT* rtb, const Decision* da,
+                       Decision* db, double* part, int rev, SpecArgs sa) {
+  const SlotStrides ss{0, 0, 0};
+#define QEC_SP(AK, AP, BK, BP)                                                                              \
+  if (h.akind == AK && ap == AP && h.bkind == BK && bp == BP) {                                             \
+    if (redo)                                                                                               \
+      hipLaunchKernelGGL((k_uredo<T, AK, AP, BK, BP>), g, b, 0, s, st, pd, jc, rta, rtb, da, db, part, rev, \
+                         ss, nullptr, nullptr, sa);                                                         \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_upass<T, AK, AP, BK, BP, false, false, 1>), g, b, 0, s, st, pd, jc, rta, rtb,   \
+                         da, db, part, rev, ss, nullptr, nullptr, sa);                                      \
+    return SV_OK;                                                                                           \
+  }
+  if (h.tb <= 0) return fail(SV_EINVAL, "pass layout does not fit a tile");
+  if (h.adense || h.bdense || (h.bkind == U_Z && h.bmode == 0))
+    return fail(SV_EINVAL, "no speculative pass for this unit");
+  const int ap = h.akind == U_X ? h.wa : 0;
+  const int bp = h.bkind == U_Z ? h.lb : 0;
+  QEC_SP(U_X, 2, U_NONE, 0) QEC_SP(U_X, 4, U_NONE, 0) QEC_SP(U_XP, 0, U_NONE, 0)
+  QEC_SP(U_SC, 0, U_Z, 1) QEC_SP(U_SC, 0, U_Z, 2) QEC_SP(U_SC, 0, U_Z, 3) QEC_SP(U_SC, 0, U_Z, 4)
+  QEC_SP(U_SC, 0, U_Z, 5) QEC_SP(U_SC, 0, U_Z, 6)
+#undef QEC_SP
+  return fail(SV_EINVAL, "no speculative pass for units (%d,%d)->(%d,%d)", h.akind, h.wa, h.bkind, h.lb);
 }
 
 
@@ -975,6 +1008,38 @@ std::vector<UnitPass> make_unit_passes(int n, int tb, const Template& tp,
   return pds;
 }
 
+// Units of one round for speculative passes: consecutive X checks two by two
+// where the pair's pass fits a tile (else alone), Z checks in chains of at
+// most max_chain members.  Passes: [0] writes logical |0>; [1 + u] is unit u's
+// pass (an X unit as A, a Z chain as B after the pending renormalisation).
+std::vector<Unit> make_spec_units(const Template& tp, int max_chain, int n) {
+  const std::vector<Unit> base = make_units(tp, max_chain);
+  std::vector<Unit> out;
+  for (size_t i = 0; i < base.size();) {
+    if (base[i].kind == U_X && i + 1 < base.size() && base[i + 1].kind == U_X) {
+      const Unit pr{U_XP, base[i].first, 2};
+      bool ok = false;
+      (void)make_unit_pass(n, kTileMax, tp, &pr, nullptr, &ok);
+      if (ok) {
+        out.push_back(pr);
+        i += 2;
+        continue;
+      }
+    }
+    out.push_back(base[i++]);
+  }
+  return out;
+}
+std::vector<UnitPass> make_spec_passes(int n, int tb, const Template& tp, const std::vector<Unit>& units) {
+  std::vector<UnitPass> pds(units.size() + 1);
+  pds[0] = make_unit_pass(n, tb, tp, nullptr, nullptr);
+  const Unit sc{U_SC, 0, 0};
+  for (size_t u = 0; u < units.size(); ++u)
+    pds[1 + u] = units[u].kind == U_Z ? make_unit_pass(n, tb, tp, &sc, &units[u])
+                                      : make_unit_pass(n, tb, tp, &units[u], nullptr);
+  return pds;
+}
+
 }  // namespace
 
 namespace {
@@ -1002,9 +1067,20 @@ bool template_is_monomial(const Template& tp, const std::vector<double>& eps) {
   return true;
 }
 
+int env_int(const char* name, int dflt);
+
 // done == nullptr: synchronous.  Otherwise every step is enqueued on the
 // job's stream, `done` is recorded after the results' copies to the host and
 // the call returns without waiting (no graph replay, no final states).
+// Speculative units (stream launches of a register of at least 2^12
+// amplitudes whose blocks are all monomial): each unit is summed and applied
+// in one pass with predicted outcomes, then confirmed or redone (see
+// k_sdecide); two register buffers.  They pay when outcomes repeat from round
+// to round, i.e. without the data ZZ layer: at d = 5, p = 1e-3 a round takes
+// 2.18 ms instead of 2.96 (complex128); with zeta = 0.01 the layer turns 15 %
+// of the X checks' outcomes from one round to the next and the redos make
+// them slower (3.1 against 3.0 ms).  So they run when zeta = 0;
+// QECSV_SPEC = 0 / 1 turns them off / on whatever zeta is.
 template <typename T>
 sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
                        const std::atomic<int>* cancel = nullptr, hipEvent_t done = nullptr) {
@@ -1016,6 +1092,23 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   const std::vector<Unit> units = make_units_paired(tp, tune.zchain, n, tune.xpair);
   const int nu = (int)units.size();
   const int per_units = R * nu;  // passes per trajectory after the first
+  const int spec_env = env_int("QECSV_SPEC", -1);
+  bool spec = (spec_env < 0 ? job->zeta == 0.0 : spec_env != 0) && n >= kTileMax && !tp.any_dense && !async &&
+              !(job->flags & SV_RUN_GRAPH);
+  std::vector<Unit> sunits;
+  std::vector<UnitPass> spds;
+  if (spec) {
+    sunits = make_spec_units(tp, tune.zchain, n);
+    spds = make_spec_passes(n, tb, tp, sunits);
+    // a chain that has to be summed amplitude by amplitude keeps the plain passes
+    for (const UnitPass& h : spds)
+      if (h.tb <= 0 || (h.bkind == U_Z && h.bmode == 0)) spec = false;
+  }
+  if (!spec) sunits.clear();
+  const int nus = (int)sunits.size();
+  const int per_units_s = R * nus;
+  // decision record of the register the final measurement reads
+  const int fin = spec ? per_units_s : per_units;
   hipStream_t s = (hipStream_t)job->hip_stream;
   DevBufs M(s);
   T* st = nullptr;
@@ -1052,7 +1145,8 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   HIP_OK(M.alloc(&dpass, sizeof(UnitPass) * (nu + 2)));
   HIP_OK(M.alloc(&djc, sizeof(JobConst)));
   HIP_OK(M.alloc(&deps, sizeof(double) * n_angles));
-  HIP_OK(M.alloc(&ddec, sizeof(Decision) * (per_units + 1)));
+  const int n_dec = std::max(per_units, per_units_s) + 1;
+  HIP_OK(M.alloc(&ddec, sizeof(Decision) * n_dec));
   HIP_OK(M.alloc(&drec, nrec));
   HIP_OK(M.alloc(&dbits, (size_t)job->n_traj * n));
   if (res->p1_trace) HIP_OK(M.alloc(&dp1, sizeof(double) * nrec));
@@ -1064,6 +1158,28 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
 
   const std::vector<UnitPass> pds = make_unit_passes(n, tb, tp, units);
   const bool xbasis = (job->flags & SV_RUN_XBASIS) != 0;
+  // speculative runs: the second register, pass descriptors, control records,
+  // first-round predictions (the trivial outcome of every check), redo count
+  T* st2 = nullptr;
+  UnitPass* dspass = nullptr;
+  SpecCtl* dctl = nullptr;
+  uint8_t* dpred0 = nullptr;
+  int* dredos = nullptr;
+  std::vector<uint8_t> pred0;
+  if (spec) {
+    for (const TBlock& b : tp.blocks)
+      pred0.push_back(job->gateset == SV_GATESET_CR ? (uint8_t)((b.w / 2) % 2) : (uint8_t)0);
+    HIP_OK(M.alloc(&st2, sizeof(T) * 2 * na));
+    HIP_OK(M.alloc(&dspass, sizeof(UnitPass) * spds.size()));
+    HIP_OK(M.alloc(&dctl, sizeof(SpecCtl) * per_units_s));
+    HIP_OK(M.alloc(&dpred0, pred0.size()));
+    HIP_OK(M.alloc(&dredos, sizeof(int)));
+    HIP_OK(hipMemcpyAsync(dspass, spds.data(), sizeof(UnitPass) * spds.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(dpred0, pred0.data(), pred0.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemsetAsync(dredos, 0, sizeof(int), s));
+    // the host vectors are read by the copies: wait before they can go
+    HIP_OK(hipStreamSynchronize(s));
+  }
   std::vector<double> eps(n_angles, job->eps);
   if (job->eps_site)
     for (int i = 0; i < tp.n_sites; ++i) eps[i] = job->eps_site[i];
@@ -1109,7 +1225,11 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
     }
   }
   HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
-  HIP_OK(hipMemsetAsync(ddec, 0, sizeof(Decision) * (per_units + 1), s));
+  HIP_OK(hipMemsetAsync(ddec, 0, sizeof(Decision) * n_dec, s));
+  if (spec) {  // the register logical |0> is written in: norm 1, frame 0
+    static const Decision d0{1.0, 0, 0u};
+    HIP_OK(hipMemcpyAsync(ddec, &d0, sizeof d0, hipMemcpyHostToDevice, s));
+  }
 
   // whole-run events plus one pair around every pass of the last trajectory
   struct Events {
@@ -1118,7 +1238,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
   } E;
-  E.ev.resize(async ? 0 : 2 + 2 * per_units, nullptr);
+  E.ev.resize(async ? 0 : 2 + 2 * std::max(per_units, per_units_s), nullptr);
   for (auto& e : E.ev) HIP_OK(hipEventCreate(&e));
   hipEvent_t ev0 = async ? nullptr : E.ev[0], ev1 = async ? nullptr : E.ev[1];
   hipEvent_t* evs = async ? nullptr : E.ev.data() + 2;
@@ -1166,17 +1286,62 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
     HIP_OK(hipGetLastError());
     return SV_OK;
   };
-  // final Z measurement of the data register (draw stream t, or *tptr); in
-  // the X basis a Walsh-Hadamard transform of the whole register first, which
-  // removes the Pauli-X frame from the outcome probabilities
-  auto traj_final = [&](hipStream_t q, uint8_t* bits, uint64_t t, const uint64_t* tptr) {
-    if (xbasis) launch_wht_all<T>(q, st, n);
-    hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb)), dim3(256), 0, q, st, cb, dsums,
+  // speculative passes of one trajectory: logical |0> into st, then per unit
+  // instance its prediction pass (st <-> st2 alternate), the decision and the
+  // redos it may need (an X pair two, with a decision between them; a single
+  // check or a chain one).  Returns the register that holds the result.
+  auto traj_spec = [&](hipStream_t q, const BlockRT* rt, uint8_t* rec, double* p1, bool timed,
+                       T** out) -> sv_status {
+    T* cur = st;
+    T* oth = st2;
+    SV_OK_OR_RETURN(launch_upass<T>(spds[0], grid, block, q, cur, &dspass[0], djc, nullptr, nullptr, nullptr,
+                                    &ddec[0], partials, 0, ss0));
+    for (int ui = 0; ui < per_units_s; ++ui) {
+      const int u = ui % nus, r = ui / nus;
+      const Unit& U = sunits[u];
+      const bool zb = U.kind == U_Z;
+      const size_t bi = (size_t)r * ns + U.first;
+      const uint8_t* pred = r == 0 ? dpred0 + U.first : rec + bi - ns;
+      const SpecArgs sa{oth, &dctl[ui], pred, dredos};
+      const BlockRT* rta = zb ? nullptr : rt + bi;
+      const BlockRT* rtb = zb ? rt + bi : nullptr;
+      const int rev = snake ? (ui & 1) : 0;
+      auto pass = [&](bool redo) {
+        return launch_spass<T>(spds[1 + u], redo, grid, block, q, cur, &dspass[1 + u], djc, rta, rtb, &ddec[ui],
+                               &ddec[ui + 1], partials, rev, sa);
+      };
+      auto decide = [&]() {
+        hipLaunchKernelGGL(k_sdecide, dim3(zb ? unit_sums(U.len) : 2 * U.len), dim3(256), 0, q, partials,
+                           (int)grid.x, U.len, zb ? 1 : 0, rt + bi, &ddec[ui], &ddec[ui + 1], rec + bi,
+                           p1 ? p1 + bi : nullptr, &dctl[ui], dacc, dticket);
+      };
+      if (timed) HIP_OK(hipEventRecord(evs[2 * ui], q));
+      SV_OK_OR_RETURN(pass(false));
+      if (timed) HIP_OK(hipEventRecord(evs[2 * ui + 1], q));
+      decide();
+      const int redos = (!zb && U.len == 2) ? 2 : 1;
+      for (int k = 0; k < redos; ++k) {
+        SV_OK_OR_RETURN(pass(true));
+        if (k + 1 < redos) decide();
+      }
+      std::swap(cur, oth);
+    }
+    HIP_OK(hipGetLastError());
+    *out = cur;
+    return SV_OK;
+  };
+  // final Z measurement of the data register buf (draw stream t, or *tptr);
+  // in the X basis a Walsh-Hadamard transform of the whole register first,
+  // which removes the Pauli-X frame from the outcome probabilities (the
+  // outcome probabilities are ratios: a pending renormalisation is harmless)
+  auto traj_final = [&](hipStream_t q, T* buf, uint8_t* bits, uint64_t t, const uint64_t* tptr) {
+    if (xbasis) launch_wht_all<T>(q, buf, n);
+    hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb)), dim3(256), 0, q, buf, cb, dsums,
                        (size_t)0);
-    hipLaunchKernelGGL(k_final_measure<T>, dim3(1), dim3(1024), 0, q, st, n, cb, dsums, job->seed, t,
+    hipLaunchKernelGGL(k_final_measure<T>, dim3(1), dim3(1024), 0, q, buf, n, cb, dsums, job->seed, t,
                        (uint64_t)R * (uint64_t)draws_round, bits, (size_t)0, (const uint64_t*)nullptr,
                        tptr, (const int*)nullptr, (uint64_t)0,
-                       xbasis ? (const Decision*)nullptr : (const Decision*)&ddec[per_units],
+                       xbasis ? (const Decision*)nullptr : (const Decision*)&ddec[fin],
                        (size_t)0);
   };
   double pass_ms_graph = -1.0;
@@ -1226,7 +1391,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
                            (const uint64_t*)(dcur + 1), (const double*)dthr);
       cst = traj_passes(G.q, rt_s, dn_s, rec_s, p1_s, false);
       if (cst == SV_OK) {
-        traj_final(G.q, bits_s, 0, dcur + 1);
+        traj_final(G.q, st, bits_s, 0, dcur + 1);
         hipLaunchKernelGGL(k_commit, dim3(1), dim3(256), 0, G.q, rec_s, p1_s, bits_s, drec, dp1, dbits,
                            per_traj, n, dcur, dcur + 1, job->traj0);
       }
@@ -1268,18 +1433,28 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
           return fail(SV_EBUSY, "cancelled");
         }
         const int tg = c0 + ti;
-        SV_OK_OR_RETURN(traj_passes(s, drt + (size_t)ti * per_traj, ddn ? ddn + (size_t)ti * per_traj : nullptr,
-                                    drec + (size_t)tg * per_traj,
-                                    dp1 ? dp1 + (size_t)tg * per_traj : nullptr, tg == last_t && !async));
-        if (res->final_states) {
-          HIP_OK(hipMemcpyAsync((char*)res->final_states + (size_t)tg * sizeof(T) * 2 * na, st,
-                                sizeof(T) * 2 * na, hipMemcpyDeviceToHost, s));
-          Decision fin{};
-          HIP_OK(hipMemcpyAsync(&fin, &ddec[per_units], sizeof fin, hipMemcpyDeviceToHost, s));
-          HIP_OK(hipStreamSynchronize(s));
-          phi_host[tg] = fin.phi;
+        T* buf = st;
+        if (spec) {
+          SV_OK_OR_RETURN(traj_spec(s, drt + (size_t)ti * per_traj, drec + (size_t)tg * per_traj,
+                                    dp1 ? dp1 + (size_t)tg * per_traj : nullptr, tg == last_t, &buf));
+        } else {
+          SV_OK_OR_RETURN(traj_passes(s, drt + (size_t)ti * per_traj, ddn ? ddn + (size_t)ti * per_traj : nullptr,
+                                      drec + (size_t)tg * per_traj,
+                                      dp1 ? dp1 + (size_t)tg * per_traj : nullptr, tg == last_t && !async));
         }
-        traj_final(s, dbits + (size_t)tg * n, job->traj0 + (uint64_t)tg, nullptr);
+        if (res->final_states) {
+          // a speculative run leaves the last unit's renormalisation pending
+          if (spec)
+            hipLaunchKernelGGL(k_renorm<T>, dim3((unsigned)std::min<uint64_t>(na / 256, 65536)), dim3(256), 0, s,
+                               buf, na, (const Decision*)&ddec[fin]);
+          HIP_OK(hipMemcpyAsync((char*)res->final_states + (size_t)tg * sizeof(T) * 2 * na, buf,
+                                sizeof(T) * 2 * na, hipMemcpyDeviceToHost, s));
+          Decision fd{};
+          HIP_OK(hipMemcpyAsync(&fd, &ddec[fin], sizeof fd, hipMemcpyDeviceToHost, s));
+          HIP_OK(hipStreamSynchronize(s));
+          phi_host[tg] = fd.phi;
+        }
+        traj_final(s, buf, dbits + (size_t)tg * n, job->traj0 + (uint64_t)tg, nullptr);
         HIP_OK(hipGetLastError());
       }
     }
@@ -1294,6 +1469,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       res->gpu_ms = -1.0;
       res->pass_ms = -1.0;
       res->passes_per_round = nu;
+      res->redo_passes = 0;
       return SV_OK;
     }
     HIP_OK(hipEventRecord(ev1, s));
@@ -1321,8 +1497,9 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, ev0, ev1));
   double pass_sum = 0.0;
+  const int timed_units = spec ? per_units_s : per_units;
   if (pass_ms_graph < 0.0) {
-    for (int ui = 0; ui < per_units; ++ui) {
+    for (int ui = 0; ui < timed_units; ++ui) {
       float pm = 0.f;
       HIP_OK(hipEventElapsedTime(&pm, evs[2 * ui], evs[2 * ui + 1]));
       pass_sum += pm;
@@ -1331,8 +1508,10 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   res->gpu_ms = ms;
   // replayed graphs: the last trajectory's device time per pass (an upper
   // bound that includes its decisions, draws and final measurement)
-  res->pass_ms = pass_ms_graph >= 0.0 ? pass_ms_graph : pass_sum / per_units;
-  res->passes_per_round = nu;
+  res->pass_ms = pass_ms_graph >= 0.0 ? pass_ms_graph : pass_sum / timed_units;
+  res->passes_per_round = spec ? nus : nu;
+  res->redo_passes = 0;
+  if (spec) HIP_OK(hipMemcpy(&res->redo_passes, dredos, sizeof(int), hipMemcpyDeviceToHost));
   return SV_OK;
 }
 

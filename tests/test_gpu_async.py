@@ -20,8 +20,11 @@ def _jobs():
     return a, b
 
 
-def test_two_streams_match_synchronous_runs():
+def test_two_streams_match_synchronous_runs(monkeypatch):
     import torch
+    # enqueued runs use the plain passes (no speculative units), so does the
+    # synchronous reference here
+    monkeypatch.setenv("QECSV_SPEC", "0")
     a, b = _jobs()
     ref_a = qs.run_rounds(**a)
     ref_b = qs.run_rounds(**b)

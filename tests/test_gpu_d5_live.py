@@ -21,8 +21,11 @@ pytestmark = pytest.mark.gpu
 
 D, R, N_TRAJ, SEED, P, ZETA = 5, 2, 2, 1, 1e-2, 0.01
 # the pass launch parameters the benchmark's autotuner picks on MI355X
-BENCH_TUNING = {"QECSV_PASS_WGS_PER_CU": "16", "QECSV_ZCHAIN": "4", "QECSV_SNAKE": "1"}
-DEFAULT_TUNING = {"QECSV_PASS_WGS_PER_CU": "0", "QECSV_ZCHAIN": "4", "QECSV_SNAKE": "1"}
+# (speculative units, Z chains of six), the plain passes in that launch
+# configuration with Z chains of four, and the built-in defaults
+SPEC_TUNING = {"QECSV_PASS_WGS_PER_CU": "16", "QECSV_ZCHAIN": "6", "QECSV_SNAKE": "1", "QECSV_SPEC": "1"}
+BENCH_TUNING = {"QECSV_PASS_WGS_PER_CU": "16", "QECSV_ZCHAIN": "4", "QECSV_SNAKE": "1", "QECSV_SPEC": "0"}
+DEFAULT_TUNING = {"QECSV_PASS_WGS_PER_CU": "0", "QECSV_ZCHAIN": "4", "QECSV_SNAKE": "1", "QECSV_SPEC": "0"}
 _ORACLE = {}
 
 
@@ -64,9 +67,26 @@ def _compare(variant, dtype, tuning, monkeypatch):
     return g
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_d5_live_speculative(dtype, monkeypatch):
+    """The benchmark's configuration: speculative units (six pairs of X
+    checks, two chains of six Z checks: 8 prediction passes a round), 16 pass
+    workgroups per CU taking tiles grid-stride, alternating traversal; the
+    first round's X checks are random, so redos run."""
+    g = _compare("base", dtype, SPEC_TUNING, monkeypatch)
+    assert g["passes_per_round"] == 8
+    assert g["redo_passes"] > 0
+
+
+@pytest.mark.parametrize("variant", ["xbasis", "idle"])
+def test_d5_live_speculative_flags(variant, monkeypatch):
+    _compare(variant, "c128" if variant == "xbasis" else "c64", SPEC_TUNING, monkeypatch)
+
+
 def test_d5_live_c128_bench_tuning(monkeypatch):
-    """The benchmark's configuration: 16 pass workgroups per CU, each taking
-    tiles grid-stride, Z chains of four, alternating traversal."""
+    """The plain passes in the benchmark's launch configuration: 16 pass
+    workgroups per CU, each taking tiles grid-stride, Z chains of four,
+    alternating traversal."""
     g = _compare("base", "c128", BENCH_TUNING, monkeypatch)
     assert qs.tuning_get(5, "c128")["pass_wgs_per_cu"] == 16
     assert g["passes_per_round"] == 15

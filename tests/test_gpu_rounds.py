@@ -152,11 +152,13 @@ def test_high_noise_frames_d4():
 
 
 @pytest.mark.parametrize("d,dtype", [(3, "c128"), (4, "c64"), (5, "c128")])
-def test_graph_replay_matches_stream_launches(d, dtype):
+def test_graph_replay_matches_stream_launches(monkeypatch, d, dtype):
     """SV_RUN_GRAPH (one trajectory's launch sequence captured once, replayed
     per trajectory with a device-side trajectory counter) gives the records,
     p1 and final bits of the stream launches, for every replay; an eager run
-    sits between two graph runs."""
+    sits between two graph runs.  Graph runs use the plain passes, as do the
+    stream launches here (no speculative units)."""
+    monkeypatch.setenv("QECSV_SPEC", "0")
     n_sites = oracle.template_counts(d, oracle.GATESET_CR)[1]
     eps = workloads.eps_sites(n_sites, (0.0, 0.05), 8)
     n = {3: 24, 4: 6, 5: 2}[d]
@@ -306,6 +308,7 @@ def test_zz_plaquette_graph_and_d5():
 @pytest.mark.parametrize("chain", [1, 2, 4])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_x_pairs_parity_d4(monkeypatch, dtype, chain):
+    monkeypatch.setenv("QECSV_SPEC", "0")
     monkeypatch.setenv("QECSV_XPAIR", "1")
     monkeypatch.setenv("QECSV_ZCHAIN", str(chain))
     n_sites = oracle.template_counts(4, oracle.GATESET_CR)[1]
@@ -320,6 +323,7 @@ def test_x_pairs_parity_d4(monkeypatch, dtype, chain):
 def test_x_pairs_parity_d4_flags(monkeypatch, flags):
     """Pairs under the textbook gate set and the physical-schedule flags (the
     X basis starts from logical |+> in the pass that sums the first pair)."""
+    monkeypatch.setenv("QECSV_SPEC", "0")
     monkeypatch.setenv("QECSV_XPAIR", "1")
     gs = "textbook" if flags == "textbook" else "cr"
     _compare(4, gs, 2, 3, seed=73, p=0.02, eps=0.03, zeta=0.01, xbasis=flags == "xbasis",
@@ -327,6 +331,7 @@ def test_x_pairs_parity_d4_flags(monkeypatch, flags):
 
 
 def test_x_pairs_graph_replay(monkeypatch):
+    monkeypatch.setenv("QECSV_SPEC", "0")
     monkeypatch.setenv("QECSV_XPAIR", "1")
     kw = dict(d=4, gateset="cr", rounds=2, n_traj=3, seed=77, p=0.02, eps=0.02, zeta=0.01, want_p1=True)
     a = qs.run_rounds(**kw)
