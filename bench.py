@@ -414,6 +414,9 @@ def main():
                     help="time only the library's plain register copy (HBM calibration)")
     ap.add_argument("--only", choices=["batch", "serving", "precision", "fused", "gates"], default=None,
                     help="run one side measurement alone and print it (for profiling)")
+    ap.add_argument("--zeta", type=float, default=None,
+                    help="data ZZ angle of the timed d=5 workload (default: the workload's 0.01; "
+                         "0 runs the speculative passes; for profiles, not the benchmark line)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-launch, serving and precision measurements")
     ap.add_argument("--precision-traj", type=int, default=20,
@@ -458,6 +461,8 @@ def main():
         print(json.dumps({"precision": precision_run(qs, args.precision_traj, args.precision_stat_traj)}))
         return
     c = dict(workloads.CONFIGS["d5_cr_c128"])
+    if args.zeta is not None:
+        c["zeta"] = args.zeta
     d, R = c["d"], c["rounds"]
     n_stab, n_sites, _ = qs.template_info(d, "cr")
     eps = workloads.eps_sites(n_sites, c["theta"], c["seed"])
@@ -498,11 +503,13 @@ def main():
         "dtype": "f64" if args.dtype == "c128" else "f32",
         "data": "synthetic",
         "config": {"workload": "d5_cr_c128: rotated surface code d=5, 26 qubits, cross-resonance "
-                               "gates, p=1e-3, theta~U[0,0.05) per site, zeta=0.01, 5 rounds",
+                               f"gates, p=1e-3, theta~U[0,0.05) per site, zeta={c['zeta']:g}, 5 rounds",
                    "state": args.dtype, "trajectories_per_step": 1, "rounds": R,
                    "stabilizers_per_round": n_stab},
         "per_circuit_equivalent_gbs": per_circuit_gbs,
-        "hbm_gbs_moved": (R * r["passes_per_round"] + 1) * blk_bytes / (ms_round * R * 1e-3) / 1e9,
+        "hbm_gbs_moved": (R * r["passes_per_round"] + r["redo_passes"] / args.steps + 1) * blk_bytes
+                         / (ms_round * R * 1e-3) / 1e9,
+        "redo_passes_per_round": r["redo_passes"] / rounds_total,
         "tuning": tuning,
         "kernel_sources_sha256": kernel_source_hash(),
         "gpu_ms_device": r["gpu_ms"],
