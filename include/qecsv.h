@@ -356,7 +356,9 @@ sv_status sv_tuning_load(const char* path);
  * per SIMD; the environment variable QECSV_BATCH_SPLIT = 1, 2 or 4 forces the
  * count); d = 4 keeps the registers in HBM and runs the trajectories in
  * lockstep through the register passes, the trajectory being a grid
- * dimension.  Synchronous. */
+ * dimension; with zeta = 0 those passes are speculative as in sv_run_rounds
+ * (each slot then holds two registers; QECSV_SPEC = 0 / 1 forces the mode).
+ * Synchronous. */
 typedef struct sv_batch_job {
   int d;                    /* 2..4 */
   int gateset;              /* sv_gateset */

@@ -863,12 +863,15 @@ struct UpassWaves {
 
 // Speculative passes (SP = 1: prediction, SP = 2: redo): the register they
 // write, the unit instance's control record, the predicted outcome of each
-// member (prediction pass), a counter of the redos that ran.
+// member (prediction pass), a counter of the redos that ran; lockstep
+// launches: per trajectory slot the register moves by the slot stride of st,
+// the record by ctl_stride, the predictions by pred_stride.
 struct SpecArgs {
   void* out;
   SpecCtl* ctl;
   const uint8_t* pred;
   int* redos;
+  size_t ctl_stride, pred_stride;
 };
 
 template <typename T, int AK, int AP, int BK, int BP, bool DN, bool BM0, int SP>
@@ -883,29 +886,32 @@ __device__ __forceinline__ void upass_body(
   constexpr bool kSpecA = SP != 0 && (AK == U_X || AK == U_XP);
   constexpr bool kSpecB = SP != 0 && BK == U_Z;
   static_assert(SP == 0 || (kSpecA && BK == U_NONE) || (kSpecB && AK == U_SC), "speculative unit kinds");
-  int sm = 0;  // outcome bits applied to the speculative unit
-  if constexpr (SP == 2) {
-    if (!sa.ctl->run) return;  // nothing to redo
-    sm = sa.ctl->m;
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(sa.redos, 1);
-  } else if constexpr (SP == 1) {
-    constexpr int kLen = kSpecA ? (AK == U_XP ? 2 : 1) : BP;
-#pragma unroll
-    for (int l = 0; l < kLen; ++l) sm |= (sa.pred[l] & 1) << l;
-    // (byte loads go through the vector unit: the bits are uniform, and the
-    // tables they select must stay scalar loads)
-    sm = __builtin_amdgcn_readfirstlane(sm);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *sa.ctl = SpecCtl{sm, 0, 1, 0};
-  }
   // trajectory slot (lockstep launches): walked backwards with the tiles, so
   // that a pass starts on the registers its predecessor wrote last
   const size_t slot = reverse ? gridDim.y - 1 - blockIdx.y : blockIdx.y;
+  int sm = 0;  // outcome bits applied to the speculative unit
+  if constexpr (SP == 2) {
+    SpecCtl* const ctl = sa.ctl + slot * sa.ctl_stride;
+    if (!ctl->run) return;  // nothing to redo
+    sm = ctl->m;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(sa.redos, 1);
+  } else if constexpr (SP == 1) {
+    constexpr int kLen = kSpecA ? (AK == U_XP ? 2 : 1) : BP;
+    const uint8_t* const pred = sa.pred + slot * sa.pred_stride;
+#pragma unroll
+    for (int l = 0; l < kLen; ++l) sm |= (pred[l] & 1) << l;
+    // (byte loads go through the vector unit: the bits are uniform, and the
+    // tables they select must stay scalar loads)
+    sm = __builtin_amdgcn_readfirstlane(sm);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sa.ctl[slot * sa.ctl_stride] = SpecCtl{sm, 0, 1, 0};
+  }
   st += slot * ss.st;
   constexpr uint32_t kAmp = 2 * sizeof(T);  // bytes per amplitude
   const RegBuf<T> reg(st, (uint32_t)(kAmp << (pd->tb + pd->n_outer)));
   // speculative passes write the other register buffer (the redo reads the
   // pass's input again)
-  const RegBuf<T> regw(SP != 0 ? static_cast<T*>(sa.out) : st, (uint32_t)(kAmp << (pd->tb + pd->n_outer)));
+  const RegBuf<T> regw(SP != 0 ? static_cast<T*>(sa.out) + slot * ss.st : st,
+                       (uint32_t)(kAmp << (pd->tb + pd->n_outer)));
   if (rta) rta += slot * ss.rt;
   if (rtb) rtb += slot * ss.rt;
   if (dna) dna += slot * ss.rt;
@@ -1833,11 +1839,27 @@ __global__ __launch_bounds__(256) void k_udecide(const double* __restrict__ part
 // renormalisation is applied by the next pass).  A redo that re-applied a
 // decided unit leaves nothing to decide (run is cleared); after a redo that
 // did not run the kernel returns at once.
+// split = 1, grid (sums, slots): workgroup a reduces sum a, the last of a
+// slot to finish (ticket) decides; split = 0, grid (slots): one workgroup
+// per slot (lockstep launches: thousands of slots, each with few partials,
+// and no fence per workgroup).  A slot's tables, records, control record,
+// partials and ticket are found with the lockstep strides.
 __global__ __launch_bounds__(256) void k_sdecide(const double* __restrict__ partials, int n, int len, int tree,
                                                  const BlockRT* __restrict__ rtb, const Decision* __restrict__ dec_a,
                                                  Decision* __restrict__ dec_b, uint8_t* __restrict__ rec_b,
                                                  double* __restrict__ p1_b, SpecCtl* __restrict__ ctl,
-                                                 double* __restrict__ sums, unsigned* __restrict__ ticket) {
+                                                 double* __restrict__ sums, unsigned* __restrict__ ticket,
+                                                 SlotStrides ss, size_t rec_stride, size_t ctl_stride, int split) {
+  const size_t slot = split ? blockIdx.y : blockIdx.x;
+  partials += slot * kChainAcc * n;
+  rtb += slot * ss.rt;
+  dec_a += slot * ss.dec;
+  dec_b += slot * ss.dec;
+  rec_b += slot * rec_stride;
+  if (p1_b) p1_b += slot * rec_stride;
+  ctl += slot * ctl_stride;
+  sums += slot * kChainAcc;
+  ticket += slot;
   // the record as the workgroup sees it (workgroup 0 may clear run meanwhile)
   __shared__ int c_run, c_known;
   if (threadIdx.x == 0) {
@@ -1848,37 +1870,51 @@ __global__ __launch_bounds__(256) void k_sdecide(const double* __restrict__ part
   __syncthreads();
   if (!c_run) return;
   if (c_known >= len) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->run = 0;
+    if ((!split || blockIdx.x == 0) && threadIdx.x == 0) ctl->run = 0;
     return;
   }
   const int nacc = tree ? unit_sums(len) : 2 * len;
-  const int a = blockIdx.x;
-  if (a >= nacc) return;
-  partials += (size_t)a * n;
-  __shared__ double red[8];
   __shared__ double full[kChainAcc];
-  __shared__ int last;
-  double s = 0.0, dummy = 0.0;
-  for (int i0 = 0; i0 < n; i0 += 8 * (int)blockDim.x) {
-    double v[8];
+  __shared__ double col[kChainAcc];
+  const volatile double* vs = col;
+  if (split) {
+    const int a = blockIdx.x;
+    if (a >= nacc) return;
+    partials += (size_t)a * n;
+    __shared__ double red[8];
+    __shared__ int last;
+    double s = 0.0, dummy = 0.0;
+    for (int i0 = 0; i0 < n; i0 += 8 * (int)blockDim.x) {
+      double v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int i = i0 + k * (int)blockDim.x + (int)threadIdx.x;
-      v[k] = i < n ? partials[i] : 0.0;
+      for (int k = 0; k < 8; ++k) {
+        const int i = i0 + k * (int)blockDim.x + (int)threadIdx.x;
+        v[k] = i < n ? partials[i] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += v[k];
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) s += v[k];
-  }
-  block_sum2(s, dummy, red);
-  if (threadIdx.x == 0) {
-    sums[a] = s;
+    block_sum2(s, dummy, red);
+    if (threadIdx.x == 0) {
+      sums[a] = s;
+      __threadfence();
+      last = atomicAdd(ticket, 1u) == (unsigned)(nacc - 1);
+    }
+    __syncthreads();
+    if (!last) return;
     __threadfence();
-    last = atomicAdd(ticket, 1u) == (unsigned)(nacc - 1);
+    vs = sums;
+    if (threadIdx.x == 0) *ticket = 0u;
+  } else {
+    // one workgroup per slot (lockstep: few partials per sum): thread a
+    // sums sum a serially, in the order of the partials
+    for (int a = threadIdx.x; a < nacc; a += blockDim.x) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s += partials[(size_t)a * n + i];
+      col[a] = s;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const volatile double* vs = sums;
   if (tree) {
     chain_tree_lds(len, [&](int b) { return vs[b]; }, full);
     if (threadIdx.x == 0) {
@@ -1887,7 +1923,6 @@ __global__ __launch_bounds__(256) void k_sdecide(const double* __restrict__ part
       ctl->m = dec_b->m;
       ctl->known = len;
       ctl->run = dec_b->m != applied;
-      *ticket = 0u;
     }
     return;
   }
@@ -1918,8 +1953,14 @@ __global__ __launch_bounds__(256) void k_sdecide(const double* __restrict__ part
       dec_b->m = m;
       dec_b->Sm = Sm;
     }
-    *ticket = 0u;
   }
+}
+
+// Decision records of n trajectory slots (stride apart) for a register that
+// logical |0> is written into: norm 1, frame 0.
+__global__ void k_dec_init(Decision* __restrict__ d, int n, size_t stride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[(size_t)i * stride] = Decision{1.0, 0, 0u};
 }
 
 // The pending renormalisation 1 / sqrt(d->Sm) applied to a whole register.

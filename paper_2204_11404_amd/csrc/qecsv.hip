@@ -888,8 +888,7 @@ sv_status launch_upass(const UnitPass& h, dim3 g, dim3 b, hipStream_t s, T* st, 
 template <typename T>
 sv_status launch_spass(const UnitPass& h, bool redo, dim3 g, dim3 b, hipStream_t s, T* st, const UnitPass* pd,
                        const JobConst* jc, const BlockRT* rta, const BlockRT* rtb, const Decision* da,
-                       Decision* db, double* part, int rev, SpecArgs sa) {
-  const SlotStrides ss{0, 0, 0};
+                       Decision* db, double* part, int rev, SpecArgs sa, SlotStrides ss) {
 #define QEC_SP(AK, AP, BK, BP)                                                                              \
   if (h.akind == AK && ap == AP && h.bkind == BK && bp == BP) {                                             \
     if (redo)                                                                                               \
@@ -1177,8 +1176,6 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
     HIP_OK(hipMemcpyAsync(dspass, spds.data(), sizeof(UnitPass) * spds.size(), hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(dpred0, pred0.data(), pred0.size(), hipMemcpyHostToDevice, s));
     HIP_OK(hipMemsetAsync(dredos, 0, sizeof(int), s));
-    // the host vectors are read by the copies: wait before they can go
-    HIP_OK(hipStreamSynchronize(s));
   }
   std::vector<double> eps(n_angles, job->eps);
   if (job->eps_site)
@@ -1302,18 +1299,18 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       const bool zb = U.kind == U_Z;
       const size_t bi = (size_t)r * ns + U.first;
       const uint8_t* pred = r == 0 ? dpred0 + U.first : rec + bi - ns;
-      const SpecArgs sa{oth, &dctl[ui], pred, dredos};
+      const SpecArgs sa{oth, &dctl[ui], pred, dredos, 0, 0};
       const BlockRT* rta = zb ? nullptr : rt + bi;
       const BlockRT* rtb = zb ? rt + bi : nullptr;
       const int rev = snake ? (ui & 1) : 0;
       auto pass = [&](bool redo) {
         return launch_spass<T>(spds[1 + u], redo, grid, block, q, cur, &dspass[1 + u], djc, rta, rtb, &ddec[ui],
-                               &ddec[ui + 1], partials, rev, sa);
+                               &ddec[ui + 1], partials, rev, sa, ss0);
       };
       auto decide = [&]() {
         hipLaunchKernelGGL(k_sdecide, dim3(zb ? unit_sums(U.len) : 2 * U.len), dim3(256), 0, q, partials,
                            (int)grid.x, U.len, zb ? 1 : 0, rt + bi, &ddec[ui], &ddec[ui + 1], rec + bi,
-                           p1 ? p1 + bi : nullptr, &dctl[ui], dacc, dticket);
+                           p1 ? p1 + bi : nullptr, &dctl[ui], dacc, dticket, ss0, (size_t)0, (size_t)0, 1);
       };
       if (timed) HIP_OK(hipEventRecord(evs[2 * ui], q));
       SV_OK_OR_RETURN(pass(false));
@@ -1511,7 +1508,10 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   res->pass_ms = pass_ms_graph >= 0.0 ? pass_ms_graph : pass_sum / timed_units;
   res->passes_per_round = spec ? nus : nu;
   res->redo_passes = 0;
-  if (spec) HIP_OK(hipMemcpy(&res->redo_passes, dredos, sizeof(int), hipMemcpyDeviceToHost));
+  if (spec) {  // on the job's stream (a plain copy would wait for every stream of the device)
+    HIP_OK(hipMemcpyAsync(&res->redo_passes, dredos, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
   return SV_OK;
 }
 
@@ -1804,11 +1804,25 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
   const size_t per_reg_bytes = reg * sizeof(T);
   const sv_tuning tune = tuning_for(d, sizeof(T) == 8 ? SV_C128 : SV_C64);
   const size_t cap = (size_t)tune.lockstep_mib << 20;
-  const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)nt, cap / per_reg_bytes));
   const int per_traj = in.max_rounds * ns;
   const std::vector<Unit> units = make_units_paired(tp, tune.zchain, n, tune.xpair);
   const int nu = (int)units.size();
-  const size_t dec_stride = (size_t)in.max_rounds * nu + 1;
+  // speculative units (as for one register: on when zeta = 0 unless
+  // QECSV_SPEC says otherwise); each slot then holds two registers
+  const int spec_env = env_int("QECSV_SPEC", -1);
+  bool spec = (spec_env < 0 ? in.zeta == 0.0 : spec_env != 0) && !tp.any_dense;
+  std::vector<Unit> sunits;
+  std::vector<UnitPass> spds;
+  if (spec) {
+    sunits = make_spec_units(tp, tune.zchain, n);
+    spds = make_spec_passes(n, tb, tp, sunits);
+    for (const UnitPass& h : spds)
+      if (h.tb <= 0 || (h.bkind == U_Z && h.bmode == 0)) spec = false;
+  }
+  const int nus = spec ? (int)sunits.size() : 0;
+  const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)nt, cap / (per_reg_bytes * (spec ? 2 : 1))));
+  const size_t dec_stride = (size_t)in.max_rounds * (spec ? nus : nu) + 1;
+  const size_t ctl_stride = (size_t)in.max_rounds * nus;
   const int n_sites = std::max(1, tp.n_sites);
   hipStream_t s = in.hs;
   DevBufs M(s);
@@ -1847,6 +1861,24 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
   HIP_OK(M.alloc(&derr, sizeof(int)));
   HIP_OK(M.alloc(&drec, (size_t)per_traj * G));
   HIP_OK(M.alloc(&dbits, (size_t)n * G));
+  T* st2 = nullptr;
+  UnitPass* dspass = nullptr;
+  SpecCtl* dctl = nullptr;
+  uint8_t* dpred0 = nullptr;
+  int* dredos = nullptr;
+  std::vector<uint8_t> pred0;
+  if (spec) {
+    for (const TBlock& b : tp.blocks)
+      pred0.push_back(in.gateset == SV_GATESET_CR ? (uint8_t)((b.w / 2) % 2) : (uint8_t)0);
+    HIP_OK(M.alloc(&st2, per_reg_bytes * G));
+    HIP_OK(M.alloc(&dspass, sizeof(UnitPass) * spds.size()));
+    HIP_OK(M.alloc(&dctl, sizeof(SpecCtl) * ctl_stride * G));
+    HIP_OK(M.alloc(&dpred0, pred0.size()));
+    HIP_OK(M.alloc(&dredos, sizeof(int)));
+    HIP_OK(hipMemcpyAsync(dspass, spds.data(), sizeof(UnitPass) * spds.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(dpred0, pred0.data(), pred0.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemsetAsync(dredos, 0, sizeof(int), s));
+  }
 
   const std::vector<UnitPass> pds = make_unit_passes(n, tb, tp, units);
   const JobConst jc = make_job_const(d, in.zeta);
@@ -1937,10 +1969,79 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
                          ss, (size_t)per_traj, dacc, dticket, 0);
     };
     prepare(s, 0, rtA, gn);
+    const int R0 = hrounds[0];
+    // final Z measurement of the slots [from, from + cnt) on register buffer
+    // buf, their frames in the decision records at dfin
+    auto measure = [&](const T* buf, int from, int cnt, const Decision* dfin) {
+      hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb), cnt), dim3(256), 0, s, buf + (size_t)from * reg, cb,
+                         dsums, reg);
+      hipLaunchKernelGGL(k_final_measure<T>, dim3(cnt), dim3(1024), 0, s, buf + (size_t)from * reg, n, cb, dsums,
+                         (uint64_t)0, (uint64_t)0, (uint64_t)0, dbits + (size_t)from * n, reg, dseed + from,
+                         dstream + from, drounds + from, (uint64_t)tp.n_draws, dfin, dec_stride);
+    };
+    if (spec) {
+      // speculative units: logical |0> into st, then per unit of every round
+      // its prediction pass over the active slots (st <-> st2 for all of
+      // them), the decision and the redos (see run_rounds_t)
+      T* cur = st;
+      T* oth = st2;
+      hipLaunchKernelGGL(k_dec_init, dim3((unsigned)((gn + 255) / 256)), dim3(256), 0, s, ddec, gn, dec_stride);
+      SV_OK_OR_RETURN(launch_upass<T>(spds[0], dim3(gx_of(spds[0]), gn), block, s, cur, &dspass[0], djc, nullptr,
+                                      nullptr, nullptr, ddec, partials, 0, ss));
+      int ui = 0;
+      for (int r = 0; r < R0; ++r) {
+        const int Ar = active(r), An = active(r + 1);
+        BlockRT* rt_cur = (r & 1) ? rtB : rtA;
+        BlockRT* rt_nxt = (r & 1) ? rtA : rtB;
+        if (An > 0) {
+          HIP_OK(hipEventRecord(ev.fork, s));
+          HIP_OK(hipStreamWaitEvent(ev.s2, ev.fork, 0));
+          prepare(ev.s2, r + 1, rt_nxt, An);
+          HIP_OK(hipEventRecord(ev.join, ev.s2));
+        }
+        for (int u = 0; u < nus; ++u, ++ui) {
+          const Unit& U = sunits[u];
+          const bool zb = U.kind == U_Z;
+          const UnitPass& h = spds[1 + u];
+          const unsigned gx = gx_of(h);
+          const int bi = r * ns + U.first;
+          const SpecArgs sa{oth, dctl + ui, r == 0 ? dpred0 + U.first : drec + bi - ns, dredos, ctl_stride,
+                            r == 0 ? (size_t)0 : (size_t)per_traj};
+          const BlockRT* rtu = rt_cur + U.first;
+          const int rev = (++pass_no) & 1;
+          // redo grid: a quarter of the pass's workgroups per slot.  Nearly
+          // every redo launch has some slot to redo among thousands, and a
+          // full-width grid mostly dispatches workgroups that return at once
+          // (d=4, 4096 trajectories: 38.7 ms per launch; 39.0 full width,
+          // 40.7 with two and 44.9 with one workgroup per slot)
+          const unsigned gr = std::max(1u, gx / 4);
+          auto pass = [&](bool redo) {
+            return launch_spass<T>(h, redo, dim3(redo ? gr : gx, Ar), block, s, cur, &dspass[1 + u], djc,
+                                   zb ? nullptr : rtu, zb ? rtu : nullptr, ddec + ui, ddec + ui + 1, partials, rev,
+                                   sa, ss);
+          };
+          auto sdecide = [&](unsigned parts) {
+            hipLaunchKernelGGL(k_sdecide, dim3(Ar), dim3(64), 0, s, partials, (int)parts, U.len, zb ? 1 : 0, rtu,
+                               ddec + ui, ddec + ui + 1, drec + bi, (double*)nullptr, dctl + ui, dacc, dticket, ss,
+                               (size_t)per_traj, ctl_stride, 0);
+          };
+          SV_OK_OR_RETURN(pass(false));
+          sdecide(gx);
+          const int redos = (!zb && U.len == 2) ? 2 : 1;
+          for (int k = 0; k < redos; ++k) {
+            SV_OK_OR_RETURN(pass(true));
+            if (k + 1 < redos) sdecide(gr);
+          }
+          std::swap(cur, oth);
+        }
+        if (An > 0) HIP_OK(hipStreamWaitEvent(s, ev.join, 0));
+        if (Ar > An) measure(cur, An, Ar - An, ddec + (size_t)An * dec_stride + ui);
+        HIP_OK(hipGetLastError());
+      }
+    } else {
     SV_OK_OR_RETURN(launch_upass<T>(pds[0], dim3(gx_of(pds[0]), gn), block, s, st, &dpass[0], djc,
                                     nullptr, rtA + units[0].first, nullptr, ddec, partials, 0, ss));
     decide(gn, rtA, 0, 0, gx_of(pds[0]));
-    const int R0 = hrounds[0];
     for (int r = 0; r < R0; ++r) {
       const int Ar = active(r), An = active(r + 1);
       BlockRT* rt_cur = (r & 1) ? rtB : rtA;
@@ -1978,15 +2079,11 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
                                           st + (size_t)An * reg, &dpass[nu + 1], djc,
                                           rta + (size_t)An * ns, nullptr,
                                           ddec + (size_t)An * dec_stride + ui, dfin, partials, rev, ss));
-          hipLaunchKernelGGL(k_final_sums<T>, dim3(1u << (n - cb), cnt), dim3(256), 0, s,
-                             st + (size_t)An * reg, cb, dsums, reg);
-          hipLaunchKernelGGL(k_final_measure<T>, dim3(cnt), dim3(1024), 0, s, st + (size_t)An * reg, n,
-                             cb, dsums, (uint64_t)0, (uint64_t)0, (uint64_t)0, dbits + (size_t)An * n,
-                             reg, dseed + An, dstream + An, drounds + An, (uint64_t)tp.n_draws,
-                             (const Decision*)dfin, dec_stride);
+          measure(st, An, cnt, dfin);
         }
       }
       HIP_OK(hipGetLastError());
+    }
     }
     HIP_OK(hipMemcpyAsync(hrec.data(), drec, (size_t)per_traj * gn, hipMemcpyDeviceToHost, s));
     HIP_OK(hipMemcpyAsync(hbits.data(), dbits, (size_t)n * gn, hipMemcpyDeviceToHost, s));
@@ -2019,8 +2116,11 @@ size_t batch_footprint(int d, int dtype, int n_traj, int max_rounds, int n_sites
     const size_t reg = elem << n;
     const size_t cap = (size_t)tuning_for(d, dtype).lockstep_mib << 20;
     const size_t G = std::max<size_t>(1, std::min<size_t>((size_t)n_traj, cap / reg));
+    // speculative units hold two registers per slot in groups half as large
+    const size_t G2 = std::max<size_t>(1, std::min<size_t>((size_t)n_traj, cap / (2 * reg)));
     const size_t n_tiles = (size_t)1 << (n - std::min(kTileMax, n));
-    b += G * (reg + sizeof(double) * kChainAcc * n_tiles + sizeof(Decision) * (size_t)max_rounds * n);
+    b += std::max(G, 2 * G2) * reg +
+         G * (sizeof(double) * kChainAcc * n_tiles + sizeof(Decision) * (size_t)max_rounds * n);
   }
   return b + (1 << 20);
 }

@@ -26,7 +26,8 @@ size_t rounds_footprint(int d, int dtype, int n_traj, int rounds) {
   const size_t ns = (size_t)d * d - 1;
   const size_t per_traj = sizeof(BlockRT) * (size_t)rounds * ns;
   const size_t table = std::min<size_t>((size_t)n_traj * per_traj, std::max<size_t>(per_traj, (size_t)64 << 20));
-  return (elem << n) + table + (size_t)n_traj * (rounds * ns + n) + (sizeof(double) << (n > 12 ? n - 12 : 0)) +
+  // two registers: a speculative run writes the other buffer each pass
+  return (2 * elem << n) + table + (size_t)n_traj * (rounds * ns + n) + (sizeof(double) << (n > 12 ? n - 12 : 0)) +
          (2u << 20);
 }
 

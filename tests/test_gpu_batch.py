@@ -209,3 +209,37 @@ def test_batch_d4_x_pairs(dtype, monkeypatch):
     monkeypatch.setenv("QECSV_LOCKSTEP_MIB", "2")
     print(f"case batch d=4 x pairs {dtype}", flush=True)
     _check(4, "cr", dtype, 12, seed=67, p_range=(5e-3, 3e-2), zeta=0.01)
+
+
+# ------------------------------------------- speculative lockstep passes
+# Without the data ZZ layer (zeta = 0) the lockstep passes are speculative
+# (a pair of X checks or a chain of Z checks summed and applied in one pass
+# with predicted outcomes, redone per slot when a prediction fails); with
+# QECSV_SPEC=1 also at zeta = 0.01 and high noise, where predictions fail
+# often.  Several lockstep groups (each slot then holds two registers).
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_d4_speculative_groups(dtype, monkeypatch):
+    monkeypatch.delenv("QECSV_SPEC", raising=False)
+    monkeypatch.setenv("QECSV_LOCKSTEP_MIB", "2")
+    print(f"case batch d=4 speculative groups {dtype}", flush=True)
+    _check(4, "cr", dtype, 16, seed=81, p_range=(5e-4, 2e-2))
+
+
+@pytest.mark.parametrize("gateset", ["cr", "textbook"])
+def test_batch_d4_speculative_forced(gateset, monkeypatch):
+    monkeypatch.setenv("QECSV_SPEC", "1")
+    print(f"case batch d=4 speculative forced {gateset}", flush=True)
+    _check(4, gateset, "c128", 12, seed=83, p_range=(1e-2, 5e-2), zeta=0.01)
+
+
+def test_batch_d4_speculative_matches_plain(monkeypatch):
+    """The same launch with speculation on and off: identical records and
+    final bits."""
+    n_sites = qs.template_info(4, "cr")[1]
+    R, p, eps = workloads.batch_params(64, n_sites, 85, p=(5e-4, 5e-3))
+    out = []
+    for spec in ("1", "0"):
+        monkeypatch.setenv("QECSV_SPEC", spec)
+        out.append(qs.run_batch(4, "cr", R, p, 85, eps_site=eps, dtype="c64", max_rounds=9))
+    assert np.array_equal(out[0]["records"], out[1]["records"])
+    assert np.array_equal(out[0]["final_bits"], out[1]["final_bits"])
