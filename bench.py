@@ -288,10 +288,12 @@ def batch_run(qs, d, n_traj, dtype, seed=7):
            "trajectories_per_s": n_traj / (g["gpu_ms"] * 1e-3),
            "per_circuit_equivalent_gbs": alg / (g["gpu_ms"] * 1e-3) / 1e9, "tuning": tuning}
     if d == 4:
-        # registers in HBM: one pass per X check or pair and per chain of Z checks
-        passes = qs.check_pass_layouts(d, "cr", tuning["zchain"], tuning.get("xpair", 0)) - 2
-        moved = (int(R.sum()) * passes + n_traj) * reg
+        # registers in HBM: one pass per unit (an X check, a pair of them or a
+        # chain of Z checks) and round, one per redo of a speculative unit
+        passes = g["passes_per_round"]
+        moved = (int(R.sum()) * passes + g["redo_passes"] + n_traj) * reg
         out["passes_per_round"] = passes
+        out["redo_passes_per_round"] = g["redo_passes"] / int(R.sum())
         out["hbm_gbs_moved"] = moved / (g["gpu_ms"] * 1e-3) / 1e9
         out["hbm_frac_moved"] = out["hbm_gbs_moved"] / PEAK_HBM_GBS
     return out

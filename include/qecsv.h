@@ -380,6 +380,10 @@ typedef struct sv_batch_result {
   uint8_t* records;     /* host [n_traj][max_rounds][d^2-1]; rows past rounds[i] are 0 */
   uint8_t* final_bits;  /* host [n_traj][d^2] */
   double gpu_ms;        /* out: device time of the launch (hipEvents) */
+  int passes_per_round; /* out: d = 4: register passes per round (speculative
+                           units: prediction passes); 0 for d <= 3 */
+  int redo_passes;      /* out: speculative redos that ran (one per trajectory
+                           and unit); 0 without speculative units */
 } sv_batch_result;
 
 sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res);

@@ -62,7 +62,7 @@ class BatchJob(ctypes.Structure):
 class BatchResult(ctypes.Structure):
     _fields_ = [
         ("records", ctypes.POINTER(ctypes.c_uint8)), ("final_bits", ctypes.POINTER(ctypes.c_uint8)),
-        ("gpu_ms", ctypes.c_double),
+        ("gpu_ms", ctypes.c_double), ("passes_per_round", ctypes.c_int), ("redo_passes", ctypes.c_int),
     ]
 
 
@@ -454,7 +454,8 @@ def run_batch(d, gateset, rounds, p, seed, eps=0.0, eps_site=None, zeta=0.0, dty
     entry = lib().sv_run_batch_noalloc if no_alloc else lib().sv_run_batch
     _check(entry(ctypes.byref(job), ctypes.byref(res)))
     del keep
-    return dict(records=rec, final_bits=fb, gpu_ms=res.gpu_ms)
+    return dict(records=rec, final_bits=fb, gpu_ms=res.gpu_ms, passes_per_round=res.passes_per_round,
+                redo_passes=res.redo_passes)
 
 
 class Server:

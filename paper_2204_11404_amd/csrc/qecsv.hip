@@ -1581,6 +1581,8 @@ struct BatchInputs {
   uint8_t* final_bits;  // host [n_traj][d^2]
   hipStream_t hs;
   double gpu_ms;
+  int passes_per_round = 0;  // out: register passes per round (lockstep launches)
+  int redo_passes = 0;       // out: speculative redos that ran, one per slot and unit
 };
 
 template <typename T>
@@ -2103,6 +2105,12 @@ sv_status run_batch_lockstep(BatchInputs& in, const Template& tp) {
   float ms = 0.f;
   HIP_OK(hipEventElapsedTime(&ms, ev.a, ev.b));
   in.gpu_ms = ms;
+  in.passes_per_round = spec ? nus : nu;
+  in.redo_passes = 0;
+  if (spec) {
+    HIP_OK(hipMemcpyAsync(&in.redo_passes, dredos, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
   return SV_OK;
 }
 
@@ -2834,6 +2842,8 @@ sv_status sv_run_batch(const sv_batch_job* job, sv_batch_result* res) {
   const sv_status st =
       job->dtype == SV_C128 ? run_batch_core<double>(h.in, tp) : run_batch_core<float>(h.in, tp);
   res->gpu_ms = h.in.gpu_ms;
+  res->passes_per_round = h.in.passes_per_round;
+  res->redo_passes = h.in.redo_passes;
   return st;
 }
 
@@ -2894,6 +2904,8 @@ sv_status sv_run_batch_noalloc(const sv_batch_job* job, sv_batch_result* res) {
     return fail(SV_ENOMEM, "the job needs more than the %zu MiB no-allocation scratch",
                 kNoAllocScratchBytes >> 20);
   res->gpu_ms = h.in.gpu_ms;
+  res->passes_per_round = h.in.passes_per_round;
+  res->redo_passes = h.in.redo_passes;
   return st;
 }
 

@@ -243,3 +243,4 @@ def test_batch_d4_speculative_matches_plain(monkeypatch):
         out.append(qs.run_batch(4, "cr", R, p, 85, eps_site=eps, dtype="c64", max_rounds=9))
     assert np.array_equal(out[0]["records"], out[1]["records"])
     assert np.array_equal(out[0]["final_bits"], out[1]["final_bits"])
+    assert out[0]["passes_per_round"] < out[1]["passes_per_round"] and out[1]["redo_passes"] == 0
