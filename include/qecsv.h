@@ -243,7 +243,8 @@ typedef struct sv_result {
   int passes_per_round; /* out: register passes per round (speculative units:
                            prediction passes per round) */
   int redo_passes;      /* out: speculative units' redo passes that ran, over
-                           the whole run (0 without speculative units) */
+                           the whole run (0 without speculative units and for
+                           sv_run_rounds_async, which does not wait for it) */
 } sv_result;
 
 /* Run job->n_traj trajectories (indices traj0 ..): logical |0>, `rounds`
@@ -260,8 +261,8 @@ typedef struct sv_result {
  * trivial ones in the first round, the previous round's after that) and the
  * pass runs again when a drawn outcome differs; records, p1 and states are
  * those of the plain passes.  The environment variable QECSV_SPEC = 0 / 1
- * turns this off / on whatever zeta is (not with SV_RUN_GRAPH, the dense
- * crosstalk or asynchronous runs, which always use the plain passes). */
+ * turns this off / on whatever zeta is (not with SV_RUN_GRAPH or the dense
+ * crosstalk, which always use the plain passes). */
 sv_status sv_run_rounds(const sv_job* job, sv_result* res);
 
 /* The same run enqueued without waiting, so that jobs on several streams

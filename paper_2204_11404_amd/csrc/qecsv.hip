@@ -1051,6 +1051,8 @@ struct RunStage {
   std::vector<UnitPass> pds;
   JobConst jc;
   std::vector<double> eps, thr;
+  std::vector<UnitPass> spds;   // speculative passes
+  std::vector<uint8_t> pred0;   // first-round predictions
 };
 
 // Every block of the template builds a monomial Kraus pair with no Pauli
@@ -1071,8 +1073,8 @@ int env_int(const char* name, int dflt);
 // done == nullptr: synchronous.  Otherwise every step is enqueued on the
 // job's stream, `done` is recorded after the results' copies to the host and
 // the call returns without waiting (no graph replay, no final states).
-// Speculative units (stream launches of a register of at least 2^12
-// amplitudes whose blocks are all monomial): each unit is summed and applied
+// Speculative units (stream launches, also asynchronous ones, of a register
+// of at least 2^12 amplitudes whose blocks are all monomial): each unit is summed and applied
 // in one pass with predicted outcomes, then confirmed or redone (see
 // k_sdecide); two register buffers.  They pay when outcomes repeat from round
 // to round, i.e. without the data ZZ layer: at d = 5, p = 1e-3 a round takes
@@ -1092,7 +1094,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   const int nu = (int)units.size();
   const int per_units = R * nu;  // passes per trajectory after the first
   const int spec_env = env_int("QECSV_SPEC", -1);
-  bool spec = (spec_env < 0 ? job->zeta == 0.0 : spec_env != 0) && n >= kTileMax && !tp.any_dense && !async &&
+  bool spec = (spec_env < 0 ? job->zeta == 0.0 : spec_env != 0) && n >= kTileMax && !tp.any_dense &&
               !(job->flags & SV_RUN_GRAPH);
   std::vector<Unit> sunits;
   std::vector<UnitPass> spds;
@@ -1173,8 +1175,6 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
     HIP_OK(M.alloc(&dctl, sizeof(SpecCtl) * per_units_s));
     HIP_OK(M.alloc(&dpred0, pred0.size()));
     HIP_OK(M.alloc(&dredos, sizeof(int)));
-    HIP_OK(hipMemcpyAsync(dspass, spds.data(), sizeof(UnitPass) * spds.size(), hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(dpred0, pred0.data(), pred0.size(), hipMemcpyHostToDevice, s));
     HIP_OK(hipMemsetAsync(dredos, 0, sizeof(int), s));
   }
   std::vector<double> eps(n_angles, job->eps);
@@ -1198,7 +1198,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   {
     // set-up copies from a staging block that a host function on the stream
     // deletes once the stream has passed them (the call may return first)
-    RunStage* stage = new RunStage{tp.blocks, pds, make_job_const(d, job->zeta, xbasis), eps, thr};
+    RunStage* stage = new RunStage{tp.blocks, pds, make_job_const(d, job->zeta, xbasis), eps, thr, spds, pred0};
     const hipError_t e = [&]() -> hipError_t {
       hipError_t r;
       if ((r = hipMemcpyAsync(dblocks, stage->blocks.data(), sizeof(TBlock) * ns, hipMemcpyHostToDevice, s)))
@@ -1212,6 +1212,11 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
         return r;
       if (dthr && (r = hipMemcpyAsync(dthr, stage->thr.data(), sizeof(double) * stage->thr.size(),
                                       hipMemcpyHostToDevice, s)))
+        return r;
+      if (spec && (r = hipMemcpyAsync(dspass, stage->spds.data(), sizeof(UnitPass) * stage->spds.size(),
+                                      hipMemcpyHostToDevice, s)))
+        return r;
+      if (spec && (r = hipMemcpyAsync(dpred0, stage->pred0.data(), stage->pred0.size(), hipMemcpyHostToDevice, s)))
         return r;
       return hipLaunchHostFunc(s, [](void* q) { delete static_cast<RunStage*>(q); }, stage);
     }();
@@ -1433,7 +1438,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
         T* buf = st;
         if (spec) {
           SV_OK_OR_RETURN(traj_spec(s, drt + (size_t)ti * per_traj, drec + (size_t)tg * per_traj,
-                                    dp1 ? dp1 + (size_t)tg * per_traj : nullptr, tg == last_t, &buf));
+                                    dp1 ? dp1 + (size_t)tg * per_traj : nullptr, tg == last_t && !async, &buf));
         } else {
           SV_OK_OR_RETURN(traj_passes(s, drt + (size_t)ti * per_traj, ddn ? ddn + (size_t)ti * per_traj : nullptr,
                                       drec + (size_t)tg * per_traj,
@@ -1465,8 +1470,8 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
       // scope
       res->gpu_ms = -1.0;
       res->pass_ms = -1.0;
-      res->passes_per_round = nu;
-      res->redo_passes = 0;
+      res->passes_per_round = spec ? nus : nu;
+      res->redo_passes = 0;  // not waited for
       return SV_OK;
     }
     HIP_OK(hipEventRecord(ev1, s));

@@ -67,3 +67,22 @@ def test_async_zero_trajectories_records_the_event():
     r = qs.run_rounds_async(3, "cr", 2, 0, 0, 0.01, stream=s)
     g = r.wait()
     assert g["records"].shape == (0, 2, 8)
+
+
+def test_async_speculative_runs_match_synchronous(monkeypatch):
+    """Without the data ZZ layer both the enqueued and the synchronous runs
+    use speculative units (predicted outcomes, redone when they fail): the
+    same records, final bits and p1 bit for bit."""
+    import torch
+    monkeypatch.delenv("QECSV_SPEC", raising=False)
+    n4 = qs.template_info(4, "cr")[1]
+    kw = dict(d=4, gateset="cr", rounds=3, n_traj=5, seed=9, p=5e-3,
+              eps_site=workloads.eps_sites(n4, (0.0, 0.05), 9), zeta=0.0, dtype="c128", want_p1=True)
+    ref = qs.run_rounds(**kw)
+    s = torch.cuda.Stream()
+    r = qs.run_rounds_async(stream=s, **kw)
+    g = r.wait()
+    assert g["passes_per_round"] == ref["passes_per_round"] < 10
+    assert np.array_equal(g["records"], ref["records"])
+    assert np.array_equal(g["final_bits"], ref["final_bits"])
+    assert np.array_equal(g["p1"], ref["p1"])
