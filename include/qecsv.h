@@ -261,8 +261,8 @@ typedef struct sv_result {
  * trivial ones in the first round, the previous round's after that) and the
  * pass runs again when a drawn outcome differs; records, p1 and states are
  * those of the plain passes.  The environment variable QECSV_SPEC = 0 / 1
- * turns this off / on whatever zeta is (not with SV_RUN_GRAPH or the dense
- * crosstalk, which always use the plain passes). */
+ * turns this off / on whatever zeta is (not with the dense crosstalk, which
+ * always uses the plain passes). */
 sv_status sv_run_rounds(const sv_job* job, sv_result* res);
 
 /* The same run enqueued without waiting, so that jobs on several streams

@@ -1073,8 +1073,9 @@ int env_int(const char* name, int dflt);
 // done == nullptr: synchronous.  Otherwise every step is enqueued on the
 // job's stream, `done` is recorded after the results' copies to the host and
 // the call returns without waiting (no graph replay, no final states).
-// Speculative units (stream launches, also asynchronous ones, of a register
-// of at least 2^12 amplitudes whose blocks are all monomial): each unit is summed and applied
+// Speculative units (stream launches, asynchronous runs and graph replay of
+// a register of at least 2^12 amplitudes whose blocks are all monomial): each
+// unit is summed and applied
 // in one pass with predicted outcomes, then confirmed or redone (see
 // k_sdecide); two register buffers.  They pay when outcomes repeat from round
 // to round, i.e. without the data ZZ layer: at d = 5, p = 1e-3 a round takes
@@ -1094,8 +1095,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
   const int nu = (int)units.size();
   const int per_units = R * nu;  // passes per trajectory after the first
   const int spec_env = env_int("QECSV_SPEC", -1);
-  bool spec = (spec_env < 0 ? job->zeta == 0.0 : spec_env != 0) && n >= kTileMax && !tp.any_dense &&
-              !(job->flags & SV_RUN_GRAPH);
+  bool spec = (spec_env < 0 ? job->zeta == 0.0 : spec_env != 0) && n >= kTileMax && !tp.any_dense;
   std::vector<Unit> sunits;
   std::vector<UnitPass> spds;
   if (spec) {
@@ -1391,9 +1391,10 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
         hipLaunchKernelGGL(k_prepare_dense, dim3((unsigned)((per_traj * 16 + 127) / 128)), dim3(128), 0, G.q,
                            dblocks, ns, R, draws_round, job->seed, job->traj0, 1, job->p, deps, dn_s, derr,
                            (const uint64_t*)(dcur + 1), (const double*)dthr);
-      cst = traj_passes(G.q, rt_s, dn_s, rec_s, p1_s, false);
+      T* fbuf = st;
+      cst = spec ? traj_spec(G.q, rt_s, rec_s, p1_s, false, &fbuf) : traj_passes(G.q, rt_s, dn_s, rec_s, p1_s, false);
       if (cst == SV_OK) {
-        traj_final(G.q, st, bits_s, 0, dcur + 1);
+        traj_final(G.q, fbuf, bits_s, 0, dcur + 1);
         hipLaunchKernelGGL(k_commit, dim3(1), dim3(256), 0, G.q, rec_s, p1_s, bits_s, drec, dp1, dbits,
                            per_traj, n, dcur, dcur + 1, job->traj0);
       }
@@ -1416,7 +1417,7 @@ sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
     HIP_OK(hipStreamSynchronize(G.q));
     float tm = 0.f;
     HIP_OK(hipEventElapsedTime(&tm, G.a, G.b));
-    pass_ms_graph = tm / (per_units + 1);
+    pass_ms_graph = tm / ((spec ? per_units_s : per_units) + 1);
   } else {
     for (int c0 = 0; c0 < job->n_traj; c0 += chunk) {
       const int cn = std::min(chunk, job->n_traj - c0);

@@ -146,6 +146,26 @@ def test_spec_grid_and_traversal_variants(monkeypatch):
         assert np.max(np.abs(g["p1"] - out[0]["p1"])) < 1e-12
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_spec_graph_replay(monkeypatch, dtype):
+    """A trajectory's speculative launch sequence captured once and replayed
+    per trajectory (its redos are launched every time, run when needed): the
+    stream launches' records, p1 and final bits for every replay, with an
+    eager run between two graph runs."""
+    monkeypatch.setenv("QECSV_SPEC", "1")
+    kw = dict(d=4, gateset="cr", rounds=3, n_traj=5, seed=55, p=0.02, eps=0.02, zeta=0.0, dtype=dtype,
+              traj0=2, want_p1=True)
+    g1 = qs.run_rounds(graph=True, **kw)
+    e = qs.run_rounds(**kw)
+    g2 = qs.run_rounds(graph=True, **kw)
+    assert e["redo_passes"] > 0 and g1["redo_passes"] == e["redo_passes"]
+    for g in (g1, g2):
+        assert g["passes_per_round"] == e["passes_per_round"]
+        assert np.array_equal(g["records"], e["records"])
+        assert np.array_equal(g["final_bits"], e["final_bits"])
+        assert np.array_equal(g["p1"], e["p1"])
+
+
 def test_spec_runs_without_the_zz_layer(monkeypatch):
     """Unless QECSV_SPEC says otherwise, the speculative units run exactly
     when the data ZZ layer is off (zeta = 0), where outcomes repeat from round
