@@ -1075,14 +1075,13 @@ int env_int(const char* name, int dflt);
 // the call returns without waiting (no graph replay, no final states).
 // Speculative units (stream launches, asynchronous runs and graph replay of
 // a register of at least 2^12 amplitudes whose blocks are all monomial): each
-// unit is summed and applied
-// in one pass with predicted outcomes, then confirmed or redone (see
-// k_sdecide); two register buffers.  They pay when outcomes repeat from round
-// to round, i.e. without the data ZZ layer: at d = 5, p = 1e-3 a round takes
-// 2.18 ms instead of 2.96 (complex128); with zeta = 0.01 the layer turns 15 %
-// of the X checks' outcomes from one round to the next and the redos make
-// them slower (3.1 against 3.0 ms).  So they run when zeta = 0;
-// QECSV_SPEC = 0 / 1 turns them off / on whatever zeta is.
+// unit is summed and applied in one pass with predicted outcomes, then
+// confirmed or redone (see k_sdecide); two register buffers.  They pay when
+// outcomes repeat from round to round, i.e. without the data ZZ layer: at
+// d = 5, p = 1e-3 a round takes 2.1 ms instead of 2.9 (complex128); with
+// zeta = 0.01 the layer turns 15 % of the X checks' outcomes from one round to
+// the next and the redos make them slower (3.1 against 3.0 ms).  So they run
+// when zeta = 0; QECSV_SPEC = 0 / 1 turns them off / on whatever zeta is.
 template <typename T>
 sv_status run_rounds_t(const sv_job* job, sv_result* res, const Template& tp,
                        const std::atomic<int>* cancel = nullptr, hipEvent_t done = nullptr) {
