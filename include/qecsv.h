@@ -209,6 +209,18 @@ sv_status sv_template_info(int d, int gateset, int* n_stab, int* n_sites, int* n
  * the first failing pass or block. */
 sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int xpair, int* n_passes);
 
+/* Host-side self-check of the speculative passes sv_run_rounds and
+ * sv_run_batch use for (d, gateset) with Z chains of at most zchain checks
+ * when the data ZZ layer is off: for each unit (a pair of consecutive X
+ * checks, a single X check or a Z chain) its pass fits a tile; a pair's tile
+ * holds both members' qubits, the second member's layout covers the same
+ * tile bits with that member's qubits on its register slots, and a pair
+ * stored from that layout keeps the three lowest bits on its first lanes.  No
+ * device work.  *n_units receives the units per round, or 0 when the plain
+ * passes run instead (fewer than 12 qubits, or a chain that would have to be
+ * summed amplitude by amplitude); SV_EINVAL names the first failing unit. */
+sv_status sv_check_spec_layouts(int d, int gateset, int zchain, int* n_units);
+
 typedef struct sv_job {
   int d;               /* code distance, 2..5 */
   int gateset;         /* sv_gateset */

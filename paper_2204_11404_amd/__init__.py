@@ -119,6 +119,8 @@ _SIGS = {
                                                        ctypes.POINTER(ctypes.c_double)]),
     "sv_check_pass_layouts": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_int)]),
+    "sv_check_spec_layouts": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int)]),
     "sv_template_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "sv_run_rounds": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(Result)]),
@@ -214,6 +216,14 @@ def check_pass_layouts(d, gateset, zchain=4, xpair=0):
     layouts; returns the pass count of one round sequence."""
     n = ctypes.c_int()
     _check(lib().sv_check_pass_layouts(d, _GATESETS[gateset], int(zchain), int(xpair), ctypes.byref(n)))
+    return n.value
+
+
+def check_spec_layouts(d, gateset, zchain=4):
+    """sv_check_spec_layouts: host-side consistency of the speculative
+    passes' layouts; returns the units per round (0: the plain passes run)."""
+    n = ctypes.c_int()
+    _check(lib().sv_check_spec_layouts(d, _GATESETS[gateset], int(zchain), ctypes.byref(n)))
     return n.value
 
 

@@ -2571,6 +2571,44 @@ sv_status sv_template_info(int d, int gateset, int* n_stab, int* n_sites, int* n
   return SV_OK;
 }
 
+sv_status sv_check_spec_layouts(int d, int gateset, int zchain, int* n_units) {
+  if (!n_units) return fail(SV_EINVAL, "NULL n_units");
+  *n_units = 0;
+  if (d < 2 || d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", d);
+  if (gateset != SV_GATESET_CR && gateset != SV_GATESET_TEXTBOOK) return fail(SV_EINVAL, "bad gateset");
+  if (zchain < 1 || zchain > kChainMax) return fail(SV_EINVAL, "zchain %d out of 1..%d", zchain, kChainMax);
+  const Template tp = build_template(d, gateset);
+  const int n = d * d;
+  if (n < kTileMax) return SV_OK;  // the plain passes
+  const int tb = std::min(kTileMax, n);
+  const std::vector<Unit> units = make_spec_units(tp, zchain, n);
+  const std::vector<UnitPass> pds = make_spec_passes(n, tb, tp, units);
+  for (const UnitPass& h : pds)
+    if (h.tb <= 0 || (h.bkind == U_Z && h.bmode == 0)) return SV_OK;  // the plain passes
+  auto bits_of = [](const uint32_t* m, int k) {
+    uint32_t r = 0;
+    for (int i = 0; i < k; ++i) r |= m[i];
+    return r;
+  };
+  for (size_t u = 0; u < units.size(); ++u) {
+    const UnitPass& h = pds[1 + u];
+    if (units[u].kind != U_XP) continue;
+    const uint32_t tile = bits_of(h.tid_g, h.tb - 4) | bits_of(h.j_g, 16);
+    const uint32_t tile_p = bits_of(h.p_tid_g[0], h.tb - 4) | bits_of(h.p_j_g[0], 16);
+    uint32_t q0 = 0, q1 = 0;
+    for (int l = 0; l < h.aw[0]; ++l) q0 |= h.aq[0][l];
+    for (int l = 0; l < h.aw[1]; ++l) q1 |= h.aq[1][l];
+    if (__builtin_popcount(tile) != h.tb || tile_p != tile || (q0 & ~tile) || (q1 & ~tile))
+      return fail(SV_EINVAL, "speculative unit %zu: the pair's tile does not hold both members", u);
+    if ((q1 & ~bits_of(h.p_j_g[0], 16)) != 0)
+      return fail(SV_EINVAL, "speculative unit %zu: second member not on its layout's register slots", u);
+    if (h.pstore && (h.p_tid_g[0][0] != 1u || h.p_tid_g[0][1] != 2u || h.p_tid_g[0][2] != 4u))
+      return fail(SV_EINVAL, "speculative unit %zu: stored from a layout without the lowest bits on its lanes", u);
+  }
+  *n_units = (int)units.size();
+  return SV_OK;
+}
+
 sv_status sv_check_pass_layouts(int d, int gateset, int zchain, int xpair, int* n_passes) {
   if (d < 2 || d > 5) return fail(SV_EINVAL, "d=%d out of 2..5", d);
   if (gateset != SV_GATESET_CR && gateset != SV_GATESET_TEXTBOOK) return fail(SV_EINVAL, "bad gateset");

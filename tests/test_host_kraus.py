@@ -197,3 +197,28 @@ def test_x_pair_layouts(d, gateset):
         assert qs.check_pass_layouts(d, gateset, zchain, 1) == best + -(-n_z // zchain) + 2
     with pytest.raises(qs.SvError):
         qs.check_pass_layouts(d, gateset, 4, 2)
+
+
+@pytest.mark.parametrize("gateset", [CR, TB])
+@pytest.mark.parametrize("d", [2, 3, 4, 5])
+def test_spec_layouts(d, gateset):
+    """Speculative passes (no data ZZ layer): consecutive X checks two by two
+    where the pair's tile (both members' qubits and the three lowest bits)
+    fits 2^12 amplitudes, then the Z chains; every layout checks out
+    (host-side builder).  Below 12 qubits, and at d = 4 with chains of five or
+    six (a chain no four tile bits avoid, summed amplitude by amplitude), the
+    plain passes run (0 units)."""
+    xs = [frozenset(q - 1 for q in s if q) for t, s in oracle.layout(d) if t == "X"]
+    n_x, n_z = len(xs), (d * d - 1) - len(xs)
+    units_x, i = 0, 0
+    while i < n_x:
+        i += 2 if i + 1 < n_x and _pair_fits([xs[i] | xs[i + 1]]) else 1
+        units_x += 1
+    for zchain in (1, 2, 3, 4, 5, 6):
+        plain = d * d < 12 or (d == 4 and zchain >= 5)
+        want = 0 if plain else units_x + -(-n_z // zchain)
+        assert qs.check_spec_layouts(d, gateset, zchain) == want
+    if d >= 4:
+        assert units_x == (n_x + 1) // 2  # every pair fits at d = 4, 5
+    with pytest.raises(qs.SvError):
+        qs.check_spec_layouts(d, gateset, 7)
