@@ -1827,8 +1827,7 @@ __global__ __launch_bounds__(256) void k_udecide(const double* __restrict__ part
 }
 
 // Decision of a speculative unit instance of len members after a prediction
-// pass or a redo (grid: one workgroup per sum; the last to finish decides).
-// tree = 0: 2 len sums along the applied outcomes (S[2 l + m], taken before
+// pass or a redo (the grid is set by `split`, below).  tree = 0: 2 len sums along the applied outcomes (S[2 l + m], taken before
 // the pass applied the pending renormalisation of dec_a->Sm); each member from
 // `known` on is decided as in a plain pass while the members before it match
 // what was applied; at the first mismatch the outcome is fixed and a redo is
